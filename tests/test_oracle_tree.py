@@ -1,0 +1,181 @@
+"""Pins for the oracle tree code (O2): coverage by brute force, the theta -> 0
+special case, exactness for kernels in the interpolation space, the
+child-to-parent proxy-charge identity, tangency, and the paper's error
+behaviour in the degree."""
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import direct, metrics, interp
+from oracle import tree as T
+from oracle import geometry as G
+
+
+def _coverage_matrix(tc):
+    n = len(tc.x)
+    C = np.zeros((n, n), dtype=np.int32)
+    pt = tc.ptree
+
+    def leaves_under(node):
+        return pt.members(node)
+    for kind, lst in tc.lists.items():
+        for t, s in lst:
+            it, js = leaves_under(t), leaves_under(s)
+            C[np.ix_(it, js)] += 1
+    return C
+
+
+@pytest.mark.parametrize("case", ["grid", "random", "clustered"])
+def test_every_pair_covered_exactly_once(case):
+    if case == "grid":
+        x = S.icosahedral_grid(3)
+    elif case == "random":
+        x = S.random_sphere_points(1500, 8)
+    else:
+        x = S.clustered_sphere_points(1500, 9, width=0.01)
+    n = len(x)
+    tc = T.TreeCode(x, np.ones(n), S.uniform_areas(n), theta=0.7, degree=2, n_crit=12,
+                    max_level=4 if case == "clustered" else None)
+    C = _coverage_matrix(tc)
+    assert (C == 1).all()
+    assert sum(tc.list_counts().values()) > 0
+    if case == "clustered":
+        # the depth limit is reached: some PP pairs hold more than N_T particles
+        big_pp = [(t, s) for t, s in tc.lists["PP"] if tc.ptree.count[t] > 12]
+        assert big_pp
+
+
+def test_theta_to_zero_is_direct_sum():
+    x = S.icosahedral_grid(3)
+    n = len(x)
+    z = S.rossby_haurwitz(x, 4)
+    a = S.uniform_areas(n)
+    tc = T.TreeCode(x, z, a, theta=1e-6, degree=4, n_crit=8)
+    assert tc.list_counts()["PC"] == tc.list_counts()["CC"] == tc.list_counts()["CP"] == 0
+    u = tc.velocity()
+    ud = direct.velocity(x, z, a)
+    assert np.abs(u - ud).max() / np.abs(ud).max() < 1e-13
+
+
+@pytest.mark.parametrize("d,theta", [(2, 0.7), (4, 0.9), (6, 0.7)])
+def test_polynomial_kernel_is_exact(d, theta):
+    """K(x, y) = a (x . y)^d lies in the degree-d interpolation space in both
+    arguments, so PC, CP and CC reproduce it: tree == direct up to rounding."""
+    x = S.random_sphere_points(2000, 12)
+    n = len(x)
+    q = np.random.default_rng(3).standard_normal(n)
+    kern = T.polynomial_kernel(d)
+    tc = T.TreeCode(x, q, np.ones(n), theta=theta, degree=d, n_crit=16, kernel=kern)
+    c = tc.list_counts()
+    assert c["PC"] > 0 and c["CP"] > 0 and c["CC"] > 0
+    W = tc.evaluate()
+    Wd = direct.kernel_sum(x, x, q, kern, exclude=np.arange(n))
+    assert np.abs(W - Wd).max() / np.abs(Wd).max() < 1e-11
+
+
+def test_polynomial_kernel_one_degree_too_high_is_not_exact():
+    """Negative control for the test above: degree d+1 is not reproduced."""
+    x = S.random_sphere_points(2000, 12)
+    n = len(x)
+    q = np.random.default_rng(3).standard_normal(n)
+    kern = T.polynomial_kernel(5)
+    tc = T.TreeCode(x, q, np.ones(n), theta=0.7, degree=4, n_crit=16, kernel=kern)
+    W = tc.evaluate()
+    Wd = direct.kernel_sum(x, x, q, kern, exclude=np.arange(n))
+    assert np.abs(W - Wd).max() / np.abs(Wd).max() > 1e-8
+
+
+def test_child_to_parent_proxy_charge_identity():
+    """Every triangle's basis spans the same space (homogeneous polynomials of
+    degree d), so a parent's proxy charges equal its children's proxy charges
+    re-interpolated at the parent: w_m(P) = sum_c sum_n L^P_m(y^c_n) w^c_n."""
+    x = S.random_sphere_points(3000, 21)
+    n = len(x)
+    q = np.random.default_rng(2).standard_normal(n)
+    tc = T.TreeCode(x, q, np.ones(n), theta=0.7, degree=6, n_crit=20, max_level=3)
+    wq = tc.all_proxy_charges()
+    checked = 0
+    for P in list(wq)[:30]:
+        lvl, key = G.node_level_key(P)
+        if lvl >= tc.max_level:
+            continue
+        acc = np.zeros_like(wq[P])
+        for c in tc.ptree.children(P):
+            if tc.ptree.count[c] == 0:
+                continue
+            wc = wq.get(c)
+            if wc is None:   # a small child: use its particles directly
+                idx = tc.ptree.members(c)
+                pts, ch = tc.x[idx], tc.q[idx]
+            else:
+                pts, ch = tc.proxies(c), wc
+            Lp = interp.lagrange_matrix(tc.geom.node_vertices(P), tc.degree, pts)
+            acc += Lp.T @ ch
+        assert np.abs(acc - wq[P]).max() / np.abs(wq[P]).max() < 1e-10
+        checked += 1
+    assert checked >= 5
+
+
+def test_lagrange_basis_interpolates():
+    geom = G.TreeGeometry(2)
+    tri = geom.verts[2][17]
+    for d in (2, 5, 8):
+        prox = interp.proxy_points(tri, d)
+        L = interp.lagrange_matrix(tri, d, prox)
+        np.testing.assert_allclose(L, np.eye(len(prox)), atol=1e-10)
+
+
+def test_gll_nodes_closed_forms():
+    np.testing.assert_allclose(interp.gll_nodes01(2), [0, 0.5, 1], atol=1e-15)
+    np.testing.assert_allclose(interp.gll_nodes01(3), [0, (1 - 5 ** -0.5) / 2, (1 + 5 ** -0.5) / 2, 1], atol=1e-15)
+    r = (3 / 7) ** 0.5 / 2
+    np.testing.assert_allclose(interp.gll_nodes01(4), [0, 0.5 - r, 0.5, 0.5 + r, 1], atol=1e-15)
+    for d in (2, 4, 6, 8, 10, 12, 14):
+        assert len(interp.reference_points(d)) == interp.n_basis(d)
+        np.testing.assert_allclose(interp.reference_points(d).sum(1), 1.0, atol=1e-15)
+
+
+def test_tangency_and_lists_independent_of_vorticity():
+    x = S.icosahedral_grid(4)
+    n = len(x)
+    a = S.uniform_areas(n)
+    t1 = T.TreeCode(x, S.rossby_haurwitz(x, 4), a, theta=0.7, degree=4, n_crit=32)
+    t2 = T.TreeCode(x, S.gaussian_vortex(x, seed=2), a, theta=0.7, degree=4, n_crit=32)
+    for k in t1.lists:
+        np.testing.assert_array_equal(t1.lists[k], t2.lists[k])
+    u = t1.velocity()
+    assert np.abs((x * u).sum(1)).max() / np.abs(u).max() < 1e-15
+
+
+def test_error_decreases_with_degree():
+    """Sec. 4: at theta = 0.7 the error falls as the degree rises; d = 6 gives
+    three to four digits (our interpolation points and N differ, so the band
+    is loose)."""
+    x = S.icosahedral_grid(4)
+    n = len(x)
+    z = S.rossby_haurwitz(x, 4)
+    a = S.uniform_areas(n)
+    ud = direct.velocity(x, z, a)
+    errs = {}
+    for d in (2, 4, 6, 8):
+        errs[d] = metrics.rel_l2_velocity(T.velocity(x, z, a, theta=0.7, degree=d, n_crit=16), ud, a)
+    assert errs[2] > errs[4] > errs[6] > errs[8]
+    assert 1e-7 < errs[6] < 1e-3
+
+
+def test_node_counts_match_brute_force_containment():
+    """Leaf counts against a direct containment test of each point."""
+    L = 2
+    x = S.random_sphere_points(800, 30)
+    geom = G.TreeGeometry(L)
+    key = G.locate(x, geom)
+    tri = geom.verts[L]
+    for i in range(0, 800, 37):
+        inside = []
+        for k in range(len(tri)):
+            a, b, c = tri[k]
+            if (np.dot(x[i], np.cross(a, b)) >= 0 and np.dot(x[i], np.cross(b, c)) >= 0
+                    and np.dot(x[i], np.cross(c, a)) >= 0):
+                inside.append(k)
+        assert inside == [key[i]]
