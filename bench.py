@@ -1,0 +1,159 @@
+"""Benchmark: particle velocity evaluations per second of the spherical tree
+code at N = 655362 (icosahedron refined 8 times), Gaussian vortex of width 0.1
+plus 1e-3 uniform noise, A = 4 pi / N, precision form (FP32 kernel sums with
+the |x - y|^2 / 2 denominator, FP64 proxy charges), accuracy checked against
+the FP64 direct sum on 4096 seeded targets.
+
+One step = one full velocity evaluation (tree build, upward pass, traversal,
+near and far field, output) on inputs already resident in HBM.  Prints one
+JSON line.  Single GPU only.
+"""
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_FLOPS = 16   # per |x-y|^2/2 kernel evaluation: 3 sub, |d|^2 5, div 1, *q 1, 3 fma 6
+FP64_FLOPS = 17   # per 1 - x.y evaluation with the (y - x) form: dot 5, 1- 1, div 1, *q 1, 3 sub, 3 fma 6
+PEAK_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, without packed FP32
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+_G = {}
+
+
+def _oracle_worker(idx):
+    from oracle import direct
+    return direct.velocity(_G["x"], _G["z"], _G["a"], targets=idx)
+
+
+def cpu_baseline(x, z, a, subset, budget_s=15.0):
+    """The oracle's direct sum (O(N) per target) timed on the host cores over a
+    bounded sample of the target subset."""
+    from oracle import direct
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    _G.update(x=x, z=z, a=a)
+    t0 = time.perf_counter()
+    probe = direct.velocity(x, z, a, targets=subset[:8])
+    per_target = (time.perf_counter() - t0) / 8
+    m = int(min(len(subset), max(cores * 8, budget_s * cores / per_target)))
+    m = max(8, (m // cores) * cores) if m >= cores else m
+    sample = subset[:m]
+    chunks = np.array_split(sample, cores * 4)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        parts = pool.map(_oracle_worker, chunks)
+    dt = time.perf_counter() - t0
+    u = np.concatenate(parts)
+    return dict(value=m / dt, unit="velocity evals/s", cores=cores, kind="oracle",
+                sample=f"{m} of the 4096 seeded targets, all {len(x)} sources, FP64 direct sum, "
+                       f"{dt:.1f} s wall"), sample, u
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=0.6)
+    ap.add_argument("--degree", type=int, default=12)
+    ap.add_argument("--n-crit", type=int, default=64)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--level", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthetic as S
+    from paper_2401_07361_amd import stc
+
+    wl = S.make_workload("gv_l8", level=args.level)
+    x, z, a, subset = wl["x"], wl["zeta"], wl["area"], wl["subset"]
+    n = len(x)
+    log(f"workload gv_l8 N={n} theta={args.theta} d={args.degree} n_crit={args.n_crit} {args.precision}")
+    xd = torch.from_numpy(x).cuda()
+    zd = torch.from_numpy(z).cuda()
+    ad = torch.from_numpy(a).cuda()
+    sd = torch.from_numpy(subset).cuda()
+    out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    den = "dist2" if args.precision == "fp32" else "dot"
+    ctx = stc.Context(n, theta=args.theta, degree=args.degree, n_crit=args.n_crit,
+                      precision=args.precision, denominator=den)
+    for _ in range(args.warmup):
+        ctx.velocity(xd, zd, ad, out=out)
+    ctx.sync()
+    log("warmup done")
+
+    ctx.set_timing(args.steps)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        ctx.velocity(xd, zd, ad, out=out)
+    t1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms = t0.elapsed_time(t1) / args.steps
+    phases, k = ctx.phase_times()
+    phase_ms = {p: v / max(k, 1) for p, v in phases.items()}
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step; phases {json.dumps({p: round(v, 4) for p, v in phase_ms.items()})}")
+
+    counts, evals = ctx.list_counts()
+    # accuracy: FP64 direct sum on the GPU (parity-tested against the oracle) at the 4096 targets
+    ud = stc.direct(xd, zd, ad, targets=sd).cpu().numpy()
+    ut = out.cpu().numpy()[subset]
+    from oracle import metrics
+    err = metrics.rel_l2_velocity(ut, ud, a[subset])
+    log(f"E vs FP64 direct (4096 targets) = {err:.3e}; lists {counts}")
+
+    flops_per = FP32_FLOPS if args.precision == "fp32" else FP64_FLOPS
+    near_flops = (evals["PP"] + evals["PC"]) * flops_per
+    near_s = phase_ms["near"] / 1e3
+    achieved = near_flops / near_s / 1e12
+    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=None,
+                kernel="k_near (PP + PC)", kernel_ms=round(phase_ms["near"], 4),
+                kernel_evals_per_launch=int(evals["PP"] + evals["PC"]))
+
+    result = dict(
+        metric="particle velocity evals/s at N=655362, rel-L2 err <=1e-6 vs FP64 direct sum",
+        value=n / (ms / 1e3), unit="velocity evals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32" if args.precision == "fp32" else "f64", data="synthetic",
+        config=dict(workload="gv_l8 (Gaussian vortex, icosahedral level %d)" % args.level, N=n,
+                    theta=args.theta, degree=args.degree, n_crit=args.n_crit, max_level=ctx.max_level,
+                    precision=args.precision, denominator=den, rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"),
+                    err_ok=bool(err <= 1e-6), lists=counts,
+                    kernel_evals=int(sum(evals.values())), phase_ms={p: round(v, 4) for p, v in phase_ms.items()}),
+        roofline=roof,
+    )
+    ctx.close()
+    if not args.no_cpu:
+        log("cpu baseline (oracle direct sum on a bounded target sample)")
+        cb, sample, uo = cpu_baseline(x, z, a, subset)
+        pos = np.searchsorted(subset, sample)
+        cb["rel_l2_err_gpu_vs_oracle_on_sample"] = float(f"{metrics.rel_l2_velocity(ut[pos], uo, a[sample]):.3e}")
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

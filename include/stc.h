@@ -1,0 +1,227 @@
+/*
+ * stc.h -- C ABI of the MI355X spherical tree code.
+ *
+ * Evaluates the velocity of the Lagrangian barotropic vorticity equation
+ * (Chen & Jablonowski, Sec. 2, the midpoint-rule particle system)
+ *
+ *     u_i = -(1/4pi) sum_{j != i} (x_i x x_j) zeta_j A_j / (1 - x_i . x_j)
+ *
+ * for N particles x_i on the unit sphere, through the spherical tree code of
+ * Sec. 3: an icosahedral triangle tree, proxy charges at interpolation points
+ * of each triangle (spherical Bernstein-Bezier basis), a dual tree traversal
+ * with multipole acceptance criterion theta, and particle-particle (PP),
+ * particle-cluster (PC), cluster-particle (CP) and cluster-cluster (CC)
+ * interactions.
+ *
+ * Conventions for every call:
+ *  - Pointers named d_* are DEVICE pointers (HIP, gfx950), h_* are HOST
+ *    pointers.  The caller owns every pointer it passes; the library never
+ *    frees them and keeps none of them after the call returns, except that
+ *    stc_upward reads the last d_x given to stc_tree_build (see there).
+ *  - Particle positions are (n, 3) FP64, row-major (x0 y0 z0 x1 y1 z1 ...).
+ *    zeta, area: (n,) FP64.  Velocities are (n, 3) FP64 in INPUT order.
+ *  - All pipeline calls are asynchronous on the context's HIP stream and
+ *    allocate nothing: every device buffer is allocated by stc_create.
+ *    Host-side argument errors return at once and enqueue nothing.
+ *    Device-side conditions (list capacity exceeded) raise a flag in device
+ *    memory that the next synchronising call (stc_sync, stc_list_counts,
+ *    stc_copy_*) reports as STC_ERR_CAPACITY; outputs are then undefined.
+ *  - A context is not thread safe.  No call aborts the process or lets a C++
+ *    exception escape; stc_last_error() gives a message for the last error.
+ */
+#ifndef STC_H
+#define STC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum stc_status {
+    STC_OK = 0,
+    STC_ERR_INVALID_ARG = 1, /* bad pointer, size or parameter               */
+    STC_ERR_CAPACITY = 2,    /* an interaction list outgrew its capacity      */
+    STC_ERR_DEVICE = 3,      /* a HIP runtime call failed                     */
+    STC_ERR_STATE = 4,       /* call out of order (e.g. upward before build)  */
+    STC_ERR_ALLOC = 5        /* device allocation failed in stc_create        */
+} stc_status;
+
+enum { STC_FP64 = 0, STC_FP32 = 1 };           /* arithmetic of the PP/PC/CP/CC sums   */
+enum { STC_DEN_DOT = 0, STC_DEN_DIST2 = 1 };   /* 1 - x.y (Sec. 2) | |x-y|^2/2 (Sec. 2, alt. kernel) */
+enum { STC_LIST_PP = 0, STC_LIST_PC = 1, STC_LIST_CP = 2, STC_LIST_CC = 3 };
+
+/* Method parameters (Sec. 3, dual tree traversal).
+ *  theta       MAC: a pair is well separated iff (r_t + r_s) / R < theta,
+ *              with r the circumradius (largest chord from the circumcentre to
+ *              a vertex) and R the chord between circumcentres.  (0, 1].
+ *  degree      interpolation degree d, (d+1)(d+2)/2 points per triangle. 1..14.
+ *  n_crit      N_T: a triangle has "many" particles iff count > n_crit.  >= 1.
+ *  max_level   depth limit of the tree (root faces are level 0).  0..12, or
+ *              -1 for the default: two levels below the level at which an
+ *              average node of a uniform distribution holds n_crit particles.
+ *  precision   STC_FP64, or STC_FP32: PP/PC/CP/CC kernel sums in FP32 with
+ *              target-relative coordinates and FP64 accumulation per tile;
+ *              proxy charges, interpolation weights and the output stay FP64.
+ *  denominator STC_DEN_DOT or STC_DEN_DIST2.
+ *  list_capacity entries per interaction list and per traversal frontier;
+ *              0 for the default (16 * n_max, at least 65536).            */
+typedef struct stc_params {
+    double theta;
+    int32_t degree;
+    int32_t n_crit;
+    int32_t max_level;
+    int32_t precision;
+    int32_t denominator;
+    int32_t reserved0;
+    int64_t list_capacity;
+} stc_params;
+
+typedef struct stc_ctx stc_ctx;
+
+/* Message for a status code (static string). */
+const char* stc_status_string(int32_t status);
+
+/* Fills *p with theta 0.7, degree 8, n_crit 64, max_level -1, FP64, DOT. */
+stc_status stc_default_params(stc_params* p);
+
+/* Number of interpolation points (d+1)(d+2)/2 (Sec. 3, interpolation in
+ * triangles); 0 if d is out of range. */
+int32_t stc_n_basis(int32_t degree);
+
+/* Number of nodes of the complete tree down to max_level: 20 (4^(L+1)-1)/3.
+ * Node id of (level l, key k) is 20 (4^l - 1)/3 + k. */
+int64_t stc_total_nodes(int32_t max_level);
+
+/* The depth limit stc_create uses for max_level = -1. */
+int32_t stc_default_max_level(int64_t n_max, int32_t n_crit);
+
+/* Creates a context for up to n_max particles: builds the triangle geometry
+ * of every node down to max_level on the host (FP64, fixed operation order),
+ * the interpolation tables, and allocates all device buffers.  hip_stream is
+ * a hipStream_t (NULL = default stream).  On success *out owns the context. */
+stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_ctx** out);
+
+/* Frees the context and its device buffers (synchronises its stream). */
+stc_status stc_destroy(stc_ctx* ctx);
+
+/* Changes the stream later calls are enqueued on. */
+stc_status stc_set_stream(stc_ctx* ctx, void* hip_stream);
+
+/* The parameters the context resolved (max_level filled in). */
+stc_status stc_get_params(const stc_ctx* ctx, stc_params* out);
+
+/* --- the pipeline (Sec. 3) ------------------------------------------------ */
+
+/* Tree build: locates every particle in the icosahedral triangle tree
+ * (exact orientation predicates; a point on a shared edge goes to the lowest
+ * root face containing it and, inside a triangle, to a corner child only if
+ * strictly inside it), sorts particles by leaf (stable in input index) and
+ * finds every node's particle range.  0 <= n <= n_max.  d_x must stay valid
+ * and unchanged until the evaluation calls that follow have completed. */
+stc_status stc_tree_build(stc_ctx* ctx, int64_t n, const double* d_x);
+
+/* Upward pass: charges q_j = zeta_j A_j and, for every node with more than
+ * n_crit particles, the proxy charges w_m = sum_j L_m(y_j) q_j (Sec. 3,
+ * particle-cluster interaction: the paper's proxy weights omega_k transformed
+ * by the inverse transposed Vandermonde matrix).  FP64.  Needs a tree. */
+stc_status stc_upward(stc_ctx* ctx, const double* d_zeta, const double* d_area);
+
+/* Dual tree traversal from the 400 root pairs (Sec. 3) -> PP, PC, CP, CC
+ * lists, grouped by target.  Needs a tree. */
+stc_status stc_traverse(stc_ctx* ctx);
+
+/* Near field: the PP interactions only, u_near = -(1/4pi) x_i x sum_PP.
+ * Writes d_u (n,3) (adds to it if accumulate != 0).  Needs upward+traverse. */
+stc_status stc_eval_near(stc_ctx* ctx, double* d_u, int32_t accumulate);
+
+/* Far field: the PC, CP and CC interactions with target-side interpolation
+ * back to the particles.  Writes or adds to d_u like stc_eval_near. */
+stc_status stc_eval_far(stc_ctx* ctx, double* d_u, int32_t accumulate);
+
+/* One full velocity evaluation: tree build, upward pass, traversal, near and
+ * far field, written to d_u (n,3) in input order. */
+stc_status stc_velocity(stc_ctx* ctx, int64_t n, const double* d_x, const double* d_zeta,
+                        const double* d_area, double* d_u);
+
+/* Direct O(N^2) sum (Sec. 2, discrete system) for m targets: d_targets (m,)
+ * int64 indices into [0, n), or NULL for all (then m must equal n).  Sources
+ * are all n particles, the self term excluded by index.  precision STC_FP64
+ * or STC_FP32 (FP32 kernel, FP64 accumulation per tile of 256 sources).
+ * d_u is (m, 3).  Asynchronous on hip_stream; needs no context. */
+stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
+                      const double* d_area, int64_t m, const int64_t* d_targets,
+                      int32_t precision, int32_t denominator, double* d_u);
+
+/* Classical RK4 (Sec. 4) for n_steps steps of dt on (x, zeta):
+ *   dx/dt = u(x; zeta A),  dzeta/dt = -2 omega u_z  (Sec. 2, discrete system)
+ * Every stage is a full stc_velocity (tree rebuilt).  Stage positions are
+ * used as computed; after each step x <- x / |x|.  d_x, d_zeta are updated
+ * in place.  Units are the caller's (dt * omega dimensionless). */
+stc_status stc_rk4(stc_ctx* ctx, int64_t n, double* d_x, double* d_zeta, const double* d_area,
+                   double dt, double omega, int32_t n_steps);
+
+/* --- introspection (these synchronise the context stream) ------------------ */
+
+/* Waits for queued work; reports device-side error flags. */
+stc_status stc_sync(stc_ctx* ctx);
+
+/* counts[4]: list lengths PP, PC, CP, CC of the last traversal.  If
+ * kernel_evals != NULL, *kernel_evals[0..3] receive the number of kernel
+ * evaluations each list implies (PP: n_t n_s, minus n_t on self pairs; PC:
+ * n_t n_p; CP: n_p n_s; CC: n_p^2). */
+stc_status stc_list_counts(stc_ctx* ctx, int64_t counts[4], int64_t kernel_evals[4]);
+
+/* Copies list `type` as (target id, source id) pairs, sorted by (t, s), into
+ * h_pairs (2 * cap int64).  *n_out = list length (may exceed cap: then only
+ * cap pairs are written and STC_ERR_CAPACITY is returned). */
+stc_status stc_copy_list(stc_ctx* ctx, int32_t type, int64_t cap, int64_t* h_pairs,
+                         int64_t* n_out);
+
+/* Copies the tree: h_perm (n) = input index of the i-th particle in tree
+ * order; h_count (node_cap) = particle count of each node id.  Either may be
+ * NULL.  node_cap must be >= stc_total_nodes(max_level) if h_count != NULL. */
+stc_status stc_copy_tree(stc_ctx* ctx, int64_t n, int32_t* h_perm, int64_t node_cap,
+                         int32_t* h_count);
+
+/* Copies the proxy charges w (n_p) of one node (zero if the node has at most
+ * n_crit particles). */
+stc_status stc_copy_proxy_charges(stc_ctx* ctx, int64_t node_id, double* h_w);
+
+/* Host-only geometry introspection (no device work): vertices (9), the
+ * circumcentre (3) and radius (1) of a node, as used by the traversal. */
+stc_status stc_node_geometry(const stc_ctx* ctx, int64_t node_id, double* h_v9, double* h_c3,
+                             double* h_r);
+
+/* Host-only: builds the geometry of the complete tree down to max_level
+ * without a device (for checks on machines without a GPU).  h_v: 9 doubles
+ * per node, h_c: 3, h_r: 1; each array sized for stc_total_nodes(max_level). */
+stc_status stc_geometry_tables(int32_t max_level, double* h_v, double* h_c, double* h_r);
+
+/* Host-only: the reference interpolation points (n_p x 3 planar
+ * barycentrics) and the inverse reference Vandermonde matrix (n_p x n_p,
+ * row k = basis index, column m = point index) for degree d. */
+stc_status stc_reference_tables(int32_t degree, double* h_points, double* h_vinv);
+
+/* Phase timing.  stc_set_timing(ctx, k) with k > 0 creates HIP events for k
+ * evaluations; each following evaluation (stc_velocity, or the pipeline calls
+ * that make one up) records events on the context stream around its phases:
+ * 0 tree build, 1 upward pass, 2 traversal (incl. list sort), 3 near-side
+ * interactions (one kernel: PP and PC), 4 target-proxy interactions (one
+ * kernel: CP and CC), 5 interpolation to particles and output.  k = 0 turns
+ * timing off and frees the events.  stc_phase_times synchronises and returns
+ * the summed milliseconds per phase over the recorded evaluations (ms[6]) and
+ * their number; recording restarts afterwards.  Evaluations beyond k are not
+ * recorded. */
+stc_status stc_set_timing(stc_ctx* ctx, int32_t max_evals);
+stc_status stc_phase_times(stc_ctx* ctx, double ms[6], int64_t* n_evals);
+
+/* Message of the last error on this context ("" if none). */
+const char* stc_last_error(const stc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STC_H */

@@ -1,0 +1,682 @@
+// C ABI of the spherical tree code (declared in include/stc.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "stc.h"
+
+using namespace stc;
+
+struct stc_ctx {
+    stc_params p{};
+    int L = 0, np = 0, W = 0;
+    i64 n_max = 0, n_nodes = 0;
+    u32 cap = 0;
+    hipStream_t stream = nullptr;
+    int grid = 2048;
+    std::vector<NodeGeo> geo_host;
+    RefTables ref_host;
+    std::vector<i64> level_off_host;
+    // device buffers (all allocated in stc_create)
+    NodeGeo* geo = nullptr;
+    i64* level_off = nullptr;
+    double *ref_points = nullptr, *ref_vinv = nullptr, *ref_coef = nullptr;
+    int* ref_expo = nullptr;
+    u64 *keys_a = nullptr, *keys_b = nullptr, *keys_sorted = nullptr;
+    i32* perm = nullptr;
+    u32* leaf = nullptr;
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr, *sq = nullptr;
+    i32 *nbeg = nullptr, *nend = nullptr;
+    double *wq = nullptr, *alpha = nullptr, *Wacc = nullptr;
+    u64 *front0 = nullptr, *front1 = nullptr;
+    u64 *tlist_a = nullptr, *tlist_b = nullptr, *nlist_a = nullptr, *nlist_b = nullptr;
+    u64 *tlist = nullptr, *nlist = nullptr;
+    i32 *tseg_beg = nullptr, *tseg_end = nullptr, *nseg_beg = nullptr, *nseg_end = nullptr;
+    u32* counters = nullptr;
+    u32* flags = nullptr;
+    unsigned long long* evals = nullptr;
+    u32* hist = nullptr;
+    int hist_blocks = 0;
+    // RK4 buffers
+    double *rk_x = nullptr, *rk_z = nullptr, *rk_u = nullptr, *rk_xacc = nullptr, *rk_zacc = nullptr;
+    // phase timing: 7 events per recorded evaluation
+    std::vector<hipEvent_t> tev;
+    int t_max = 0, t_used = 0, t_phase = -1;
+    // state
+    i64 n = -1;
+    const double* x = nullptr;
+    bool have_tree = false, have_upward = false, have_lists = false;
+    std::vector<void*> allocs;
+    std::string err;
+};
+
+namespace {
+
+const char* kStatusText[] = {"ok", "invalid argument", "interaction list capacity exceeded", "HIP device error",
+                             "call out of order", "device allocation failed"};
+
+// Records the event that opens `phase` (and closes the previous one) of the
+// evaluation being recorded.  Phase 6 closes the evaluation.
+void mark(stc_ctx* c, int phase) {
+    if (c->t_max == 0 || c->t_used >= c->t_max) return;
+    (void)hipEventRecord(c->tev[(size_t)c->t_used * 7 + phase], c->stream);
+    if (phase == 6) ++c->t_used;
+}
+
+stc_status fail(stc_ctx* c, stc_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+stc_status check_launch(stc_ctx* c, const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, STC_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+    return STC_OK;
+}
+
+template <typename T>
+bool dalloc(stc_ctx* c, T** p, size_t count) {
+    if (count == 0) count = 1;
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, count * sizeof(T)) != hipSuccess) return false;
+    c->allocs.push_back(ptr);
+    *p = static_cast<T*>(ptr);
+    return true;
+}
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+int bits_for(i64 v) {
+    int b = 0;
+    while (((i64)1 << b) < v) ++b;
+    return b;
+}
+
+RefDev ref_dev(const stc_ctx* c) {
+    RefDev r;
+    r.points = c->ref_points;
+    r.vinv = c->ref_vinv;
+    r.expo = c->ref_expo;
+    r.coef = c->ref_coef;
+    r.degree = c->p.degree;
+    r.np = c->np;
+    return r;
+}
+
+EvalArgs eval_args(stc_ctx* c) {
+    EvalArgs a{};
+    a.tlist = c->tlist;
+    a.nlist = c->nlist;
+    a.counters = c->counters;
+    a.cap = c->cap;
+    a.W = c->W;
+    a.tseg_end = c->tseg_end;
+    a.nseg_beg = c->nseg_beg;
+    a.nseg_end = c->nseg_end;
+    a.nbeg = c->nbeg;
+    a.nend = c->nend;
+    a.geo = c->geo;
+    a.level_off_tab = c->level_off;
+    a.L = c->L;
+    a.sx = c->sx;
+    a.sy = c->sy;
+    a.sz = c->sz;
+    a.sq = c->sq;
+    a.wq = c->wq;
+    a.alpha = c->alpha;
+    a.Wacc = c->Wacc;
+    a.leaf = c->leaf;
+    a.perm = c->perm;
+    a.n = c->n;
+    a.ref = ref_dev(c);
+    a.precision = c->p.precision;
+    a.denominator = c->p.denominator;
+    a.grid = c->grid;
+    return a;
+}
+
+stc_status validate_params(const stc_params* p, i64 n_max) {
+    if (!p) return STC_ERR_INVALID_ARG;
+    if (!(p->theta > 0.0 && p->theta <= 1.0)) return STC_ERR_INVALID_ARG;
+    if (p->degree < 1 || p->degree > kMaxDegree) return STC_ERR_INVALID_ARG;
+    if (p->n_crit < 1) return STC_ERR_INVALID_ARG;
+    if (p->max_level < -1 || p->max_level > 12) return STC_ERR_INVALID_ARG;
+    if (p->precision != STC_FP64 && p->precision != STC_FP32) return STC_ERR_INVALID_ARG;
+    if (p->denominator != STC_DEN_DOT && p->denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
+    if (p->precision == STC_FP32 && p->denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
+    if (p->list_capacity < 0 || p->list_capacity > 0x7fffffffLL) return STC_ERR_INVALID_ARG;
+    if (n_max < 0 || n_max >= 0x7fffffffLL) return STC_ERR_INVALID_ARG;
+    return STC_OK;
+}
+
+stc_status do_build(stc_ctx* c, i64 n, const double* d_x) {
+    hipStream_t s = c->stream;
+    c->n = n;
+    c->x = d_x;
+    c->have_tree = true;
+    c->have_upward = false;
+    c->have_lists = false;
+    mark(c, 0);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nbeg), c->n_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nend), c->n_nodes, 0u);
+    if (n == 0) return check_launch(c, "tree_build");
+    launch_bin(s, d_x, n, c->geo, c->L, c->keys_a, c->flags);
+    radix_sort(s, c->keys_a, c->keys_b, nullptr, (u32)n, 32, 32 + 2 * c->L + 5, SortScratch{c->hist, c->hist_blocks},
+               &c->keys_sorted);
+    launch_gather(s, c->keys_sorted, n, d_x, c->perm, c->leaf, c->sx, c->sy, c->sz);
+    launch_node_ranges(s, c->leaf, n, c->L, c->nbeg, c->nend);
+    return check_launch(c, "tree_build");
+}
+
+stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
+    hipStream_t s = c->stream;
+    mark(c, 1);
+    launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sq);
+    if (c->n > 0)
+        launch_p2m(s, c->nbeg, c->nend, c->n_nodes, c->p.n_crit, c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c), c->wq);
+    c->have_upward = true;
+    return check_launch(c, "upward");
+}
+
+stc_status do_traverse(stc_ctx* c) {
+    hipStream_t s = c->stream;
+    mark(c, 2);
+    launch_traverse(s, c->nbeg, c->nend, c->level_off, c->L, c->geo, c->p.theta, c->p.n_crit, c->W, c->front0,
+                    c->front1, c->cap, c->tlist_a, c->nlist_a, c->counters);
+    const int bits = 2 * c->W + 1;
+    SortScratch sc{c->hist, c->hist_blocks};
+    radix_sort(s, c->tlist_a, c->tlist_b, c->counters + C_TLIST, c->cap, 0, bits, sc, &c->tlist);
+    radix_sort(s, c->nlist_a, c->nlist_b, c->counters + C_NLIST, c->cap, 0, bits, sc, &c->nlist);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_beg), c->n_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_end), c->n_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_beg), c->n_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_end), c->n_nodes, 0u);
+    launch_segments(s, c->tlist, c->counters + C_TLIST, c->cap, c->W, c->tseg_beg, c->tseg_end);
+    launch_segments(s, c->nlist, c->counters + C_NLIST, c->cap, c->W, c->nseg_beg, c->nseg_end);
+    c->have_lists = true;
+    return check_launch(c, "traverse");
+}
+
+stc_status do_eval(stc_ctx* c, bool near, bool far, double* d_u, bool accumulate) {
+    if (c->n == 0) return STC_OK;
+    hipStream_t s = c->stream;
+    EvalArgs a = eval_args(c);
+    launch_fill_f64(s, c->Wacc, 3 * c->n, 0.0);
+    u32 mask = (near ? 1u : 0u) | (far ? 2u : 0u);
+    mark(c, 3);
+    launch_near(s, a, mask);
+    mark(c, 4);
+    if (far) launch_far_targets(s, a);
+    mark(c, 5);
+    launch_l2p_finalize(s, a, far, d_u, accumulate);
+    mark(c, 6);
+    return check_launch(c, "eval");
+}
+
+stc_status check_ready(stc_ctx* c, bool need_lists) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (!c->have_tree) return fail(c, STC_ERR_STATE, "no tree: call stc_tree_build first");
+    if (need_lists && !(c->have_upward && c->have_lists))
+        return fail(c, STC_ERR_STATE, "call stc_upward and stc_traverse before evaluating");
+    return STC_OK;
+}
+
+// RK4 stage helpers ---------------------------------------------------------
+__global__ void k_rk4_combine(i64 n, const double* __restrict__ x0, const double* __restrict__ z0,
+                              const double* __restrict__ u, double omega, double c_next, double w_acc,
+                              double* __restrict__ xs, double* __restrict__ zs, double* __restrict__ xacc,
+                              double* __restrict__ zacc, int first) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dz = -2.0 * omega * u[3 * i + 2];
+    for (int c = 0; c < 3; ++c) {
+        const double base = first ? x0[3 * i + c] : xacc[3 * i + c];
+        xacc[3 * i + c] = base + w_acc * u[3 * i + c];
+        xs[3 * i + c] = x0[3 * i + c] + c_next * u[3 * i + c];
+    }
+    const double zb = first ? z0[i] : zacc[i];
+    zacc[i] = zb + w_acc * dz;
+    zs[i] = z0[i] + c_next * dz;
+}
+
+__global__ void k_rk4_finish(i64 n, const double* __restrict__ xacc, const double* __restrict__ zacc,
+                             double* __restrict__ x, double* __restrict__ z) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = xacc[3 * i], b = xacc[3 * i + 1], cc = xacc[3 * i + 2];
+    const double nr = sqrt((a * a + b * b) + cc * cc);
+    x[3 * i] = a / nr;
+    x[3 * i + 1] = b / nr;
+    x[3 * i + 2] = cc / nr;
+    z[i] = zacc[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stc_status_string(int32_t status) {
+    if (status < 0 || status > 5) return "unknown status";
+    return kStatusText[status];
+}
+
+stc_status stc_default_params(stc_params* p) {
+    if (!p) return STC_ERR_INVALID_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->theta = 0.7;
+    p->degree = 8;
+    p->n_crit = 64;
+    p->max_level = -1;
+    p->precision = STC_FP64;
+    p->denominator = STC_DEN_DOT;
+    p->list_capacity = 0;
+    return STC_OK;
+}
+
+int32_t stc_n_basis(int32_t degree) {
+    if (degree < 1 || degree > kMaxDegree) return 0;
+    return (degree + 1) * (degree + 2) / 2;
+}
+
+int64_t stc_total_nodes(int32_t max_level) {
+    if (max_level < 0 || max_level > 12) return 0;
+    return stc::total_nodes(max_level);
+}
+
+int32_t stc_default_max_level(int64_t n_max, int32_t n_crit) {
+    if (n_crit < 1) n_crit = 1;
+    int lvl = 0;
+    while ((i64)20 * ((i64)1 << (2 * lvl)) * n_crit < n_max && lvl < 30) ++lvl;
+    return std::min(12, lvl + 2);
+}
+
+stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_ctx** out) {
+    if (!out) return STC_ERR_INVALID_ARG;
+    *out = nullptr;
+    stc_status st = validate_params(p, n_max);
+    if (st != STC_OK) return st;
+    stc_ctx* c = new (std::nothrow) stc_ctx();
+    if (!c) return STC_ERR_ALLOC;
+    c->p = *p;
+    c->n_max = n_max;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->L = p->max_level >= 0 ? p->max_level : stc_default_max_level(n_max, p->n_crit);
+    c->p.max_level = c->L;
+    c->np = stc_n_basis(p->degree);
+    c->n_nodes = stc::total_nodes(c->L);
+    c->W = std::max(1, bits_for(c->n_nodes));
+    i64 cap = p->list_capacity > 0 ? p->list_capacity : std::max<i64>(65536, 16 * n_max);
+    c->cap = (u32)std::min<i64>(cap, 0x7fffffffLL);
+    try {
+        build_tree_geometry(c->L, c->geo_host);
+        if (!build_reference_tables(p->degree, c->ref_host)) {
+            delete c;
+            return STC_ERR_INVALID_ARG;
+        }
+    } catch (...) {
+        delete c;
+        return STC_ERR_ALLOC;
+    }
+    c->level_off_host.resize(c->L + 2);
+    for (int l = 0; l <= c->L + 1; ++l) c->level_off_host[l] = level_offset(l);
+    const i64 nm = std::max<i64>(n_max, 1);
+    c->hist_blocks = (int)((std::max<i64>(c->cap, nm) + 4095) / 4096);
+    bool ok = dalloc(c, &c->geo, c->geo_host.size()) && dalloc(c, &c->level_off, c->level_off_host.size()) &&
+              dalloc(c, &c->ref_points, 3 * c->np) && dalloc(c, &c->ref_vinv, (size_t)c->np * c->np) &&
+              dalloc(c, &c->ref_coef, c->np) && dalloc(c, &c->ref_expo, 3 * c->np) &&
+              dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) && dalloc(c, &c->perm, nm) &&
+              dalloc(c, &c->leaf, nm) && dalloc(c, &c->sx, nm) && dalloc(c, &c->sy, nm) && dalloc(c, &c->sz, nm) &&
+              dalloc(c, &c->sq, nm) && dalloc(c, &c->nbeg, c->n_nodes) && dalloc(c, &c->nend, c->n_nodes) &&
+              dalloc(c, &c->wq, (size_t)c->n_nodes * c->np) && dalloc(c, &c->alpha, (size_t)c->n_nodes * c->np * 3) &&
+              dalloc(c, &c->Wacc, 3 * nm) && dalloc(c, &c->front0, c->cap) && dalloc(c, &c->front1, c->cap) &&
+              dalloc(c, &c->tlist_a, c->cap) && dalloc(c, &c->tlist_b, c->cap) && dalloc(c, &c->nlist_a, c->cap) &&
+              dalloc(c, &c->nlist_b, c->cap) && dalloc(c, &c->tseg_beg, c->n_nodes) &&
+              dalloc(c, &c->tseg_end, c->n_nodes) && dalloc(c, &c->nseg_beg, c->n_nodes) &&
+              dalloc(c, &c->nseg_end, c->n_nodes) && dalloc(c, &c->counters, C_COUNT) && dalloc(c, &c->flags, 4) &&
+              dalloc(c, &c->evals, 8) && dalloc(c, &c->hist, (size_t)256 * c->hist_blocks) &&
+              dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
+              dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm);
+    if (!ok) {
+        stc_destroy(c);
+        return STC_ERR_ALLOC;
+    }
+    c->tlist = c->tlist_a;
+    c->nlist = c->nlist_a;
+    hipStream_t s = c->stream;
+    bool cp = hipMemcpyAsync(c->geo, c->geo_host.data(), c->geo_host.size() * sizeof(NodeGeo), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->level_off, c->level_off_host.data(), c->level_off_host.size() * sizeof(i64), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->ref_points, c->ref_host.points.data(), 3 * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->ref_vinv, c->ref_host.vinv.data(), (size_t)c->np * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->ref_coef, c->ref_host.coef.data(), c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->ref_expo, c->ref_host.expo.data(), 3 * c->np * sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess;
+    launch_fill_u32(s, c->counters, C_COUNT, 0u);
+    launch_fill_u32(s, c->flags, 4, 0u);
+    if (!cp || hipStreamSynchronize(s) != hipSuccess) {
+        stc_destroy(c);
+        return STC_ERR_DEVICE;
+    }
+    // persistent segment kernels: a multiple of 8 workgroups (one per XCD slot)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    c->grid = std::max(8, (cus * 16 / 8) * 8);
+    *out = c;
+    return STC_OK;
+}
+
+stc_status stc_destroy(stc_ctx* c) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    for (void* p : c->allocs) (void)hipFree(p);
+    delete c;
+    return STC_OK;
+}
+
+stc_status stc_set_stream(stc_ctx* c, void* hip_stream) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return STC_OK;
+}
+
+stc_status stc_get_params(const stc_ctx* c, stc_params* out) {
+    if (!c || !out) return STC_ERR_INVALID_ARG;
+    *out = c->p;
+    return STC_OK;
+}
+
+stc_status stc_tree_build(stc_ctx* c, int64_t n, const double* d_x) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (n < 0 || n > c->n_max) return fail(c, STC_ERR_INVALID_ARG, "n out of range [0, n_max]");
+    if (n > 0 && (!d_x || !aligned8(d_x))) return fail(c, STC_ERR_INVALID_ARG, "d_x is NULL or misaligned");
+    return do_build(c, n, d_x);
+}
+
+stc_status stc_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
+    stc_status st = check_ready(c, false);
+    if (st != STC_OK) return st;
+    if (c->n > 0 && (!d_zeta || !d_area || !aligned8(d_zeta) || !aligned8(d_area)))
+        return fail(c, STC_ERR_INVALID_ARG, "d_zeta / d_area NULL or misaligned");
+    return do_upward(c, d_zeta, d_area);
+}
+
+stc_status stc_traverse(stc_ctx* c) {
+    stc_status st = check_ready(c, false);
+    if (st != STC_OK) return st;
+    return do_traverse(c);
+}
+
+stc_status stc_eval_near(stc_ctx* c, double* d_u, int32_t accumulate) {
+    stc_status st = check_ready(c, true);
+    if (st != STC_OK) return st;
+    if (c->n > 0 && (!d_u || !aligned8(d_u))) return fail(c, STC_ERR_INVALID_ARG, "d_u NULL or misaligned");
+    return do_eval(c, true, false, d_u, accumulate != 0);
+}
+
+stc_status stc_eval_far(stc_ctx* c, double* d_u, int32_t accumulate) {
+    stc_status st = check_ready(c, true);
+    if (st != STC_OK) return st;
+    if (c->n > 0 && (!d_u || !aligned8(d_u))) return fail(c, STC_ERR_INVALID_ARG, "d_u NULL or misaligned");
+    return do_eval(c, false, true, d_u, accumulate != 0);
+}
+
+stc_status stc_velocity(stc_ctx* c, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
+                        double* d_u) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (n < 0 || n > c->n_max) return fail(c, STC_ERR_INVALID_ARG, "n out of range [0, n_max]");
+    if (n > 0 && (!d_x || !d_zeta || !d_area || !d_u || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area) ||
+                  !aligned8(d_u)))
+        return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
+    stc_status st = do_build(c, n, d_x);
+    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
+    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_eval(c, true, true, d_u, false);
+    return st;
+}
+
+stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
+                      int64_t m, const int64_t* d_targets, int32_t precision, int32_t denominator, double* d_u) {
+    if (n < 0 || m < 0 || n >= 0x7fffffffLL) return STC_ERR_INVALID_ARG;
+    if (precision != STC_FP64 && precision != STC_FP32) return STC_ERR_INVALID_ARG;
+    if (denominator != STC_DEN_DOT && denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
+    if (precision == STC_FP32 && denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
+    if (!d_targets && m != n) return STC_ERR_INVALID_ARG;
+    if (m == 0) return STC_OK;
+    if (n == 0 || !d_x || !d_zeta || !d_area || !d_u || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area) ||
+        !aligned8(d_u) || (d_targets && !aligned8(d_targets)))
+        return STC_ERR_INVALID_ARG;
+    launch_direct(static_cast<hipStream_t>(hip_stream), n, d_x, d_zeta, d_area, m, d_targets, precision, denominator,
+                  d_u);
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
+stc_status stc_rk4(stc_ctx* c, int64_t n, double* d_x, double* d_zeta, const double* d_area, double dt, double omega,
+                   int32_t n_steps) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (n < 0 || n > c->n_max || n_steps < 0 || !std::isfinite(dt) || !std::isfinite(omega))
+        return fail(c, STC_ERR_INVALID_ARG, "bad n, n_steps, dt or omega");
+    if (n == 0 || n_steps == 0) return STC_OK;
+    if (!d_x || !d_zeta || !d_area || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area))
+        return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
+    hipStream_t s = c->stream;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    // stage nodes 0, 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6
+    const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
+    const double wacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    for (int step = 0; step < n_steps; ++step) {
+        const double* xs = d_x;
+        const double* zs = d_zeta;
+        for (int stg = 0; stg < 4; ++stg) {
+            stc_status st = stc_velocity(c, n, xs, zs, d_area, c->rk_u);
+            if (st != STC_OK) return st;
+            hipLaunchKernelGGL(k_rk4_combine, g, b, 0, s, (i64)n, d_x, d_zeta, c->rk_u, omega, cnext[stg], wacc[stg],
+                               c->rk_x, c->rk_z, c->rk_xacc, c->rk_zacc, stg == 0 ? 1 : 0);
+            xs = c->rk_x;
+            zs = c->rk_z;
+        }
+        hipLaunchKernelGGL(k_rk4_finish, g, b, 0, s, (i64)n, c->rk_xacc, c->rk_zacc, d_x, d_zeta);
+        stc_status st = check_launch(c, "rk4");
+        if (st != STC_OK) return st;
+    }
+    c->have_tree = c->have_upward = c->have_lists = false;  // stage data, not the final state
+    return STC_OK;
+}
+
+stc_status stc_sync(stc_ctx* c) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, STC_ERR_DEVICE, "stream synchronisation failed");
+    u32 h[C_COUNT];
+    u32 f[4];
+    if (hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(f, c->flags, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "reading device flags failed");
+    if (h[C_OVERFLOW] || h[C_TLIST] > c->cap || h[C_NLIST] > c->cap)
+        return fail(c, STC_ERR_CAPACITY, "interaction list or frontier exceeded list_capacity");
+    if (f[0]) return fail(c, STC_ERR_INVALID_ARG, "non-finite particle position");
+    return STC_OK;
+}
+
+stc_status stc_list_counts(stc_ctx* c, int64_t counts[4], int64_t kernel_evals[4]) {
+    stc_status st = check_ready(c, true);
+    if (st != STC_OK) return st;
+    st = stc_sync(c);
+    if (st != STC_OK) return st;
+    unsigned long long h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    (void)hipMemsetAsync(c->evals, 0, sizeof(h), c->stream);
+    launch_count_evals(c->stream, c->tlist, c->counters + C_TLIST, c->cap, c->W, c->np, c->nbeg, c->nend, 0, c->evals);
+    launch_count_evals(c->stream, c->nlist, c->counters + C_NLIST, c->cap, c->W, c->np, c->nbeg, c->nend, 1,
+                       c->evals + 4);
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipMemcpy(h, c->evals, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "counting list work failed");
+    if (counts) {
+        counts[0] = (int64_t)h[2];
+        counts[1] = (int64_t)h[3];
+        counts[2] = (int64_t)h[6];
+        counts[3] = (int64_t)h[7];
+    }
+    if (kernel_evals) {
+        kernel_evals[0] = (int64_t)h[0];
+        kernel_evals[1] = (int64_t)h[1];
+        kernel_evals[2] = (int64_t)h[4];
+        kernel_evals[3] = (int64_t)h[5];
+    }
+    return STC_OK;
+}
+
+stc_status stc_copy_list(stc_ctx* c, int32_t type, int64_t cap, int64_t* h_pairs, int64_t* n_out) {
+    stc_status st = check_ready(c, true);
+    if (st != STC_OK) return st;
+    if (type < 0 || type > 3 || cap < 0 || (cap > 0 && !h_pairs) || !n_out)
+        return fail(c, STC_ERR_INVALID_ARG, "bad list type or buffer");
+    st = stc_sync(c);
+    if (st != STC_OK) return st;
+    u32 cnt[2];
+    if (hipMemcpy(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "reading counters failed");
+    const bool tl = type <= 1;
+    const u32 len = std::min(tl ? cnt[0] : cnt[1], c->cap);
+    std::vector<u64> buf(len);
+    if (len && hipMemcpy(buf.data(), tl ? c->tlist : c->nlist, len * sizeof(u64), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "copying list failed");
+    const u64 mask = ((u64)1 << c->W) - 1;
+    const u64 want = (u64)(type & 1);
+    int64_t k = 0;
+    for (u32 i = 0; i < len; ++i) {
+        const u64 key = buf[i];
+        if (((key >> c->W) & 1u) != want) continue;
+        if (k < cap) {
+            h_pairs[2 * k] = (int64_t)(key >> (c->W + 1));
+            h_pairs[2 * k + 1] = (int64_t)(key & mask);
+        }
+        ++k;
+    }
+    *n_out = k;
+    return k > cap ? fail(c, STC_ERR_CAPACITY, "h_pairs too small") : STC_OK;
+}
+
+stc_status stc_copy_tree(stc_ctx* c, int64_t n, int32_t* h_perm, int64_t node_cap, int32_t* h_count) {
+    stc_status st = check_ready(c, false);
+    if (st != STC_OK) return st;
+    if (h_perm && n != c->n) return fail(c, STC_ERR_INVALID_ARG, "n differs from the built tree");
+    if (h_count && node_cap < c->n_nodes) return fail(c, STC_ERR_INVALID_ARG, "node_cap too small");
+    st = stc_sync(c);
+    if (st != STC_OK) return st;
+    if (h_perm && n > 0 && hipMemcpy(h_perm, c->perm, n * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "copying perm failed");
+    if (h_count) {
+        std::vector<i32> b(c->n_nodes), e(c->n_nodes);
+        if (hipMemcpy(b.data(), c->nbeg, c->n_nodes * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(e.data(), c->nend, c->n_nodes * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, STC_ERR_DEVICE, "copying node ranges failed");
+        for (i64 i = 0; i < c->n_nodes; ++i) h_count[i] = e[i] - b[i];
+    }
+    return STC_OK;
+}
+
+stc_status stc_copy_proxy_charges(stc_ctx* c, int64_t node_id, double* h_w) {
+    stc_status st = check_ready(c, false);
+    if (st != STC_OK) return st;
+    if (!c->have_upward) return fail(c, STC_ERR_STATE, "call stc_upward first");
+    if (node_id < 0 || node_id >= c->n_nodes || !h_w) return fail(c, STC_ERR_INVALID_ARG, "bad node id or buffer");
+    st = stc_sync(c);
+    if (st != STC_OK) return st;
+    i32 b = 0, e = 0;
+    if (hipMemcpy(&b, c->nbeg + node_id, sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(&e, c->nend + node_id, sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "copy failed");
+    if (e - b <= c->p.n_crit) {
+        for (int m = 0; m < c->np; ++m) h_w[m] = 0.0;
+        return STC_OK;
+    }
+    if (hipMemcpy(h_w, c->wq + (size_t)node_id * c->np, c->np * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "copy failed");
+    return STC_OK;
+}
+
+stc_status stc_node_geometry(const stc_ctx* c, int64_t node_id, double* h_v9, double* h_c3, double* h_r) {
+    if (!c || node_id < 0 || node_id >= c->n_nodes) return STC_ERR_INVALID_ARG;
+    const NodeGeo& g = c->geo_host[node_id];
+    if (h_v9)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) h_v9[3 * a + b] = g.v[a][b];
+    if (h_c3)
+        for (int b = 0; b < 3; ++b) h_c3[b] = g.c[b];
+    if (h_r) *h_r = g.r;
+    return STC_OK;
+}
+
+stc_status stc_geometry_tables(int32_t max_level, double* h_v, double* h_c, double* h_r) {
+    if (max_level < 0 || max_level > 12) return STC_ERR_INVALID_ARG;
+    std::vector<NodeGeo> geo;
+    try {
+        build_tree_geometry(max_level, geo);
+    } catch (...) {
+        return STC_ERR_ALLOC;
+    }
+    for (size_t i = 0; i < geo.size(); ++i) {
+        if (h_v)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) h_v[9 * i + 3 * a + b] = geo[i].v[a][b];
+        if (h_c)
+            for (int b = 0; b < 3; ++b) h_c[3 * i + b] = geo[i].c[b];
+        if (h_r) h_r[i] = geo[i].r;
+    }
+    return STC_OK;
+}
+
+stc_status stc_reference_tables(int32_t degree, double* h_points, double* h_vinv) {
+    RefTables t;
+    if (!build_reference_tables(degree, t) || degree > kMaxDegree) return STC_ERR_INVALID_ARG;
+    if (h_points) std::memcpy(h_points, t.points.data(), t.points.size() * sizeof(double));
+    if (h_vinv) std::memcpy(h_vinv, t.vinv.data(), t.vinv.size() * sizeof(double));
+    return STC_OK;
+}
+
+stc_status stc_set_timing(stc_ctx* c, int32_t max_evals) {
+    if (!c || max_evals < 0 || max_evals > 100000) return STC_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    c->tev.clear();
+    c->t_max = c->t_used = 0;
+    if (max_evals == 0) return STC_OK;
+    c->tev.resize((size_t)max_evals * 7);
+    for (auto& e : c->tev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            return fail(c, STC_ERR_DEVICE, "hipEventCreate failed");
+        }
+    c->t_max = max_evals;
+    return STC_OK;
+}
+
+stc_status stc_phase_times(stc_ctx* c, double ms[6], int64_t* n_evals) {
+    if (!c || !ms || !n_evals) return STC_ERR_INVALID_ARG;
+    for (int p = 0; p < 6; ++p) ms[p] = 0.0;
+    *n_evals = 0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, STC_ERR_DEVICE, "synchronisation failed");
+    for (int k = 0; k < c->t_used; ++k) {
+        for (int p = 0; p < 6; ++p) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, c->tev[(size_t)k * 7 + p], c->tev[(size_t)k * 7 + p + 1]) != hipSuccess)
+                return fail(c, STC_ERR_DEVICE, "event timing failed (was every phase of the evaluation run?)");
+            ms[p] += t;
+        }
+    }
+    *n_evals = c->t_used;
+    c->t_used = 0;
+    return STC_OK;
+}
+
+const char* stc_last_error(const stc_ctx* c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,333 @@
+"""Python binding of the C ABI in include/stc.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libstc.so`` built in this package
+directory; if it is missing, importing this module raises.  Device arrays are
+torch CUDA tensors (ROCm), FP64 and contiguous; calls are enqueued on the
+current torch stream unless a stream is given.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstc.so")
+
+FP64, FP32 = 0, 1
+DEN_DOT, DEN_DIST2 = 0, 1
+PP, PC, CP, CC = 0, 1, 2, 3
+LIST_NAMES = ("PP", "PC", "CP", "CC")
+
+
+class StcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(message)
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("degree", ctypes.c_int32), ("n_crit", ctypes.c_int32),
+                ("max_level", ctypes.c_int32), ("precision", ctypes.c_int32), ("denominator", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libstc.so is not built: run `python -m paper_2401_07361_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, VP = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    PI64 = ctypes.POINTER(ctypes.c_int64)
+    PD = ctypes.POINTER(ctypes.c_double)
+    PI32 = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "stc_status_string": (ctypes.c_char_p, [I32]),
+        "stc_default_params": (I32, [ctypes.POINTER(Params)]),
+        "stc_n_basis": (I32, [I32]),
+        "stc_total_nodes": (I64, [I32]),
+        "stc_default_max_level": (I32, [I64, I32]),
+        "stc_create": (I32, [ctypes.POINTER(Params), I64, VP, ctypes.POINTER(P)]),
+        "stc_destroy": (I32, [P]),
+        "stc_set_stream": (I32, [P, VP]),
+        "stc_get_params": (I32, [P, ctypes.POINTER(Params)]),
+        "stc_tree_build": (I32, [P, I64, VP]),
+        "stc_upward": (I32, [P, VP, VP]),
+        "stc_traverse": (I32, [P]),
+        "stc_eval_near": (I32, [P, VP, I32]),
+        "stc_eval_far": (I32, [P, VP, I32]),
+        "stc_velocity": (I32, [P, I64, VP, VP, VP, VP]),
+        "stc_direct": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
+        "stc_rk4": (I32, [P, I64, VP, VP, VP, D, D, I32]),
+        "stc_sync": (I32, [P]),
+        "stc_list_counts": (I32, [P, PI64, PI64]),
+        "stc_copy_list": (I32, [P, I32, I64, PI64, PI64]),
+        "stc_copy_tree": (I32, [P, I64, PI32, I64, PI32]),
+        "stc_copy_proxy_charges": (I32, [P, I64, PD]),
+        "stc_node_geometry": (I32, [P, I64, PD, PD, PD]),
+        "stc_geometry_tables": (I32, [I32, PD, PD, PD]),
+        "stc_reference_tables": (I32, [I32, PD, PD]),
+        "stc_set_timing": (I32, [P, I32]),
+        "stc_phase_times": (I32, [P, PD, PI64]),
+        "stc_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+#: every function the header declares (checked by the CPU test-suite)
+EXPORTED = tuple(n for n in dir(_lib) if n.startswith("stc_"))
+
+
+def library():
+    return _lib
+
+
+def status_string(st):
+    return _lib.stc_status_string(st).decode()
+
+
+def _check(st, ctx=None):
+    if st != 0:
+        msg = status_string(st)
+        if ctx is not None:
+            detail = _lib.stc_last_error(ctx).decode()
+            if detail:
+                msg = msg + ": " + detail
+        raise StcError(st, msg)
+
+
+def _dptr(t, name, dtype=None, numel=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def n_basis(degree):
+    return int(_lib.stc_n_basis(degree))
+
+
+def total_nodes(max_level):
+    return int(_lib.stc_total_nodes(max_level))
+
+
+def default_max_level(n, n_crit):
+    return int(_lib.stc_default_max_level(n, n_crit))
+
+
+def geometry_tables(max_level):
+    """Host-only: (vertices (M,3,3), centres (M,3), radii (M,)) of every node."""
+    m = total_nodes(max_level)
+    v = np.zeros((m, 3, 3))
+    c = np.zeros((m, 3))
+    r = np.zeros(m)
+    PD = ctypes.POINTER(ctypes.c_double)
+    _check(_lib.stc_geometry_tables(max_level, v.ctypes.data_as(PD), c.ctypes.data_as(PD), r.ctypes.data_as(PD)))
+    return v, c, r
+
+
+def reference_tables(degree):
+    """Host-only: (points (np,3), V_ref^{-1} (np,np), [k, m])."""
+    npt = n_basis(degree)
+    if npt == 0:
+        raise ValueError("degree out of range")
+    pts = np.zeros((npt, 3))
+    vinv = np.zeros((npt, npt))
+    PD = ctypes.POINTER(ctypes.c_double)
+    _check(_lib.stc_reference_tables(degree, pts.ctypes.data_as(PD), vinv.ctypes.data_as(PD)))
+    return pts, vinv
+
+
+def _prec(p):
+    return {"fp64": FP64, "fp32": FP32, FP64: FP64, FP32: FP32}[p]
+
+
+def _den(d):
+    return {"dot": DEN_DOT, "dist2": DEN_DIST2, DEN_DOT: DEN_DOT, DEN_DIST2: DEN_DIST2}[d]
+
+
+def direct(x, zeta, area, targets=None, precision="fp64", denominator="dot", out=None, stream=None):
+    """Direct O(N^2) velocity at `targets` (int64 CUDA tensor, or None = all)."""
+    import torch
+    n = x.shape[0]
+    m = n if targets is None else targets.numel()
+    if out is None:
+        out = torch.empty((m, 3), dtype=torch.float64, device=x.device)
+    st = _lib.stc_direct(_stream(stream), n, _dptr(x, "x", torch.float64, 3 * n),
+                         _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n), m,
+                         _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
+                         _dptr(out, "out", torch.float64, 3 * m))
+    _check(st)
+    return out
+
+
+class Context:
+    """A tree-code context for up to n_max particles (stc_create)."""
+
+    def __init__(self, n_max, theta=0.7, degree=8, n_crit=64, max_level=-1, precision="fp64",
+                 denominator="dot", list_capacity=0, stream=None):
+        p = Params()
+        _lib.stc_default_params(ctypes.byref(p))
+        p.theta, p.degree, p.n_crit, p.max_level = theta, degree, n_crit, max_level
+        p.precision, p.denominator, p.list_capacity = _prec(precision), _den(denominator), list_capacity
+        self._ctx = ctypes.c_void_p()
+        self._stream_obj = stream
+        _check(_lib.stc_create(ctypes.byref(p), n_max, _stream(stream), ctypes.byref(self._ctx)))
+        q = Params()
+        _lib.stc_get_params(self._ctx, ctypes.byref(q))
+        self.theta, self.degree, self.n_crit, self.max_level = q.theta, q.degree, q.n_crit, q.max_level
+        self.precision, self.denominator = q.precision, q.denominator
+        self.n_max = n_max
+        self.np = n_basis(q.degree)
+        self.n_nodes = total_nodes(q.max_level)
+        self._keep = None
+        self.n = None
+
+    def close(self):
+        if self._ctx:
+            _lib.stc_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream):
+        _check(_lib.stc_set_stream(self._ctx, _stream(stream)), self._ctx)
+
+    # pipeline -------------------------------------------------------------------
+    def tree_build(self, x):
+        import torch
+        n = x.shape[0]
+        _check(_lib.stc_tree_build(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n)), self._ctx)
+        self._keep = x
+        self.n = n
+
+    def upward(self, zeta, area):
+        import torch
+        _check(_lib.stc_upward(self._ctx, _dptr(zeta, "zeta", torch.float64, self.n),
+                               _dptr(area, "area", torch.float64, self.n)), self._ctx)
+
+    def traverse(self):
+        _check(_lib.stc_traverse(self._ctx), self._ctx)
+
+    def _out(self, out):
+        import torch
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64, device=self._keep.device)
+        return out
+
+    def eval_near(self, out=None, accumulate=False):
+        import torch
+        out = self._out(out)
+        _check(_lib.stc_eval_near(self._ctx, _dptr(out, "out", torch.float64, 3 * self.n), int(accumulate)), self._ctx)
+        return out
+
+    def eval_far(self, out=None, accumulate=False):
+        import torch
+        out = self._out(out)
+        _check(_lib.stc_eval_far(self._ctx, _dptr(out, "out", torch.float64, 3 * self.n), int(accumulate)), self._ctx)
+        return out
+
+    def velocity(self, x, zeta, area, out=None):
+        import torch
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        st = _lib.stc_velocity(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n), _dptr(zeta, "zeta", torch.float64, n),
+                               _dptr(area, "area", torch.float64, n), _dptr(out, "out", torch.float64, 3 * n))
+        _check(st, self._ctx)
+        self._keep = x
+        self.n = n
+        return out
+
+    def rk4(self, x, zeta, area, dt, omega, n_steps):
+        import torch
+        n = x.shape[0]
+        st = _lib.stc_rk4(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n), _dptr(zeta, "zeta", torch.float64, n),
+                          _dptr(area, "area", torch.float64, n), float(dt), float(omega), int(n_steps))
+        _check(st, self._ctx)
+
+    # timing -------------------------------------------------------------------------
+    PHASES = ("build", "upward", "traverse", "near", "far_targets", "l2p")
+
+    def set_timing(self, max_evals):
+        _check(_lib.stc_set_timing(self._ctx, int(max_evals)), self._ctx)
+
+    def phase_times(self):
+        """(dict phase -> summed ms, number of evaluations recorded)."""
+        ms = (ctypes.c_double * 6)()
+        k = ctypes.c_int64(0)
+        _check(_lib.stc_phase_times(self._ctx, ms, ctypes.byref(k)), self._ctx)
+        return dict(zip(self.PHASES, list(ms))), k.value
+
+    # introspection ----------------------------------------------------------------
+    def sync(self):
+        _check(_lib.stc_sync(self._ctx), self._ctx)
+
+    def list_counts(self):
+        c = (ctypes.c_int64 * 4)()
+        e = (ctypes.c_int64 * 4)()
+        _check(_lib.stc_list_counts(self._ctx, c, e), self._ctx)
+        return dict(zip(LIST_NAMES, list(c))), dict(zip(LIST_NAMES, list(e)))
+
+    def copy_list(self, kind):
+        k = LIST_NAMES.index(kind) if isinstance(kind, str) else int(kind)
+        nout = ctypes.c_int64(0)
+        _check(_lib.stc_copy_list(self._ctx, k, 0, None, ctypes.byref(nout)), self._ctx)
+        buf = np.zeros((max(nout.value, 1), 2), dtype=np.int64)
+        PI64 = ctypes.POINTER(ctypes.c_int64)
+        _check(_lib.stc_copy_list(self._ctx, k, nout.value, buf.ctypes.data_as(PI64), ctypes.byref(nout)), self._ctx)
+        return buf[:nout.value]
+
+    def copy_tree(self):
+        perm = np.zeros(max(self.n, 1), dtype=np.int32)
+        cnt = np.zeros(self.n_nodes, dtype=np.int32)
+        PI32 = ctypes.POINTER(ctypes.c_int32)
+        _check(_lib.stc_copy_tree(self._ctx, self.n, perm.ctypes.data_as(PI32), self.n_nodes,
+                                  cnt.ctypes.data_as(PI32)), self._ctx)
+        return perm[:self.n], cnt
+
+    def proxy_charges(self, node_id):
+        w = np.zeros(self.np)
+        _check(_lib.stc_copy_proxy_charges(self._ctx, node_id, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               self._ctx)
+        return w
+
+    def node_geometry(self, node_id):
+        v = np.zeros(9)
+        c = np.zeros(3)
+        r = ctypes.c_double(0)
+        PD = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.stc_node_geometry(self._ctx, node_id, v.ctypes.data_as(PD), c.ctypes.data_as(PD),
+                                      ctypes.byref(r)))
+        return v.reshape(3, 3), c, r.value
