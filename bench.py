@@ -68,8 +68,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--theta", type=float, default=0.6)
-    ap.add_argument("--degree", type=int, default=12)
+    ap.add_argument("--theta", type=float, default=0.7)
+    ap.add_argument("--degree", type=int, default=10)
     ap.add_argument("--n-crit", type=int, default=64)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)

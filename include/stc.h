@@ -175,7 +175,8 @@ stc_status stc_list_counts(stc_ctx* ctx, int64_t counts[4], int64_t kernel_evals
 
 /* Copies list `type` as (target id, source id) pairs, sorted by (t, s), into
  * h_pairs (2 * cap int64).  *n_out = list length (may exceed cap: then only
- * cap pairs are written and STC_ERR_CAPACITY is returned). */
+ * cap pairs are written and STC_ERR_CAPACITY is returned).  With h_pairs NULL
+ * and cap 0 it only reports the length. */
 stc_status stc_copy_list(stc_ctx* ctx, int32_t type, int64_t cap, int64_t* h_pairs,
                          int64_t* n_out);
 

