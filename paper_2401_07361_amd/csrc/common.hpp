@@ -28,10 +28,17 @@ enum Counter : int {
     C_COUNT = 64
 };
 
+// An interpolation point of a node with its proxy charge (written by the
+// upward pass for every node with more than N_T particles).
+struct Prox {
+    double x, y, z, w;
+};
+
 // Interpolation tables on the device.
 struct RefDev {
     const double* points;  // np x 3
     const double* vinv;    // np x np, [k*np + m]
+    const double* vinvT;   // np x np, [m*np + k] (transposed copy for coalesced loads)
     const int* expo;       // np x 3
     const double* coef;    // np
     int degree;
@@ -106,9 +113,48 @@ __device__ __noinline__ int orient_exact_slow(const double* a, const double* b, 
     return 0;
 }
 
+// Second stage: the determinant in double-double arithmetic.  Each 2x2
+// minor a_i b_j - a_j b_i is formed from exact products (two_prod) as s + t
+// with |error| <= ~4.1 eps^2 P (P the sum of the two |products|); each p_i s_i
+// is an exact two_prod, each p_i t_i is rounded once, the three leading
+// products are summed exactly and the eight small terms in plain FP64.  The
+// total error stays below 64 eps^2 perm; the sign is taken when |det| exceeds
+// twice that, otherwise -2 (undecided) is returned.
+__device__ __noinline__ int orient_dd(const double* a, const double* b, const double* p, double perm) {
+#pragma clang fp contract(off)
+    double hs[3], sm[8];
+    int nsm = 0;
+    const int i1[3] = {1, 2, 0}, i2[3] = {2, 0, 1};
+    for (int c = 0; c < 3; ++c) {
+        double h1, l1, h2, l2, s, e;
+        two_prod(a[i1[c]], b[i2[c]], h1, l1);
+        two_prod(a[i2[c]], b[i1[c]], h2, l2);
+        two_sum(h1, -h2, s, e);
+        const double t = (l1 - l2) + e;
+        double H, Lo;
+        two_prod(p[c], s, H, Lo);
+        hs[c] = H;
+        sm[nsm++] = Lo;
+        sm[nsm++] = p[c] * t;
+    }
+    double A, a1, B, b1;
+    two_sum(hs[0], hs[1], A, a1);
+    two_sum(A, hs[2], B, b1);
+    double r = a1 + b1;
+    for (int i = 0; i < nsm; ++i) r += sm[i];
+    const double f = B + r;
+    const double eps2 = 1.2325951644078310e-32;  // 2^-106
+    const double bound = 128.0 * eps2 * perm;
+    if (f > bound) return 1;
+    if (f < -bound) return -1;
+    return -2;
+}
+
 // Filtered exact orientation.  The plain FP64 evaluation below has a
 // rounding error of at most about 5 eps * perm; when |det| exceeds 8 eps *
-// perm its sign is certain, otherwise the exact path decides.
+// perm its sign is certain; otherwise the double-double stage decides, and
+// only when that cannot (|det| below ~1e-30 perm, typically an exact zero)
+// the exact expansion does.
 __device__ __forceinline__ int orient(const double* a, const double* b, const double* p) {
 #pragma clang fp contract(off)
     const double cx = a[1] * b[2] - a[2] * b[1];
@@ -121,6 +167,11 @@ __device__ __forceinline__ int orient(const double* a, const double* b, const do
     const double bound = 8.0 * 1.1102230246251565e-16 * perm;
     if (det > bound) return 1;
     if (det < -bound) return -1;
+    // p equal to a or b: the determinant is exactly zero (grid particles are
+    // the vertices of the finer triangles, so this is the common exact case)
+    if ((p[0] == a[0] && p[1] == a[1] && p[2] == a[2]) || (p[0] == b[0] && p[1] == b[1] && p[2] == b[2])) return 0;
+    const int dd = orient_dd(a, b, p, perm);
+    if (dd != -2) return dd;
     return orient_exact_slow(a, b, p);
 }
 
@@ -159,13 +210,62 @@ __device__ __forceinline__ int level_of_offset_table(const i64* off, int L, i64 
     return l;
 }
 
+// Block-wide product out[k][c] = sum_m Mt[m * np + k] * sc[m] * in[m][c] for
+// k < np, c < NC, with all NT threads: thread t handles row k = t % np and
+// the m-range of group t / np (NT / np groups); partial sums meet in red
+// (LDS, >= NT * NC doubles).  Mt is read row by row, consecutive threads
+// reading consecutive k (coalesced).  sc may be null (all ones).  Must be
+// called by every thread of the block; ends with a barrier.
+template <int NT, int NC>
+__device__ __forceinline__ void block_matvec(const double* __restrict__ Mt, int np, const double* sc,
+                                             const double (*in)[NC], double* red, double (*out)[NC]) {
+    const int tid = threadIdx.x;
+    const int G = NT / np;
+    const int k = tid % np, g = tid / np;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    if (g < G) {
+        const int per = (np + G - 1) / G;
+        const int m0 = g * per, m1 = (m0 + per) < np ? (m0 + per) : np;
+#pragma unroll 4
+        for (int m = m0; m < m1; ++m) {
+            const double f = Mt[(size_t)m * np + k] * (sc ? sc[m] : 1.0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += f * in[m][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[c * NT + tid] = (g < G) ? acc[c] : 0.0;
+    __syncthreads();
+    if (tid < np) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double s = 0.0;
+            for (int gg = 0; gg < G; ++gg) s += red[c * NT + gg * np + tid];
+            out[tid][c] = s;
+        }
+    }
+    __syncthreads();
+}
+
 // host-side launch helpers (implemented in the .hip files)
 struct SortScratch {
-    u32* hist;       // 256 * max_blocks
+    u32* hist;       // 2 * 256 * max_blocks
+    u32* totals;     // 2 * 256
     int max_blocks;
+};
+
+// up to two independent key arrays sorted in the same passes
+struct SortBatch {
+    const u64* in[2];
+    u64* out[2];
+    const u32* dn[2];
 };
 
 void radix_sort(hipStream_t s, u64* keys, u64* tmp, const u32* d_n, u32 n_bound, int bit_lo,
                 int bit_hi, SortScratch scratch, u64** result);
+void radix_sort_batch(hipStream_t s, int nb, u64* const* keys, u64* const* tmp, const u32* const* d_n, u32 n_bound,
+                      int bit_lo, int bit_hi, SortScratch scratch, u64** result);
 
 }  // namespace stc

@@ -28,6 +28,11 @@ struct NodeGeo {
     double minv[3][3];
 };
 
+// The traversal's view of a node: circumcentre and radius (32 bytes).
+struct NodeMac {
+    double cx, cy, cz, r;
+};
+
 inline int64_t level_offset(int level) { return 20 * ((int64_t(1) << (2 * level)) - 1) / 3; }
 inline int64_t total_nodes(int max_level) { return level_offset(max_level + 1); }
 

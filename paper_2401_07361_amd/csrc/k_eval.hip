@@ -15,12 +15,13 @@
 //                    i that received CP/CC work; then the cross product and
 //                    the scatter back to input order.
 //
-// Segment kernels run one wave per workgroup.  A persistent grid splits the
-// target-sorted list into equal contiguous ranges of entries; a workgroup
-// handles every target whose run of entries starts inside its range.  The
-// block -> range map is XCD aware (consecutive ranges, i.e. neighbouring
-// triangles that share sources, run on the same XCD and its L2).  Sources
-// are staged into 256-entry LDS tiles; lanes split as (target, source slice).
+// Segment kernels run 256 threads per workgroup.  A persistent grid splits
+// the target-sorted list into equal contiguous ranges of entries; a
+// workgroup handles every target whose run of entries starts inside its
+// range.  The block -> range map is XCD aware (consecutive ranges, i.e.
+// neighbouring triangles that share sources, run on the same XCD and its
+// L2).  Sources are staged into 256-entry LDS tiles, one source per thread;
+// threads split as (target, source slice) with 256 / n_targets slices.
 // FP32 mode: coordinates relative to the target triangle's circumcentre,
 // rounded from FP64; partial sums per tile in FP32, added into FP64.
 #include "common.hpp"
@@ -49,26 +50,37 @@ __device__ __forceinline__ double rcp_t<double>(double v) {
     return rcp64(v);
 }
 
-// sum over staged sources j = sl, sl + S, ... < cnt
+// one kernel evaluation: q (y - x) / den added to (px, py, pz)
+template <typename T, int DEN>
+__device__ __forceinline__ void interact(const Src<T>& s, T tx, T ty, T tz, T& px, T& py, T& pz) {
+    const T dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
+    T den;
+    if (DEN == STC_DEN_DIST2) den = dx * dx + dy * dy + dz * dz;  // charges carry the factor 2
+    else den = T(1) - (tx * s.x + ty * s.y + tz * s.z);
+    const T w = s.q * rcp_t<T>(den);
+    px += w * dx;
+    py += w * dy;
+    pz += w * dz;
+}
+
+// sum over staged sources j = sl, sl + S, ... < cnt.  The main loop has the
+// same trip count (cnt / S) in every lane, so it unrolls; the at most one
+// remaining source per lane follows.
 template <typename T, int DEN, bool SELF>
 __device__ __forceinline__ void tile_sum(const Src<T>* __restrict__ tile, int cnt, int sl, int S, T tx, T ty, T tz,
                                          int self_j, double& ax, double& ay, double& az) {
     T px = T(0), py = T(0), pz = T(0);
-    for (int j = sl; j < cnt; j += S) {
-        const Src<T> s = tile[j];
-        const T dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
-        T den;
-        if (DEN == STC_DEN_DIST2) den = dx * dx + dy * dy + dz * dz;  // charges carry the factor 2
-        else den = T(1) - (tx * s.x + ty * s.y + tz * s.z);
-        T q = s.q;
-        if (SELF && j == self_j) {  // the j = i term is excluded
-            den = T(1);
-            q = T(0);
+    const int m = cnt / S;
+    int j = sl;
+    if (!SELF) {
+#pragma unroll 4
+        for (int it = 0; it < m; ++it, j += S) interact<T, DEN>(tile[j], tx, ty, tz, px, py, pz);
+        if (j < cnt) interact<T, DEN>(tile[j], tx, ty, tz, px, py, pz);
+    } else {
+        for (; j < cnt; j += S) {
+            if (j == self_j) continue;  // the j = i term is excluded
+            interact<T, DEN>(tile[j], tx, ty, tz, px, py, pz);
         }
-        const T w = q * rcp_t<T>(den);
-        px += w * dx;
-        py += w * dy;
-        pz += w * dz;
     }
     ax += (double)px;
     ay += (double)py;
@@ -80,128 +92,186 @@ __device__ __forceinline__ u32 logical_block() {
     return (b % 8u) * (G / 8u) + (b / 8u);
 }
 
-// stage source l of an entry into tile slot `slot`
+constexpr int NT = 256;   // threads per workgroup of the segment kernels
+constexpr int EB = 256;   // list entries per batch
+
+template <typename T, int NTT>
+struct SegShared {
+    Src<T> tile[TILE];
+    u32 ent_s[EB];         // source node of each entry of the batch
+    i32 ent_first[EB];     // first particle of a particle source, -1 for proxy points
+    u32 ent_pre[EB + 1];   // exclusive prefix of the entries' source counts
+    u32 wave_tot[NTT / 64];
+    int self_flag;
+    double red[3][NTT];
+};
+
+// exclusive prefix over the NTT threads; returns the prefix, *total the sum
+template <int NTT>
+__device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* wave_tot, u32* total) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    u32 incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const u32 t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wave_tot[w] = incl;
+    __syncthreads();
+    u32 base = 0, tot = 0;
+    for (int k = 0; k < NTT / 64; ++k) {
+        const u32 wt = wave_tot[k];
+        if (k < w) base += wt;
+        tot += wt;
+    }
+    *total = tot;
+    return base + incl - v;
+}
+
+// One source point relative to (cx, cy, cz), charge scaled by qscale.
 template <typename T>
-__device__ __forceinline__ void stage(const EvalArgs& a, int type, u32 s, i32 first, int l, double cx, double cy,
-                                      double cz, double qscale, Src<T>* tile, int slot) {
+__device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 first, int l, double cx, double cy,
+                                              double cz, double qscale) {
     Src<T> v;
-    if (type == 0) {
+    if (first >= 0) {
         const i32 j = first + l;
         v.x = (T)(a.sx[j] - cx);
         v.y = (T)(a.sy[j] - cy);
         v.z = (T)(a.sz[j] - cz);
         v.q = (T)(qscale * a.sq[j]);
     } else {
-        double y[3];
-        proxy_point(a.geo[s], a.ref.points + 3 * l, y);
-        v.x = (T)(y[0] - cx);
-        v.y = (T)(y[1] - cy);
-        v.z = (T)(y[2] - cz);
-        v.q = (T)(qscale * a.wq[(size_t)s * a.ref.np + l]);
+        const Prox pr = a.prox[(size_t)s * a.ref.np + l];
+        v.x = (T)(pr.x - cx);
+        v.y = (T)(pr.y - cy);
+        v.z = (T)(pr.z - cz);
+        v.q = (T)(qscale * pr.w);
     }
-    tile[slot] = v;
+    return v;
 }
 
-// Accumulates, for the targets (tx, ty, tz) of this lane, every entry of
-// [e0, e1) in `list` whose type bit is in type_mask.  self_t: target node id
-// for PP self exclusion (0xffffffff: none), me: the lane's target index in
-// that node.
-template <typename T, int DEN>
+// Accumulates, for this thread's target (tx, ty, tz), every entry of [e0, e1)
+// in `list` whose type bit is in type_mask.  Entries are taken in batches of
+// EB: their source counts are scanned into an LDS prefix, so that for each
+// 256-source tile every thread stages exactly one source (its entry found by
+// binary search) and all global loads of a tile are in flight together.  A
+// PP entry whose source is the target leaf itself (self_t) is evaluated on
+// its own with the j != i exclusion (me: the thread's target index there).
+template <typename T, int DEN, int NTT>
 __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ list, u32 e0, u32 e1, u32 type_mask,
                                    u32 self_t, int me, bool act, int sl, int S, T tx, T ty, T tz, double cx,
-                                   double cy, double cz, Src<T>* tile, double& ax, double& ay, double& az) {
-    const int lane = threadIdx.x;
+                                   double cy, double cz, SegShared<T, NTT>& sh, double& ax, double& ay, double& az) {
+    const int tid = threadIdx.x;
     const u64 mask = ((u64)1 << a.W) - 1;
     const double qscale = (DEN == STC_DEN_DIST2) ? 2.0 : 1.0;
-    int fill = 0;
-    for (u32 e = e0; e < e1; ++e) {
-        const u64 key = list[e];
-        const int type = (int)((key >> a.W) & 1u);
-        const u32 s = (u32)(key & mask);
-        if (!((type_mask >> type) & 1u)) continue;
-        const int nsrc = type == 0 ? (a.nend[s] - a.nbeg[s]) : a.ref.np;
-        const i32 first = type == 0 ? a.nbeg[s] : 0;
-        if (type == 0 && s == self_t) {
-            if (fill > 0) {
-                __syncthreads();
-                if (act) tile_sum<T, DEN, false>(tile, fill, sl, S, tx, ty, tz, -1, ax, ay, az);
-                __syncthreads();
-                fill = 0;
+    for (u32 eb = e0; eb < e1; eb += EB) {
+        const u32 ne = (e1 - eb) < (u32)EB ? (e1 - eb) : (u32)EB;
+        if (tid == 0) sh.self_flag = 0;
+        __syncthreads();
+        u32 size = 0;
+        if ((u32)tid < ne) {
+            const u64 key = list[eb + tid];
+            const int type = (int)((key >> a.W) & 1u);
+            const u32 s = (u32)(key & mask);
+            sh.ent_s[tid] = s;
+            if ((type_mask >> type) & 1u) {
+                if (type == 0) {
+                    const i32 b = a.nbeg[s];
+                    sh.ent_first[tid] = b;
+                    if (s == self_t) sh.self_flag = 1;
+                    else size = (u32)(a.nend[s] - b);
+                } else {
+                    sh.ent_first[tid] = -1;
+                    size = (u32)a.ref.np;
+                }
+            } else {
+                sh.ent_first[tid] = 0;
             }
+        }
+        u32 total = 0;
+        const u32 pre = block_exclusive_scan<NTT>(size, sh.wave_tot, &total);
+        if ((u32)tid < ne) sh.ent_pre[tid] = pre;
+        if (tid == 0) sh.ent_pre[ne] = total;
+        __syncthreads();
+        if (sh.self_flag) {
+            const i32 tb = a.nbeg[self_t];
+            const int nsrc = a.nend[self_t] - tb;
             for (int j0 = 0; j0 < nsrc; j0 += TILE) {
                 const int cnt = (nsrc - j0) < TILE ? (nsrc - j0) : TILE;
-                for (int l = lane; l < cnt; l += 64) stage<T>(a, 0, s, first, j0 + l, cx, cy, cz, qscale, tile, l);
+                if (tid < cnt) sh.tile[tid] = load_source<T>(a, self_t, tb, j0 + tid, cx, cy, cz, qscale);
                 __syncthreads();
-                if (act) tile_sum<T, DEN, true>(tile, cnt, sl, S, tx, ty, tz, me - j0, ax, ay, az);
+                if (act) tile_sum<T, DEN, true>(sh.tile, cnt, sl, S, tx, ty, tz, me - j0, ax, ay, az);
                 __syncthreads();
             }
-            continue;
         }
-        int off = 0;
-        while (off < nsrc) {
-            const int room = TILE - fill;
-            const int take = (nsrc - off) < room ? (nsrc - off) : room;
-            for (int l = lane; l < take; l += 64) stage<T>(a, type, s, first, off + l, cx, cy, cz, qscale, tile, fill + l);
-            fill += take;
-            off += take;
-            if (fill == TILE) {
-                __syncthreads();
-                if (act) tile_sum<T, DEN, false>(tile, fill, sl, S, tx, ty, tz, -1, ax, ay, az);
-                __syncthreads();
-                fill = 0;
+        for (u32 g0 = 0; g0 < total; g0 += TILE) {
+            const int cnt = (total - g0) < (u32)TILE ? (int)(total - g0) : TILE;
+            if (tid < cnt) {
+                const u32 g = g0 + tid;
+                u32 lo = 0, hi = ne;
+                while (hi - lo > 1) {
+                    const u32 mid = (lo + hi) >> 1;
+                    if (sh.ent_pre[mid] <= g) lo = mid;
+                    else hi = mid;
+                }
+                sh.tile[tid] = load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g - sh.ent_pre[lo]), cx, cy,
+                                              cz, qscale);
             }
+            __syncthreads();
+            if (act) tile_sum<T, DEN, false>(sh.tile, cnt, sl, S, tx, ty, tz, -1, ax, ay, az);
+            __syncthreads();
         }
-    }
-    if (fill > 0) {
-        __syncthreads();
-        if (act) tile_sum<T, DEN, false>(tile, fill, sl, S, tx, ty, tz, -1, ax, ay, az);
-        __syncthreads();
     }
 }
 
-template <typename T, int DEN>
-__global__ __launch_bounds__(64) void k_near(EvalArgs a, u32 type_mask) {
-    __shared__ Src<T> tile[TILE];
-    __shared__ double red[3][64];
-    const int lane = threadIdx.x;
-    u32 n = a.counters[C_TLIST];
-    if (n > a.cap) n = a.cap;
+// range of list entries of this workgroup; returns false if empty
+__device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int W, u32& e, u32& e_hi) {
     const u32 G = gridDim.x;
     const u32 chunk = (n + G - 1) / G;
     const u64 lo = (u64)logical_block() * chunk;
-    if (lo >= n) return;
-    u32 e = (u32)lo;
-    const u32 e_hi = (u64)e + chunk < n ? e + chunk : n;
-    const int sh = a.W + 1;
-    if (e > 0 && (a.tlist[e] >> sh) == (a.tlist[e - 1] >> sh)) e = (u32)a.tseg_end[a.tlist[e] >> sh];
+    if (lo >= n) return false;
+    e = (u32)lo;
+    e_hi = (u64)e + chunk < n ? e + chunk : n;
+    const int sh = W + 1;
+    if (e > 0 && (list[e] >> sh) == (list[e - 1] >> sh)) e = (u32)seg_end[list[e] >> sh];
+    return true;
+}
+
+template <typename T, int DEN>
+__global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
+    __shared__ SegShared<T, NT> sh;
+    const int tid = threadIdx.x;
+    u32 n = a.counters[C_TLIST];
+    if (n > a.cap) n = a.cap;
+    u32 e, e_hi;
+    if (!wg_range(n, a.tlist, a.tseg_end, a.W, e, e_hi)) return;
+    const int shf = a.W + 1;
     const bool rel = sizeof(T) == 4;  // FP32: coordinates relative to the target circumcentre
     while (e < e_hi) {
-        const u32 t = (u32)(a.tlist[e] >> sh);
+        const u32 t = (u32)(a.tlist[e] >> shf);
         const u32 se = (u32)a.tseg_end[t];
         const i32 tb = a.nbeg[t];
         const int nt = a.nend[t] - tb;
         const double cx = rel ? a.geo[t].c[0] : 0.0, cy = rel ? a.geo[t].c[1] : 0.0, cz = rel ? a.geo[t].c[2] : 0.0;
-        for (int cb = 0; cb < nt; cb += 64) {
-            const int ntc = (nt - cb) < 64 ? (nt - cb) : 64;
-            const int S = 64 / ntc;
-            const int ti = lane % ntc, sl = lane / ntc;
+        for (int cb = 0; cb < nt; cb += NT) {
+            const int ntc = (nt - cb) < NT ? (nt - cb) : NT;
+            const int S = NT / ntc;
+            const int ti = tid % ntc, sl = tid / ntc;
             const bool act = sl < S;
             const int me = cb + ti;
             const i32 gi = tb + me;
             const T tx = (T)(a.sx[gi] - cx), ty = (T)(a.sy[gi] - cy), tz = (T)(a.sz[gi] - cz);
             double ax = 0.0, ay = 0.0, az = 0.0;
-            accumulate_entries<T, DEN>(a, a.tlist, e, se, type_mask, t, me, act, sl, S, tx, ty, tz, cx, cy, cz, tile,
-                                       ax, ay, az);
-            red[0][lane] = act ? ax : 0.0;
-            red[1][lane] = act ? ay : 0.0;
-            red[2][lane] = act ? az : 0.0;
+            accumulate_entries<T, DEN, NT>(a, a.tlist, e, se, type_mask, t, me, act, sl, S, tx, ty, tz, cx, cy, cz,
+                                           sh, ax, ay, az);
+            sh.red[0][tid] = act ? ax : 0.0;
+            sh.red[1][tid] = act ? ay : 0.0;
+            sh.red[2][tid] = act ? az : 0.0;
             __syncthreads();
             if (act && sl == 0) {
                 double sx = 0.0, sy = 0.0, sz = 0.0;
                 for (int k = 0; k < S; ++k) {
-                    sx += red[0][k * ntc + ti];
-                    sy += red[1][k * ntc + ti];
-                    sz += red[2][k * ntc + ti];
+                    sx += sh.red[0][k * ntc + ti];
+                    sy += sh.red[1][k * ntc + ti];
+                    sz += sh.red[2][k * ntc + ti];
                 }
                 a.Wacc[3 * (size_t)gi + 0] += sx;
                 a.Wacc[3 * (size_t)gi + 1] += sy;
@@ -213,117 +283,133 @@ __global__ __launch_bounds__(64) void k_near(EvalArgs a, u32 type_mask) {
     }
 }
 
-template <typename T, int DEN>
-__global__ __launch_bounds__(64) void k_far_targets(EvalArgs a) {
-    __shared__ Src<T> tile[TILE];
-    __shared__ double red[3][64];
+template <typename T, int DEN, int NTT>
+__global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
+    __shared__ SegShared<T, NTT> sh;
     __shared__ double wt[kMaxNp][3];
+    __shared__ double co[kMaxNp][3];
     __shared__ double nd[kMaxNp];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     u32 n = a.counters[C_NLIST];
     if (n > a.cap) n = a.cap;
-    const u32 G = gridDim.x;
-    const u32 chunk = (n + G - 1) / G;
-    const u64 lo = (u64)logical_block() * chunk;
-    if (lo >= n) return;
-    u32 e = (u32)lo;
-    const u32 e_hi = (u64)e + chunk < n ? e + chunk : n;
-    const int sh = a.W + 1;
-    if (e > 0 && (a.nlist[e] >> sh) == (a.nlist[e - 1] >> sh)) e = (u32)a.nseg_end[a.nlist[e] >> sh];
+    u32 e, e_hi;
+    if (!wg_range(n, a.nlist, a.nseg_end, a.W, e, e_hi)) return;
+    const int shf = a.W + 1;
     const bool rel = sizeof(T) == 4;
     const int np = a.ref.np, d = a.ref.degree;
     while (e < e_hi) {
-        const u32 t = (u32)(a.nlist[e] >> sh);
+        const u32 t = (u32)(a.nlist[e] >> shf);
         const u32 se = (u32)a.nseg_end[t];
         const NodeGeo& gt = a.geo[t];
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
-        for (int cb = 0; cb < np; cb += 64) {
-            const int ntc = (np - cb) < 64 ? (np - cb) : 64;
-            const int S = 64 / ntc;
-            const int ti = lane % ntc, sl = lane / ntc;
-            const bool act = sl < S;
-            const int me = cb + ti;
-            double y[3];
-            const double nrm = proxy_point(gt, a.ref.points + 3 * me, y);
-            if (act && sl == 0) nd[me] = ipow(nrm, d);
-            const T tx = (T)(y[0] - cx), ty = (T)(y[1] - cy), tz = (T)(y[2] - cz);
-            double ax = 0.0, ay = 0.0, az = 0.0;
-            accumulate_entries<T, DEN>(a, a.nlist, e, se, 3u, 0xffffffffu, me, act, sl, S, tx, ty, tz, cx, cy, cz,
-                                       tile, ax, ay, az);
-            red[0][lane] = act ? ax : 0.0;
-            red[1][lane] = act ? ay : 0.0;
-            red[2][lane] = act ? az : 0.0;
-            __syncthreads();
-            if (act && sl == 0) {
-                double sx = 0.0, sy = 0.0, sz = 0.0;
-                for (int k = 0; k < S; ++k) {
-                    sx += red[0][k * ntc + ti];
-                    sy += red[1][k * ntc + ti];
-                    sz += red[2][k * ntc + ti];
-                }
-                wt[me][0] = sx;
-                wt[me][1] = sy;
-                wt[me][2] = sz;
+        const int ntc = np;  // np <= 120 < NTT
+        const int S = NTT / ntc;
+        const int ti = tid % ntc, sl = tid / ntc;
+        const bool act = sl < S;
+        double y[3];
+        const double nrm = proxy_point(gt, a.ref.points + 3 * ti, y);
+        if (act && sl == 0) nd[ti] = ipow(nrm, d);
+        const T tx = (T)(y[0] - cx), ty = (T)(y[1] - cy), tz = (T)(y[2] - cz);
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        accumulate_entries<T, DEN, NTT>(a, a.nlist, e, se, 3u, 0xffffffffu, ti, act, sl, S, tx, ty, tz, cx, cy, cz,
+                                        sh, ax, ay, az);
+        sh.red[0][tid] = act ? ax : 0.0;
+        sh.red[1][tid] = act ? ay : 0.0;
+        sh.red[2][tid] = act ? az : 0.0;
+        __syncthreads();
+        if (act && sl == 0) {
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int k = 0; k < S; ++k) {
+                sx += sh.red[0][k * ntc + ti];
+                sy += sh.red[1][k * ntc + ti];
+                sz += sh.red[2][k * ntc + ti];
             }
-            __syncthreads();
+            wt[ti][0] = sx;
+            wt[ti][1] = sy;
+            wt[ti][2] = sz;
         }
+        __syncthreads();
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
-        for (int k = lane; k < np; k += 64) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            const double* vr = a.ref.vinv + (size_t)k * np;
-            for (int m = 0; m < np; ++m) {
-                const double c = vr[m] * nd[m];
-                s0 += c * wt[m][0];
-                s1 += c * wt[m][1];
-                s2 += c * wt[m][2];
-            }
-            double* out = a.alpha + ((size_t)t * np + k) * 3;
-            out[0] = s0;
-            out[1] = s1;
-            out[2] = s2;
-        }
+        block_matvec<NTT, 3>(a.ref.vinvT, np, nd, wt, &sh.red[0][0], co);
+        for (int k = tid; k < 3 * np; k += NTT) a.alpha[(size_t)t * np * 3 + k] = co[k / 3][k % 3];
         __syncthreads();
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
     }
 }
 
+// Interpolation to the particles and output.  For every node t holding
+// particle i that received CP/CC work, W_i += sum_k B_k(b_t(x_i)) alpha_k(t)
+// (the target-side interpolation of Sec. 3); then u_i = -(1/4pi) x_i x W_i,
+// scattered to input order.  A workgroup takes 256 consecutive particles in
+// tree order and walks the levels; at each level its particles lie in a few
+// consecutive nodes, whose coefficients are staged in LDS (KS at a time) and
+// read from there by every particle of the node.
+constexpr int KS = 4;  // coefficient slots in LDS
+
 template <int D>
 __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, double* __restrict__ u, int accumulate) {
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    constexpr int NP = (D + 1) * (D + 2) / 2;
+    __shared__ double al[KS][NP][3];
+    __shared__ i64 slot_node[256];
+    __shared__ u32 wtot[4];
+    const int tid = threadIdx.x;
+    const i64 i0 = (i64)blockIdx.x * blockDim.x + tid;
+    const bool valid = i0 < a.n;
+    const i64 i = valid ? i0 : a.n - 1;
     const double x0 = a.sx[i], x1 = a.sy[i], x2 = a.sz[i];
     double W0 = a.Wacc[3 * i], W1 = a.Wacc[3 * i + 1], W2 = a.Wacc[3 * i + 2];
     if (do_far) {
         const u32 leaf = a.leaf[i];
         const int L = a.L;
-        constexpr int NP = (D + 1) * (D + 2) / 2;
         for (int lvl = 0; lvl <= L; ++lvl) {
-            const i64 node = a.level_off_tab[lvl] + (i64)(leaf >> (2 * (L - lvl)));
-            if (a.nseg_end[node] == 0) continue;
-            const NodeGeo& g = a.geo[node];
-            double P[3][D + 1];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double be = (g.minv[c][0] * x0 + g.minv[c][1] * x1) + g.minv[c][2] * x2;
-                P[c][0] = 1.0;
-#pragma unroll
-                for (int t = 1; t <= D; ++t) P[c][t] = P[c][t - 1] * be;
-            }
-            const double* al = a.alpha + (size_t)node * NP * 3;
-            int k = 0;
-#pragma unroll
-            for (int i1 = 0; i1 <= D; ++i1) {
-#pragma unroll
-                for (int j1 = 0; j1 <= D - i1; ++j1) {
-                    const double B = a.ref.coef[k] * (P[0][i1] * P[1][j1] * P[2][D - i1 - j1]);
-                    W0 += B * al[3 * k];
-                    W1 += B * al[3 * k + 1];
-                    W2 += B * al[3 * k + 2];
-                    ++k;
+            const i64 nd = a.level_off_tab[lvl] + (i64)(leaf >> (2 * (L - lvl)));
+            const bool has = valid && a.nseg_end[nd] != 0;
+            // the first particle of each node with far work opens a slot
+            slot_node[tid] = has ? nd : (i64)-1;
+            __syncthreads();
+            const bool first = has && (tid == 0 || slot_node[tid - 1] != nd);
+            u32 nslots = 0;
+            const u32 before = block_exclusive_scan<256>(first ? 1u : 0u, wtot, &nslots);
+            const int my_slot = has ? (int)(before + (first ? 1u : 0u)) - 1 : -1;
+            __syncthreads();
+            if (first) slot_node[my_slot] = nd;
+            __syncthreads();
+            for (u32 s0 = 0; s0 < nslots; s0 += KS) {
+                const int ns = (nslots - s0) < (u32)KS ? (int)(nslots - s0) : KS;
+                for (int k = tid; k < ns * NP * 3; k += 256) {
+                    const int sl = k / (NP * 3), r = k % (NP * 3);
+                    al[sl][r / 3][r % 3] = a.alpha[(size_t)slot_node[s0 + sl] * NP * 3 + r];
                 }
+                __syncthreads();
+                const int ms = my_slot - (int)s0;
+                if (ms >= 0 && ms < ns) {
+                    const NodeGeo& g = a.geo[nd];
+                    double P[3][D + 1];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double be = (g.minv[c][0] * x0 + g.minv[c][1] * x1) + g.minv[c][2] * x2;
+                        P[c][0] = 1.0;
+#pragma unroll
+                        for (int t = 1; t <= D; ++t) P[c][t] = P[c][t - 1] * be;
+                    }
+                    int k = 0;
+#pragma unroll
+                    for (int i1 = 0; i1 <= D; ++i1) {
+#pragma unroll
+                        for (int j1 = 0; j1 <= D - i1; ++j1) {
+                            const double B = a.ref.coef[k] * (P[0][i1] * P[1][j1] * P[2][D - i1 - j1]);
+                            W0 += B * al[ms][k][0];
+                            W1 += B * al[ms][k][1];
+                            W2 += B * al[ms][k][2];
+                            ++k;
+                        }
+                    }
+                }
+                __syncthreads();
             }
         }
     }
+    if (!valid) return;
     // u = -(1/4pi) x x W
     const double u0 = -kInv4Pi * (x1 * W2 - x2 * W1);
     const double u1 = -kInv4Pi * (x2 * W0 - x0 * W2);
@@ -395,17 +481,18 @@ __global__ __launch_bounds__(256) void k_direct(i64 n, const double* __restrict_
 }  // namespace
 
 void launch_near(hipStream_t s, const EvalArgs& a, u32 type_mask) {
-    const dim3 g(a.grid), b(64);
+    const dim3 g(a.grid), b(NT);
     if (a.precision == STC_FP32) hipLaunchKernelGGL((k_near<float, STC_DEN_DIST2>), g, b, 0, s, a, type_mask);
     else if (a.denominator == STC_DEN_DIST2) hipLaunchKernelGGL((k_near<double, STC_DEN_DIST2>), g, b, 0, s, a, type_mask);
     else hipLaunchKernelGGL((k_near<double, STC_DEN_DOT>), g, b, 0, s, a, type_mask);
 }
 
 void launch_far_targets(hipStream_t s, const EvalArgs& a) {
-    const dim3 g(a.grid), b(64);
-    if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2>), g, b, 0, s, a);
-    else if (a.denominator == STC_DEN_DIST2) hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DOT>), g, b, 0, s, a);
+    const dim3 g(a.grid), b(NT);
+    if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NT>), g, b, 0, s, a);
+    else if (a.denominator == STC_DEN_DIST2)
+        hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2, NT>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DOT, NT>), g, b, 0, s, a);
 }
 
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate) {

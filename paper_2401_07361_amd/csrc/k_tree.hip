@@ -19,6 +19,22 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n
     if (i >= n) return;
     const double p[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
     int face = -1;
+    // candidate: the face whose circumcentre is nearest; if p is strictly
+    // inside it no other face contains p, else scan in index order
+    int best = 0;
+    double bd = -2.0;
+    for (int f = 0; f < 20; ++f) {
+        const double dt = (geo[f].c[0] * p[0] + geo[f].c[1] * p[1]) + geo[f].c[2] * p[2];
+        if (dt > bd) {
+            bd = dt;
+            best = f;
+        }
+    }
+    {
+        const NodeGeo& g = geo[best];
+        if (orient(g.v[0], g.v[1], p) > 0 && orient(g.v[1], g.v[2], p) > 0 && orient(g.v[2], g.v[0], p) > 0)
+            face = best;
+    }
     for (int f = 0; f < 20 && face < 0; ++f) {
         const NodeGeo& g = geo[f];
         if (orient(g.v[0], g.v[1], p) >= 0 && orient(g.v[1], g.v[2], p) >= 0 &&
@@ -89,27 +105,39 @@ __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i
 }
 
 // ---------------------------------------------------------------------------
-// Upward pass (Sec. 3, particle-cluster interaction): for every node with
-// more than N_T particles, omega_k = sum_j B_k(b(y_j)) q_j with b = M^{-1} y
-// and the multinomial-scaled SBB basis, then the proxy charges
-//   w_m = |b_m1 v1 + b_m2 v2 + b_m3 v3|^d * sum_k (V_ref^{-1})_{km} omega_k,
-// i.e. w = V^{-T} omega for the node's Vandermonde matrix V = diag(s^d) V_ref.
-// One workgroup per node; chunks of 64 particles have their barycentric
-// powers staged in LDS, and thread t accumulates basis function t % np over
-// every (256 / np)-th particle of the chunk.
+// Upward pass (Sec. 3, particle-cluster interaction).  For every node P with
+// more than N_T particles:
+//   omega_k = sum over sources y of B_k(b(y)) q(y),  b = M_P^{-1} y,
+//   w_m     = |b_m1 v1 + b_m2 v2 + b_m3 v3|^d * sum_k (V_ref^{-1})_{km} omega_k
+// (w = V^{-T} omega with the node's Vandermonde matrix V = diag(s^d) V_ref).
+// The sources of P are its particles when P is at the depth limit, and
+// otherwise its four children: a child with more than N_T particles
+// contributes its interpolation points with their proxy charges, a smaller
+// child its particles.  Every triangle's basis spans the same space
+// (homogeneous polynomials of degree d restricted to the sphere), so
+// re-interpolating a child's proxy charges at the parent reproduces the
+// parent's proxy charges computed from the particles, up to rounding.
+// Levels are processed bottom-up, one launch per level, one workgroup per
+// node; sources go through LDS in chunks of 64 (barycentric powers), thread
+// t accumulating basis function t % np over every (256/np)-th source.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_p2m(const i32* __restrict__ nbeg, const i32* __restrict__ nend,
-                                              i64 n_nodes, int n_crit, const NodeGeo* __restrict__ geo,
-                                              const double* __restrict__ sx, const double* __restrict__ sy,
-                                              const double* __restrict__ sz, const double* __restrict__ q,
-                                              RefDev ref, double* __restrict__ w) {
+__global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int chunk, int lvl, int L,
+                                                       i64 child_off, const i32* __restrict__ nbeg,
+                                                       const i32* __restrict__ nend, int n_crit,
+                                                       const NodeGeo* __restrict__ geo, const double* __restrict__ sx,
+                                                       const double* __restrict__ sy, const double* __restrict__ sz,
+                                                       const double* __restrict__ q, RefDev ref,
+                                                       Prox* __restrict__ prox) {
     __shared__ double pw[64][3][kMaxDegree + 1];
     __shared__ double qs[64];
     __shared__ double red[256];
-    __shared__ double omega[kMaxNp];
+    __shared__ double omega[kMaxNp][1];
+    __shared__ double wout[kMaxNp][1];
+    __shared__ i32 big[256];
+    __shared__ int nbig;
     const int tid = threadIdx.x;
     const int d = ref.degree, np = ref.np;
-    const int S = 256 / np;  // particle slices
+    const int S = 256 / np;  // source slices
     const int k = tid % np, sl = tid / np;
     int e0 = 0, e1 = 0, e2 = 0;
     if (sl < S) {
@@ -117,48 +145,110 @@ __global__ __launch_bounds__(256) void k_p2m(const i32* __restrict__ nbeg, const
         e1 = ref.expo[3 * k + 1];
         e2 = ref.expo[3 * k + 2];
     }
-    for (i64 node = blockIdx.x; node < n_nodes; node += gridDim.x) {
-        const i32 b = nbeg[node], e = nend[node];
-        if (e - b <= n_crit) continue;  // uniform over the block
-        const NodeGeo& g = geo[node];
-        double acc = 0.0;
-        for (i32 c0 = b; c0 < e; c0 += 64) {
-            const int cnt = (e - c0) < 64 ? (e - c0) : 64;
-            if (tid < cnt) {
-                const i32 j = c0 + tid;
-                const double y0 = sx[j], y1 = sy[j], y2 = sz[j];
-                for (int a = 0; a < 3; ++a) {
-                    const double be = (g.minv[a][0] * y0 + g.minv[a][1] * y1) + g.minv[a][2] * y2;
-                    double pp = 1.0;
-                    for (int t = 0; t <= d; ++t) {
-                        pw[tid][a][t] = pp;
-                        pp *= be;
+    for (i64 base = (i64)blockIdx.x * chunk; base < nnodes; base += (i64)gridDim.x * chunk) {
+        // the nodes of this chunk with more than N_T particles, found in parallel
+        if (tid == 0) nbig = 0;
+        __syncthreads();
+        if (tid < chunk && base + tid < nnodes) {
+            const i64 nd = node0 + base + tid;
+            if (nend[nd] - nbeg[nd] > n_crit) big[atomicAdd(&nbig, 1)] = (i32)(base + tid);
+        }
+        __syncthreads();
+        const int nb = nbig;
+        for (int bi = 0; bi < nb; ++bi) {
+            const i64 t = big[bi];
+            const i64 node = node0 + t;
+            const i32 b = nbeg[node], e = nend[node];
+            const NodeGeo& g = geo[node];
+            // source segments: kind 0 = particle range [first, first+cnt), 1 = points of node `id`
+            int seg_kind[4], seg_cnt[4];
+            i64 seg_id[4];
+            int nseg = 0;
+            if (lvl == L) {
+                seg_kind[0] = 0;
+                seg_id[0] = b;
+                seg_cnt[0] = e - b;
+                nseg = 1;
+            } else {
+                for (int c = 0; c < 4; ++c) {
+                    const i64 cid = child_off + 4 * t + c;
+                    const i32 cb = nbeg[cid], cn = nend[cid] - cb;
+                    if (cn <= 0) continue;
+                    if (cn > n_crit) {
+                        seg_kind[nseg] = 1;
+                        seg_id[nseg] = cid;
+                        seg_cnt[nseg] = np;
+                    } else {
+                        seg_kind[nseg] = 0;
+                        seg_id[nseg] = cb;
+                        seg_cnt[nseg] = cn;
                     }
+                    ++nseg;
                 }
-                qs[tid] = q[j];
+            }
+            int total = 0;
+            for (int sgi = 0; sgi < nseg; ++sgi) total += seg_cnt[sgi];
+            double acc = 0.0;
+            for (int c0 = 0; c0 < total; c0 += 64) {
+                const int cnt = (total - c0) < 64 ? (total - c0) : 64;
+                if (tid < cnt) {
+                    int idx = c0 + tid, sgi = 0;
+                    while (idx >= seg_cnt[sgi]) {
+                        idx -= seg_cnt[sgi];
+                        ++sgi;
+                    }
+                    double y0, y1, y2, qq;
+                    if (seg_kind[sgi] == 0) {
+                        const i64 j = seg_id[sgi] + idx;
+                        y0 = sx[j];
+                        y1 = sy[j];
+                        y2 = sz[j];
+                        qq = q[j];
+                    } else {
+                        const Prox pr = prox[(size_t)seg_id[sgi] * np + idx];
+                        y0 = pr.x;
+                        y1 = pr.y;
+                        y2 = pr.z;
+                        qq = pr.w;
+                    }
+                    for (int a = 0; a < 3; ++a) {
+                        const double be = (g.minv[a][0] * y0 + g.minv[a][1] * y1) + g.minv[a][2] * y2;
+                        double pp = 1.0;
+                        for (int tt = 0; tt <= d; ++tt) {
+                            pw[tid][a][tt] = pp;
+                            pp *= be;
+                        }
+                    }
+                    qs[tid] = qq;
+                }
+                __syncthreads();
+                if (sl < S) {
+                    for (int j = sl; j < cnt; j += S) acc += qs[j] * (pw[j][0][e0] * pw[j][1][e1] * pw[j][2][e2]);
+                }
+                __syncthreads();
+            }
+            red[tid] = (sl < S) ? acc : 0.0;
+            __syncthreads();
+            if (tid < np) {
+                double sum = 0.0;
+                for (int tt = 0; tt < S; ++tt) sum += red[tt * np + tid];
+                omega[tid][0] = ref.coef[tid] * sum;
             }
             __syncthreads();
-            if (sl < S) {
-                for (int j = sl; j < cnt; j += S) acc += qs[j] * (pw[j][0][e0] * pw[j][1][e1] * pw[j][2][e2]);
+            // w_m = |.|^d sum_k (V_ref^{-1})_{km} omega_k  (row m of V_ref^{-T})
+            block_matvec<256, 1>(ref.vinv, np, nullptr, omega, red, wout);
+            for (int m = tid; m < np; m += 256) {
+                double y[3];
+                const double nrm = proxy_point(g, ref.points + 3 * m, y);
+                Prox pr;
+                pr.x = y[0];
+                pr.y = y[1];
+                pr.z = y[2];
+                pr.w = ipow(nrm, d) * wout[m][0];
+                prox[(size_t)node * np + m] = pr;
             }
             __syncthreads();
         }
-        red[tid] = (sl < S) ? acc : 0.0;
-        __syncthreads();
-        if (tid < np) {
-            double s = 0.0;
-            for (int t = 0; t < S; ++t) s += red[t * np + tid];
-            omega[tid] = ref.coef[tid] * s;
-        }
-        __syncthreads();
-        for (int m = tid; m < np; m += 256) {
-            double y[3];
-            const double nrm = proxy_point(g, ref.points + 3 * m, y);
-            double s = 0.0;
-            for (int kk = 0; kk < np; ++kk) s += ref.vinv[(size_t)kk * np + m] * omega[kk];
-            w[(size_t)node * np + m] = ipow(nrm, d) * s;
-        }
-        __syncthreads();
     }
 }
 
@@ -174,10 +264,10 @@ __global__ __launch_bounds__(256) void k_p2m(const i32* __restrict__ nbeg, const
 // Target-particle entries (PP, PC) and target-proxy entries (CP, CC) go to
 // two lists as sort keys (t << (W+1)) | (type << W) | s.
 // ---------------------------------------------------------------------------
-__global__ void k_trav_init(const i32* __restrict__ nbeg, const i32* __restrict__ nend,
-                            u64* __restrict__ front, u32 cap, u32* __restrict__ counters) {
+__global__ void k_trav_init(const i32* __restrict__ ncnt, u64* __restrict__ front, u32 cap,
+                            u32* __restrict__ counters) {
     const int i = threadIdx.x;  // 512 threads, 400 used
-    const bool ok = i < 400 && (nend[i / 20] - nbeg[i / 20]) > 0 && (nend[i % 20] - nbeg[i % 20]) > 0;
+    const bool ok = i < 400 && ncnt[i / 20] > 0 && ncnt[i % 20] > 0;
     const u32 slot = wave_append(&counters[C_FRONT], ok);
     if (ok) {
         if (slot < cap) front[slot] = ((u64)(i / 20) << 32) | (u64)(i % 20);
@@ -185,97 +275,142 @@ __global__ void k_trav_init(const i32* __restrict__ nbeg, const i32* __restrict_
     }
 }
 
-__device__ __forceinline__ bool mac_separated(const NodeGeo& a, const NodeGeo& b, double theta2) {
+__device__ __forceinline__ bool mac_separated(const NodeMac& a, const NodeMac& b, double theta2) {
 #pragma clang fp contract(off)
     const double s = a.r + b.r;
-    const double dx = a.c[0] - b.c[0];
-    const double dy = a.c[1] - b.c[1];
-    const double dz = a.c[2] - b.c[2];
+    const double dx = a.cx - b.cx;
+    const double dy = a.cy - b.cy;
+    const double dz = a.cz - b.cz;
     const double R2 = (dx * dx + dy * dy) + dz * dz;
     return s * s < theta2 * R2;
 }
 
+// exclusive prefix of v over the 256 threads of the block, *total = sum
+__device__ __forceinline__ u32 block_scan_u32(u32 v, u32* wsum, u32* total) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    u32 incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const u32 t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    u32 b = 0, tot = 0;
+    for (int k = 0; k < 4; ++k) {
+        const u32 x = wsum[k];
+        if (k < w) b += x;
+        tot += x;
+    }
+    *total = tot;
+    return b + incl - v;
+}
+
+constexpr int TRAV_IPT = 4;  // frontier pairs per thread per round
+
 __global__ __launch_bounds__(256) void k_trav_level(
-    int iter, const u64* __restrict__ fin, u64* __restrict__ fout, u32 cap, const i32* __restrict__ nbeg,
-    const i32* __restrict__ nend, const i64* __restrict__ level_off_tab, int L, const NodeGeo* __restrict__ geo,
-    double theta2, int n_crit, int W, u64* __restrict__ tlist, u64* __restrict__ nlist, u32* __restrict__ counters) {
+    int iter, const u64* __restrict__ fin, u64* __restrict__ fout, u32 cap, const i32* __restrict__ ncnt,
+    const NodeMac* __restrict__ mac, const i64* __restrict__ level_off_tab, int L, double theta2, int n_crit, int W,
+    u64* __restrict__ tlist, u64* __restrict__ nlist, u32* __restrict__ counters) {
+    __shared__ u32 wsum[3][4];
+    __shared__ u32 bases[3];
     u32 nin = counters[C_FRONT + iter];
     if (nin > cap) nin = cap;
-    const int lane = threadIdx.x & 63;
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    // every lane of a wave runs the same number of iterations (ballots below)
-    for (u64 base = (u64)blockIdx.x * blockDim.x + (threadIdx.x - lane); base < nin; base += stride) {
-        const u64 i = base + lane;
-        const bool active = i < nin;
-        int kind = -1;        // 0 PP, 1 PC, 2 CP, 3 CC; -1 none
-        bool split_t = false; // when children are pushed: which side was split
-        int nkids = 0;
-        u32 kid_ids[4] = {0, 0, 0, 0};
-        u32 t = 0, s = 0;
-        if (active) {
-            const u64 pr = fin[i];
-            t = (u32)(pr >> 32);
-            s = (u32)(pr & 0xffffffffu);
-            const i32 nt = nend[t] - nbeg[t], ns = nend[s] - nbeg[s];
-            const bool big_t = nt > n_crit, big_s = ns > n_crit;
-            if (mac_separated(geo[t], geo[s], theta2)) {
-                kind = (big_t ? 2 : 0) + (big_s ? 1 : 0);
-            } else if (!big_t && !big_s) {
-                kind = 0;
-            } else {
-                const int lt = level_of_offset_table(level_off_tab, L, t);
-                const int ls = level_of_offset_table(level_off_tab, L, s);
-                const bool int_t = big_t && lt < L, int_s = big_s && ls < L;
-                split_t = nt >= ns;
-                if (split_t && !int_t) split_t = false;
-                if (!split_t && !int_s) {
-                    if (int_t) split_t = true;
-                    else kind = 0;
-                }
-                if (kind < 0) {
-                    const u32 x = split_t ? t : s;
-                    const int lx = split_t ? lt : ls;
-                    const i64 child0 = level_off_tab[lx + 1] + 4 * ((i64)x - level_off_tab[lx]);
-                    for (int c = 0; c < 4; ++c) {
-                        const u32 cid = (u32)(child0 + c);
-                        if (nend[cid] - nbeg[cid] > 0) kid_ids[nkids++] = cid;
+    const int tid = threadIdx.x;
+    const u64 round = (u64)256 * TRAV_IPT;
+    for (u64 r0 = (u64)blockIdx.x * round; r0 < nin; r0 += (u64)gridDim.x * round) {
+        u64 keyv[TRAV_IPT];
+        int kind[TRAV_IPT];
+        bool split_t[TRAV_IPT];
+        int nkids[TRAV_IPT];
+        u32 kids[TRAV_IPT][4];
+        u32 tt[TRAV_IPT], ss[TRAV_IPT];
+        u32 ct = 0, cn = 0, ck = 0;
+#pragma unroll
+        for (int k = 0; k < TRAV_IPT; ++k) {
+            const u64 i = r0 + (u64)k * 256 + tid;
+            kind[k] = -1;
+            split_t[k] = false;
+            nkids[k] = 0;
+            tt[k] = ss[k] = 0;
+            if (i < nin) {
+                const u64 pr = fin[i];
+                const u32 t = (u32)(pr >> 32), s = (u32)(pr & 0xffffffffu);
+                tt[k] = t;
+                ss[k] = s;
+                const i32 nt = ncnt[t], ns = ncnt[s];
+                const bool big_t = nt > n_crit, big_s = ns > n_crit;
+                if (mac_separated(mac[t], mac[s], theta2)) {
+                    kind[k] = (big_t ? 2 : 0) + (big_s ? 1 : 0);
+                } else if (!big_t && !big_s) {
+                    kind[k] = 0;
+                } else {
+                    const int lt = level_of_offset_table(level_off_tab, L, t);
+                    const int ls = level_of_offset_table(level_off_tab, L, s);
+                    const bool int_t = big_t && lt < L, int_s = big_s && ls < L;
+                    bool st = nt >= ns;
+                    if (st && !int_t) st = false;
+                    if (!st && !int_s) {
+                        if (int_t) st = true;
+                        else kind[k] = 0;
+                    }
+                    if (kind[k] < 0) {
+                        split_t[k] = st;
+                        const u32 x = st ? t : s;
+                        const int lx = st ? lt : ls;
+                        const i64 child0 = level_off_tab[lx + 1] + 4 * ((i64)x - level_off_tab[lx]);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const u32 cid = (u32)(child0 + c);
+                            if (ncnt[cid] > 0) kids[k][nkids[k]++] = cid;
+                        }
                     }
                 }
+                keyv[k] = ((u64)t << (W + 1)) | ((u64)(kind[k] & 1) << W) | (u64)s;
+            }
+            ct += (kind[k] == 0 || kind[k] == 1) ? 1u : 0u;
+            cn += (kind[k] == 2 || kind[k] == 3) ? 1u : 0u;
+            ck += (u32)nkids[k];
+        }
+        u32 tot_t, tot_n, tot_k;
+        u32 pt = block_scan_u32(ct, wsum[0], &tot_t);
+        u32 pn = block_scan_u32(cn, wsum[1], &tot_n);
+        u32 pk = block_scan_u32(ck, wsum[2], &tot_k);
+        if (tid == 0) {
+            bases[0] = tot_t ? atomicAdd(&counters[C_TLIST], tot_t) : 0u;
+            bases[1] = tot_n ? atomicAdd(&counters[C_NLIST], tot_n) : 0u;
+            bases[2] = tot_k ? atomicAdd(&counters[C_FRONT + iter + 1], tot_k) : 0u;
+        }
+        __syncthreads();
+        u32 ot = bases[0] + pt, on = bases[1] + pn, ok = bases[2] + pk;
+        bool overflow = false;
+#pragma unroll
+        for (int k = 0; k < TRAV_IPT; ++k) {
+            if (kind[k] == 0 || kind[k] == 1) {
+                if (ot < cap) tlist[ot] = keyv[k];
+                else overflow = true;
+                ++ot;
+            } else if (kind[k] >= 2) {
+                if (on < cap) nlist[on] = keyv[k];
+                else overflow = true;
+                ++on;
+            }
+            for (int c = 0; c < nkids[k]; ++c) {
+                const u64 pr = split_t[k] ? (((u64)kids[k][c] << 32) | (u64)ss[k]) : (((u64)tt[k] << 32) | (u64)kids[k][c]);
+                if (ok < cap) fout[ok] = pr;
+                else overflow = true;
+                ++ok;
             }
         }
-        // list appends (PP/PC -> tlist, CP/CC -> nlist)
-        const bool to_t = kind == 0 || kind == 1;
-        const bool to_n = kind == 2 || kind == 3;
-        const u32 st = wave_append(&counters[C_TLIST], to_t);
-        const u32 sn = wave_append(&counters[C_NLIST], to_n);
-        const u64 keyv = ((u64)t << (W + 1)) | ((u64)(kind & 1) << W) | (u64)s;
-        if (to_t) {
-            if (st < cap) tlist[st] = keyv;
-            else atomicOr(&counters[C_OVERFLOW], 1u);
-        }
-        if (to_n) {
-            if (sn < cap) nlist[sn] = keyv;
-            else atomicOr(&counters[C_OVERFLOW], 1u);
-        }
-        // frontier pushes: wave inclusive scan of nkids
-        int incl = nkids;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int v = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += v;
-        }
-        const int total = __shfl(incl, 63, 64);
-        if (total > 0) {
-            u32 fbase = 0;
-            if (lane == 0) fbase = atomicAdd(&counters[C_FRONT + iter + 1], (u32)total);
-            fbase = __shfl(fbase, 0, 64);
-            const u32 my = fbase + (u32)(incl - nkids);
-            for (int c = 0; c < nkids; ++c) {
-                const u64 pr = split_t ? (((u64)kid_ids[c] << 32) | (u64)s) : (((u64)t << 32) | (u64)kid_ids[c]);
-                if (my + c < cap) fout[my + c] = pr;
-                else atomicOr(&counters[C_OVERFLOW], 1u);
-            }
-        }
+        if (overflow) atomicOr(&counters[C_OVERFLOW], 1u);
+        __syncthreads();  // wsum / bases reused by the next round
     }
+}
+
+// per-node particle count and the compact MAC record (circumcentre, radius)
+__global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbeg, const i32* __restrict__ nend,
+                                                      i64 n_nodes, i32* __restrict__ ncnt) {
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < (u64)n_nodes; i += stride) ncnt[i] = nend[i] - nbeg[i];
 }
 
 // Segments of a sorted list: entries with the same target t occupy
@@ -359,10 +494,21 @@ void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, c
     hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, q);
 }
 
-void launch_p2m(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, const NodeGeo* geo,
-                const double* sx, const double* sy, const double* sz, const double* q, RefDev ref, double* w) {
-    const unsigned grid = (unsigned)(n_nodes < 8192 ? n_nodes : 8192);
-    hipLaunchKernelGGL(k_p2m, dim3(grid), dim3(256), 0, s, nbeg, nend, n_nodes, n_crit, geo, sx, sy, sz, q, ref, w);
+void launch_upward(hipStream_t s, const i32* nbeg, const i32* nend, const i64* level_off_host, int L, int n_crit,
+                   const NodeGeo* geo, const double* sx, const double* sy, const double* sz, const double* q,
+                   RefDev ref, Prox* prox) {
+    for (int lvl = L; lvl >= 0; --lvl) {
+        const i64 node0 = level_off_host[lvl];
+        const i64 nn = level_off_host[lvl + 1] - node0;
+        const i64 child_off = lvl < L ? level_off_host[lvl + 1] : 0;
+        // few nodes: one workgroup per node; many: 256 nodes per workgroup,
+        // checked in parallel, the big ones processed in turn
+        const int chunk = nn > 8192 ? 256 : 1;
+        const i64 nchunks = (nn + chunk - 1) / chunk;
+        const unsigned grid = (unsigned)(nchunks < 4096 ? nchunks : 4096);
+        hipLaunchKernelGGL(k_upward_level, dim3(grid), dim3(256), 0, s, node0, nn, chunk, lvl, L, child_off, nbeg,
+                           nend, n_crit, geo, sx, sy, sz, q, ref, prox);
+    }
 }
 
 void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v) {
@@ -377,18 +523,24 @@ void launch_fill_f64(hipStream_t s, double* p, i64 n, double v) {
     hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, p, n, v);
 }
 
-void launch_traverse(hipStream_t s, const i32* nbeg, const i32* nend, const i64* level_off_tab, int L,
-                     const NodeGeo* geo, double theta, int n_crit, int W, u64* front0, u64* front1, u32 cap,
-                     u64* tlist, u64* nlist, u32* counters) {
+void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, i32* ncnt) {
+    const i64 b = blocks_for(n_nodes, 256);
+    hipLaunchKernelGGL(k_node_counts, dim3((unsigned)(b < 2048 ? b : 2048)), dim3(256), 0, s, nbeg, nend, n_nodes,
+                       ncnt);
+}
+
+void launch_traverse(hipStream_t s, const i32* ncnt, const NodeMac* mac, const i64* level_off_tab, int L,
+                     double theta, int n_crit, int W, u64* front0, u64* front1, u32 cap, u64* tlist, u64* nlist,
+                     u32* counters) {
     launch_fill_u32(s, counters, C_COUNT, 0u);
-    hipLaunchKernelGGL(k_trav_init, dim3(1), dim3(512), 0, s, nbeg, nend, front0, cap, counters);
+    hipLaunchKernelGGL(k_trav_init, dim3(1), dim3(512), 0, s, ncnt, front0, cap, counters);
     const double theta2 = theta * theta;
     const int iters = 2 * L + 2;
     for (int it = 0; it < iters; ++it) {
         const u64* fin = (it % 2 == 0) ? front0 : front1;
         u64* fout = (it % 2 == 0) ? front1 : front0;
-        hipLaunchKernelGGL(k_trav_level, dim3(1024), dim3(256), 0, s, it, fin, fout, cap, nbeg, nend,
-                           level_off_tab, L, geo, theta2, n_crit, W, tlist, nlist, counters);
+        hipLaunchKernelGGL(k_trav_level, dim3(1024), dim3(256), 0, s, it, fin, fout, cap, ncnt, mac, level_off_tab,
+                           L, theta2, n_crit, W, tlist, nlist, counters);
     }
 }
 

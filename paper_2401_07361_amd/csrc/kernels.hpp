@@ -11,11 +11,13 @@ void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* 
                    double* sx, double* sy, double* sz);
 void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, i32* nbeg, i32* nend);
 void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area, double* q);
-void launch_p2m(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, const NodeGeo* geo,
-                const double* sx, const double* sy, const double* sz, const double* q, RefDev ref, double* w);
-void launch_traverse(hipStream_t s, const i32* nbeg, const i32* nend, const i64* level_off_tab, int L,
-                     const NodeGeo* geo, double theta, int n_crit, int W, u64* front0, u64* front1, u32 cap,
-                     u64* tlist, u64* nlist, u32* counters);
+void launch_upward(hipStream_t s, const i32* nbeg, const i32* nend, const i64* level_off_host, int L, int n_crit,
+                   const NodeGeo* geo, const double* sx, const double* sy, const double* sz, const double* q,
+                   RefDev ref, Prox* prox);
+void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, i32* ncnt);
+void launch_traverse(hipStream_t s, const i32* ncnt, const NodeMac* mac, const i64* level_off_tab, int L,
+                     double theta, int n_crit, int W, u64* front0, u64* front1, u32 cap, u64* tlist, u64* nlist,
+                     u32* counters);
 void launch_segments(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, i32* seg_beg, i32* seg_end);
 void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v);
 void launch_fill_f64(hipStream_t s, double* p, i64 n, double v);
@@ -34,6 +36,8 @@ struct EvalArgs {
     const i32* nseg_end;
     const i32* nbeg;
     const i32* nend;
+    const i32* ncnt;
+    int n_crit;
     const NodeGeo* geo;
     const i64* level_off_tab;
     int L;
@@ -41,7 +45,7 @@ struct EvalArgs {
     const double* sy;
     const double* sz;
     const double* sq;
-    const double* wq;    // proxy charges, n_nodes x np
+    const Prox* prox;    // interpolation points with proxy charges, n_nodes x np
     double* alpha;       // target-side coefficients, n_nodes x np x 3
     double* Wacc;        // per-particle sums, n x 3 (tree order)
     const u32* leaf;

@@ -25,15 +25,18 @@ struct stc_ctx {
     std::vector<i64> level_off_host;
     // device buffers (all allocated in stc_create)
     NodeGeo* geo = nullptr;
+    NodeMac* mac = nullptr;
+    i32* ncnt = nullptr;
     i64* level_off = nullptr;
-    double *ref_points = nullptr, *ref_vinv = nullptr, *ref_coef = nullptr;
+    double *ref_points = nullptr, *ref_vinv = nullptr, *ref_vinvT = nullptr, *ref_coef = nullptr;
     int* ref_expo = nullptr;
     u64 *keys_a = nullptr, *keys_b = nullptr, *keys_sorted = nullptr;
     i32* perm = nullptr;
     u32* leaf = nullptr;
     double *sx = nullptr, *sy = nullptr, *sz = nullptr, *sq = nullptr;
     i32 *nbeg = nullptr, *nend = nullptr;
-    double *wq = nullptr, *alpha = nullptr, *Wacc = nullptr;
+    Prox* prox = nullptr;
+    double *alpha = nullptr, *Wacc = nullptr;
     u64 *front0 = nullptr, *front1 = nullptr;
     u64 *tlist_a = nullptr, *tlist_b = nullptr, *nlist_a = nullptr, *nlist_b = nullptr;
     u64 *tlist = nullptr, *nlist = nullptr;
@@ -42,6 +45,7 @@ struct stc_ctx {
     u32* flags = nullptr;
     unsigned long long* evals = nullptr;
     u32* hist = nullptr;
+    u32* hist_totals = nullptr;
     int hist_blocks = 0;
     // RK4 buffers
     double *rk_x = nullptr, *rk_z = nullptr, *rk_u = nullptr, *rk_xacc = nullptr, *rk_zacc = nullptr;
@@ -102,6 +106,7 @@ RefDev ref_dev(const stc_ctx* c) {
     RefDev r;
     r.points = c->ref_points;
     r.vinv = c->ref_vinv;
+    r.vinvT = c->ref_vinvT;
     r.expo = c->ref_expo;
     r.coef = c->ref_coef;
     r.degree = c->p.degree;
@@ -121,6 +126,8 @@ EvalArgs eval_args(stc_ctx* c) {
     a.nseg_end = c->nseg_end;
     a.nbeg = c->nbeg;
     a.nend = c->nend;
+    a.ncnt = c->ncnt;
+    a.n_crit = c->p.n_crit;
     a.geo = c->geo;
     a.level_off_tab = c->level_off;
     a.L = c->L;
@@ -128,7 +135,7 @@ EvalArgs eval_args(stc_ctx* c) {
     a.sy = c->sy;
     a.sz = c->sz;
     a.sq = c->sq;
-    a.wq = c->wq;
+    a.prox = c->prox;
     a.alpha = c->alpha;
     a.Wacc = c->Wacc;
     a.leaf = c->leaf;
@@ -165,12 +172,16 @@ stc_status do_build(stc_ctx* c, i64 n, const double* d_x) {
     mark(c, 0);
     launch_fill_u32(s, reinterpret_cast<u32*>(c->nbeg), c->n_nodes, 0u);
     launch_fill_u32(s, reinterpret_cast<u32*>(c->nend), c->n_nodes, 0u);
-    if (n == 0) return check_launch(c, "tree_build");
+    if (n == 0) {
+        launch_fill_u32(s, reinterpret_cast<u32*>(c->ncnt), c->n_nodes, 0u);
+        return check_launch(c, "tree_build");
+    }
     launch_bin(s, d_x, n, c->geo, c->L, c->keys_a, c->flags);
-    radix_sort(s, c->keys_a, c->keys_b, nullptr, (u32)n, 32, 32 + 2 * c->L + 5, SortScratch{c->hist, c->hist_blocks},
+    radix_sort(s, c->keys_a, c->keys_b, nullptr, (u32)n, 32, 32 + 2 * c->L + 5, SortScratch{c->hist, c->hist_totals, c->hist_blocks},
                &c->keys_sorted);
     launch_gather(s, c->keys_sorted, n, d_x, c->perm, c->leaf, c->sx, c->sy, c->sz);
     launch_node_ranges(s, c->leaf, n, c->L, c->nbeg, c->nend);
+    launch_node_counts(s, c->nbeg, c->nend, c->n_nodes, c->ncnt);
     return check_launch(c, "tree_build");
 }
 
@@ -179,7 +190,8 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
     mark(c, 1);
     launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sq);
     if (c->n > 0)
-        launch_p2m(s, c->nbeg, c->nend, c->n_nodes, c->p.n_crit, c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c), c->wq);
+        launch_upward(s, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit, c->geo, c->sx, c->sy, c->sz,
+                      c->sq, ref_dev(c), c->prox);
     c->have_upward = true;
     return check_launch(c, "upward");
 }
@@ -187,12 +199,19 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
 stc_status do_traverse(stc_ctx* c) {
     hipStream_t s = c->stream;
     mark(c, 2);
-    launch_traverse(s, c->nbeg, c->nend, c->level_off, c->L, c->geo, c->p.theta, c->p.n_crit, c->W, c->front0,
-                    c->front1, c->cap, c->tlist_a, c->nlist_a, c->counters);
+    launch_traverse(s, c->ncnt, c->mac, c->level_off, c->L, c->p.theta, c->p.n_crit, c->W, c->front0, c->front1,
+                    c->cap, c->tlist_a, c->nlist_a, c->counters);
     const int bits = 2 * c->W + 1;
-    SortScratch sc{c->hist, c->hist_blocks};
-    radix_sort(s, c->tlist_a, c->tlist_b, c->counters + C_TLIST, c->cap, 0, bits, sc, &c->tlist);
-    radix_sort(s, c->nlist_a, c->nlist_b, c->counters + C_NLIST, c->cap, 0, bits, sc, &c->nlist);
+    SortScratch sc{c->hist, c->hist_totals, c->hist_blocks};
+    {
+        u64* keys[2] = {c->tlist_a, c->nlist_a};
+        u64* tmp[2] = {c->tlist_b, c->nlist_b};
+        const u32* cnt[2] = {c->counters + C_TLIST, c->counters + C_NLIST};
+        u64* res[2];
+        radix_sort_batch(s, 2, keys, tmp, cnt, c->cap, 0, bits, sc, res);
+        c->tlist = res[0];
+        c->nlist = res[1];
+    }
     launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_beg), c->n_nodes, 0u);
     launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_end), c->n_nodes, 0u);
     launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_beg), c->n_nodes, 0u);
@@ -327,19 +346,20 @@ stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_
     for (int l = 0; l <= c->L + 1; ++l) c->level_off_host[l] = level_offset(l);
     const i64 nm = std::max<i64>(n_max, 1);
     c->hist_blocks = (int)((std::max<i64>(c->cap, nm) + 4095) / 4096);
-    bool ok = dalloc(c, &c->geo, c->geo_host.size()) && dalloc(c, &c->level_off, c->level_off_host.size()) &&
-              dalloc(c, &c->ref_points, 3 * c->np) && dalloc(c, &c->ref_vinv, (size_t)c->np * c->np) &&
+    bool ok = dalloc(c, &c->geo, c->geo_host.size()) && dalloc(c, &c->mac, c->geo_host.size()) &&
+              dalloc(c, &c->ncnt, c->n_nodes) && dalloc(c, &c->level_off, c->level_off_host.size()) &&
+              dalloc(c, &c->ref_points, 3 * c->np) && dalloc(c, &c->ref_vinv, (size_t)c->np * c->np) && dalloc(c, &c->ref_vinvT, (size_t)c->np * c->np) &&
               dalloc(c, &c->ref_coef, c->np) && dalloc(c, &c->ref_expo, 3 * c->np) &&
               dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) && dalloc(c, &c->perm, nm) &&
               dalloc(c, &c->leaf, nm) && dalloc(c, &c->sx, nm) && dalloc(c, &c->sy, nm) && dalloc(c, &c->sz, nm) &&
               dalloc(c, &c->sq, nm) && dalloc(c, &c->nbeg, c->n_nodes) && dalloc(c, &c->nend, c->n_nodes) &&
-              dalloc(c, &c->wq, (size_t)c->n_nodes * c->np) && dalloc(c, &c->alpha, (size_t)c->n_nodes * c->np * 3) &&
+              dalloc(c, &c->prox, (size_t)c->n_nodes * c->np) && dalloc(c, &c->alpha, (size_t)c->n_nodes * c->np * 3) &&
               dalloc(c, &c->Wacc, 3 * nm) && dalloc(c, &c->front0, c->cap) && dalloc(c, &c->front1, c->cap) &&
               dalloc(c, &c->tlist_a, c->cap) && dalloc(c, &c->tlist_b, c->cap) && dalloc(c, &c->nlist_a, c->cap) &&
               dalloc(c, &c->nlist_b, c->cap) && dalloc(c, &c->tseg_beg, c->n_nodes) &&
               dalloc(c, &c->tseg_end, c->n_nodes) && dalloc(c, &c->nseg_beg, c->n_nodes) &&
               dalloc(c, &c->nseg_end, c->n_nodes) && dalloc(c, &c->counters, C_COUNT) && dalloc(c, &c->flags, 4) &&
-              dalloc(c, &c->evals, 8) && dalloc(c, &c->hist, (size_t)256 * c->hist_blocks) &&
+              dalloc(c, &c->evals, 8) && dalloc(c, &c->hist, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->hist_totals, 512) &&
               dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
               dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm);
     if (!ok) {
@@ -349,10 +369,18 @@ stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_
     c->tlist = c->tlist_a;
     c->nlist = c->nlist_a;
     hipStream_t s = c->stream;
+    std::vector<double> vinvT_host((size_t)c->np * c->np);
+    for (int k = 0; k < c->np; ++k)
+        for (int m = 0; m < c->np; ++m) vinvT_host[(size_t)m * c->np + k] = c->ref_host.vinv[(size_t)k * c->np + m];
+    std::vector<NodeMac> mac_host(c->geo_host.size());
+    for (size_t i = 0; i < mac_host.size(); ++i)
+        mac_host[i] = NodeMac{c->geo_host[i].c[0], c->geo_host[i].c[1], c->geo_host[i].c[2], c->geo_host[i].r};
     bool cp = hipMemcpyAsync(c->geo, c->geo_host.data(), c->geo_host.size() * sizeof(NodeGeo), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->mac, mac_host.data(), mac_host.size() * sizeof(NodeMac), hipMemcpyHostToDevice, s) == hipSuccess &&
               hipMemcpyAsync(c->level_off, c->level_off_host.data(), c->level_off_host.size() * sizeof(i64), hipMemcpyHostToDevice, s) == hipSuccess &&
               hipMemcpyAsync(c->ref_points, c->ref_host.points.data(), 3 * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
               hipMemcpyAsync(c->ref_vinv, c->ref_host.vinv.data(), (size_t)c->np * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(c->ref_vinvT, vinvT_host.data(), (size_t)c->np * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
               hipMemcpyAsync(c->ref_coef, c->ref_host.coef.data(), c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
               hipMemcpyAsync(c->ref_expo, c->ref_host.expo.data(), 3 * c->np * sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess;
     launch_fill_u32(s, c->counters, C_COUNT, 0u);
@@ -368,7 +396,7 @@ stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
-    c->grid = std::max(8, (cus * 16 / 8) * 8);
+    c->grid = std::max(8, (cus * 12 / 8) * 8);
     *out = c;
     return STC_OK;
 }
@@ -599,8 +627,11 @@ stc_status stc_copy_proxy_charges(stc_ctx* c, int64_t node_id, double* h_w) {
         for (int m = 0; m < c->np; ++m) h_w[m] = 0.0;
         return STC_OK;
     }
-    if (hipMemcpy(h_w, c->wq + (size_t)node_id * c->np, c->np * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    std::vector<Prox> pr(c->np);
+    if (hipMemcpy(pr.data(), c->prox + (size_t)node_id * c->np, c->np * sizeof(Prox), hipMemcpyDeviceToHost) !=
+        hipSuccess)
         return fail(c, STC_ERR_DEVICE, "copy failed");
+    for (int m = 0; m < c->np; ++m) h_w[m] = pr[m].w;
     return STC_OK;
 }
 
