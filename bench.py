@@ -22,9 +22,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Benchmark setting: the fastest (theta, degree, N_T) found with E <= 5e-7
+# (half the 1e-6 bar) on this workload; see the design doc for the sweep.
+BENCH_THETA = 0.8
+BENCH_DEGREE = 10
+BENCH_N_CRIT = 64
+
 FP32_FLOPS = 16   # per |x-y|^2/2 kernel evaluation: 3 sub, |d|^2 5, div 1, *q 1, 3 fma 6
 FP64_FLOPS = 17   # per 1 - x.y evaluation with the (y - x) form: dot 5, 1- 1, div 1, *q 1, 3 sub, 3 fma 6
 PEAK_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, without packed FP32
+COPY_BYTES = 256 << 20    # calibration copy: bytes read = bytes written
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_near_gv_l8_hbm_traffic.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_eval.hip", "common.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2401_07361_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(config_tag):
+    """HBM bytes per k_near launch from the committed counter summary, if it
+    was taken on the current kernel source and the same configuration."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].strip().split(": ", 1)
+            rec[k] = v.strip("` ")
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("config") != config_tag:
+        return None
+    try:
+        return int(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -68,12 +103,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--theta", type=float, default=0.7)
-    ap.add_argument("--degree", type=int, default=10)
-    ap.add_argument("--n-crit", type=int, default=64)
+    ap.add_argument("--theta", type=float, default=BENCH_THETA)
+    ap.add_argument("--degree", type=int, default=BENCH_DEGREE)
+    ap.add_argument("--n-crit", type=int, default=BENCH_N_CRIT)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-check", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -96,6 +133,12 @@ def main():
     den = "dist2" if args.precision == "fp32" else "dot"
     ctx = stc.Context(n, theta=args.theta, degree=args.degree, n_crit=args.n_crit,
                       precision=args.precision, denominator=den)
+    if args.copy_check:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         ctx.velocity(xd, zd, ad, out=out)
     ctx.sync()
@@ -128,8 +171,9 @@ def main():
     near_flops = (evals["PP"] + evals["PC"]) * flops_per
     near_s = phase_ms["near"] / 1e3
     achieved = near_flops / near_s / 1e12
+    config_tag = f"gv_l8 L{args.level} theta={args.theta} d={args.degree} n_crit={args.n_crit} {args.precision}"
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=None,
+                frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=recorded_traffic(config_tag),
                 kernel="k_near (PP + PC)", kernel_ms=round(phase_ms["near"], 4),
                 kernel_evals_per_launch=int(evals["PP"] + evals["PC"]))
 
@@ -142,7 +186,8 @@ def main():
                     theta=args.theta, degree=args.degree, n_crit=args.n_crit, max_level=ctx.max_level,
                     precision=args.precision, denominator=den, rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"),
                     err_ok=bool(err <= 1e-6), lists=counts,
-                    kernel_evals=int(sum(evals.values())), phase_ms={p: round(v, 4) for p, v in phase_ms.items()}),
+                    kernel_evals=int(sum(evals.values())), phase_ms={p: round(v, 4) for p, v in phase_ms.items()},
+                    kernel_source_hash=kernel_source_hash()),
         roofline=roof,
     )
     ctx.close()

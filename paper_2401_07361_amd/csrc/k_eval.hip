@@ -302,33 +302,38 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
         const u32 se = (u32)a.nseg_end[t];
         const NodeGeo& gt = a.geo[t];
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
-        const int ntc = np;  // np <= 120 < NTT
-        const int S = NTT / ntc;
-        const int ti = tid % ntc, sl = tid / ntc;
-        const bool act = sl < S;
-        double y[3];
-        const double nrm = proxy_point(gt, a.ref.points + 3 * ti, y);
-        if (act && sl == 0) nd[ti] = ipow(nrm, d);
-        const T tx = (T)(y[0] - cx), ty = (T)(y[1] - cy), tz = (T)(y[2] - cz);
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        accumulate_entries<T, DEN, NTT>(a, a.nlist, e, se, 3u, 0xffffffffu, ti, act, sl, S, tx, ty, tz, cx, cy, cz,
-                                        sh, ax, ay, az);
-        sh.red[0][tid] = act ? ax : 0.0;
-        sh.red[1][tid] = act ? ay : 0.0;
-        sh.red[2][tid] = act ? az : 0.0;
-        __syncthreads();
-        if (act && sl == 0) {
-            double sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int k = 0; k < S; ++k) {
-                sx += sh.red[0][k * ntc + ti];
-                sy += sh.red[1][k * ntc + ti];
-                sz += sh.red[2][k * ntc + ti];
+        // target points in chunks of at most NTT/4, so that full chunks keep
+        // every thread busy with 4 source slices
+        for (int cb = 0; cb < np; cb += NTT / 4) {
+            const int ntc = (np - cb) < NTT / 4 ? (np - cb) : NTT / 4;
+            const int S = NTT / ntc;
+            const int ti = tid % ntc, sl = tid / ntc;
+            const bool act = sl < S;
+            const int me = cb + ti;
+            double y[3];
+            const double nrm = proxy_point(gt, a.ref.points + 3 * me, y);
+            if (act && sl == 0) nd[me] = ipow(nrm, d);
+            const T tx = (T)(y[0] - cx), ty = (T)(y[1] - cy), tz = (T)(y[2] - cz);
+            double ax = 0.0, ay = 0.0, az = 0.0;
+            accumulate_entries<T, DEN, NTT>(a, a.nlist, e, se, 3u, 0xffffffffu, me, act, sl, S, tx, ty, tz, cx, cy,
+                                            cz, sh, ax, ay, az);
+            sh.red[0][tid] = act ? ax : 0.0;
+            sh.red[1][tid] = act ? ay : 0.0;
+            sh.red[2][tid] = act ? az : 0.0;
+            __syncthreads();
+            if (act && sl == 0) {
+                double sx = 0.0, sy = 0.0, sz = 0.0;
+                for (int k = 0; k < S; ++k) {
+                    sx += sh.red[0][k * ntc + ti];
+                    sy += sh.red[1][k * ntc + ti];
+                    sz += sh.red[2][k * ntc + ti];
+                }
+                wt[me][0] = sx;
+                wt[me][1] = sy;
+                wt[me][2] = sz;
             }
-            wt[ti][0] = sx;
-            wt[ti][1] = sy;
-            wt[ti][2] = sz;
+            __syncthreads();
         }
-        __syncthreads();
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
         block_matvec<NTT, 3>(a.ref.vinvT, np, nd, wt, &sh.red[0][0], co);
         for (int k = tid; k < 3 * np; k += NTT) a.alpha[(size_t)t * np * 3 + k] = co[k / 3][k % 3];

@@ -1,0 +1,82 @@
+"""GPU checks at the benchmark's full sizes, in the launch configuration
+bench.py times: sampled targets against the oracle's FP64 direct sum
+(computed target by target), and properties that hold at any size."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import direct as odirect
+from oracle import metrics
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pair_coverage(ctx, n):
+    """Number of ordered particle pairs (i, j), i != j, that the four lists
+    cover; must be n (n - 1) for any tree and any theta."""
+    _, cnt = ctx.copy_tree()
+    cnt = cnt.astype(np.int64)
+    total = 0
+    for kind in ("PP", "PC", "CP", "CC"):
+        lst = ctx.copy_list(kind)
+        t, s = lst[:, 0], lst[:, 1]
+        total += int((cnt[t] * cnt[s]).sum())
+        if kind == "PP":
+            total -= int(cnt[t[t == s]].sum())
+    return total
+
+
+@pytest.mark.parametrize("wl_name", ["gv_l8", "gvpair_l9"])
+def test_bench_configuration_at_full_size(stc_lib, wl_name):
+    import bench
+    wl = S.make_workload(wl_name)
+    x, z, a = wl["x"], wl["zeta"], wl["area"]
+    n = len(x)
+    say(f"full size {wl_name} N={n} theta={bench.BENCH_THETA} d={bench.BENCH_DEGREE}")
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    ctx = stc_lib.Context(n, theta=bench.BENCH_THETA, degree=bench.BENCH_DEGREE, n_crit=bench.BENCH_N_CRIT,
+                          precision="fp32", denominator="dist2")
+    u = ctx.velocity(xd, zd, ad).cpu().numpy()
+    ctx.sync()
+    # pair coverage holds at any size
+    assert _pair_coverage(ctx, n) == n * (n - 1)
+    # tangency is exact by construction (up to the final FP64 cross product)
+    assert np.abs((x * u).sum(1)).max() <= 1e-12 * np.abs(u).max()
+    # sampled targets against the oracle's direct sum
+    idx = S.subset_indices(n, 48, 17)
+    ref = odirect.velocity(x, z, a, targets=idx)
+    err = metrics.rel_l2_velocity(u[idx], ref, a[idx])
+    say(f"  E on 48 sampled targets vs oracle direct = {err:.3e}")
+    assert err <= 1e-6
+    ctx.close()
+
+
+def test_fp32_and_fp64_trees_differ_by_rounding_only(stc_lib):
+    """Same lists, same interpolation: the precision form differs from the
+    FP64 tree code by FP32 rounding of the kernel sums only."""
+    import bench
+    wl = S.make_workload("gv_l8")
+    x, z, a, sub = wl["x"], wl["zeta"], wl["area"], wl["subset"]
+    n = len(x)
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    say("fp32 vs fp64 tree at N=655362")
+    kw = dict(theta=bench.BENCH_THETA, degree=bench.BENCH_DEGREE, n_crit=bench.BENCH_N_CRIT, denominator="dist2")
+    c32 = stc_lib.Context(n, precision="fp32", **kw)
+    c64 = stc_lib.Context(n, precision="fp64", **kw)
+    u32 = c32.velocity(xd, zd, ad).cpu().numpy()
+    u64 = c64.velocity(xd, zd, ad).cpu().numpy()
+    c32.close()
+    c64.close()
+    assert metrics.rel_l2_velocity(u32, u64, a) < 2e-7
+    # and the FP64 tree against the GPU FP64 direct sum on the 4096 targets
+    ud = stc_lib.direct(xd, zd, ad, targets=torch.from_numpy(sub).cuda()).cpu().numpy()
+    assert metrics.rel_l2_velocity(u64[sub], ud, a[sub]) < 1e-6
