@@ -51,6 +51,7 @@ typedef enum stc_status {
 enum { STC_FP64 = 0, STC_FP32 = 1 };           /* arithmetic of the PP/PC/CP/CC sums   */
 enum { STC_DEN_DOT = 0, STC_DEN_DIST2 = 1 };   /* 1 - x.y (Sec. 2) | |x-y|^2/2 (Sec. 2, alt. kernel) */
 enum { STC_LIST_PP = 0, STC_LIST_PC = 1, STC_LIST_CP = 2, STC_LIST_CC = 3 };
+enum { STC_FLAG_EAGER_RK4 = 1 };              /* stc_rk4 without graph capture */
 
 /* Method parameters (Sec. 3, dual tree traversal).
  *  theta       MAC: a pair is well separated iff (r_t + r_s) / R < theta,
@@ -65,6 +66,7 @@ enum { STC_LIST_PP = 0, STC_LIST_PC = 1, STC_LIST_CP = 2, STC_LIST_CC = 3 };
  *              target-relative coordinates and FP64 accumulation per tile;
  *              proxy charges, interpolation weights and the output stay FP64.
  *  denominator STC_DEN_DOT or STC_DEN_DIST2.
+ *  flags       0, or STC_FLAG_EAGER_RK4.
  *  list_capacity entries per interaction list and per traversal frontier;
  *              0 for the default (16 * n_max, at least 65536).            */
 typedef struct stc_params {
@@ -74,7 +76,7 @@ typedef struct stc_params {
     int32_t max_level;
     int32_t precision;
     int32_t denominator;
-    int32_t reserved0;
+    int32_t flags;
     int64_t list_capacity;
 } stc_params;
 
@@ -157,8 +159,15 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
 /* Classical RK4 (Sec. 4) for n_steps steps of dt on (x, zeta):
  *   dx/dt = u(x; zeta A),  dzeta/dt = -2 omega u_z  (Sec. 2, discrete system)
  * Every stage is a full stc_velocity (tree rebuilt).  Stage positions are
- * used as computed; after each step x <- x / |x|.  d_x, d_zeta are updated
- * in place.  Units are the caller's (dt * omega dimensionless). */
+ * used as computed (off the sphere), so the context must use STC_DEN_DIST2
+ * (Sec. 2: the |x-y|^2/2 form stays well defined off the sphere, while
+ * 1 - x.y vanishes for close pairs there); otherwise STC_ERR_INVALID_ARG.
+ * After each step x <- x / |x|.  d_x, d_zeta are updated
+ * in place.  Units are the caller's (dt * omega dimensionless).
+ * Unless the context has STC_FLAG_EAGER_RK4, one step is captured once into a
+ * HIP graph (on a stream the context creates) and the graph is launched on
+ * the context stream once per step; it is re-captured when n, the pointers,
+ * dt or omega change.  Results are bitwise those of the eager path. */
 stc_status stc_rk4(stc_ctx* ctx, int64_t n, double* d_x, double* d_zeta, const double* d_area,
                    double dt, double omega, int32_t n_steps);
 

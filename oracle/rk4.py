@@ -6,8 +6,10 @@ State (x, zeta); right-hand side (Sec. 2, discrete system)
     dzeta_i/dt = -2 Omega dz_i/dt = -2 Omega u_i,z
 The velocity is re-evaluated from scratch at every stage (the tree is rebuilt
 for the stage positions).  Readings: stage positions are used as computed
-(the |x - y|^2 / 2 kernel is well defined off the sphere); after each full
-step every particle is projected back to the unit sphere, x <- x / |x|.  The
+(the |x - y|^2 / 2 kernel is well defined off the sphere, Sec. 2; with
+1 - x . y the denominator of close pairs vanishes there, so time stepping
+uses the former); after each full step every particle is projected back to
+the unit sphere, x <- x / |x|.  The
 areas A are constant in time.
 """
 

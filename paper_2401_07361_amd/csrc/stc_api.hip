@@ -49,6 +49,12 @@ struct stc_ctx {
     int hist_blocks = 0;
     // RK4 buffers
     double *rk_x = nullptr, *rk_z = nullptr, *rk_u = nullptr, *rk_xacc = nullptr, *rk_zacc = nullptr;
+    // one captured RK4 step, replayed per step (key: the arguments it was captured for)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t rk_exec = nullptr;
+    i64 rk_n = -1;
+    const void *rk_px = nullptr, *rk_pz = nullptr, *rk_pa = nullptr;
+    double rk_dt = 0.0, rk_om = 0.0;
     // phase timing: 7 events per recorded evaluation
     std::vector<hipEvent_t> tev;
     int t_max = 0, t_used = 0, t_phase = -1;
@@ -59,6 +65,8 @@ struct stc_ctx {
     std::vector<void*> allocs;
     std::string err;
 };
+
+static void rk4_drop_graph(stc_ctx* c);
 
 namespace {
 
@@ -158,6 +166,7 @@ stc_status validate_params(const stc_params* p, i64 n_max) {
     if (p->denominator != STC_DEN_DOT && p->denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
     if (p->precision == STC_FP32 && p->denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
     if (p->list_capacity < 0 || p->list_capacity > 0x7fffffffLL) return STC_ERR_INVALID_ARG;
+    if (p->flags & ~STC_FLAG_EAGER_RK4) return STC_ERR_INVALID_ARG;
     if (n_max < 0 || n_max >= 0x7fffffffLL) return STC_ERR_INVALID_ARG;
     return STC_OK;
 }
@@ -404,6 +413,8 @@ stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_
 stc_status stc_destroy(stc_ctx* c) {
     if (!c) return STC_ERR_INVALID_ARG;
     (void)hipStreamSynchronize(c->stream);
+    rk4_drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
@@ -487,6 +498,71 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
     return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
 }
 
+// Enqueues one RK4 step on c->stream (no host synchronisation, no memsets).
+static stc_status rk4_enqueue_step(stc_ctx* c, i64 n, double* d_x, double* d_zeta, const double* d_area, double dt,
+                                   double omega) {
+    hipStream_t s = c->stream;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    // stage nodes 0, 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6
+    const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
+    const double wacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    const double* xs = d_x;
+    const double* zs = d_zeta;
+    for (int stg = 0; stg < 4; ++stg) {
+        stc_status st = stc_velocity(c, n, xs, zs, d_area, c->rk_u);
+        if (st != STC_OK) return st;
+        hipLaunchKernelGGL(k_rk4_combine, g, b, 0, s, (i64)n, d_x, d_zeta, c->rk_u, omega, cnext[stg], wacc[stg],
+                           c->rk_x, c->rk_z, c->rk_xacc, c->rk_zacc, stg == 0 ? 1 : 0);
+        xs = c->rk_x;
+        zs = c->rk_z;
+    }
+    hipLaunchKernelGGL(k_rk4_finish, g, b, 0, s, (i64)n, c->rk_xacc, c->rk_zacc, d_x, d_zeta);
+    return check_launch(c, "rk4");
+}
+
+static void rk4_drop_graph(stc_ctx* c) {
+    if (c->rk_exec) (void)hipGraphExecDestroy(c->rk_exec);
+    c->rk_exec = nullptr;
+    c->rk_n = -1;
+}
+
+// Captures one RK4 step into a graph (on the context's capture stream).
+static stc_status rk4_capture(stc_ctx* c, i64 n, double* d_x, double* d_zeta, const double* d_area, double dt,
+                              double omega) {
+    rk4_drop_graph(c);
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "creating the capture stream failed");
+    // the capture must not record timing events
+    const int tmax = c->t_max;
+    c->t_max = 0;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    stc_status st = STC_OK;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = fail(c, STC_ERR_DEVICE, "hipStreamBeginCapture failed");
+    } else {
+        st = rk4_enqueue_step(c, n, d_x, d_zeta, d_area, dt, omega);
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        if (st == STC_OK && e != hipSuccess) st = fail(c, STC_ERR_DEVICE, "hipStreamEndCapture failed");
+    }
+    c->stream = user;
+    c->t_max = tmax;
+    if (st == STC_OK && hipGraphInstantiate(&c->rk_exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        c->rk_exec = nullptr;
+        st = fail(c, STC_ERR_DEVICE, "hipGraphInstantiate failed");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != STC_OK) return st;
+    c->rk_n = n;
+    c->rk_px = d_x;
+    c->rk_pz = d_zeta;
+    c->rk_pa = d_area;
+    c->rk_dt = dt;
+    c->rk_om = omega;
+    return STC_OK;
+}
+
 stc_status stc_rk4(stc_ctx* c, int64_t n, double* d_x, double* d_zeta, const double* d_area, double dt, double omega,
                    int32_t n_steps) {
     if (!c) return STC_ERR_INVALID_ARG;
@@ -495,25 +571,25 @@ stc_status stc_rk4(stc_ctx* c, int64_t n, double* d_x, double* d_zeta, const dou
     if (n == 0 || n_steps == 0) return STC_OK;
     if (!d_x || !d_zeta || !d_area || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area))
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
-    hipStream_t s = c->stream;
-    const dim3 g((unsigned)((n + 255) / 256)), b(256);
-    // stage nodes 0, 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6
-    const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
-    const double wacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
-    for (int step = 0; step < n_steps; ++step) {
-        const double* xs = d_x;
-        const double* zs = d_zeta;
-        for (int stg = 0; stg < 4; ++stg) {
-            stc_status st = stc_velocity(c, n, xs, zs, d_area, c->rk_u);
+    // RK4 stage points leave the sphere (|x_s| - 1 ~ (dt |u|)^2 / 8); 1 - x.y can
+    // then vanish or turn negative for close pairs, |x - y|^2 / 2 cannot
+    if (c->p.denominator != STC_DEN_DIST2)
+        return fail(c, STC_ERR_INVALID_ARG, "stc_rk4 needs the |x-y|^2/2 denominator (stage points are off the sphere)");
+    const bool use_graph = (c->p.flags & STC_FLAG_EAGER_RK4) == 0;
+    if (!use_graph) {
+        for (int step = 0; step < n_steps; ++step) {
+            stc_status st = rk4_enqueue_step(c, n, d_x, d_zeta, d_area, dt, omega);
             if (st != STC_OK) return st;
-            hipLaunchKernelGGL(k_rk4_combine, g, b, 0, s, (i64)n, d_x, d_zeta, c->rk_u, omega, cnext[stg], wacc[stg],
-                               c->rk_x, c->rk_z, c->rk_xacc, c->rk_zacc, stg == 0 ? 1 : 0);
-            xs = c->rk_x;
-            zs = c->rk_z;
         }
-        hipLaunchKernelGGL(k_rk4_finish, g, b, 0, s, (i64)n, c->rk_xacc, c->rk_zacc, d_x, d_zeta);
-        stc_status st = check_launch(c, "rk4");
-        if (st != STC_OK) return st;
+    } else {
+        if (!(c->rk_exec && c->rk_n == n && c->rk_px == d_x && c->rk_pz == d_zeta && c->rk_pa == d_area &&
+              c->rk_dt == dt && c->rk_om == omega)) {
+            stc_status st = rk4_capture(c, n, d_x, d_zeta, d_area, dt, omega);
+            if (st != STC_OK) return st;
+        }
+        for (int step = 0; step < n_steps; ++step)
+            if (hipGraphLaunch(c->rk_exec, c->stream) != hipSuccess)
+                return fail(c, STC_ERR_DEVICE, "hipGraphLaunch failed");
     }
     c->have_tree = c->have_upward = c->have_lists = false;  // stage data, not the final state
     return STC_OK;

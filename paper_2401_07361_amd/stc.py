@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libstc.so")
 FP64, FP32 = 0, 1
 DEN_DOT, DEN_DIST2 = 0, 1
 PP, PC, CP, CC = 0, 1, 2, 3
+FLAG_EAGER_RK4 = 1
 LIST_NAMES = ("PP", "PC", "CP", "CC")
 
 
@@ -29,7 +30,7 @@ class StcError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("degree", ctypes.c_int32), ("n_crit", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("precision", ctypes.c_int32), ("denominator", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
+                ("flags", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
 
 
 def _load():
@@ -186,10 +187,11 @@ class Context:
     """A tree-code context for up to n_max particles (stc_create)."""
 
     def __init__(self, n_max, theta=0.7, degree=8, n_crit=64, max_level=-1, precision="fp64",
-                 denominator="dot", list_capacity=0, stream=None):
+                 denominator="dot", list_capacity=0, stream=None, eager_rk4=False):
         p = Params()
         _lib.stc_default_params(ctypes.byref(p))
         p.theta, p.degree, p.n_crit, p.max_level = theta, degree, n_crit, max_level
+        p.flags = FLAG_EAGER_RK4 if eager_rk4 else 0
         p.precision, p.denominator, p.list_capacity = _prec(precision), _den(denominator), list_capacity
         self._ctx = ctypes.c_void_p()
         self._stream_obj = stream

@@ -274,10 +274,10 @@ def test_rk4_matches_oracle(stc_lib):
     a = S.uniform_areas(len(x0))
     th, d, nc = 0.7, 6, 32
     Om = S.OMEGA_EARTH_S
-    vel = lambda xx, zz, aa: otree.velocity(xx, zz, aa, theta=th, degree=d, n_crit=nc, max_level=4)
+    vel = lambda xx, zz, aa: otree.velocity(xx, zz, aa, theta=th, degree=d, n_crit=nc, max_level=4, den="dist2")
     say("rk4 2 steps N=2562")
     xr, zr = ork4.integrate(x0, z0, a, 1800.0, Om, 2, vel)
-    ctx = stc_lib.Context(len(x0), theta=th, degree=d, n_crit=nc, max_level=4)
+    ctx = stc_lib.Context(len(x0), theta=th, degree=d, n_crit=nc, max_level=4, denominator="dist2")
     xg, zg = dev(x0), dev(z0)
     ctx.rk4(xg, zg, dev(a), 1800.0, Om, 2)
     ctx.sync()
