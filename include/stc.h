@@ -52,6 +52,7 @@ enum { STC_FP64 = 0, STC_FP32 = 1 };           /* arithmetic of the PP/PC/CP/CC 
 enum { STC_DEN_DOT = 0, STC_DEN_DIST2 = 1 };   /* 1 - x.y (Sec. 2) | |x-y|^2/2 (Sec. 2, alt. kernel) */
 enum { STC_LIST_PP = 0, STC_LIST_PC = 1, STC_LIST_CP = 2, STC_LIST_CC = 3 };
 enum { STC_FLAG_EAGER_RK4 = 1 };              /* stc_rk4 without graph capture */
+enum { STC_MAX_MEMBERS = 64 };                /* members of one batched context */
 
 /* Method parameters (Sec. 3, dual tree traversal).
  *  theta       MAC: a pair is well separated iff (r_t + r_s) / R < theta,
@@ -82,6 +83,20 @@ typedef struct stc_params {
 
 typedef struct stc_ctx stc_ctx;
 
+/* Launch shape of the two persistent interaction kernels (near side: PP and
+ * PC; target proxies: CP and CC): workgroup size (128, 256 or 512 threads;
+ * one LDS source tile and one batch of list entries per workgroup hold that
+ * many items) and workgroups per compute unit (1..64; the grid is rounded up
+ * to a multiple of 8, one slot per XCD).  Default {256, 12, 256, 12}.  The
+ * shape changes only the grouping of the FP32/FP64 partial sums, not what is
+ * summed. */
+typedef struct stc_launch_config {
+    int32_t near_threads;
+    int32_t near_blocks_per_cu;
+    int32_t far_threads;
+    int32_t far_blocks_per_cu;
+} stc_launch_config;
+
 /* Message for a status code (static string). */
 const char* stc_status_string(int32_t status);
 
@@ -105,6 +120,27 @@ int32_t stc_default_max_level(int64_t n_max, int32_t n_crit);
  * a hipStream_t (NULL = default stream).  On success *out owns the context. */
 stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_ctx** out);
 
+/* Ensembles (batching): a context for up to max_members independent particle
+ * sets ("members") evaluated together, one kernel launch per phase for all of
+ * them.  The members' particles are concatenated in one array: member m owns
+ * rows [h_offsets[m], h_offsets[m+1]) of x, zeta, area and u, with
+ * h_offsets a HOST array of members + 1 int64, h_offsets[0] = 0,
+ * non-decreasing, h_offsets[members] <= n_max_total.  Members never interact:
+ * every member gets its own tree (Sec. 3) and its own lists, and its result is
+ * bitwise the one a single-member context with the same parameters gives.
+ * max_level = -1 resolves with n_max_member (the largest member expected).
+ * Node ids of member m are (m << node_bits) + local id (stc_node_layout).
+ * 1 <= max_members <= STC_MAX_MEMBERS; 2 max_level + 5 + bits(max_members)
+ * <= 32.  stc_create(p, n, s, out) is stc_create_batched(p, 1, n, n, s, out). */
+stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t n_max_member,
+                              int64_t n_max_total, void* hip_stream, stc_ctx** out);
+
+/* Node id layout: node id = (member << *node_bits) + local id, local ids
+ * 0 .. *nodes_per_member - 1 as stc_total_nodes describes; per-node arrays
+ * (stc_copy_tree) have *node_array_len entries.  Any pointer may be NULL. */
+stc_status stc_node_layout(const stc_ctx* ctx, int32_t* node_bits, int64_t* nodes_per_member,
+                           int64_t* node_array_len);
+
 /* Frees the context and its device buffers (synchronises its stream). */
 stc_status stc_destroy(stc_ctx* ctx);
 
@@ -123,6 +159,11 @@ stc_status stc_get_params(const stc_ctx* ctx, stc_params* out);
  * finds every node's particle range.  0 <= n <= n_max.  d_x must stay valid
  * and unchanged until the evaluation calls that follow have completed. */
 stc_status stc_tree_build(stc_ctx* ctx, int64_t n, const double* d_x);
+
+/* Tree build of an ensemble (see stc_create_batched); the pipeline calls
+ * below then work on all its members. */
+stc_status stc_tree_build_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offsets,
+                                  const double* d_x);
 
 /* Upward pass: charges q_j = zeta_j A_j and, for every node with more than
  * n_crit particles, the proxy charges w_m = sum_j L_m(y_j) q_j (Sec. 3,
@@ -146,6 +187,12 @@ stc_status stc_eval_far(stc_ctx* ctx, double* d_u, int32_t accumulate);
  * far field, written to d_u (n,3) in input order. */
 stc_status stc_velocity(stc_ctx* ctx, int64_t n, const double* d_x, const double* d_zeta,
                         const double* d_area, double* d_u);
+
+/* One velocity evaluation of every member of an ensemble, all members in the
+ * same launches (tree build, upward pass, traversal, near and far field). */
+stc_status stc_velocity_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offsets,
+                                const double* d_x, const double* d_zeta, const double* d_area,
+                                double* d_u);
 
 /* Direct O(N^2) sum (Sec. 2, discrete system) for m targets: d_targets (m,)
  * int64 indices into [0, n), or NULL for all (then m must equal n).  Sources
@@ -171,6 +218,32 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
 stc_status stc_rk4(stc_ctx* ctx, int64_t n, double* d_x, double* d_zeta, const double* d_area,
                    double dt, double omega, int32_t n_steps);
 
+/* RK4 of every member of an ensemble (same dt and omega), each stage one
+ * stc_velocity_batched; graph-captured like stc_rk4 (re-captured when the
+ * offsets change). */
+stc_status stc_rk4_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offsets, double* d_x,
+                           double* d_zeta, const double* d_area, double dt, double omega,
+                           int32_t n_steps);
+
+/* --- launch shapes ------------------------------------------------------------ */
+
+/* The shape used for a total particle count n_total (size classes are
+ * powers of two: the shape applies to every n with the same bit length). */
+stc_status stc_get_launch_config(const stc_ctx* ctx, int64_t n_total, stc_launch_config* out);
+
+/* Sets the shape for n_total's size class, or, with n_total < 0, the default
+ * for classes without one. */
+stc_status stc_set_launch_config(stc_ctx* ctx, int64_t n_total, const stc_launch_config* cfg);
+
+/* Times every candidate shape (workgroup sizes 128/256/512 x 4, 8, 12, 16 or
+ * 24 workgroups per CU, for each of the two kernels) on the lists of the last
+ * traversal, `repeats` launches each after one warm-up, keeps the fastest
+ * for the current size class (the precision and degree are the context's)
+ * and writes it to *out.  Needs stc_upward and stc_traverse (or a velocity
+ * evaluation) first; synchronises.  The evaluation's output is not touched,
+ * internal accumulators are: evaluate again afterwards. */
+stc_status stc_autotune(stc_ctx* ctx, int32_t repeats, stc_launch_config* out);
+
 /* --- introspection (these synchronise the context stream) ------------------ */
 
 /* Waits for queued work; reports device-side error flags. */
@@ -190,8 +263,10 @@ stc_status stc_copy_list(stc_ctx* ctx, int32_t type, int64_t cap, int64_t* h_pai
                          int64_t* n_out);
 
 /* Copies the tree: h_perm (n) = input index of the i-th particle in tree
- * order; h_count (node_cap) = particle count of each node id.  Either may be
- * NULL.  node_cap must be >= stc_total_nodes(max_level) if h_count != NULL. */
+ * order (indices into the concatenated arrays for an ensemble); h_count
+ * (node_cap) = particle count of each node id.  Either may be NULL.
+ * node_cap must be >= the node array length (stc_node_layout; for a single
+ * member stc_total_nodes(max_level)) if h_count != NULL. */
 stc_status stc_copy_tree(stc_ctx* ctx, int64_t n, int32_t* h_perm, int64_t node_cap,
                          int32_t* h_count);
 
@@ -200,7 +275,8 @@ stc_status stc_copy_tree(stc_ctx* ctx, int64_t n, int32_t* h_perm, int64_t node_
 stc_status stc_copy_proxy_charges(stc_ctx* ctx, int64_t node_id, double* h_w);
 
 /* Host-only geometry introspection (no device work): vertices (9), the
- * circumcentre (3) and radius (1) of a node, as used by the traversal. */
+ * circumcentre (3) and radius (1) of a node (of any member: the local part of
+ * the id is used), as used by the traversal. */
 stc_status stc_node_geometry(const stc_ctx* ctx, int64_t node_id, double* h_v9, double* h_c3,
                              double* h_r);
 

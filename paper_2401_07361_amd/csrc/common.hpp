@@ -18,6 +18,27 @@ constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
 constexpr int kMaxDegree = 14;
 constexpr int kMaxNp = (kMaxDegree + 1) * (kMaxDegree + 2) / 2;  // 120
 
+// Ensembles (batched evaluation): up to kMaxMembers independent particle
+// sets share one launch per phase.  Node ids carry the member above the local
+// id, id = (member << NB) | local, with local = 20 (4^l - 1)/3 + key as for a
+// single tree and NB = bits of the local node count; particle leaf keys carry
+// it the same way above their 2 L + 5 bits.  Geometry is indexed by local id.
+constexpr int kMaxMembers = 64;
+
+// member m owns particles [off[m], off[m+1]) of the concatenated arrays
+struct MemberOffsets {
+    i64 off[kMaxMembers + 1];
+    int m;
+};
+
+// flag slots in the context's u32 flag array
+enum Flag : int {
+    F_NONFINITE = 0,  // a particle position lies in no root face
+    F_SLOTS = 1,      // more nodes with proxy charges than storage slots
+    F_SLOT_CTR = 2,   // next free storage slot (counter)
+    F_COUNT = 8
+};
+
 // counter slots in the context's u32 counter array
 enum Counter : int {
     C_TLIST = 0,      // entries in the target-particle list (PP + PC)

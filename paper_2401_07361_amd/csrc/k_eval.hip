@@ -15,13 +15,14 @@
 //                    i that received CP/CC work; then the cross product and
 //                    the scatter back to input order.
 //
-// Segment kernels run 256 threads per workgroup.  A persistent grid splits
+// Segment kernels run NTT threads per workgroup (256 by default; 128 or 512
+// when the launch autotuner picks them).  A persistent grid splits
 // the target-sorted list into equal contiguous ranges of entries; a
 // workgroup handles every target whose run of entries starts inside its
 // range.  The block -> range map is XCD aware (consecutive ranges, i.e.
 // neighbouring triangles that share sources, run on the same XCD and its
-// L2).  Sources are staged into 256-entry LDS tiles, one source per thread;
-// threads split as (target, source slice) with 256 / n_targets slices.
+// L2).  Sources are staged into NTT-entry LDS tiles, one source per thread;
+// threads split as (target, source slice) with NTT / n_targets slices.
 // FP32 mode: coordinates relative to the target triangle's circumcentre,
 // rounded from FP64; partial sums per tile in FP32, added into FP64.
 #include "common.hpp"
@@ -31,8 +32,6 @@
 namespace stc {
 
 namespace {
-
-constexpr int TILE = 256;
 
 template <typename T>
 struct Src {
@@ -92,15 +91,14 @@ __device__ __forceinline__ u32 logical_block() {
     return (b % 8u) * (G / 8u) + (b / 8u);
 }
 
-constexpr int NT = 256;   // threads per workgroup of the segment kernels
-constexpr int EB = 256;   // list entries per batch
-
+// LDS of a segment kernel with NTT threads: one NTT-source tile, one batch of
+// NTT list entries
 template <typename T, int NTT>
 struct SegShared {
-    Src<T> tile[TILE];
-    u32 ent_s[EB];         // source node of each entry of the batch
-    i32 ent_first[EB];     // first particle of a particle source, -1 for proxy points
-    u32 ent_pre[EB + 1];   // exclusive prefix of the entries' source counts
+    Src<T> tile[NTT];
+    u32 ent_s[NTT];        // source node of a particle entry, storage slot of a proxy entry
+    i32 ent_first[NTT];    // first particle of a particle source, -1 for proxy points
+    u32 ent_pre[NTT + 1];  // exclusive prefix of the entries' source counts
     u32 wave_tot[NTT / 64];
     int self_flag;
     double red[3][NTT];
@@ -127,7 +125,8 @@ __device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* wave_tot, u32* t
     return base + incl - v;
 }
 
-// One source point relative to (cx, cy, cz), charge scaled by qscale.
+// One source point relative to (cx, cy, cz), charge scaled by qscale: point l
+// of particle range `first`, or (first < 0) proxy point l of storage slot s.
 template <typename T>
 __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 first, int l, double cx, double cy,
                                               double cz, double qscale) {
@@ -150,8 +149,8 @@ __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 firs
 
 // Accumulates, for this thread's target (tx, ty, tz), every entry of [e0, e1)
 // in `list` whose type bit is in type_mask.  Entries are taken in batches of
-// EB: their source counts are scanned into an LDS prefix, so that for each
-// 256-source tile every thread stages exactly one source (its entry found by
+// NTT: their source counts are scanned into an LDS prefix, so that for each
+// NTT-source tile every thread stages exactly one source (its entry found by
 // binary search) and all global loads of a tile are in flight together.  A
 // PP entry whose source is the target leaf itself (self_t) is evaluated on
 // its own with the j != i exclusion (me: the thread's target index there).
@@ -162,8 +161,8 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
     const int tid = threadIdx.x;
     const u64 mask = ((u64)1 << a.W) - 1;
     const double qscale = (DEN == STC_DEN_DIST2) ? 2.0 : 1.0;
-    for (u32 eb = e0; eb < e1; eb += EB) {
-        const u32 ne = (e1 - eb) < (u32)EB ? (e1 - eb) : (u32)EB;
+    for (u32 eb = e0; eb < e1; eb += NTT) {
+        const u32 ne = (e1 - eb) < (u32)NTT ? (e1 - eb) : (u32)NTT;
         if (tid == 0) sh.self_flag = 0;
         __syncthreads();
         u32 size = 0;
@@ -179,6 +178,7 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                     if (s == self_t) sh.self_flag = 1;
                     else size = (u32)(a.nend[s] - b);
                 } else {
+                    sh.ent_s[tid] = (u32)a.slot[s];
                     sh.ent_first[tid] = -1;
                     size = (u32)a.ref.np;
                 }
@@ -194,16 +194,16 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
         if (sh.self_flag) {
             const i32 tb = a.nbeg[self_t];
             const int nsrc = a.nend[self_t] - tb;
-            for (int j0 = 0; j0 < nsrc; j0 += TILE) {
-                const int cnt = (nsrc - j0) < TILE ? (nsrc - j0) : TILE;
+            for (int j0 = 0; j0 < nsrc; j0 += NTT) {
+                const int cnt = (nsrc - j0) < NTT ? (nsrc - j0) : NTT;
                 if (tid < cnt) sh.tile[tid] = load_source<T>(a, self_t, tb, j0 + tid, cx, cy, cz, qscale);
                 __syncthreads();
                 if (act) tile_sum<T, DEN, true>(sh.tile, cnt, sl, S, tx, ty, tz, me - j0, ax, ay, az);
                 __syncthreads();
             }
         }
-        for (u32 g0 = 0; g0 < total; g0 += TILE) {
-            const int cnt = (total - g0) < (u32)TILE ? (int)(total - g0) : TILE;
+        for (u32 g0 = 0; g0 < total; g0 += NTT) {
+            const int cnt = (total - g0) < (u32)NTT ? (int)(total - g0) : NTT;
             if (tid < cnt) {
                 const u32 g = g0 + tid;
                 u32 lo = 0, hi = ne;
@@ -235,7 +235,7 @@ __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_
     return true;
 }
 
-template <typename T, int DEN>
+template <typename T, int DEN, int NT>
 __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
     __shared__ SegShared<T, NT> sh;
     const int tid = threadIdx.x;
@@ -250,7 +250,8 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
         const u32 se = (u32)a.tseg_end[t];
         const i32 tb = a.nbeg[t];
         const int nt = a.nend[t] - tb;
-        const double cx = rel ? a.geo[t].c[0] : 0.0, cy = rel ? a.geo[t].c[1] : 0.0, cz = rel ? a.geo[t].c[2] : 0.0;
+        const NodeGeo& gt = a.geo[t & a.node_mask];
+        const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
         for (int cb = 0; cb < nt; cb += NT) {
             const int ntc = (nt - cb) < NT ? (nt - cb) : NT;
             const int S = NT / ntc;
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
     while (e < e_hi) {
         const u32 t = (u32)(a.nlist[e] >> shf);
         const u32 se = (u32)a.nseg_end[t];
-        const NodeGeo& gt = a.geo[t];
+        const NodeGeo& gt = a.geo[t & a.node_mask];
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
         // target points in chunks of at most NTT/4, so that full chunks keep
         // every thread busy with 4 source slices
@@ -336,7 +337,8 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
         }
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
         block_matvec<NTT, 3>(a.ref.vinvT, np, nd, wt, &sh.red[0][0], co);
-        for (int k = tid; k < 3 * np; k += NTT) a.alpha[(size_t)t * np * 3 + k] = co[k / 3][k % 3];
+        const size_t ts = (size_t)a.slot[t];
+        for (int k = tid; k < 3 * np; k += NTT) a.alpha[ts * np * 3 + k] = co[k / 3][k % 3];
         __syncthreads();
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
     }
@@ -356,6 +358,7 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
     constexpr int NP = (D + 1) * (D + 2) / 2;
     __shared__ double al[KS][NP][3];
     __shared__ i64 slot_node[256];
+    __shared__ i32 slot_store[256];
     __shared__ u32 wtot[4];
     const int tid = threadIdx.x;
     const i64 i0 = (i64)blockIdx.x * blockDim.x + tid;
@@ -366,8 +369,11 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
     if (do_far) {
         const u32 leaf = a.leaf[i];
         const int L = a.L;
+        const i64 mbase = (i64)(leaf >> a.LB) << a.NB;
+        const u32 kl = leaf & ((1u << a.LB) - 1u);
         for (int lvl = 0; lvl <= L; ++lvl) {
-            const i64 nd = a.level_off_tab[lvl] + (i64)(leaf >> (2 * (L - lvl)));
+            const i64 ndl = a.level_off_tab[lvl] + (i64)(kl >> (2 * (L - lvl)));  // local id
+            const i64 nd = mbase + ndl;
             const bool has = valid && a.nseg_end[nd] != 0;
             // the first particle of each node with far work opens a slot
             slot_node[tid] = has ? nd : (i64)-1;
@@ -377,18 +383,21 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
             const u32 before = block_exclusive_scan<256>(first ? 1u : 0u, wtot, &nslots);
             const int my_slot = has ? (int)(before + (first ? 1u : 0u)) - 1 : -1;
             __syncthreads();
-            if (first) slot_node[my_slot] = nd;
+            if (first) {
+                slot_node[my_slot] = nd;
+                slot_store[my_slot] = a.slot[nd];
+            }
             __syncthreads();
             for (u32 s0 = 0; s0 < nslots; s0 += KS) {
                 const int ns = (nslots - s0) < (u32)KS ? (int)(nslots - s0) : KS;
                 for (int k = tid; k < ns * NP * 3; k += 256) {
                     const int sl = k / (NP * 3), r = k % (NP * 3);
-                    al[sl][r / 3][r % 3] = a.alpha[(size_t)slot_node[s0 + sl] * NP * 3 + r];
+                    al[sl][r / 3][r % 3] = a.alpha[(size_t)slot_store[s0 + sl] * NP * 3 + r];
                 }
                 __syncthreads();
                 const int ms = my_slot - (int)s0;
                 if (ms >= 0 && ms < ns) {
-                    const NodeGeo& g = a.geo[nd];
+                    const NodeGeo& g = a.geo[ndl];
                     double P[3][D + 1];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -485,19 +494,37 @@ __global__ __launch_bounds__(256) void k_direct(i64 n, const double* __restrict_
 
 }  // namespace
 
+namespace {
+template <int NTT>
+void near_shape(hipStream_t s, const EvalArgs& a, u32 type_mask) {
+    const dim3 g(a.near_grid), b(NTT);
+    if (a.precision == STC_FP32) hipLaunchKernelGGL((k_near<float, STC_DEN_DIST2, NTT>), g, b, 0, s, a, type_mask);
+    else if (a.denominator == STC_DEN_DIST2)
+        hipLaunchKernelGGL((k_near<double, STC_DEN_DIST2, NTT>), g, b, 0, s, a, type_mask);
+    else hipLaunchKernelGGL((k_near<double, STC_DEN_DOT, NTT>), g, b, 0, s, a, type_mask);
+}
+
+template <int NTT>
+void far_shape(hipStream_t s, const EvalArgs& a) {
+    const dim3 g(a.far_grid), b(NTT);
+    if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NTT>), g, b, 0, s, a);
+    else if (a.denominator == STC_DEN_DIST2)
+        hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2, NTT>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DOT, NTT>), g, b, 0, s, a);
+}
+}  // namespace
+
+// workgroup sizes 128, 256 and 512 are built; the caller validates the shape
 void launch_near(hipStream_t s, const EvalArgs& a, u32 type_mask) {
-    const dim3 g(a.grid), b(NT);
-    if (a.precision == STC_FP32) hipLaunchKernelGGL((k_near<float, STC_DEN_DIST2>), g, b, 0, s, a, type_mask);
-    else if (a.denominator == STC_DEN_DIST2) hipLaunchKernelGGL((k_near<double, STC_DEN_DIST2>), g, b, 0, s, a, type_mask);
-    else hipLaunchKernelGGL((k_near<double, STC_DEN_DOT>), g, b, 0, s, a, type_mask);
+    if (a.near_threads == 512) near_shape<512>(s, a, type_mask);
+    else if (a.near_threads == 128) near_shape<128>(s, a, type_mask);
+    else near_shape<256>(s, a, type_mask);
 }
 
 void launch_far_targets(hipStream_t s, const EvalArgs& a) {
-    const dim3 g(a.grid), b(NT);
-    if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NT>), g, b, 0, s, a);
-    else if (a.denominator == STC_DEN_DIST2)
-        hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2, NT>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DOT, NT>), g, b, 0, s, a);
+    if (a.far_threads == 512) far_shape<512>(s, a);
+    else if (a.far_threads == 128) far_shape<128>(s, a);
+    else far_shape<256>(s, a);
 }
 
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate) {

@@ -1,4 +1,6 @@
 // Tree build, upward pass and dual tree traversal kernels.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -10,10 +12,12 @@ namespace stc {
 // centre child's vertices (m12, m23, m31) are read from the next level; the
 // point goes to corner 1, 2 or 3 if it lies strictly outside the centre child
 // across the edge facing that corner (tested in that order), otherwise to
-// the centre child.  All orientations are exact.
+// the centre child.  All orientations are exact.  The sort key is
+// (member, leaf key, index): the member of particle i is the last m with
+// off[m] <= i (a fixed-index scan, so the offsets stay in kernel arguments).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n,
-                                              const NodeGeo* __restrict__ geo, int L,
+                                              const NodeGeo* __restrict__ geo, int L, MemberOffsets mo,
                                               u64* __restrict__ keys, u32* __restrict__ flags) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -42,7 +46,7 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n
             face = f;
     }
     if (face < 0) {  // non-finite input: no face contains it
-        atomicOr(&flags[0], 1u);
+        atomicOr(&flags[F_NONFINITE], 1u);
         face = 0;
     }
     u32 key = (u32)face;
@@ -57,6 +61,13 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n
         key = 4 * key + digit;
         off = 4 * off + 20;  // level_offset(lvl + 2)
     }
+    u32 member = 0;
+    if (mo.m > 1) {
+#pragma unroll
+        for (int k = 1; k < kMaxMembers; ++k)
+            if (k < mo.m && mo.off[k] <= i) member = (u32)k;
+    }
+    key |= member << (2 * L + 5);
     keys[i] = ((u64)key << 32) | (u64)i;
 }
 
@@ -77,20 +88,25 @@ __global__ __launch_bounds__(256) void k_gather(const u64* __restrict__ keys, i6
 }
 
 // Particle range [begin, end) of every node that holds particles, from the
-// boundaries of the sorted leaf keys at each level.  Arrays must be zeroed.
-__global__ __launch_bounds__(256) void k_node_ranges(const u32* __restrict__ leaf, i64 n, int L,
+// boundaries of the sorted leaf keys at each level (the member bits above the
+// key take part in the comparison).  Arrays must be zeroed.
+__global__ __launch_bounds__(256) void k_node_ranges(const u32* __restrict__ leaf, i64 n, int L, int NB,
                                                       i32* __restrict__ nbeg, i32* __restrict__ nend) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int LB = 2 * L + 5;
     const u32 k = leaf[i];
     const u32 kp = i > 0 ? leaf[i - 1] : 0u;
     const u32 kn = i + 1 < n ? leaf[i + 1] : 0u;
+    const i64 base = (i64)(k >> LB) << NB;
+    const u32 kl = k & ((1u << LB) - 1u);
     i64 off = 0;
     for (int lvl = 0; lvl <= L; ++lvl) {
         const int sh = 2 * (L - lvl);
         const u32 pf = k >> sh;
-        if (i == 0 || (kp >> sh) != pf) nbeg[off + pf] = (i32)i;
-        if (i == n - 1 || (kn >> sh) != pf) nend[off + pf] = (i32)(i + 1);
+        const i64 node = base + off + (kl >> sh);
+        if (i == 0 || (kp >> sh) != pf) nbeg[node] = (i32)i;
+        if (i == n - 1 || (kn >> sh) != pf) nend[node] = (i32)(i + 1);
         off = 4 * off + 20;
     }
 }
@@ -117,17 +133,18 @@ __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i
 // (homogeneous polynomials of degree d restricted to the sphere), so
 // re-interpolating a child's proxy charges at the parent reproduces the
 // parent's proxy charges computed from the particles, up to rounding.
-// Levels are processed bottom-up, one launch per level, one workgroup per
-// node; sources go through LDS in chunks of 64 (barycentric powers), thread
-// t accumulating basis function t % np over every (256/np)-th source.
+// Levels are processed bottom-up, one launch per level (grid.y = member), one
+// workgroup per node; sources go through LDS in chunks of 64 (barycentric
+// powers), thread t accumulating basis function t % np over every
+// (256/np)-th source.  Proxy records live in the node's storage slot.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int chunk, int lvl, int L,
+__global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int chunk, int lvl, int L, int NB,
                                                        i64 child_off, const i32* __restrict__ nbeg,
                                                        const i32* __restrict__ nend, int n_crit,
                                                        const NodeGeo* __restrict__ geo, const double* __restrict__ sx,
                                                        const double* __restrict__ sy, const double* __restrict__ sz,
                                                        const double* __restrict__ q, RefDev ref,
-                                                       Prox* __restrict__ prox) {
+                                                       const i32* __restrict__ slot, Prox* __restrict__ prox) {
     __shared__ double pw[64][3][kMaxDegree + 1];
     __shared__ double qs[64];
     __shared__ double red[256];
@@ -145,21 +162,22 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
         e1 = ref.expo[3 * k + 1];
         e2 = ref.expo[3 * k + 2];
     }
+    const i64 mbase = (i64)blockIdx.y << NB;
     for (i64 base = (i64)blockIdx.x * chunk; base < nnodes; base += (i64)gridDim.x * chunk) {
         // the nodes of this chunk with more than N_T particles, found in parallel
         if (tid == 0) nbig = 0;
         __syncthreads();
         if (tid < chunk && base + tid < nnodes) {
-            const i64 nd = node0 + base + tid;
+            const i64 nd = mbase + node0 + base + tid;
             if (nend[nd] - nbeg[nd] > n_crit) big[atomicAdd(&nbig, 1)] = (i32)(base + tid);
         }
         __syncthreads();
         const int nb = nbig;
         for (int bi = 0; bi < nb; ++bi) {
             const i64 t = big[bi];
-            const i64 node = node0 + t;
+            const i64 node = mbase + node0 + t;
             const i32 b = nbeg[node], e = nend[node];
-            const NodeGeo& g = geo[node];
+            const NodeGeo& g = geo[node0 + t];
             // source segments: kind 0 = particle range [first, first+cnt), 1 = points of node `id`
             int seg_kind[4], seg_cnt[4];
             i64 seg_id[4];
@@ -171,7 +189,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                 nseg = 1;
             } else {
                 for (int c = 0; c < 4; ++c) {
-                    const i64 cid = child_off + 4 * t + c;
+                    const i64 cid = mbase + child_off + 4 * t + c;
                     const i32 cb = nbeg[cid], cn = nend[cid] - cb;
                     if (cn <= 0) continue;
                     if (cn > n_crit) {
@@ -205,7 +223,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                         y2 = sz[j];
                         qq = q[j];
                     } else {
-                        const Prox pr = prox[(size_t)seg_id[sgi] * np + idx];
+                        const Prox pr = prox[(size_t)slot[seg_id[sgi]] * np + idx];
                         y0 = pr.x;
                         y1 = pr.y;
                         y2 = pr.z;
@@ -237,6 +255,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
             __syncthreads();
             // w_m = |.|^d sum_k (V_ref^{-1})_{km} omega_k  (row m of V_ref^{-T})
             block_matvec<256, 1>(ref.vinv, np, nullptr, omega, red, wout);
+            const size_t my_slot = (size_t)slot[node];
             for (int m = tid; m < np; m += 256) {
                 double y[3];
                 const double nrm = proxy_point(g, ref.points + 3 * m, y);
@@ -245,7 +264,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                 pr.y = y[1];
                 pr.z = y[2];
                 pr.w = ipow(nrm, d) * wout[m][0];
-                prox[(size_t)node * np + m] = pr;
+                prox[my_slot * np + m] = pr;
             }
             __syncthreads();
         }
@@ -264,13 +283,16 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
 // Target-particle entries (PP, PC) and target-proxy entries (CP, CC) go to
 // two lists as sort keys (t << (W+1)) | (type << W) | s.
 // ---------------------------------------------------------------------------
-__global__ void k_trav_init(const i32* __restrict__ ncnt, u64* __restrict__ front, u32 cap,
-                            u32* __restrict__ counters) {
-    const int i = threadIdx.x;  // 512 threads, 400 used
-    const bool ok = i < 400 && ncnt[i / 20] > 0 && ncnt[i % 20] > 0;
+// the 400 root pairs of every member (never pairs of two members)
+__global__ __launch_bounds__(256) void k_trav_init(int members, int NB, const i32* __restrict__ ncnt,
+                                                    u64* __restrict__ front, u32 cap, u32* __restrict__ counters) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = g / 400, i = g % 400;
+    const u32 t = ((u32)m << NB) + (u32)(i / 20), s = ((u32)m << NB) + (u32)(i % 20);
+    const bool ok = m < members && ncnt[t] > 0 && ncnt[s] > 0;
     const u32 slot = wave_append(&counters[C_FRONT], ok);
     if (ok) {
-        if (slot < cap) front[slot] = ((u64)(i / 20) << 32) | (u64)(i % 20);
+        if (slot < cap) front[slot] = ((u64)t << 32) | (u64)s;
         else atomicOr(&counters[C_OVERFLOW], 1u);
     }
 }
@@ -309,13 +331,14 @@ constexpr int TRAV_IPT = 4;  // frontier pairs per thread per round
 
 __global__ __launch_bounds__(256) void k_trav_level(
     int iter, const u64* __restrict__ fin, u64* __restrict__ fout, u32 cap, const i32* __restrict__ ncnt,
-    const NodeMac* __restrict__ mac, const i64* __restrict__ level_off_tab, int L, double theta2, int n_crit, int W,
-    u64* __restrict__ tlist, u64* __restrict__ nlist, u32* __restrict__ counters) {
+    const NodeMac* __restrict__ mac, const i64* __restrict__ level_off_tab, int L, int NB, double theta2, int n_crit,
+    int W, u64* __restrict__ tlist, u64* __restrict__ nlist, u32* __restrict__ counters) {
     __shared__ u32 wsum[3][4];
     __shared__ u32 bases[3];
     u32 nin = counters[C_FRONT + iter];
     if (nin > cap) nin = cap;
     const int tid = threadIdx.x;
+    const u32 lm = (1u << NB) - 1u;  // local part of a node id
     const u64 round = (u64)256 * TRAV_IPT;
     for (u64 r0 = (u64)blockIdx.x * round; r0 < nin; r0 += (u64)gridDim.x * round) {
         u64 keyv[TRAV_IPT];
@@ -339,13 +362,13 @@ __global__ __launch_bounds__(256) void k_trav_level(
                 ss[k] = s;
                 const i32 nt = ncnt[t], ns = ncnt[s];
                 const bool big_t = nt > n_crit, big_s = ns > n_crit;
-                if (mac_separated(mac[t], mac[s], theta2)) {
+                if (mac_separated(mac[t & lm], mac[s & lm], theta2)) {
                     kind[k] = (big_t ? 2 : 0) + (big_s ? 1 : 0);
                 } else if (!big_t && !big_s) {
                     kind[k] = 0;
                 } else {
-                    const int lt = level_of_offset_table(level_off_tab, L, t);
-                    const int ls = level_of_offset_table(level_off_tab, L, s);
+                    const int lt = level_of_offset_table(level_off_tab, L, t & lm);
+                    const int ls = level_of_offset_table(level_off_tab, L, s & lm);
                     const bool int_t = big_t && lt < L, int_s = big_s && ls < L;
                     bool st = nt >= ns;
                     if (st && !int_t) st = false;
@@ -357,7 +380,8 @@ __global__ __launch_bounds__(256) void k_trav_level(
                         split_t[k] = st;
                         const u32 x = st ? t : s;
                         const int lx = st ? lt : ls;
-                        const i64 child0 = level_off_tab[lx + 1] + 4 * ((i64)x - level_off_tab[lx]);
+                        const i64 child0 =
+                            (i64)(x & ~lm) + level_off_tab[lx + 1] + 4 * ((i64)(x & lm) - level_off_tab[lx]);
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
                             const u32 cid = (u32)(child0 + c);
@@ -406,11 +430,25 @@ __global__ __launch_bounds__(256) void k_trav_level(
     }
 }
 
-// per-node particle count and the compact MAC record (circumcentre, radius)
+// Per-node particle count, and a storage slot for the proxy records and
+// target coefficients of every node with more than N_T particles (slots are
+// handed out in any order; only where a node's data lives depends on it).
 __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbeg, const i32* __restrict__ nend,
-                                                      i64 n_nodes, i32* __restrict__ ncnt) {
+                                                      i64 n_nodes, int n_crit, i32* __restrict__ ncnt,
+                                                      i32* __restrict__ slot, u32 slot_cap, u32* __restrict__ flags) {
     const u64 stride = (u64)gridDim.x * blockDim.x;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < (u64)n_nodes; i += stride) ncnt[i] = nend[i] - nbeg[i];
+    for (u64 b0 = (u64)blockIdx.x * blockDim.x; b0 < (u64)n_nodes; b0 += stride) {
+        const u64 i = b0 + threadIdx.x;
+        const bool ok = i < (u64)n_nodes;
+        const i32 c = ok ? nend[i] - nbeg[i] : 0;
+        const bool big = ok && c > n_crit;
+        const u32 sl = wave_append(&flags[F_SLOT_CTR], big);  // every lane of the wave takes part
+        if (big && sl >= slot_cap) atomicOr(&flags[F_SLOTS], 1u);
+        if (ok) {
+            ncnt[i] = c;
+            slot[i] = big ? (i32)(sl < slot_cap ? sl : slot_cap - 1) : -1;
+        }
+    }
 }
 
 // Segments of a sorted list: entries with the same target t occupy
@@ -473,9 +511,10 @@ namespace {
 inline unsigned blocks_for(i64 n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 }
 
-void launch_bin(hipStream_t s, const double* x, i64 n, const NodeGeo* geo, int L, u64* keys, u32* flags) {
+void launch_bin(hipStream_t s, const double* x, i64 n, const NodeGeo* geo, int L, const MemberOffsets& mo,
+                u64* keys, u32* flags) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n, geo, L, keys, flags);
+    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n, geo, L, mo, keys, flags);
 }
 
 void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* perm, u32* leaf, double* sx,
@@ -484,9 +523,9 @@ void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* 
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, n, x, perm, leaf, sx, sy, sz);
 }
 
-void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, i32* nbeg, i32* nend) {
+void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i32* nbeg, i32* nend) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_node_ranges, dim3(blocks_for(n, 256)), dim3(256), 0, s, leaf, n, L, nbeg, nend);
+    hipLaunchKernelGGL(k_node_ranges, dim3(blocks_for(n, 256)), dim3(256), 0, s, leaf, n, L, NB, nbeg, nend);
 }
 
 void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area, double* q) {
@@ -494,9 +533,9 @@ void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, c
     hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, q);
 }
 
-void launch_upward(hipStream_t s, const i32* nbeg, const i32* nend, const i64* level_off_host, int L, int n_crit,
-                   const NodeGeo* geo, const double* sx, const double* sy, const double* sz, const double* q,
-                   RefDev ref, Prox* prox) {
+void launch_upward(hipStream_t s, int members, int NB, const i32* nbeg, const i32* nend, const i64* level_off_host,
+                   int L, int n_crit, const NodeGeo* geo, const double* sx, const double* sy, const double* sz,
+                   const double* q, RefDev ref, const i32* slot, Prox* prox) {
     for (int lvl = L; lvl >= 0; --lvl) {
         const i64 node0 = level_off_host[lvl];
         const i64 nn = level_off_host[lvl + 1] - node0;
@@ -505,9 +544,10 @@ void launch_upward(hipStream_t s, const i32* nbeg, const i32* nend, const i64* l
         // checked in parallel, the big ones processed in turn
         const int chunk = nn > 8192 ? 256 : 1;
         const i64 nchunks = (nn + chunk - 1) / chunk;
-        const unsigned grid = (unsigned)(nchunks < 4096 ? nchunks : 4096);
-        hipLaunchKernelGGL(k_upward_level, dim3(grid), dim3(256), 0, s, node0, nn, chunk, lvl, L, child_off, nbeg,
-                           nend, n_crit, geo, sx, sy, sz, q, ref, prox);
+        const i64 per_member = std::max<i64>(1, 4096 / members);
+        const unsigned grid = (unsigned)(nchunks < per_member ? nchunks : per_member);
+        hipLaunchKernelGGL(k_upward_level, dim3(grid, (unsigned)members), dim3(256), 0, s, node0, nn, chunk, lvl, L,
+                           NB, child_off, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, slot, prox);
     }
 }
 
@@ -523,24 +563,26 @@ void launch_fill_f64(hipStream_t s, double* p, i64 n, double v) {
     hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, p, n, v);
 }
 
-void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, i32* ncnt) {
+void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, i32* ncnt,
+                        i32* slot, u32 slot_cap, u32* flags) {
     const i64 b = blocks_for(n_nodes, 256);
     hipLaunchKernelGGL(k_node_counts, dim3((unsigned)(b < 2048 ? b : 2048)), dim3(256), 0, s, nbeg, nend, n_nodes,
-                       ncnt);
+                       n_crit, ncnt, slot, slot_cap, flags);
 }
 
-void launch_traverse(hipStream_t s, const i32* ncnt, const NodeMac* mac, const i64* level_off_tab, int L,
-                     double theta, int n_crit, int W, u64* front0, u64* front1, u32 cap, u64* tlist, u64* nlist,
-                     u32* counters) {
+void launch_traverse(hipStream_t s, int members, int NB, const i32* ncnt, const NodeMac* mac,
+                     const i64* level_off_tab, int L, double theta, int n_crit, int W, u64* front0, u64* front1,
+                     u32 cap, u64* tlist, u64* nlist, u32* counters) {
     launch_fill_u32(s, counters, C_COUNT, 0u);
-    hipLaunchKernelGGL(k_trav_init, dim3(1), dim3(512), 0, s, ncnt, front0, cap, counters);
+    hipLaunchKernelGGL(k_trav_init, dim3(blocks_for((i64)members * 400, 256)), dim3(256), 0, s, members, NB, ncnt,
+                       front0, cap, counters);
     const double theta2 = theta * theta;
     const int iters = 2 * L + 2;
     for (int it = 0; it < iters; ++it) {
         const u64* fin = (it % 2 == 0) ? front0 : front1;
         u64* fout = (it % 2 == 0) ? front1 : front0;
         hipLaunchKernelGGL(k_trav_level, dim3(1024), dim3(256), 0, s, it, fin, fout, cap, ncnt, mac, level_off_tab,
-                           L, theta2, n_crit, W, tlist, nlist, counters);
+                           L, NB, theta2, n_crit, W, tlist, nlist, counters);
     }
 }
 

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,10 +17,19 @@ using namespace stc;
 struct stc_ctx {
     stc_params p{};
     int L = 0, np = 0, W = 0;
-    i64 n_max = 0, n_nodes = 0;
+    // ensembles: node id = (member << NB) | local id, leaf key bits LB = 2L + 5
+    int max_members = 1, members = 1, NB = 0, LB = 0;
+    i64 n_max = 0, n_max_member = 0;
+    i64 n_local = 0;      // nodes of one member's tree
+    i64 n_nodes = 0;      // length of the per-node arrays: ((max_members - 1) << NB) + n_local
+    i64 used_nodes = 0;   // the part the last build touched
+    u32 slot_cap = 0;     // nodes with proxy charges that fit the proxy / coefficient storage
     u32 cap = 0;
     hipStream_t stream = nullptr;
-    int grid = 2048;
+    int cus = 256;
+    stc_launch_config shape_default{};
+    std::map<int, stc_launch_config> shapes;  // per size class (bits of the particle count)
+    std::vector<i64> offsets;                 // member offsets of the last build
     std::vector<NodeGeo> geo_host;
     RefTables ref_host;
     std::vector<i64> level_off_host;
@@ -27,6 +37,7 @@ struct stc_ctx {
     NodeGeo* geo = nullptr;
     NodeMac* mac = nullptr;
     i32* ncnt = nullptr;
+    i32* slot = nullptr;
     i64* level_off = nullptr;
     double *ref_points = nullptr, *ref_vinv = nullptr, *ref_vinvT = nullptr, *ref_coef = nullptr;
     int* ref_expo = nullptr;
@@ -53,6 +64,7 @@ struct stc_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t rk_exec = nullptr;
     i64 rk_n = -1;
+    std::vector<i64> rk_offsets;
     const void *rk_px = nullptr, *rk_pz = nullptr, *rk_pa = nullptr;
     double rk_dt = 0.0, rk_om = 0.0;
     // phase timing: 7 events per recorded evaluation
@@ -110,6 +122,22 @@ int bits_for(i64 v) {
     return b;
 }
 
+int size_class(i64 n) { return bits_for(std::max<i64>(n, 1)); }
+
+stc_launch_config shape_for(const stc_ctx* c, i64 n) {
+    auto it = c->shapes.find(size_class(n));
+    return it != c->shapes.end() ? it->second : c->shape_default;
+}
+
+// workgroups of a persistent segment kernel: a multiple of 8 (one per XCD slot)
+int grid_for(const stc_ctx* c, int per_cu) { return std::max(8, ((c->cus * per_cu + 7) / 8) * 8); }
+
+bool valid_shape(const stc_launch_config* s) {
+    auto ok_threads = [](int t) { return t == 128 || t == 256 || t == 512; };
+    return s && ok_threads(s->near_threads) && ok_threads(s->far_threads) && s->near_blocks_per_cu >= 1 &&
+           s->near_blocks_per_cu <= 64 && s->far_blocks_per_cu >= 1 && s->far_blocks_per_cu <= 64;
+}
+
 RefDev ref_dev(const stc_ctx* c) {
     RefDev r;
     r.points = c->ref_points;
@@ -143,6 +171,7 @@ EvalArgs eval_args(stc_ctx* c) {
     a.sy = c->sy;
     a.sz = c->sz;
     a.sq = c->sq;
+    a.slot = c->slot;
     a.prox = c->prox;
     a.alpha = c->alpha;
     a.Wacc = c->Wacc;
@@ -152,7 +181,14 @@ EvalArgs eval_args(stc_ctx* c) {
     a.ref = ref_dev(c);
     a.precision = c->p.precision;
     a.denominator = c->p.denominator;
-    a.grid = c->grid;
+    a.node_mask = (u32)(((u64)1 << c->NB) - 1);
+    a.NB = c->NB;
+    a.LB = c->LB;
+    const stc_launch_config sh = shape_for(c, c->n);
+    a.near_threads = sh.near_threads;
+    a.near_grid = grid_for(c, sh.near_blocks_per_cu);
+    a.far_threads = sh.far_threads;
+    a.far_grid = grid_for(c, sh.far_blocks_per_cu);
     return a;
 }
 
@@ -171,26 +207,46 @@ stc_status validate_params(const stc_params* p, i64 n_max) {
     return STC_OK;
 }
 
-stc_status do_build(stc_ctx* c, i64 n, const double* d_x) {
+// Checks member offsets (host array of members + 1 entries) against the
+// context; returns the total particle count or -1.
+i64 check_offsets(const stc_ctx* c, int members, const int64_t* h_off) {
+    if (members < 1 || members > c->max_members || !h_off || h_off[0] != 0) return -1;
+    for (int m = 0; m < members; ++m)
+        if (h_off[m + 1] < h_off[m]) return -1;
+    const i64 n = h_off[members];
+    return n <= c->n_max ? n : -1;
+}
+
+// Tree build of `members` particle sets concatenated in d_x (member m owns
+// [off[m], off[m+1])).
+stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) {
     hipStream_t s = c->stream;
+    const i64 n = off[members];
     c->n = n;
     c->x = d_x;
+    c->members = members;
+    c->offsets.assign(off, off + members + 1);
+    c->used_nodes = ((i64)(members - 1) << c->NB) + c->n_local;
     c->have_tree = true;
     c->have_upward = false;
     c->have_lists = false;
     mark(c, 0);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nbeg), c->n_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nend), c->n_nodes, 0u);
+    launch_fill_u32(s, c->flags, F_COUNT, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nbeg), c->used_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nend), c->used_nodes, 0u);
     if (n == 0) {
-        launch_fill_u32(s, reinterpret_cast<u32*>(c->ncnt), c->n_nodes, 0u);
+        launch_fill_u32(s, reinterpret_cast<u32*>(c->ncnt), c->used_nodes, 0u);
         return check_launch(c, "tree_build");
     }
-    launch_bin(s, d_x, n, c->geo, c->L, c->keys_a, c->flags);
-    radix_sort(s, c->keys_a, c->keys_b, nullptr, (u32)n, 32, 32 + 2 * c->L + 5, SortScratch{c->hist, c->hist_totals, c->hist_blocks},
-               &c->keys_sorted);
+    MemberOffsets mo{};
+    mo.m = members;
+    for (int m = 0; m <= members; ++m) mo.off[m] = off[m];
+    launch_bin(s, d_x, n, c->geo, c->L, mo, c->keys_a, c->flags);
+    radix_sort(s, c->keys_a, c->keys_b, nullptr, (u32)n, 32, 32 + c->LB + bits_for(members),
+               SortScratch{c->hist, c->hist_totals, c->hist_blocks}, &c->keys_sorted);
     launch_gather(s, c->keys_sorted, n, d_x, c->perm, c->leaf, c->sx, c->sy, c->sz);
-    launch_node_ranges(s, c->leaf, n, c->L, c->nbeg, c->nend);
-    launch_node_counts(s, c->nbeg, c->nend, c->n_nodes, c->ncnt);
+    launch_node_ranges(s, c->leaf, n, c->L, c->NB, c->nbeg, c->nend);
+    launch_node_counts(s, c->nbeg, c->nend, c->used_nodes, c->p.n_crit, c->ncnt, c->slot, c->slot_cap, c->flags);
     return check_launch(c, "tree_build");
 }
 
@@ -199,8 +255,8 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
     mark(c, 1);
     launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sq);
     if (c->n > 0)
-        launch_upward(s, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit, c->geo, c->sx, c->sy, c->sz,
-                      c->sq, ref_dev(c), c->prox);
+        launch_upward(s, c->members, c->NB, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit, c->geo,
+                      c->sx, c->sy, c->sz, c->sq, ref_dev(c), c->slot, c->prox);
     c->have_upward = true;
     return check_launch(c, "upward");
 }
@@ -208,8 +264,8 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
 stc_status do_traverse(stc_ctx* c) {
     hipStream_t s = c->stream;
     mark(c, 2);
-    launch_traverse(s, c->ncnt, c->mac, c->level_off, c->L, c->p.theta, c->p.n_crit, c->W, c->front0, c->front1,
-                    c->cap, c->tlist_a, c->nlist_a, c->counters);
+    launch_traverse(s, c->members, c->NB, c->ncnt, c->mac, c->level_off, c->L, c->p.theta, c->p.n_crit, c->W,
+                    c->front0, c->front1, c->cap, c->tlist_a, c->nlist_a, c->counters);
     const int bits = 2 * c->W + 1;
     SortScratch sc{c->hist, c->hist_totals, c->hist_blocks};
     {
@@ -221,10 +277,10 @@ stc_status do_traverse(stc_ctx* c) {
         c->tlist = res[0];
         c->nlist = res[1];
     }
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_beg), c->n_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_end), c->n_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_beg), c->n_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_end), c->n_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_beg), c->used_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_end), c->used_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_beg), c->used_nodes, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_end), c->used_nodes, 0u);
     launch_segments(s, c->tlist, c->counters + C_TLIST, c->cap, c->W, c->tseg_beg, c->tseg_end);
     launch_segments(s, c->nlist, c->counters + C_NLIST, c->cap, c->W, c->nseg_beg, c->nseg_end);
     c->have_lists = true;
@@ -325,21 +381,43 @@ int32_t stc_default_max_level(int64_t n_max, int32_t n_crit) {
 }
 
 stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_ctx** out) {
+    return stc_create_batched(p, 1, n_max, n_max, hip_stream, out);
+}
+
+stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t n_max_member, int64_t n_max_total,
+                              void* hip_stream, stc_ctx** out) {
     if (!out) return STC_ERR_INVALID_ARG;
     *out = nullptr;
-    stc_status st = validate_params(p, n_max);
+    stc_status st = validate_params(p, n_max_total);
     if (st != STC_OK) return st;
+    if (max_members < 1 || max_members > STC_MAX_MEMBERS || n_max_member < 0 || n_max_member > n_max_total)
+        return STC_ERR_INVALID_ARG;
+    const int L = p->max_level >= 0 ? p->max_level : stc_default_max_level(n_max_member, p->n_crit);
+    const int mbits = bits_for(max_members);
+    const int NB = std::max(1, bits_for(stc::total_nodes(L)));
+    // leaf keys (member, face, 2L digits) are 32-bit; list keys hold two node ids and a type bit
+    if (2 * L + 5 + mbits > 32 || NB + mbits > 31) return STC_ERR_INVALID_ARG;
     stc_ctx* c = new (std::nothrow) stc_ctx();
     if (!c) return STC_ERR_ALLOC;
     c->p = *p;
-    c->n_max = n_max;
+    c->n_max = n_max_total;
+    c->n_max_member = n_max_member;
+    c->max_members = max_members;
     c->stream = static_cast<hipStream_t>(hip_stream);
-    c->L = p->max_level >= 0 ? p->max_level : stc_default_max_level(n_max, p->n_crit);
+    c->L = L;
     c->p.max_level = c->L;
     c->np = stc_n_basis(p->degree);
-    c->n_nodes = stc::total_nodes(c->L);
-    c->W = std::max(1, bits_for(c->n_nodes));
-    i64 cap = p->list_capacity > 0 ? p->list_capacity : std::max<i64>(65536, 16 * n_max);
+    c->NB = NB;
+    c->LB = 2 * L + 5;
+    c->n_local = stc::total_nodes(c->L);
+    c->n_nodes = ((i64)(max_members - 1) << NB) + c->n_local;
+    c->used_nodes = c->n_local;
+    c->W = NB + mbits;
+    // nodes with more than n_crit particles are disjoint within a level:
+    // at most n_max / (n_crit + 1) per level over all members
+    const i64 nm = std::max<i64>(n_max_total, 1);
+    c->slot_cap = (u32)std::min<i64>((i64)(c->L + 1) * (nm / (p->n_crit + 1)) + 1, 0x7fffffffLL);
+    i64 cap = p->list_capacity > 0 ? p->list_capacity : std::max<i64>(65536, 16 * n_max_total);
     c->cap = (u32)std::min<i64>(cap, 0x7fffffffLL);
     try {
         build_tree_geometry(c->L, c->geo_host);
@@ -353,22 +431,23 @@ stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_
     }
     c->level_off_host.resize(c->L + 2);
     for (int l = 0; l <= c->L + 1; ++l) c->level_off_host[l] = level_offset(l);
-    const i64 nm = std::max<i64>(n_max, 1);
     c->hist_blocks = (int)((std::max<i64>(c->cap, nm) + 4095) / 4096);
+    const size_t np = (size_t)c->np, ns = c->slot_cap;
     bool ok = dalloc(c, &c->geo, c->geo_host.size()) && dalloc(c, &c->mac, c->geo_host.size()) &&
-              dalloc(c, &c->ncnt, c->n_nodes) && dalloc(c, &c->level_off, c->level_off_host.size()) &&
-              dalloc(c, &c->ref_points, 3 * c->np) && dalloc(c, &c->ref_vinv, (size_t)c->np * c->np) && dalloc(c, &c->ref_vinvT, (size_t)c->np * c->np) &&
-              dalloc(c, &c->ref_coef, c->np) && dalloc(c, &c->ref_expo, 3 * c->np) &&
-              dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) && dalloc(c, &c->perm, nm) &&
-              dalloc(c, &c->leaf, nm) && dalloc(c, &c->sx, nm) && dalloc(c, &c->sy, nm) && dalloc(c, &c->sz, nm) &&
-              dalloc(c, &c->sq, nm) && dalloc(c, &c->nbeg, c->n_nodes) && dalloc(c, &c->nend, c->n_nodes) &&
-              dalloc(c, &c->prox, (size_t)c->n_nodes * c->np) && dalloc(c, &c->alpha, (size_t)c->n_nodes * c->np * 3) &&
+              dalloc(c, &c->ncnt, c->n_nodes) && dalloc(c, &c->slot, c->n_nodes) &&
+              dalloc(c, &c->level_off, c->level_off_host.size()) && dalloc(c, &c->ref_points, 3 * np) &&
+              dalloc(c, &c->ref_vinv, np * np) && dalloc(c, &c->ref_vinvT, np * np) && dalloc(c, &c->ref_coef, np) &&
+              dalloc(c, &c->ref_expo, 3 * np) && dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) &&
+              dalloc(c, &c->perm, nm) && dalloc(c, &c->leaf, nm) && dalloc(c, &c->sx, nm) && dalloc(c, &c->sy, nm) &&
+              dalloc(c, &c->sz, nm) && dalloc(c, &c->sq, nm) && dalloc(c, &c->nbeg, c->n_nodes) &&
+              dalloc(c, &c->nend, c->n_nodes) && dalloc(c, &c->prox, ns * np) && dalloc(c, &c->alpha, ns * np * 3) &&
               dalloc(c, &c->Wacc, 3 * nm) && dalloc(c, &c->front0, c->cap) && dalloc(c, &c->front1, c->cap) &&
               dalloc(c, &c->tlist_a, c->cap) && dalloc(c, &c->tlist_b, c->cap) && dalloc(c, &c->nlist_a, c->cap) &&
               dalloc(c, &c->nlist_b, c->cap) && dalloc(c, &c->tseg_beg, c->n_nodes) &&
               dalloc(c, &c->tseg_end, c->n_nodes) && dalloc(c, &c->nseg_beg, c->n_nodes) &&
-              dalloc(c, &c->nseg_end, c->n_nodes) && dalloc(c, &c->counters, C_COUNT) && dalloc(c, &c->flags, 4) &&
-              dalloc(c, &c->evals, 8) && dalloc(c, &c->hist, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->hist_totals, 512) &&
+              dalloc(c, &c->nseg_end, c->n_nodes) && dalloc(c, &c->counters, C_COUNT) &&
+              dalloc(c, &c->flags, F_COUNT) && dalloc(c, &c->evals, 8) &&
+              dalloc(c, &c->hist, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->hist_totals, 512) &&
               dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
               dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm);
     if (!ok) {
@@ -378,34 +457,36 @@ stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_
     c->tlist = c->tlist_a;
     c->nlist = c->nlist_a;
     hipStream_t s = c->stream;
-    std::vector<double> vinvT_host((size_t)c->np * c->np);
-    for (int k = 0; k < c->np; ++k)
-        for (int m = 0; m < c->np; ++m) vinvT_host[(size_t)m * c->np + k] = c->ref_host.vinv[(size_t)k * c->np + m];
+    std::vector<double> vinvT_host(np * np);
+    for (size_t k = 0; k < np; ++k)
+        for (size_t m = 0; m < np; ++m) vinvT_host[m * np + k] = c->ref_host.vinv[k * np + m];
     std::vector<NodeMac> mac_host(c->geo_host.size());
     for (size_t i = 0; i < mac_host.size(); ++i)
         mac_host[i] = NodeMac{c->geo_host[i].c[0], c->geo_host[i].c[1], c->geo_host[i].c[2], c->geo_host[i].r};
-    bool cp = hipMemcpyAsync(c->geo, c->geo_host.data(), c->geo_host.size() * sizeof(NodeGeo), hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(c->mac, mac_host.data(), mac_host.size() * sizeof(NodeMac), hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(c->level_off, c->level_off_host.data(), c->level_off_host.size() * sizeof(i64), hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(c->ref_points, c->ref_host.points.data(), 3 * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(c->ref_vinv, c->ref_host.vinv.data(), (size_t)c->np * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(c->ref_vinvT, vinvT_host.data(), (size_t)c->np * c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(c->ref_coef, c->ref_host.coef.data(), c->np * sizeof(double), hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(c->ref_expo, c->ref_host.expo.data(), 3 * c->np * sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    bool cp = up(c->geo, c->geo_host.data(), c->geo_host.size() * sizeof(NodeGeo)) &&
+              up(c->mac, mac_host.data(), mac_host.size() * sizeof(NodeMac)) &&
+              up(c->level_off, c->level_off_host.data(), c->level_off_host.size() * sizeof(i64)) &&
+              up(c->ref_points, c->ref_host.points.data(), 3 * np * sizeof(double)) &&
+              up(c->ref_vinv, c->ref_host.vinv.data(), np * np * sizeof(double)) &&
+              up(c->ref_vinvT, vinvT_host.data(), np * np * sizeof(double)) &&
+              up(c->ref_coef, c->ref_host.coef.data(), np * sizeof(double)) &&
+              up(c->ref_expo, c->ref_host.expo.data(), 3 * np * sizeof(int));
     launch_fill_u32(s, c->counters, C_COUNT, 0u);
-    launch_fill_u32(s, c->flags, 4, 0u);
+    launch_fill_u32(s, c->flags, F_COUNT, 0u);
     if (!cp || hipStreamSynchronize(s) != hipSuccess) {
         stc_destroy(c);
         return STC_ERR_DEVICE;
     }
-    // persistent segment kernels: a multiple of 8 workgroups (one per XCD slot)
-    int dev = 0, cus = 256;
+    int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
+            c->cus = prop.multiProcessorCount;
     }
-    c->grid = std::max(8, (cus * 12 / 8) * 8);
+    c->shape_default = stc_launch_config{256, 12, 256, 12};
     *out = c;
     return STC_OK;
 }
@@ -437,7 +518,16 @@ stc_status stc_tree_build(stc_ctx* c, int64_t n, const double* d_x) {
     if (!c) return STC_ERR_INVALID_ARG;
     if (n < 0 || n > c->n_max) return fail(c, STC_ERR_INVALID_ARG, "n out of range [0, n_max]");
     if (n > 0 && (!d_x || !aligned8(d_x))) return fail(c, STC_ERR_INVALID_ARG, "d_x is NULL or misaligned");
-    return do_build(c, n, d_x);
+    const i64 off[2] = {0, n};
+    return do_build(c, 1, off, d_x);
+}
+
+stc_status stc_tree_build_batched(stc_ctx* c, int32_t members, const int64_t* h_offsets, const double* d_x) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    const i64 n = check_offsets(c, members, h_offsets);
+    if (n < 0) return fail(c, STC_ERR_INVALID_ARG, "bad member count or offsets");
+    if (n > 0 && (!d_x || !aligned8(d_x))) return fail(c, STC_ERR_INVALID_ARG, "d_x is NULL or misaligned");
+    return do_build(c, members, h_offsets, d_x);
 }
 
 stc_status stc_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
@@ -475,7 +565,23 @@ stc_status stc_velocity(stc_ctx* c, int64_t n, const double* d_x, const double* 
     if (n > 0 && (!d_x || !d_zeta || !d_area || !d_u || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area) ||
                   !aligned8(d_u)))
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
-    stc_status st = do_build(c, n, d_x);
+    const i64 off[2] = {0, n};
+    stc_status st = do_build(c, 1, off, d_x);
+    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
+    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_eval(c, true, true, d_u, false);
+    return st;
+}
+
+stc_status stc_velocity_batched(stc_ctx* c, int32_t members, const int64_t* h_offsets, const double* d_x,
+                                const double* d_zeta, const double* d_area, double* d_u) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    const i64 n = check_offsets(c, members, h_offsets);
+    if (n < 0) return fail(c, STC_ERR_INVALID_ARG, "bad member count or offsets");
+    if (n > 0 && (!d_x || !d_zeta || !d_area || !d_u || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area) ||
+                  !aligned8(d_u)))
+        return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
+    stc_status st = do_build(c, members, h_offsets, d_x);
     if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
     if (st == STC_OK) st = do_traverse(c);
     if (st == STC_OK) st = do_eval(c, true, true, d_u, false);
@@ -498,10 +604,12 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
     return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
 }
 
-// Enqueues one RK4 step on c->stream (no host synchronisation, no memsets).
-static stc_status rk4_enqueue_step(stc_ctx* c, i64 n, double* d_x, double* d_zeta, const double* d_area, double dt,
-                                   double omega) {
+// Enqueues one RK4 step of every member on c->stream (no host
+// synchronisation, no memsets).
+static stc_status rk4_enqueue_step(stc_ctx* c, int members, const i64* off, double* d_x, double* d_zeta,
+                                   const double* d_area, double dt, double omega) {
     hipStream_t s = c->stream;
+    const i64 n = off[members];
     const dim3 g((unsigned)((n + 255) / 256)), b(256);
     // stage nodes 0, 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6
     const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
@@ -509,7 +617,10 @@ static stc_status rk4_enqueue_step(stc_ctx* c, i64 n, double* d_x, double* d_zet
     const double* xs = d_x;
     const double* zs = d_zeta;
     for (int stg = 0; stg < 4; ++stg) {
-        stc_status st = stc_velocity(c, n, xs, zs, d_area, c->rk_u);
+        stc_status st = do_build(c, members, off, xs);
+        if (st == STC_OK) st = do_upward(c, zs, d_area);
+        if (st == STC_OK) st = do_traverse(c);
+        if (st == STC_OK) st = do_eval(c, true, true, c->rk_u, false);
         if (st != STC_OK) return st;
         hipLaunchKernelGGL(k_rk4_combine, g, b, 0, s, (i64)n, d_x, d_zeta, c->rk_u, omega, cnext[stg], wacc[stg],
                            c->rk_x, c->rk_z, c->rk_xacc, c->rk_zacc, stg == 0 ? 1 : 0);
@@ -524,11 +635,12 @@ static void rk4_drop_graph(stc_ctx* c) {
     if (c->rk_exec) (void)hipGraphExecDestroy(c->rk_exec);
     c->rk_exec = nullptr;
     c->rk_n = -1;
+    c->rk_offsets.clear();
 }
 
 // Captures one RK4 step into a graph (on the context's capture stream).
-static stc_status rk4_capture(stc_ctx* c, i64 n, double* d_x, double* d_zeta, const double* d_area, double dt,
-                              double omega) {
+static stc_status rk4_capture(stc_ctx* c, int members, const i64* off, double* d_x, double* d_zeta,
+                              const double* d_area, double dt, double omega) {
     rk4_drop_graph(c);
     if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(c, STC_ERR_DEVICE, "creating the capture stream failed");
@@ -542,7 +654,7 @@ static stc_status rk4_capture(stc_ctx* c, i64 n, double* d_x, double* d_zeta, co
     if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         st = fail(c, STC_ERR_DEVICE, "hipStreamBeginCapture failed");
     } else {
-        st = rk4_enqueue_step(c, n, d_x, d_zeta, d_area, dt, omega);
+        st = rk4_enqueue_step(c, members, off, d_x, d_zeta, d_area, dt, omega);
         const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
         if (st == STC_OK && e != hipSuccess) st = fail(c, STC_ERR_DEVICE, "hipStreamEndCapture failed");
     }
@@ -554,7 +666,8 @@ static stc_status rk4_capture(stc_ctx* c, i64 n, double* d_x, double* d_zeta, co
     }
     if (graph) (void)hipGraphDestroy(graph);
     if (st != STC_OK) return st;
-    c->rk_n = n;
+    c->rk_n = off[members];
+    c->rk_offsets.assign(off, off + members + 1);
     c->rk_px = d_x;
     c->rk_pz = d_zeta;
     c->rk_pa = d_area;
@@ -563,11 +676,11 @@ static stc_status rk4_capture(stc_ctx* c, i64 n, double* d_x, double* d_zeta, co
     return STC_OK;
 }
 
-stc_status stc_rk4(stc_ctx* c, int64_t n, double* d_x, double* d_zeta, const double* d_area, double dt, double omega,
-                   int32_t n_steps) {
-    if (!c) return STC_ERR_INVALID_ARG;
-    if (n < 0 || n > c->n_max || n_steps < 0 || !std::isfinite(dt) || !std::isfinite(omega))
-        return fail(c, STC_ERR_INVALID_ARG, "bad n, n_steps, dt or omega");
+static stc_status rk4_run(stc_ctx* c, int members, const i64* off, double* d_x, double* d_zeta,
+                          const double* d_area, double dt, double omega, int32_t n_steps) {
+    const i64 n = off[members];
+    if (n_steps < 0 || !std::isfinite(dt) || !std::isfinite(omega))
+        return fail(c, STC_ERR_INVALID_ARG, "bad n_steps, dt or omega");
     if (n == 0 || n_steps == 0) return STC_OK;
     if (!d_x || !d_zeta || !d_area || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area))
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
@@ -578,13 +691,16 @@ stc_status stc_rk4(stc_ctx* c, int64_t n, double* d_x, double* d_zeta, const dou
     const bool use_graph = (c->p.flags & STC_FLAG_EAGER_RK4) == 0;
     if (!use_graph) {
         for (int step = 0; step < n_steps; ++step) {
-            stc_status st = rk4_enqueue_step(c, n, d_x, d_zeta, d_area, dt, omega);
+            stc_status st = rk4_enqueue_step(c, members, off, d_x, d_zeta, d_area, dt, omega);
             if (st != STC_OK) return st;
         }
     } else {
-        if (!(c->rk_exec && c->rk_n == n && c->rk_px == d_x && c->rk_pz == d_zeta && c->rk_pa == d_area &&
-              c->rk_dt == dt && c->rk_om == omega)) {
-            stc_status st = rk4_capture(c, n, d_x, d_zeta, d_area, dt, omega);
+        const bool same = c->rk_exec && c->rk_n == n && c->rk_px == d_x && c->rk_pz == d_zeta &&
+                          c->rk_pa == d_area && c->rk_dt == dt && c->rk_om == omega &&
+                          c->rk_offsets.size() == (size_t)members + 1 &&
+                          std::equal(c->rk_offsets.begin(), c->rk_offsets.end(), off);
+        if (!same) {
+            stc_status st = rk4_capture(c, members, off, d_x, d_zeta, d_area, dt, omega);
             if (st != STC_OK) return st;
         }
         for (int step = 0; step < n_steps; ++step)
@@ -595,17 +711,114 @@ stc_status stc_rk4(stc_ctx* c, int64_t n, double* d_x, double* d_zeta, const dou
     return STC_OK;
 }
 
+stc_status stc_rk4(stc_ctx* c, int64_t n, double* d_x, double* d_zeta, const double* d_area, double dt, double omega,
+                   int32_t n_steps) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (n < 0 || n > c->n_max) return fail(c, STC_ERR_INVALID_ARG, "n out of range [0, n_max]");
+    const i64 off[2] = {0, n};
+    return rk4_run(c, 1, off, d_x, d_zeta, d_area, dt, omega, n_steps);
+}
+
+stc_status stc_rk4_batched(stc_ctx* c, int32_t members, const int64_t* h_offsets, double* d_x, double* d_zeta,
+                           const double* d_area, double dt, double omega, int32_t n_steps) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (check_offsets(c, members, h_offsets) < 0) return fail(c, STC_ERR_INVALID_ARG, "bad member count or offsets");
+    return rk4_run(c, members, h_offsets, d_x, d_zeta, d_area, dt, omega, n_steps);
+}
+
+stc_status stc_node_layout(const stc_ctx* c, int32_t* node_bits, int64_t* nodes_per_member, int64_t* node_array_len) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (node_bits) *node_bits = c->NB;
+    if (nodes_per_member) *nodes_per_member = c->n_local;
+    if (node_array_len) *node_array_len = c->n_nodes;
+    return STC_OK;
+}
+
+stc_status stc_get_launch_config(const stc_ctx* c, int64_t n_total, stc_launch_config* out) {
+    if (!c || !out) return STC_ERR_INVALID_ARG;
+    *out = shape_for(c, n_total);
+    return STC_OK;
+}
+
+stc_status stc_set_launch_config(stc_ctx* c, int64_t n_total, const stc_launch_config* cfg) {
+    if (!c || !valid_shape(cfg)) return STC_ERR_INVALID_ARG;
+    if (n_total < 0) c->shape_default = *cfg;
+    else c->shapes[size_class(n_total)] = *cfg;
+    return STC_OK;
+}
+
+stc_status stc_autotune(stc_ctx* c, int32_t repeats, stc_launch_config* out) {
+    stc_status st = check_ready(c, true);
+    if (st != STC_OK) return st;
+    if (repeats < 1 || repeats > 100 || !out) return fail(c, STC_ERR_INVALID_ARG, "repeats must be in [1, 100]");
+    st = stc_sync(c);
+    if (st != STC_OK) return st;
+    stc_launch_config best = shape_for(c, c->n);
+    if (c->n == 0) {
+        *out = best;
+        return STC_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(c, STC_ERR_DEVICE, "hipEventCreate failed");
+    }
+    hipStream_t s = c->stream;
+    EvalArgs a = eval_args(c);
+    bool ok = true;
+    auto timed = [&](auto launch) -> float {
+        launch();  // warm-up
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < repeats; ++r) launch();
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ok = false;
+        return ms / repeats;
+    };
+    const int threads[3] = {128, 256, 512};
+    const int per_cu[5] = {4, 8, 12, 16, 24};
+    float tn = 1e30f, tf = 1e30f;
+    for (int t : threads)
+        for (int b : per_cu) {
+            a.near_threads = t;
+            a.near_grid = grid_for(c, b);
+            const float ms = timed([&] { launch_near(s, a, 3u); });
+            if (ms < tn) {
+                tn = ms;
+                best.near_threads = t;
+                best.near_blocks_per_cu = b;
+            }
+            a.far_threads = t;
+            a.far_grid = grid_for(c, b);
+            const float mf = timed([&] { launch_far_targets(s, a); });
+            if (mf < tf) {
+                tf = mf;
+                best.far_threads = t;
+                best.far_blocks_per_cu = b;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st = check_launch(c, "autotune");
+    if (st != STC_OK) return st;
+    if (!ok) return fail(c, STC_ERR_DEVICE, "event timing failed");
+    c->shapes[size_class(c->n)] = best;
+    *out = best;
+    return STC_OK;
+}
+
 stc_status stc_sync(stc_ctx* c) {
     if (!c) return STC_ERR_INVALID_ARG;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, STC_ERR_DEVICE, "stream synchronisation failed");
     u32 h[C_COUNT];
-    u32 f[4];
+    u32 f[F_COUNT];
     if (hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(f, c->flags, sizeof(f), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, STC_ERR_DEVICE, "reading device flags failed");
     if (h[C_OVERFLOW] || h[C_TLIST] > c->cap || h[C_NLIST] > c->cap)
         return fail(c, STC_ERR_CAPACITY, "interaction list or frontier exceeded list_capacity");
-    if (f[0]) return fail(c, STC_ERR_INVALID_ARG, "non-finite particle position");
+    if (f[F_SLOTS]) return fail(c, STC_ERR_CAPACITY, "proxy storage slots exceeded");
+    if (f[F_NONFINITE]) return fail(c, STC_ERR_INVALID_ARG, "non-finite particle position");
     return STC_OK;
 }
 
@@ -674,16 +887,17 @@ stc_status stc_copy_tree(stc_ctx* c, int64_t n, int32_t* h_perm, int64_t node_ca
     if (st != STC_OK) return st;
     if (h_perm && n != c->n) return fail(c, STC_ERR_INVALID_ARG, "n differs from the built tree");
     if (h_count && node_cap < c->n_nodes) return fail(c, STC_ERR_INVALID_ARG, "node_cap too small");
+    const i64 un = c->used_nodes;
     st = stc_sync(c);
     if (st != STC_OK) return st;
     if (h_perm && n > 0 && hipMemcpy(h_perm, c->perm, n * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, STC_ERR_DEVICE, "copying perm failed");
     if (h_count) {
-        std::vector<i32> b(c->n_nodes), e(c->n_nodes);
-        if (hipMemcpy(b.data(), c->nbeg, c->n_nodes * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(e.data(), c->nend, c->n_nodes * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess)
+        std::vector<i32> b(un), e(un);
+        if (hipMemcpy(b.data(), c->nbeg, un * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(e.data(), c->nend, un * sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess)
             return fail(c, STC_ERR_DEVICE, "copying node ranges failed");
-        for (i64 i = 0; i < c->n_nodes; ++i) h_count[i] = e[i] - b[i];
+        for (i64 i = 0; i < c->n_nodes; ++i) h_count[i] = i < un ? e[i] - b[i] : 0;
     }
     return STC_OK;
 }
@@ -692,7 +906,7 @@ stc_status stc_copy_proxy_charges(stc_ctx* c, int64_t node_id, double* h_w) {
     stc_status st = check_ready(c, false);
     if (st != STC_OK) return st;
     if (!c->have_upward) return fail(c, STC_ERR_STATE, "call stc_upward first");
-    if (node_id < 0 || node_id >= c->n_nodes || !h_w) return fail(c, STC_ERR_INVALID_ARG, "bad node id or buffer");
+    if (node_id < 0 || node_id >= c->used_nodes || !h_w) return fail(c, STC_ERR_INVALID_ARG, "bad node id or buffer");
     st = stc_sync(c);
     if (st != STC_OK) return st;
     i32 b = 0, e = 0;
@@ -703,9 +917,11 @@ stc_status stc_copy_proxy_charges(stc_ctx* c, int64_t node_id, double* h_w) {
         for (int m = 0; m < c->np; ++m) h_w[m] = 0.0;
         return STC_OK;
     }
+    i32 sl = -1;
+    if (hipMemcpy(&sl, c->slot + node_id, sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess || sl < 0)
+        return fail(c, STC_ERR_DEVICE, "copy failed");
     std::vector<Prox> pr(c->np);
-    if (hipMemcpy(pr.data(), c->prox + (size_t)node_id * c->np, c->np * sizeof(Prox), hipMemcpyDeviceToHost) !=
-        hipSuccess)
+    if (hipMemcpy(pr.data(), c->prox + (size_t)sl * c->np, c->np * sizeof(Prox), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, STC_ERR_DEVICE, "copy failed");
     for (int m = 0; m < c->np; ++m) h_w[m] = pr[m].w;
     return STC_OK;
@@ -713,7 +929,9 @@ stc_status stc_copy_proxy_charges(stc_ctx* c, int64_t node_id, double* h_w) {
 
 stc_status stc_node_geometry(const stc_ctx* c, int64_t node_id, double* h_v9, double* h_c3, double* h_r) {
     if (!c || node_id < 0 || node_id >= c->n_nodes) return STC_ERR_INVALID_ARG;
-    const NodeGeo& g = c->geo_host[node_id];
+    const i64 local = node_id & (((i64)1 << c->NB) - 1);
+    if (local >= c->n_local) return STC_ERR_INVALID_ARG;
+    const NodeGeo& g = c->geo_host[local];
     if (h_v9)
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) h_v9[3 * a + b] = g.v[a][b];

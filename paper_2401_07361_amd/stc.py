@@ -18,6 +18,7 @@ FP64, FP32 = 0, 1
 DEN_DOT, DEN_DIST2 = 0, 1
 PP, PC, CP, CC = 0, 1, 2, 3
 FLAG_EAGER_RK4 = 1
+MAX_MEMBERS = 64
 LIST_NAMES = ("PP", "PC", "CP", "CC")
 
 
@@ -31,6 +32,14 @@ class Params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("degree", ctypes.c_int32), ("n_crit", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("precision", ctypes.c_int32), ("denominator", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("near_threads", ctypes.c_int32), ("near_blocks_per_cu", ctypes.c_int32),
+                ("far_threads", ctypes.c_int32), ("far_blocks_per_cu", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.near_threads, self.near_blocks_per_cu, self.far_threads, self.far_blocks_per_cu)
 
 
 def _load():
@@ -49,6 +58,14 @@ def _load():
         "stc_total_nodes": (I64, [I32]),
         "stc_default_max_level": (I32, [I64, I32]),
         "stc_create": (I32, [ctypes.POINTER(Params), I64, VP, ctypes.POINTER(P)]),
+        "stc_create_batched": (I32, [ctypes.POINTER(Params), I32, I64, I64, VP, ctypes.POINTER(P)]),
+        "stc_node_layout": (I32, [P, PI32, PI64, PI64]),
+        "stc_tree_build_batched": (I32, [P, I32, PI64, VP]),
+        "stc_velocity_batched": (I32, [P, I32, PI64, VP, VP, VP, VP]),
+        "stc_rk4_batched": (I32, [P, I32, PI64, VP, VP, VP, D, D, I32]),
+        "stc_get_launch_config": (I32, [P, I64, ctypes.POINTER(LaunchConfig)]),
+        "stc_set_launch_config": (I32, [P, I64, ctypes.POINTER(LaunchConfig)]),
+        "stc_autotune": (I32, [P, I32, ctypes.POINTER(LaunchConfig)]),
         "stc_destroy": (I32, [P]),
         "stc_set_stream": (I32, [P, VP]),
         "stc_get_params": (I32, [P, ctypes.POINTER(Params)]),
@@ -183,11 +200,22 @@ def direct(x, zeta, area, targets=None, precision="fp64", denominator="dot", out
     return out
 
 
+def _offsets(offsets, n_rows):
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or off.size < 2 or off[0] != 0 or off[-1] != n_rows:
+        raise ValueError("offsets must be [0, ..., n] with n the number of rows")
+    return off, off.size - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
 class Context:
-    """A tree-code context for up to n_max particles (stc_create)."""
+    """A tree-code context for up to n_max particles (stc_create), or, with
+    members > 1, for an ensemble of up to `members` particle sets with
+    n_max particles in total and up to n_max_member each
+    (stc_create_batched)."""
 
     def __init__(self, n_max, theta=0.7, degree=8, n_crit=64, max_level=-1, precision="fp64",
-                 denominator="dot", list_capacity=0, stream=None, eager_rk4=False):
+                 denominator="dot", list_capacity=0, stream=None, eager_rk4=False, members=1,
+                 n_max_member=None):
         p = Params()
         _lib.stc_default_params(ctypes.byref(p))
         p.theta, p.degree, p.n_crit, p.max_level = theta, degree, n_crit, max_level
@@ -195,14 +223,18 @@ class Context:
         p.precision, p.denominator, p.list_capacity = _prec(precision), _den(denominator), list_capacity
         self._ctx = ctypes.c_void_p()
         self._stream_obj = stream
-        _check(_lib.stc_create(ctypes.byref(p), n_max, _stream(stream), ctypes.byref(self._ctx)))
+        nmm = n_max if n_max_member is None else n_max_member
+        _check(_lib.stc_create_batched(ctypes.byref(p), members, nmm, n_max, _stream(stream), ctypes.byref(self._ctx)))
         q = Params()
         _lib.stc_get_params(self._ctx, ctypes.byref(q))
         self.theta, self.degree, self.n_crit, self.max_level = q.theta, q.degree, q.n_crit, q.max_level
         self.precision, self.denominator = q.precision, q.denominator
         self.n_max = n_max
         self.np = n_basis(q.degree)
-        self.n_nodes = total_nodes(q.max_level)
+        nb, npm, nlen = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _lib.stc_node_layout(self._ctx, ctypes.byref(nb), ctypes.byref(npm), ctypes.byref(nlen))
+        self.node_bits, self.nodes_per_member, self.n_nodes = nb.value, npm.value, nlen.value
+        self.members = members
         self._keep = None
         self.n = None
 
@@ -271,6 +303,61 @@ class Context:
         self._keep = x
         self.n = n
         return out
+
+    # ensembles -----------------------------------------------------------------------
+    def tree_build_batched(self, x, offsets):
+        import torch
+        n = x.shape[0]
+        off, m, poff = _offsets(offsets, n)
+        _check(_lib.stc_tree_build_batched(self._ctx, m, poff, _dptr(x, "x", torch.float64, 3 * n)), self._ctx)
+        self._keep = x
+        self.n = n
+
+    def velocity_batched(self, x, zeta, area, offsets, out=None):
+        """Velocities of all members; x (n,3), zeta, area (n,) concatenated,
+        member m = rows offsets[m]:offsets[m+1]."""
+        import torch
+        n = x.shape[0]
+        off, m, poff = _offsets(offsets, n)
+        if out is None:
+            out = torch.empty((n, 3), dtype=torch.float64, device=x.device)
+        st = _lib.stc_velocity_batched(self._ctx, m, poff, _dptr(x, "x", torch.float64, 3 * n),
+                                       _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n),
+                                       _dptr(out, "out", torch.float64, 3 * n))
+        _check(st, self._ctx)
+        self._keep = x
+        self.n = n
+        return out
+
+    def rk4_batched(self, x, zeta, area, offsets, dt, omega, n_steps):
+        import torch
+        n = x.shape[0]
+        off, m, poff = _offsets(offsets, n)
+        st = _lib.stc_rk4_batched(self._ctx, m, poff, _dptr(x, "x", torch.float64, 3 * n),
+                                  _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n),
+                                  float(dt), float(omega), int(n_steps))
+        _check(st, self._ctx)
+
+    def member_of_node(self, node_id):
+        return np.asarray(node_id) >> self.node_bits
+
+    def local_node(self, node_id):
+        return np.asarray(node_id) & ((1 << self.node_bits) - 1)
+
+    # launch shapes -----------------------------------------------------------------
+    def launch_config(self, n_total):
+        c = LaunchConfig()
+        _check(_lib.stc_get_launch_config(self._ctx, int(n_total), ctypes.byref(c)), self._ctx)
+        return c.as_tuple()
+
+    def set_launch_config(self, n_total, near_threads, near_blocks_per_cu, far_threads, far_blocks_per_cu):
+        c = LaunchConfig(near_threads, near_blocks_per_cu, far_threads, far_blocks_per_cu)
+        _check(_lib.stc_set_launch_config(self._ctx, int(n_total), ctypes.byref(c)), self._ctx)
+
+    def autotune(self, repeats=3):
+        c = LaunchConfig()
+        _check(_lib.stc_autotune(self._ctx, int(repeats), ctypes.byref(c)), self._ctx)
+        return c.as_tuple()
 
     def rk4(self, x, zeta, area, dt, omega, n_steps):
         import torch

@@ -13,13 +13,19 @@ conditions; no dataset exists or is needed):
                dt = 1800 s.
 * ``gvpair_l9`` N = 2621442 (level 9), RH n = 4 background plus a +/- vortex
                pair of amplitude 4 pi per day.
+
+``make_ensemble`` builds the ensemble workload: members with seeds 4 + m, each
+an icosahedral grid of level 5, 6 or 7 (N = 10242, 40962, 163842) under a
+random rotation, node-patch areas, a Rossby-Haurwitz wave of wavenumber 3, 4
+or 5 plus a Gaussian bump 1e-6 exp(-(d/0.1)^2) s^-1 at a random centre; RK4
+with dt = 1800 s for 24 steps.
 """
 
 import numpy as np
 
 from .grids import (icosahedral_grid, uniform_areas, node_patch_areas,
                     subset_indices, random_rotation)
-from .fields import rossby_haurwitz, gaussian_vortex, gaussian_pair
+from .fields import rossby_haurwitz, gaussian_vortex, gaussian_pair, great_circle_distance
 
 WORKLOADS = ("rh4_l5", "gv_l8", "rh4_l7", "gvpair_l9")
 
@@ -68,3 +74,38 @@ def make_workload(name, level=None):
                     area=uniform_areas(n), subset=np.arange(n),
                     theta=0.7, degree=6, seed=11)
     raise KeyError(name)
+
+
+_GRID_CACHE = {}
+
+
+def _grid_with_areas(level):
+    if level not in _GRID_CACHE:
+        x, faces = icosahedral_grid(level, return_faces=True)
+        _GRID_CACHE[level] = (x, node_patch_areas(x, faces))
+    return _GRID_CACHE[level]
+
+
+def make_member(m, seed0=4, levels=(5, 6, 7)):
+    """Member m of the ensemble workload (see the module docstring)."""
+    seed = seed0 + m
+    rng = np.random.Generator(np.random.PCG64(seed))
+    level = int(rng.choice(levels))
+    n_wave = int(rng.integers(3, 6))
+    c = rng.standard_normal(3)
+    c /= np.linalg.norm(c)
+    x0, a = _grid_with_areas(level)
+    x = x0 @ random_rotation(seed).T
+    z = rossby_haurwitz(x, n_wave) + 1e-6 * np.exp(-(great_circle_distance(x, c) / 0.1) ** 2)
+    return dict(x=x, zeta=z, area=a.copy(), level=level, n_wave=n_wave, seed=seed)
+
+
+def make_ensemble(members=48, seed0=4, levels=(5, 6, 7)):
+    """Concatenated ensemble: x (N,3), zeta, area (N,), offsets (members+1,)
+    and the per-member records."""
+    mem = [make_member(m, seed0, levels) for m in range(members)]
+    off = np.zeros(members + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(r["x"]) for r in mem])
+    return dict(x=np.concatenate([r["x"] for r in mem]), zeta=np.concatenate([r["zeta"] for r in mem]),
+                area=np.concatenate([r["area"] for r in mem]), offsets=off, members=mem,
+                dt=1800.0, steps=24)
