@@ -7,6 +7,12 @@ the FP64 direct sum on 4096 seeded targets.
 One step = one full velocity evaluation (tree build, upward pass, traversal,
 near and far field, output) on inputs already resident in HBM.  Prints one
 JSON line.  Single GPU only.
+
+``--workload ensemble`` times the batching form instead: 48 seeded members
+(levels 5-7, 3.87e6 particles in total, random rotations, RH waves of
+wavenumber 3-5 plus a Gaussian bump), all members in one launch per phase,
+against the same members evaluated one context after the other; it also
+times graph-captured RK4 steps of the whole ensemble.
 """
 
 import argparse
@@ -98,6 +104,98 @@ def cpu_baseline(x, z, a, subset, budget_s=15.0):
                        f"{dt:.1f} s wall"), sample, u
 
 
+ENS_THETA, ENS_DEGREE, ENS_N_CRIT = 0.7, 8, 64
+
+
+def bench_ensemble(args):
+    import torch
+    import synthetic as S
+    from paper_2401_07361_amd import stc
+
+    ens = S.make_ensemble()
+    off = ens["offsets"]
+    M, N = len(off) - 1, int(off[-1])
+    log(f"workload ensemble members={M} N={N} theta={ENS_THETA} d={ENS_DEGREE} n_crit={ENS_N_CRIT} fp32")
+    x, z, a = (torch.from_numpy(ens[k]).cuda() for k in ("x", "zeta", "area"))
+    out = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    kw = dict(theta=ENS_THETA, degree=ENS_DEGREE, n_crit=ENS_N_CRIT, precision="fp32", denominator="dist2")
+    ctx = stc.Context(N, members=M, n_max_member=int(np.diff(off).max()), **kw)
+    ctx.velocity_batched(x, z, a, off, out=out)
+    shape = ctx.autotune(repeats=3)
+    log(f"autotuned launch shape {shape}")
+    for _ in range(args.warmup):
+        ctx.velocity_batched(x, z, a, off, out=out)
+    ctx.set_timing(args.steps)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        ctx.velocity_batched(x, z, a, off, out=out)
+    t1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms = t0.elapsed_time(t1) / args.steps
+    phases, k = ctx.phase_times()
+    phase_ms = {p: round(v / max(k, 1), 4) for p, v in phases.items()}
+    counts, evals = ctx.list_counts()
+    log(f"batched: {ms:.3f} ms per ensemble evaluation; phases {phase_ms}")
+    # accuracy: 64 seeded targets per member against that member's FP64 direct sum
+    worst = 0.0
+    un = out.cpu().numpy()
+    for m in range(M):
+        lo, hi = int(off[m]), int(off[m + 1])
+        tg = np.random.default_rng(100 + m).choice(hi - lo, 64, replace=False)
+        ref = stc.direct(x[lo:hi], z[lo:hi], a[lo:hi], targets=torch.from_numpy(tg.astype(np.int64)).cuda(),
+                         denominator="dist2").cpu().numpy()
+        got = un[lo:hi][tg]
+        worst = max(worst, float(np.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum())))
+    # the same members one context at a time (one launch sequence per member)
+    singles = [stc.Context(int(off[m + 1] - off[m]), max_level=ctx.max_level, **kw) for m in range(M)]
+    views = [(x[int(off[m]):int(off[m + 1])], z[int(off[m]):int(off[m + 1])], a[int(off[m]):int(off[m + 1])],
+              out[int(off[m]):int(off[m + 1])]) for m in range(M)]
+    for c, (xv, zv, av, ov) in zip(singles, views):
+        c.velocity(xv, zv, av, out=ov)
+    torch.cuda.synchronize()
+    seq_steps = max(1, args.steps // 4)
+    t0.record()
+    for _ in range(seq_steps):
+        for c, (xv, zv, av, ov) in zip(singles, views):
+            c.velocity(xv, zv, av, out=ov)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_seq = t0.elapsed_time(t1) / seq_steps
+    for c in singles:
+        c.close()
+    log(f"one member at a time: {ms_seq:.3f} ms per ensemble evaluation")
+    # graph-captured RK4 steps of the whole ensemble (dt = 1800 s)
+    xr, zr = x.clone(), z.clone()
+    ctx.rk4_batched(xr, zr, a, off, ens["dt"], S.OMEGA_EARTH_S, 1)
+    torch.cuda.synchronize()
+    rk_steps = max(1, args.steps // 4)
+    t0.record()
+    ctx.rk4_batched(xr, zr, a, off, ens["dt"], S.OMEGA_EARTH_S, rk_steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms_rk = t0.elapsed_time(t1) / rk_steps
+    ctx.sync()
+    log(f"rk4 step (4 evaluations, one graph): {ms_rk:.3f} ms")
+    ctx.close()
+    result = dict(
+        metric="ensemble particle velocity evals/s (48 members, one launch per phase)",
+        value=N / (ms / 1e3), unit="velocity evals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload="ensemble (48 members, icosahedral levels 5-7, RH n=3-5 + Gaussian bump)",
+                    members=M, N=N, theta=ENS_THETA, degree=ENS_DEGREE, n_crit=ENS_N_CRIT,
+                    max_level=int(ctx.max_level), precision="fp32", denominator="dist2",
+                    launch_shape=list(shape), worst_member_rel_l2_err_vs_fp64_direct=float(f"{worst:.3e}"),
+                    lists=counts, kernel_evals=int(sum(evals.values())), phase_ms=phase_ms,
+                    ms_one_member_at_a_time=round(ms_seq, 4), batching_speedup=round(ms_seq / ms, 3),
+                    ms_per_rk4_step=round(ms_rk, 4)),
+    )
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +207,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble"])
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -116,6 +215,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ensemble":
+        bench_ensemble(args)
+        return
 
     import torch
     import synthetic as S
