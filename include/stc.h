@@ -51,7 +51,8 @@ typedef enum stc_status {
 enum { STC_FP64 = 0, STC_FP32 = 1 };           /* arithmetic of the PP/PC/CP/CC sums   */
 enum { STC_DEN_DOT = 0, STC_DEN_DIST2 = 1 };   /* 1 - x.y (Sec. 2) | |x-y|^2/2 (Sec. 2, alt. kernel) */
 enum { STC_LIST_PP = 0, STC_LIST_PC = 1, STC_LIST_CP = 2, STC_LIST_CC = 3 };
-enum { STC_FLAG_EAGER_RK4 = 1 };              /* stc_rk4 without graph capture */
+enum { STC_FLAG_EAGER_RK4 = 1,                /* stc_rk4 without graph capture */
+       STC_FLAG_LEARNED = 2 };                /* learned gating (see stc_set_model) */
 enum { STC_MAX_MEMBERS = 64 };                /* members of one batched context */
 
 /* Method parameters (Sec. 3, dual tree traversal).
@@ -67,9 +68,20 @@ enum { STC_MAX_MEMBERS = 64 };                /* members of one batched context 
  *              target-relative coordinates and FP64 accumulation per tile;
  *              proxy charges, interpolation weights and the output stay FP64.
  *  denominator STC_DEN_DOT or STC_DEN_DIST2.
- *  flags       0, or STC_FLAG_EAGER_RK4.
+ *  flags       0 or a combination of STC_FLAG_EAGER_RK4, STC_FLAG_LEARNED.
  *  list_capacity entries per interaction list and per traversal frontier;
- *              0 for the default (16 * n_max, at least 65536).            */
+ *              0 for the default (16 * n_max, at least 65536).
+ *  theta_max   learned form only: the wider acceptance parameter whose
+ *              separated pairs the network judges (0 = theta).  [theta, 1].
+ *
+ * The learned form (STC_FLAG_LEARNED; one member): far-field interactions are
+ * evaluated per list entry at one of four degrees, 4, 6, 8 or 10 (classes
+ * 0..3), and `degree` (one of these) is the fallback degree.  The traversal
+ * first collects candidate pairs -- well separated at theta_max with a side
+ * of more than n_crit particles -- and a network (stc_set_model) accepts each
+ * at a degree class or rejects it; rejected pairs are traversed by the plain
+ * method (theta, the fallback degree) from there on, so without a model the
+ * result is that of the fixed-degree method.                                */
 typedef struct stc_params {
     double theta;
     int32_t degree;
@@ -79,6 +91,7 @@ typedef struct stc_params {
     int32_t denominator;
     int32_t flags;
     int64_t list_capacity;
+    double theta_max;
 } stc_params;
 
 typedef struct stc_ctx stc_ctx;
@@ -224,6 +237,83 @@ stc_status stc_rk4(stc_ctx* ctx, int64_t n, double* d_x, double* d_zeta, const d
 stc_status stc_rk4_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offsets, double* d_x,
                            double* d_zeta, const double* d_area, double dt, double omega,
                            int32_t n_steps);
+
+/* --- the learned form: gating network ---------------------------------------
+ *
+ * Network: 12 inputs -> 64 -> 64 -> 4 outputs, ReLU, BF16 weights and
+ * activations, FP32 accumulation on the matrix cores.  Parameters are one
+ * flat BF16 vector of stc_mlp_param_count() = 5252 values: W1 [12][64]
+ * (input f -> hidden h, row-major), b1 [64], W2 [64][64], b2 [64], W3 [64][4],
+ * b3 [4].  Inputs: rows of 16 BF16 features (the 12 below, then 4 zeros).
+ * Outputs per row: o0 acceptance logit, o1..o3 ordinal logits ("degree above
+ * 4", "above 6", "above 8"); a pair is accepted iff o0 > 0, at degree class
+ * #{k : o_k > 0}.  Features of a candidate (t, s), R the chord between the
+ * circumcentres, r the circumradii, Q_x the sum of |q| over node x, Q over all
+ * particles:  log2 n_t / 16, log2 n_s / 16, level_t / 8, level_s / 8, r_t/R,
+ * r_s/R, (r_t + r_s)/R, -log10 R / 2, log10(Q_s/Q)/8 + 1, |sum_s q|/Q_s,
+ * log10(|w_s^(4)|_1 / Q_s)/2 (degree-4 proxy charges; 0 for a small source),
+ * log10(Q_t/Q)/8 + 1.  Training loss per row: BCE(o0, y0) + y0 sum_k BCE(o_k,
+ * y_k) (labels y: accept, then the three ordinal targets).  */
+
+/* The BF16 parameters the traversal of a learned context uses (device
+ * pointer, 16-byte aligned, kept until replaced; NULL rejects every candidate,
+ * i.e. the fixed-degree method).  The caller keeps the buffer alive. */
+stc_status stc_set_model(stc_ctx* ctx, const uint16_t* d_params);
+
+/* Training samples from the current tree (after stc_tree_build and
+ * stc_upward of a learned context): the candidates of theta_max, their
+ * features (d_features: cap x 16 BF16), for each degree class the largest
+ * error over the target particles of the interaction the pair would get at
+ * that degree against the exact pair sum (d_errors: cap x 4 FP64, W units:
+ * the sum before the cross product), and labels (d_labels: cap x 4 float):
+ * accept iff some class has error <= abs_tol, ordinal targets from the
+ * smallest such class.  *n_out = number of candidates (samples beyond cap are
+ * dropped and STC_ERR_CAPACITY returned).  Synchronises.  The lists of the
+ * context are invalid afterwards (evaluate again). */
+stc_status stc_learned_samples(stc_ctx* ctx, double abs_tol, int64_t cap, uint16_t* d_features,
+                               float* d_labels, double* d_errors, int64_t* n_out);
+
+/* Introspection after a learned traversal or stc_learned_samples: candidate
+ * pairs (2 x int64 each, in the order of the sample arrays), network outputs
+ * (4 floats; written only when a model is set) and features (16 BF16; after
+ * a traversal only when a model is set); any may be NULL.  Synchronises. */
+stc_status stc_copy_candidates(stc_ctx* ctx, int64_t cap, int64_t* h_pairs, float* h_out,
+                               uint16_t* h_feat, int64_t* n_out);
+
+/* Degree class (0..3) of every entry of list `type`, in stc_copy_list order
+ * (all 0 for a single-degree context). */
+stc_status stc_copy_list_classes(stc_ctx* ctx, int32_t type, int64_t cap, int32_t* h_class,
+                                 int64_t* n_out);
+
+int32_t stc_mlp_param_count(void);
+
+/* Device workspace bytes stc_mlp_grad / stc_mlp_train need for a batch. */
+int64_t stc_mlp_workspace_bytes(int64_t n_batch);
+
+/* Network outputs (n x 4 float) for n input rows; asynchronous on hip_stream.
+ * d_x, d_out 16-byte aligned. */
+stc_status stc_mlp_forward(void* hip_stream, int64_t n, const uint16_t* d_x, const uint16_t* d_params,
+                           float* d_out);
+
+/* Gradient (5252 floats, FP32) and loss (1 float) of the mean training loss
+ * over the n rows d_index[0..n) of (d_x, d_y) (d_index NULL: rows 0..n);
+ * d_y: rows of 4 floats.  The sum over rows runs in a fixed order. */
+stc_status stc_mlp_grad(void* hip_stream, int64_t n, const int32_t* d_index, const uint16_t* d_x,
+                        const float* d_y, const uint16_t* d_params, float* d_ws, int64_t ws_bytes,
+                        float* d_grad, float* d_loss);
+
+/* Adam training on the GPU: `epochs` passes over the n_samples rows in
+ * minibatches of `batch` (a seeded bijection of the rows per epoch), each
+ * step a gradient (as stc_mlp_grad) and an Adam update (beta 0.9, 0.999,
+ * eps 1e-8, learning rate lr) of the FP32 master weights d_master with
+ * moments d_m1, d_m2 (5252 floats each, zero at the start of training), whose
+ * BF16 copy is written to d_params.  d_index: batch int32 of scratch.  d_loss
+ * (optional): one float per step, the minibatch loss before the step.
+ * Asynchronous on hip_stream. */
+stc_status stc_mlp_train(void* hip_stream, int64_t n_samples, const uint16_t* d_x, const float* d_y,
+                         int32_t epochs, int32_t batch, float lr, uint64_t seed, float* d_master,
+                         float* d_m1, float* d_m2, uint16_t* d_params, int32_t* d_index, float* d_ws,
+                         int64_t ws_bytes, float* d_loss);
 
 /* --- launch shapes ------------------------------------------------------------ */
 

@@ -1,0 +1,124 @@
+"""O5a: the learned form's network in plain NumPy.  TEST INFRASTRUCTURE ONLY.
+
+The network: 12 inputs -> 64 -> 64 -> 4 outputs with ReLU hidden layers.
+Parameters are one flat vector of 5252 values: W1 [12][64] (input f to hidden
+h), b1 [64], W2 [64][64], b2 [64], W3 [64][4], b3 [4].  Outputs: o0 the
+acceptance logit, o1..o3 ordinal logits (degree above 4, 6, 8).  Loss per
+row, averaged over the batch:
+    BCE(o0, y0) + y0 * sum_{k=1..3} BCE(o_k, y_k),
+BCE(o, y) = max(o, 0) - o y + log(1 + exp(-|o|)) (logits), so the ordinal
+targets count only where the pair is acceptable.
+
+Everything is FP64.  `act_round`, when given, is applied to the hidden
+activations and to the back-propagated pre-activation gradients, the places
+where the GPU kernels round to BF16 before a matrix product; it lets a test
+compare against the kernels' own precision (decisions that depend on a
+rounded value are taken in the precision of the kernel).
+"""
+
+import numpy as np
+
+N_IN, N_H, N_OUT = 12, 64, 4
+SLICES = {
+    "W1": (0, (12, 64)), "b1": (768, (64,)), "W2": (832, (64, 64)),
+    "b2": (4928, (64,)), "W3": (4992, (64, 4)), "b3": (5248, (4,)),
+}
+N_PARAMS = 5252
+
+
+def unpack(theta):
+    theta = np.asarray(theta, dtype=np.float64)
+    return {k: theta[o:o + int(np.prod(s))].reshape(s) for k, (o, s) in SLICES.items()}
+
+
+def pack(p):
+    out = np.zeros(N_PARAMS)
+    for k, (o, s) in SLICES.items():
+        out[o:o + int(np.prod(s))] = np.asarray(p[k], dtype=np.float64).ravel()
+    return out
+
+
+def bf16_round(a):
+    """Round float values to BF16 (round to nearest, ties to even) and back."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def bf16_bits(a):
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def from_bf16_bits(b):
+    return (np.asarray(b, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def forward(theta, x, act_round=None):
+    """x (n, 12 or 16) -> outputs (n, 4) and the intermediate values."""
+    p = unpack(theta)
+    x = np.asarray(x, dtype=np.float64)[:, :N_IN]
+    r = act_round if act_round is not None else (lambda v: v)
+    z1 = x @ p["W1"] + p["b1"]
+    h1 = r(np.maximum(z1, 0.0))
+    z2 = h1 @ p["W2"] + p["b2"]
+    h2 = r(np.maximum(z2, 0.0))
+    o = h2 @ p["W3"] + p["b3"]
+    return o, dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2)
+
+
+def bce(o, y):
+    return np.maximum(o, 0.0) - o * y + np.log1p(np.exp(-np.abs(o)))
+
+
+def loss(theta, x, y, act_round=None):
+    o, _ = forward(theta, x, act_round)
+    y = np.asarray(y, dtype=np.float64)
+    per = bce(o[:, 0], y[:, 0]) + y[:, 0] * bce(o[:, 1:], y[:, 1:]).sum(1)
+    return float(per.mean())
+
+
+def _sigmoid(o):
+    return 0.5 * (1.0 + np.tanh(0.5 * o))
+
+
+def grad(theta, x, y, act_round=None):
+    """Gradient of `loss` with respect to the flat parameters (chain rule
+    written out layer by layer)."""
+    p = unpack(theta)
+    o, c = forward(theta, x, act_round)
+    y = np.asarray(y, dtype=np.float64)
+    n = len(o)
+    r = act_round if act_round is not None else (lambda v: v)
+    d3 = np.empty_like(o)
+    d3[:, 0] = (_sigmoid(o[:, 0]) - y[:, 0]) / n
+    d3[:, 1:] = y[:, :1] * (_sigmoid(o[:, 1:]) - y[:, 1:]) / n
+    d3r = r(d3)
+    g = {"W3": c["h2"].T @ d3r, "b3": d3.sum(0)}
+    d2 = (d3r @ p["W3"].T) * (c["z2"] > 0)
+    d2r = r(d2)
+    g["W2"] = c["h1"].T @ d2r
+    g["b2"] = d2.sum(0)
+    d1 = (d2r @ p["W2"].T) * (c["z1"] > 0)
+    d1r = r(d1)
+    g["W1"] = c["x"].T @ d1r
+    g["b1"] = d1.sum(0)
+    return pack(g)
+
+
+def decide(outputs):
+    """(accept, degree class) from network outputs: accept iff o0 > 0; class
+    = number of positive ordinal logits."""
+    o = np.asarray(outputs)
+    return o[:, 0] > 0, (o[:, 1:] > 0).sum(1)
+
+
+def init_params(seed):
+    """He-style random initialisation (used as a starting point in tests)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = {"W1": rng.standard_normal((12, 64)) * np.sqrt(2.0 / 12), "b1": np.zeros(64),
+         "W2": rng.standard_normal((64, 64)) * np.sqrt(2.0 / 64), "b2": np.zeros(64),
+         "W3": rng.standard_normal((64, 4)) * np.sqrt(2.0 / 64), "b3": np.zeros(4)}
+    return pack(p)

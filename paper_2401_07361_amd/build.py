@@ -36,6 +36,8 @@ SOURCES = [
     ("k_sort.hip", [], True),
     ("k_tree.hip", ["-ffp-contract=off"], True),
     ("k_eval.hip", [], True),
+    ("k_mlp.hip", [], True),
+    ("k_learned.hip", [], True),
     ("stc_api.hip", [], True),
 ]
 

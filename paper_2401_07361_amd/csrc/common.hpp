@@ -9,6 +9,7 @@
 
 namespace stc {
 
+using u16 = uint16_t;
 using u32 = uint32_t;
 using u64 = uint64_t;
 using i32 = int32_t;
@@ -45,8 +46,10 @@ enum Counter : int {
     C_NLIST = 1,      // entries in the target-proxy list (CP + CC)
     C_PP = 2, C_PC = 3, C_CP = 4, C_CC = 5,
     C_OVERFLOW = 6,   // set to 1 when any list or frontier outgrows capacity
+    C_CAND = 7,       // candidate pairs of a gated traversal
     C_FRONT = 16,     // C_FRONT + k: frontier length at traversal iteration k
-    C_COUNT = 64
+    C_FRONT2 = 64,    // the same for the fallback traversal of rejected candidates
+    C_COUNT = 128
 };
 
 // An interpolation point of a node with its proxy charge (written by the

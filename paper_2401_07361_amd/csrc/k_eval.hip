@@ -126,7 +126,8 @@ __device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* wave_tot, u32* t
 }
 
 // One source point relative to (cx, cy, cz), charge scaled by qscale: point l
-// of particle range `first`, or (first < 0) proxy point l of storage slot s.
+// of particle range `first`, or (first < 0) proxy record s + l (s: first
+// record of the source node's degree class).
 template <typename T>
 __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 first, int l, double cx, double cy,
                                               double cz, double qscale) {
@@ -138,7 +139,7 @@ __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 firs
         v.z = (T)(a.sz[j] - cz);
         v.q = (T)(qscale * a.sq[j]);
     } else {
-        const Prox pr = a.prox[(size_t)s * a.ref.np + l];
+        const Prox pr = a.prox[(size_t)s + l];
         v.x = (T)(pr.x - cx);
         v.y = (T)(pr.y - cy);
         v.z = (T)(pr.z - cz);
@@ -160,6 +161,7 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                                    double cy, double cz, SegShared<T, NTT>& sh, double& ax, double& ay, double& az) {
     const int tid = threadIdx.x;
     const u64 mask = ((u64)1 << a.W) - 1;
+    const u32 cmask = (1u << a.DB) - 1u;
     const double qscale = (DEN == STC_DEN_DIST2) ? 2.0 : 1.0;
     for (u32 eb = e0; eb < e1; eb += NTT) {
         const u32 ne = (e1 - eb) < (u32)NTT ? (e1 - eb) : (u32)NTT;
@@ -178,9 +180,10 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                     if (s == self_t) sh.self_flag = 1;
                     else size = (u32)(a.nend[s] - b);
                 } else {
-                    sh.ent_s[tid] = (u32)a.slot[s];
+                    const int c = (int)((key >> (a.W + 1)) & cmask);
+                    sh.ent_s[tid] = (u32)a.slot[s] * (u32)a.NPT + (u32)STC_PICK4(a.cls.poff, c);
                     sh.ent_first[tid] = -1;
-                    size = (u32)a.ref.np;
+                    size = (u32)STC_PICK4(a.cls.np, c);
                 }
             } else {
                 sh.ent_first[tid] = 0;
@@ -222,15 +225,15 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
     }
 }
 
-// range of list entries of this workgroup; returns false if empty
-__device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int W, u32& e, u32& e_hi) {
+// range of list entries of this workgroup (segments: key >> sh); returns
+// false if empty
+__device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int sh, u32& e, u32& e_hi) {
     const u32 G = gridDim.x;
     const u32 chunk = (n + G - 1) / G;
     const u64 lo = (u64)logical_block() * chunk;
     if (lo >= n) return false;
     e = (u32)lo;
     e_hi = (u64)e + chunk < n ? e + chunk : n;
-    const int sh = W + 1;
     if (e > 0 && (list[e] >> sh) == (list[e - 1] >> sh)) e = (u32)seg_end[list[e] >> sh];
     return true;
 }
@@ -242,8 +245,8 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
     u32 n = a.counters[C_TLIST];
     if (n > a.cap) n = a.cap;
     u32 e, e_hi;
-    if (!wg_range(n, a.tlist, a.tseg_end, a.W, e, e_hi)) return;
-    const int shf = a.W + 1;
+    const int shf = a.W + 1 + a.DB;
+    if (!wg_range(n, a.tlist, a.tseg_end, shf, e, e_hi)) return;
     const bool rel = sizeof(T) == 4;  // FP32: coordinates relative to the target circumcentre
     while (e < e_hi) {
         const u32 t = (u32)(a.tlist[e] >> shf);
@@ -294,13 +297,16 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
     u32 n = a.counters[C_NLIST];
     if (n > a.cap) n = a.cap;
     u32 e, e_hi;
-    if (!wg_range(n, a.nlist, a.nseg_end, a.W, e, e_hi)) return;
-    const int shf = a.W + 1;
+    const int shf = a.W + 1;  // segments by (target, degree class)
+    if (!wg_range(n, a.nlist, a.nseg_end, shf, e, e_hi)) return;
     const bool rel = sizeof(T) == 4;
-    const int np = a.ref.np, d = a.ref.degree;
     while (e < e_hi) {
-        const u32 t = (u32)(a.nlist[e] >> shf);
-        const u32 se = (u32)a.nseg_end[t];
+        const u32 vt = (u32)(a.nlist[e] >> shf);
+        const u32 t = vt >> a.DB;
+        const int c = (int)(vt & ((1u << a.DB) - 1u));
+        const int np = STC_PICK4(a.cls.np, c), d = STC_PICK4(a.cls.deg, c);
+        const int poff = STC_PICK4(a.cls.poff, c), qoff = STC_PICK4(a.cls.qoff, c);
+        const u32 se = (u32)a.nseg_end[vt];
         const NodeGeo& gt = a.geo[t & a.node_mask];
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
         // target points in chunks of at most NTT/4, so that full chunks keep
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
             const bool act = sl < S;
             const int me = cb + ti;
             double y[3];
-            const double nrm = proxy_point(gt, a.ref.points + 3 * me, y);
+            const double nrm = proxy_point(gt, a.ref.points + 3 * (poff + me), y);
             if (act && sl == 0) nd[me] = ipow(nrm, d);
             const T tx = (T)(y[0] - cx), ty = (T)(y[1] - cy), tz = (T)(y[2] - cz);
             double ax = 0.0, ay = 0.0, az = 0.0;
@@ -336,9 +342,9 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
             __syncthreads();
         }
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
-        block_matvec<NTT, 3>(a.ref.vinvT, np, nd, wt, &sh.red[0][0], co);
-        const size_t ts = (size_t)a.slot[t];
-        for (int k = tid; k < 3 * np; k += NTT) a.alpha[ts * np * 3 + k] = co[k / 3][k % 3];
+        block_matvec<NTT, 3>(a.ref.vinvT + qoff, np, nd, wt, &sh.red[0][0], co);
+        const size_t ts = (size_t)a.slot[t] * a.NPT + poff;
+        for (int k = tid; k < 3 * np; k += NTT) a.alpha[ts * 3 + k] = co[k / 3][k % 3];
         __syncthreads();
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
     }
@@ -346,20 +352,86 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
 
 // Interpolation to the particles and output.  For every node t holding
 // particle i that received CP/CC work, W_i += sum_k B_k(b_t(x_i)) alpha_k(t)
-// (the target-side interpolation of Sec. 3); then u_i = -(1/4pi) x_i x W_i,
-// scattered to input order.  A workgroup takes 256 consecutive particles in
-// tree order and walks the levels; at each level its particles lie in a few
-// consecutive nodes, whose coefficients are staged in LDS (KS at a time) and
-// read from there by every particle of the node.
+// (the target-side interpolation of Sec. 3), per degree class; then
+// u_i = -(1/4pi) x_i x W_i, scattered to input order.  A workgroup takes 256
+// consecutive particles in tree order and walks the levels; at each level
+// its particles lie in a few consecutive nodes, whose coefficients are
+// staged in LDS (KS at a time) and read from there by every particle of the
+// node.
 constexpr int KS = 4;  // coefficient slots in LDS
 
-template <int D>
-__global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, double* __restrict__ u, int accumulate) {
+template <int NP>
+struct L2PShared {
+    double al[KS][NP][3];
+    i64 slot_node[256];
+    i32 slot_store[256];
+    u32 wtot[4];
+};
+
+// class `cls` (degree D) of node nd (local id ndl) for this thread's particle
+template <int D, int NPM>
+__device__ __forceinline__ void l2p_class(const EvalArgs& a, int cls, bool valid, i64 nd, i64 ndl, double x0,
+                                          double x1, double x2, double& W0, double& W1, double& W2,
+                                          L2PShared<NPM>& sh) {
     constexpr int NP = (D + 1) * (D + 2) / 2;
-    __shared__ double al[KS][NP][3];
-    __shared__ i64 slot_node[256];
-    __shared__ i32 slot_store[256];
-    __shared__ u32 wtot[4];
+    const int tid = threadIdx.x;
+    const int poff = STC_PICK4(a.cls.poff, cls);
+    const bool has = valid && a.nseg_end[(nd << a.DB) | cls] != 0;
+    // the first particle of each node with far work opens a slot
+    sh.slot_node[tid] = has ? nd : (i64)-1;
+    __syncthreads();
+    const bool first = has && (tid == 0 || sh.slot_node[tid - 1] != nd);
+    u32 nslots = 0;
+    const u32 before = block_exclusive_scan<256>(first ? 1u : 0u, sh.wtot, &nslots);
+    const int my_slot = has ? (int)(before + (first ? 1u : 0u)) - 1 : -1;
+    __syncthreads();
+    if (first) {
+        sh.slot_node[my_slot] = nd;
+        sh.slot_store[my_slot] = a.slot[nd];
+    }
+    __syncthreads();
+    for (u32 s0 = 0; s0 < nslots; s0 += KS) {
+        const int ns = (nslots - s0) < (u32)KS ? (int)(nslots - s0) : KS;
+        for (int k = tid; k < ns * NP * 3; k += 256) {
+            const int sl = k / (NP * 3), r = k % (NP * 3);
+            sh.al[sl][r / 3][r % 3] = a.alpha[((size_t)sh.slot_store[s0 + sl] * a.NPT + poff) * 3 + r];
+        }
+        __syncthreads();
+        const int ms = my_slot - (int)s0;
+        if (ms >= 0 && ms < ns) {
+            const NodeGeo& g = a.geo[ndl];
+            const double* coef = a.ref.coef + poff;
+            double P[3][D + 1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double be = (g.minv[c][0] * x0 + g.minv[c][1] * x1) + g.minv[c][2] * x2;
+                P[c][0] = 1.0;
+#pragma unroll
+                for (int t = 1; t <= D; ++t) P[c][t] = P[c][t - 1] * be;
+            }
+            int k = 0;
+#pragma unroll
+            for (int i1 = 0; i1 <= D; ++i1) {
+#pragma unroll
+                for (int j1 = 0; j1 <= D - i1; ++j1) {
+                    const double B = coef[k] * (P[0][i1] * P[1][j1] * P[2][D - i1 - j1]);
+                    W0 += B * sh.al[ms][k][0];
+                    W1 += B * sh.al[ms][k][1];
+                    W2 += B * sh.al[ms][k][2];
+                    ++k;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// D0..D3: degrees of the classes in use (0 = class unused)
+template <int D0, int D1, int D2, int D3>
+__global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, double* __restrict__ u, int accumulate) {
+    constexpr int DM = D0 > D1 ? (D0 > D2 ? (D0 > D3 ? D0 : D3) : (D2 > D3 ? D2 : D3))
+                               : (D1 > D2 ? (D1 > D3 ? D1 : D3) : (D2 > D3 ? D2 : D3));
+    __shared__ L2PShared<(DM + 1) * (DM + 2) / 2> sh;
     const int tid = threadIdx.x;
     const i64 i0 = (i64)blockIdx.x * blockDim.x + tid;
     const bool valid = i0 < a.n;
@@ -374,53 +446,10 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
         for (int lvl = 0; lvl <= L; ++lvl) {
             const i64 ndl = a.level_off_tab[lvl] + (i64)(kl >> (2 * (L - lvl)));  // local id
             const i64 nd = mbase + ndl;
-            const bool has = valid && a.nseg_end[nd] != 0;
-            // the first particle of each node with far work opens a slot
-            slot_node[tid] = has ? nd : (i64)-1;
-            __syncthreads();
-            const bool first = has && (tid == 0 || slot_node[tid - 1] != nd);
-            u32 nslots = 0;
-            const u32 before = block_exclusive_scan<256>(first ? 1u : 0u, wtot, &nslots);
-            const int my_slot = has ? (int)(before + (first ? 1u : 0u)) - 1 : -1;
-            __syncthreads();
-            if (first) {
-                slot_node[my_slot] = nd;
-                slot_store[my_slot] = a.slot[nd];
-            }
-            __syncthreads();
-            for (u32 s0 = 0; s0 < nslots; s0 += KS) {
-                const int ns = (nslots - s0) < (u32)KS ? (int)(nslots - s0) : KS;
-                for (int k = tid; k < ns * NP * 3; k += 256) {
-                    const int sl = k / (NP * 3), r = k % (NP * 3);
-                    al[sl][r / 3][r % 3] = a.alpha[(size_t)slot_store[s0 + sl] * NP * 3 + r];
-                }
-                __syncthreads();
-                const int ms = my_slot - (int)s0;
-                if (ms >= 0 && ms < ns) {
-                    const NodeGeo& g = a.geo[ndl];
-                    double P[3][D + 1];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const double be = (g.minv[c][0] * x0 + g.minv[c][1] * x1) + g.minv[c][2] * x2;
-                        P[c][0] = 1.0;
-#pragma unroll
-                        for (int t = 1; t <= D; ++t) P[c][t] = P[c][t - 1] * be;
-                    }
-                    int k = 0;
-#pragma unroll
-                    for (int i1 = 0; i1 <= D; ++i1) {
-#pragma unroll
-                        for (int j1 = 0; j1 <= D - i1; ++j1) {
-                            const double B = a.ref.coef[k] * (P[0][i1] * P[1][j1] * P[2][D - i1 - j1]);
-                            W0 += B * al[ms][k][0];
-                            W1 += B * al[ms][k][1];
-                            W2 += B * al[ms][k][2];
-                            ++k;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
+            l2p_class<D0>(a, 0, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D1 > 0) l2p_class<D1 ? D1 : 1>(a, 1, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D2 > 0) l2p_class<D2 ? D2 : 1>(a, 2, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D3 > 0) l2p_class<D3 ? D3 : 1>(a, 3, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
         }
     }
     if (!valid) return;
@@ -531,9 +560,13 @@ void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* 
     if (a.n <= 0) return;
     const dim3 g((unsigned)((a.n + 255) / 256)), b(256);
     const int f = do_far ? 1 : 0, acc = accumulate ? 1 : 0;
-    switch (a.ref.degree) {
+    if (a.ndeg == 4) {  // the learned form's classes: degrees 4, 6, 8, 10
+        hipLaunchKernelGGL((k_l2p_finalize<4, 6, 8, 10>), g, b, 0, s, a, f, d_u, acc);
+        return;
+    }
+    switch (a.cls.deg[0]) {
 #define STC_L2P_CASE(D) \
-    case D: hipLaunchKernelGGL((k_l2p_finalize<D>), g, b, 0, s, a, f, d_u, acc); break;
+    case D: hipLaunchKernelGGL((k_l2p_finalize<D, 0, 0, 0>), g, b, 0, s, a, f, d_u, acc); break;
         STC_L2P_CASE(1) STC_L2P_CASE(2) STC_L2P_CASE(3) STC_L2P_CASE(4) STC_L2P_CASE(5) STC_L2P_CASE(6)
         STC_L2P_CASE(7) STC_L2P_CASE(8) STC_L2P_CASE(9) STC_L2P_CASE(10) STC_L2P_CASE(11) STC_L2P_CASE(12)
         STC_L2P_CASE(13) STC_L2P_CASE(14)

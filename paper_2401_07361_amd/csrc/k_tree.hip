@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                                                        const i32* __restrict__ nend, int n_crit,
                                                        const NodeGeo* __restrict__ geo, const double* __restrict__ sx,
                                                        const double* __restrict__ sy, const double* __restrict__ sz,
-                                                       const double* __restrict__ q, RefDev ref,
+                                                       const double* __restrict__ q, RefDev ref, int NPT, int poff,
                                                        const i32* __restrict__ slot, Prox* __restrict__ prox) {
     __shared__ double pw[64][3][kMaxDegree + 1];
     __shared__ double qs[64];
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                         y2 = sz[j];
                         qq = q[j];
                     } else {
-                        const Prox pr = prox[(size_t)slot[seg_id[sgi]] * np + idx];
+                        const Prox pr = prox[(size_t)slot[seg_id[sgi]] * NPT + poff + idx];
                         y0 = pr.x;
                         y1 = pr.y;
                         y2 = pr.z;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
             __syncthreads();
             // w_m = |.|^d sum_k (V_ref^{-1})_{km} omega_k  (row m of V_ref^{-T})
             block_matvec<256, 1>(ref.vinv, np, nullptr, omega, red, wout);
-            const size_t my_slot = (size_t)slot[node];
+            const size_t my_rec = (size_t)slot[node] * NPT + poff;
             for (int m = tid; m < np; m += 256) {
                 double y[3];
                 const double nrm = proxy_point(g, ref.points + 3 * m, y);
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                 pr.y = y[1];
                 pr.z = y[2];
                 pr.w = ipow(nrm, d) * wout[m][0];
-                prox[my_slot * np + m] = pr;
+                prox[my_rec + m] = pr;
             }
             __syncthreads();
         }
@@ -329,13 +329,15 @@ __device__ __forceinline__ u32 block_scan_u32(u32 v, u32* wsum, u32* total) {
 
 constexpr int TRAV_IPT = 4;  // frontier pairs per thread per round
 
+template <bool CAND>
 __global__ __launch_bounds__(256) void k_trav_level(
-    int iter, const u64* __restrict__ fin, u64* __restrict__ fout, u32 cap, const i32* __restrict__ ncnt,
+    int iter, int fbase, const u64* __restrict__ fin, u64* __restrict__ fout, u32 cap, const i32* __restrict__ ncnt,
     const NodeMac* __restrict__ mac, const i64* __restrict__ level_off_tab, int L, int NB, double theta2, int n_crit,
-    int W, u64* __restrict__ tlist, u64* __restrict__ nlist, u32* __restrict__ counters) {
-    __shared__ u32 wsum[3][4];
-    __shared__ u32 bases[3];
-    u32 nin = counters[C_FRONT + iter];
+    int W, int DB, int dcf, u64* __restrict__ tlist, u64* __restrict__ nlist, u64* __restrict__ cand_buf,
+    u32* __restrict__ counters) {
+    __shared__ u32 wsum[4][4];
+    __shared__ u32 bases[4];
+    u32 nin = counters[fbase + iter];
     if (nin > cap) nin = cap;
     const int tid = threadIdx.x;
     const u32 lm = (1u << NB) - 1u;  // local part of a node id
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(256) void k_trav_level(
         int nkids[TRAV_IPT];
         u32 kids[TRAV_IPT][4];
         u32 tt[TRAV_IPT], ss[TRAV_IPT];
-        u32 ct = 0, cn = 0, ck = 0;
+        u32 ct = 0, cn = 0, ck = 0, cc = 0;
 #pragma unroll
         for (int k = 0; k < TRAV_IPT; ++k) {
             const u64 i = r0 + (u64)k * 256 + tid;
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(256) void k_trav_level(
                 const i32 nt = ncnt[t], ns = ncnt[s];
                 const bool big_t = nt > n_crit, big_s = ns > n_crit;
                 if (mac_separated(mac[t & lm], mac[s & lm], theta2)) {
-                    kind[k] = (big_t ? 2 : 0) + (big_s ? 1 : 0);
+                    kind[k] = (CAND && (big_t || big_s)) ? 4 : (big_t ? 2 : 0) + (big_s ? 1 : 0);
                 } else if (!big_t && !big_s) {
                     kind[k] = 0;
                 } else {
@@ -389,27 +391,37 @@ __global__ __launch_bounds__(256) void k_trav_level(
                         }
                     }
                 }
-                keyv[k] = ((u64)t << (W + 1)) | ((u64)(kind[k] & 1) << W) | (u64)s;
+                // PP entries carry class 0, far entries the class dcf
+                const u64 dc = (kind[k] >= 1 && kind[k] <= 3) ? (u64)dcf : 0u;
+                keyv[k] = ((u64)t << (W + 1 + DB)) | (dc << (W + 1)) | ((u64)(kind[k] & 1) << W) | (u64)s;
             }
             ct += (kind[k] == 0 || kind[k] == 1) ? 1u : 0u;
             cn += (kind[k] == 2 || kind[k] == 3) ? 1u : 0u;
+            cc += kind[k] == 4 ? 1u : 0u;
             ck += (u32)nkids[k];
         }
-        u32 tot_t, tot_n, tot_k;
+        u32 tot_t, tot_n, tot_k, tot_c = 0;
         u32 pt = block_scan_u32(ct, wsum[0], &tot_t);
         u32 pn = block_scan_u32(cn, wsum[1], &tot_n);
         u32 pk = block_scan_u32(ck, wsum[2], &tot_k);
+        u32 pc = 0;
+        if (CAND) pc = block_scan_u32(cc, wsum[3], &tot_c);
         if (tid == 0) {
             bases[0] = tot_t ? atomicAdd(&counters[C_TLIST], tot_t) : 0u;
             bases[1] = tot_n ? atomicAdd(&counters[C_NLIST], tot_n) : 0u;
-            bases[2] = tot_k ? atomicAdd(&counters[C_FRONT + iter + 1], tot_k) : 0u;
+            bases[2] = tot_k ? atomicAdd(&counters[fbase + iter + 1], tot_k) : 0u;
+            bases[3] = tot_c ? atomicAdd(&counters[C_CAND], tot_c) : 0u;
         }
         __syncthreads();
-        u32 ot = bases[0] + pt, on = bases[1] + pn, ok = bases[2] + pk;
+        u32 ot = bases[0] + pt, on = bases[1] + pn, ok = bases[2] + pk, oc = bases[3] + pc;
         bool overflow = false;
 #pragma unroll
         for (int k = 0; k < TRAV_IPT; ++k) {
-            if (kind[k] == 0 || kind[k] == 1) {
+            if (CAND && kind[k] == 4) {
+                if (oc < cap) cand_buf[oc] = ((u64)tt[k] << 32) | (u64)ss[k];
+                else overflow = true;
+                ++oc;
+            } else if (kind[k] == 0 || kind[k] == 1) {
                 if (ot < cap) tlist[ot] = keyv[k];
                 else overflow = true;
                 ++ot;
@@ -451,18 +463,19 @@ __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbe
     }
 }
 
-// Segments of a sorted list: entries with the same target t occupy
-// [seg_beg[t], seg_end[t]).  Arrays must be zeroed before.
+// Segments of a sorted list: entries with the same key >> shift (the target,
+// or the target and degree class) occupy [seg_beg[.], seg_end[.]).  Arrays
+// must be zeroed before.
 __global__ __launch_bounds__(256) void k_segments(const u64* __restrict__ list, const u32* __restrict__ d_n,
-                                                   u32 cap, int W, i32* __restrict__ seg_beg,
+                                                   u32 cap, int shift, i32* __restrict__ seg_beg,
                                                    i32* __restrict__ seg_end) {
     u32 n = *d_n;
     if (n > cap) n = cap;
     const u64 stride = (u64)gridDim.x * blockDim.x;
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const u64 t = list[i] >> (W + 1);
-        if (i == 0 || (list[i - 1] >> (W + 1)) != t) seg_beg[t] = (i32)i;
-        if (i + 1 == n || (list[i + 1] >> (W + 1)) != t) seg_end[t] = (i32)(i + 1);
+        const u64 t = list[i] >> shift;
+        if (i == 0 || (list[i - 1] >> shift) != t) seg_beg[t] = (i32)i;
+        if (i + 1 == n || (list[i + 1] >> shift) != t) seg_end[t] = (i32)(i + 1);
     }
 }
 
@@ -478,7 +491,7 @@ __global__ __launch_bounds__(256) void k_fill_f64(double* __restrict__ p, i64 n,
 
 // Kernel-evaluation count implied by the lists (introspection only).
 __global__ __launch_bounds__(256) void k_count_evals(const u64* __restrict__ list, const u32* __restrict__ d_n,
-                                                      u32 cap, int W, int np, const i32* __restrict__ nbeg,
+                                                      u32 cap, int W, int DB, ClassTab cls, const i32* __restrict__ nbeg,
                                                       const i32* __restrict__ nend, int target_is_proxy,
                                                       unsigned long long* __restrict__ out) {
     // out[0], out[1]: evaluations of type 0 / 1 entries; out[2], out[3]: entries
@@ -489,8 +502,10 @@ __global__ __launch_bounds__(256) void k_count_evals(const u64* __restrict__ lis
     unsigned long long a0 = 0, a1 = 0, c0 = 0, c1 = 0;
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const u64 k = list[i];
-        const u64 t = k >> (W + 1), s = k & mask;
+        const u64 t = k >> (W + 1 + DB), s = k & mask;
         const int ty = (int)((k >> W) & 1);
+        const int c = (int)((k >> (W + 1)) & ((1u << DB) - 1u));
+        const int np = STC_PICK4(cls.np, c);
         const u64 nt = target_is_proxy ? (u64)np : (u64)(nend[t] - nbeg[t]);
         const u64 ns = ty ? (u64)np : (u64)(nend[s] - nbeg[s]);
         u64 v = nt * ns;
@@ -535,7 +550,7 @@ void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, c
 
 void launch_upward(hipStream_t s, int members, int NB, const i32* nbeg, const i32* nend, const i64* level_off_host,
                    int L, int n_crit, const NodeGeo* geo, const double* sx, const double* sy, const double* sz,
-                   const double* q, RefDev ref, const i32* slot, Prox* prox) {
+                   const double* q, RefDev ref, int NPT, int poff, const i32* slot, Prox* prox) {
     for (int lvl = L; lvl >= 0; --lvl) {
         const i64 node0 = level_off_host[lvl];
         const i64 nn = level_off_host[lvl + 1] - node0;
@@ -547,7 +562,7 @@ void launch_upward(hipStream_t s, int members, int NB, const i32* nbeg, const i3
         const i64 per_member = std::max<i64>(1, 4096 / members);
         const unsigned grid = (unsigned)(nchunks < per_member ? nchunks : per_member);
         hipLaunchKernelGGL(k_upward_level, dim3(grid, (unsigned)members), dim3(256), 0, s, node0, nn, chunk, lvl, L,
-                           NB, child_off, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, slot, prox);
+                           NB, child_off, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff, slot, prox);
     }
 }
 
@@ -570,29 +585,37 @@ void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_n
                        n_crit, ncnt, slot, slot_cap, flags);
 }
 
-void launch_traverse(hipStream_t s, int members, int NB, const i32* ncnt, const NodeMac* mac,
-                     const i64* level_off_tab, int L, double theta, int n_crit, int W, u64* front0, u64* front1,
-                     u32 cap, u64* tlist, u64* nlist, u32* counters) {
-    launch_fill_u32(s, counters, C_COUNT, 0u);
-    hipLaunchKernelGGL(k_trav_init, dim3(blocks_for((i64)members * 400, 256)), dim3(256), 0, s, members, NB, ncnt,
-                       front0, cap, counters);
-    const double theta2 = theta * theta;
-    const int iters = 2 * L + 2;
+void launch_traverse_init(hipStream_t s, const TravArgs& t) {
+    launch_fill_u32(s, t.counters, C_COUNT, 0u);
+    hipLaunchKernelGGL(k_trav_init, dim3(blocks_for((i64)t.members * 400, 256)), dim3(256), 0, s, t.members, t.NB,
+                       t.ncnt, t.front0, t.cap, t.counters);
+}
+
+void launch_traverse_levels(hipStream_t s, const TravArgs& t, int fbase, bool cand, u64* cand_buf) {
+    const double theta2 = t.theta * t.theta;
+    const int iters = 2 * t.L + 2;
     for (int it = 0; it < iters; ++it) {
-        const u64* fin = (it % 2 == 0) ? front0 : front1;
-        u64* fout = (it % 2 == 0) ? front1 : front0;
-        hipLaunchKernelGGL(k_trav_level, dim3(1024), dim3(256), 0, s, it, fin, fout, cap, ncnt, mac, level_off_tab,
-                           L, NB, theta2, n_crit, W, tlist, nlist, counters);
+        const u64* fin = (it % 2 == 0) ? t.front0 : t.front1;
+        u64* fout = (it % 2 == 0) ? t.front1 : t.front0;
+        if (cand)
+            hipLaunchKernelGGL(k_trav_level<true>, dim3(1024), dim3(256), 0, s, it, fbase, fin, fout, t.cap, t.ncnt,
+                               t.mac, t.level_off_tab, t.L, t.NB, theta2, t.n_crit, t.W, t.DB, t.dcf, t.tlist,
+                               t.nlist, cand_buf, t.counters);
+        else
+            hipLaunchKernelGGL(k_trav_level<false>, dim3(1024), dim3(256), 0, s, it, fbase, fin, fout, t.cap, t.ncnt,
+                               t.mac, t.level_off_tab, t.L, t.NB, theta2, t.n_crit, t.W, t.DB, t.dcf, t.tlist,
+                               t.nlist, cand_buf, t.counters);
     }
 }
 
-void launch_segments(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, i32* seg_beg, i32* seg_end) {
-    hipLaunchKernelGGL(k_segments, dim3(1024), dim3(256), 0, s, list, d_n, cap, W, seg_beg, seg_end);
+void launch_segments(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int shift, i32* seg_beg,
+                     i32* seg_end) {
+    hipLaunchKernelGGL(k_segments, dim3(1024), dim3(256), 0, s, list, d_n, cap, shift, seg_beg, seg_end);
 }
 
-void launch_count_evals(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, int np, const i32* nbeg,
-                        const i32* nend, int target_is_proxy, unsigned long long* out) {
-    hipLaunchKernelGGL(k_count_evals, dim3(256), dim3(256), 0, s, list, d_n, cap, W, np, nbeg, nend,
+void launch_count_evals(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, int DB, ClassTab cls,
+                        const i32* nbeg, const i32* nend, int target_is_proxy, unsigned long long* out) {
+    hipLaunchKernelGGL(k_count_evals, dim3(256), dim3(256), 0, s, list, d_n, cap, W, DB, cls, nbeg, nend,
                        target_is_proxy, out);
 }
 

@@ -5,6 +5,21 @@
 
 namespace stc {
 
+// Degree classes: a context evaluates far-field interactions at one degree
+// (class 0) or, with learned gating, at the degree class each list entry
+// carries (degrees 4, 6, 8, 10).  Per class: points per node, offset of the
+// class's points inside a node's record of NPT points, degree, offset of its
+// np x np matrices in the concatenated reference tables.
+struct ClassTab {
+    int np[4], poff[4], deg[4], qoff[4];
+};
+
+#define STC_PICK4(arr, c) ((c) == 0 ? (arr)[0] : (c) == 1 ? (arr)[1] : (c) == 2 ? (arr)[2] : (arr)[3])
+
+// List keys: (t << (W + 1 + DB)) | (class << (W + 1)) | (type << W) | s, with
+// DB = 0 (single degree) or 2 (degree classes).  The target-particle list is
+// grouped by t, the target-proxy list by (t, class).
+
 // k_tree.hip
 void launch_bin(hipStream_t s, const double* x, i64 n, const NodeGeo* geo, int L, const MemberOffsets& mo,
                 u64* keys, u32* flags);
@@ -14,17 +29,32 @@ void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i3
 void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area, double* q);
 void launch_upward(hipStream_t s, int members, int NB, const i32* nbeg, const i32* nend, const i64* level_off_host,
                    int L, int n_crit, const NodeGeo* geo, const double* sx, const double* sy, const double* sz,
-                   const double* q, RefDev ref, const i32* slot, Prox* prox);
+                   const double* q, RefDev ref, int NPT, int poff, const i32* slot, Prox* prox);
 void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, i32* ncnt,
                         i32* slot, u32 slot_cap, u32* flags);
-void launch_traverse(hipStream_t s, int members, int NB, const i32* ncnt, const NodeMac* mac,
-                     const i64* level_off_tab, int L, double theta, int n_crit, int W, u64* front0, u64* front1,
-                     u32 cap, u64* tlist, u64* nlist, u32* counters);
-void launch_segments(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, i32* seg_beg, i32* seg_end);
+// Traversal: the root pairs of every member into front0 (counters zeroed),
+// then 2L + 2 level iterations from front0 whose frontier lengths live at
+// counters[fbase + k].  Far entries get degree class dcf; with `cand`, pairs
+// that are separated and have a side with more than n_crit particles go to
+// cand_buf (counter C_CAND) instead of the lists.
+struct TravArgs {
+    int members, NB, L, n_crit, W, DB, dcf;
+    double theta;
+    const i32* ncnt;
+    const NodeMac* mac;
+    const i64* level_off_tab;
+    u64 *front0, *front1;
+    u32 cap;
+    u64 *tlist, *nlist;
+    u32* counters;
+};
+void launch_traverse_init(hipStream_t s, const TravArgs& t);
+void launch_traverse_levels(hipStream_t s, const TravArgs& t, int fbase, bool cand, u64* cand_buf);
+void launch_segments(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int shift, i32* seg_beg, i32* seg_end);
 void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v);
 void launch_fill_f64(hipStream_t s, double* p, i64 n, double v);
-void launch_count_evals(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, int np, const i32* nbeg,
-                        const i32* nend, int target_is_proxy, unsigned long long* out);
+void launch_count_evals(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, int DB, ClassTab cls,
+                        const i32* nbeg, const i32* nend, int target_is_proxy, unsigned long long* out);
 
 // k_eval.hip
 struct EvalArgs {
@@ -54,7 +84,11 @@ struct EvalArgs {
     const u32* leaf;
     const i32* perm;
     i64 n;
-    RefDev ref;
+    RefDev ref;          // all classes' tables concatenated (class offsets in cls)
+    ClassTab cls;
+    int ndeg;            // degree classes in use (1 or 4)
+    int DB;              // class bits in the list keys (0 or 2)
+    int NPT;             // points per node record (sum over classes)
     int precision;
     int denominator;
     u32 node_mask;       // local part of a node id
@@ -68,5 +102,46 @@ void launch_far_targets(hipStream_t s, const EvalArgs& a);
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate);
 void launch_direct(hipStream_t s, i64 n, const double* x, const double* zeta, const double* area, i64 m,
                    const i64* targets, int precision, int denominator, double* u);
+
+// k_mlp.hip -- the learned form's network (12 -> 64 -> 64 -> 4, BF16 on the matrix cores)
+int mlp_param_count();
+i64 mlp_workspace_floats(i64 n_batch);
+void launch_mlp_forward(hipStream_t s, const u16* X, i64 n, const u32* d_n, u32 cap, const u16* P, float* out);
+int launch_mlp_grad(hipStream_t s, const u16* X, const float* Y, const i32* idx, i64 nb, const u16* P, float* ws);
+void launch_mlp_reduce_adam(hipStream_t s, const float* ws, int nwaves, float* grad, float* loss, float* master,
+                            float* m1, float* m2, u16* P, float lr, float beta1, float beta2, float eps, int step);
+void launch_mlp_batch_index(hipStream_t s, i64 n, i64 base, i64 nb, u64 a, u64 c, i32* idx);
+
+// k_learned.hip -- gated traversal of the learned form (single member)
+struct LearnedArgs {
+    const u64* cand;         // candidate pairs (t << 32 | s), count at counters[C_CAND]
+    u32* counters;
+    u32 cap;
+    const i32* ncnt;
+    const i32* nbeg;
+    const i32* nend;
+    const NodeMac* mac;
+    const NodeGeo* geo;
+    const i64* level_off_tab;
+    int L, n_crit, W, DB;
+    const double* qabs;      // per node: sum of |q| and of q over its particles
+    const double* qsum;
+    const i32* slot;
+    const Prox* prox;        // proxy records (class 0 = degree 4 first in each record)
+    int NPT;
+    u16* feat;               // cap x 16 BF16 features
+    float* out;              // cap x 4 network outputs
+    const u16* model;        // BF16 parameters
+    u64* tlist;
+    u64* nlist;
+    u64* front;              // frontier of the fallback traversal (counter C_FRONT2)
+};
+void launch_node_charge_sums(hipStream_t s, const i32* nbeg, const i32* nend, const i64* level_off_host, int L,
+                             const double* q, double* qabs, double* qsum);
+void launch_features(hipStream_t s, const LearnedArgs& a);
+void launch_mlp_forward_list(hipStream_t s, const LearnedArgs& a);
+void launch_resolve(hipStream_t s, const LearnedArgs& a, bool use_model);
+void launch_pair_errors(hipStream_t s, const LearnedArgs& la, const EvalArgs& a, int dist2, u32 lim, double* err);
+void launch_labels(hipStream_t s, const LearnedArgs& la, u32 lim, const double* err, double tol, float* y);
 
 }  // namespace stc

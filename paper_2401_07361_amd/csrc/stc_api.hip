@@ -31,7 +31,18 @@ struct stc_ctx {
     std::map<int, stc_launch_config> shapes;  // per size class (bits of the particle count)
     std::vector<i64> offsets;                 // member offsets of the last build
     std::vector<NodeGeo> geo_host;
-    RefTables ref_host;
+    // degree classes: 1 (the context's degree) or 4 (degrees 4, 6, 8, 10:
+    // learned gating); list keys carry DB class bits; a node's proxy record
+    // holds NPT points, the classes' points one after the other
+    bool learned = false;
+    int ndeg = 1, DB = 0, NPT = 0, fb_class = 0;
+    ClassTab cls{};
+    RefTables ref_host[4];
+    u64* cand = nullptr;          // candidate pairs of the gated traversal
+    u16* feat = nullptr;          // their features (BF16, 16 per candidate)
+    float* mlp_out = nullptr;     // network outputs per candidate
+    double *qabs = nullptr, *qsum = nullptr;  // per-node charge sums
+    const uint16_t* model = nullptr;  // BF16 network parameters (caller's), or null: reject every candidate
     std::vector<i64> level_off_host;
     // device buffers (all allocated in stc_create)
     NodeGeo* geo = nullptr;
@@ -138,15 +149,17 @@ bool valid_shape(const stc_launch_config* s) {
            s->near_blocks_per_cu <= 64 && s->far_blocks_per_cu >= 1 && s->far_blocks_per_cu <= 64;
 }
 
-RefDev ref_dev(const stc_ctx* c) {
+// tables of degree class k
+RefDev ref_dev(const stc_ctx* c, int k = 0) {
     RefDev r;
-    r.points = c->ref_points;
-    r.vinv = c->ref_vinv;
-    r.vinvT = c->ref_vinvT;
-    r.expo = c->ref_expo;
-    r.coef = c->ref_coef;
-    r.degree = c->p.degree;
-    r.np = c->np;
+    const int poff = c->cls.poff[k], qoff = c->cls.qoff[k];
+    r.points = c->ref_points + 3 * poff;
+    r.vinv = c->ref_vinv + qoff;
+    r.vinvT = c->ref_vinvT + qoff;
+    r.expo = c->ref_expo + 3 * poff;
+    r.coef = c->ref_coef + poff;
+    r.degree = c->cls.deg[k];
+    r.np = c->cls.np[k];
     return r;
 }
 
@@ -178,7 +191,16 @@ EvalArgs eval_args(stc_ctx* c) {
     a.leaf = c->leaf;
     a.perm = c->perm;
     a.n = c->n;
-    a.ref = ref_dev(c);
+    a.ref = ref_dev(c, 0);
+    a.ref.points = c->ref_points;  // class offsets are applied in the kernels
+    a.ref.vinv = c->ref_vinv;
+    a.ref.vinvT = c->ref_vinvT;
+    a.ref.expo = c->ref_expo;
+    a.ref.coef = c->ref_coef;
+    a.cls = c->cls;
+    a.ndeg = c->ndeg;
+    a.DB = c->DB;
+    a.NPT = c->NPT;
     a.precision = c->p.precision;
     a.denominator = c->p.denominator;
     a.node_mask = (u32)(((u64)1 << c->NB) - 1);
@@ -202,7 +224,12 @@ stc_status validate_params(const stc_params* p, i64 n_max) {
     if (p->denominator != STC_DEN_DOT && p->denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
     if (p->precision == STC_FP32 && p->denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
     if (p->list_capacity < 0 || p->list_capacity > 0x7fffffffLL) return STC_ERR_INVALID_ARG;
-    if (p->flags & ~STC_FLAG_EAGER_RK4) return STC_ERR_INVALID_ARG;
+    if (p->flags & ~(STC_FLAG_EAGER_RK4 | STC_FLAG_LEARNED)) return STC_ERR_INVALID_ARG;
+    if (!(p->theta_max >= 0.0 && p->theta_max <= 1.0)) return STC_ERR_INVALID_ARG;
+    if (p->flags & STC_FLAG_LEARNED) {
+        if (p->degree != 4 && p->degree != 6 && p->degree != 8 && p->degree != 10) return STC_ERR_INVALID_ARG;
+        if (p->theta_max > 0.0 && p->theta_max < p->theta) return STC_ERR_INVALID_ARG;
+    }
     if (n_max < 0 || n_max >= 0x7fffffffLL) return STC_ERR_INVALID_ARG;
     return STC_OK;
 }
@@ -255,18 +282,92 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
     mark(c, 1);
     launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sq);
     if (c->n > 0)
-        launch_upward(s, c->members, c->NB, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit, c->geo,
-                      c->sx, c->sy, c->sz, c->sq, ref_dev(c), c->slot, c->prox);
+        for (int k = 0; k < c->ndeg; ++k)
+            launch_upward(s, c->members, c->NB, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit,
+                          c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, k), c->NPT, c->cls.poff[k], c->slot,
+                          c->prox);
+    if (c->learned && c->n > 0)
+        launch_node_charge_sums(s, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->sq, c->qabs, c->qsum);
     c->have_upward = true;
     return check_launch(c, "upward");
+}
+
+LearnedArgs learned_args(stc_ctx* c) {
+    LearnedArgs l{};
+    l.cand = c->cand;
+    l.counters = c->counters;
+    l.cap = c->cap;
+    l.ncnt = c->ncnt;
+    l.nbeg = c->nbeg;
+    l.nend = c->nend;
+    l.mac = c->mac;
+    l.geo = c->geo;
+    l.level_off_tab = c->level_off;
+    l.L = c->L;
+    l.n_crit = c->p.n_crit;
+    l.W = c->W;
+    l.DB = c->DB;
+    l.qabs = c->qabs;
+    l.qsum = c->qsum;
+    l.slot = c->slot;
+    l.prox = c->prox;
+    l.NPT = c->NPT;
+    l.feat = c->feat;
+    l.out = c->mlp_out;
+    l.model = c->model;
+    l.tlist = c->tlist_a;
+    l.nlist = c->nlist_a;
+    l.front = c->front0;
+    return l;
+}
+
+TravArgs trav_args(stc_ctx* c, double theta, int dcf) {
+    TravArgs t{};
+    t.members = c->members;
+    t.NB = c->NB;
+    t.L = c->L;
+    t.n_crit = c->p.n_crit;
+    t.W = c->W;
+    t.DB = c->DB;
+    t.dcf = dcf;
+    t.theta = theta;
+    t.ncnt = c->ncnt;
+    t.mac = c->mac;
+    t.level_off_tab = c->level_off;
+    t.front0 = c->front0;
+    t.front1 = c->front1;
+    t.cap = c->cap;
+    t.tlist = c->tlist_a;
+    t.nlist = c->nlist_a;
+    t.counters = c->counters;
+    return t;
 }
 
 stc_status do_traverse(stc_ctx* c) {
     hipStream_t s = c->stream;
     mark(c, 2);
-    launch_traverse(s, c->members, c->NB, c->ncnt, c->mac, c->level_off, c->L, c->p.theta, c->p.n_crit, c->W,
-                    c->front0, c->front1, c->cap, c->tlist_a, c->nlist_a, c->counters);
-    const int bits = 2 * c->W + 1;
+    if (!c->learned) {
+        const TravArgs t = trav_args(c, c->p.theta, 0);
+        launch_traverse_init(s, t);
+        launch_traverse_levels(s, t, C_FRONT, false, nullptr);
+    } else {
+        // gated traversal (learned form): pairs separated at theta_max with a
+        // side of more than N_T particles are candidates; the network accepts
+        // each at a degree class or rejects it; rejected pairs are traversed
+        // by the plain method (theta, the fallback degree) from there on
+        const TravArgs tc = trav_args(c, c->p.theta_max, 0);
+        launch_traverse_init(s, tc);
+        launch_traverse_levels(s, tc, C_FRONT, true, c->cand);
+        LearnedArgs la = learned_args(c);
+        if (c->model) {
+            launch_features(s, la);
+            launch_mlp_forward_list(s, la);
+        }
+        launch_resolve(s, la, c->model != nullptr);
+        const TravArgs tf = trav_args(c, c->p.theta, c->fb_class);
+        launch_traverse_levels(s, tf, C_FRONT2, false, nullptr);
+    }
+    const int bits = 2 * c->W + 1 + c->DB;
     SortScratch sc{c->hist, c->hist_totals, c->hist_blocks};
     {
         u64* keys[2] = {c->tlist_a, c->nlist_a};
@@ -277,12 +378,13 @@ stc_status do_traverse(stc_ctx* c) {
         c->tlist = res[0];
         c->nlist = res[1];
     }
+    const i64 nv = c->used_nodes << c->DB;  // (target, class) segments of the target-proxy list
     launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_beg), c->used_nodes, 0u);
     launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_end), c->used_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_beg), c->used_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_end), c->used_nodes, 0u);
-    launch_segments(s, c->tlist, c->counters + C_TLIST, c->cap, c->W, c->tseg_beg, c->tseg_end);
-    launch_segments(s, c->nlist, c->counters + C_NLIST, c->cap, c->W, c->nseg_beg, c->nseg_end);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_beg), nv, 0u);
+    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_end), nv, 0u);
+    launch_segments(s, c->tlist, c->counters + C_TLIST, c->cap, c->W + 1 + c->DB, c->tseg_beg, c->tseg_end);
+    launch_segments(s, c->nlist, c->counters + C_NLIST, c->cap, c->W + 1, c->nseg_beg, c->nseg_end);
     c->have_lists = true;
     return check_launch(c, "traverse");
 }
@@ -392,6 +494,8 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     if (st != STC_OK) return st;
     if (max_members < 1 || max_members > STC_MAX_MEMBERS || n_max_member < 0 || n_max_member > n_max_total)
         return STC_ERR_INVALID_ARG;
+    const bool learned = (p->flags & STC_FLAG_LEARNED) != 0;
+    if (learned && max_members != 1) return STC_ERR_INVALID_ARG;
     const int L = p->max_level >= 0 ? p->max_level : stc_default_max_level(n_max_member, p->n_crit);
     const int mbits = bits_for(max_members);
     const int NB = std::max(1, bits_for(stc::total_nodes(L)));
@@ -407,6 +511,25 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     c->L = L;
     c->p.max_level = c->L;
     c->np = stc_n_basis(p->degree);
+    c->learned = learned;
+    c->ndeg = learned ? 4 : 1;
+    c->DB = learned ? 2 : 0;
+    c->fb_class = learned ? (p->degree - 4) / 2 : 0;
+    if (learned && !(c->p.theta_max > 0.0)) c->p.theta_max = p->theta;
+    {
+        int poff = 0, qoff = 0;
+        for (int k = 0; k < 4; ++k) {
+            const int d = learned ? 4 + 2 * k : (k == 0 ? p->degree : 0);
+            const int np = k < c->ndeg ? stc_n_basis(d) : 0;
+            c->cls.np[k] = np;
+            c->cls.deg[k] = k < c->ndeg ? d : 0;
+            c->cls.poff[k] = poff;
+            c->cls.qoff[k] = qoff;
+            poff += np;
+            qoff += np * np;
+        }
+        c->NPT = poff;
+    }
     c->NB = NB;
     c->LB = 2 * L + 5;
     c->n_local = stc::total_nodes(c->L);
@@ -421,10 +544,11 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     c->cap = (u32)std::min<i64>(cap, 0x7fffffffLL);
     try {
         build_tree_geometry(c->L, c->geo_host);
-        if (!build_reference_tables(p->degree, c->ref_host)) {
-            delete c;
-            return STC_ERR_INVALID_ARG;
-        }
+        for (int k = 0; k < c->ndeg; ++k)
+            if (!build_reference_tables(c->cls.deg[k], c->ref_host[k])) {
+                delete c;
+                return STC_ERR_INVALID_ARG;
+            }
     } catch (...) {
         delete c;
         return STC_ERR_ALLOC;
@@ -432,24 +556,31 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     c->level_off_host.resize(c->L + 2);
     for (int l = 0; l <= c->L + 1; ++l) c->level_off_host[l] = level_offset(l);
     c->hist_blocks = (int)((std::max<i64>(c->cap, nm) + 4095) / 4096);
-    const size_t np = (size_t)c->np, ns = c->slot_cap;
+    const size_t NPT = (size_t)c->NPT, ns = c->slot_cap;
+    size_t nq = 0;
+    for (int k = 0; k < c->ndeg; ++k) nq += (size_t)c->cls.np[k] * c->cls.np[k];
+    const i64 nseg = c->n_nodes << c->DB;
     bool ok = dalloc(c, &c->geo, c->geo_host.size()) && dalloc(c, &c->mac, c->geo_host.size()) &&
               dalloc(c, &c->ncnt, c->n_nodes) && dalloc(c, &c->slot, c->n_nodes) &&
-              dalloc(c, &c->level_off, c->level_off_host.size()) && dalloc(c, &c->ref_points, 3 * np) &&
-              dalloc(c, &c->ref_vinv, np * np) && dalloc(c, &c->ref_vinvT, np * np) && dalloc(c, &c->ref_coef, np) &&
-              dalloc(c, &c->ref_expo, 3 * np) && dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) &&
+              dalloc(c, &c->level_off, c->level_off_host.size()) && dalloc(c, &c->ref_points, 3 * NPT) &&
+              dalloc(c, &c->ref_vinv, nq) && dalloc(c, &c->ref_vinvT, nq) && dalloc(c, &c->ref_coef, NPT) &&
+              dalloc(c, &c->ref_expo, 3 * NPT) && dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) &&
               dalloc(c, &c->perm, nm) && dalloc(c, &c->leaf, nm) && dalloc(c, &c->sx, nm) && dalloc(c, &c->sy, nm) &&
               dalloc(c, &c->sz, nm) && dalloc(c, &c->sq, nm) && dalloc(c, &c->nbeg, c->n_nodes) &&
-              dalloc(c, &c->nend, c->n_nodes) && dalloc(c, &c->prox, ns * np) && dalloc(c, &c->alpha, ns * np * 3) &&
+              dalloc(c, &c->nend, c->n_nodes) && dalloc(c, &c->prox, ns * NPT) && dalloc(c, &c->alpha, ns * NPT * 3) &&
               dalloc(c, &c->Wacc, 3 * nm) && dalloc(c, &c->front0, c->cap) && dalloc(c, &c->front1, c->cap) &&
               dalloc(c, &c->tlist_a, c->cap) && dalloc(c, &c->tlist_b, c->cap) && dalloc(c, &c->nlist_a, c->cap) &&
               dalloc(c, &c->nlist_b, c->cap) && dalloc(c, &c->tseg_beg, c->n_nodes) &&
-              dalloc(c, &c->tseg_end, c->n_nodes) && dalloc(c, &c->nseg_beg, c->n_nodes) &&
-              dalloc(c, &c->nseg_end, c->n_nodes) && dalloc(c, &c->counters, C_COUNT) &&
+              dalloc(c, &c->tseg_end, c->n_nodes) && dalloc(c, &c->nseg_beg, nseg) &&
+              dalloc(c, &c->nseg_end, nseg) && dalloc(c, &c->counters, C_COUNT) &&
               dalloc(c, &c->flags, F_COUNT) && dalloc(c, &c->evals, 8) &&
               dalloc(c, &c->hist, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->hist_totals, 512) &&
               dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
               dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm);
+    if (ok && learned)
+        ok = dalloc(c, &c->cand, c->cap) && dalloc(c, &c->feat, (size_t)c->cap * 16) &&
+             dalloc(c, &c->mlp_out, (size_t)c->cap * 4) && dalloc(c, &c->qabs, c->n_nodes) &&
+             dalloc(c, &c->qsum, c->n_nodes);
     if (!ok) {
         stc_destroy(c);
         return STC_ERR_ALLOC;
@@ -457,9 +588,19 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     c->tlist = c->tlist_a;
     c->nlist = c->nlist_a;
     hipStream_t s = c->stream;
-    std::vector<double> vinvT_host(np * np);
-    for (size_t k = 0; k < np; ++k)
-        for (size_t m = 0; m < np; ++m) vinvT_host[m * np + k] = c->ref_host.vinv[k * np + m];
+    // all classes' tables, concatenated (class k at poff[k] points, qoff[k] matrix entries)
+    std::vector<double> pts_h, vinv_h, vinvT_h, coef_h;
+    std::vector<int> expo_h;
+    for (int k = 0; k < c->ndeg; ++k) {
+        const RefTables& t = c->ref_host[k];
+        const size_t n = (size_t)t.np;
+        pts_h.insert(pts_h.end(), t.points.begin(), t.points.end());
+        vinv_h.insert(vinv_h.end(), t.vinv.begin(), t.vinv.end());
+        for (size_t m = 0; m < n; ++m)
+            for (size_t kk = 0; kk < n; ++kk) vinvT_h.push_back(t.vinv[kk * n + m]);
+        coef_h.insert(coef_h.end(), t.coef.begin(), t.coef.end());
+        expo_h.insert(expo_h.end(), t.expo.begin(), t.expo.end());
+    }
     std::vector<NodeMac> mac_host(c->geo_host.size());
     for (size_t i = 0; i < mac_host.size(); ++i)
         mac_host[i] = NodeMac{c->geo_host[i].c[0], c->geo_host[i].c[1], c->geo_host[i].c[2], c->geo_host[i].r};
@@ -469,11 +610,11 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     bool cp = up(c->geo, c->geo_host.data(), c->geo_host.size() * sizeof(NodeGeo)) &&
               up(c->mac, mac_host.data(), mac_host.size() * sizeof(NodeMac)) &&
               up(c->level_off, c->level_off_host.data(), c->level_off_host.size() * sizeof(i64)) &&
-              up(c->ref_points, c->ref_host.points.data(), 3 * np * sizeof(double)) &&
-              up(c->ref_vinv, c->ref_host.vinv.data(), np * np * sizeof(double)) &&
-              up(c->ref_vinvT, vinvT_host.data(), np * np * sizeof(double)) &&
-              up(c->ref_coef, c->ref_host.coef.data(), np * sizeof(double)) &&
-              up(c->ref_expo, c->ref_host.expo.data(), 3 * np * sizeof(int));
+              up(c->ref_points, pts_h.data(), pts_h.size() * sizeof(double)) &&
+              up(c->ref_vinv, vinv_h.data(), vinv_h.size() * sizeof(double)) &&
+              up(c->ref_vinvT, vinvT_h.data(), vinvT_h.size() * sizeof(double)) &&
+              up(c->ref_coef, coef_h.data(), coef_h.size() * sizeof(double)) &&
+              up(c->ref_expo, expo_h.data(), expo_h.size() * sizeof(int));
     launch_fill_u32(s, c->counters, C_COUNT, 0u);
     launch_fill_u32(s, c->flags, F_COUNT, 0u);
     if (!cp || hipStreamSynchronize(s) != hipSuccess) {
@@ -807,6 +948,163 @@ stc_status stc_autotune(stc_ctx* c, int32_t repeats, stc_launch_config* out) {
     return STC_OK;
 }
 
+stc_status stc_set_model(stc_ctx* c, const uint16_t* d_params) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (!c->learned) return fail(c, STC_ERR_STATE, "the context was created without STC_FLAG_LEARNED");
+    if (d_params && (reinterpret_cast<uintptr_t>(d_params) & 15u))
+        return fail(c, STC_ERR_INVALID_ARG, "d_params must be 16-byte aligned");
+    c->model = d_params;
+    return STC_OK;
+}
+
+stc_status stc_copy_candidates(stc_ctx* c, int64_t cap, int64_t* h_pairs, float* h_out, uint16_t* h_feat,
+                               int64_t* n_out) {
+    stc_status st = check_ready(c, false);
+    if (st != STC_OK) return st;
+    if (!c->learned) return fail(c, STC_ERR_STATE, "the context was created without STC_FLAG_LEARNED");
+    if (!n_out || cap < 0) return fail(c, STC_ERR_INVALID_ARG, "bad buffer");
+    st = stc_sync(c);
+    if (st != STC_OK) return st;
+    u32 nc = 0;
+    if (hipMemcpy(&nc, c->counters + C_CAND, sizeof(u32), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "reading counters failed");
+    nc = std::min(nc, c->cap);
+    *n_out = nc;
+    const i64 m = std::min<i64>(nc, cap);
+    if (m > 0) {
+        std::vector<u64> buf(m);
+        if (h_pairs) {
+            if (hipMemcpy(buf.data(), c->cand, m * sizeof(u64), hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(c, STC_ERR_DEVICE, "copy failed");
+            for (i64 i = 0; i < m; ++i) {
+                h_pairs[2 * i] = (int64_t)(buf[i] >> 32);
+                h_pairs[2 * i + 1] = (int64_t)(buf[i] & 0xffffffffu);
+            }
+        }
+        if (h_out && c->model &&
+            hipMemcpy(h_out, c->mlp_out, m * 4 * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, STC_ERR_DEVICE, "copy failed");
+        if (h_feat &&
+            hipMemcpy(h_feat, c->feat, m * 16 * sizeof(uint16_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(c, STC_ERR_DEVICE, "copy failed");
+    }
+    return (h_pairs || h_out || h_feat) && nc > cap ? fail(c, STC_ERR_CAPACITY, "buffers too small") : STC_OK;
+}
+
+stc_status stc_learned_samples(stc_ctx* c, double abs_tol, int64_t cap, uint16_t* d_features, float* d_labels,
+                               double* d_errors, int64_t* n_out) {
+    stc_status st = check_ready(c, false);
+    if (st != STC_OK) return st;
+    if (!c->learned) return fail(c, STC_ERR_STATE, "the context was created without STC_FLAG_LEARNED");
+    if (!c->have_upward) return fail(c, STC_ERR_STATE, "call stc_upward first");
+    if (!n_out || cap < 0 || !(abs_tol > 0.0) || (cap > 0 && (!d_features || !d_labels || !d_errors)))
+        return fail(c, STC_ERR_INVALID_ARG, "bad tolerance or buffers");
+    if ((reinterpret_cast<uintptr_t>(d_labels) & 15u) || (reinterpret_cast<uintptr_t>(d_errors) & 7u))
+        return fail(c, STC_ERR_INVALID_ARG, "misaligned buffers");
+    hipStream_t s = c->stream;
+    // candidates of the wider criterion, their features and measured errors
+    const TravArgs tc = trav_args(c, c->p.theta_max, 0);
+    launch_traverse_init(s, tc);
+    launch_traverse_levels(s, tc, C_FRONT, true, c->cand);
+    LearnedArgs la = learned_args(c);
+    launch_features(s, la);
+    EvalArgs a = eval_args(c);
+    const u32 lim = (u32)std::min<i64>(cap, 0x7fffffffLL);
+    launch_pair_errors(s, la, a, c->p.denominator == STC_DEN_DIST2 ? 1 : 0, lim, d_errors);
+    launch_labels(s, la, lim, d_errors, abs_tol, d_labels);
+    c->have_lists = false;  // the lists hold only the candidate pass now
+    st = check_launch(c, "learned_samples");
+    if (st != STC_OK) return st;
+    st = stc_sync(c);
+    if (st != STC_OK) return st;
+    u32 nc = 0;
+    if (hipMemcpy(&nc, c->counters + C_CAND, sizeof(u32), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "reading counters failed");
+    nc = std::min(nc, c->cap);
+    *n_out = nc;
+    const i64 m = std::min<i64>(nc, cap);
+    if (m > 0) {
+        const bool ok =
+            hipMemcpyAsync(d_features, c->feat, m * 16 * sizeof(uint16_t), hipMemcpyDeviceToDevice, s) == hipSuccess;
+        if (!ok || hipStreamSynchronize(s) != hipSuccess) return fail(c, STC_ERR_DEVICE, "copying samples failed");
+    }
+    return nc > cap && cap > 0 ? fail(c, STC_ERR_CAPACITY, "sample buffers too small") : STC_OK;
+}
+
+// --- the network (context-free) ----------------------------------------------
+
+int32_t stc_mlp_param_count(void) { return mlp_param_count(); }
+
+int64_t stc_mlp_workspace_bytes(int64_t n_batch) {
+    if (n_batch < 0) return 0;
+    return (int64_t)mlp_workspace_floats(n_batch) * (int64_t)sizeof(float);
+}
+
+stc_status stc_mlp_forward(void* hip_stream, int64_t n, const uint16_t* d_x, const uint16_t* d_params, float* d_out) {
+    if (n < 0 || (n > 0 && (!d_x || !d_params || !d_out))) return STC_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_x) & 15u) || (reinterpret_cast<uintptr_t>(d_out) & 15u)) return STC_ERR_INVALID_ARG;
+    if (n == 0) return STC_OK;
+    launch_mlp_forward(static_cast<hipStream_t>(hip_stream), d_x, n, nullptr, 0, d_params, d_out);
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
+stc_status stc_mlp_grad(void* hip_stream, int64_t n, const int32_t* d_index, const uint16_t* d_x, const float* d_y,
+                        const uint16_t* d_params, float* d_ws, int64_t ws_bytes, float* d_grad, float* d_loss) {
+    if (n < 1 || n > 0x7fffffffLL || !d_x || !d_y || !d_params || !d_ws || !d_grad) return STC_ERR_INVALID_ARG;
+    if (ws_bytes < stc_mlp_workspace_bytes(n)) return STC_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_x) & 15u) || (reinterpret_cast<uintptr_t>(d_y) & 15u)) return STC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int nw = launch_mlp_grad(s, d_x, d_y, d_index, n, d_params, d_ws);
+    launch_mlp_reduce_adam(s, d_ws, nw, d_grad, d_loss, nullptr, nullptr, nullptr, nullptr, 0.f, 0.9f, 0.999f, 1e-8f, 1);
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
+stc_status stc_mlp_train(void* hip_stream, int64_t n_samples, const uint16_t* d_x, const float* d_y, int32_t epochs,
+                         int32_t batch, float lr, uint64_t seed, float* d_master, float* d_m1, float* d_m2,
+                         uint16_t* d_params, int32_t* d_index, float* d_ws, int64_t ws_bytes, float* d_loss) {
+    if (n_samples < 1 || n_samples > 0x7fffffffLL || epochs < 0 || batch < 1 || !(lr > 0.f) || !d_x || !d_y ||
+        !d_master || !d_m1 || !d_m2 || !d_params || !d_index || !d_ws)
+        return STC_ERR_INVALID_ARG;
+    const i64 nb = std::min<i64>(batch, n_samples);
+    if (ws_bytes < stc_mlp_workspace_bytes(nb)) return STC_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_x) & 15u) || (reinterpret_cast<uintptr_t>(d_y) & 15u)) return STC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const i64 steps = (n_samples + nb - 1) / nb;
+    u64 state = seed * 0x9e3779b97f4a7c15ull + 1;
+    auto next = [&state]() {  // splitmix64
+        u64 z = (state += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    };
+    const u64 n = (u64)n_samples;
+    int step = 0;
+    for (int e = 0; e < epochs; ++e) {
+        // a bijection i -> (a i + c) mod n with gcd(a, n) = 1
+        u64 a = next() % n;
+        auto gcd = [](u64 x, u64 y) {
+            while (y) {
+                const u64 t = x % y;
+                x = y;
+                y = t;
+            }
+            return x;
+        };
+        while (a == 0 || gcd(a, n) != 1) a = (a + 1) % n;
+        const u64 cc = next() % n;
+        for (i64 b = 0; b < steps; ++b) {
+            const i64 base = b * nb;
+            const i64 m = std::min<i64>(nb, n_samples - base);
+            launch_mlp_batch_index(s, n_samples, base, m, n == 1 ? 1 : a, cc, d_index);
+            const int nw = launch_mlp_grad(s, d_x, d_y, d_index, m, d_params, d_ws);
+            ++step;
+            launch_mlp_reduce_adam(s, d_ws, nw, nullptr, d_loss ? d_loss + (step - 1) : nullptr, d_master, d_m1, d_m2,
+                                   d_params, lr, 0.9f, 0.999f, 1e-8f, step);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
 stc_status stc_sync(stc_ctx* c) {
     if (!c) return STC_ERR_INVALID_ARG;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, STC_ERR_DEVICE, "stream synchronisation failed");
@@ -829,8 +1127,9 @@ stc_status stc_list_counts(stc_ctx* c, int64_t counts[4], int64_t kernel_evals[4
     if (st != STC_OK) return st;
     unsigned long long h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     (void)hipMemsetAsync(c->evals, 0, sizeof(h), c->stream);
-    launch_count_evals(c->stream, c->tlist, c->counters + C_TLIST, c->cap, c->W, c->np, c->nbeg, c->nend, 0, c->evals);
-    launch_count_evals(c->stream, c->nlist, c->counters + C_NLIST, c->cap, c->W, c->np, c->nbeg, c->nend, 1,
+    launch_count_evals(c->stream, c->tlist, c->counters + C_TLIST, c->cap, c->W, c->DB, c->cls, c->nbeg, c->nend, 0,
+                       c->evals);
+    launch_count_evals(c->stream, c->nlist, c->counters + C_NLIST, c->cap, c->W, c->DB, c->cls, c->nbeg, c->nend, 1,
                        c->evals + 4);
     if (hipStreamSynchronize(c->stream) != hipSuccess ||
         hipMemcpy(h, c->evals, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
@@ -850,10 +1149,11 @@ stc_status stc_list_counts(stc_ctx* c, int64_t counts[4], int64_t kernel_evals[4
     return STC_OK;
 }
 
-stc_status stc_copy_list(stc_ctx* c, int32_t type, int64_t cap, int64_t* h_pairs, int64_t* n_out) {
+static stc_status copy_list_impl(stc_ctx* c, int32_t type, int64_t cap, int64_t* h_pairs, int32_t* h_class,
+                                 int64_t* n_out) {
     stc_status st = check_ready(c, true);
     if (st != STC_OK) return st;
-    if (type < 0 || type > 3 || cap < 0 || (cap > 0 && !h_pairs) || !n_out)
+    if (type < 0 || type > 3 || cap < 0 || (cap > 0 && !h_pairs && !h_class) || !n_out)
         return fail(c, STC_ERR_INVALID_ARG, "bad list type or buffer");
     st = stc_sync(c);
     if (st != STC_OK) return st;
@@ -872,14 +1172,25 @@ stc_status stc_copy_list(stc_ctx* c, int32_t type, int64_t cap, int64_t* h_pairs
         const u64 key = buf[i];
         if (((key >> c->W) & 1u) != want) continue;
         if (k < cap) {
-            h_pairs[2 * k] = (int64_t)(key >> (c->W + 1));
-            h_pairs[2 * k + 1] = (int64_t)(key & mask);
+            if (h_pairs) {
+                h_pairs[2 * k] = (int64_t)(key >> (c->W + 1 + c->DB));
+                h_pairs[2 * k + 1] = (int64_t)(key & mask);
+            }
+            if (h_class) h_class[k] = (int32_t)((key >> (c->W + 1)) & ((1u << c->DB) - 1u));
         }
         ++k;
     }
     *n_out = k;
-    if (h_pairs == nullptr) return STC_OK;  // size query
-    return k > cap ? fail(c, STC_ERR_CAPACITY, "h_pairs too small") : STC_OK;
+    if (h_pairs == nullptr && h_class == nullptr) return STC_OK;  // size query
+    return k > cap ? fail(c, STC_ERR_CAPACITY, "output buffer too small") : STC_OK;
+}
+
+stc_status stc_copy_list(stc_ctx* c, int32_t type, int64_t cap, int64_t* h_pairs, int64_t* n_out) {
+    return copy_list_impl(c, type, cap, h_pairs, nullptr, n_out);
+}
+
+stc_status stc_copy_list_classes(stc_ctx* c, int32_t type, int64_t cap, int32_t* h_class, int64_t* n_out) {
+    return copy_list_impl(c, type, cap, nullptr, h_class, n_out);
 }
 
 stc_status stc_copy_tree(stc_ctx* c, int64_t n, int32_t* h_perm, int64_t node_cap, int32_t* h_count) {
@@ -921,7 +1232,8 @@ stc_status stc_copy_proxy_charges(stc_ctx* c, int64_t node_id, double* h_w) {
     if (hipMemcpy(&sl, c->slot + node_id, sizeof(i32), hipMemcpyDeviceToHost) != hipSuccess || sl < 0)
         return fail(c, STC_ERR_DEVICE, "copy failed");
     std::vector<Prox> pr(c->np);
-    if (hipMemcpy(pr.data(), c->prox + (size_t)sl * c->np, c->np * sizeof(Prox), hipMemcpyDeviceToHost) != hipSuccess)
+    const size_t rec = (size_t)sl * c->NPT + c->cls.poff[c->fb_class];
+    if (hipMemcpy(pr.data(), c->prox + rec, c->np * sizeof(Prox), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(c, STC_ERR_DEVICE, "copy failed");
     for (int m = 0; m < c->np; ++m) h_w[m] = pr[m].w;
     return STC_OK;

@@ -18,7 +18,9 @@ FP64, FP32 = 0, 1
 DEN_DOT, DEN_DIST2 = 0, 1
 PP, PC, CP, CC = 0, 1, 2, 3
 FLAG_EAGER_RK4 = 1
+FLAG_LEARNED = 2
 MAX_MEMBERS = 64
+CLASS_DEGREES = (4, 6, 8, 10)
 LIST_NAMES = ("PP", "PC", "CP", "CC")
 
 
@@ -31,7 +33,7 @@ class StcError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("degree", ctypes.c_int32), ("n_crit", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("precision", ctypes.c_int32), ("denominator", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("list_capacity", ctypes.c_int64)]
+                ("flags", ctypes.c_int32), ("list_capacity", ctypes.c_int64), ("theta_max", ctypes.c_double)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -66,6 +68,16 @@ def _load():
         "stc_get_launch_config": (I32, [P, I64, ctypes.POINTER(LaunchConfig)]),
         "stc_set_launch_config": (I32, [P, I64, ctypes.POINTER(LaunchConfig)]),
         "stc_autotune": (I32, [P, I32, ctypes.POINTER(LaunchConfig)]),
+        "stc_set_model": (I32, [P, VP]),
+        "stc_learned_samples": (I32, [P, D, I64, VP, VP, VP, PI64]),
+        "stc_copy_candidates": (I32, [P, I64, PI64, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint16), PI64]),
+        "stc_copy_list_classes": (I32, [P, I32, I64, PI32, PI64]),
+        "stc_mlp_param_count": (I32, []),
+        "stc_mlp_workspace_bytes": (I64, [I64]),
+        "stc_mlp_forward": (I32, [VP, I64, VP, VP, VP]),
+        "stc_mlp_grad": (I32, [VP, I64, VP, VP, VP, VP, VP, I64, VP, VP]),
+        "stc_mlp_train": (I32, [VP, I64, VP, VP, I32, I32, ctypes.c_float, ctypes.c_uint64, VP, VP, VP, VP, VP, VP,
+                                I64, VP]),
         "stc_destroy": (I32, [P]),
         "stc_set_stream": (I32, [P, VP]),
         "stc_get_params": (I32, [P, ctypes.POINTER(Params)]),
@@ -207,6 +219,72 @@ def _offsets(offsets, n_rows):
     return off, off.size - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
 
 
+# --- the learned form's network ----------------------------------------------------
+
+def mlp_param_count():
+    return int(_lib.stc_mlp_param_count())
+
+
+def mlp_workspace_bytes(n_batch):
+    return int(_lib.stc_mlp_workspace_bytes(int(n_batch)))
+
+
+def _bf16(t, name, numel=None):
+    import torch
+    if t.dtype not in (torch.bfloat16, torch.int16, torch.uint16):
+        raise TypeError(f"{name} must hold BF16 values (torch.bfloat16)")
+    return _dptr(t, name, None, numel)
+
+
+def mlp_forward(x, params, out=None, stream=None):
+    """Outputs (n, 4) float32 of the network for BF16 rows x (n, 16)."""
+    import torch
+    n = x.shape[0]
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.float32, device=x.device)
+    _check(_lib.stc_mlp_forward(_stream(stream), n, _bf16(x, "x", 16 * n), _bf16(params, "params", mlp_param_count()),
+                                _dptr(out, "out", torch.float32, 4 * n)))
+    return out
+
+
+def mlp_grad(x, y, params, index=None, stream=None):
+    """(gradient (5252,) float32, loss (1,) float32) of the mean loss over rows
+    `index` (int32) of (x, y), or all rows."""
+    import torch
+    n = x.shape[0] if index is None else index.numel()
+    ws = torch.empty(max(1, mlp_workspace_bytes(n) // 4), dtype=torch.float32, device=x.device)
+    grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(_lib.stc_mlp_grad(_stream(stream), n, _dptr(index, "index", torch.int32), _bf16(x, "x"),
+                             _dptr(y, "y", torch.float32), _bf16(params, "params", mlp_param_count()),
+                             _dptr(ws, "ws", torch.float32), ws.numel() * 4, _dptr(grad, "grad", torch.float32),
+                             _dptr(loss, "loss", torch.float32)))
+    return grad, loss
+
+
+def mlp_train(x, y, master, epochs, batch, lr, seed=0, m1=None, m2=None, params=None, stream=None):
+    """Adam training of the FP32 master weights (updated in place) on rows
+    (x, y); returns (BF16 params, per-step losses)."""
+    import torch
+    n = x.shape[0]
+    dev = x.device
+    P = mlp_param_count()
+    m1 = torch.zeros(P, dtype=torch.float32, device=dev) if m1 is None else m1
+    m2 = torch.zeros(P, dtype=torch.float32, device=dev) if m2 is None else m2
+    params = torch.empty(P, dtype=torch.bfloat16, device=dev) if params is None else params
+    nb = min(batch, n)
+    steps = epochs * ((n + nb - 1) // nb)
+    idx = torch.empty(nb, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(1, mlp_workspace_bytes(nb) // 4), dtype=torch.float32, device=dev)
+    losses = torch.empty(max(steps, 1), dtype=torch.float32, device=dev)
+    _check(_lib.stc_mlp_train(_stream(stream), n, _bf16(x, "x", 16 * n), _dptr(y, "y", torch.float32, 4 * n),
+                              int(epochs), int(batch), float(lr), int(seed), _dptr(master, "master", torch.float32, P),
+                              _dptr(m1, "m1", torch.float32, P), _dptr(m2, "m2", torch.float32, P),
+                              _bf16(params, "params", P), _dptr(idx, "index", torch.int32),
+                              _dptr(ws, "ws", torch.float32), ws.numel() * 4, _dptr(losses, "loss", torch.float32)))
+    return params, losses[:steps]
+
+
 class Context:
     """A tree-code context for up to n_max particles (stc_create), or, with
     members > 1, for an ensemble of up to `members` particle sets with
@@ -215,11 +293,12 @@ class Context:
 
     def __init__(self, n_max, theta=0.7, degree=8, n_crit=64, max_level=-1, precision="fp64",
                  denominator="dot", list_capacity=0, stream=None, eager_rk4=False, members=1,
-                 n_max_member=None):
+                 n_max_member=None, learned=False, theta_max=0.0):
         p = Params()
         _lib.stc_default_params(ctypes.byref(p))
         p.theta, p.degree, p.n_crit, p.max_level = theta, degree, n_crit, max_level
-        p.flags = FLAG_EAGER_RK4 if eager_rk4 else 0
+        p.flags = (FLAG_EAGER_RK4 if eager_rk4 else 0) | (FLAG_LEARNED if learned else 0)
+        p.theta_max = theta_max
         p.precision, p.denominator, p.list_capacity = _prec(precision), _den(denominator), list_capacity
         self._ctx = ctypes.c_void_p()
         self._stream_obj = stream
@@ -229,6 +308,9 @@ class Context:
         _lib.stc_get_params(self._ctx, ctypes.byref(q))
         self.theta, self.degree, self.n_crit, self.max_level = q.theta, q.degree, q.n_crit, q.max_level
         self.precision, self.denominator = q.precision, q.denominator
+        self.theta_max = q.theta_max
+        self.learned = learned
+        self._model = None
         self.n_max = n_max
         self.np = n_basis(q.degree)
         nb, npm, nlen = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int64(0)
@@ -343,6 +425,49 @@ class Context:
 
     def local_node(self, node_id):
         return np.asarray(node_id) & ((1 << self.node_bits) - 1)
+
+    # the learned form ----------------------------------------------------------------
+    def set_model(self, params):
+        """BF16 network parameters (5252) used by the traversal, or None."""
+        self._model = params
+        ptr = None if params is None else _bf16(params, "params", mlp_param_count())
+        _check(_lib.stc_set_model(self._ctx, ptr), self._ctx)
+
+    def learned_samples(self, abs_tol, cap):
+        """(features (m,16) bf16, labels (m,4) f32, errors (m,4) f64, number
+        of candidates) on the current tree."""
+        import torch
+        dev = self._keep.device
+        feat = torch.zeros((cap, 16), dtype=torch.bfloat16, device=dev)
+        lab = torch.zeros((cap, 4), dtype=torch.float32, device=dev)
+        err = torch.zeros((cap, 4), dtype=torch.float64, device=dev)
+        n = ctypes.c_int64(0)
+        _check(_lib.stc_learned_samples(self._ctx, float(abs_tol), cap, _dptr(feat, "feat"), _dptr(lab, "lab"),
+                                        _dptr(err, "err"), ctypes.byref(n)), self._ctx)
+        m = min(n.value, cap)
+        return feat[:m], lab[:m], err[:m], n.value
+
+    def copy_candidates(self):
+        n = ctypes.c_int64(0)
+        _check(_lib.stc_copy_candidates(self._ctx, 0, None, None, None, ctypes.byref(n)), self._ctx)
+        m = n.value
+        pairs = np.zeros((max(m, 1), 2), dtype=np.int64)
+        out = np.zeros((max(m, 1), 4), dtype=np.float32)
+        feat = np.zeros((max(m, 1), 16), dtype=np.uint16)
+        _check(_lib.stc_copy_candidates(self._ctx, m, pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                        feat.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)), ctypes.byref(n)),
+               self._ctx)
+        return pairs[:m], out[:m], feat[:m]
+
+    def copy_list_classes(self, kind):
+        k = LIST_NAMES.index(kind) if isinstance(kind, str) else int(kind)
+        nout = ctypes.c_int64(0)
+        _check(_lib.stc_copy_list_classes(self._ctx, k, 0, None, ctypes.byref(nout)), self._ctx)
+        buf = np.zeros(max(nout.value, 1), dtype=np.int32)
+        _check(_lib.stc_copy_list_classes(self._ctx, k, nout.value, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          ctypes.byref(nout)), self._ctx)
+        return buf[:nout.value]
 
     # launch shapes -----------------------------------------------------------------
     def launch_config(self, n_total):

@@ -1,0 +1,148 @@
+"""Pins of the learned form's oracle (CPU): the network's gradient against
+finite differences and closed forms, BF16 rounding, the gated traversal's
+coverage under any decisions, and the pair errors against cases whose answer
+is known."""
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import mlp
+from oracle import learned as OL
+from oracle import tree as otree
+from oracle.tree import polynomial_kernel
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 16))
+    x[:, :12] = rng.uniform(-1, 1, (n, 12))
+    y = (rng.uniform(size=(n, 4)) < 0.5).astype(np.float64)
+    return x, y
+
+
+def test_gradient_matches_finite_differences():
+    x, y = _data(37, 1)
+    th = mlp.init_params(3) + 0.05 * np.random.default_rng(4).standard_normal(mlp.N_PARAMS)
+    g = mlp.grad(th, x, y)
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([rng.choice(np.arange(o, o + int(np.prod(sh))), 12, replace=False)
+                          for o, sh in mlp.SLICES.values() if np.prod(sh) > 12] + [np.arange(5248, 5252)])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(mlp.N_PARAMS)
+        e[i] = h
+        fd = (mlp.loss(th + e, x, y) - mlp.loss(th - e, x, y)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, np.abs(g).max()), i
+
+
+def test_loss_and_output_bias_gradient_closed_form():
+    # all weights zero: outputs = b3 for every row
+    b3 = np.array([0.3, -1.2, 0.7, 2.0])
+    th = mlp.pack({"W1": np.zeros((12, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+                   "W3": np.zeros((64, 4)), "b3": b3})
+    x, y = _data(10, 2)
+    sig = 1 / (1 + np.exp(-b3))
+    soft = np.log1p(np.exp(b3))            # BCE(o, y) = log(1 + e^o) - o y
+    want = np.mean([soft[0] - b3[0] * r[0] + r[0] * sum(soft[k] - b3[k] * r[k] for k in (1, 2, 3)) for r in y])
+    assert abs(mlp.loss(th, x, y) - want) < 1e-14
+    g = mlp.unpack(mlp.grad(th, x, y))["b3"]
+    assert abs(g[0] - np.mean(sig[0] - y[:, 0])) < 1e-14
+    for k in (1, 2, 3):
+        assert abs(g[k] - np.mean(y[:, 0] * (sig[k] - y[:, k]))) < 1e-14
+
+
+def test_bf16_rounding_ties_to_even():
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -7, -2.5, 1 + 2 ** -9])
+    want = np.array([1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -2.5, 1.0])
+    assert np.array_equal(mlp.bf16_round(vals), want)
+    assert np.array_equal(mlp.from_bf16_bits(mlp.bf16_bits(vals)), want)
+
+
+def _coverage(lt, n):
+    c = np.zeros((n, n), dtype=np.int64)
+    for name in ("PP", "PC", "CP", "CC"):
+        for t, s in lt.lists[name]:
+            it, js = lt.ptree.members(t), lt.ptree.members(s)
+            c[np.ix_(it, js)] += 1
+    return c
+
+
+def _case(level=3, seed=7):
+    x = S.icosahedral_grid(level) @ S.random_rotation(seed).T
+    z = S.rossby_haurwitz(x, 4) + S.gaussian_vortex(x, seed=seed, amplitude=1e-4)
+    return x, z, S.uniform_areas(len(x))
+
+
+def test_reject_all_is_the_fixed_degree_method():
+    x, z, a = _case()
+    lt = OL.LearnedTree(x, z, a, theta=0.6, theta_max=0.8, degree=10, n_crit=16)
+    ref = otree.TreeCode(x, z, a, theta=0.6, degree=10, n_crit=16, den="dist2")
+    assert len(lt.candidates) > 0
+    for k in ("PP", "PC", "CP", "CC"):
+        assert np.array_equal(lt.lists[k], ref.lists[k]), k
+        assert (lt.classes[k][lt.classes[k] > -1] == (0 if k == "PP" else 3)).all()
+    assert np.abs(lt.velocity() - ref.velocity()).max() <= 1e-13 * np.abs(ref.velocity()).max()
+
+
+@pytest.mark.parametrize("rule", ["accept_all", "random"])
+def test_any_decisions_cover_every_pair_once(rule):
+    x, z, a = _case()
+    rng = np.random.default_rng(11)
+
+    def decide(F):
+        m = len(F)
+        if rule == "accept_all":
+            return np.ones(m, bool), np.full(m, 2)
+        return rng.uniform(size=m) < 0.6, rng.integers(0, 4, m)
+
+    lt = OL.LearnedTree(x, z, a, theta=0.6, theta_max=0.9, degree=8, n_crit=16, decide=decide)
+    n = len(x)
+    c = _coverage(lt, n)
+    np.testing.assert_array_equal(c, np.ones((n, n), dtype=np.int64))
+    # and the result is a tree-code approximation of the direct sum
+    from oracle import direct
+    ud = direct.velocity(x, z, a, den="dist2")
+    e = np.sqrt(((lt.velocity() - ud) ** 2).sum() / (ud ** 2).sum())
+    assert e < 1e-2
+
+
+def test_pair_errors_vanish_for_a_kernel_in_the_interpolation_space():
+    # K(x, y) = a (x . y)^4 lies in the degree-4 space in both arguments, so
+    # every class (degree >= 4) reproduces it: PC, CP and CC alike
+    x, z, a = _case(level=3, seed=5)
+    lt = OL.LearnedTree(x, z, a, theta=0.6, theta_max=0.9, degree=10, n_crit=16, kernel=polynomial_kernel(4))
+    E = lt.pair_errors()
+    cnt = lt.ptree.count
+    kinds = {(cnt[t] > 16, cnt[s] > 16) for t, s in lt.candidates}
+    assert {(False, True), (True, False), (True, True)} <= kinds
+    scale = np.abs(lt.q).sum()
+    assert E.max() < 1e-11 * scale
+    # degree 5 is outside the degree-4 class: the negative control must fail
+    lt5 = OL.LearnedTree(x, z, a, theta=0.6, theta_max=0.9, degree=10, n_crit=16, kernel=polynomial_kernel(5))
+    assert lt5.pair_errors()[:, 0].max() > 1e-6 * scale
+
+
+def test_pair_errors_fall_with_degree():
+    x, z, a = _case(level=4, seed=3)
+    lt = OL.LearnedTree(x, z, a, theta=0.6, theta_max=0.8, degree=10, n_crit=32)
+    E = lt.pair_errors()
+    med = np.median(E, axis=0)
+    assert med[0] > med[1] > med[2] > med[3]
+    # and the candidates' features sit inside the acceptance region (f6 =
+    # (r_t + r_s)/R < theta_max up to BF16 rounding)
+    F = lt.features
+    assert (F[:, 6] <= 0.8 * (1 + 2 ** -8)).all()
+    assert ((F[:, 9] >= 0) & (F[:, 9] <= 1)).all()
+    np.testing.assert_allclose(F[:, 4] + F[:, 5], F[:, 6], rtol=2 ** -7)
+
+
+def test_labels_from_errors():
+    E = np.array([[1e-9, 1e-10, 1e-11, 1e-12],
+                  [1e-5, 1e-7, 1e-9, 1e-12],
+                  [1e-5, 1e-6, 1e-7, 1e-8],
+                  [1e-5, 1e-9, 1e-6, 1e-6]])
+    y = OL.labels_from_errors(E, 1e-8)
+    np.testing.assert_array_equal(y, [[1, 0, 0, 0], [1, 1, 1, 0], [1, 1, 1, 1], [1, 1, 0, 0]])
+    y = OL.labels_from_errors(E, 1e-13)
+    np.testing.assert_array_equal(y[:, 0], [0, 0, 0, 0])
