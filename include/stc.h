@@ -307,7 +307,8 @@ stc_status stc_mlp_grad(void* hip_stream, int64_t n, const int32_t* d_index, con
  * step a gradient (as stc_mlp_grad) and an Adam update (beta 0.9, 0.999,
  * eps 1e-8, learning rate lr) of the FP32 master weights d_master with
  * moments d_m1, d_m2 (5252 floats each, zero at the start of training), whose
- * BF16 copy is written to d_params.  d_index: batch int32 of scratch.  d_loss
+ * BF16 copy is written to d_params (first from d_master, then after every
+ * step).  d_index: batch int32 of scratch.  d_loss
  * (optional): one float per step, the minibatch loss before the step.
  * Asynchronous on hip_stream. */
 stc_status stc_mlp_train(void* hip_stream, int64_t n_samples, const uint16_t* d_x, const float* d_y,

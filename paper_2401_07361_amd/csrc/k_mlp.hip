@@ -392,9 +392,18 @@ __global__ __launch_bounds__(256) void k_mlp_batch_index(i64 n, i64 base, i64 nb
     idx[i] = (i32)((a * k + c) % (u64)n);
 }
 
+__global__ __launch_bounds__(256) void k_mlp_round(const float* __restrict__ master, u16* __restrict__ P) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P_N) P[p] = f2bf(master[p]);
+}
+
 }  // namespace
 
 int mlp_param_count() { return P_N; }
+
+void launch_mlp_round(hipStream_t s, const float* master, u16* P) {
+    hipLaunchKernelGGL(k_mlp_round, dim3((P_N + 255) / 256), dim3(256), 0, s, master, P);
+}
 
 i64 mlp_workspace_floats(i64 n_batch) {
     const i64 tiles = (n_batch + 15) / 16;

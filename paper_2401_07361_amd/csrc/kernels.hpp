@@ -111,6 +111,7 @@ int launch_mlp_grad(hipStream_t s, const u16* X, const float* Y, const i32* idx,
 void launch_mlp_reduce_adam(hipStream_t s, const float* ws, int nwaves, float* grad, float* loss, float* master,
                             float* m1, float* m2, u16* P, float lr, float beta1, float beta2, float eps, int step);
 void launch_mlp_batch_index(hipStream_t s, i64 n, i64 base, i64 nb, u64 a, u64 c, i32* idx);
+void launch_mlp_round(hipStream_t s, const float* master, u16* P);
 
 // k_learned.hip -- gated traversal of the learned form (single member)
 struct LearnedArgs {

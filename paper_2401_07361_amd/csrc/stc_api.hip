@@ -1078,6 +1078,7 @@ stc_status stc_mlp_train(void* hip_stream, int64_t n_samples, const uint16_t* d_
         return z ^ (z >> 31);
     };
     const u64 n = (u64)n_samples;
+    launch_mlp_round(s, d_master, d_params);  // the BF16 copy the first step reads
     int step = 0;
     for (int e = 0; e < epochs; ++e) {
         // a bijection i -> (a i + c) mod n with gcd(a, n) = 1

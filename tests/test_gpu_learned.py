@@ -1,0 +1,247 @@
+"""GPU learned form: the BF16 network kernels against the oracle network, the
+gated traversal against the oracle's gated tree code, and the measured pair
+errors against the oracle's, through the C ABI.
+
+Bars: network outputs and gradients within the BF16 tolerance of the FP64
+oracle (and closer to the oracle run at the kernels' activation precision);
+without a model the learned context is bitwise the fixed-degree method; with
+a rule network the lists and their degree classes equal the oracle's and the
+FP64 velocity is within 1e-10; pair errors within 1e-9 of the scale.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import learned as OL
+from oracle import mlp as OM
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def bf16_tensor(vals):
+    """BF16 device tensor holding exactly OM.bf16_round(vals)."""
+    bits = OM.bf16_bits(vals).astype(np.int16)
+    return dev(bits).view(torch.bfloat16)
+
+
+def _rows(n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 16))
+    x[:, :12] = rng.uniform(-1, 1, (n, 12))
+    y = (rng.uniform(size=(n, 4)) < 0.5).astype(np.float32)
+    return OM.bf16_round(x), y
+
+
+def _params(seed):
+    th = OM.init_params(seed)
+    th[OM.SLICES["b1"][0]:OM.SLICES["b1"][0] + 64] = np.random.default_rng(seed + 1).normal(0, 0.1, 64)
+    th[OM.SLICES["b2"][0]:OM.SLICES["b2"][0] + 64] = np.random.default_rng(seed + 2).normal(0, 0.1, 64)
+    return OM.bf16_round(th)
+
+
+def _cos(a, b):
+    return float((a * b).sum() / np.sqrt((a * a).sum() * (b * b).sum()))
+
+
+def test_forward_matches_oracle(stc_lib):
+    th = _params(1)
+    x, _ = _rows(1003, 2)
+    out = stc_lib.mlp_forward(bf16_tensor(x), bf16_tensor(th)).cpu().numpy()
+    ref_k, _ = OM.forward(th, x, act_round=OM.bf16_round)   # the kernels' activation precision
+    ref, _ = OM.forward(th, x)                               # plain FP64
+    scale = np.abs(ref).max()
+    assert np.abs(out - ref_k).max() / scale < 1e-5
+    assert np.abs(out - ref).max() / scale < 2e-2
+
+
+@pytest.mark.parametrize("use_index", [False, True])
+def test_gradient_matches_oracle(stc_lib, use_index):
+    th = _params(3)
+    x, y = _rows(2000, 4)
+    idx = np.random.default_rng(5).choice(2000, 777, replace=False).astype(np.int32) if use_index else None
+    g, loss = stc_lib.mlp_grad(bf16_tensor(x), dev(y), bf16_tensor(th), index=None if idx is None else dev(idx))
+    g, loss = g.cpu().numpy(), float(loss.cpu().numpy()[0])
+    xs, ys = (x[idx], y[idx]) if use_index else (x, y)
+    gk = OM.grad(th, xs, ys, act_round=OM.bf16_round)
+    g64 = OM.grad(th, xs, ys)
+    assert abs(loss - OM.loss(th, xs, ys, act_round=OM.bf16_round)) < 1e-5 * abs(loss)
+    for name, (o, sh) in OM.SLICES.items():
+        n = int(np.prod(sh))
+        a, bk, b = g[o:o + n], gk[o:o + n], g64[o:o + n]
+        say(f"  {name}: cos(kernel precision) {_cos(a, bk):.6f} cos(FP64) {_cos(a, b):.6f}")
+        assert _cos(a, bk) > 0.9999, name
+        assert np.abs(a - bk).max() <= 2e-3 * np.abs(bk).max() + 1e-9, name
+        assert _cos(a, b) > 0.999, name
+
+
+def test_training_learns_a_rule(stc_lib):
+    """Labels from a fixed rule on two features; GPU training (forward,
+    backward, Adam) must reach a low loss and a high accuracy."""
+    rng = np.random.default_rng(7)
+    n = 20000
+    x = np.zeros((n, 16))
+    x[:, :12] = rng.uniform(0, 1, (n, 12))
+    x = OM.bf16_round(x)
+    y = np.zeros((n, 4), dtype=np.float32)
+    y[:, 0] = x[:, 6] < 0.6
+    for k in range(3):
+        y[:, k + 1] = y[:, 0] * (x[:, 4] > 0.2 + 0.2 * k)
+    master = dev(OM.init_params(9).astype(np.float32))
+    params, losses = stc_lib.mlp_train(bf16_tensor(x), dev(y), master, epochs=20, batch=1024, lr=3e-3, seed=1)
+    losses = losses.cpu().numpy()
+    say(f"  loss first {losses[0]:.4f} last {losses[-20:].mean():.4f}")
+    assert losses[-20:].mean() < 0.25 * losses[0]
+    out = stc_lib.mlp_forward(bf16_tensor(x), params).cpu().numpy()
+    acc, cls = OM.decide(out)
+    assert (acc == (y[:, 0] > 0)).mean() > 0.97
+    ok = y[:, 0] > 0
+    assert (cls[ok] == y[ok, 1:].sum(1)).mean() > 0.9
+    # the BF16 copy is the rounded master copy
+    assert np.array_equal(OM.bf16_round(master.cpu().numpy()), params.float().cpu().numpy())
+
+
+def _case(level=4, seed=7):
+    x = S.icosahedral_grid(level) @ S.random_rotation(seed).T
+    z = S.rossby_haurwitz(x, 4) + S.gaussian_vortex(x, seed=seed, amplitude=1e-4)
+    return x, z, S.uniform_areas(len(x))
+
+
+KW = dict(theta=0.6, n_crit=16)
+
+
+def test_without_model_equals_fixed_degree(stc_lib):
+    x, z, a = _case()
+    say(f"learned vs fixed degree N={len(x)}")
+    for precision in ("fp64", "fp32"):
+        cl = stc_lib.Context(len(x), degree=10, precision=precision, denominator="dist2", learned=True,
+                             theta_max=0.85, **KW)
+        cp = stc_lib.Context(len(x), degree=10, precision=precision, denominator="dist2", max_level=cl.max_level,
+                             **KW)
+        ul = cl.velocity(dev(x), dev(z), dev(a)).cpu().numpy()
+        up = cp.velocity(dev(x), dev(z), dev(a)).cpu().numpy()
+        assert np.array_equal(ul, up), precision
+        for k in ("PP", "PC", "CP", "CC"):
+            assert np.array_equal(cl.copy_list(k), cp.copy_list(k)), k
+        assert (cl.copy_list_classes("CC") == 3).all()
+        assert cl.list_counts() == cp.list_counts()
+        cl.close()
+        cp.close()
+
+
+def _rule_params(taus):
+    """A network whose decisions are a rule on feature 6, (r_t + r_s) / R:
+    accept iff f6 < tau0, degree class = #{k : f6 > tau_k}; every weight a
+    power of two and every hidden value of one sign, so the decisions do not
+    depend on rounding."""
+    p = {"W1": np.zeros((12, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+         "W3": np.zeros((64, 4)), "b3": np.zeros(4)}
+    for j, tau in enumerate(taus):
+        p["W1"][6, 2 * j], p["b1"][2 * j] = 1.0, -tau          # relu(f6 - tau_j)
+        p["W1"][6, 2 * j + 1], p["b1"][2 * j + 1] = -1.0, tau  # relu(tau_j - f6)
+    for i in range(8):
+        p["W2"][i, i] = 1.0
+    p["W3"][1, 0], p["W3"][0, 0] = 64.0, -64.0                 # o0 = 64 (tau0 - f6)
+    for k in (1, 2, 3):
+        p["W3"][2 * k, k], p["W3"][2 * k + 1, k] = 64.0, -64.0  # ok = 64 (f6 - tau_k)
+    return OM.pack(p)
+
+
+def _gap_thresholds(f6):
+    """Four BF16 thresholds strictly between observed feature values."""
+    vals = np.unique(f6)
+    out = []
+    for q in (0.8, 0.2, 0.45, 0.65):
+        i = int(q * (len(vals) - 1))
+        lo, hi = vals[i], vals[min(i + 1, len(vals) - 1)]
+        cand = OM.bf16_round(np.array([(lo + hi) / 2]))[0]
+        if not (lo < cand < hi):   # adjacent BF16 values: move to the next gap
+            j = i + 1
+            while j + 1 < len(vals):
+                lo, hi = vals[j], vals[j + 1]
+                cand = OM.bf16_round(np.array([(lo + hi) / 2]))[0]
+                if lo < cand < hi:
+                    break
+                j += 1
+        assert lo < cand < hi
+        out.append(float(cand))
+    return out
+
+
+def test_rule_network_lists_and_velocity_match_oracle(stc_lib):
+    x, z, a = _case()
+    say(f"rule network N={len(x)}")
+    # the oracle's own features fix the thresholds
+    probe = OL.LearnedTree(x, z, a, theta_max=0.85, degree=8, den="dist2", **KW)
+    taus = _gap_thresholds(probe.features[:, 6])
+    th = _rule_params(taus)
+
+    def rule(F):
+        f6 = F[:, 6]
+        return f6 < taus[0], (f6[:, None] > np.array(taus[1:])[None, :]).sum(1)
+
+    ot = OL.LearnedTree(x, z, a, theta_max=0.85, degree=8, den="dist2", decide=rule, max_level=probe.max_level,
+                        **KW)
+    assert ot.accept.any() and not ot.accept.all()
+    assert len(np.unique(ot.cls[ot.accept])) >= 3
+    cl = stc_lib.Context(len(x), degree=8, precision="fp64", denominator="dist2", learned=True, theta_max=0.85,
+                         max_level=probe.max_level, **KW)
+    model = bf16_tensor(th)
+    cl.set_model(model)
+    u = cl.velocity(dev(x), dev(z), dev(a)).cpu().numpy()
+    pairs, out, feat = cl.copy_candidates()
+    order = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    assert np.array_equal(pairs[order], ot.candidates)
+    gf = OM.from_bf16_bits(feat[order])
+    assert np.array_equal(gf[:, 6], ot.features[:, 6])
+    # the other features: equal up to one BF16 step (transcendentals may round apart)
+    assert (np.abs(gf - ot.features) <= np.abs(ot.features) * 2 ** -7 + 1e-30).all()
+    for k in ("PP", "PC", "CP", "CC"):
+        got = cl.copy_list(k)
+        cls = cl.copy_list_classes(k)
+        o = np.lexsort((cls, got[:, 1], got[:, 0]))
+        assert np.array_equal(got[o], ot.lists[k]), k
+        assert np.array_equal(cls[o], ot.classes[k]), k
+    ref = ot.velocity()
+    assert np.abs(u - ref).max() / np.abs(ref).max() < 1e-10
+    cl.close()
+
+
+def test_pair_errors_and_labels_match_oracle(stc_lib):
+    x, z, a = _case(level=4, seed=3)
+    say(f"pair errors N={len(x)}")
+    ot = OL.LearnedTree(x, z, a, theta_max=0.8, degree=10, den="dist2", theta=0.6, n_crit=32)
+    E = ot.pair_errors()
+    tol = float(np.median(E[:, 2]))
+    cl = stc_lib.Context(len(x), degree=10, precision="fp64", denominator="dist2", learned=True, theta_max=0.8,
+                         theta=0.6, n_crit=32, max_level=ot.max_level)
+    cl.tree_build(dev(x))
+    cl.upward(dev(z), dev(a))
+    feat, lab, err, n = cl.learned_samples(tol, 4 * len(ot.candidates) + 16)
+    pairs, _, _ = cl.copy_candidates()
+    assert n == len(ot.candidates)
+    o = np.lexsort((pairs[:, 1], pairs[:, 0]))
+    assert np.array_equal(pairs[o], ot.candidates)
+    err = err.cpu().numpy()[o]
+    scale = np.abs(ot.q).sum()
+    assert np.abs(err - E).max() < 1e-9 * scale
+    lab = lab.cpu().numpy()[o]
+    want = OL.labels_from_errors(E, tol)
+    clear = (np.abs(E - tol) > 1e-6 * tol).all(1)
+    assert clear.mean() > 0.95
+    assert np.array_equal(lab[clear], want[clear])
+    fb = feat.view(torch.int16).cpu().numpy().view(np.uint16)
+    assert np.array_equal(OM.from_bf16_bits(fb[o][:, 6]), ot.features[:, 6])
+    cl.close()
