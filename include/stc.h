@@ -249,7 +249,7 @@ stc_status stc_rk4_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offse
  * 4", "above 6", "above 8"); a pair is accepted iff o0 > 0, at degree class
  * #{k : o_k > 0}.  Features of a candidate (t, s), R the chord between the
  * circumcentres, r the circumradii, Q_x the sum of |q| over node x, Q over all
- * particles:  log2 n_t / 16, log2 n_s / 16, level_t / 8, level_s / 8, r_t/R,
+ * particles:  [n_t > n_crit], [n_s > n_crit] (1 or 0), level_t / 8, level_s / 8, r_t/R,
  * r_s/R, (r_t + r_s)/R, -log10 R / 2, log10(Q_s/Q)/8 + 1, |sum_s q|/Q_s,
  * log10(|w_s^(4)|_1 / Q_s)/2 (degree-4 proxy charges; 0 for a small source),
  * log10(Q_t/Q)/8 + 1.  Training loss per row: BCE(o0, y0) + y0 sum_k BCE(o_k,

@@ -21,7 +21,7 @@ Features of a candidate (t, s), computed in FP64, rounded to float32 and then
 to BF16 (R the chord between the circumcentres, r the circumradii, Q_x the
 sum of |q| over node x, Q over all particles, w^(4) the source's degree-4
 proxy charges):
-  0 log2 n_t / 16      1 log2 n_s / 16      2 level_t / 8      3 level_s / 8
+  0 [n_t > N_T]        1 [n_s > N_T]        2 level_t / 8      3 level_s / 8
   4 r_t / R            5 r_s / R            6 (r_t + r_s) / R
   7 -log10 R / 2       8 log10(Q_s / Q) / 8 + 1                9 |sum_s q| / Q_s
  10 log10(|w^(4)|_1 / Q_s) / 2 (0 for a small source)         11 log10(Q_t / Q) / 8 + 1
@@ -213,7 +213,7 @@ class LearnedTree(TreeCode):
             dz = float(ct[2]) - float(cs[2])
             R = float(np.sqrt((dx * dx + dy * dy) + dz * dz))
             qs, qt = self.qabs(s), self.qabs(t)
-            f = [np.log2(cnt[t]) / 16, np.log2(cnt[s]) / 16, self.level(t) / 8, self.level(s) / 8,
+            f = [float(cnt[t] > self.n_crit), float(cnt[s] > self.n_crit), self.level(t) / 8, self.level(s) / 8,
                  rt / R, rs / R, (rt + rs) / R, -_log10(R) / 2,
                  _log10(qs / Q if Q > 0 else 0.0) / 8 + 1,
                  abs(float(self.q[self.ptree.members(s)].sum())) / qs if qs > 0 else 0.0,

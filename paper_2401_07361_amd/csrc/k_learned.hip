@@ -56,7 +56,7 @@ __device__ __forceinline__ u16 f2bf(float f) {
 __device__ __forceinline__ float lg10(double v) { return (float)log10(v > 1e-30 ? v : 1e-30); }
 
 // The 12 features of candidate (t, s), rounded to BF16:
-//   0 log2 n_t / 16         1 log2 n_s / 16        2 level_t / 8     3 level_s / 8
+//   0 [n_t > N_T]           1 [n_s > N_T]          2 level_t / 8     3 level_s / 8
 //   4 r_t / R               5 r_s / R              6 (r_t + r_s) / R (the MAC ratio)
 //   7 -log10 R / 2          8 log10(Q_s / Q) / 8 + 1                 9 |sum_s q| / Q_s
 //  10 log10(|w^(4)|_1 / Q_s) / 2 (0 for a small source)             11 log10(Q_t / Q) / 8 + 1
@@ -77,8 +77,8 @@ __global__ __launch_bounds__(256) void k_features(LearnedArgs a) {
         const double R = sqrt((dx * dx + dy * dy) + dz * dz);
         const i32 nt = a.ncnt[t], ns = a.ncnt[s];
         float f[16];
-        f[0] = log2f((float)nt) / 16.f;
-        f[1] = log2f((float)ns) / 16.f;
+        f[0] = nt > a.n_crit ? 1.f : 0.f;
+        f[1] = ns > a.n_crit ? 1.f : 0.f;
         f[2] = (float)level_of_offset_table(a.level_off_tab, a.L, t) / 8.f;
         f[3] = (float)level_of_offset_table(a.level_off_tab, a.L, s) / 8.f;
         f[4] = (float)(mt.r / R);

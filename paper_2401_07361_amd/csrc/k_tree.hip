@@ -137,6 +137,11 @@ __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i
 // workgroup per node; sources go through LDS in chunks of 64 (barycentric
 // powers), thread t accumulating basis function t % np over every
 // (256/np)-th source.  Proxy records live in the node's storage slot.
+// With src_np > 0 every big node instead takes its own src_np proxy points
+// at record offset src_poff as sources: re-interpolating a higher degree's
+// proxy charges gives a lower degree's exactly (its space is contained in
+// the higher one's), so the learned form's four degrees need one pass over
+// the particles.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int chunk, int lvl, int L, int NB,
                                                        i64 child_off, const i32* __restrict__ nbeg,
@@ -144,7 +149,8 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                                                        const NodeGeo* __restrict__ geo, const double* __restrict__ sx,
                                                        const double* __restrict__ sy, const double* __restrict__ sz,
                                                        const double* __restrict__ q, RefDev ref, int NPT, int poff,
-                                                       const i32* __restrict__ slot, Prox* __restrict__ prox) {
+                                                       int src_poff, int src_np, const i32* __restrict__ slot,
+                                                       Prox* __restrict__ prox) {
     __shared__ double pw[64][3][kMaxDegree + 1];
     __shared__ double qs[64];
     __shared__ double red[256];
@@ -182,7 +188,14 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
             int seg_kind[4], seg_cnt[4];
             i64 seg_id[4];
             int nseg = 0;
-            if (lvl == L) {
+            int rpoff = poff;  // record offset of proxy sources
+            if (src_np > 0) {
+                seg_kind[0] = 1;
+                seg_id[0] = node;
+                seg_cnt[0] = src_np;
+                nseg = 1;
+                rpoff = src_poff;
+            } else if (lvl == L) {
                 seg_kind[0] = 0;
                 seg_id[0] = b;
                 seg_cnt[0] = e - b;
@@ -223,7 +236,7 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                         y2 = sz[j];
                         qq = q[j];
                     } else {
-                        const Prox pr = prox[(size_t)slot[seg_id[sgi]] * NPT + poff + idx];
+                        const Prox pr = prox[(size_t)slot[seg_id[sgi]] * NPT + rpoff + idx];
                         y0 = pr.x;
                         y1 = pr.y;
                         y2 = pr.z;
@@ -550,19 +563,22 @@ void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, c
 
 void launch_upward(hipStream_t s, int members, int NB, const i32* nbeg, const i32* nend, const i64* level_off_host,
                    int L, int n_crit, const NodeGeo* geo, const double* sx, const double* sy, const double* sz,
-                   const double* q, RefDev ref, int NPT, int poff, const i32* slot, Prox* prox) {
+                   const double* q, RefDev ref, int NPT, int poff, int src_poff, int src_np, const i32* slot,
+                   Prox* prox) {
     for (int lvl = L; lvl >= 0; --lvl) {
         const i64 node0 = level_off_host[lvl];
         const i64 nn = level_off_host[lvl + 1] - node0;
         const i64 child_off = lvl < L ? level_off_host[lvl + 1] : 0;
-        // few nodes: one workgroup per node; many: 256 nodes per workgroup,
-        // checked in parallel, the big ones processed in turn
-        const int chunk = nn > 8192 ? 256 : 1;
+        // the nodes of a level in chunks (checked in parallel, the big ones
+        // processed in turn), at most ~16k workgroups per member: one node per
+        // workgroup on coarse levels, a few on fine ones, so that the big
+        // nodes of any level spread over the whole chip
+        const i64 target = std::max<i64>(1, 16384 / members);
+        const int chunk = (int)std::min<i64>(256, std::max<i64>(1, (nn + target - 1) / target));
         const i64 nchunks = (nn + chunk - 1) / chunk;
-        const i64 per_member = std::max<i64>(1, 4096 / members);
-        const unsigned grid = (unsigned)(nchunks < per_member ? nchunks : per_member);
-        hipLaunchKernelGGL(k_upward_level, dim3(grid, (unsigned)members), dim3(256), 0, s, node0, nn, chunk, lvl, L,
-                           NB, child_off, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff, slot, prox);
+        hipLaunchKernelGGL(k_upward_level, dim3((unsigned)nchunks, (unsigned)members), dim3(256), 0, s, node0, nn,
+                           chunk, lvl, L, NB, child_off, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff,
+                           src_poff, src_np, slot, prox);
     }
 }
 

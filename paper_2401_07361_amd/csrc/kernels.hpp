@@ -29,7 +29,8 @@ void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i3
 void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area, double* q);
 void launch_upward(hipStream_t s, int members, int NB, const i32* nbeg, const i32* nend, const i64* level_off_host,
                    int L, int n_crit, const NodeGeo* geo, const double* sx, const double* sy, const double* sz,
-                   const double* q, RefDev ref, int NPT, int poff, const i32* slot, Prox* prox);
+                   const double* q, RefDev ref, int NPT, int poff, int src_poff, int src_np, const i32* slot,
+                   Prox* prox);
 void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, i32* ncnt,
                         i32* slot, u32 slot_cap, u32* flags);
 // Traversal: the root pairs of every member into front0 (counters zeroed),

@@ -281,11 +281,17 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
     hipStream_t s = c->stream;
     mark(c, 1);
     launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sq);
-    if (c->n > 0)
-        for (int k = 0; k < c->ndeg; ++k)
+    if (c->n > 0) {
+        // the highest class from the particles; the others (learned form) by
+        // re-interpolating each node's own record of the highest class
+        const int top = c->ndeg - 1;
+        launch_upward(s, c->members, c->NB, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit, c->geo,
+                      c->sx, c->sy, c->sz, c->sq, ref_dev(c, top), c->NPT, c->cls.poff[top], 0, 0, c->slot, c->prox);
+        for (int k = 0; k < top; ++k)
             launch_upward(s, c->members, c->NB, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit,
-                          c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, k), c->NPT, c->cls.poff[k], c->slot,
-                          c->prox);
+                          c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, k), c->NPT, c->cls.poff[k],
+                          c->cls.poff[top], c->cls.np[top], c->slot, c->prox);
+    }
     if (c->learned && c->n > 0)
         launch_node_charge_sums(s, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->sq, c->qabs, c->qsum);
     c->have_upward = true;

@@ -1,0 +1,87 @@
+"""Training the learned form's gating network on the GPU.
+
+The training data are measured by the tree code itself: for each input,
+stc_learned_samples takes the candidates of the wider criterion theta_max,
+measures every candidate's error at the four degrees against its exact pair
+sum and labels it against a tolerance; stc_mlp_train then runs Adam with the
+library's BF16 forward and backward kernels.  This module only sequences
+those calls over a set of inputs (device tensors the caller provides).
+"""
+
+import numpy as np
+
+from . import stc
+
+
+def velocity_scale(u):
+    """4 pi times the root mean square speed: the size of W (the sum before
+    the cross product), the unit the label tolerance is given in."""
+    un = u.double().cpu().numpy()
+    return 4.0 * np.pi * float(np.sqrt((un * un).sum(1).mean()))
+
+
+def collect(inputs, tol_rel, theta, theta_max, degree=10, n_crit=64, cap_per_input=None, log=None):
+    """Features (m, 16) BF16 and labels (m, 4) float32 from every input
+    (x, zeta, area); the label tolerance of an input is tol_rel times its
+    velocity scale (from a fixed-degree evaluation of the same context)."""
+    import torch
+    feats, labs = [], []
+    for i, (x, z, a) in enumerate(inputs):
+        n = x.shape[0]
+        cap = cap_per_input or 4 * n
+        ctx = stc.Context(n, theta=theta, theta_max=theta_max, degree=degree, n_crit=n_crit, precision="fp64",
+                          denominator="dist2", learned=True)
+        u = ctx.velocity(x, z, a)            # no model: the fixed-degree method
+        scale = velocity_scale(u)
+        ctx.tree_build(x)
+        ctx.upward(z, a)
+        f, y, _, m = ctx.learned_samples(tol_rel * scale, cap)
+        ctx.close()
+        feats.append(f.clone())
+        labs.append(y.clone())
+        if log:
+            yn = y.cpu().numpy()
+            log(f"input {i}: N={n} candidates {m} accepted {yn[:, 0].mean():.3f} "
+                f"class mean {(yn[:, 1:].sum(1)[yn[:, 0] > 0]).mean():.2f}")
+    return torch.cat(feats), torch.cat(labs)
+
+
+def train(features, labels, epochs=8, batch=4096, lr=2e-3, seed=0, init_seed=1):
+    """Trained BF16 parameters and the per-step losses."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(init_seed))
+    p = np.zeros(stc.mlp_param_count(), dtype=np.float32)
+    # He initialisation of the three weight blocks, zero biases
+    p[0:768] = rng.standard_normal(768) * np.sqrt(2.0 / 12)
+    p[832:4928] = rng.standard_normal(4096) * np.sqrt(2.0 / 64)
+    p[4992:5248] = rng.standard_normal(256) * np.sqrt(2.0 / 64)
+    master = torch.from_numpy(p).to(features.device)
+    params, losses = stc.mlp_train(features, labels, master, epochs, batch, lr, seed=seed)
+    return params, losses
+
+
+def calibrate(features, labels, params, max_false_accept=1e-3, max_under_class=1e-3):
+    """Shifts the output biases so that, on the given samples, at most
+    max_false_accept of them are accepted against their label and at most
+    max_under_class of the correctly accepted ones get a lower degree class
+    than labelled: b3[0] -= delta_a, b3[1..3] += delta_c with the smallest
+    such deltas.  Returns new BF16 parameters and the two shifts."""
+    import torch
+    out = stc.mlp_forward(features, params).cpu().numpy().astype(np.float64)
+    y = labels.cpu().numpy()
+    acc = y[:, 0] > 0
+    need = y[:, 1:].sum(1)
+    deltas = np.concatenate([[0.0], np.geomspace(1e-3, 64.0, 200)])
+    da = next((d for d in deltas if ((out[:, 0] - d > 0) & ~acc).mean() <= max_false_accept), deltas[-1])
+    keep = acc & (out[:, 0] - da > 0)
+    dc = 0.0
+    if keep.any():
+        dc = next((d for d in deltas
+                   if ((out[keep, 1:] + d > 0).sum(1) < need[keep]).mean() <= max_under_class), deltas[-1])
+    p = params.float().cpu().numpy().astype(np.float64)
+    p[5248] -= da
+    p[5249:5252] += dc
+    bits = np.asarray(p, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    bits = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype(np.int16)
+    newp = torch.from_numpy(bits).to(params.device).view(torch.bfloat16)
+    return newp, float(da), float(dc)

@@ -34,7 +34,7 @@ from .fields import (
     gaussian_pair,
     lonlat,
 )
-from .workloads import make_workload, make_ensemble, make_member, WORKLOADS
+from .workloads import make_workload, make_ensemble, make_member, make_gate_training_input, WORKLOADS
 
 __all__ = [
     "icosahedron_vertices", "icosahedral_grid", "grid_size", "uniform_areas",
@@ -42,5 +42,5 @@ __all__ = [
     "clustered_sphere_points", "subset_indices", "OMEGA_EARTH_S",
     "OMEGA_EARTH_DAY", "rossby_haurwitz", "rossby_haurwitz_paper",
     "gaussian_vortex", "gaussian_vortex_paper", "gaussian_pair", "lonlat",
-    "make_workload", "make_ensemble", "make_member", "WORKLOADS",
+    "make_workload", "make_ensemble", "make_member", "make_gate_training_input", "WORKLOADS",
 ]

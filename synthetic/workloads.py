@@ -109,3 +109,21 @@ def make_ensemble(members=48, seed0=4, levels=(5, 6, 7)):
     return dict(x=np.concatenate([r["x"] for r in mem]), zeta=np.concatenate([r["zeta"] for r in mem]),
                 area=np.concatenate([r["area"] for r in mem]), offsets=off, members=mem,
                 dt=1800.0, steps=24)
+
+
+def make_gate_training_input(k, level=7, seed0=100):
+    """Training input k of the learned form: an icosahedral grid of the given
+    level under a random rotation, A = 4 pi / N, a Rossby-Haurwitz wave of
+    wavenumber 3, 4 or 5 plus one to three Gaussian vortices (width 0.1) of
+    amplitude +-(0.5..1.5) x 4 pi per day at random centres (seed seed0 + k)."""
+    seed = seed0 + k
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = icosahedral_grid(level) @ random_rotation(seed).T
+    z = rossby_haurwitz(x, int(rng.integers(3, 6)))
+    zv = 4.0 * np.pi / 86400.0
+    for _ in range(int(rng.integers(1, 4))):
+        c = rng.standard_normal(3)
+        c /= np.linalg.norm(c)
+        amp = zv * rng.uniform(0.5, 1.5) * (1 if rng.uniform() < 0.5 else -1)
+        z = z + amp * np.exp(-(great_circle_distance(x, c) / 0.1) ** 2)
+    return x, z, uniform_areas(len(x))
