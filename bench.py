@@ -8,6 +8,13 @@ One step = one full velocity evaluation (tree build, upward pass, traversal,
 near and far field, output) on inputs already resident in HBM.  Prints one
 JSON line.  Single GPU only.
 
+``--workload learned`` times the learned form: the gating network is trained
+on the GPU from six seeded N = 163842 inputs (samples labelled by the tree
+code's measured pair errors), then one step is a learned-form evaluation at
+N = 2621442 (Gaussian vortex pair on a Rossby-Haurwitz background), checked
+against the FP64 direct sum and the fixed-degree-10 FP64 tree, and set
+beside the fixed-degree method in FP32 and FP64.
+
 ``--workload ensemble`` times the batching form instead: 48 seeded members
 (levels 5-7, 3.87e6 particles in total, random rotations, RH waves of
 wavenumber 3-5 plus a Gaussian bump), all members in one launch per phase,
@@ -196,6 +203,98 @@ def bench_ensemble(args):
     print(json.dumps(result), flush=True)
 
 
+LEARNED = dict(theta=0.7, theta_max=0.9, degree=10, n_crit=64, tol_rel=3e-8, train_inputs=6, epochs=8,
+               batch=4096, lr=2e-3)
+
+
+def _timed(ctx, fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    ctx.set_timing(steps)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ph, k = ctx.phase_times()
+    return t0.elapsed_time(t1) / steps, {p: round(v / max(k, 1), 4) for p, v in ph.items()}
+
+
+def bench_learned(args):
+    import torch
+    import synthetic as S
+    from paper_2401_07361_amd import stc, gate_training as G
+    from oracle import metrics
+
+    P = LEARNED
+    t0 = time.perf_counter()
+    inputs = []
+    for k in range(P["train_inputs"]):
+        x, z, a = S.make_gate_training_input(k)
+        inputs.append(tuple(torch.from_numpy(v).cuda() for v in (x, z, a)))
+    F, Y = G.collect(inputs, P["tol_rel"], P["theta"], P["theta_max"], degree=P["degree"], n_crit=P["n_crit"],
+                     log=log)
+    torch.cuda.synchronize()
+    t_samples = time.perf_counter() - t0
+    del inputs
+    t1 = time.perf_counter()
+    params, losses = G.train(F, Y, epochs=P["epochs"], batch=P["batch"], lr=P["lr"])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    params, da, dc = G.calibrate(F, Y, params, 1e-3, 1e-3)
+    ln = losses.cpu().numpy()
+    log(f"{F.shape[0]} samples in {t_samples:.2f} s, {len(ln)} training steps in {t_train:.2f} s, "
+        f"loss {ln[0]:.3f} -> {ln[-50:].mean():.3f}")
+    wl = S.make_workload("gvpair_l9")
+    x, z, a, sub = wl["x"], wl["zeta"], wl["area"], wl["subset"]
+    n = len(x)
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    ud = stc.direct(xd, zd, ad, targets=torch.from_numpy(sub).cuda(), denominator="dist2").cpu().numpy()
+    out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    rows = {}
+
+    def run(name, model=None, **kw):
+        ctx = stc.Context(n, denominator="dist2", n_crit=P["n_crit"], **kw)
+        if model is not None:
+            ctx.set_model(model)
+        ms, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, args.warmup)
+        cnt, ev = ctx.list_counts()
+        u = out.cpu().numpy()
+        rows[name] = dict(ms=round(ms, 4), rel_l2_err_vs_fp64_direct=float(f"{metrics.rel_l2_velocity(u[sub], ud, a[sub]):.3e}"),
+                          kernel_evals=int(sum(ev.values())), phase_ms=ph)
+        log(f"{name}: {ms:.3f} ms, E = {rows[name]['rel_l2_err_vs_fp64_direct']}, evals {sum(ev.values()) / 1e9:.3f}e9")
+        ctx.close()
+        return u
+
+    uj = run("fixed_fp64_theta0.7_d10", theta=0.7, degree=10, precision="fp64")
+    run("fixed_fp32_theta0.8_d10", theta=0.8, degree=10, precision="fp32")
+    ul64 = run("learned_fp64", model=params, theta=P["theta"], theta_max=P["theta_max"], degree=P["degree"],
+               precision="fp64", learned=True)
+    ul = run("learned_fp32", model=params, theta=P["theta"], theta_max=P["theta_max"], degree=P["degree"],
+             precision="fp32", learned=True)
+    e_judge = metrics.rel_l2_velocity(ul, uj, a)
+    r = rows["learned_fp32"]
+    result = dict(
+        metric="particle velocity evals/s at N=2621442 with learned degree/acceptance gating, rel-L2 err <=1e-6 vs FP64 direct sum",
+        value=n / (r["ms"] / 1e3), unit="velocity evals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=r["ms"], higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="gvpair_l9 (Gaussian vortex pair + RH n=4, icosahedral level 9)", N=n,
+                    **{k: v for k, v in P.items()}, rel_l2_err_vs_fp64_direct=r["rel_l2_err_vs_fp64_direct"],
+                    rel_l2_err_vs_fixed_degree_fp64_tree=float(f"{e_judge:.3e}"),
+                    err_ok=bool(r["rel_l2_err_vs_fp64_direct"] <= 1e-6 and e_judge <= 1e-6),
+                    training=dict(samples=int(F.shape[0]), seconds_samples=round(t_samples, 3),
+                                  seconds_train=round(t_train, 3), steps=len(ln),
+                                  loss_first=float(f"{ln[0]:.4f}"), loss_last=float(f"{ln[-50:].mean():.4f}"),
+                                  calibration=dict(accept_shift=da, class_shift=dc)),
+                    runs=rows),
+    )
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +306,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble"])
+    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned"])
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -217,6 +316,9 @@ def main():
         sys.exit(2)
     if args.workload == "ensemble":
         bench_ensemble(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
 
     import torch

@@ -37,7 +37,8 @@ enum Flag : int {
     F_NONFINITE = 0,  // a particle position lies in no root face
     F_SLOTS = 1,      // more nodes with proxy charges than storage slots
     F_SLOT_CTR = 2,   // next free storage slot (counter)
-    F_COUNT = 8
+    F_LEVEL = 8,      // F_LEVEL + l: nodes of level l with more than N_T particles (list length)
+    F_COUNT = 24
 };
 
 // counter slots in the context's u32 counter array

@@ -368,8 +368,10 @@ struct L2PShared {
     u32 wtot[4];
 };
 
-// class `cls` (degree D) of node nd (local id ndl) for this thread's particle
-template <int D, int NPM>
+// class `cls` (degree D) of node nd (local id ndl) for this thread's particle;
+// SKIP: return at once when no particle of the block has work in this class
+// (worth the extra barrier only when there are several classes)
+template <int D, bool SKIP, int NPM>
 __device__ __forceinline__ void l2p_class(const EvalArgs& a, int cls, bool valid, i64 nd, i64 ndl, double x0,
                                           double x1, double x2, double& W0, double& W1, double& W2,
                                           L2PShared<NPM>& sh) {
@@ -377,6 +379,7 @@ __device__ __forceinline__ void l2p_class(const EvalArgs& a, int cls, bool valid
     const int tid = threadIdx.x;
     const int poff = STC_PICK4(a.cls.poff, cls);
     const bool has = valid && a.nseg_end[(nd << a.DB) | cls] != 0;
+    if (SKIP && !__syncthreads_or(has)) return;
     // the first particle of each node with far work opens a slot
     sh.slot_node[tid] = has ? nd : (i64)-1;
     __syncthreads();
@@ -446,10 +449,11 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
         for (int lvl = 0; lvl <= L; ++lvl) {
             const i64 ndl = a.level_off_tab[lvl] + (i64)(kl >> (2 * (L - lvl)));  // local id
             const i64 nd = mbase + ndl;
-            l2p_class<D0>(a, 0, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D1 > 0) l2p_class<D1 ? D1 : 1>(a, 1, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D2 > 0) l2p_class<D2 ? D2 : 1>(a, 2, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D3 > 0) l2p_class<D3 ? D3 : 1>(a, 3, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            constexpr bool SK = D1 > 0;
+            l2p_class<D0, SK>(a, 0, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D1 > 0) l2p_class<D1 ? D1 : 1, SK>(a, 1, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D2 > 0) l2p_class<D2 ? D2 : 1, SK>(a, 2, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D3 > 0) l2p_class<D3 ? D3 : 1, SK>(a, 3, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
         }
     }
     if (!valid) return;

@@ -143,8 +143,10 @@ __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i
 // the higher one's), so the learned form's four degrees need one pass over
 // the particles.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int chunk, int lvl, int L, int NB,
-                                                       i64 child_off, const i32* __restrict__ nbeg,
+__global__ __launch_bounds__(256) void k_upward_level(int lvl_lo, int lvl_hi, int L, int NB,
+                                                       const i64* __restrict__ level_off_tab,
+                                                       const u32* __restrict__ flags, const i32* __restrict__ big_list,
+                                                       u32 per_level, const i32* __restrict__ nbeg,
                                                        const i32* __restrict__ nend, int n_crit,
                                                        const NodeGeo* __restrict__ geo, const double* __restrict__ sx,
                                                        const double* __restrict__ sy, const double* __restrict__ sz,
@@ -156,8 +158,6 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
     __shared__ double red[256];
     __shared__ double omega[kMaxNp][1];
     __shared__ double wout[kMaxNp][1];
-    __shared__ i32 big[256];
-    __shared__ int nbig;
     const int tid = threadIdx.x;
     const int d = ref.degree, np = ref.np;
     const int S = 256 / np;  // source slices
@@ -168,22 +168,16 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
         e1 = ref.expo[3 * k + 1];
         e2 = ref.expo[3 * k + 2];
     }
-    const i64 mbase = (i64)blockIdx.y << NB;
-    for (i64 base = (i64)blockIdx.x * chunk; base < nnodes; base += (i64)gridDim.x * chunk) {
-        // the nodes of this chunk with more than N_T particles, found in parallel
-        if (tid == 0) nbig = 0;
-        __syncthreads();
-        if (tid < chunk && base + tid < nnodes) {
-            const i64 nd = mbase + node0 + base + tid;
-            if (nend[nd] - nbeg[nd] > n_crit) big[atomicAdd(&nbig, 1)] = (i32)(base + tid);
-        }
-        __syncthreads();
-        const int nb = nbig;
-        for (int bi = 0; bi < nb; ++bi) {
-            const i64 t = big[bi];
-            const i64 node = mbase + node0 + t;
+    const u32 lm = (1u << NB) - 1u;
+    for (int lvl = lvl_hi; lvl >= lvl_lo; --lvl) {
+        u32 nbl = flags[F_LEVEL + lvl];
+        if (nbl > per_level) nbl = per_level;
+        for (u32 bi = blockIdx.x; bi < nbl; bi += gridDim.x) {
+            const i64 node = big_list[(size_t)lvl * per_level + bi];
+            const i64 local = node & lm, mbase = node & ~(i64)lm;
+            const i64 t = local - level_off_tab[lvl];  // index within the level
             const i32 b = nbeg[node], e = nend[node];
-            const NodeGeo& g = geo[node0 + t];
+            const NodeGeo& g = geo[local];
             // source segments: kind 0 = particle range [first, first+cnt), 1 = points of node `id`
             int seg_kind[4], seg_cnt[4];
             i64 seg_id[4];
@@ -201,8 +195,9 @@ __global__ __launch_bounds__(256) void k_upward_level(i64 node0, i64 nnodes, int
                 seg_cnt[0] = e - b;
                 nseg = 1;
             } else {
+                const i64 child_off = mbase + level_off_tab[lvl + 1];
                 for (int c = 0; c < 4; ++c) {
-                    const i64 cid = mbase + child_off + 4 * t + c;
+                    const i64 cid = child_off + 4 * t + c;
                     const i32 cb = nbeg[cid], cn = nend[cid] - cb;
                     if (cn <= 0) continue;
                     if (cn > n_crit) {
@@ -455,12 +450,16 @@ __global__ __launch_bounds__(256) void k_trav_level(
     }
 }
 
-// Per-node particle count, and a storage slot for the proxy records and
-// target coefficients of every node with more than N_T particles (slots are
-// handed out in any order; only where a node's data lives depends on it).
+// Per-node particle count, and for every node with more than N_T particles a
+// storage slot for its proxy records and target coefficients and an entry in
+// its level's list (the upward pass walks those lists).  Slots and list
+// positions are handed out in any order; only where a node's data lives
+// depends on it.
 __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbeg, const i32* __restrict__ nend,
-                                                      i64 n_nodes, int n_crit, i32* __restrict__ ncnt,
-                                                      i32* __restrict__ slot, u32 slot_cap, u32* __restrict__ flags) {
+                                                      i64 n_nodes, int n_crit, int NB, int L,
+                                                      const i64* __restrict__ level_off_tab, i32* __restrict__ ncnt,
+                                                      i32* __restrict__ slot, u32 slot_cap, i32* __restrict__ big_list,
+                                                      u32 per_level, u32* __restrict__ flags) {
     const u64 stride = (u64)gridDim.x * blockDim.x;
     for (u64 b0 = (u64)blockIdx.x * blockDim.x; b0 < (u64)n_nodes; b0 += stride) {
         const u64 i = b0 + threadIdx.x;
@@ -472,6 +471,20 @@ __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbe
         if (ok) {
             ncnt[i] = c;
             slot[i] = big ? (i32)(sl < slot_cap ? sl : slot_cap - 1) : -1;
+        }
+        // level lists: the lanes of a wave at the level of its first big node
+        // share one atomic (node ids run level by level, so that is nearly all)
+        const int lvl = big ? level_of_offset_table(level_off_tab, L, (i64)(i & (((u64)1 << NB) - 1))) : -1;
+        const u64 bm = __ballot(big);
+        if (bm) {
+            const int l0 = __shfl(lvl, __ffsll((unsigned long long)bm) - 1, 64);
+            const bool same = big && lvl == l0;
+            u32 pos = wave_append(&flags[F_LEVEL + l0], same);
+            if (big && !same) pos = atomicAdd(&flags[F_LEVEL + lvl], 1u);
+            if (big) {
+                if (pos < per_level) big_list[(size_t)lvl * per_level + pos] = (i32)i;
+                else atomicOr(&flags[F_SLOTS], 1u);
+            }
         }
     }
 }
@@ -561,25 +574,24 @@ void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, c
     hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, q);
 }
 
-void launch_upward(hipStream_t s, int members, int NB, const i32* nbeg, const i32* nend, const i64* level_off_host,
-                   int L, int n_crit, const NodeGeo* geo, const double* sx, const double* sy, const double* sz,
-                   const double* q, RefDev ref, int NPT, int poff, int src_poff, int src_np, const i32* slot,
-                   Prox* prox) {
-    for (int lvl = L; lvl >= 0; --lvl) {
-        const i64 node0 = level_off_host[lvl];
-        const i64 nn = level_off_host[lvl + 1] - node0;
-        const i64 child_off = lvl < L ? level_off_host[lvl + 1] : 0;
-        // the nodes of a level in chunks (checked in parallel, the big ones
-        // processed in turn), at most ~16k workgroups per member: one node per
-        // workgroup on coarse levels, a few on fine ones, so that the big
-        // nodes of any level spread over the whole chip
-        const i64 target = std::max<i64>(1, 16384 / members);
-        const int chunk = (int)std::min<i64>(256, std::max<i64>(1, (nn + target - 1) / target));
-        const i64 nchunks = (nn + chunk - 1) / chunk;
-        hipLaunchKernelGGL(k_upward_level, dim3((unsigned)nchunks, (unsigned)members), dim3(256), 0, s, node0, nn,
-                           chunk, lvl, L, NB, child_off, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff,
-                           src_poff, src_np, slot, prox);
+void launch_upward(hipStream_t s, int NB, const i64* level_off_dev, const u32* flags, const i32* big_list,
+                   u32 per_level, const i32* nbeg, const i32* nend, int L, int n_crit, const NodeGeo* geo,
+                   const double* sx, const double* sy, const double* sz, const double* q, RefDev ref, int NPT,
+                   int poff, int src_poff, int src_np, const i32* slot, Prox* prox) {
+    // one workgroup per listed node (a fixed grid walks the list); levels
+    // bottom-up, or, to re-interpolate (reads only each node's own record),
+    // all levels in one launch
+    const unsigned grid = (unsigned)std::min<u32>(std::max<u32>(per_level, 1u), 2048u);
+    if (src_np > 0) {
+        hipLaunchKernelGGL(k_upward_level, dim3(grid), dim3(256), 0, s, 0, L, L, NB, level_off_dev, flags, big_list,
+                           per_level, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff, src_poff, src_np,
+                           slot, prox);
+        return;
     }
+    for (int lvl = L; lvl >= 0; --lvl)
+        hipLaunchKernelGGL(k_upward_level, dim3(grid), dim3(256), 0, s, lvl, lvl, L, NB, level_off_dev, flags,
+                           big_list, per_level, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff, src_poff,
+                           src_np, slot, prox);
 }
 
 void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v) {
@@ -594,11 +606,12 @@ void launch_fill_f64(hipStream_t s, double* p, i64 n, double v) {
     hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, p, n, v);
 }
 
-void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, i32* ncnt,
-                        i32* slot, u32 slot_cap, u32* flags) {
+void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, int NB, int L,
+                        const i64* level_off_dev, i32* ncnt, i32* slot, u32 slot_cap, i32* big_list, u32 per_level,
+                        u32* flags) {
     const i64 b = blocks_for(n_nodes, 256);
     hipLaunchKernelGGL(k_node_counts, dim3((unsigned)(b < 2048 ? b : 2048)), dim3(256), 0, s, nbeg, nend, n_nodes,
-                       n_crit, ncnt, slot, slot_cap, flags);
+                       n_crit, NB, L, level_off_dev, ncnt, slot, slot_cap, big_list, per_level, flags);
 }
 
 void launch_traverse_init(hipStream_t s, const TravArgs& t) {

@@ -24,6 +24,8 @@ struct stc_ctx {
     i64 n_nodes = 0;      // length of the per-node arrays: ((max_members - 1) << NB) + n_local
     i64 used_nodes = 0;   // the part the last build touched
     u32 slot_cap = 0;     // nodes with proxy charges that fit the proxy / coefficient storage
+    u32 per_level = 0;    // capacity of each level's list of such nodes
+    i32* big_list = nullptr;
     u32 cap = 0;
     hipStream_t stream = nullptr;
     int cus = 256;
@@ -273,7 +275,8 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
                SortScratch{c->hist, c->hist_totals, c->hist_blocks}, &c->keys_sorted);
     launch_gather(s, c->keys_sorted, n, d_x, c->perm, c->leaf, c->sx, c->sy, c->sz);
     launch_node_ranges(s, c->leaf, n, c->L, c->NB, c->nbeg, c->nend);
-    launch_node_counts(s, c->nbeg, c->nend, c->used_nodes, c->p.n_crit, c->ncnt, c->slot, c->slot_cap, c->flags);
+    launch_node_counts(s, c->nbeg, c->nend, c->used_nodes, c->p.n_crit, c->NB, c->L, c->level_off, c->ncnt, c->slot,
+                       c->slot_cap, c->big_list, c->per_level, c->flags);
     return check_launch(c, "tree_build");
 }
 
@@ -285,11 +288,12 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
         // the highest class from the particles; the others (learned form) by
         // re-interpolating each node's own record of the highest class
         const int top = c->ndeg - 1;
-        launch_upward(s, c->members, c->NB, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit, c->geo,
-                      c->sx, c->sy, c->sz, c->sq, ref_dev(c, top), c->NPT, c->cls.poff[top], 0, 0, c->slot, c->prox);
+        launch_upward(s, c->NB, c->level_off, c->flags, c->big_list, c->per_level, c->nbeg, c->nend, c->L,
+                      c->p.n_crit, c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, top), c->NPT, c->cls.poff[top], 0, 0,
+                      c->slot, c->prox);
         for (int k = 0; k < top; ++k)
-            launch_upward(s, c->members, c->NB, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->p.n_crit,
-                          c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, k), c->NPT, c->cls.poff[k],
+            launch_upward(s, c->NB, c->level_off, c->flags, c->big_list, c->per_level, c->nbeg, c->nend, c->L,
+                          c->p.n_crit, c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, k), c->NPT, c->cls.poff[k],
                           c->cls.poff[top], c->cls.np[top], c->slot, c->prox);
     }
     if (c->learned && c->n > 0)
@@ -545,7 +549,8 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     // nodes with more than n_crit particles are disjoint within a level:
     // at most n_max / (n_crit + 1) per level over all members
     const i64 nm = std::max<i64>(n_max_total, 1);
-    c->slot_cap = (u32)std::min<i64>((i64)(c->L + 1) * (nm / (p->n_crit + 1)) + 1, 0x7fffffffLL);
+    c->per_level = (u32)std::min<i64>(nm / (p->n_crit + 1) + 1, 0x7fffffffLL);
+    c->slot_cap = (u32)std::min<i64>((i64)(c->L + 1) * c->per_level, 0x7fffffffLL);
     i64 cap = p->list_capacity > 0 ? p->list_capacity : std::max<i64>(65536, 16 * n_max_total);
     c->cap = (u32)std::min<i64>(cap, 0x7fffffffLL);
     try {
@@ -568,6 +573,7 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     const i64 nseg = c->n_nodes << c->DB;
     bool ok = dalloc(c, &c->geo, c->geo_host.size()) && dalloc(c, &c->mac, c->geo_host.size()) &&
               dalloc(c, &c->ncnt, c->n_nodes) && dalloc(c, &c->slot, c->n_nodes) &&
+              dalloc(c, &c->big_list, (size_t)(c->L + 1) * c->per_level) &&
               dalloc(c, &c->level_off, c->level_off_host.size()) && dalloc(c, &c->ref_points, 3 * NPT) &&
               dalloc(c, &c->ref_vinv, nq) && dalloc(c, &c->ref_vinvT, nq) && dalloc(c, &c->ref_coef, NPT) &&
               dalloc(c, &c->ref_expo, 3 * NPT) && dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) &&

@@ -290,4 +290,4 @@ def test_trained_gate_gains_over_fixed_degree(stc_lib):
     assert e_direct <= 1e-6
     assert e_judge <= 1e-6
     assert sum(el.values()) < 0.6 * sum(ej.values())
-    assert min(cls["CC"][:3]) > 0   # the network uses several degrees
+    assert sum(1 for c in cls["CC"] if c > 0) >= 3   # the network uses several degrees
