@@ -105,17 +105,38 @@ __global__ __launch_bounds__(256) void k_features(LearnedArgs a) {
     }
 }
 
+// exclusive prefix of v over the 256 threads of the block, *total = sum
+__device__ __forceinline__ u32 scan256(u32 v, u32* wsum, u32* total) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    u32 incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const u32 t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    u32 b = 0, tot = 0;
+    for (int k = 0; k < 4; ++k) {
+        const u32 x = wsum[k];
+        if (k < w) b += x;
+        tot += x;
+    }
+    *total = tot;
+    return b + incl - v;
+}
+
 // Accepted candidates (o0 > 0; degree class = number of positive ordinal
 // logits) become list entries; the others go to the fallback frontier.
+// Slots come from one atomic per list per 256 candidates.
 __global__ __launch_bounds__(256) void k_resolve(LearnedArgs a, int use_model) {
+    __shared__ u32 wsum[3][4];
+    __shared__ u32 bases[3];
     u32 n = a.counters[C_CAND];
     if (n > a.cap) n = a.cap;
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    const u64 smask = ((u64)1 << a.W) - 1;
-    (void)smask;
+    const int tid = threadIdx.x;
     bool overflow = false;
-    for (u64 b0 = (u64)blockIdx.x * blockDim.x; b0 < n; b0 += stride) {
-        const u64 i = b0 + threadIdx.x;
+    for (u64 b0 = (u64)blockIdx.x * 256; b0 < n; b0 += (u64)gridDim.x * 256) {
+        const u64 i = b0 + tid;
         const bool ok = i < n;
         u64 pr = 0;
         bool acc = false;
@@ -134,23 +155,34 @@ __global__ __launch_bounds__(256) void k_resolve(LearnedArgs a, int use_model) {
         const bool to_t = ok && acc && kind == 1;
         const bool to_n = ok && acc && kind >= 2;
         const bool to_f = ok && !acc;
-        const u32 st = wave_append(&a.counters[C_TLIST], to_t);
-        const u32 sn = wave_append(&a.counters[C_NLIST], to_n);
-        const u32 sf = wave_append(&a.counters[C_FRONT2], to_f);
+        u32 tt, tn, tf;
+        const u32 pt = scan256(to_t ? 1u : 0u, wsum[0], &tt);
+        const u32 pn = scan256(to_n ? 1u : 0u, wsum[1], &tn);
+        const u32 pf = scan256(to_f ? 1u : 0u, wsum[2], &tf);
+        if (tid == 0) {
+            bases[0] = tt ? atomicAdd(&a.counters[C_TLIST], tt) : 0u;
+            bases[1] = tn ? atomicAdd(&a.counters[C_NLIST], tn) : 0u;
+            bases[2] = tf ? atomicAdd(&a.counters[C_FRONT2], tf) : 0u;
+        }
+        __syncthreads();
         const u64 t = pr >> 32, s = pr & 0xffffffffu;
         const u64 key = (t << (a.W + 1 + a.DB)) | ((u64)dc << (a.W + 1)) | ((u64)(kind & 1) << a.W) | s;
         if (to_t) {
+            const u32 st = bases[0] + pt;
             if (st < a.cap) a.tlist[st] = key;
             else overflow = true;
         }
         if (to_n) {
+            const u32 sn = bases[1] + pn;
             if (sn < a.cap) a.nlist[sn] = key;
             else overflow = true;
         }
         if (to_f) {
+            const u32 sf = bases[2] + pf;
             if (sf < a.cap) a.front[sf] = pr;
             else overflow = true;
         }
+        __syncthreads();  // wsum / bases reused by the next round
     }
     if (overflow) atomicOr(&a.counters[C_OVERFLOW], 1u);
 }

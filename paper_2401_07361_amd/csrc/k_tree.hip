@@ -280,6 +280,60 @@ __global__ __launch_bounds__(256) void k_upward_level(int lvl_lo, int lvl_hi, in
 }
 
 // ---------------------------------------------------------------------------
+// Lower-degree proxy charges from the degree-10 ones (learned form).  The
+// degree-d interpolant's space lies inside the degree-10 one, so the degree-d
+// charges are the degree-10 point charges re-interpolated:
+//   w_d,m = |P_d,m|^d sum_n T_mn w_10,n / |P_10,n|^d,
+// P = b_1 v_1 + b_2 v_2 + b_3 v_3 the unnormalised point of reference
+// barycentrics b, and T_mn = sum_k (V_ref,d^{-1})_km B_k(b_10,n) a fixed
+// reference matrix (the multinomial-scaled basis is homogeneous of degree d,
+// so the node's geometry enters only through |P|).  One wave per node.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_downsample(int L, int NB, const u32* __restrict__ flags,
+                                                     const i32* __restrict__ big_list, u32 per_level,
+                                                     const NodeGeo* __restrict__ geo, const i32* __restrict__ slot,
+                                                     const double* __restrict__ ref_points, const double* __restrict__ T,
+                                                     ClassTab cls, int NPT, Prox* __restrict__ prox) {
+    __shared__ double src[4][3][kMaxNp];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const u32 lm = (1u << NB) - 1u;
+    const int np10 = cls.np[3], poff10 = cls.poff[3];
+    const int nout = cls.poff[3];  // points of classes 0..2
+    for (int lvl = 0; lvl <= L; ++lvl) {
+        u32 nbl = flags[F_LEVEL + lvl];
+        if (nbl > per_level) nbl = per_level;
+        for (u32 b0 = blockIdx.x * 4; b0 < nbl; b0 += gridDim.x * 4) {
+            const u32 bi = b0 + w;
+            const bool ok = bi < nbl;
+            const i64 node = ok ? big_list[(size_t)lvl * per_level + bi] : 0;
+            const NodeGeo& g = geo[node & lm];
+            const size_t rec = ok ? (size_t)slot[node] * NPT : 0;
+            for (int n = lane; n < np10 && ok; n += 64) {
+                double y[3];
+                const double nrm = proxy_point(g, ref_points + 3 * (poff10 + n), y);
+                const double w10 = prox[rec + poff10 + n].w;
+                for (int c = 0; c < 3; ++c) src[w][c][n] = w10 / ipow(nrm, cls.deg[c]);
+            }
+            __syncthreads();
+            for (int o = lane; o < nout && ok; o += 64) {
+                const int c = o < cls.poff[1] ? 0 : (o < cls.poff[2] ? 1 : 2);
+                double acc = 0.0;
+                for (int n = 0; n < np10; ++n) acc += T[(size_t)o * np10 + n] * src[w][c][n];
+                double y[3];
+                const double nrm = proxy_point(g, ref_points + 3 * o, y);
+                Prox pr;
+                pr.x = y[0];
+                pr.y = y[1];
+                pr.z = y[2];
+                pr.w = ipow(nrm, cls.deg[c]) * acc;
+                prox[rec + o] = pr;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Dual tree traversal (Sec. 3), level-synchronous.  Iteration k reads the
 // frontier of node pairs and, per pair (t, s):
 //   well separated: (r_t + r_s)^2 < theta^2 R^2 (FP64, no contraction) ->
@@ -592,6 +646,14 @@ void launch_upward(hipStream_t s, int NB, const i64* level_off_dev, const u32* f
         hipLaunchKernelGGL(k_upward_level, dim3(grid), dim3(256), 0, s, lvl, lvl, L, NB, level_off_dev, flags,
                            big_list, per_level, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff, src_poff,
                            src_np, slot, prox);
+}
+
+void launch_downsample(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
+                       const NodeGeo* geo, const i32* slot, const double* ref_points, const double* T, ClassTab cls,
+                       int NPT, Prox* prox) {
+    const unsigned grid = (unsigned)std::min<u32>(std::max<u32>((per_level + 3) / 4, 1u), 2048u);
+    hipLaunchKernelGGL(k_downsample, dim3(grid), dim3(256), 0, s, L, NB, flags, big_list, per_level, geo, slot,
+                       ref_points, T, cls, NPT, prox);
 }
 
 void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v) {

@@ -31,6 +31,9 @@ void launch_upward(hipStream_t s, int NB, const i64* level_off_dev, const u32* f
                    u32 per_level, const i32* nbeg, const i32* nend, int L, int n_crit, const NodeGeo* geo,
                    const double* sx, const double* sy, const double* sz, const double* q, RefDev ref, int NPT,
                    int poff, int src_poff, int src_np, const i32* slot, Prox* prox);
+void launch_downsample(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
+                       const NodeGeo* geo, const i32* slot, const double* ref_points, const double* T, ClassTab cls,
+                       int NPT, Prox* prox);
 void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, int NB, int L,
                         const i64* level_off_dev, i32* ncnt, i32* slot, u32 slot_cap, i32* big_list, u32 per_level,
                         u32* flags);

@@ -44,6 +44,7 @@ struct stc_ctx {
     u16* feat = nullptr;          // their features (BF16, 16 per candidate)
     float* mlp_out = nullptr;     // network outputs per candidate
     double *qabs = nullptr, *qsum = nullptr;  // per-node charge sums
+    double* ref_T = nullptr;      // degree-10 -> lower-degree re-interpolation matrices
     const uint16_t* model = nullptr;  // BF16 network parameters (caller's), or null: reject every candidate
     std::vector<i64> level_off_host;
     // device buffers (all allocated in stc_create)
@@ -291,10 +292,9 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
         launch_upward(s, c->NB, c->level_off, c->flags, c->big_list, c->per_level, c->nbeg, c->nend, c->L,
                       c->p.n_crit, c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, top), c->NPT, c->cls.poff[top], 0, 0,
                       c->slot, c->prox);
-        for (int k = 0; k < top; ++k)
-            launch_upward(s, c->NB, c->level_off, c->flags, c->big_list, c->per_level, c->nbeg, c->nend, c->L,
-                          c->p.n_crit, c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, k), c->NPT, c->cls.poff[k],
-                          c->cls.poff[top], c->cls.np[top], c->slot, c->prox);
+        if (top > 0)
+            launch_downsample(s, c->L, c->NB, c->flags, c->big_list, c->per_level, c->geo, c->slot, c->ref_points,
+                              c->ref_T, c->cls, c->NPT, c->prox);
     }
     if (c->learned && c->n > 0)
         launch_node_charge_sums(s, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->sq, c->qabs, c->qsum);
@@ -590,7 +590,7 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
               dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
               dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm);
     if (ok && learned)
-        ok = dalloc(c, &c->cand, c->cap) && dalloc(c, &c->feat, (size_t)c->cap * 16) &&
+        ok = dalloc(c, &c->ref_T, (size_t)c->cls.poff[3] * c->cls.np[3]) && dalloc(c, &c->cand, c->cap) && dalloc(c, &c->feat, (size_t)c->cap * 16) &&
              dalloc(c, &c->mlp_out, (size_t)c->cap * 4) && dalloc(c, &c->qabs, c->n_nodes) &&
              dalloc(c, &c->qsum, c->n_nodes);
     if (!ok) {
@@ -627,6 +627,27 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
               up(c->ref_vinvT, vinvT_h.data(), vinvT_h.size() * sizeof(double)) &&
               up(c->ref_coef, coef_h.data(), coef_h.size() * sizeof(double)) &&
               up(c->ref_expo, expo_h.data(), expo_h.size() * sizeof(int));
+    // learned form: T[(poff_c + m) * 66 + n] = sum_k (V_ref,d^{-1})_km B_k(b_10,n),
+    // degree-10 point charges -> degree-d (classes 0..2), in long double
+    std::vector<double> T_h;
+    if (learned) {
+        const RefTables& t10 = c->ref_host[3];
+        for (int k = 0; k < 3; ++k) {
+            const RefTables& td = c->ref_host[k];
+            for (int m = 0; m < td.np; ++m)
+                for (int n = 0; n < t10.np; ++n) {
+                    long double acc = 0.0L;
+                    for (int kk = 0; kk < td.np; ++kk) {
+                        long double B = td.coef[kk];
+                        for (int a = 0; a < 3; ++a)
+                            for (int e = 0; e < td.expo[3 * kk + a]; ++e) B *= (long double)t10.points[3 * n + a];
+                        acc += (long double)td.vinv[(size_t)kk * td.np + m] * B;
+                    }
+                    T_h.push_back((double)acc);
+                }
+        }
+        cp = cp && up(c->ref_T, T_h.data(), T_h.size() * sizeof(double));
+    }
     launch_fill_u32(s, c->counters, C_COUNT, 0u);
     launch_fill_u32(s, c->flags, F_COUNT, 0u);
     if (!cp || hipStreamSynchronize(s) != hipSuccess) {
