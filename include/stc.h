@@ -100,7 +100,7 @@ typedef struct stc_ctx stc_ctx;
  * PC; target proxies: CP and CC): workgroup size (128, 256 or 512 threads;
  * one LDS source tile and one batch of list entries per workgroup hold that
  * many items) and workgroups per compute unit (1..64; the grid is rounded up
- * to a multiple of 8, one slot per XCD).  Default {256, 12, 256, 12}.  The
+ * to a multiple of 8, one slot per XCD).  Default {256, 48, 256, 48}.  The
  * shape changes only the grouping of the FP32/FP64 partial sums, not what is
  * summed. */
 typedef struct stc_launch_config {
@@ -326,8 +326,8 @@ stc_status stc_get_launch_config(const stc_ctx* ctx, int64_t n_total, stc_launch
  * for classes without one. */
 stc_status stc_set_launch_config(stc_ctx* ctx, int64_t n_total, const stc_launch_config* cfg);
 
-/* Times every candidate shape (workgroup sizes 128/256/512 x 4, 8, 12, 16 or
- * 24 workgroups per CU, for each of the two kernels) on the lists of the last
+/* Times every candidate shape (workgroup sizes 128/256/512 x 8, 16, 24, 32,
+ * 48 or 64 workgroups per CU, for each of the two kernels) on the lists of the last
  * traversal, `repeats` launches each after one warm-up, keeps the fastest
  * for the current size class (the precision and degree are the context's)
  * and writes it to *out.  Needs stc_upward and stc_traverse (or a velocity

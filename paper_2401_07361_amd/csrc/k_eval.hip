@@ -62,28 +62,48 @@ __device__ __forceinline__ void interact(const Src<T>& s, T tx, T ty, T tz, T& p
     pz += w * dz;
 }
 
-// sum over staged sources j = sl, sl + S, ... < cnt.  The main loop has the
-// same trip count (cnt / S) in every lane, so it unrolls; the at most one
-// remaining source per lane follows.
-template <typename T, int DEN, bool SELF>
-__device__ __forceinline__ void tile_sum(const Src<T>* __restrict__ tile, int cnt, int sl, int S, T tx, T ty, T tz,
-                                         int self_j, double& ax, double& ay, double& az) {
-    T px = T(0), py = T(0), pz = T(0);
-    const int m = cnt / S;
-    int j = sl;
+// Sum over this slice's staged sources for the thread's TP targets (each
+// source read from LDS once and used for all of them): slice sl takes the
+// contiguous block [sl m, (sl + 1) m) of the tile, m = cnt / S (the same trip
+// count in every lane, so the loop unrolls with constant LDS offsets from one
+// base), then at most one of the cnt - S m remaining sources, S m + sl.  With
+// SELF, source self_j[k] is skipped for target k (the j = i exclusion).
+template <typename T, int DEN, bool SELF, int TP>
+__device__ __forceinline__ void tile_sum(const Src<T>* __restrict__ tile, int cnt, int sl, int S, const T* tx,
+                                         const T* ty, const T* tz, const int* self_j, double* ax, double* ay,
+                                         double* az) {
+    T px[TP], py[TP], pz[TP];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) px[k] = py[k] = pz[k] = T(0);
     if (!SELF) {
+        const int m = cnt / S;
+        const Src<T>* __restrict__ blk = tile + sl * m;
 #pragma unroll 4
-        for (int it = 0; it < m; ++it, j += S) interact<T, DEN>(tile[j], tx, ty, tz, px, py, pz);
-        if (j < cnt) interact<T, DEN>(tile[j], tx, ty, tz, px, py, pz);
+        for (int it = 0; it < m; ++it) {
+            const Src<T> src = blk[it];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) interact<T, DEN>(src, tx[k], ty[k], tz[k], px[k], py[k], pz[k]);
+        }
+        const int j = S * m + sl;
+        if (j < cnt) {
+            const Src<T> src = tile[j];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) interact<T, DEN>(src, tx[k], ty[k], tz[k], px[k], py[k], pz[k]);
+        }
     } else {
-        for (; j < cnt; j += S) {
-            if (j == self_j) continue;  // the j = i term is excluded
-            interact<T, DEN>(tile[j], tx, ty, tz, px, py, pz);
+        for (int j = sl; j < cnt; j += S) {
+            const Src<T> src = tile[j];
+#pragma unroll
+            for (int k = 0; k < TP; ++k)
+                if (j != self_j[k]) interact<T, DEN>(src, tx[k], ty[k], tz[k], px[k], py[k], pz[k]);
         }
     }
-    ax += (double)px;
-    ay += (double)py;
-    az += (double)pz;
+#pragma unroll
+    for (int k = 0; k < TP; ++k) {
+        ax[k] += (double)px[k];
+        ay[k] += (double)py[k];
+        az[k] += (double)pz[k];
+    }
 }
 
 __device__ __forceinline__ u32 logical_block() {
@@ -93,7 +113,7 @@ __device__ __forceinline__ u32 logical_block() {
 
 // LDS of a segment kernel with NTT threads: one NTT-source tile, one batch of
 // NTT list entries
-template <typename T, int NTT>
+template <typename T, int NTT, int TP>
 struct SegShared {
     Src<T> tile[NTT];
     u32 ent_s[NTT];        // source node of a particle entry, storage slot of a proxy entry
@@ -101,7 +121,7 @@ struct SegShared {
     u32 ent_pre[NTT + 1];  // exclusive prefix of the entries' source counts
     u32 wave_tot[NTT / 64];
     int self_flag;
-    double red[3][NTT];
+    double red[TP][3][NTT];  // per-slice partial sums of each thread's TP targets
 };
 
 // exclusive prefix over the NTT threads; returns the prefix, *total the sum
@@ -148,17 +168,18 @@ __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 firs
     return v;
 }
 
-// Accumulates, for this thread's target (tx, ty, tz), every entry of [e0, e1)
-// in `list` whose type bit is in type_mask.  Entries are taken in batches of
+// Accumulates, for this thread's TP targets, every entry of [e0, e1) in
+// `list` whose type bit is in type_mask.  Entries are taken in batches of
 // NTT: their source counts are scanned into an LDS prefix, so that for each
 // NTT-source tile every thread stages exactly one source (its entry found by
 // binary search) and all global loads of a tile are in flight together.  A
 // PP entry whose source is the target leaf itself (self_t) is evaluated on
-// its own with the j != i exclusion (me: the thread's target index there).
-template <typename T, int DEN, int NTT>
+// its own with the j != i exclusion (me: the targets' indices there).
+template <typename T, int DEN, int NTT, int TP>
 __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ list, u32 e0, u32 e1, u32 type_mask,
-                                   u32 self_t, int me, bool act, int sl, int S, T tx, T ty, T tz, double cx,
-                                   double cy, double cz, SegShared<T, NTT>& sh, double& ax, double& ay, double& az) {
+                                   u32 self_t, const int* me, bool act, int sl, int S, const T* tx, const T* ty,
+                                   const T* tz, double cx, double cy, double cz, SegShared<T, NTT, TP>& sh, double* ax,
+                                   double* ay, double* az) {
     const int tid = threadIdx.x;
     const u64 mask = ((u64)1 << a.W) - 1;
     const u32 cmask = (1u << a.DB) - 1u;
@@ -201,7 +222,10 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                 const int cnt = (nsrc - j0) < NTT ? (nsrc - j0) : NTT;
                 if (tid < cnt) sh.tile[tid] = load_source<T>(a, self_t, tb, j0 + tid, cx, cy, cz, qscale);
                 __syncthreads();
-                if (act) tile_sum<T, DEN, true>(sh.tile, cnt, sl, S, tx, ty, tz, me - j0, ax, ay, az);
+                int sj[TP];
+#pragma unroll
+                for (int k = 0; k < TP; ++k) sj[k] = me[k] - j0;
+                if (act) tile_sum<T, DEN, true, TP>(sh.tile, cnt, sl, S, tx, ty, tz, sj, ax, ay, az);
                 __syncthreads();
             }
         }
@@ -219,11 +243,32 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                                               cz, qscale);
             }
             __syncthreads();
-            if (act) tile_sum<T, DEN, false>(sh.tile, cnt, sl, S, tx, ty, tz, -1, ax, ay, az);
+            if (act) tile_sum<T, DEN, false, TP>(sh.tile, cnt, sl, S, tx, ty, tz, nullptr, ax, ay, az);
             __syncthreads();
         }
     }
 }
+
+// A pass over up to TP x NTT targets: thread (ti, sl) takes targets ti,
+// ti + h, ... (h = ceil(ntc / TP)) and source slice sl of S = NTT / h.
+// Targets past ntc duplicate the first one and are not written back.
+template <int TP>
+struct TargetGroup {
+    int h, S, ti, sl, me[TP];
+    bool act, valid[TP];
+    __device__ TargetGroup(int ntc, int nthreads, int base) {
+        h = (ntc + TP - 1) / TP;
+        S = nthreads / h;
+        ti = threadIdx.x % h;
+        sl = threadIdx.x / h;
+        act = sl < S;
+#pragma unroll
+        for (int k = 0; k < TP; ++k) {
+            valid[k] = ti + k * h < ntc;
+            me[k] = base + (valid[k] ? ti + k * h : ti);
+        }
+    }
+};
 
 // range of list entries of this workgroup (segments: key >> sh); returns
 // false if empty
@@ -238,9 +283,13 @@ __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_
     return true;
 }
 
+constexpr int NEAR_TP = 1;  // targets per thread: leaves are small, occupancy matters more
+constexpr int FAR_TP = 2;   // the proxy points of a node: each staged source feeds two targets
+
 template <typename T, int DEN, int NT>
 __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
-    __shared__ SegShared<T, NT> sh;
+    constexpr int TP = NEAR_TP;
+    __shared__ SegShared<T, NT, TP> sh;
     const int tid = threadIdx.x;
     u32 n = a.counters[C_TLIST];
     if (n > a.cap) n = a.cap;
@@ -255,31 +304,46 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
         const int nt = a.nend[t] - tb;
         const NodeGeo& gt = a.geo[t & a.node_mask];
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
-        for (int cb = 0; cb < nt; cb += NT) {
-            const int ntc = (nt - cb) < NT ? (nt - cb) : NT;
-            const int S = NT / ntc;
-            const int ti = tid % ntc, sl = tid / ntc;
-            const bool act = sl < S;
-            const int me = cb + ti;
-            const i32 gi = tb + me;
-            const T tx = (T)(a.sx[gi] - cx), ty = (T)(a.sy[gi] - cy), tz = (T)(a.sz[gi] - cz);
-            double ax = 0.0, ay = 0.0, az = 0.0;
-            accumulate_entries<T, DEN, NT>(a, a.tlist, e, se, type_mask, t, me, act, sl, S, tx, ty, tz, cx, cy, cz,
-                                           sh, ax, ay, az);
-            sh.red[0][tid] = act ? ax : 0.0;
-            sh.red[1][tid] = act ? ay : 0.0;
-            sh.red[2][tid] = act ? az : 0.0;
+        for (int cb = 0; cb < nt; cb += TP * NT) {
+            const int ntc = (nt - cb) < TP * NT ? (nt - cb) : TP * NT;
+            const TargetGroup<TP> tg(ntc, NT, cb);
+            T tx[TP], ty[TP], tz[TP];
+            int me[TP];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) {
+                const i32 gi = tb + tg.me[k];
+                tx[k] = (T)(a.sx[gi] - cx);
+                ty[k] = (T)(a.sy[gi] - cy);
+                tz[k] = (T)(a.sz[gi] - cz);
+                me[k] = tg.valid[k] ? tg.me[k] : -1;  // a duplicate target's exclusion never matches
+            }
+            double ax[TP], ay[TP], az[TP];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) ax[k] = ay[k] = az[k] = 0.0;
+            accumulate_entries<T, DEN, NT, TP>(a, a.tlist, e, se, type_mask, t, me, tg.act, tg.sl, tg.S, tx, ty, tz,
+                                               cx, cy, cz, sh, ax, ay, az);
+#pragma unroll
+            for (int k = 0; k < TP; ++k) {
+                sh.red[k][0][tid] = tg.act ? ax[k] : 0.0;
+                sh.red[k][1][tid] = tg.act ? ay[k] : 0.0;
+                sh.red[k][2][tid] = tg.act ? az[k] : 0.0;
+            }
             __syncthreads();
-            if (act && sl == 0) {
-                double sx = 0.0, sy = 0.0, sz = 0.0;
-                for (int k = 0; k < S; ++k) {
-                    sx += sh.red[0][k * ntc + ti];
-                    sy += sh.red[1][k * ntc + ti];
-                    sz += sh.red[2][k * ntc + ti];
+            if (tg.act && tg.sl == 0) {
+#pragma unroll
+                for (int k = 0; k < TP; ++k) {
+                    if (!tg.valid[k]) continue;
+                    double sx = 0.0, sy = 0.0, sz = 0.0;
+                    for (int q = 0; q < tg.S; ++q) {
+                        sx += sh.red[k][0][q * tg.h + tg.ti];
+                        sy += sh.red[k][1][q * tg.h + tg.ti];
+                        sz += sh.red[k][2][q * tg.h + tg.ti];
+                    }
+                    const size_t gi = (size_t)(tb + tg.me[k]);
+                    a.Wacc[3 * gi + 0] += sx;
+                    a.Wacc[3 * gi + 1] += sy;
+                    a.Wacc[3 * gi + 2] += sz;
                 }
-                a.Wacc[3 * (size_t)gi + 0] += sx;
-                a.Wacc[3 * (size_t)gi + 1] += sy;
-                a.Wacc[3 * (size_t)gi + 2] += sz;
             }
             __syncthreads();
         }
@@ -289,7 +353,8 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
 
 template <typename T, int DEN, int NTT>
 __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
-    __shared__ SegShared<T, NTT> sh;
+    constexpr int TP = FAR_TP;
+    __shared__ SegShared<T, NTT, TP> sh;
     __shared__ double wt[kMaxNp][3];
     __shared__ double co[kMaxNp][3];
     __shared__ double nd[kMaxNp];
@@ -309,40 +374,54 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
         const u32 se = (u32)a.nseg_end[vt];
         const NodeGeo& gt = a.geo[t & a.node_mask];
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
-        // target points in chunks of at most NTT/4, so that full chunks keep
-        // every thread busy with 4 source slices
-        for (int cb = 0; cb < np; cb += NTT / 4) {
-            const int ntc = (np - cb) < NTT / 4 ? (np - cb) : NTT / 4;
-            const int S = NTT / ntc;
-            const int ti = tid % ntc, sl = tid / ntc;
-            const bool act = sl < S;
-            const int me = cb + ti;
-            double y[3];
-            const double nrm = proxy_point(gt, a.ref.points + 3 * (poff + me), y);
-            if (act && sl == 0) nd[me] = ipow(nrm, d);
-            const T tx = (T)(y[0] - cx), ty = (T)(y[1] - cy), tz = (T)(y[2] - cz);
-            double ax = 0.0, ay = 0.0, az = 0.0;
-            accumulate_entries<T, DEN, NTT>(a, a.nlist, e, se, 3u, 0xffffffffu, me, act, sl, S, tx, ty, tz, cx, cy,
-                                            cz, sh, ax, ay, az);
-            sh.red[0][tid] = act ? ax : 0.0;
-            sh.red[1][tid] = act ? ay : 0.0;
-            sh.red[2][tid] = act ? az : 0.0;
+        // target points in passes of up to TP NTT / 4 (degree 10 with 256
+        // threads: all 66 points in one pass, 33 target pairs x 7 slices)
+        for (int cb = 0; cb < np; cb += TP * NTT / 4) {
+            const int ntc = (np - cb) < TP * NTT / 4 ? (np - cb) : TP * NTT / 4;
+            const TargetGroup<TP> tg(ntc, NTT, cb);
+            T tx[TP], ty[TP], tz[TP];
+            int nome[TP];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) {
+                double y[3];
+                const double nrm = proxy_point(gt, a.ref.points + 3 * (poff + tg.me[k]), y);
+                if (tg.act && tg.sl == 0 && tg.valid[k]) nd[tg.me[k]] = ipow(nrm, d);
+                tx[k] = (T)(y[0] - cx);
+                ty[k] = (T)(y[1] - cy);
+                tz[k] = (T)(y[2] - cz);
+                nome[k] = -1;
+            }
+            double ax[TP], ay[TP], az[TP];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) ax[k] = ay[k] = az[k] = 0.0;
+            accumulate_entries<T, DEN, NTT, TP>(a, a.nlist, e, se, 3u, 0xffffffffu, nome, tg.act, tg.sl, tg.S, tx, ty,
+                                                tz, cx, cy, cz, sh, ax, ay, az);
+#pragma unroll
+            for (int k = 0; k < TP; ++k) {
+                sh.red[k][0][tid] = tg.act ? ax[k] : 0.0;
+                sh.red[k][1][tid] = tg.act ? ay[k] : 0.0;
+                sh.red[k][2][tid] = tg.act ? az[k] : 0.0;
+            }
             __syncthreads();
-            if (act && sl == 0) {
-                double sx = 0.0, sy = 0.0, sz = 0.0;
-                for (int k = 0; k < S; ++k) {
-                    sx += sh.red[0][k * ntc + ti];
-                    sy += sh.red[1][k * ntc + ti];
-                    sz += sh.red[2][k * ntc + ti];
+            if (tg.act && tg.sl == 0) {
+#pragma unroll
+                for (int k = 0; k < TP; ++k) {
+                    if (!tg.valid[k]) continue;
+                    double sx = 0.0, sy = 0.0, sz = 0.0;
+                    for (int q = 0; q < tg.S; ++q) {
+                        sx += sh.red[k][0][q * tg.h + tg.ti];
+                        sy += sh.red[k][1][q * tg.h + tg.ti];
+                        sz += sh.red[k][2][q * tg.h + tg.ti];
+                    }
+                    wt[tg.me[k]][0] = sx;
+                    wt[tg.me[k]][1] = sy;
+                    wt[tg.me[k]][2] = sz;
                 }
-                wt[me][0] = sx;
-                wt[me][1] = sy;
-                wt[me][2] = sz;
             }
             __syncthreads();
         }
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
-        block_matvec<NTT, 3>(a.ref.vinvT + qoff, np, nd, wt, &sh.red[0][0], co);
+        block_matvec<NTT, 3>(a.ref.vinvT + qoff, np, nd, wt, &sh.red[0][0][0], co);
         const size_t ts = (size_t)a.slot[t] * a.NPT + poff;
         for (int k = tid; k < 3 * np; k += NTT) a.alpha[ts * 3 + k] = co[k / 3][k % 3];
         __syncthreads();
@@ -503,8 +582,10 @@ __global__ __launch_bounds__(256) void k_direct(i64 n, const double* __restrict_
         const int cnt = (n - j0) < 256 ? (int)(n - j0) : 256;
         const i64 self = gi - j0;
         if (act) {
-            if (self >= 0 && self < cnt) tile_sum<T, DEN, true>(tile, cnt, sl, 4, tx, ty, tz, (int)self, ax, ay, az);
-            else tile_sum<T, DEN, false>(tile, cnt, sl, 4, tx, ty, tz, -1, ax, ay, az);
+            const T txa[1] = {tx}, tya[1] = {ty}, tza[1] = {tz};
+            const int sj[1] = {(int)self};
+            if (self >= 0 && self < cnt) tile_sum<T, DEN, true, 1>(tile, cnt, sl, 4, txa, tya, tza, sj, &ax, &ay, &az);
+            else tile_sum<T, DEN, false, 1>(tile, cnt, sl, 4, txa, tya, tza, nullptr, &ax, &ay, &az);
         }
         __syncthreads();
     }

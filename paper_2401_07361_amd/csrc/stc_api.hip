@@ -660,7 +660,7 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             c->cus = prop.multiProcessorCount;
     }
-    c->shape_default = stc_launch_config{256, 12, 256, 12};
+    c->shape_default = stc_launch_config{256, 48, 256, 48};
     *out = c;
     return STC_OK;
 }
@@ -950,7 +950,7 @@ stc_status stc_autotune(stc_ctx* c, int32_t repeats, stc_launch_config* out) {
         return ms / repeats;
     };
     const int threads[3] = {128, 256, 512};
-    const int per_cu[5] = {4, 8, 12, 16, 24};
+    const int per_cu[6] = {8, 16, 24, 32, 48, 64};
     float tn = 1e30f, tf = 1e30f;
     for (int t : threads)
         for (int b : per_cu) {

@@ -291,3 +291,21 @@ def test_trained_gate_gains_over_fixed_degree(stc_lib):
     assert e_judge <= 1e-6
     assert sum(el.values()) < 0.6 * sum(ej.values())
     assert sum(1 for c in cls["CC"] if c > 0) >= 3   # the network uses several degrees
+
+
+def test_learned_arguments_are_checked(stc_lib):
+    with pytest.raises(stc_lib.StcError):        # one member only
+        stc_lib.Context(1000, members=2, learned=True, degree=10, denominator="dist2")
+    with pytest.raises(stc_lib.StcError):        # degree must be a class degree
+        stc_lib.Context(1000, learned=True, degree=7, denominator="dist2")
+    with pytest.raises(stc_lib.StcError):        # theta_max below theta
+        stc_lib.Context(1000, learned=True, degree=10, theta=0.7, theta_max=0.5, denominator="dist2")
+    plain = stc_lib.Context(1000, degree=10)
+    with pytest.raises(stc_lib.StcError):        # no learned traversal in a plain context
+        plain.set_model(bf16_tensor(np.zeros(stc_lib.mlp_param_count())))
+    plain.close()
+    cl = stc_lib.Context(1000, learned=True, degree=10, denominator="dist2")
+    p = bf16_tensor(np.zeros(stc_lib.mlp_param_count() + 8))
+    with pytest.raises(stc_lib.StcError):        # misaligned parameters
+        cl.set_model(p[1:1 + stc_lib.mlp_param_count()])
+    cl.close()
