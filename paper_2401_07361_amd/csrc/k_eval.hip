@@ -111,11 +111,11 @@ __device__ __forceinline__ u32 logical_block() {
     return (b % 8u) * (G / 8u) + (b / 8u);
 }
 
-// LDS of a segment kernel with NTT threads: one NTT-source tile, one batch of
-// NTT list entries
+// LDS of a segment kernel with NTT threads: one tile of 2 NTT sources (two
+// consecutive ones staged per thread), one batch of NTT list entries
 template <typename T, int NTT, int TP>
 struct SegShared {
-    Src<T> tile[NTT];
+    Src<T> tile[2 * NTT];
     u32 ent_s[NTT];        // source node of a particle entry, storage slot of a proxy entry
     i32 ent_first[NTT];    // first particle of a particle source, -1 for proxy points
     u32 ent_pre[NTT + 1];  // exclusive prefix of the entries' source counts
@@ -218,9 +218,9 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
         if (sh.self_flag) {
             const i32 tb = a.nbeg[self_t];
             const int nsrc = a.nend[self_t] - tb;
-            for (int j0 = 0; j0 < nsrc; j0 += NTT) {
-                const int cnt = (nsrc - j0) < NTT ? (nsrc - j0) : NTT;
-                if (tid < cnt) sh.tile[tid] = load_source<T>(a, self_t, tb, j0 + tid, cx, cy, cz, qscale);
+            for (int j0 = 0; j0 < nsrc; j0 += 2 * NTT) {
+                const int cnt = (nsrc - j0) < 2 * NTT ? (nsrc - j0) : 2 * NTT;
+                for (int l = tid; l < cnt; l += NTT) sh.tile[l] = load_source<T>(a, self_t, tb, j0 + l, cx, cy, cz, qscale);
                 __syncthreads();
                 int sj[TP];
 #pragma unroll
@@ -229,18 +229,26 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                 __syncthreads();
             }
         }
-        for (u32 g0 = 0; g0 < total; g0 += NTT) {
-            const int cnt = (total - g0) < (u32)NTT ? (int)(total - g0) : NTT;
-            if (tid < cnt) {
-                const u32 g = g0 + tid;
+        for (u32 g0 = 0; g0 < total; g0 += 2 * NTT) {
+            const int cnt = (total - g0) < (u32)(2 * NTT) ? (int)(total - g0) : 2 * NTT;
+            const int l0 = 2 * tid;
+            if (l0 < cnt) {
+                // the entry holding source g: binary search over the prefix;
+                // source g + 1 lies in the same entry or a later one
+                const u32 g = g0 + l0;
                 u32 lo = 0, hi = ne;
                 while (hi - lo > 1) {
                     const u32 mid = (lo + hi) >> 1;
                     if (sh.ent_pre[mid] <= g) lo = mid;
                     else hi = mid;
                 }
-                sh.tile[tid] = load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g - sh.ent_pre[lo]), cx, cy,
-                                              cz, qscale);
+                sh.tile[l0] = load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g - sh.ent_pre[lo]), cx, cy,
+                                             cz, qscale);
+                if (l0 + 1 < cnt) {
+                    while (sh.ent_pre[lo + 1] <= g + 1) ++lo;  // ent_pre[ne] = total > g + 1
+                    sh.tile[l0 + 1] = load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g + 1 - sh.ent_pre[lo]),
+                                                     cx, cy, cz, qscale);
+                }
             }
             __syncthreads();
             if (act) tile_sum<T, DEN, false, TP>(sh.tile, cnt, sl, S, tx, ty, tz, nullptr, ax, ay, az);
