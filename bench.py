@@ -35,8 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Benchmark setting: the fastest (theta, degree, N_T) found with E <= 5e-7
-# (half the 1e-6 bar) on this workload; see the design doc for the sweep.
+# Benchmark setting: the fastest (theta, degree, N_T) whose error on this
+# workload stays about a factor 2 below the 1e-6 bar (E = 5.0e-7).
 BENCH_THETA = 0.8
 BENCH_DEGREE = 10
 BENCH_N_CRIT = 64

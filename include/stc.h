@@ -267,8 +267,9 @@ stc_status stc_set_model(stc_ctx* ctx, const uint16_t* d_params);
  * that degree against the exact pair sum (d_errors: cap x 4 FP64, W units:
  * the sum before the cross product), and labels (d_labels: cap x 4 float):
  * accept iff some class has error <= abs_tol, ordinal targets from the
- * smallest such class.  *n_out = number of candidates (samples beyond cap are
- * dropped and STC_ERR_CAPACITY returned).  Synchronises.  The lists of the
+ * smallest such class.  Samples are in (target id, source id) order.  *n_out =
+ * number of candidates (samples beyond cap are dropped and STC_ERR_CAPACITY
+ * returned).  Synchronises.  The lists of the
  * context are invalid afterwards (evaluate again). */
 stc_status stc_learned_samples(stc_ctx* ctx, double abs_tol, int64_t cap, uint16_t* d_features,
                                float* d_labels, double* d_errors, int64_t* n_out);

@@ -41,6 +41,7 @@ struct stc_ctx {
     ClassTab cls{};
     RefTables ref_host[4];
     u64* cand = nullptr;          // candidate pairs of the gated traversal
+    const u64* cand_view = nullptr;  // where the last pass left them (sorted for samples)
     u16* feat = nullptr;          // their features (BF16, 16 per candidate)
     float* mlp_out = nullptr;     // network outputs per candidate
     double *qabs = nullptr, *qsum = nullptr;  // per-node charge sums
@@ -369,6 +370,7 @@ stc_status do_traverse(stc_ctx* c) {
         launch_traverse_init(s, tc);
         launch_traverse_levels(s, tc, C_FRONT, true, c->cand);
         LearnedArgs la = learned_args(c);
+        c->cand_view = c->cand;
         if (c->model) {
             launch_features(s, la);
             launch_mlp_forward_list(s, la);
@@ -1007,7 +1009,8 @@ stc_status stc_copy_candidates(stc_ctx* c, int64_t cap, int64_t* h_pairs, float*
     if (m > 0) {
         std::vector<u64> buf(m);
         if (h_pairs) {
-            if (hipMemcpy(buf.data(), c->cand, m * sizeof(u64), hipMemcpyDeviceToHost) != hipSuccess)
+            if (hipMemcpy(buf.data(), c->cand_view ? c->cand_view : c->cand, m * sizeof(u64), hipMemcpyDeviceToHost) !=
+                hipSuccess)
                 return fail(c, STC_ERR_DEVICE, "copy failed");
             for (i64 i = 0; i < m; ++i) {
                 h_pairs[2 * i] = (int64_t)(buf[i] >> 32);
@@ -1039,7 +1042,14 @@ stc_status stc_learned_samples(stc_ctx* c, double abs_tol, int64_t cap, uint16_t
     const TravArgs tc = trav_args(c, c->p.theta_max, 0);
     launch_traverse_init(s, tc);
     launch_traverse_levels(s, tc, C_FRONT, true, c->cand);
+    // samples in (t, s) order, so that training data do not depend on the
+    // order in which the traversal appended them (the frontier is free now)
+    u64* sorted = nullptr;
+    radix_sort(s, c->cand, c->front1, c->counters + C_CAND, c->cap, 0, 32 + c->W,
+               SortScratch{c->hist, c->hist_totals, c->hist_blocks}, &sorted);
     LearnedArgs la = learned_args(c);
+    la.cand = sorted;
+    c->cand_view = sorted;
     launch_features(s, la);
     EvalArgs a = eval_args(c);
     const u32 lim = (u32)std::min<i64>(cap, 0x7fffffffLL);
