@@ -84,17 +84,17 @@ _G = {}
 
 def _oracle_worker(idx):
     from oracle import direct
-    return direct.velocity(_G["x"], _G["z"], _G["a"], targets=idx)
+    return direct.velocity(_G["x"], _G["z"], _G["a"], targets=idx, den=_G["den"])
 
 
-def cpu_baseline(x, z, a, subset, budget_s=15.0):
+def cpu_baseline(x, z, a, subset, budget_s=15.0, den="dot", what="the 4096 seeded targets"):
     """The oracle's direct sum (O(N) per target) timed on the host cores over a
     bounded sample of the target subset."""
     from oracle import direct
     cores = min(len(os.sched_getaffinity(0)), 16)
-    _G.update(x=x, z=z, a=a)
+    _G.update(x=x, z=z, a=a, den=den)
     t0 = time.perf_counter()
-    probe = direct.velocity(x, z, a, targets=subset[:8])
+    probe = direct.velocity(x, z, a, targets=subset[:8], den=den)
     per_target = (time.perf_counter() - t0) / 8
     m = int(min(len(subset), max(cores * 8, budget_s * cores / per_target)))
     m = max(8, (m // cores) * cores) if m >= cores else m
@@ -107,8 +107,17 @@ def cpu_baseline(x, z, a, subset, budget_s=15.0):
     dt = time.perf_counter() - t0
     u = np.concatenate(parts)
     return dict(value=m / dt, unit="velocity evals/s", cores=cores, kind="oracle",
-                sample=f"{m} of the 4096 seeded targets, all {len(x)} sources, FP64 direct sum, "
+                sample=f"{m} of {what}, all {len(x)} sources, FP64 direct sum, "
                        f"{dt:.1f} s wall"), sample, u
+
+
+def near_roofline(evals, ms, precision):
+    """The near-field kernel's ALU roofline entry (traffic not measured here)."""
+    flops = FP32_FLOPS if precision == "fp32" else FP64_FLOPS
+    achieved = evals * flops / (ms / 1e3) / 1e12
+    return dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
+                frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=None, kernel="k_near (PP + PC)",
+                kernel_ms=round(ms, 4), kernel_evals_per_launch=int(evals))
 
 
 ENS_THETA, ENS_DEGREE, ENS_N_CRIT = 0.7, 8, 64
@@ -187,6 +196,14 @@ def bench_ensemble(args):
     ctx.sync()
     log(f"rk4 step (4 evaluations, one graph): {ms_rk:.3f} ms")
     ctx.close()
+    roof = near_roofline(evals["PP"] + evals["PC"], phase_ms["near"], "fp32")
+    m0 = ens["members"][0]
+    cb = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle direct sum, member 0, bounded target sample)")
+        tg = np.random.default_rng(100).choice(len(m0["x"]), 64, replace=False)
+        cb, _, _ = cpu_baseline(m0["x"], m0["zeta"], m0["area"], tg, budget_s=8.0, den="dist2",
+                                what=f"64 seeded targets of member 0 (N={len(m0['x'])})")
     result = dict(
         metric="ensemble particle velocity evals/s (48 members, one launch per phase)",
         value=N / (ms / 1e3), unit="velocity evals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -199,7 +216,10 @@ def bench_ensemble(args):
                     lists=counts, kernel_evals=int(sum(evals.values())), phase_ms=phase_ms,
                     ms_one_member_at_a_time=round(ms_seq, 4), batching_speedup=round(ms_seq / ms, 3),
                     ms_per_rk4_step=round(ms_rk, 4)),
+        roofline=roof,
     )
+    if cb is not None:
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
 
@@ -263,6 +283,9 @@ def bench_learned(args):
             ctx.set_model(model)
         ms, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
+        if model is not None and kw.get("precision") == "fp32":
+            pairs, _, _ = ctx.copy_candidates()
+            rows["_near"] = (ev["PP"] + ev["PC"], ph["near"], len(pairs))
         u = out.cpu().numpy()
         rows[name] = dict(ms=round(ms, 4), rel_l2_err_vs_fp64_direct=float(f"{metrics.rel_l2_velocity(u[sub], ud, a[sub]):.3e}"),
                           kernel_evals=int(sum(ev.values())), phase_ms=ph)
@@ -277,6 +300,24 @@ def bench_learned(args):
     ul = run("learned_fp32", model=params, theta=P["theta"], theta_max=P["theta_max"], degree=P["degree"],
              precision="fp32", learned=True)
     e_judge = metrics.rel_l2_velocity(ul, uj, a)
+    near_evals, near_ms, n_cand = rows.pop("_near")
+    # the network's forward pass over the candidates, timed on its own (MFMA, BF16)
+    feats = F[: min(len(F), n_cand)] if n_cand <= len(F) else F
+    fwd = torch.empty((feats.shape[0], 4), dtype=torch.float32, device="cuda")
+    stc.mlp_forward(feats, params, out=fwd)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        stc.mlp_forward(feats, params, out=fwd)
+    e1.record()
+    torch.cuda.synchronize()
+    mlp_ms = e0.elapsed_time(e1) / 20
+    mlp_flops = 2.0 * (16 * 64 + 64 * 64 + 64 * 16) * feats.shape[0]   # padded MFMA shapes
+    mlp_roof = dict(bound="mfma", achieved=round(mlp_flops / (mlp_ms / 1e3) / 1e12, 3), peak=2500.0,
+                    unit="TFLOP/s", frac=round(mlp_flops / (mlp_ms / 1e3) / 1e12 / 2500.0, 6), traffic=None,
+                    kernel="k_mlp_forward (BF16)", kernel_ms=round(mlp_ms, 4), rows=int(feats.shape[0]))
+    log(f"network forward over {feats.shape[0]} rows: {mlp_ms:.4f} ms")
     r = rows["learned_fp32"]
     result = dict(
         metric="particle velocity evals/s at N=2621442 with learned degree/acceptance gating, rel-L2 err <=1e-6 vs FP64 direct sum",
@@ -290,8 +331,66 @@ def bench_learned(args):
                                   seconds_train=round(t_train, 3), steps=len(ln),
                                   loss_first=float(f"{ln[0]:.4f}"), loss_last=float(f"{ln[-50:].mean():.4f}"),
                                   calibration=dict(accept_shift=da, class_shift=dc)),
-                    runs=rows),
+                    runs=rows, network_forward=mlp_roof),
+        roofline=near_roofline(near_evals, near_ms, "fp32"),
     )
+    if not args.no_cpu:
+        log("cpu baseline (oracle direct sum, bounded target sample)")
+        cb, _, _ = cpu_baseline(x, z, a, sub, budget_s=10.0, den="dist2")
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+def bench_rk4(args):
+    import torch
+    import synthetic as S
+    from paper_2401_07361_amd import stc
+    from oracle import metrics
+
+    wl = S.make_workload("rh4_l7")
+    x, z, a, sub = wl["x"], wl["zeta"], wl["area"], wl["subset"]
+    n = len(x)
+    dt, Om = wl["dt"], S.OMEGA_EARTH_S
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    ud = stc.direct(xd, zd, ad, targets=torch.from_numpy(sub).cuda(), denominator="dist2").cpu().numpy()
+    runs = {}
+    for prec in ("fp32", "fp64"):
+        ctx = stc.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision=prec, denominator="dist2")
+        u = ctx.velocity(xd, zd, ad)
+        err = metrics.rel_l2_velocity(u.cpu().numpy()[sub], ud, a[sub])
+        ms_eval, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
+        cnt, ev = ctx.list_counts()
+        xs, zs = xd.clone(), zd.clone()
+        ctx.rk4(xs, zs, ad, dt, Om, 1)   # captures the step graph
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        ctx.rk4(xs, zs, ad, dt, Om, args.steps)
+        t1.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        ms_step = t0.elapsed_time(t1) / args.steps
+        runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4),
+                          rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), phase_ms=ph,
+                          near=(ev["PP"] + ev["PC"], ph["near"]))
+        log(f"{prec}: {ms_step:.3f} ms per RK4 step (graph), {ms_eval:.3f} ms per evaluation, E = {err:.3e}")
+        ctx.close()
+    r = runs["fp32"]
+    near_evals, near_ms = r.pop("near")
+    runs["fp64"].pop("near")
+    result = dict(
+        metric="particle velocity evals/s in RK4 time stepping at N=163842 (4 evaluations per step, one HIP graph per step)",
+        value=4 * n / (r["ms_per_rk4_step"] / 1e3), unit="velocity evals/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=r["ms_per_rk4_step"], higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="rh4_l7 (Rossby-Haurwitz n=4, icosahedral level 7, node-patch areas)", N=n,
+                    theta=wl["theta"], degree=wl["degree"], n_crit=64, dt_seconds=dt, omega=Om, runs=runs),
+        roofline=near_roofline(near_evals, near_ms, "fp32"),
+    )
+    if not args.no_cpu:
+        log("cpu baseline (oracle direct sum, bounded target sample)")
+        cb, _, _ = cpu_baseline(x, z, a, sub, budget_s=8.0, den="dist2", what="4096 seeded targets")
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
 
@@ -306,7 +405,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned"])
+    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4"])
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -319,6 +418,9 @@ def main():
         return
     if args.workload == "learned":
         bench_learned(args)
+        return
+    if args.workload == "rk4":
+        bench_rk4(args)
         return
 
     import torch
@@ -365,7 +467,17 @@ def main():
 
     counts, evals = ctx.list_counts()
     # accuracy: FP64 direct sum on the GPU (parity-tested against the oracle) at the 4096 targets
-    ud = stc.direct(xd, zd, ad, targets=sd).cpu().numpy()
+    ud_t = stc.direct(xd, zd, ad, targets=sd)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    stc.direct(xd, zd, ad, targets=sd, out=ud_t)
+    e1.record()
+    torch.cuda.synchronize()
+    direct_ms = e0.elapsed_time(e1)
+    ud = ud_t.cpu().numpy()
+    direct_evals = len(subset) * (n - 1)
+    direct_tf = direct_evals * FP64_FLOPS / (direct_ms / 1e3) / 1e12
     ut = out.cpu().numpy()[subset]
     from oracle import metrics
     err = metrics.rel_l2_velocity(ut, ud, a[subset])
@@ -391,7 +503,10 @@ def main():
                     precision=args.precision, denominator=den, rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"),
                     err_ok=bool(err <= 1e-6), lists=counts,
                     kernel_evals=int(sum(evals.values())), phase_ms={p: round(v, 4) for p, v in phase_ms.items()},
-                    kernel_source_hash=kernel_source_hash()),
+                    kernel_source_hash=kernel_source_hash(),
+                    direct_sum=dict(kernel="k_direct FP64 (1 - x.y), 4096 targets x all sources", ms=round(direct_ms, 4),
+                                    evals_per_s=direct_evals / (direct_ms / 1e3), tflops=round(direct_tf, 3),
+                                    frac_of_fp64_peak=round(direct_tf / PEAK_VALU_TFLOPS, 4))),
         roofline=roof,
     )
     ctx.close()
