@@ -211,7 +211,11 @@ stc_status stc_velocity_batched(stc_ctx* ctx, int32_t members, const int64_t* h_
  * int64 indices into [0, n), or NULL for all (then m must equal n).  Sources
  * are all n particles, the self term excluded by index.  precision STC_FP64
  * or STC_FP32 (FP32 kernel, FP64 accumulation per tile of 256 sources).
- * d_u is (m, 3).  Asynchronous on hip_stream; needs no context. */
+ * d_u is (m, 3).  Asynchronous on hip_stream; needs no context.  When m is
+ * too small to fill the GPU the sources are split into chunks whose partial
+ * sums (chunks x m x 3 doubles, a few MB at most) come from a stream-ordered
+ * allocation (hipMallocAsync / hipFreeAsync on hip_stream); the chunks are
+ * added in a fixed order, so the result does not vary between calls. */
 stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
                       const double* d_area, int64_t m, const int64_t* d_targets,
                       int32_t precision, int32_t denominator, double* d_u);

@@ -49,17 +49,73 @@ __device__ __forceinline__ double rcp_t<double>(double v) {
     return rcp64(v);
 }
 
+// A target coordinate as a value computed in a register (the FP32 rounding,
+// or an FMA by 1 in FP64) rather than the register a memory load filled:
+// the compiler's wait counting otherwise makes the interaction loops wait on
+// every outstanding load (the next tile's) when they read such a register.
+template <typename T>
+__device__ __forceinline__ T target_reg(double v);
+template <>
+__device__ __forceinline__ float target_reg<float>(double v) {
+    return (float)v;
+}
+template <>
+__device__ __forceinline__ double target_reg<double>(double v) {
+    return __fma_rn(v, 1.0, 0.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+    return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+
 // one kernel evaluation: q (y - x) / den added to (px, py, pz)
 template <typename T, int DEN>
 __device__ __forceinline__ void interact(const Src<T>& s, T tx, T ty, T tz, T& px, T& py, T& pz) {
     const T dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
     T den;
     if (DEN == STC_DEN_DIST2) den = dx * dx + dy * dy + dz * dz;  // charges carry the factor 2
-    else den = T(1) - (tx * s.x + ty * s.y + tz * s.z);
+    else den = fma_t<T>(-tx, s.x, fma_t<T>(-ty, s.y, fma_t<T>(-tz, s.z, T(1))));  // 1 - x.y in three FMAs
     const T w = s.q * rcp_t<T>(den);
     px += w * dx;
     py += w * dy;
     pz += w * dz;
+}
+
+// Four FP64 kernel evaluations with one reciprocal: v_rcp_f64 issues at a
+// quarter of the FMA rate and needs two Newton steps, so 1 / (d0 d1 d2 d3)
+// is formed once and each 1 / d_k recovered by multiplying it with the other
+// three denominators (a few ulp, against the half ulp of four separate
+// reciprocals).  The denominators lie in (0, 2] and above ~1e-20 for any
+// two distinct points a double can tell apart near the sphere, so the
+// product neither overflows nor underflows; a zero denominator (coincident
+// particles) makes all four non-finite, as it makes its own one with
+// separate reciprocals.
+template <int DEN>
+__device__ __forceinline__ void interact4(const Src<double>* __restrict__ s, double tx, double ty, double tz,
+                                          double& px, double& py, double& pz) {
+    double dx[4], dy[4], dz[4], den[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dx[k] = s[k].x - tx, dy[k] = s[k].y - ty, dz[k] = s[k].z - tz;
+        if (DEN == STC_DEN_DIST2) den[k] = dx[k] * dx[k] + dy[k] * dy[k] + dz[k] * dz[k];
+        else den[k] = __fma_rn(-tx, s[k].x, __fma_rn(-ty, s[k].y, __fma_rn(-tz, s[k].z, 1.0)));
+    }
+    const double p01 = den[0] * den[1], p23 = den[2] * den[3];
+    const double r = rcp64(p01 * p23);
+    const double r01 = r * p23, r23 = r * p01;  // 1 / (d0 d1), 1 / (d2 d3)
+    const double inv[4] = {r01 * den[1], r01 * den[0], r23 * den[3], r23 * den[2]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double w = s[k].q * inv[k];
+        px += w * dx[k];
+        py += w * dy[k];
+        pz += w * dz[k];
+    }
 }
 
 // Sum over this slice's staged sources for the thread's TP targets (each
@@ -78,11 +134,27 @@ __device__ __forceinline__ void tile_sum(const Src<T>* __restrict__ tile, int cn
     if (!SELF) {
         const int m = cnt / S;
         const Src<T>* __restrict__ blk = tile + sl * m;
-#pragma unroll 4
-        for (int it = 0; it < m; ++it) {
-            const Src<T> src = blk[it];
+        if constexpr (sizeof(T) == 8) {
+            int it = 0;
+            for (; it + 4 <= m; it += 4) {
+                Src<T> src[4];
 #pragma unroll
-            for (int k = 0; k < TP; ++k) interact<T, DEN>(src, tx[k], ty[k], tz[k], px[k], py[k], pz[k]);
+                for (int l = 0; l < 4; ++l) src[l] = blk[it + l];
+#pragma unroll
+                for (int k = 0; k < TP; ++k) interact4<DEN>(src, tx[k], ty[k], tz[k], px[k], py[k], pz[k]);
+            }
+            for (; it < m; ++it) {
+                const Src<T> src = blk[it];
+#pragma unroll
+                for (int k = 0; k < TP; ++k) interact<T, DEN>(src, tx[k], ty[k], tz[k], px[k], py[k], pz[k]);
+            }
+        } else {
+#pragma unroll 4
+            for (int it = 0; it < m; ++it) {
+                const Src<T> src = blk[it];
+#pragma unroll
+                for (int k = 0; k < TP; ++k) interact<T, DEN>(src, tx[k], ty[k], tz[k], px[k], py[k], pz[k]);
+            }
         }
         const int j = S * m + sl;
         if (j < cnt) {
@@ -320,9 +392,9 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
 #pragma unroll
             for (int k = 0; k < TP; ++k) {
                 const i32 gi = tb + tg.me[k];
-                tx[k] = (T)(a.sx[gi] - cx);
-                ty[k] = (T)(a.sy[gi] - cy);
-                tz[k] = (T)(a.sz[gi] - cz);
+                tx[k] = target_reg<T>(a.sx[gi] - cx);
+                ty[k] = target_reg<T>(a.sy[gi] - cy);
+                tz[k] = target_reg<T>(a.sz[gi] - cz);
                 me[k] = tg.valid[k] ? tg.me[k] : -1;  // a duplicate target's exclusion never matches
             }
             double ax[TP], ay[TP], az[TP];
@@ -394,9 +466,9 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
                 double y[3];
                 const double nrm = proxy_point(gt, a.ref.points + 3 * (poff + tg.me[k]), y);
                 if (tg.act && tg.sl == 0 && tg.valid[k]) nd[tg.me[k]] = ipow(nrm, d);
-                tx[k] = (T)(y[0] - cx);
-                ty[k] = (T)(y[1] - cy);
-                tz[k] = (T)(y[2] - cz);
+                tx[k] = target_reg<T>(y[0] - cx);
+                ty[k] = target_reg<T>(y[1] - cy);
+                tz[k] = target_reg<T>(y[2] - cz);
                 nome[k] = -1;
             }
             double ax[TP], ay[TP], az[TP];
@@ -560,58 +632,124 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
     }
 }
 
-// Direct sum: 64 targets x 4 source slices per workgroup, 256-source LDS tiles.
-template <typename T, int DEN>
+// Direct sum over sources [j_lo, j_hi) for 64 TPD targets per workgroup
+// (lane l holds targets l, l + 64, ...; 4 source slices per target; every
+// lane of a wave reads the same staged source, an LDS broadcast, and uses it
+// for its TPD targets).  Workgroup b takes target block b % tblocks and
+// source chunk b / tblocks; the block index goes through the XCD-aware map
+// when the grid divides by 8, so the workgroups of one XCD share a few
+// source chunks in its L2.  With one chunk the velocity is written directly;
+// else the chunk's W goes to part[chunk][target][3].
+template <typename T, int DEN, int TPD>
 __global__ __launch_bounds__(256) void k_direct(i64 n, const double* __restrict__ x, const double* __restrict__ zeta,
                                                 const double* __restrict__ area, i64 m, const i64* __restrict__ targets,
-                                                double* __restrict__ u) {
+                                                i64 chunk_len, u32 tblocks, double* __restrict__ u,
+                                                double* __restrict__ part) {
     __shared__ Src<T> tile[256];
-    __shared__ double red[3][256];
+    __shared__ double red[TPD][3][256];
+    const u32 b = (gridDim.x % 8u == 0u) ? logical_block() : blockIdx.x;
+    const u32 tb = b % tblocks, ch = b / tblocks;
+    const i64 j_lo = (i64)ch * chunk_len;
+    const i64 j_hi = (j_lo + chunk_len) < n ? j_lo + chunk_len : n;
     const int tid = threadIdx.x;
     const int tl = tid & 63, sl = tid >> 6;
-    const i64 ti = (i64)blockIdx.x * 64 + tl;
-    const bool act = ti < m;
-    const i64 gi = act ? (targets ? targets[ti] : ti) : 0;
-    const double xg0 = x[3 * gi], xg1 = x[3 * gi + 1], xg2 = x[3 * gi + 2];
-    const T tx = (T)xg0, ty = (T)xg1, tz = (T)xg2;
+    i64 ti[TPD], gi[TPD];
+    T tx[TPD], ty[TPD], tz[TPD];
+    double ax[TPD], ay[TPD], az[TPD];
+#pragma unroll
+    for (int k = 0; k < TPD; ++k) {
+        ti[k] = (i64)tb * 64 * TPD + 64 * k + tl;
+        gi[k] = ti[k] < m ? (targets ? targets[ti[k]] : ti[k]) : 0;  // targets past m repeat particle 0
+        tx[k] = target_reg<T>(x[3 * gi[k]]);
+        ty[k] = target_reg<T>(x[3 * gi[k] + 1]);
+        tz[k] = target_reg<T>(x[3 * gi[k] + 2]);
+        ax[k] = ay[k] = az[k] = 0.0;
+    }
     const double qscale = (DEN == STC_DEN_DIST2) ? 2.0 : 1.0;
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (i64 j0 = 0; j0 < n; j0 += 256) {
-        const i64 j = j0 + tid;
-        if (j < n) {
+    // the next tile's source is loaded into registers before the current
+    // tile is summed, so its memory latency overlaps the arithmetic
+    // (the pointers stay live across the tile loop, so no register of an
+    // address is reused while its load is still in flight)
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, sz = 0.0, sa = 0.0;
+    const double* px = x + 3 * (j_lo + tid);
+    const double* pz = zeta + (j_lo + tid);
+    const double* pa = area + (j_lo + tid);
+    if (j_lo + tid < j_hi) s0 = px[0], s1 = px[1], s2 = px[2], sz = pz[0], sa = pa[0];
+    for (i64 j0 = j_lo; j0 < j_hi; j0 += 256) {
+        if (j0 + tid < j_hi) {
             Src<T> v;
-            v.x = (T)x[3 * j];
-            v.y = (T)x[3 * j + 1];
-            v.z = (T)x[3 * j + 2];
-            v.q = (T)(qscale * zeta[j] * area[j]);
+            v.x = (T)s0;
+            v.y = (T)s1;
+            v.z = (T)s2;
+            v.q = (T)(qscale * sz * sa);
             tile[tid] = v;
         }
         __syncthreads();
-        const int cnt = (n - j0) < 256 ? (int)(n - j0) : 256;
-        const i64 self = gi - j0;
-        if (act) {
-            const T txa[1] = {tx}, tya[1] = {ty}, tza[1] = {tz};
-            const int sj[1] = {(int)self};
-            if (self >= 0 && self < cnt) tile_sum<T, DEN, true, 1>(tile, cnt, sl, 4, txa, tya, tza, sj, &ax, &ay, &az);
-            else tile_sum<T, DEN, false, 1>(tile, cnt, sl, 4, txa, tya, tza, nullptr, &ax, &ay, &az);
+        px += 3 * 256, pz += 256, pa += 256;
+        if (j0 + 256 + tid < j_hi) s0 = px[0], s1 = px[1], s2 = px[2], sz = pz[0], sa = pa[0];
+        const int cnt = (j_hi - j0) < 256 ? (int)(j_hi - j0) : 256;
+        int sj[TPD];
+        bool self_in = false;
+#pragma unroll
+        for (int k = 0; k < TPD; ++k) {
+            const i64 d = gi[k] - j0;
+            sj[k] = (d >= 0 && d < cnt) ? (int)d : -1;
+            self_in |= sj[k] >= 0;
         }
+        if (self_in) tile_sum<T, DEN, true, TPD>(tile, cnt, sl, 4, tx, ty, tz, sj, ax, ay, az);
+        else tile_sum<T, DEN, false, TPD>(tile, cnt, sl, 4, tx, ty, tz, nullptr, ax, ay, az);
         __syncthreads();
     }
-    red[0][tid] = ax;
-    red[1][tid] = ay;
-    red[2][tid] = az;
-    __syncthreads();
-    if (act && sl == 0) {
-        double W0 = 0.0, W1 = 0.0, W2 = 0.0;
-        for (int k = 0; k < 4; ++k) {
-            W0 += red[0][k * 64 + tl];
-            W1 += red[1][k * 64 + tl];
-            W2 += red[2][k * 64 + tl];
-        }
-        u[3 * ti + 0] = -kInv4Pi * (xg1 * W2 - xg2 * W1);
-        u[3 * ti + 1] = -kInv4Pi * (xg2 * W0 - xg0 * W2);
-        u[3 * ti + 2] = -kInv4Pi * (xg0 * W1 - xg1 * W0);
+#pragma unroll
+    for (int k = 0; k < TPD; ++k) {
+        red[k][0][tid] = ax[k];
+        red[k][1][tid] = ay[k];
+        red[k][2][tid] = az[k];
     }
+    __syncthreads();
+    if (sl == 0) {
+#pragma unroll
+        for (int k = 0; k < TPD; ++k) {
+            if (ti[k] >= m) continue;
+            double W0 = 0.0, W1 = 0.0, W2 = 0.0;
+            for (int q = 0; q < 4; ++q) {
+                W0 += red[k][0][q * 64 + tl];
+                W1 += red[k][1][q * 64 + tl];
+                W2 += red[k][2][q * 64 + tl];
+            }
+            if (part) {
+                double* p = part + 3 * ((i64)ch * m + ti[k]);
+                p[0] = W0;
+                p[1] = W1;
+                p[2] = W2;
+            } else {
+                const double xg0 = x[3 * gi[k]], xg1 = x[3 * gi[k] + 1], xg2 = x[3 * gi[k] + 2];
+                u[3 * ti[k] + 0] = -kInv4Pi * (xg1 * W2 - xg2 * W1);
+                u[3 * ti[k] + 1] = -kInv4Pi * (xg2 * W0 - xg0 * W2);
+                u[3 * ti[k] + 2] = -kInv4Pi * (xg0 * W1 - xg1 * W0);
+            }
+        }
+    }
+}
+
+// sum of the chunks' W in chunk order (deterministic), then the cross product
+__global__ __launch_bounds__(256) void k_direct_reduce(const double* __restrict__ x, i64 m,
+                                                       const i64* __restrict__ targets, u32 chunks,
+                                                       const double* __restrict__ part, double* __restrict__ u) {
+    const i64 ti = (i64)blockIdx.x * 256 + threadIdx.x;
+    if (ti >= m) return;
+    const i64 gi = targets ? targets[ti] : ti;
+    double W0 = 0.0, W1 = 0.0, W2 = 0.0;
+    for (u32 c = 0; c < chunks; ++c) {
+        const double* p = part + 3 * ((i64)c * m + ti);
+        W0 += p[0];
+        W1 += p[1];
+        W2 += p[2];
+    }
+    const double xg0 = x[3 * gi], xg1 = x[3 * gi + 1], xg2 = x[3 * gi + 2];
+    u[3 * ti + 0] = -kInv4Pi * (xg1 * W2 - xg2 * W1);
+    u[3 * ti + 1] = -kInv4Pi * (xg2 * W0 - xg0 * W2);
+    u[3 * ti + 2] = -kInv4Pi * (xg0 * W1 - xg1 * W0);
 }
 
 }  // namespace
@@ -668,13 +806,73 @@ void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* 
     }
 }
 
+// targets per lane of the direct-sum kernel (two per lane halve the LDS
+// reads but cost a wave per SIMD; measured 5-10% slower in both precisions)
+constexpr int DIRECT_TP32 = 1;
+constexpr int DIRECT_TP64 = 1;
+
+int direct_targets_per_block(int precision) {
+    return 64 * (precision == STC_FP32 ? DIRECT_TP32 : DIRECT_TP64);
+}
+
+// Workgroups of the direct-sum kernel that fit on one CU at once.
+int direct_blocks_per_cu(int precision, int denominator) {
+    int nb = 0;
+    hipError_t e;
+    if (precision == STC_FP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_direct<float, STC_DEN_DIST2, DIRECT_TP32>, 256, 0);
+    else if (denominator == STC_DEN_DIST2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_direct<double, STC_DEN_DIST2, DIRECT_TP64>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_direct<double, STC_DEN_DOT, DIRECT_TP64>, 256, 0);
+    if (e != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb;
+}
+
+// Number of source chunks for m targets and n sources: about four times as
+// many workgroups as fit on the chip at once (cus x blocks_per_cu), each
+// chunk at least 2048 sources.  Workgroups of one round share the SIMDs
+// unevenly and finish at different times; with several rounds the free
+// slots take new workgroups, so the chip stays full to the end (measured on
+// 4096 targets: 1.02 ms in one round, 0.87 ms in four).
+void direct_split(i64 n, i64 m, int cus, int blocks_per_cu, int targets_per_block, u32* chunks, i64* chunk_len) {
+    const i64 tblocks = (m + targets_per_block - 1) / targets_per_block;
+    const i64 want = 4 * (i64)(cus > 0 ? cus : 1) * (blocks_per_cu > 0 ? blocks_per_cu : 1);
+    i64 c = want / tblocks;
+    const i64 cmax = (n + 2047) / 2048;
+    if (c > cmax) c = cmax;
+    if (c < 1) c = 1;
+    i64 len = (n + c - 1) / c;
+    len = (len + 255) / 256 * 256;
+    c = (n + len - 1) / len;
+    *chunks = (u32)c;
+    *chunk_len = len;
+}
+
 void launch_direct(hipStream_t s, i64 n, const double* x, const double* zeta, const double* area, i64 m,
-                   const i64* targets, int precision, int denominator, double* u) {
+                   const i64* targets, int precision, int denominator, u32 chunks, i64 chunk_len, double* part,
+                   double* u) {
     if (m <= 0) return;
-    const dim3 g((unsigned)((m + 63) / 64)), b(256);
-    if (precision == STC_FP32) hipLaunchKernelGGL((k_direct<float, STC_DEN_DIST2>), g, b, 0, s, n, x, zeta, area, m, targets, u);
-    else if (denominator == STC_DEN_DIST2) hipLaunchKernelGGL((k_direct<double, STC_DEN_DIST2>), g, b, 0, s, n, x, zeta, area, m, targets, u);
-    else hipLaunchKernelGGL((k_direct<double, STC_DEN_DOT>), g, b, 0, s, n, x, zeta, area, m, targets, u);
+    const int tpb = direct_targets_per_block(precision);
+    const u32 tblocks = (u32)((m + tpb - 1) / tpb);
+    if (!part) chunks = 1, chunk_len = n;
+    double* pp = chunks > 1 ? part : nullptr;
+    const dim3 g(tblocks * chunks), b(256);
+    if (precision == STC_FP32)
+        hipLaunchKernelGGL((k_direct<float, STC_DEN_DIST2, DIRECT_TP32>), g, b, 0, s, n, x, zeta, area, m, targets, chunk_len,
+                           tblocks, u, pp);
+    else if (denominator == STC_DEN_DIST2)
+        hipLaunchKernelGGL((k_direct<double, STC_DEN_DIST2, DIRECT_TP64>), g, b, 0, s, n, x, zeta, area, m, targets, chunk_len,
+                           tblocks, u, pp);
+    else
+        hipLaunchKernelGGL((k_direct<double, STC_DEN_DOT, DIRECT_TP64>), g, b, 0, s, n, x, zeta, area, m, targets, chunk_len,
+                           tblocks, u, pp);
+    if (pp)
+        hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, x, m, targets, chunks,
+                           pp, u);
 }
 
 }  // namespace stc

@@ -105,8 +105,12 @@ struct EvalArgs {
 void launch_near(hipStream_t s, const EvalArgs& a, u32 type_mask);
 void launch_far_targets(hipStream_t s, const EvalArgs& a);
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate);
+int direct_blocks_per_cu(int precision, int denominator);
+int direct_targets_per_block(int precision);
+void direct_split(i64 n, i64 m, int cus, int blocks_per_cu, int targets_per_block, u32* chunks, i64* chunk_len);
 void launch_direct(hipStream_t s, i64 n, const double* x, const double* zeta, const double* area, i64 m,
-                   const i64* targets, int precision, int denominator, double* u);
+                   const i64* targets, int precision, int denominator, u32 chunks, i64 chunk_len, double* part,
+                   double* u);
 
 // k_mlp.hip -- the learned form's network (12 -> 64 -> 64 -> 4, BF16 on the matrix cores)
 int mlp_param_count();

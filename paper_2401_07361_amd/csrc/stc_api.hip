@@ -775,9 +775,29 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
     if (n == 0 || !d_x || !d_zeta || !d_area || !d_u || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area) ||
         !aligned8(d_u) || (d_targets && !aligned8(d_targets)))
         return STC_ERR_INVALID_ARG;
-    launch_direct(static_cast<hipStream_t>(hip_stream), n, d_x, d_zeta, d_area, m, d_targets, precision, denominator,
-                  d_u);
-    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+    // Few targets cannot fill the chip: split the sources into chunks whose
+    // partial sums live in a stream-ordered allocation, released on the same
+    // stream after the fixed-order reduction.  If that allocation fails the
+    // sum runs unsplit.
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    u32 chunks = 1;
+    i64 chunk_len = n;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+        return STC_ERR_DEVICE;
+    direct_split(n, m, cus, direct_blocks_per_cu(precision, denominator), direct_targets_per_block(precision), &chunks,
+                 &chunk_len);
+    double* part = nullptr;
+    if (chunks > 1 && hipMallocAsync(reinterpret_cast<void**>(&part), (size_t)chunks * (size_t)m * 3 * sizeof(double),
+                                     s) != hipSuccess) {
+        (void)hipGetLastError();
+        part = nullptr;
+    }
+    launch_direct(s, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, chunks, chunk_len, part, d_u);
+    const hipError_t le = hipGetLastError();
+    if (part && hipFreeAsync(part, s) != hipSuccess) return STC_ERR_DEVICE;
+    return le == hipSuccess ? STC_OK : STC_ERR_DEVICE;
 }
 
 // Enqueues one RK4 step of every member on c->stream (no host
