@@ -37,6 +37,7 @@ enum Flag : int {
     F_NONFINITE = 0,  // a particle position lies in no root face
     F_SLOTS = 1,      // more nodes with proxy charges than storage slots
     F_SLOT_CTR = 2,   // next free storage slot (counter)
+    F_BIN_EXACT = 3,  // points queued for exact point location
     F_LEVEL = 8,      // F_LEVEL + l: nodes of level l with more than N_T particles (list length)
     F_COUNT = 24
 };
@@ -106,36 +107,39 @@ __device__ __forceinline__ void two_prod(double a, double b, double& p, double& 
 // products, by error-free transformations: each triple product becomes four
 // doubles summing to it exactly, and the 24 terms are accumulated into a
 // non-overlapping expansion (Shewchuk's grow-expansion); the sign of the
-// largest non-zero component is the sign of the sum.
+// largest non-zero component is the sign of the sum.  Every term is appended
+// (zeros included), so the expansion length at each step is a compile-time
+// constant: with the loops unrolled the expansion stays in registers.
 __device__ __noinline__ int orient_exact_slow(const double* a, const double* b, const double* p) {
     double e[24];
-    int m = 0;
     const double tx[6] = {p[0], p[0], p[1], p[1], p[2], p[2]};
     const double ty[6] = {a[1], a[2], a[2], a[0], a[0], a[1]};
-    const double tz[6] = {b[2], b[1], b[0], b[2], b[1], b[0]};
-    const double sg[6] = {1.0, -1.0, 1.0, -1.0, 1.0, -1.0};
+    const double tz[6] = {b[2], -b[1], b[0], -b[2], b[1], -b[0]};
+#pragma unroll
     for (int t = 0; t < 6; ++t) {
         double h1, l1, h2, l2, h3, l3;
         two_prod(tx[t], ty[t], h1, l1);
-        two_prod(h1, sg[t] * tz[t], h2, l2);
-        two_prod(l1, sg[t] * tz[t], h3, l3);
+        two_prod(h1, tz[t], h2, l2);
+        two_prod(l1, tz[t], h3, l3);
         const double parts[4] = {h2, l2, h3, l3};
+#pragma unroll
         for (int u = 0; u < 4; ++u) {
             double q = parts[u];
+            const int m = 4 * t + u;
+#pragma unroll
             for (int i = 0; i < m; ++i) {
                 double s, h;
                 two_sum(q, e[i], s, h);
                 e[i] = h;
                 q = s;
             }
-            e[m++] = q;
+            e[m] = q;
         }
     }
-    for (int i = m - 1; i >= 0; --i) {
-        if (e[i] > 0) return 1;
-        if (e[i] < 0) return -1;
-    }
-    return 0;
+    int sign = 0;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) sign = e[i] > 0 ? 1 : (e[i] < 0 ? -1 : sign);
+    return sign;
 }
 
 // Second stage: the determinant in double-double arithmetic.  Each 2x2
@@ -145,7 +149,7 @@ __device__ __noinline__ int orient_exact_slow(const double* a, const double* b, 
 // products are summed exactly and the eight small terms in plain FP64.  The
 // total error stays below 64 eps^2 perm; the sign is taken when |det| exceeds
 // twice that, otherwise -2 (undecided) is returned.
-__device__ __noinline__ int orient_dd(const double* a, const double* b, const double* p, double perm) {
+__device__ __forceinline__ int orient_dd(const double* a, const double* b, const double* p, double perm) {
 #pragma clang fp contract(off)
     double hs[3], sm[8];
     int nsm = 0;
@@ -175,29 +179,49 @@ __device__ __noinline__ int orient_dd(const double* a, const double* b, const do
     return -2;
 }
 
-// Filtered exact orientation.  The plain FP64 evaluation below has a
-// rounding error of at most about 5 eps * perm; when |det| exceeds 8 eps *
-// perm its sign is certain; otherwise the double-double stage decides, and
-// only when that cannot (|det| below ~1e-30 perm, typically an exact zero)
-// the exact expansion does.
-__device__ __forceinline__ int orient(const double* a, const double* b, const double* p) {
+// Bound on perm = sum_i |p_i| (|a_j b_k| + |a_k b_j|) for a and b of unit
+// length (the tree's vertices, normalised in FP64): every |a_j b_k| is at
+// most (1 + eps)^2, so perm <= 2 (1 + eps)^2 |p|_1.  One value per point.
+__device__ __forceinline__ double perm_bound(const double* p) {
+    return 2.000001 * ((fabs(p[0]) + fabs(p[1])) + fabs(p[2]));
+}
+
+// The orientation without the exact expansion: +1, -1 or 0 where the FP64
+// filter, a shared vertex or the double-double stage decides, else -2.
+__device__ __forceinline__ int orient_filtered(const double* a, const double* b, const double* p, double pb) {
 #pragma clang fp contract(off)
     const double cx = a[1] * b[2] - a[2] * b[1];
     const double cy = a[2] * b[0] - a[0] * b[2];
     const double cz = a[0] * b[1] - a[1] * b[0];
     const double det = (p[0] * cx + p[1] * cy) + p[2] * cz;
-    const double perm = fabs(p[0]) * (fabs(a[1] * b[2]) + fabs(a[2] * b[1])) +
-                        fabs(p[1]) * (fabs(a[2] * b[0]) + fabs(a[0] * b[2])) +
-                        fabs(p[2]) * (fabs(a[0] * b[1]) + fabs(a[1] * b[0]));
-    const double bound = 8.0 * 1.1102230246251565e-16 * perm;
+    const double bound = 8.0 * 1.1102230246251565e-16 * pb;
     if (det > bound) return 1;
     if (det < -bound) return -1;
     // p equal to a or b: the determinant is exactly zero (grid particles are
     // the vertices of the finer triangles, so this is the common exact case)
     if ((p[0] == a[0] && p[1] == a[1] && p[2] == a[2]) || (p[0] == b[0] && p[1] == b[1] && p[2] == b[2])) return 0;
-    const int dd = orient_dd(a, b, p, perm);
-    if (dd != -2) return dd;
-    return orient_exact_slow(a, b, p);
+    // p the antipode of a or b (a root vertex seen from the far side)
+    if ((p[0] == -a[0] && p[1] == -a[1] && p[2] == -a[2]) || (p[0] == -b[0] && p[1] == -b[1] && p[2] == -b[2]))
+        return 0;
+    // every term p_i (a_j b_k - a_k b_j) with a zero factor: the determinant
+    // is exactly zero (a point on a root edge that lies in a coordinate plane)
+    if ((p[0] == 0.0 || ((a[1] == 0.0 || b[2] == 0.0) && (a[2] == 0.0 || b[1] == 0.0))) &&
+        (p[1] == 0.0 || ((a[2] == 0.0 || b[0] == 0.0) && (a[0] == 0.0 || b[2] == 0.0))) &&
+        (p[2] == 0.0 || ((a[0] == 0.0 || b[1] == 0.0) && (a[1] == 0.0 || b[0] == 0.0))))
+        return 0;
+    return orient_dd(a, b, p, pb);
+}
+
+// Filtered exact orientation, a and b of unit length, pb = perm_bound(p).
+// The plain FP64 evaluation below has a rounding error of at most about
+// 5 eps * perm <= 5 eps * pb; when |det| exceeds 8 eps * pb its sign is
+// certain; otherwise the double-double stage decides, and only when that
+// cannot (|det| below ~1e-30, typically an exact zero) the exact expansion
+// does.  Points of a grid finer than the tree lie within rounding distance
+// of tree edges, so the double-double stage is common: it is inlined.
+__device__ __forceinline__ int orient(const double* a, const double* b, const double* p, double pb) {
+    const int o = orient_filtered(a, b, p, pb);
+    return o != -2 ? o : orient_exact_slow(a, b, p);
 }
 
 // Interpolation point m of node g (Sec. 3, interpolation in triangles):

@@ -15,14 +15,24 @@ namespace stc {
 // the centre child.  All orientations are exact.  The sort key is
 // (member, leaf key, index): the member of particle i is the last m with
 // off[m] <= i (a fixed-index scan, so the offsets stay in kernel arguments).
+//
+// Two passes: k_bin decides every orientation with the FP64 filter or the
+// double-double stage and queues the points where neither can (an exact zero
+// that no structural test recognises); k_bin_exact locates the queued points
+// with the exact expansion.  Keeping the expansion out of k_bin keeps its register
+// count, and so its occupancy, those of the common path.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n,
-                                              const NodeGeo* __restrict__ geo, int L, MemberOffsets mo,
-                                              u64* __restrict__ keys, u32* __restrict__ flags) {
-    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double p[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
-    int face = -1;
+template <bool EXACT>
+__device__ __forceinline__ int orient_sel(const double* a, const double* b, const double* p, double pb) {
+    if (EXACT) return orient(a, b, p, pb);
+    return orient_filtered(a, b, p, pb);  // -2 where only the exact expansion can decide
+}
+
+// Leaf key of point p (face in the top bits, one base-4 digit per level).
+// Returns false if, without EXACT, an orientation could not be decided.
+template <bool EXACT>
+__device__ __forceinline__ bool locate(const double* p, const NodeGeo* __restrict__ geo, int L, u32* key_out) {
+    const double pb = perm_bound(p);
     // candidate: the face whose circumcentre is nearest; if p is strictly
     // inside it no other face contains p, else scan in index order
     int best = 0;
@@ -34,33 +44,61 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n
             best = f;
         }
     }
+    int face = -1;
     {
         const NodeGeo& g = geo[best];
-        if (orient(g.v[0], g.v[1], p) > 0 && orient(g.v[1], g.v[2], p) > 0 && orient(g.v[2], g.v[0], p) > 0)
-            face = best;
+        int o = orient_sel<EXACT>(g.v[0], g.v[1], p, pb);
+        if (o == -2) return false;
+        if (o > 0) {
+            o = orient_sel<EXACT>(g.v[1], g.v[2], p, pb);
+            if (o == -2) return false;
+            if (o > 0) {
+                o = orient_sel<EXACT>(g.v[2], g.v[0], p, pb);
+                if (o == -2) return false;
+                if (o > 0) face = best;
+            }
+        }
     }
     for (int f = 0; f < 20 && face < 0; ++f) {
         const NodeGeo& g = geo[f];
-        if (orient(g.v[0], g.v[1], p) >= 0 && orient(g.v[1], g.v[2], p) >= 0 &&
-            orient(g.v[2], g.v[0], p) >= 0)
-            face = f;
+        int o = orient_sel<EXACT>(g.v[0], g.v[1], p, pb);
+        if (o == -2) return false;
+        if (o < 0) continue;
+        o = orient_sel<EXACT>(g.v[1], g.v[2], p, pb);
+        if (o == -2) return false;
+        if (o < 0) continue;
+        o = orient_sel<EXACT>(g.v[2], g.v[0], p, pb);
+        if (o == -2) return false;
+        if (o < 0) continue;
+        face = f;
     }
-    if (face < 0) {  // non-finite input: no face contains it
-        atomicOr(&flags[F_NONFINITE], 1u);
-        face = 0;
-    }
+    if (face < 0) face = 0;  // cannot happen for a finite point (the faces cover the sphere)
     u32 key = (u32)face;
     i64 off = 20;  // level_offset(1)
     for (int lvl = 0; lvl < L; ++lvl) {
         const NodeGeo& c = geo[off + 4 * (i64)key + 3];  // (m12, m23, m31)
-        u32 digit;
-        if (orient(c.v[2], c.v[0], p) < 0) digit = 0;
-        else if (orient(c.v[0], c.v[1], p) < 0) digit = 1;
-        else if (orient(c.v[1], c.v[2], p) < 0) digit = 2;
-        else digit = 3;
+        u32 digit = 3;
+        int o = orient_sel<EXACT>(c.v[2], c.v[0], p, pb);
+        if (o == -2) return false;
+        if (o < 0) digit = 0;
+        else {
+            o = orient_sel<EXACT>(c.v[0], c.v[1], p, pb);
+            if (o == -2) return false;
+            if (o < 0) digit = 1;
+            else {
+                o = orient_sel<EXACT>(c.v[1], c.v[2], p, pb);
+                if (o == -2) return false;
+                if (o < 0) digit = 2;
+            }
+        }
         key = 4 * key + digit;
         off = 4 * off + 20;  // level_offset(lvl + 2)
     }
+    *key_out = key;
+    return true;
+}
+
+__device__ __forceinline__ u64 bin_key(u32 key, i64 i, int L, const MemberOffsets& mo) {
     u32 member = 0;
     if (mo.m > 1) {
 #pragma unroll
@@ -68,7 +106,40 @@ __global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n
             if (k < mo.m && mo.off[k] <= i) member = (u32)k;
     }
     key |= member << (2 * L + 5);
-    keys[i] = ((u64)key << 32) | (u64)i;
+    return ((u64)key << 32) | (u64)i;
+}
+
+// queue: room for n indices; flags[F_BIN_EXACT] counts the queued points
+__global__ __launch_bounds__(256) void k_bin(const double* __restrict__ x, i64 n,
+                                              const NodeGeo* __restrict__ geo, int L, MemberOffsets mo,
+                                              u64* __restrict__ keys, u32* __restrict__ queue,
+                                              u32* __restrict__ flags) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double p[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+    u32 key = 0;
+    bool decided = true;
+    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) {
+        atomicOr(&flags[F_NONFINITE], 1u);  // reported at synchronisation; the key is arbitrary
+    } else {
+        decided = locate<false>(p, geo, L, &key);
+    }
+    const u32 slot = wave_append(&flags[F_BIN_EXACT], !decided);
+    if (decided) keys[i] = bin_key(key, i, L, mo);
+    else queue[slot] = (u32)i;
+}
+
+__global__ __launch_bounds__(256) void k_bin_exact(const double* __restrict__ x, const NodeGeo* __restrict__ geo,
+                                                    int L, MemberOffsets mo, const u32* __restrict__ queue,
+                                                    const u32* __restrict__ flags, u64* __restrict__ keys) {
+    const u32 cnt = flags[F_BIN_EXACT];
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+        const i64 i = queue[q];
+        const double p[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+        u32 key = 0;
+        (void)locate<true>(p, geo, L, &key);
+        keys[i] = bin_key(key, i, L, mo);
+    }
 }
 
 // sorted position -> input index, leaf key, FP64 SoA positions
@@ -607,9 +678,10 @@ inline unsigned blocks_for(i64 n, int threads) { return (unsigned)((n + threads 
 }
 
 void launch_bin(hipStream_t s, const double* x, i64 n, const NodeGeo* geo, int L, const MemberOffsets& mo,
-                u64* keys, u32* flags) {
+                u64* keys, u32* queue, u32* flags) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n, geo, L, mo, keys, flags);
+    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, n, geo, L, mo, keys, queue, flags);
+    hipLaunchKernelGGL(k_bin_exact, dim3(64), dim3(256), 0, s, x, geo, L, mo, queue, flags, keys);
 }
 
 void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* perm, u32* leaf, double* sx,

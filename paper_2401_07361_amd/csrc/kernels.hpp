@@ -22,7 +22,7 @@ struct ClassTab {
 
 // k_tree.hip
 void launch_bin(hipStream_t s, const double* x, i64 n, const NodeGeo* geo, int L, const MemberOffsets& mo,
-                u64* keys, u32* flags);
+                u64* keys, u32* queue, u32* flags);
 void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* perm, u32* leaf,
                    double* sx, double* sy, double* sz);
 void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i32* nbeg, i32* nend);

@@ -272,7 +272,9 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     MemberOffsets mo{};
     mo.m = members;
     for (int m = 0; m <= members; ++m) mo.off[m] = off[m];
-    launch_bin(s, d_x, n, c->geo, c->L, mo, c->keys_a, c->flags);
+    // the sort's second key buffer is free until the sort: it holds the
+    // queue of points located exactly
+    launch_bin(s, d_x, n, c->geo, c->L, mo, c->keys_a, reinterpret_cast<u32*>(c->keys_b), c->flags);
     radix_sort(s, c->keys_a, c->keys_b, nullptr, (u32)n, 32, 32 + c->LB + bits_for(members),
                SortScratch{c->hist, c->hist_totals, c->hist_blocks}, &c->keys_sorted);
     launch_gather(s, c->keys_sorted, n, d_x, c->perm, c->leaf, c->sx, c->sy, c->sz);

@@ -51,6 +51,12 @@ def _case(name):
     elif name == "clustered_6000":  # depth limit reached, leaves above N_T
         x = S.clustered_sphere_points(6000, 9, width=0.004)
         z = S.gaussian_vortex(x, seed=9)
+    elif name == "planes_3000":     # a coordinate exactly 0: on the root edges that lie in
+        x = S.random_sphere_points(3000, 7)   # coordinate planes (orientation exactly 0)
+        x[np.arange(3000) % 3 == 0, 0] = 0.0
+        x[np.arange(3000) % 3 == 1, 1] = 0.0
+        x /= np.linalg.norm(x, axis=1)[:, None]
+        z = S.gaussian_vortex(x, seed=7)
     elif name == "tiny_50":
         x = S.random_sphere_points(50, 1)
         z = np.random.default_rng(1).standard_normal(50)
@@ -66,6 +72,7 @@ CASES = {
     "random_7001": (0.6, 5, 20, None),
     "clustered_6000": (0.8, 4, 24, 4),
     "tiny_50": (0.7, 3, 4, None),
+    "planes_3000": (0.7, 5, 16, None),
 }
 
 # Denominator for the FP64 parity of each case.  The literal 1 - x.y loses
@@ -75,7 +82,7 @@ CASES = {
 # |x - y|^2 / 2 form (the paper's remedy, Sec. 2), whose rounding error
 # does not grow as pairs approach.
 CASE_DEN = {"grid_l5": "dot", "rotated_l4": "dot", "random_7001": "dist2", "clustered_6000": "dist2",
-            "tiny_50": "dot"}
+            "tiny_50": "dot", "planes_3000": "dist2"}
 
 
 @functools.lru_cache(maxsize=None)
