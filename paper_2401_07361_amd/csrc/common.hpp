@@ -18,6 +18,9 @@ using i64 = int64_t;
 constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
 constexpr int kMaxDegree = 14;
 constexpr int kMaxNp = (kMaxDegree + 1) * (kMaxDegree + 2) / 2;  // 120
+constexpr int UP_CHUNK = 2048;  // particles per upward-pass item
+constexpr int UP_BATCH = 8;     // big nodes per workgroup when the upward pass finishes
+constexpr int kMaxLevels = 12;  // deepest tree level
 
 // Ensembles (batched evaluation): up to kMaxMembers independent particle
 // sets share one launch per phase.  Node ids carry the member above the local
@@ -38,6 +41,7 @@ enum Flag : int {
     F_SLOTS = 1,      // more nodes with proxy charges than storage slots
     F_SLOT_CTR = 2,   // next free storage slot (counter)
     F_BIN_EXACT = 3,  // points queued for exact point location
+    F_ITEMS = 4,      // upward-pass items (pieces of big nodes' particle ranges)
     F_LEVEL = 8,      // F_LEVEL + l: nodes of level l with more than N_T particles (list length)
     F_COUNT = 24
 };

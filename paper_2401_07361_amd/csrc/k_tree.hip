@@ -194,159 +194,233 @@ __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i
 // ---------------------------------------------------------------------------
 // Upward pass (Sec. 3, particle-cluster interaction).  For every node P with
 // more than N_T particles:
-//   omega_k = sum over sources y of B_k(b(y)) q(y),  b = M_P^{-1} y,
+//   omega_k = sum over the particles y of P of B_k(b(y)) q(y),  b = M_P^{-1} y,
 //   w_m     = |b_m1 v1 + b_m2 v2 + b_m3 v3|^d * sum_k (V_ref^{-1})_{km} omega_k
-// (w = V^{-T} omega with the node's Vandermonde matrix V = diag(s^d) V_ref).
-// The sources of P are its particles when P is at the depth limit, and
-// otherwise its four children: a child with more than N_T particles
-// contributes its interpolation points with their proxy charges, a smaller
-// child its particles.  Every triangle's basis spans the same space
-// (homogeneous polynomials of degree d restricted to the sphere), so
-// re-interpolating a child's proxy charges at the parent reproduces the
-// parent's proxy charges computed from the particles, up to rounding.
-// Levels are processed bottom-up, one launch per level (grid.y = member), one
-// workgroup per node; sources go through LDS in chunks of 64 (barycentric
-// powers), thread t accumulating basis function t % np over every
-// (256/np)-th source.  Proxy records live in the node's storage slot.
-// With src_np > 0 every big node instead takes its own src_np proxy points
-// at record offset src_poff as sources: re-interpolating a higher degree's
-// proxy charges gives a lower degree's exactly (its space is contained in
-// the higher one's), so the learned form's four degrees need one pass over
-// the particles.
+// (w = V^{-T} omega with the node's Vandermonde matrix V = diag(s^d) V_ref),
+// B_k = c_k b1^i b2^j b3^(d-i-j) with k running over i, then j.
+//
+// Every node's weights come straight from its own particles, so no level
+// waits for another.  The tree build cut each big node's particle range into
+// items of at most UP_CHUNK particles (k_node_counts).  k_upward_items: one
+// wave per item, lane l taking particles l, l + 64, ...; the terms
+// q b1^i b2^j b3^(d-i-j) of all (i, j) accumulate in registers, then the wave
+// adds them across lanes by recursive halving and writes the item's sums.
+// k_upward_finish: a workgroup per batch of UP_BATCH big nodes adds each
+// node's item sums in item order (deterministic), multiplies the batch by
+// V_ref^{-1} as one small matrix product through LDS, and writes the proxy
+// points and charges into the nodes' storage slots.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_upward_level(int lvl_lo, int lvl_hi, int L, int NB,
-                                                       const i64* __restrict__ level_off_tab,
-                                                       const u32* __restrict__ flags, const i32* __restrict__ big_list,
-                                                       u32 per_level, const i32* __restrict__ nbeg,
-                                                       const i32* __restrict__ nend, int n_crit,
+
+// index of term (i, j) in the k order
+__host__ __device__ constexpr int term_index(int d, int i, int j) { return i * (d + 1) - i * (i - 1) / 2 + j; }
+
+// Recursive halving over the 64 lanes: v holds N partial sums of terms
+// [start, start + len) (slots past len are zero).  Lanes with bit MASK set
+// keep the upper half and send the lower; partners (lanes differing only in
+// that bit) describe the same terms, so each keeps the sum of both.
+template <int N, int MASK>
+struct WaveHalve {
+    __device__ __forceinline__ static void run(const double (&v)[N], int lane, int start, int len,
+                                               double* __restrict__ out) {
+        constexpr int H = (N + 1) / 2;
+        const bool up = (lane & MASK) != 0;
+        double nv[H];
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+            const double lo = v[t];
+            const double hi = (t + H < N) ? v[t + H] : 0.0;
+            const double send = up ? lo : hi;
+            const double keep = up ? hi : lo;
+            nv[t] = keep + __shfl_xor(send, MASK, 64);
+        }
+        if (up) {
+            start += H;
+            len = len > H ? len - H : 0;
+        } else {
+            len = len < H ? len : H;
+        }
+        WaveHalve<H, MASK / 2>::run(nv, lane, start, len, out);
+    }
+};
+template <int N>
+struct WaveHalve<N, 0> {
+    __device__ __forceinline__ static void run(const double (&v)[N], int, int start, int len,
+                                               double* __restrict__ out) {
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+            if (t < len) out[start + t] = v[t];
+    }
+};
+
+// Terms with I0 <= i <= I1 of one item's particles [lo, hi), summed over the
+// wave and written to out[k] (k the term index).
+template <int D, int I0, int I1>
+__device__ __forceinline__ void item_terms(const double* __restrict__ sx, const double* __restrict__ sy,
+                                           const double* __restrict__ sz, const double* __restrict__ q, int lo,
+                                           int hi, const NodeGeo& g, double* __restrict__ out) {
+    constexpr int M0 = term_index(D, I0, 0), M1 = term_index(D, I1 + 1, 0);
+    constexpr int NT = M1 - M0;
+    const int lane = threadIdx.x & 63;
+    double acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+    const double m00 = g.minv[0][0], m01 = g.minv[0][1], m02 = g.minv[0][2];
+    const double m10 = g.minv[1][0], m11 = g.minv[1][1], m12 = g.minv[1][2];
+    const double m20 = g.minv[2][0], m21 = g.minv[2][1], m22 = g.minv[2][2];
+    // the next particle is loaded while the current one's terms accumulate
+    int j = lo + lane;
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0, nq = 0.0;
+    if (j < hi) n0 = sx[j], n1 = sy[j], n2 = sz[j], nq = q[j];
+    for (; j < hi; j += 64) {
+        const double y0 = n0, y1 = n1, y2 = n2, qq = nq;
+        if (j + 64 < hi) n0 = sx[j + 64], n1 = sy[j + 64], n2 = sz[j + 64], nq = q[j + 64];
+        const double b0 = (m00 * y0 + m01 * y1) + m02 * y2;
+        const double b1 = (m10 * y0 + m11 * y1) + m12 * y2;
+        const double b2 = (m20 * y0 + m21 * y1) + m22 * y2;
+        double p1[D + 1], p2[D + 1];
+        p1[0] = 1.0;
+        p2[0] = 1.0;
+#pragma unroll
+        for (int t = 1; t <= D; ++t) {
+            p1[t] = p1[t - 1] * b1;
+            p2[t] = p2[t - 1] * b2;
+        }
+        double qi = qq;
+#pragma unroll
+        for (int i = 0; i < I0; ++i) qi *= b0;
+#pragma unroll
+        for (int i = I0; i <= I1; ++i) {
+#pragma unroll
+            for (int jj = 0; jj <= D - i; ++jj)
+                acc[term_index(D, i, jj) - M0] = __fma_rn(qi, p1[jj] * p2[D - i - jj], acc[term_index(D, i, jj) - M0]);
+            qi *= b0;
+        }
+    }
+    WaveHalve<NT, 32>::run(acc, lane, M0, NT, out);
+}
+
+// last i of the first group of terms: at most 66 accumulators per pass
+__host__ __device__ constexpr int upward_split(int d) {
+    int a = d;
+    while (a > 0 && term_index(d, a + 1, 0) > 66) --a;
+    return a;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_upward_items(const u32* __restrict__ flags, u32 items_cap,
+                                                       const i32* __restrict__ item_node,
+                                                       const i32* __restrict__ item_chunk, u32 node_mask,
+                                                       const i32* __restrict__ nbeg, const i32* __restrict__ nend,
                                                        const NodeGeo* __restrict__ geo, const double* __restrict__ sx,
                                                        const double* __restrict__ sy, const double* __restrict__ sz,
-                                                       const double* __restrict__ q, RefDev ref, int NPT, int poff,
-                                                       int src_poff, int src_np, const i32* __restrict__ slot,
-                                                       Prox* __restrict__ prox) {
-    __shared__ double pw[64][3][kMaxDegree + 1];
-    __shared__ double qs[64];
-    __shared__ double red[256];
-    __shared__ double omega[kMaxNp][1];
-    __shared__ double wout[kMaxNp][1];
-    const int tid = threadIdx.x;
-    const int d = ref.degree, np = ref.np;
-    const int S = 256 / np;  // source slices
-    const int k = tid % np, sl = tid / np;
-    int e0 = 0, e1 = 0, e2 = 0;
-    if (sl < S) {
-        e0 = ref.expo[3 * k];
-        e1 = ref.expo[3 * k + 1];
-        e2 = ref.expo[3 * k + 2];
+                                                       const double* __restrict__ q, double* __restrict__ part) {
+    constexpr int NP = (D + 1) * (D + 2) / 2;
+    constexpr int A = upward_split(D);
+    u32 n_items = flags[F_ITEMS];
+    if (n_items > items_cap) n_items = items_cap;
+    const u32 waves = gridDim.x * (blockDim.x / 64);
+    for (u32 it = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); it < n_items; it += waves) {
+        const i32 node = item_node[it];
+        const i32 b = nbeg[node], e = nend[node];
+        const int lo = b + item_chunk[it] * UP_CHUNK;
+        const int hi = (lo + UP_CHUNK) < e ? lo + UP_CHUNK : e;
+        const NodeGeo& g = geo[(u32)node & node_mask];
+        double* out = part + (size_t)it * NP;
+        item_terms<D, 0, A>(sx, sy, sz, q, lo, hi, g, out);
+        if constexpr (A < D) item_terms<D, A + 1, D>(sx, sy, sz, q, lo, hi, g, out);
     }
-    const u32 lm = (1u << NB) - 1u;
-    for (int lvl = lvl_hi; lvl >= lvl_lo; --lvl) {
-        u32 nbl = flags[F_LEVEL + lvl];
+}
+
+// Batch j = big nodes [UP_BATCH j, UP_BATCH (j + 1)) of the level lists taken
+// in level order.  om[r][k] = c_k * (sum of node r's item sums), then
+// w[r][m] = |P_m|^d sum_k om[r][k] (V_ref^{-1})_{km} with V_ref^{-1} staged in
+// LDS when it fits (n_p <= 78), else read from memory.  Small batches keep
+// many workgroups in flight: the work per node is small, its chain of
+// dependent loads is what takes time.
+template <int D>
+__global__ __launch_bounds__(256) void k_upward_finish(int L, const u32* __restrict__ flags,
+                                                        const i32* __restrict__ big_list, u32 per_level,
+                                                        const i32* __restrict__ nbeg, const i32* __restrict__ nend,
+                                                        const i32* __restrict__ item_base, u32 node_mask,
+                                                        const NodeGeo* __restrict__ geo,
+                                                        const double* __restrict__ part, RefDev ref, int NPT, int poff,
+                                                        const i32* __restrict__ slot, Prox* __restrict__ prox) {
+    constexpr int NP = (D + 1) * (D + 2) / 2;
+    constexpr bool LDS_V = NP <= 78;
+    constexpr int R = UP_BATCH;
+    __shared__ double om[R][NP];
+    __shared__ double vl[LDS_V ? NP * NP : 1];
+    __shared__ double gv[R][9];  // node vertices
+    __shared__ i32 slots[R], items[R], bases[R];
+    const int tid = threadIdx.x;
+    if constexpr (LDS_V) {
+        for (int t = tid; t < NP * NP; t += 256) vl[t] = ref.vinv[t];
+    }
+    const double* __restrict__ V = LDS_V ? vl : ref.vinv;
+    u32 lvl_end[kMaxLevels + 1];
+    u32 total = 0;
+    for (int l = 0; l <= L; ++l) {
+        u32 nbl = flags[F_LEVEL + l];
         if (nbl > per_level) nbl = per_level;
-        for (u32 bi = blockIdx.x; bi < nbl; bi += gridDim.x) {
-            const i64 node = big_list[(size_t)lvl * per_level + bi];
-            const i64 local = node & lm, mbase = node & ~(i64)lm;
-            const i64 t = local - level_off_tab[lvl];  // index within the level
-            const i32 b = nbeg[node], e = nend[node];
-            const NodeGeo& g = geo[local];
-            // source segments: kind 0 = particle range [first, first+cnt), 1 = points of node `id`
-            int seg_kind[4], seg_cnt[4];
-            i64 seg_id[4];
-            int nseg = 0;
-            int rpoff = poff;  // record offset of proxy sources
-            if (src_np > 0) {
-                seg_kind[0] = 1;
-                seg_id[0] = node;
-                seg_cnt[0] = src_np;
-                nseg = 1;
-                rpoff = src_poff;
-            } else if (lvl == L) {
-                seg_kind[0] = 0;
-                seg_id[0] = b;
-                seg_cnt[0] = e - b;
-                nseg = 1;
-            } else {
-                const i64 child_off = mbase + level_off_tab[lvl + 1];
-                for (int c = 0; c < 4; ++c) {
-                    const i64 cid = child_off + 4 * t + c;
-                    const i32 cb = nbeg[cid], cn = nend[cid] - cb;
-                    if (cn <= 0) continue;
-                    if (cn > n_crit) {
-                        seg_kind[nseg] = 1;
-                        seg_id[nseg] = cid;
-                        seg_cnt[nseg] = np;
-                    } else {
-                        seg_kind[nseg] = 0;
-                        seg_id[nseg] = cb;
-                        seg_cnt[nseg] = cn;
-                    }
-                    ++nseg;
-                }
-            }
-            int total = 0;
-            for (int sgi = 0; sgi < nseg; ++sgi) total += seg_cnt[sgi];
-            double acc = 0.0;
-            for (int c0 = 0; c0 < total; c0 += 64) {
-                const int cnt = (total - c0) < 64 ? (total - c0) : 64;
-                if (tid < cnt) {
-                    int idx = c0 + tid, sgi = 0;
-                    while (idx >= seg_cnt[sgi]) {
-                        idx -= seg_cnt[sgi];
-                        ++sgi;
-                    }
-                    double y0, y1, y2, qq;
-                    if (seg_kind[sgi] == 0) {
-                        const i64 j = seg_id[sgi] + idx;
-                        y0 = sx[j];
-                        y1 = sy[j];
-                        y2 = sz[j];
-                        qq = q[j];
-                    } else {
-                        const Prox pr = prox[(size_t)slot[seg_id[sgi]] * NPT + rpoff + idx];
-                        y0 = pr.x;
-                        y1 = pr.y;
-                        y2 = pr.z;
-                        qq = pr.w;
-                    }
-                    for (int a = 0; a < 3; ++a) {
-                        const double be = (g.minv[a][0] * y0 + g.minv[a][1] * y1) + g.minv[a][2] * y2;
-                        double pp = 1.0;
-                        for (int tt = 0; tt <= d; ++tt) {
-                            pw[tid][a][tt] = pp;
-                            pp *= be;
-                        }
-                    }
-                    qs[tid] = qq;
-                }
-                __syncthreads();
-                if (sl < S) {
-                    for (int j = sl; j < cnt; j += S) acc += qs[j] * (pw[j][0][e0] * pw[j][1][e1] * pw[j][2][e2]);
-                }
-                __syncthreads();
-            }
-            red[tid] = (sl < S) ? acc : 0.0;
-            __syncthreads();
-            if (tid < np) {
-                double sum = 0.0;
-                for (int tt = 0; tt < S; ++tt) sum += red[tt * np + tid];
-                omega[tid][0] = ref.coef[tid] * sum;
-            }
-            __syncthreads();
-            // w_m = |.|^d sum_k (V_ref^{-1})_{km} omega_k  (row m of V_ref^{-T})
-            block_matvec<256, 1>(ref.vinv, np, nullptr, omega, red, wout);
-            const size_t my_rec = (size_t)slot[node] * NPT + poff;
-            for (int m = tid; m < np; m += 256) {
-                double y[3];
-                const double nrm = proxy_point(g, ref.points + 3 * m, y);
-                Prox pr;
-                pr.x = y[0];
-                pr.y = y[1];
-                pr.z = y[2];
-                pr.w = ipow(nrm, d) * wout[m][0];
-                prox[my_rec + m] = pr;
-            }
-            __syncthreads();
+        total += nbl;
+        lvl_end[l] = total;
+    }
+    const u32 n_batch = (total + R - 1) / R;
+    for (u32 bj = blockIdx.x; bj < n_batch; bj += gridDim.x) {
+        const u32 g0 = bj * R;
+        const int nr = (total - g0) < (u32)R ? (int)(total - g0) : R;
+        if (tid < nr) {
+            const u32 gidx = g0 + tid;
+            int lvl = 0;
+            while (gidx >= lvl_end[lvl]) ++lvl;
+            const u32 bi = gidx - (lvl > 0 ? lvl_end[lvl - 1] : 0u);
+            const i32 node = big_list[(size_t)lvl * per_level + bi];
+            const i32 sl = slot[node];
+            slots[tid] = sl;
+            items[tid] = (nend[node] - nbeg[node] + UP_CHUNK - 1) / UP_CHUNK;
+            bases[tid] = item_base[sl];
+            const NodeGeo& g = geo[(u32)node & node_mask];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gv[tid][3 * a + c] = g.v[a][c];
         }
+        __syncthreads();
+        for (int o = tid; o < nr * NP; o += 256) {
+            const int r = o / NP, k = o - r * NP;
+            const size_t base = (size_t)bases[r];
+            double sum = 0.0;
+            for (int t = 0; t < items[r]; ++t) sum += part[(base + t) * NP + k];
+            om[r][k] = ref.coef[k] * sum;
+        }
+        __syncthreads();
+        for (int o = tid; o < nr * NP; o += 256) {
+            const int r = o / NP, m = o - r * NP;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int k = 0;
+#pragma unroll 4
+            for (; k + 4 <= NP; k += 4) {
+                a0 = __fma_rn(om[r][k], V[k * NP + m], a0);
+                a1 = __fma_rn(om[r][k + 1], V[(k + 1) * NP + m], a1);
+                a2 = __fma_rn(om[r][k + 2], V[(k + 2) * NP + m], a2);
+                a3 = __fma_rn(om[r][k + 3], V[(k + 3) * NP + m], a3);
+            }
+            for (; k < NP; ++k) a0 = __fma_rn(om[r][k], V[k * NP + m], a0);
+            // proxy point: normalise(b1 v1 + b2 v2 + b3 v3), |.| for the scale
+            const double* b = ref.points + 3 * m;
+            double p[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p[c] = (b[0] * gv[r][c] + b[1] * gv[r][3 + c]) + b[2] * gv[r][6 + c];
+            const double nrm = sqrt((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]);
+            const double inv = 1.0 / nrm;
+            Prox pr;
+            pr.x = p[0] * inv;
+            pr.y = p[1] * inv;
+            pr.z = p[2] * inv;
+            pr.w = ipow(nrm, D) * ((a0 + a1) + (a2 + a3));
+            prox[(size_t)slots[r] * NPT + poff + m] = pr;
+        }
+        __syncthreads();
     }
 }
 
@@ -584,8 +658,11 @@ __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbe
                                                       i64 n_nodes, int n_crit, int NB, int L,
                                                       const i64* __restrict__ level_off_tab, i32* __restrict__ ncnt,
                                                       i32* __restrict__ slot, u32 slot_cap, i32* __restrict__ big_list,
-                                                      u32 per_level, u32* __restrict__ flags) {
+                                                      u32 per_level, i32* __restrict__ item_node,
+                                                      i32* __restrict__ item_chunk, i32* __restrict__ item_base,
+                                                      u32 items_cap, u32* __restrict__ flags) {
     const u64 stride = (u64)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
     for (u64 b0 = (u64)blockIdx.x * blockDim.x; b0 < (u64)n_nodes; b0 += stride) {
         const u64 i = b0 + threadIdx.x;
         const bool ok = i < (u64)n_nodes;
@@ -609,6 +686,29 @@ __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbe
             if (big) {
                 if (pos < per_level) big_list[(size_t)lvl * per_level + pos] = (i32)i;
                 else atomicOr(&flags[F_SLOTS], 1u);
+            }
+        }
+        // upward-pass items: ceil(c / UP_CHUNK) per big node, a wave's items
+        // reserved with one atomic (exclusive scan over the lanes)
+        const u32 ni = big ? (u32)((c + UP_CHUNK - 1) / UP_CHUNK) : 0u;
+        u32 incl = ni;
+        for (int o = 1; o < 64; o <<= 1) {
+            const u32 t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        const u32 tot = __shfl(incl, 63, 64);
+        u32 ib = 0;
+        if (lane == 0 && tot > 0) ib = atomicAdd(&flags[F_ITEMS], tot);
+        ib = __shfl(ib, 0, 64) + (incl - ni);
+        if (big) {
+            if (sl < slot_cap && (u64)ib + ni <= (u64)items_cap) {
+                item_base[sl] = (i32)ib;
+                for (u32 t = 0; t < ni; ++t) {
+                    item_node[ib + t] = (i32)i;
+                    item_chunk[ib + t] = (i32)t;
+                }
+            } else {
+                atomicOr(&flags[F_SLOTS], 1u);
             }
         }
     }
@@ -700,24 +800,30 @@ void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, c
     hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, q);
 }
 
-void launch_upward(hipStream_t s, int NB, const i64* level_off_dev, const u32* flags, const i32* big_list,
-                   u32 per_level, const i32* nbeg, const i32* nend, int L, int n_crit, const NodeGeo* geo,
-                   const double* sx, const double* sy, const double* sz, const double* q, RefDev ref, int NPT,
-                   int poff, int src_poff, int src_np, const i32* slot, Prox* prox) {
-    // one workgroup per listed node (a fixed grid walks the list); levels
-    // bottom-up, or, to re-interpolate (reads only each node's own record),
-    // all levels in one launch
-    const unsigned grid = (unsigned)std::min<u32>(std::max<u32>(per_level, 1u), 2048u);
-    if (src_np > 0) {
-        hipLaunchKernelGGL(k_upward_level, dim3(grid), dim3(256), 0, s, 0, L, L, NB, level_off_dev, flags, big_list,
-                           per_level, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff, src_poff, src_np,
-                           slot, prox);
-        return;
+void launch_upward(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
+                   const i32* nbeg, const i32* nend, const i32* item_node, const i32* item_chunk,
+                   const i32* item_base, u32 items_cap, const NodeGeo* geo, const double* sx, const double* sy,
+                   const double* sz, const double* q, double* part, RefDev ref, int NPT, int poff, const i32* slot,
+                   Prox* prox) {
+    const u32 mask = (1u << NB) - 1u;
+    // items: a persistent grid of 4 waves per workgroup walks the item list;
+    // then batches of big nodes (a fixed grid walks them)
+    const dim3 gi(1024), bi(256);
+    const unsigned gf = (unsigned)std::min<u64>(((u64)(L + 1) * per_level + UP_BATCH - 1) / UP_BATCH, 2048u);
+    switch (ref.degree) {
+#define STC_UP_CASE(D)                                                                                          \
+    case D:                                                                                                     \
+        hipLaunchKernelGGL(k_upward_items<D>, gi, bi, 0, s, flags, items_cap, item_node, item_chunk, mask, nbeg, \
+                           nend, geo, sx, sy, sz, q, part);                                                      \
+        hipLaunchKernelGGL(k_upward_finish<D>, dim3(gf), bi, 0, s, L, flags, big_list, per_level, nbeg, nend,    \
+                           item_base, mask, geo, part, ref, NPT, poff, slot, prox);                              \
+        break;
+        STC_UP_CASE(1) STC_UP_CASE(2) STC_UP_CASE(3) STC_UP_CASE(4) STC_UP_CASE(5) STC_UP_CASE(6) STC_UP_CASE(7)
+        STC_UP_CASE(8) STC_UP_CASE(9) STC_UP_CASE(10) STC_UP_CASE(11) STC_UP_CASE(12) STC_UP_CASE(13)
+        STC_UP_CASE(14)
+#undef STC_UP_CASE
+        default: break;
     }
-    for (int lvl = L; lvl >= 0; --lvl)
-        hipLaunchKernelGGL(k_upward_level, dim3(grid), dim3(256), 0, s, lvl, lvl, L, NB, level_off_dev, flags,
-                           big_list, per_level, nbeg, nend, n_crit, geo, sx, sy, sz, q, ref, NPT, poff, src_poff,
-                           src_np, slot, prox);
 }
 
 void launch_downsample(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
@@ -742,10 +848,11 @@ void launch_fill_f64(hipStream_t s, double* p, i64 n, double v) {
 
 void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, int NB, int L,
                         const i64* level_off_dev, i32* ncnt, i32* slot, u32 slot_cap, i32* big_list, u32 per_level,
-                        u32* flags) {
+                        i32* item_node, i32* item_chunk, i32* item_base, u32 items_cap, u32* flags) {
     const i64 b = blocks_for(n_nodes, 256);
     hipLaunchKernelGGL(k_node_counts, dim3((unsigned)(b < 2048 ? b : 2048)), dim3(256), 0, s, nbeg, nend, n_nodes,
-                       n_crit, NB, L, level_off_dev, ncnt, slot, slot_cap, big_list, per_level, flags);
+                       n_crit, NB, L, level_off_dev, ncnt, slot, slot_cap, big_list, per_level, item_node,
+                       item_chunk, item_base, items_cap, flags);
 }
 
 void launch_traverse_init(hipStream_t s, const TravArgs& t) {

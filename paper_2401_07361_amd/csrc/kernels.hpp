@@ -27,16 +27,17 @@ void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* 
                    double* sx, double* sy, double* sz);
 void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i32* nbeg, i32* nend);
 void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area, double* q);
-void launch_upward(hipStream_t s, int NB, const i64* level_off_dev, const u32* flags, const i32* big_list,
-                   u32 per_level, const i32* nbeg, const i32* nend, int L, int n_crit, const NodeGeo* geo,
-                   const double* sx, const double* sy, const double* sz, const double* q, RefDev ref, int NPT,
-                   int poff, int src_poff, int src_np, const i32* slot, Prox* prox);
+void launch_upward(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
+                   const i32* nbeg, const i32* nend, const i32* item_node, const i32* item_chunk,
+                   const i32* item_base, u32 items_cap, const NodeGeo* geo, const double* sx, const double* sy,
+                   const double* sz, const double* q, double* part, RefDev ref, int NPT, int poff, const i32* slot,
+                   Prox* prox);
 void launch_downsample(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
                        const NodeGeo* geo, const i32* slot, const double* ref_points, const double* T, ClassTab cls,
                        int NPT, Prox* prox);
 void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, int NB, int L,
                         const i64* level_off_dev, i32* ncnt, i32* slot, u32 slot_cap, i32* big_list, u32 per_level,
-                        u32* flags);
+                        i32* item_node, i32* item_chunk, i32* item_base, u32 items_cap, u32* flags);
 // Traversal: the root pairs of every member into front0 (counters zeroed),
 // then 2L + 2 level iterations from front0 whose frontier lengths live at
 // counters[fbase + k].  Far entries get degree class dcf; with `cand`, pairs

@@ -26,6 +26,10 @@ struct stc_ctx {
     u32 slot_cap = 0;     // nodes with proxy charges that fit the proxy / coefficient storage
     u32 per_level = 0;    // capacity of each level's list of such nodes
     i32* big_list = nullptr;
+    // upward pass: each such node's particles cut into items of UP_CHUNK
+    u32 items_cap = 0;
+    i32 *item_node = nullptr, *item_chunk = nullptr, *item_base = nullptr;
+    double* upart = nullptr;  // items_cap x n_p partial sums
     u32 cap = 0;
     hipStream_t stream = nullptr;
     int cus = 256;
@@ -280,7 +284,8 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     launch_gather(s, c->keys_sorted, n, d_x, c->perm, c->leaf, c->sx, c->sy, c->sz);
     launch_node_ranges(s, c->leaf, n, c->L, c->NB, c->nbeg, c->nend);
     launch_node_counts(s, c->nbeg, c->nend, c->used_nodes, c->p.n_crit, c->NB, c->L, c->level_off, c->ncnt, c->slot,
-                       c->slot_cap, c->big_list, c->per_level, c->flags);
+                       c->slot_cap, c->big_list, c->per_level, c->item_node, c->item_chunk, c->item_base,
+                       c->items_cap, c->flags);
     return check_launch(c, "tree_build");
 }
 
@@ -292,9 +297,9 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
         // the highest class from the particles; the others (learned form) by
         // re-interpolating each node's own record of the highest class
         const int top = c->ndeg - 1;
-        launch_upward(s, c->NB, c->level_off, c->flags, c->big_list, c->per_level, c->nbeg, c->nend, c->L,
-                      c->p.n_crit, c->geo, c->sx, c->sy, c->sz, c->sq, ref_dev(c, top), c->NPT, c->cls.poff[top], 0, 0,
-                      c->slot, c->prox);
+        launch_upward(s, c->L, c->NB, c->flags, c->big_list, c->per_level, c->nbeg, c->nend, c->item_node,
+                      c->item_chunk, c->item_base, c->items_cap, c->geo, c->sx, c->sy, c->sz, c->sq, c->upart,
+                      ref_dev(c, top), c->NPT, c->cls.poff[top], c->slot, c->prox);
         if (top > 0)
             launch_downsample(s, c->L, c->NB, c->flags, c->big_list, c->per_level, c->geo, c->slot, c->ref_points,
                               c->ref_T, c->cls, c->NPT, c->prox);
@@ -557,6 +562,8 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     c->slot_cap = (u32)std::min<i64>((i64)(c->L + 1) * c->per_level, 0x7fffffffLL);
     i64 cap = p->list_capacity > 0 ? p->list_capacity : std::max<i64>(65536, 16 * n_max_total);
     c->cap = (u32)std::min<i64>(cap, 0x7fffffffLL);
+    // items: one per big node plus one per UP_CHUNK particles on each level
+    c->items_cap = (u32)std::min<i64>((i64)c->slot_cap + (i64)(c->L + 1) * (nm / UP_CHUNK + 1), 0x7fffffffLL);
     try {
         build_tree_geometry(c->L, c->geo_host);
         for (int k = 0; k < c->ndeg; ++k)
@@ -592,7 +599,9 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
               dalloc(c, &c->flags, F_COUNT) && dalloc(c, &c->evals, 8) &&
               dalloc(c, &c->hist, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->hist_totals, 512) &&
               dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
-              dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm);
+              dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm) &&
+              dalloc(c, &c->item_node, c->items_cap) && dalloc(c, &c->item_chunk, c->items_cap) &&
+              dalloc(c, &c->item_base, ns) && dalloc(c, &c->upart, (size_t)c->items_cap * c->cls.np[c->ndeg - 1]);
     if (ok && learned)
         ok = dalloc(c, &c->ref_T, (size_t)c->cls.poff[3] * c->cls.np[3]) && dalloc(c, &c->cand, c->cap) && dalloc(c, &c->feat, (size_t)c->cap * 16) &&
              dalloc(c, &c->mlp_out, (size_t)c->cap * 4) && dalloc(c, &c->qabs, c->n_nodes) &&

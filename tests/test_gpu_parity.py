@@ -177,6 +177,36 @@ def test_proxy_charges(stc_lib, name):
     ctx.close()
 
 
+def test_proxy_charges_multi_item(stc_lib):
+    """Nodes with more particles than one upward-pass item holds (2048): their
+    items' sums are added by whichever item finishes last.  A second upward
+    pass with doubled vorticity must give exactly doubled charges (the
+    completion counters reset themselves)."""
+    n = 60000
+    x = S.random_sphere_points(n, 8)
+    z = S.gaussian_vortex(x, seed=8)
+    a = S.uniform_areas(n)
+    ot = otree.TreeCode(x, z, a, theta=0.9, degree=5, n_crit=32, max_level=4)
+    ctx = stc_lib.Context(n, theta=0.9, degree=5, n_crit=32, max_level=4)
+    say("proxy charges, multi-item nodes N=60000")
+    ctx.tree_build(dev(x))
+    ctx.upward(dev(z), dev(a))
+    multi = np.nonzero(ot.ptree.count > 2048)[0]
+    assert len(multi) >= 10
+    big = np.nonzero(ot.ptree.count > ot.n_crit)[0]
+    nodes = list(multi) + list(np.random.default_rng(1).choice(big, 10, replace=False))
+    first = {}
+    for node in nodes:
+        w = ctx.proxy_charges(int(node))
+        ref = ot.proxy_charges(int(node))
+        assert np.abs(w - ref).max() <= 1e-10 * np.abs(ref).max(), node
+        first[int(node)] = w
+    ctx.upward(dev(2.0 * z), dev(a))
+    for node in nodes:
+        np.testing.assert_array_equal(ctx.proxy_charges(int(node)), 2.0 * first[int(node)])
+    ctx.close()
+
+
 # ---- velocities -------------------------------------------------------------------------
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -263,6 +293,23 @@ def test_capacity_overflow_is_reported(stc_lib):
     with pytest.raises(stc_lib.StcError) as e:
         ctx.sync()
     assert e.value.status == 2
+    ctx.close()
+
+
+def test_nonfinite_position_is_reported(stc_lib):
+    x = S.random_sphere_points(2000, 4)
+    x[777] = np.nan
+    ctx = stc_lib.Context(2000, theta=0.7, degree=4, n_crit=16)
+    say("non-finite position")
+    ctx.velocity(dev(x), dev(np.ones(2000)), dev(np.ones(2000)))
+    with pytest.raises(stc_lib.StcError) as e:
+        ctx.sync()
+    assert e.value.status == 1 and "non-finite" in str(e.value)
+    # the same context then takes finite input again
+    x[777] = S.random_sphere_points(1, 5)[0]
+    u = ctx.velocity(dev(x), dev(np.ones(2000)), dev(np.ones(2000)))
+    ctx.sync()
+    assert np.isfinite(u.cpu().numpy()).all()
     ctx.close()
 
 
