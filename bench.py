@@ -139,20 +139,8 @@ def bench_ensemble(args):
     ctx.velocity_batched(x, z, a, off, out=out)
     shape = ctx.autotune(repeats=3)
     log(f"autotuned launch shape {shape}")
-    for _ in range(args.warmup):
-        ctx.velocity_batched(x, z, a, off, out=out)
-    ctx.set_timing(args.steps)
-    torch.cuda.synchronize()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        ctx.velocity_batched(x, z, a, off, out=out)
-    t1.record()
-    torch.cuda.synchronize()
-    ctx.sync()
-    ms = t0.elapsed_time(t1) / args.steps
-    phases, k = ctx.phase_times()
-    phase_ms = {p: round(v / max(k, 1), 4) for p, v in phases.items()}
+    ms, near_ms, phase_ms = _timed(ctx, lambda: ctx.velocity_batched(x, z, a, off, out=out), args.steps,
+                                   args.warmup)
     counts, evals = ctx.list_counts()
     log(f"batched: {ms:.3f} ms per ensemble evaluation; phases {phase_ms}")
     # accuracy: 64 seeded targets per member against that member's FP64 direct sum
@@ -173,6 +161,7 @@ def bench_ensemble(args):
         c.velocity(xv, zv, av, out=ov)
     torch.cuda.synchronize()
     seq_steps = max(1, args.steps // 4)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
     for _ in range(seq_steps):
         for c, (xv, zv, av, ov) in zip(singles, views):
@@ -196,7 +185,7 @@ def bench_ensemble(args):
     ctx.sync()
     log(f"rk4 step (4 evaluations, one graph): {ms_rk:.3f} ms")
     ctx.close()
-    roof = near_roofline(evals["PP"] + evals["PC"], phase_ms["near"], "fp32")
+    roof = near_roofline(evals["PP"] + evals["PC"], near_ms, "fp32")
     m0 = ens["members"][0]
     cb = None
     if not args.no_cpu:
@@ -227,11 +216,24 @@ LEARNED = dict(theta=0.7, theta_max=0.9, degree=10, n_crit=64, tol_rel=3e-8, tra
                batch=4096, lr=2e-3)
 
 
+def _phase_breakdown(ctx, fn, reps=3):
+    """Every phase of `reps` extra calls, with an event at each phase boundary
+    (outside the timed region: each event adds a gap between kernels)."""
+    ctx.set_timing(reps)
+    for _ in range(reps):
+        fn()
+    ctx.sync()
+    ph, k = ctx.phase_times()
+    return {p: round(v / max(k, 1), 4) for p, v in ph.items()}
+
+
 def _timed(ctx, fn, steps, warmup):
+    """(ms per call over the timed region, k_near ms per launch measured with
+    events around that kernel only inside the timed region, phase breakdown)."""
     import torch
     for _ in range(warmup):
         fn()
-    ctx.set_timing(steps)
+    ctx.set_timing(steps, phases=["near"])
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
@@ -241,7 +243,8 @@ def _timed(ctx, fn, steps, warmup):
     torch.cuda.synchronize()
     ctx.sync()
     ph, k = ctx.phase_times()
-    return t0.elapsed_time(t1) / steps, {p: round(v / max(k, 1), 4) for p, v in ph.items()}
+    near_ms = ph["near"] / max(k, 1)
+    return t0.elapsed_time(t1) / steps, near_ms, _phase_breakdown(ctx, fn)
 
 
 def bench_learned(args):
@@ -281,11 +284,11 @@ def bench_learned(args):
         ctx = stc.Context(n, denominator="dist2", n_crit=P["n_crit"], **kw)
         if model is not None:
             ctx.set_model(model)
-        ms, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, args.warmup)
+        ms, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
         if model is not None and kw.get("precision") == "fp32":
             pairs, _, _ = ctx.copy_candidates()
-            rows["_near"] = (ev["PP"] + ev["PC"], ph["near"], len(pairs))
+            rows["_near"] = (ev["PP"] + ev["PC"], near_ms_t, len(pairs))
         u = out.cpu().numpy()
         rows[name] = dict(ms=round(ms, 4), rel_l2_err_vs_fp64_direct=float(f"{metrics.rel_l2_velocity(u[sub], ud, a[sub]):.3e}"),
                           kernel_evals=int(sum(ev.values())), phase_ms=ph)
@@ -358,7 +361,7 @@ def bench_rk4(args):
         ctx = stc.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision=prec, denominator="dist2")
         u = ctx.velocity(xd, zd, ad)
         err = metrics.rel_l2_velocity(u.cpu().numpy()[sub], ud, a[sub])
-        ms_eval, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
+        ms_eval, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
         xs, zs = xd.clone(), zd.clone()
         ctx.rk4(xs, zs, ad, dt, Om, 1)   # captures the step graph
@@ -372,7 +375,7 @@ def bench_rk4(args):
         ms_step = t0.elapsed_time(t1) / args.steps
         runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4),
                           rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), phase_ms=ph,
-                          near=(ev["PP"] + ev["PC"], ph["near"]))
+                          near=(ev["PP"] + ev["PC"], near_ms_t))
         log(f"{prec}: {ms_step:.3f} ms per RK4 step (graph), {ms_eval:.3f} ms per evaluation, E = {err:.3e}")
         ctx.close()
     r = runs["fp32"]
@@ -450,20 +453,8 @@ def main():
     ctx.sync()
     log("warmup done")
 
-    ctx.set_timing(args.steps)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        ctx.velocity(xd, zd, ad, out=out)
-    t1.record()
-    torch.cuda.synchronize()
-    ctx.sync()
-    ms = t0.elapsed_time(t1) / args.steps
-    phases, k = ctx.phase_times()
-    phase_ms = {p: v / max(k, 1) for p, v in phases.items()}
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step; phases {json.dumps({p: round(v, 4) for p, v in phase_ms.items()})}")
+    ms, near_ms, phase_ms = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, 0)
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step; k_near {near_ms:.4f} ms; phases {json.dumps(phase_ms)}")
 
     counts, evals = ctx.list_counts()
     # accuracy: FP64 direct sum on the GPU (parity-tested against the oracle) at the 4096 targets
@@ -485,12 +476,12 @@ def main():
 
     flops_per = FP32_FLOPS if args.precision == "fp32" else FP64_FLOPS
     near_flops = (evals["PP"] + evals["PC"]) * flops_per
-    near_s = phase_ms["near"] / 1e3
+    near_s = near_ms / 1e3
     achieved = near_flops / near_s / 1e12
     config_tag = f"gv_l8 L{args.level} theta={args.theta} d={args.degree} n_crit={args.n_crit} {args.precision}"
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
                 frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=recorded_traffic(config_tag),
-                kernel="k_near (PP + PC)", kernel_ms=round(phase_ms["near"], 4),
+                kernel="k_near (PP + PC)", kernel_ms=round(near_ms, 4),
                 kernel_evals_per_launch=int(evals["PP"] + evals["PC"]))
 
     result = dict(

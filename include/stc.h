@@ -397,6 +397,12 @@ stc_status stc_reference_tables(int32_t degree, double* h_points, double* h_vinv
  * their number; recording restarts afterwards.  Evaluations beyond k are not
  * recorded. */
 stc_status stc_set_timing(stc_ctx* ctx, int32_t max_evals);
+
+/* As stc_set_timing, but only the phases whose bits are set in phase_mask
+ * (bit p = phase p above) are bracketed by events; the others report 0 ms.
+ * Each recorded event adds a few microseconds between kernels, so a
+ * benchmark that needs one phase's time times only that one. */
+stc_status stc_set_timing_phases(stc_ctx* ctx, int32_t max_evals, uint32_t phase_mask);
 stc_status stc_phase_times(stc_ctx* ctx, double ms[6], int64_t* n_evals);
 
 /* Message of the last error on this context ("" if none). */

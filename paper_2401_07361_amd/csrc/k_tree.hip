@@ -714,14 +714,17 @@ __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbe
     }
 }
 
-// Segments of a sorted list: entries with the same key >> shift (the target,
+// Segments of sorted lists: entries with the same key >> shift (the target,
 // or the target and degree class) occupy [seg_beg[.], seg_end[.]).  Arrays
-// must be zeroed before.
-__global__ __launch_bounds__(256) void k_segments(const u64* __restrict__ list, const u32* __restrict__ d_n,
-                                                   u32 cap, int shift, i32* __restrict__ seg_beg,
-                                                   i32* __restrict__ seg_end) {
-    u32 n = *d_n;
+// must be zeroed before.  grid.y = list.
+__global__ __launch_bounds__(256) void k_segments(SegLists sg, u32 cap) {
+    const int y = blockIdx.y;
+    const u64* __restrict__ list = sg.list[y];
+    u32 n = *sg.d_n[y];
     if (n > cap) n = cap;
+    const int shift = sg.shift[y];
+    i32* __restrict__ seg_beg = sg.beg[y];
+    i32* __restrict__ seg_end = sg.end[y];
     const u64 stride = (u64)gridDim.x * blockDim.x;
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const u64 t = list[i] >> shift;
@@ -733,6 +736,15 @@ __global__ __launch_bounds__(256) void k_segments(const u64* __restrict__ list, 
 __global__ __launch_bounds__(256) void k_fill_u32(u32* __restrict__ p, i64 n, u32 v) {
     const u64 stride = (u64)gridDim.x * blockDim.x;
     for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < (u64)n; i += stride) p[i] = v;
+}
+
+// up to kFillMax arrays zeroed in one launch (grid.y = array)
+__global__ __launch_bounds__(256) void k_fill_multi(FillSet f) {
+    const int y = blockIdx.y;
+    u32* __restrict__ p = f.p[y];
+    const u64 n = (u64)f.n[y];
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_fill_f64(double* __restrict__ p, i64 n, double v) {
@@ -840,6 +852,15 @@ void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, s, p, n, v);
 }
 
+void launch_fill_zero(hipStream_t s, const FillSet& f) {
+    if (f.k <= 0) return;
+    i64 mx = 0;
+    for (int y = 0; y < f.k; ++y) mx = f.n[y] > mx ? f.n[y] : mx;
+    if (mx <= 0) return;
+    const i64 b = blocks_for(mx, 256);
+    hipLaunchKernelGGL(k_fill_multi, dim3((unsigned)(b < 2048 ? b : 2048), (unsigned)f.k), dim3(256), 0, s, f);
+}
+
 void launch_fill_f64(hipStream_t s, double* p, i64 n, double v) {
     if (n <= 0) return;
     const i64 b = blocks_for(n, 256);
@@ -855,8 +876,8 @@ void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_n
                        item_chunk, item_base, items_cap, flags);
 }
 
-void launch_traverse_init(hipStream_t s, const TravArgs& t) {
-    launch_fill_u32(s, t.counters, C_COUNT, 0u);
+void launch_traverse_init(hipStream_t s, const TravArgs& t, bool zero_counters) {
+    if (zero_counters) launch_fill_u32(s, t.counters, C_COUNT, 0u);
     hipLaunchKernelGGL(k_trav_init, dim3(blocks_for((i64)t.members * 400, 256)), dim3(256), 0, s, t.members, t.NB,
                        t.ncnt, t.front0, t.cap, t.counters);
 }
@@ -878,9 +899,8 @@ void launch_traverse_levels(hipStream_t s, const TravArgs& t, int fbase, bool ca
     }
 }
 
-void launch_segments(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int shift, i32* seg_beg,
-                     i32* seg_end) {
-    hipLaunchKernelGGL(k_segments, dim3(1024), dim3(256), 0, s, list, d_n, cap, shift, seg_beg, seg_end);
+void launch_segments(hipStream_t s, const SegLists& sg, u32 cap) {
+    hipLaunchKernelGGL(k_segments, dim3(1024, (unsigned)sg.k), dim3(256), 0, s, sg, cap);
 }
 
 void launch_count_evals(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, int DB, ClassTab cls,

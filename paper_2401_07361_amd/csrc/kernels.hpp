@@ -54,10 +54,32 @@ struct TravArgs {
     u64 *tlist, *nlist;
     u32* counters;
 };
-void launch_traverse_init(hipStream_t s, const TravArgs& t);
+void launch_traverse_init(hipStream_t s, const TravArgs& t, bool zero_counters = true);
 void launch_traverse_levels(hipStream_t s, const TravArgs& t, int fbase, bool cand, u64* cand_buf);
-void launch_segments(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int shift, i32* seg_beg, i32* seg_end);
+// segments of up to two sorted lists in one launch
+struct SegLists {
+    const u64* list[2];
+    const u32* d_n[2];
+    int shift[2];
+    i32* beg[2];
+    i32* end[2];
+    int k;
+};
+void launch_segments(hipStream_t s, const SegLists& sg, u32 cap);
 void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v);
+// zero up to kFillMax u32 arrays in one launch
+constexpr int kFillMax = 6;
+struct FillSet {
+    u32* p[kFillMax];
+    i64 n[kFillMax];
+    int k;
+    void add(void* ptr, i64 count) {
+        p[k] = static_cast<u32*>(ptr);
+        n[k] = count;
+        ++k;
+    }
+};
+void launch_fill_zero(hipStream_t s, const FillSet& f);
 void launch_fill_f64(hipStream_t s, double* p, i64 n, double v);
 void launch_count_evals(hipStream_t s, const u64* list, const u32* d_n, u32 cap, int W, int DB, ClassTab cls,
                         const i32* nbeg, const i32* nend, int target_is_proxy, unsigned long long* out);

@@ -89,6 +89,7 @@ struct stc_ctx {
     // phase timing: 7 events per recorded evaluation
     std::vector<hipEvent_t> tev;
     int t_max = 0, t_used = 0, t_phase = -1;
+    u32 t_mask = 0x3f;  // phases bracketed by events
     // state
     i64 n = -1;
     const double* x = nullptr;
@@ -106,10 +107,14 @@ const char* kStatusText[] = {"ok", "invalid argument", "interaction list capacit
 
 // Records the event that opens `phase` (and closes the previous one) of the
 // evaluation being recorded.  Phase 6 closes the evaluation.
-void mark(stc_ctx* c, int phase) {
+// boundary b (0..6) starts phase b and ends phase b - 1; an event is
+// recorded only where a timed phase starts or ends (each event on the stream
+// costs a few microseconds between kernels)
+void mark(stc_ctx* c, int b) {
     if (c->t_max == 0 || c->t_used >= c->t_max) return;
-    (void)hipEventRecord(c->tev[(size_t)c->t_used * 7 + phase], c->stream);
-    if (phase == 6) ++c->t_used;
+    const bool need = ((c->t_mask >> b) & 1u) || (b > 0 && ((c->t_mask >> (b - 1)) & 1u));
+    if (need) (void)hipEventRecord(c->tev[(size_t)c->t_used * 7 + b], c->stream);
+    if (b == 6) ++c->t_used;
 }
 
 stc_status fail(stc_ctx* c, stc_status st, const std::string& msg) {
@@ -266,9 +271,13 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     c->have_upward = false;
     c->have_lists = false;
     mark(c, 0);
-    launch_fill_u32(s, c->flags, F_COUNT, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nbeg), c->used_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nend), c->used_nodes, 0u);
+    {
+        FillSet f{};
+        f.add(c->flags, F_COUNT);
+        f.add(c->nbeg, c->used_nodes);
+        f.add(c->nend, c->used_nodes);
+        launch_fill_zero(s, f);
+    }
     if (n == 0) {
         launch_fill_u32(s, reinterpret_cast<u32*>(c->ncnt), c->used_nodes, 0u);
         return check_launch(c, "tree_build");
@@ -364,9 +373,19 @@ TravArgs trav_args(stc_ctx* c, double theta, int dcf) {
 stc_status do_traverse(stc_ctx* c) {
     hipStream_t s = c->stream;
     mark(c, 2);
+    {
+        // traversal counters and the segment tables of the sorted lists
+        FillSet f{};
+        f.add(c->counters, C_COUNT);
+        f.add(c->tseg_beg, c->used_nodes);
+        f.add(c->tseg_end, c->used_nodes);
+        f.add(c->nseg_beg, c->used_nodes << c->DB);
+        f.add(c->nseg_end, c->used_nodes << c->DB);
+        launch_fill_zero(s, f);
+    }
     if (!c->learned) {
         const TravArgs t = trav_args(c, c->p.theta, 0);
-        launch_traverse_init(s, t);
+        launch_traverse_init(s, t, false);
         launch_traverse_levels(s, t, C_FRONT, false, nullptr);
     } else {
         // gated traversal (learned form): pairs separated at theta_max with a
@@ -374,7 +393,7 @@ stc_status do_traverse(stc_ctx* c) {
         // each at a degree class or rejects it; rejected pairs are traversed
         // by the plain method (theta, the fallback degree) from there on
         const TravArgs tc = trav_args(c, c->p.theta_max, 0);
-        launch_traverse_init(s, tc);
+        launch_traverse_init(s, tc, false);
         launch_traverse_levels(s, tc, C_FRONT, true, c->cand);
         LearnedArgs la = learned_args(c);
         c->cand_view = c->cand;
@@ -397,13 +416,13 @@ stc_status do_traverse(stc_ctx* c) {
         c->tlist = res[0];
         c->nlist = res[1];
     }
-    const i64 nv = c->used_nodes << c->DB;  // (target, class) segments of the target-proxy list
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_beg), c->used_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->tseg_end), c->used_nodes, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_beg), nv, 0u);
-    launch_fill_u32(s, reinterpret_cast<u32*>(c->nseg_end), nv, 0u);
-    launch_segments(s, c->tlist, c->counters + C_TLIST, c->cap, c->W + 1 + c->DB, c->tseg_beg, c->tseg_end);
-    launch_segments(s, c->nlist, c->counters + C_NLIST, c->cap, c->W + 1, c->nseg_beg, c->nseg_end);
+    SegLists sg{{c->tlist, c->nlist},
+                {c->counters + C_TLIST, c->counters + C_NLIST},
+                {c->W + 1 + c->DB, c->W + 1},
+                {c->tseg_beg, c->nseg_beg},
+                {c->tseg_end, c->nseg_end},
+                2};
+    launch_segments(s, sg, c->cap);
     c->have_lists = true;
     return check_launch(c, "traverse");
 }
@@ -1355,8 +1374,11 @@ stc_status stc_reference_tables(int32_t degree, double* h_points, double* h_vinv
     return STC_OK;
 }
 
-stc_status stc_set_timing(stc_ctx* c, int32_t max_evals) {
-    if (!c || max_evals < 0 || max_evals > 100000) return STC_ERR_INVALID_ARG;
+stc_status stc_set_timing(stc_ctx* c, int32_t max_evals) { return stc_set_timing_phases(c, max_evals, 0x3f); }
+
+stc_status stc_set_timing_phases(stc_ctx* c, int32_t max_evals, uint32_t phase_mask) {
+    if (!c || max_evals < 0 || max_evals > 100000 || (phase_mask & ~0x3fu)) return STC_ERR_INVALID_ARG;
+    c->t_mask = phase_mask;
     (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     c->tev.clear();
@@ -1379,6 +1401,7 @@ stc_status stc_phase_times(stc_ctx* c, double ms[6], int64_t* n_evals) {
     if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(c, STC_ERR_DEVICE, "synchronisation failed");
     for (int k = 0; k < c->t_used; ++k) {
         for (int p = 0; p < 6; ++p) {
+            if (!((c->t_mask >> p) & 1u)) continue;
             float t = 0.f;
             if (hipEventElapsedTime(&t, c->tev[(size_t)k * 7 + p], c->tev[(size_t)k * 7 + p + 1]) != hipSuccess)
                 return fail(c, STC_ERR_DEVICE, "event timing failed (was every phase of the evaluation run?)");

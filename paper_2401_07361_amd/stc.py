@@ -98,6 +98,7 @@ def _load():
         "stc_geometry_tables": (I32, [I32, PD, PD, PD]),
         "stc_reference_tables": (I32, [I32, PD, PD]),
         "stc_set_timing": (I32, [P, I32]),
+        "stc_set_timing_phases": (I32, [P, I32, ctypes.c_uint32]),
         "stc_phase_times": (I32, [P, PD, PI64]),
         "stc_last_error": (ctypes.c_char_p, [P]),
     }
@@ -494,8 +495,16 @@ class Context:
     # timing -------------------------------------------------------------------------
     PHASES = ("build", "upward", "traverse", "near", "far_targets", "l2p")
 
-    def set_timing(self, max_evals):
-        _check(_lib.stc_set_timing(self._ctx, int(max_evals)), self._ctx)
+    def set_timing(self, max_evals, phases=None):
+        """Time the next max_evals evaluations: every phase, or only the
+        named ones (each timed phase adds events between kernels)."""
+        if phases is None:
+            _check(_lib.stc_set_timing(self._ctx, int(max_evals)), self._ctx)
+            return
+        mask = 0
+        for p in phases:
+            mask |= 1 << self.PHASES.index(p)
+        _check(_lib.stc_set_timing_phases(self._ctx, int(max_evals), ctypes.c_uint32(mask)), self._ctx)
 
     def phase_times(self):
         """(dict phase -> summed ms, number of evaluations recorded)."""

@@ -313,6 +313,24 @@ def test_nonfinite_position_is_reported(stc_lib):
     ctx.close()
 
 
+def test_phase_timing_mask(stc_lib):
+    ctx, x, z, a = gpu_ctx(stc_lib, "random_7001", precision="fp32", den="dist2")
+    say("phase timing mask")
+    u = ctx.velocity(dev(x), dev(z), dev(a))
+    ctx.set_timing(3, phases=["near"])
+    for _ in range(3):
+        ctx.velocity(dev(x), dev(z), dev(a), out=u)
+    ph, k = ctx.phase_times()
+    assert k == 3 and ph["near"] > 0.0
+    assert all(v == 0.0 for p, v in ph.items() if p != "near")
+    ctx.set_timing(2)
+    for _ in range(2):
+        ctx.velocity(dev(x), dev(z), dev(a), out=u)
+    ph, k = ctx.phase_times()
+    assert k == 2 and all(v > 0.0 for v in ph.values())
+    ctx.close()
+
+
 def test_repeatable_bitwise(stc_lib):
     ctx, x, z, a = gpu_ctx(stc_lib, "random_7001", precision="fp32", den="dist2")
     say("repeatability")
