@@ -42,6 +42,7 @@ enum Flag : int {
     F_SLOT_CTR = 2,   // next free storage slot (counter)
     F_BIN_EXACT = 3,  // points queued for exact point location
     F_ITEMS = 4,      // upward-pass items (pieces of big nodes' particle ranges)
+    F_SORT_SPIN = 5,  // a sort's look-back exceeded its spin bound
     F_LEVEL = 8,      // F_LEVEL + l: nodes of level l with more than N_T particles (list length)
     F_COUNT = 24
 };
@@ -303,10 +304,18 @@ __device__ __forceinline__ void block_matvec(const double* __restrict__ Mt, int 
 }
 
 // host-side launch helpers (implemented in the .hip files)
+constexpr int kSortMaxPasses = 8;
+constexpr int kSortCopies = 8;  // each digit histogram kept in copies (atomics spread over addresses)
+// digit histograms (2 arrays x kSortMaxPasses x kSortCopies x 256) and tile
+// counters (2 x kSortMaxPasses); zero when a sort starts
+constexpr int kSortHistWords = 2 * kSortMaxPasses * kSortCopies * 256;
+constexpr int kSortZeroWords = kSortHistWords + 2 * kSortMaxPasses;
 struct SortScratch {
-    u32* hist;       // 2 * 256 * max_blocks
-    u32* totals;     // 2 * 256
-    int max_blocks;
+    u32* zero;    // kSortZeroWords
+    u64* status;  // 2 x max_tiles x 256 look-back status words
+    u32* epoch;   // 2 counters, advanced by every sort
+    u32* err;     // set if a look-back exceeded its spin bound
+    int max_tiles;
 };
 
 // up to two independent key arrays sorted in the same passes

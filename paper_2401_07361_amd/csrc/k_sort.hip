@@ -2,21 +2,41 @@
 // Used to order particles by leaf key (ties by input index, which is packed
 // in the low bits) and interaction lists by (target, type, source).
 //
-// Per pass: (1) per-tile digit histograms, (2) one exclusive scan over
-// (digit, tile), (3) a stable scatter: inside a tile, keys are ranked in
-// index order with wave ballots (lanes holding the same digit) and per-wave
-// digit counts in LDS.  The key count may live in device memory (n_bound is
-// then only the capacity that sizes the grid), so no host synchronisation is
-// needed between the traversal and the sort.
+// One-sweep form: k_os_hist counts the digits of every pass in one read of
+// the keys; then one kernel per pass.  A pass kernel takes its tile number
+// from an atomic counter (tiles are numbered in the order they start), ranks
+// the tile's keys stably (each wave ranks its contiguous quarter with ballots
+// and wave-private running counts in LDS, then one prefix over the four
+// waves), publishes its digit counts, and looks back over the earlier tiles'
+// published counts to find where its keys go (decoupled look-back: a tile
+// adds the counts of predecessors that only published their own counts and
+// stops at the first that published its inclusive prefix).  A tile waits
+// only on tiles that started before it, so every wait ends; the spin is also
+// bounded, and a tile that exceeds the bound sets an error flag and goes on.
+//
+// Status words: epoch (30 bits) | state (2 bits: 1 own count, 2 inclusive
+// prefix) | count (32 bits).  The epoch of a pass comes from a device counter
+// that k_os_hist advances, so statuses left by an earlier sort (or an earlier
+// replay of a captured graph) never match.  The digit histograms and tile
+// counters must be zero when a sort starts (the callers clear them together
+// with their other per-evaluation counters).  The key count may live in
+// device memory (n_bound then only sizes the grid), so no host
+// synchronisation is needed between the traversal and the sort.
 #include "common.hpp"
 
 namespace stc {
 
 namespace {
 
-constexpr int RS_THREADS = 256;
-constexpr int RS_IPT = 16;
-constexpr int RS_TILE = RS_THREADS * RS_IPT;
+constexpr int OS_THREADS = 256;
+constexpr int OS_IPT = 16;                     // keys per thread
+constexpr int OS_TILE = OS_THREADS * OS_IPT;  // 4096
+constexpr int OS_WAVE_KEYS = 64 * OS_IPT;     // a wave's contiguous quarter
+// a look-back poll takes about a microsecond: this bound (a few ms per tile)
+// is far above any real wait and keeps even a broken chain of tiles short
+constexpr u32 OS_SPIN_LIMIT = 1u << 12;
+constexpr u64 OS_AGG = 1ull << 32, OS_INC = 2ull << 32;
+constexpr int OS_WIN = 8;  // look-back window
 
 __device__ __forceinline__ u32 load_n(const u32* d_n, u32 n_bound) {
     if (d_n == nullptr) return n_bound;
@@ -24,159 +44,221 @@ __device__ __forceinline__ u32 load_n(const u32* d_n, u32 n_bound) {
     return n < n_bound ? n : n_bound;
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(SortBatch sb, u32 n_bound, int shift, u32* __restrict__ hist_all,
-                                                         int nblocks) {
+__device__ __forceinline__ u32 pass_epoch(u32 base, int p) { return ((base + (u32)p) % 0x3fffffffu) + 1u; }
+
+// Digit histogram of the first pass, ghist[y][0][d] (each pass kernel
+// counts the next pass's digits of its tile); block 0 advances the epoch
+// counter by the number of passes.
+__global__ __launch_bounds__(OS_THREADS) void k_os_hist(SortBatch sb, u32 n_bound, int bit_lo, int passes,
+                                                         u32* __restrict__ zero_region, u32* __restrict__ epoch) {
     __shared__ u32 h[256];
-    const int tid = threadIdx.x;
-    const int y = blockIdx.y;
+    const int tid = threadIdx.x, y = blockIdx.y;
     const u64* __restrict__ keys = sb.in[y];
-    const u32* d_n = sb.dn[y];
-    u32* __restrict__ hist = hist_all + (size_t)y * 256 * nblocks;
-    const u32 n = load_n(d_n, n_bound);
-    const u64 base = (u64)blockIdx.x * RS_TILE;
-    if (base >= n) return;  // tiles past the key count are never scanned
-    h[tid] = 0;
-    u32 dg[RS_IPT];
-#pragma unroll
-    for (int r = 0; r < RS_IPT; ++r) {
-        const u64 i = base + (u64)r * RS_THREADS + tid;
-        dg[r] = i < n ? ((u32)(keys[i] >> shift) & 255u) : 256u;
-    }
+    const u32 n = load_n(sb.dn[y], n_bound);
+    u32* __restrict__ ghist = zero_region + (size_t)y * kSortMaxPasses * kSortCopies * 256 +
+                              (blockIdx.x % kSortCopies) * 256;
+    if (blockIdx.x == 0 && tid == 0) epoch[y] += (u32)passes;
+    h[tid] = 0u;
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RS_IPT; ++r)
-        if (dg[r] < 256u) atomicAdd(&h[dg[r]], 1u);
+    const u64 stride = (u64)gridDim.x * OS_THREADS;
+    for (u64 i = (u64)blockIdx.x * OS_THREADS + tid; i < n; i += stride)
+        atomicAdd(&h[(u32)(keys[i] >> bit_lo) & 255u], 1u);
     __syncthreads();
-    hist[(size_t)tid * nblocks + blockIdx.x] = h[tid];
+    if (h[tid]) atomicAdd(&ghist[tid], h[tid]);
 }
 
-// Per-digit exclusive scan over the tiles in use: workgroup d scans
-// hist[d][0..used) in coalesced chunks of 256 and stores the digit total.
-// The scatter adds the exclusive prefix over digit totals.
-__global__ __launch_bounds__(256) void k_rs_scan(SortBatch sb, u32* __restrict__ hist_all, u32* __restrict__ totals_all,
-                                                 u32 n_bound, int nblocks) {
-    __shared__ u32 part[256];
-    const int tid = threadIdx.x;
-    const int d = blockIdx.x;
-    const int y = blockIdx.y;
-    const u32* d_n = sb.dn[y];
-    u32* __restrict__ hist = hist_all + (size_t)y * 256 * nblocks;
-    u32* __restrict__ totals = totals_all + 256 * y;
-    const u32 n = load_n(d_n, n_bound);
-    const u32 used = (n + RS_TILE - 1) / RS_TILE;
-    u32* h = hist + (size_t)d * nblocks;
-    u32 carry = 0;
-    for (u32 b0 = 0; b0 < used; b0 += 256) {
-        const u32 b = b0 + tid;
-        const u32 v = b < used ? h[b] : 0u;
-        part[tid] = v;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const u32 t = tid >= off ? part[tid - off] : 0u;
-            __syncthreads();
-            part[tid] += t;
-            __syncthreads();
-        }
-        if (b < used) h[b] = carry + part[tid] - v;
-        carry += part[255];
-        __syncthreads();
-    }
-    if (tid == 0) totals[d] = carry;
-}
-
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(SortBatch sb, u32 n_bound, int shift,
-                                                            const u32* __restrict__ hist_all,
-                                                            const u32* __restrict__ totals_all, int nblocks) {
-    const int y = blockIdx.y;
+__global__ __launch_bounds__(OS_THREADS) void k_os_pass(SortBatch sb, u32 n_bound, int shift, int p, int passes,
+                                                         u32* __restrict__ zero_region,
+                                                         u64* __restrict__ status_all, int max_tiles,
+                                                         const u32* __restrict__ epoch, u32* __restrict__ err) {
+    __shared__ u32 wrun[4][256];  // per wave: running digit counts, then their prefix over waves
+    __shared__ u32 dpre[256];     // global exclusive prefix over digits, then the tile's base per digit
+    __shared__ u32 hnext[256];    // the tile's digits of the next pass
+    __shared__ u32 tile_sh;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, y = blockIdx.y;
     const u64* __restrict__ in = sb.in[y];
     u64* __restrict__ out = sb.out[y];
-    const u32* d_n = sb.dn[y];
-    const u32* __restrict__ hist = hist_all + (size_t)y * 256 * nblocks;
-    const u32* __restrict__ totals = totals_all + 256 * y;
-    __shared__ u32 digit_base[256];
-    __shared__ u32 wcnt[4][256];
-    __shared__ u32 run[256];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = tid >> 6;
-    const u32 n = load_n(d_n, n_bound);
-    const u64 base = (u64)blockIdx.x * RS_TILE;
-    if (base >= n) return;  // uniform over the block
-    // exclusive prefix of the digit totals (Hillis-Steele in LDS)
-    const u32 tot = totals[tid];
-    run[tid] = tot;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const u32 t = tid >= off ? run[tid - off] : 0u;
+    const u32 n = load_n(sb.dn[y], n_bound);
+    const u32 used = (n + OS_TILE - 1) / OS_TILE;
+    u32* __restrict__ ghist = zero_region + ((size_t)y * kSortMaxPasses + p) * kSortCopies * 256;
+    u32* __restrict__ gnext = ghist + kSortCopies * 256 + (blockIdx.x % kSortCopies) * 256;  // next pass, one copy
+    u32* __restrict__ tctr = zero_region + kSortHistWords + y * kSortMaxPasses + p;
+    u64* __restrict__ status = status_all + (size_t)y * max_tiles * 256;
+    const u32 ep = pass_epoch(epoch[y] - (u32)passes, p);  // k_os_hist advanced the counter by `passes`
+    // the grid is sized by the capacity; exactly `used` workgroups (the
+    // lowest indices) take tile numbers, in the order in which they start
+    if (blockIdx.x >= used) return;
+    u32 v = 0;  // digit tid's global count: loads issued before the tile-counter atomic (latencies overlap)
+#pragma unroll
+    for (int c = 0; c < kSortCopies; ++c) v += ghist[c * 256 + tid];
+    u32 my_tile = 0;
+    if (tid == 0) my_tile = atomicAdd(tctr, 1u);
+    wrun[w][lane] = 0u;
+    wrun[w][lane + 64] = 0u;
+    wrun[w][lane + 128] = 0u;
+    wrun[w][lane + 192] = 0u;
+    hnext[tid] = 0u;
+    // exclusive prefix of the global digit counts
+    {
+        u32 incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const u32 t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) dpre[w] = incl;  // wave totals (dpre reused below)
         __syncthreads();
-        run[tid] += t;
+        u32 base = 0;
+        for (int k = 0; k < w; ++k) base += dpre[k];
         __syncthreads();
+        dpre[tid] = base + incl - v;
+        if (tid == 0) tile_sh = my_tile;
     }
-    digit_base[tid] = run[tid] - tot + hist[(size_t)tid * nblocks + blockIdx.x];
     __syncthreads();
-    run[tid] = 0;
+    const u32 tile = tile_sh;
+    // keys of this wave's quarter, all loads in flight at once
+    const u64 q0 = (u64)tile * OS_TILE + (u64)w * OS_WAVE_KEYS;
+    u64 keys[OS_IPT];
+#pragma unroll
+    for (int r = 0; r < OS_IPT; ++r) {
+        const u64 i = q0 + (u64)r * 64 + lane;
+        keys[r] = i < n ? in[i] : 0ull;
+    }
+    // stable ranks inside the wave (rounds in key order)
     const u64 lt = lanemask_lt();
-    u64 keys[RS_IPT];  // all loads of the tile in flight at once
+    u32 rank[OS_IPT];
 #pragma unroll
-    for (int r = 0; r < RS_IPT; ++r) {
-        const u64 i = base + (u64)r * RS_THREADS + tid;
-        keys[r] = i < n ? in[i] : 0;
-    }
-#pragma unroll
-    for (int r = 0; r < RS_IPT; ++r) {
-        const u64 i = base + (u64)r * RS_THREADS + tid;
-        const bool valid = i < n;
-        const u64 key = keys[r];
-        const u32 d = (u32)(key >> shift) & 255u;
-        for (int k = 0; k < 4; ++k) wcnt[k][tid] = 0;
-        __syncthreads();
+    for (int r = 0; r < OS_IPT; ++r) {
+        const bool valid = q0 + (u64)r * 64 + lane < n;
+        const u32 d = (u32)(keys[r] >> shift) & 255u;
         u64 m = __ballot(valid);
+#pragma unroll
         for (int b = 0; b < 8; ++b) {
             const bool bit = (d >> b) & 1u;
             const u64 bb = __ballot(bit);
             m &= bit ? bb : ~bb;
         }
-        const u32 rank = (u32)__popcll(m & lt);
-        if (valid && rank == 0) wcnt[w][d] = (u32)__popcll(m);
-        __syncthreads();
-        {
-            const u32 c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-            const u32 r0 = run[tid];
-            wcnt[0][tid] = r0;
-            wcnt[1][tid] = r0 + c0;
-            wcnt[2][tid] = r0 + c0 + c1;
-            wcnt[3][tid] = r0 + c0 + c1 + c2;
-            run[tid] = r0 + c0 + c1 + c2 + c3;
+        if (p + 1 < passes) {
+            const u32 d2 = (u32)(keys[r] >> (shift + 8)) & 255u;
+            const u32 d20 = (u32)__shfl(d2, 0, 64);
+            const u64 act = __ballot(valid);
+            if (__ballot(valid && d2 == d20) == act) {
+                if (lane == 0 && act) atomicAdd(&hnext[d20], (u32)__popcll(act));
+            } else if (valid) {
+                atomicAdd(&hnext[d2], 1u);
+            }
         }
-        __syncthreads();
-        if (valid) out[(u64)digit_base[d] + wcnt[w][d] + rank] = key;
-        __syncthreads();
+        const u32 before = valid ? wrun[w][d] : 0u;
+        const u32 rr = (u32)__popcll(m & lt);
+        // every lane has read its digit's count before any leader writes it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (valid && rr == 0) wrun[w][d] = before + (u32)__popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        rank[r] = before + rr;
+    }
+    __syncthreads();
+    if (p + 1 < passes && hnext[tid]) atomicAdd(&gnext[tid], hnext[tid]);
+    // per digit (thread = digit): prefix over the four waves, the tile's count
+    u32 cnt;
+    {
+        u32 acc = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32 t = wrun[k][tid];
+            wrun[k][tid] = acc;
+            acc += t;
+        }
+        cnt = acc;
+    }
+    // publish, look back, publish the inclusive prefix
+    u64* my = status + (size_t)tile * 256 + tid;
+    const u64 tag = (u64)ep << 34;
+    u32 excl = 0;
+    if (tile == 0) {
+        __hip_atomic_store(my, tag | OS_INC | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(my, tag | OS_AGG | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // predecessors read OS_WIN at a time (one memory round trip per
+        // window), taken in order: add own counts, stop at an inclusive
+        // prefix, re-read from the first tile that has not published yet
+        int j = (int)tile - 1;
+        u32 spins = 0;
+        bool done = false;
+        while (!done && j >= 0) {
+            u64 st[OS_WIN];
+#pragma unroll
+            for (int t = 0; t < OS_WIN; ++t)
+                st[t] = (j - t >= 0) ? __hip_atomic_load(status + (size_t)(j - t) * 256 + tid, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)
+                                     : 0ull;
+            int adv = 0;
+            bool stall = false;
+#pragma unroll
+            for (int t = 0; t < OS_WIN; ++t) {
+                if (done || stall || j - t < 0) continue;
+                const u32 sep = (u32)(st[t] >> 34), state = (u32)(st[t] >> 32) & 3u;
+                if (sep != ep || state == 0u) {
+                    stall = true;
+                    continue;
+                }
+                excl += (u32)st[t];
+                ++adv;
+                if (state == 2u) done = true;
+            }
+            j -= adv;
+            if (stall && !done) {
+                if (++spins > OS_SPIN_LIMIT) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __hip_atomic_store(my, tag | OS_INC | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    dpre[tid] += excl;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < OS_IPT; ++r) {
+        if (q0 + (u64)r * 64 + lane < n) {
+            const u32 d = (u32)(keys[r] >> shift) & 255u;
+            const u64 pos = (u64)dpre[d] + wrun[w][d] + rank[r];
+            if (pos < n_bound) out[pos] = keys[r];  // always true unless a look-back gave up
+        }
     }
 }
 
 }  // namespace
 
+int sort_passes(int bit_lo, int bit_hi) { return bit_hi > bit_lo ? (bit_hi - bit_lo + 7) / 8 : 0; }
+
 void radix_sort_batch(hipStream_t s, int nb, u64* const* keys, u64* const* tmp, const u32* const* d_n, u32 n_bound,
                       int bit_lo, int bit_hi, SortScratch scratch, u64** result) {
-    const int nblocks = (int)((n_bound + RS_TILE - 1) / RS_TILE);
+    const int tiles = (int)((n_bound + OS_TILE - 1) / OS_TILE);
+    const int passes = sort_passes(bit_lo, bit_hi);
+    for (int y = 0; y < nb; ++y) result[y] = keys[y];
+    if (n_bound == 0 || passes == 0 || passes > kSortMaxPasses || tiles > scratch.max_tiles || nb < 1 || nb > 2)
+        return;
     SortBatch sb{};
     u64* a[2] = {keys[0], nb > 1 ? keys[1] : nullptr};
     u64* b[2] = {tmp[0], nb > 1 ? tmp[1] : nullptr};
-    for (int y = 0; y < nb; ++y) sb.dn[y] = d_n[y];
-    if (n_bound == 0 || nblocks > scratch.max_blocks || nb < 1 || nb > 2) {
-        for (int y = 0; y < nb; ++y) result[y] = keys[y];
-        return;
+    for (int y = 0; y < nb; ++y) {
+        sb.dn[y] = d_n[y];
+        sb.in[y] = a[y];
     }
-    for (int sh = bit_lo; sh < bit_hi; sh += 8) {
+    const unsigned hb = (unsigned)(tiles < 256 ? tiles : 256);
+    hipLaunchKernelGGL(k_os_hist, dim3(hb, nb), dim3(OS_THREADS), 0, s, sb, n_bound, bit_lo, passes, scratch.zero,
+                       scratch.epoch);
+    for (int p = 0; p < passes; ++p) {
         for (int y = 0; y < nb; ++y) {
             sb.in[y] = a[y];
             sb.out[y] = b[y];
         }
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks, nb), dim3(RS_THREADS), 0, s, sb, n_bound, sh, scratch.hist, nblocks);
-        hipLaunchKernelGGL(k_rs_scan, dim3(256, nb), dim3(256), 0, s, sb, scratch.hist, scratch.totals, n_bound,
-                           nblocks);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks, nb), dim3(RS_THREADS), 0, s, sb, n_bound, sh, scratch.hist,
-                           scratch.totals, nblocks);
+        hipLaunchKernelGGL(k_os_pass, dim3(tiles, nb), dim3(OS_THREADS), 0, s, sb, n_bound, bit_lo + 8 * p, p,
+                           passes, scratch.zero, scratch.status, scratch.max_tiles, scratch.epoch, scratch.err);
         for (int y = 0; y < nb; ++y) {
             u64* t = a[y];
             a[y] = b[y];

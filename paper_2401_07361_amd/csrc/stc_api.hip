@@ -74,9 +74,11 @@ struct stc_ctx {
     u32* counters = nullptr;
     u32* flags = nullptr;
     unsigned long long* evals = nullptr;
-    u32* hist = nullptr;
-    u32* hist_totals = nullptr;
-    int hist_blocks = 0;
+    // radix sort scratch (see k_sort.hip)
+    u32* sort_zero = nullptr;
+    u64* sort_status = nullptr;
+    u32* sort_epoch = nullptr;
+    int hist_blocks = 0;  // tiles of 4096 keys in the longest array sorted
     // RK4 buffers
     double *rk_x = nullptr, *rk_z = nullptr, *rk_u = nullptr, *rk_xacc = nullptr, *rk_zacc = nullptr;
     // one captured RK4 step, replayed per step (key: the arguments it was captured for)
@@ -139,6 +141,10 @@ bool dalloc(stc_ctx* c, T** p, size_t count) {
 }
 
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+SortScratch sort_scratch(const stc_ctx* c) {
+    return SortScratch{c->sort_zero, c->sort_status, c->sort_epoch, c->flags + F_SORT_SPIN, c->hist_blocks};
+}
 
 int bits_for(i64 v) {
     int b = 0;
@@ -276,6 +282,7 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
         f.add(c->flags, F_COUNT);
         f.add(c->nbeg, c->used_nodes);
         f.add(c->nend, c->used_nodes);
+        f.add(c->sort_zero, kSortZeroWords);
         launch_fill_zero(s, f);
     }
     if (n == 0) {
@@ -289,7 +296,7 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     // queue of points located exactly
     launch_bin(s, d_x, n, c->geo, c->L, mo, c->keys_a, reinterpret_cast<u32*>(c->keys_b), c->flags);
     radix_sort(s, c->keys_a, c->keys_b, nullptr, (u32)n, 32, 32 + c->LB + bits_for(members),
-               SortScratch{c->hist, c->hist_totals, c->hist_blocks}, &c->keys_sorted);
+               sort_scratch(c), &c->keys_sorted);
     launch_gather(s, c->keys_sorted, n, d_x, c->perm, c->leaf, c->sx, c->sy, c->sz);
     launch_node_ranges(s, c->leaf, n, c->L, c->NB, c->nbeg, c->nend);
     launch_node_counts(s, c->nbeg, c->nend, c->used_nodes, c->p.n_crit, c->NB, c->L, c->level_off, c->ncnt, c->slot,
@@ -381,6 +388,7 @@ stc_status do_traverse(stc_ctx* c) {
         f.add(c->tseg_end, c->used_nodes);
         f.add(c->nseg_beg, c->used_nodes << c->DB);
         f.add(c->nseg_end, c->used_nodes << c->DB);
+        f.add(c->sort_zero, kSortZeroWords);
         launch_fill_zero(s, f);
     }
     if (!c->learned) {
@@ -406,7 +414,7 @@ stc_status do_traverse(stc_ctx* c) {
         launch_traverse_levels(s, tf, C_FRONT2, false, nullptr);
     }
     const int bits = 2 * c->W + 1 + c->DB;
-    SortScratch sc{c->hist, c->hist_totals, c->hist_blocks};
+    const SortScratch sc = sort_scratch(c);
     {
         u64* keys[2] = {c->tlist_a, c->nlist_a};
         u64* tmp[2] = {c->tlist_b, c->nlist_b};
@@ -616,7 +624,8 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
               dalloc(c, &c->tseg_end, c->n_nodes) && dalloc(c, &c->nseg_beg, nseg) &&
               dalloc(c, &c->nseg_end, nseg) && dalloc(c, &c->counters, C_COUNT) &&
               dalloc(c, &c->flags, F_COUNT) && dalloc(c, &c->evals, 8) &&
-              dalloc(c, &c->hist, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->hist_totals, 512) &&
+              dalloc(c, &c->sort_zero, kSortZeroWords) &&
+              dalloc(c, &c->sort_status, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->sort_epoch, 2) &&
               dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
               dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm) &&
               dalloc(c, &c->item_node, c->items_cap) && dalloc(c, &c->item_chunk, c->items_cap) &&
@@ -659,6 +668,10 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
               up(c->ref_vinvT, vinvT_h.data(), vinvT_h.size() * sizeof(double)) &&
               up(c->ref_coef, coef_h.data(), coef_h.size() * sizeof(double)) &&
               up(c->ref_expo, expo_h.data(), expo_h.size() * sizeof(int));
+    // sort look-back statuses and epochs start cleared (a status matches only
+    // the epoch of the pass that wrote it; epochs start at 1)
+    cp = cp && hipMemsetAsync(c->sort_status, 0, (size_t)2 * 256 * c->hist_blocks * sizeof(u64), s) == hipSuccess &&
+         hipMemsetAsync(c->sort_epoch, 0, 2 * sizeof(u32), s) == hipSuccess;
     // learned form: T[(poff_c + m) * 66 + n] = sum_k (V_ref,d^{-1})_km B_k(b_10,n),
     // degree-10 point charges -> degree-d (classes 0..2), in long double
     std::vector<double> T_h;
@@ -1090,13 +1103,14 @@ stc_status stc_learned_samples(stc_ctx* c, double abs_tol, int64_t cap, uint16_t
     hipStream_t s = c->stream;
     // candidates of the wider criterion, their features and measured errors
     const TravArgs tc = trav_args(c, c->p.theta_max, 0);
+    launch_fill_u32(s, c->sort_zero, kSortZeroWords, 0u);
     launch_traverse_init(s, tc);
     launch_traverse_levels(s, tc, C_FRONT, true, c->cand);
     // samples in (t, s) order, so that training data do not depend on the
     // order in which the traversal appended them (the frontier is free now)
     u64* sorted = nullptr;
     radix_sort(s, c->cand, c->front1, c->counters + C_CAND, c->cap, 0, 32 + c->W,
-               SortScratch{c->hist, c->hist_totals, c->hist_blocks}, &sorted);
+               sort_scratch(c), &sorted);
     LearnedArgs la = learned_args(c);
     la.cand = sorted;
     c->cand_view = sorted;
@@ -1211,6 +1225,7 @@ stc_status stc_sync(stc_ctx* c) {
         return fail(c, STC_ERR_CAPACITY, "interaction list or frontier exceeded list_capacity");
     if (f[F_SLOTS]) return fail(c, STC_ERR_CAPACITY, "proxy storage slots exceeded");
     if (f[F_NONFINITE]) return fail(c, STC_ERR_INVALID_ARG, "non-finite particle position");
+    if (f[F_SORT_SPIN]) return fail(c, STC_ERR_DEVICE, "a sort's look-back exceeded its spin bound");
     return STC_OK;
 }
 
