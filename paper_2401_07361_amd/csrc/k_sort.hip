@@ -2,8 +2,9 @@
 // Used to order particles by leaf key (ties by input index, which is packed
 // in the low bits) and interaction lists by (target, type, source).
 //
-// One-sweep form: k_os_hist counts the digits of every pass in one read of
-// the keys; then one kernel per pass.  A pass kernel takes its tile number
+// One-sweep form: k_os_hist counts the first pass's digits; then one kernel
+// per pass, which also counts its tile's digits of the next pass (the keys
+// are in registers anyway).  A pass kernel takes its tile number
 // from an atomic counter (tiles are numbered in the order they start), ranks
 // the tile's keys stably (each wave ranks its contiguous quarter with ballots
 // and wave-private running counts in LDS, then one prefix over the four
@@ -19,7 +20,9 @@
 // that k_os_hist advances, so statuses left by an earlier sort (or an earlier
 // replay of a captured graph) never match.  The digit histograms and tile
 // counters must be zero when a sort starts (the callers clear them together
-// with their other per-evaluation counters).  The key count may live in
+// with their other per-evaluation counters); each histogram is kept in
+// kSortCopies copies (workgroup b adds to copy b % kSortCopies) so that the
+// atomics of many workgroups do not all meet on 256 addresses.  The key count may live in
 // device memory (n_bound then only sizes the grid), so no host
 // synchronisation is needed between the traversal and the sort.
 #include "common.hpp"
