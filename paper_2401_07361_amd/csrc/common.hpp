@@ -81,6 +81,15 @@ __device__ __forceinline__ u64 lanemask_lt() {
     return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
+// LDS writes of a wave ordered before its later reads (and reads before
+// later writes) without a workgroup barrier, for waves that work on their
+// own data
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave-aggregated append: every lane of the wave must call this together.
 // Lanes with pred get consecutive slots of *counter; returns the slot or
 // 0xffffffff for lanes without pred.

@@ -364,7 +364,7 @@ __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_
 }
 
 constexpr int NEAR_TP = 1;  // targets per thread: leaves are small, occupancy matters more
-constexpr int FAR_TP = 2;   // the proxy points of a node: each staged source feeds two targets
+constexpr int FAR_TP = 3;   // the proxy points of a node: each staged source feeds three targets (66 = 22 x 3: 242 of 256 threads busy, against 231 at two)
 
 template <typename T, int DEN, int NT>
 __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
@@ -512,79 +512,87 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
 // Interpolation to the particles and output.  For every node t holding
 // particle i that received CP/CC work, W_i += sum_k B_k(b_t(x_i)) alpha_k(t)
 // (the target-side interpolation of Sec. 3), per degree class; then
-// u_i = -(1/4pi) x_i x W_i, scattered to input order.  A workgroup takes 256
-// consecutive particles in tree order and walks the levels; at each level
-// its particles lie in a few consecutive nodes, whose coefficients are
-// staged in LDS (KS at a time) and read from there by every particle of the
-// node.
-constexpr int KS = 4;  // coefficient slots in LDS
+// u_i = -(1/4pi) x_i x W_i, scattered to input order.  A thread per particle
+// in tree order; a level without nodes of more than N_T particles is skipped
+// (such levels hold no target node of the proxy lists).  Each wave works on
+// its own: its particles lie in a few consecutive nodes (in one or two when
+// N_T >= 64), whose coefficients it stages in its part of LDS, KS nodes at a
+// time, and every particle reads its node's from there.  No workgroup
+// barrier: the waves of a workgroup walk the levels independently.
+constexpr int KS = 4;  // coefficient blocks per wave in LDS
 
 template <int NP>
 struct L2PShared {
-    double al[KS][NP][3];
-    i64 slot_node[256];
-    i32 slot_store[256];
-    u32 wtot[4];
+    double al[4][KS][NP][3];  // [wave][block]
 };
 
-// class `cls` (degree D) of node nd (local id ndl) for this thread's particle;
-// SKIP: return at once when no particle of the block has work in this class
-// (worth the extra barrier only when there are several classes)
-template <int D, bool SKIP, int NPM>
+// class `cls` (degree D) of node nd (local id ndl) for this thread's particle
+template <int D, int NPM>
 __device__ __forceinline__ void l2p_class(const EvalArgs& a, int cls, bool valid, i64 nd, i64 ndl, double x0,
                                           double x1, double x2, double& W0, double& W1, double& W2,
                                           L2PShared<NPM>& sh) {
     constexpr int NP = (D + 1) * (D + 2) / 2;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int poff = STC_PICK4(a.cls.poff, cls);
     const bool has = valid && a.nseg_end[(nd << a.DB) | cls] != 0;
-    if (SKIP && !__syncthreads_or(has)) return;
-    // the first particle of each node with far work opens a slot
-    sh.slot_node[tid] = has ? nd : (i64)-1;
-    __syncthreads();
-    const bool first = has && (tid == 0 || sh.slot_node[tid - 1] != nd);
-    u32 nslots = 0;
-    const u32 before = block_exclusive_scan<256>(first ? 1u : 0u, sh.wtot, &nslots);
-    const int my_slot = has ? (int)(before + (first ? 1u : 0u)) - 1 : -1;
-    __syncthreads();
-    if (first) {
-        sh.slot_node[my_slot] = nd;
-        sh.slot_store[my_slot] = a.slot[nd];
-    }
-    __syncthreads();
-    for (u32 s0 = 0; s0 < nslots; s0 += KS) {
-        const int ns = (nslots - s0) < (u32)KS ? (int)(nslots - s0) : KS;
-        for (int k = tid; k < ns * NP * 3; k += 256) {
-            const int sl = k / (NP * 3), r = k % (NP * 3);
-            sh.al[sl][r / 3][r % 3] = a.alpha[((size_t)sh.slot_store[s0 + sl] * a.NPT + poff) * 3 + r];
+    if (__ballot(has) == 0) return;  // uniform over the wave
+    // the first lane of each node with far work opens a block (tree order:
+    // a node's lanes are consecutive)
+    const i64 prev = __shfl_up(nd, 1, 64);
+    const bool first = has && (lane == 0 || prev != nd);
+    const u64 fm = __ballot(first);
+    const int nblk = __popcll(fm);
+    const int mine = has ? __popcll(fm & (lanemask_lt() | (1ull << lane))) - 1 : -1;
+    u64 rest = fm;  // first lanes of the blocks not staged yet
+    for (int b0 = 0; b0 < nblk; b0 += KS) {
+        const int nb = (nblk - b0) < KS ? nblk - b0 : KS;
+        for (int sl = 0; sl < nb; ++sl) {
+            const int src = __ffsll((unsigned long long)rest) - 1;
+            rest &= rest - 1;
+            const i64 node = __shfl(nd, src, 64);
+            const double* __restrict__ from = a.alpha + ((size_t)a.slot[node] * a.NPT + poff) * 3;
+            const double* __restrict__ coef = a.ref.coef + poff;
+            // c_k alpha_k: the basis coefficient folded in while staging
+            for (int r = lane; r < NP * 3; r += 64) sh.al[w][sl][r / 3][r % 3] = coef[r / 3] * from[r];
         }
-        __syncthreads();
-        const int ms = my_slot - (int)s0;
-        if (ms >= 0 && ms < ns) {
+        wave_lds_sync();
+        const int ms = mine - b0;
+        if (ms >= 0 && ms < nb) {
             const NodeGeo& g = a.geo[ndl];
-            const double* coef = a.ref.coef + poff;
-            double P[3][D + 1];
+            const double b0 = (g.minv[0][0] * x0 + g.minv[0][1] * x1) + g.minv[0][2] * x2;
+            const double b1 = (g.minv[1][0] * x0 + g.minv[1][1] * x1) + g.minv[1][2] * x2;
+            const double b2 = (g.minv[2][0] * x0 + g.minv[2][1] * x1) + g.minv[2][2] * x2;
+            double p1[D + 1], p2[D + 1];
+            p1[0] = 1.0;
+            p2[0] = 1.0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double be = (g.minv[c][0] * x0 + g.minv[c][1] * x1) + g.minv[c][2] * x2;
-                P[c][0] = 1.0;
-#pragma unroll
-                for (int t = 1; t <= D; ++t) P[c][t] = P[c][t - 1] * be;
+            for (int t = 1; t <= D; ++t) {
+                p1[t] = p1[t - 1] * b1;
+                p2[t] = p2[t - 1] * b2;
             }
+            // b1^i b2^j b3^(d-i-j) with a running power of b1; two
+            // accumulators per component (alternating terms) shorten the
+            // FMA chains
+            double A0[2] = {0.0, 0.0}, A1[2] = {0.0, 0.0}, A2[2] = {0.0, 0.0};
+            double pi = 1.0;
             int k = 0;
 #pragma unroll
             for (int i1 = 0; i1 <= D; ++i1) {
 #pragma unroll
                 for (int j1 = 0; j1 <= D - i1; ++j1) {
-                    const double B = coef[k] * (P[0][i1] * P[1][j1] * P[2][D - i1 - j1]);
-                    W0 += B * sh.al[ms][k][0];
-                    W1 += B * sh.al[ms][k][1];
-                    W2 += B * sh.al[ms][k][2];
+                    const double B = pi * (p1[j1] * p2[D - i1 - j1]);
+                    A0[k & 1] = __fma_rn(B, sh.al[w][ms][k][0], A0[k & 1]);
+                    A1[k & 1] = __fma_rn(B, sh.al[w][ms][k][1], A1[k & 1]);
+                    A2[k & 1] = __fma_rn(B, sh.al[w][ms][k][2], A2[k & 1]);
                     ++k;
                 }
+                pi *= b0;
             }
+            W0 += A0[0] + A0[1];
+            W1 += A1[0] + A1[1];
+            W2 += A2[0] + A2[1];
         }
-        __syncthreads();
+        wave_lds_sync();  // reads done before the next blocks are staged
     }
 }
 
@@ -606,13 +614,15 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
         const i64 mbase = (i64)(leaf >> a.LB) << a.NB;
         const u32 kl = leaf & ((1u << a.LB) - 1u);
         for (int lvl = 0; lvl <= L; ++lvl) {
+            // a level without nodes of more than N_T particles has no target
+            // node of the proxy lists (a uniform test: no barrier, no scan)
+            if (a.level_big[lvl] == 0u) continue;
             const i64 ndl = a.level_off_tab[lvl] + (i64)(kl >> (2 * (L - lvl)));  // local id
             const i64 nd = mbase + ndl;
-            constexpr bool SK = D1 > 0;
-            l2p_class<D0, SK>(a, 0, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D1 > 0) l2p_class<D1 ? D1 : 1, SK>(a, 1, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D2 > 0) l2p_class<D2 ? D2 : 1, SK>(a, 2, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D3 > 0) l2p_class<D3 ? D3 : 1, SK>(a, 3, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            l2p_class<D0>(a, 0, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D1 > 0) l2p_class<D1 ? D1 : 1>(a, 1, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D2 > 0) l2p_class<D2 ? D2 : 1>(a, 2, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            if (D3 > 0) l2p_class<D3 ? D3 : 1>(a, 3, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
         }
     }
     if (!valid) return;

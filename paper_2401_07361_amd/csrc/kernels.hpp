@@ -110,6 +110,7 @@ struct EvalArgs {
     double* alpha;       // target-side coefficients, slots x np x 3
     double* Wacc;        // per-particle sums, n x 3 (tree order)
     const u32* leaf;
+    const u32* level_big;  // per level: number of nodes with more than N_T particles
     const i32* perm;
     i64 n;
     RefDev ref;          // all classes' tables concatenated (class offsets in cls)

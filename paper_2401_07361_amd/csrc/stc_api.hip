@@ -208,6 +208,7 @@ EvalArgs eval_args(stc_ctx* c) {
     a.alpha = c->alpha;
     a.Wacc = c->Wacc;
     a.leaf = c->leaf;
+    a.level_big = c->flags + F_LEVEL;
     a.perm = c->perm;
     a.n = c->n;
     a.ref = ref_dev(c, 0);
