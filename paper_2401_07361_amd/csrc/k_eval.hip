@@ -503,7 +503,9 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
         block_matvec<NTT, 3>(a.ref.vinvT + qoff, np, nd, wt, &sh.red[0][0][0], co);
         const size_t ts = (size_t)a.slot[t] * a.NPT + poff;
-        for (int k = tid; k < 3 * np; k += NTT) a.alpha[ts * 3 + k] = co[k / 3][k % 3];
+        // stored as c_k alpha_k: the basis coefficient of the interpolation
+        // folded in once per node rather than once per particle
+        for (int k = tid; k < 3 * np; k += NTT) a.alpha[ts * 3 + k] = a.ref.coef[poff + k / 3] * co[k / 3][k % 3];
         __syncthreads();
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
     }
@@ -514,54 +516,39 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
 // (the target-side interpolation of Sec. 3), per degree class; then
 // u_i = -(1/4pi) x_i x W_i, scattered to input order.  A thread per particle
 // in tree order; a level without nodes of more than N_T particles is skipped
-// (such levels hold no target node of the proxy lists).  Each wave works on
-// its own: its particles lie in a few consecutive nodes (in one or two when
-// N_T >= 64), whose coefficients it stages in its part of LDS, KS nodes at a
-// time, and every particle reads its node's from there.  No workgroup
-// barrier: the waves of a workgroup walk the levels independently.
-constexpr int KS = 4;  // coefficient blocks per wave in LDS
+// (such levels hold no target node of the proxy lists).  A wave's particles
+// lie in a few consecutive nodes (mostly one at the coarse levels): the wave
+// takes them one at a time, the node id read from one lane, so that the
+// node's coefficients are wave-uniform: they come in through scalar loads
+// and enter the FMAs as scalar operands, with only the node's lanes active.
+// Per-lane copies (from LDS) would cost 64 x 8 bytes of LDS return per
+// coefficient and wave, twice the FP64 work they feed.
 
-template <int NP>
-struct L2PShared {
-    double al[4][KS][NP][3];  // [wave][block]
-};
+// i64 value of lane `src` (wave-uniform result)
+__device__ __forceinline__ i64 readlane64(i64 v, int src) {
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, src);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)((u64)v >> 32), src);
+    return (i64)(((u64)hi << 32) | lo);
+}
 
-// class `cls` (degree D) of node nd (local id ndl) for this thread's particle
-template <int D, int NPM>
-__device__ __forceinline__ void l2p_class(const EvalArgs& a, int cls, bool valid, i64 nd, i64 ndl, double x0,
-                                          double x1, double x2, double& W0, double& W1, double& W2,
-                                          L2PShared<NPM>& sh) {
-    constexpr int NP = (D + 1) * (D + 2) / 2;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int poff = STC_PICK4(a.cls.poff, cls);
-    const bool has = valid && a.nseg_end[(nd << a.DB) | cls] != 0;
-    if (__ballot(has) == 0) return;  // uniform over the wave
-    // the first lane of each node with far work opens a block (tree order:
-    // a node's lanes are consecutive)
-    const i64 prev = __shfl_up(nd, 1, 64);
-    const bool first = has && (lane == 0 || prev != nd);
-    const u64 fm = __ballot(first);
-    const int nblk = __popcll(fm);
-    const int mine = has ? __popcll(fm & (lanemask_lt() | (1ull << lane))) - 1 : -1;
-    u64 rest = fm;  // first lanes of the blocks not staged yet
-    for (int b0 = 0; b0 < nblk; b0 += KS) {
-        const int nb = (nblk - b0) < KS ? nblk - b0 : KS;
-        for (int sl = 0; sl < nb; ++sl) {
-            const int src = __ffsll((unsigned long long)rest) - 1;
-            rest &= rest - 1;
-            const i64 node = __shfl(nd, src, 64);
-            const double* __restrict__ from = a.alpha + ((size_t)a.slot[node] * a.NPT + poff) * 3;
-            const double* __restrict__ coef = a.ref.coef + poff;
-            // c_k alpha_k: the basis coefficient folded in while staging
-            for (int r = lane; r < NP * 3; r += 64) sh.al[w][sl][r / 3][r % 3] = coef[r / 3] * from[r];
-        }
-        wave_lds_sync();
-        const int ms = mine - b0;
-        if (ms >= 0 && ms < nb) {
-            const NodeGeo& g = a.geo[ndl];
-            const double b0 = (g.minv[0][0] * x0 + g.minv[0][1] * x1) + g.minv[0][2] * x2;
-            const double b1 = (g.minv[1][0] * x0 + g.minv[1][1] * x1) + g.minv[1][2] * x2;
-            const double b2 = (g.minv[2][0] * x0 + g.minv[2][1] * x1) + g.minv[2][2] * x2;
+// class of degree D (point offset poff) at one level: `has` marks a
+// particle whose node nd at this level holds far-field coefficients
+template <int D>
+__device__ __forceinline__ void l2p_level(const EvalArgs& a, int poff, bool has, i64 nd, double x0, double x1,
+                                          double x2, double& W0, double& W1, double& W2) {
+    u64 rest = __ballot(has);
+    while (rest != 0) {
+        const i64 node = readlane64(nd, __ffsll((unsigned long long)rest) - 1);
+        const bool mine = has && nd == node;
+        rest &= ~__ballot(mine);
+        // the node's inverse vertex matrix and coefficients: scalar loads
+        const double(*__restrict__ mi)[3] = a.geo[node & a.node_mask].minv;
+        const double* __restrict__ al = a.alpha + ((size_t)a.slot[node] * a.NPT + poff) * 3;
+        if (mine) {
+            // barycentric coordinates of the particle in the node
+            const double b0 = (mi[0][0] * x0 + mi[0][1] * x1) + mi[0][2] * x2;
+            const double b1 = (mi[1][0] * x0 + mi[1][1] * x1) + mi[1][2] * x2;
+            const double b2 = (mi[2][0] * x0 + mi[2][1] * x1) + mi[2][2] * x2;
             double p1[D + 1], p2[D + 1];
             p1[0] = 1.0;
             p2[0] = 1.0;
@@ -581,9 +568,9 @@ __device__ __forceinline__ void l2p_class(const EvalArgs& a, int cls, bool valid
 #pragma unroll
                 for (int j1 = 0; j1 <= D - i1; ++j1) {
                     const double B = pi * (p1[j1] * p2[D - i1 - j1]);
-                    A0[k & 1] = __fma_rn(B, sh.al[w][ms][k][0], A0[k & 1]);
-                    A1[k & 1] = __fma_rn(B, sh.al[w][ms][k][1], A1[k & 1]);
-                    A2[k & 1] = __fma_rn(B, sh.al[w][ms][k][2], A2[k & 1]);
+                    A0[k & 1] = __fma_rn(B, al[3 * k + 0], A0[k & 1]);
+                    A1[k & 1] = __fma_rn(B, al[3 * k + 1], A1[k & 1]);
+                    A2[k & 1] = __fma_rn(B, al[3 * k + 2], A2[k & 1]);
                     ++k;
                 }
                 pi *= b0;
@@ -592,16 +579,12 @@ __device__ __forceinline__ void l2p_class(const EvalArgs& a, int cls, bool valid
             W1 += A1[0] + A1[1];
             W2 += A2[0] + A2[1];
         }
-        wave_lds_sync();  // reads done before the next blocks are staged
     }
 }
 
 // D0..D3: degrees of the classes in use (0 = class unused)
 template <int D0, int D1, int D2, int D3>
 __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, double* __restrict__ u, int accumulate) {
-    constexpr int DM = D0 > D1 ? (D0 > D2 ? (D0 > D3 ? D0 : D3) : (D2 > D3 ? D2 : D3))
-                               : (D1 > D2 ? (D1 > D3 ? D1 : D3) : (D2 > D3 ? D2 : D3));
-    __shared__ L2PShared<(DM + 1) * (DM + 2) / 2> sh;
     const int tid = threadIdx.x;
     const i64 i0 = (i64)blockIdx.x * blockDim.x + tid;
     const bool valid = i0 < a.n;
@@ -613,16 +596,32 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
         const int L = a.L;
         const i64 mbase = (i64)(leaf >> a.LB) << a.NB;
         const u32 kl = leaf & ((1u << a.LB) - 1u);
-        for (int lvl = 0; lvl <= L; ++lvl) {
+        // which of the particle's nodes hold far-field coefficients, per
+        // class (bit = level): independent loads, issued together
+        u32 hb[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int lvl = 0; lvl <= kMaxLevels; ++lvl) {
+            const int lc = lvl < L ? lvl : L;
+            const i64 nd = mbase + a.level_off_tab[lc] + (i64)(kl >> (2 * (L - lc)));
             // a level without nodes of more than N_T particles has no target
-            // node of the proxy lists (a uniform test: no barrier, no scan)
-            if (a.level_big[lvl] == 0u) continue;
-            const i64 ndl = a.level_off_tab[lvl] + (i64)(kl >> (2 * (L - lvl)));  // local id
-            const i64 nd = mbase + ndl;
-            l2p_class<D0>(a, 0, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D1 > 0) l2p_class<D1 ? D1 : 1>(a, 1, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D2 > 0) l2p_class<D2 ? D2 : 1>(a, 2, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
-            if (D3 > 0) l2p_class<D3 ? D3 : 1>(a, 3, valid, nd, ndl, x0, x1, x2, W0, W1, W2, sh);
+            // node of the proxy lists
+            const bool lv = valid && lvl <= L && a.level_big[lc] != 0u;
+            const i64 sg = nd << a.DB;
+            if (lv && a.nseg_end[sg] != 0) hb[0] |= 1u << lvl;
+            if (D1 > 0 && lv && a.nseg_end[sg | 1] != 0) hb[1] |= 1u << lvl;
+            if (D2 > 0 && lv && a.nseg_end[sg | 2] != 0) hb[2] |= 1u << lvl;
+            if (D3 > 0 && lv && a.nseg_end[sg | 3] != 0) hb[3] |= 1u << lvl;
+        }
+        for (int lvl = 0; lvl <= L; ++lvl) {
+            if (a.level_big[lvl] == 0u) continue;  // uniform: no work at all
+            const i64 nd = mbase + a.level_off_tab[lvl] + (i64)(kl >> (2 * (L - lvl)));
+            l2p_level<D0>(a, STC_PICK4(a.cls.poff, 0), (hb[0] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
+            if (D1 > 0)
+                l2p_level<D1 ? D1 : 1>(a, STC_PICK4(a.cls.poff, 1), (hb[1] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
+            if (D2 > 0)
+                l2p_level<D2 ? D2 : 1>(a, STC_PICK4(a.cls.poff, 2), (hb[2] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
+            if (D3 > 0)
+                l2p_level<D3 ? D3 : 1>(a, STC_PICK4(a.cls.poff, 3), (hb[3] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
         }
     }
     if (!valid) return;
