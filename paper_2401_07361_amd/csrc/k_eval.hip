@@ -350,6 +350,22 @@ struct TargetGroup {
     }
 };
 
+// The sums over the S source slices of the partial sums in red (target ti +
+// k h of the pass, component c, slice q at red[k][c][q h + ti]): one
+// (target, component) per thread, slices added in order from zero, as a
+// single thread per target would; f(target of the pass, c, sum).
+template <int NTT, int TP, typename F>
+__device__ __forceinline__ void slice_sums(const double (*red)[3][NTT], int h, int S, int ntc, F&& f) {
+    for (int o = threadIdx.x; o < 3 * TP * h; o += NTT) {
+        const int k = o / (3 * h), rem = o - k * 3 * h, c = rem / h, ti = rem - c * h;
+        if (ti + k * h < ntc) {
+            double sum = 0.0;
+            for (int q = 0; q < S; ++q) sum += red[k][c][q * h + ti];
+            f(ti + k * h, c, sum);
+        }
+    }
+}
+
 // range of list entries of this workgroup (segments: key >> sh); returns
 // false if empty
 __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int sh, u32& e, u32& e_hi) {
@@ -409,22 +425,9 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
                 sh.red[k][2][tid] = tg.act ? az[k] : 0.0;
             }
             __syncthreads();
-            if (tg.act && tg.sl == 0) {
-#pragma unroll
-                for (int k = 0; k < TP; ++k) {
-                    if (!tg.valid[k]) continue;
-                    double sx = 0.0, sy = 0.0, sz = 0.0;
-                    for (int q = 0; q < tg.S; ++q) {
-                        sx += sh.red[k][0][q * tg.h + tg.ti];
-                        sy += sh.red[k][1][q * tg.h + tg.ti];
-                        sz += sh.red[k][2][q * tg.h + tg.ti];
-                    }
-                    const size_t gi = (size_t)(tb + tg.me[k]);
-                    a.Wacc[3 * gi + 0] += sx;
-                    a.Wacc[3 * gi + 1] += sy;
-                    a.Wacc[3 * gi + 2] += sz;
-                }
-            }
+            slice_sums<NT, TP>(sh.red, tg.h, tg.S, ntc, [&](int j, int c, double v) {
+                a.Wacc[3 * (size_t)(tb + cb + j) + c] += v;
+            });
             __syncthreads();
         }
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
@@ -483,21 +486,7 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
                 sh.red[k][2][tid] = tg.act ? az[k] : 0.0;
             }
             __syncthreads();
-            if (tg.act && tg.sl == 0) {
-#pragma unroll
-                for (int k = 0; k < TP; ++k) {
-                    if (!tg.valid[k]) continue;
-                    double sx = 0.0, sy = 0.0, sz = 0.0;
-                    for (int q = 0; q < tg.S; ++q) {
-                        sx += sh.red[k][0][q * tg.h + tg.ti];
-                        sy += sh.red[k][1][q * tg.h + tg.ti];
-                        sz += sh.red[k][2][q * tg.h + tg.ti];
-                    }
-                    wt[tg.me[k]][0] = sx;
-                    wt[tg.me[k]][1] = sy;
-                    wt[tg.me[k]][2] = sz;
-                }
-            }
+            slice_sums<NTT, TP>(sh.red, tg.h, tg.S, ntc, [&](int j, int c, double v) { wt[cb + j][c] = v; });
             __syncthreads();
         }
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
