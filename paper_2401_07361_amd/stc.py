@@ -11,6 +11,12 @@ import os
 
 import numpy as np
 
+# torch is imported before the library is loaded, so that the library binds
+# to the HIP runtime torch brings: loaded first, the library would bring in
+# the system's HIP and HSA runtimes, torch then a second pair, and device
+# allocations fail with two runtimes in one process
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstc.so")
 
