@@ -132,7 +132,8 @@ __device__ __forceinline__ void tile_sum(const Src<T>* __restrict__ tile, int cn
 #pragma unroll
     for (int k = 0; k < TP; ++k) px[k] = py[k] = pz[k] = T(0);
     if (!SELF) {
-        const int m = cnt / S;
+        int mr;
+        const int m = div_small(cnt, S, mr);
         const Src<T>* __restrict__ blk = tile + sl * m;
         if constexpr (sizeof(T) == 8) {
             int it = 0;
@@ -338,9 +339,9 @@ struct TargetGroup {
     bool act, valid[TP];
     __device__ TargetGroup(int ntc, int nthreads, int base) {
         h = (ntc + TP - 1) / TP;
-        S = nthreads / h;
-        ti = threadIdx.x % h;
-        sl = threadIdx.x / h;
+        int r;
+        S = div_small(nthreads, h, r);
+        sl = div_small((int)threadIdx.x, h, ti);
         act = sl < S;
 #pragma unroll
         for (int k = 0; k < TP; ++k) {
@@ -357,7 +358,12 @@ struct TargetGroup {
 template <int NTT, int TP, typename F>
 __device__ __forceinline__ void slice_sums(const double (*red)[3][NTT], int h, int S, int ntc, F&& f) {
     for (int o = threadIdx.x; o < 3 * TP * h; o += NTT) {
-        const int k = o / (3 * h), rem = o - k * 3 * h, c = rem / h, ti = rem - c * h;
+        // o < 3 TP h: the quotients are small and come from comparisons
+        int k = 0;
+#pragma unroll
+        for (int j = 1; j < TP; ++j) k += o >= j * 3 * h;
+        const int rem = o - k * 3 * h;
+        const int c = (rem >= h) + (rem >= 2 * h), ti = rem - c * h;
         if (ti + k * h < ntc) {
             double sum = 0.0;
             for (int q = 0; q < S; ++q) sum += red[k][c][q * h + ti];
