@@ -22,13 +22,18 @@ def say(msg):
 
 def _pair_coverage(ctx, n):
     """Number of ordered particle pairs (i, j), i != j, that the four lists
-    cover; must be n (n - 1) for any tree and any theta."""
+    cover; must be n (n - 1) for any tree and any theta.  Also checks that
+    every list is strictly increasing in (target, source): the lists come out
+    of the radix sort by (target, type, source) and no pair occurs twice (at
+    these sizes the sort's workgroups each take several tiles)."""
     _, cnt = ctx.copy_tree()
     cnt = cnt.astype(np.int64)
     total = 0
     for kind in ("PP", "PC", "CP", "CC"):
         lst = ctx.copy_list(kind)
         t, s = lst[:, 0], lst[:, 1]
+        key = (t.astype(np.int64) << 32) | s.astype(np.int64)
+        assert np.all(np.diff(key) > 0), kind
         total += int((cnt[t] * cnt[s]).sum())
         if kind == "PP":
             total -= int(cnt[t[t == s]].sum())
