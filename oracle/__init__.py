@@ -14,6 +14,8 @@ Applications to the Barotropic Vorticity Equation"):
 * ``tree``     -- the tree code: proxy weights, PP / PC / CP / CC interactions
                   and the dual tree traversal (Sec. 3).
 * ``rk4``      -- classical RK4 on (x, zeta) (Sec. 2 and Sec. 4).
+* ``forcing``  -- the vorticity forcing F_R of the polar-vortex collapse
+                  experiment (Sec. 5) and the forced RK4 step.
 * ``metrics``  -- the relative l2 errors E and E_N (Sec. 4).
 * ``mlp``      -- FP64 forward/backward of the small interaction-gating MLP.
 
@@ -23,4 +25,4 @@ nothing from the GPU library: the two share only the seeded input generators
 in ``synthetic``.
 """
 
-from . import direct, geometry, interp, tree, rk4, metrics  # noqa: F401
+from . import direct, geometry, interp, tree, rk4, metrics, forcing  # noqa: F401

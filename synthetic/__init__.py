@@ -32,6 +32,7 @@ from .fields import (
     gaussian_vortex,
     gaussian_vortex_paper,
     gaussian_pair,
+    polar_vortex,
     lonlat,
 )
 from .workloads import make_workload, make_ensemble, make_member, make_gate_training_input, WORKLOADS
@@ -41,6 +42,6 @@ __all__ = [
     "node_patch_areas", "random_rotation", "random_sphere_points",
     "clustered_sphere_points", "subset_indices", "OMEGA_EARTH_S",
     "OMEGA_EARTH_DAY", "rossby_haurwitz", "rossby_haurwitz_paper",
-    "gaussian_vortex", "gaussian_vortex_paper", "gaussian_pair", "lonlat",
+    "gaussian_vortex", "gaussian_vortex_paper", "gaussian_pair", "polar_vortex", "lonlat",
     "make_workload", "make_ensemble", "make_member", "make_gate_training_input", "WORKLOADS",
 ]

@@ -81,3 +81,12 @@ def gaussian_pair(x, seed, width=0.1, amplitude=4.0 * np.pi / 86400.0):
     d1 = great_circle_distance(x, c[0])
     d2 = great_circle_distance(x, c[1])
     return amplitude * (np.exp(-(d1 / width) ** 2) - np.exp(-(d2 / width) ** 2))
+
+
+def polar_vortex(x, beta=1.5, lat0=15.0 * np.pi / 32.0):
+    """Initial vorticity of the polar-vortex collapse experiment (Sec. 5), a
+    zonally symmetric profile of latitude theta (per day, Omega = 2 pi per day):
+    pi exp(-2 beta^2 (1 - cos(theta0 - theta))) (2 beta^2 cos(theta) sin(theta0 - theta) + sin(theta))."""
+    lat = np.arcsin(np.clip(x[:, 2], -1.0, 1.0))
+    b2 = 2.0 * beta * beta
+    return np.pi * np.exp(-b2 * (1.0 - np.cos(lat0 - lat))) * (b2 * np.cos(lat) * np.sin(lat0 - lat) + np.sin(lat))

@@ -13,6 +13,9 @@ conditions; no dataset exists or is needed):
                dt = 1800 s.
 * ``gvpair_l9`` N = 2621442 (level 9), RH n = 4 background plus a +/- vortex
                pair of amplitude 4 pi per day.
+* ``ssw_l7``   N = 163842 (level 7), node-patch areas, the polar vortex of the
+               vortex-collapse experiment (Sec. 5) with its wavenumber-1
+               vorticity forcing; time in days; d = 6, theta = 0.7.
 
 ``make_ensemble`` builds the ensemble workload: members with seeds 4 + m, each
 an icosahedral grid of level 5, 6 or 7 (N = 10242, 40962, 163842) under a
@@ -25,9 +28,9 @@ import numpy as np
 
 from .grids import (icosahedral_grid, uniform_areas, node_patch_areas,
                     subset_indices, random_rotation)
-from .fields import rossby_haurwitz, gaussian_vortex, gaussian_pair, great_circle_distance
+from .fields import rossby_haurwitz, gaussian_vortex, gaussian_pair, great_circle_distance, polar_vortex
 
-WORKLOADS = ("rh4_l5", "gv_l8", "rh4_l7", "gvpair_l9")
+WORKLOADS = ("rh4_l5", "gv_l8", "rh4_l7", "gvpair_l9", "ssw_l7")
 
 
 def make_workload(name, level=None):
@@ -63,6 +66,18 @@ def make_workload(name, level=None):
         return dict(name=name, x=x, zeta=z, area=uniform_areas(n),
                     subset=subset_indices(n, 4096, 5),
                     theta=0.7, degree=10, seed=5)
+    if name == "ssw_l7":
+        # polar-vortex collapse (Sec. 5): the vortex profile on a level-7
+        # grid with node-patch areas, time in days (Omega = 2 pi per day),
+        # wavenumber-1 forcing with T_p = 4, T_f = 15, lat1 = pi/3; the
+        # paper's d = 6, theta = 0.7; dt = 0.01 days (the time step the paper
+        # states for its Gaussian-vortex runs; none is given for this one)
+        L = 7 if level is None else level
+        x, faces = icosahedral_grid(L, return_faces=True)
+        return dict(name=name, x=x, zeta=polar_vortex(x), area=node_patch_areas(x, faces),
+                    subset=subset_indices(len(x), 4096, 6), theta=0.7, degree=6, seed=6,
+                    omega=2.0 * np.pi, dt=0.01, steps=10,
+                    forcing=dict(k=1, lat1=np.pi / 3.0, t_ramp=4.0, t_total=15.0))
     if name == "rotated_rh":
         # an icosahedral grid under a random rotation (no particle on a
         # tree edge), used for tie-free parity cases
