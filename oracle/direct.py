@@ -69,3 +69,29 @@ def kernel_sum(xt, xs, q, kernel, exclude=None):
         ok = exclude >= 0
         w[rows[ok], exclude[ok]] = 0.0
     return (w[:, :, None] * k).sum(1)
+
+
+def stream_function(x, zeta, area, targets=None, den="dot", chunk_elems=1 << 22):
+    """Stream function psi_i (len(targets),) of the discrete system:
+
+        psi_i = (1 / 4 pi) * sum_{j != i} zeta_j A_j log(1 - x_i . x_j)
+
+    the midpoint rule of psi = int G zeta with the Green's function of the
+    Laplace-Beltrami operator on the unit sphere (Sec. 2, stream function and
+    Green's function).  Reading: the sign is the one for which Delta psi = zeta
+    (zero-mean zeta) and u = x x grad psi reproduce the Biot-Savart velocity
+    above; the paper's G carries the opposite sign (see the velocity's sign
+    reading).  `den` selects 1 - x.y or |x - y|^2 / 2 inside the logarithm."""
+    x = np.asarray(x, dtype=np.float64)
+    q = np.asarray(zeta, dtype=np.float64) * np.asarray(area, dtype=np.float64)
+    n = len(x)
+    targets = np.arange(n) if targets is None else np.asarray(targets)
+    out = np.empty(len(targets))
+    m = max(1, chunk_elems // max(n, 1))
+    for c0 in range(0, len(targets), m):
+        idx = targets[c0:c0 + m]
+        dn = _den(x[idx], x, den)
+        self_pair = idx[:, None] == np.arange(n)[None, :]
+        lg = np.log(np.where(self_pair, 1.0, dn))
+        out[c0:c0 + m] = (np.where(self_pair, 0.0, q[None, :] * lg)).sum(1)
+    return out / FOUR_PI

@@ -60,6 +60,23 @@ def biot_savart_kernel(den="dot"):
     return k
 
 
+def stream_kernel(den="dot"):
+    """The stream function's kernel log(den(X, Y)) in component 0 (the other
+    two components zero), so that the same interactions carry it; the
+    stream function is psi = W_0 / 4 pi (Sec. 2, stream function)."""
+    def k(X, Y):
+        if den == "dot":
+            dn = 1.0 - ((X[:, None, 0] * Y[None, :, 0] + X[:, None, 1] * Y[None, :, 1])
+                        + X[:, None, 2] * Y[None, :, 2])
+        else:
+            D = Y[None, :, :] - X[:, None, :]
+            dn = 0.5 * ((D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1]) + D[..., 2] * D[..., 2])
+        out = np.zeros(dn.shape + (3,))
+        out[..., 0] = np.log(dn)
+        return out
+    return k
+
+
 def polynomial_kernel(d, a=(0.3, -0.5, 0.7)):
     """A test kernel homogeneous of degree d in both arguments:
     K(x, y) = a (x . y)^d.  Interpolation of degree d reproduces it exactly."""
@@ -213,6 +230,10 @@ class TreeCode:
         W = self.evaluate(parts)
         return -np.cross(self.x, W) / FOUR_PI
 
+    def stream_function(self, parts=("near", "far")):
+        """psi_i = W_0 / 4 pi for a TreeCode built with kernel=stream_kernel()."""
+        return self.evaluate(parts)[:, 0] / FOUR_PI
+
     def list_counts(self):
         return {k: len(v) for k, v in self.lists.items()}
 
@@ -235,4 +256,4 @@ def velocity(x, zeta, area, **kw):
 
 
 __all__ = ["TreeCode", "velocity", "traverse", "well_separated", "default_max_level",
-           "biot_savart_kernel", "polynomial_kernel", "node_level_key", "level_offset"]
+           "biot_savart_kernel", "stream_kernel", "polynomial_kernel", "node_level_key", "level_offset"]
