@@ -20,6 +20,10 @@ beside the fixed-degree method in FP32 and FP64.
 wavenumber 3-5 plus a Gaussian bump), all members in one launch per phase,
 against the same members evaluated one context after the other; it also
 times graph-captured RK4 steps of the whole ensemble.
+
+``--workload rk4`` times graph-captured RK4 steps of the Rossby-Haurwitz wave
+at N = 163842; ``--workload ssw`` those of the forced polar-vortex collapse
+(Sec. 5) at N = 163842, d = 6, theta = 0.7.
 """
 
 import argparse
@@ -397,6 +401,72 @@ def bench_rk4(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_ssw(args):
+    """Forced RK4 of the polar-vortex collapse (Sec. 5) at the paper's setting
+    (N = 163842, d = 6, theta = 0.7, wavenumber-1 forcing); the accuracy check
+    is one evaluation at full forcing (day 8) against the FP64 direct sum of
+    the forced field on 4096 seeded targets."""
+    import torch
+    import synthetic as S
+    from paper_2401_07361_amd import stc
+    from oracle import metrics
+
+    wl = S.make_workload("ssw_l7")
+    x, z, a, sub = wl["x"], wl["zeta"], wl["area"], wl["subset"]
+    n = len(x)
+    dt, Om, fc = wl["dt"], wl["omega"], wl["forcing"]
+    fargs = (fc["k"], Om, fc["lat1"], fc["t_ramp"], fc["t_total"])
+    t_check = 8.0
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    zf = zd - stc.forcing_field(xd, *fargs, t_check)
+    ud = stc.direct(xd, zf, ad, targets=torch.from_numpy(sub).cuda(), denominator="dist2").cpu().numpy()
+    log(f"workload ssw_l7 N={n} theta={wl['theta']} d={wl['degree']} k={fc['k']} dt={dt} days")
+    runs = {}
+    for prec in ("fp32", "fp64"):
+        ctx = stc.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision=prec, denominator="dist2")
+        ctx.set_forcing(*fargs, time=t_check)
+        u = ctx.velocity(xd, zd, ad)
+        err = metrics.rel_l2_velocity(u.cpu().numpy()[sub], ud, a[sub])
+        ms_eval, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
+        cnt, ev = ctx.list_counts()
+        xs, zs = xd.clone(), zd.clone()
+        ctx.set_forcing(*fargs, time=0.0)
+        ctx.rk4(xs, zs, ad, dt, Om, 1)   # captures the step graph
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        ctx.rk4(xs, zs, ad, dt, Om, args.steps)
+        t1.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        ms_step = t0.elapsed_time(t1) / args.steps
+        t_end = ctx.forcing()[1]["time"]
+        runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4),
+                          rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), phase_ms=ph, forcing_time_after=t_end,
+                          near=(ev["PP"] + ev["PC"], near_ms_t))
+        log(f"{prec}: {ms_step:.3f} ms per forced RK4 step (graph), {ms_eval:.3f} ms per evaluation, E = {err:.3e}")
+        ctx.close()
+    r = runs["fp32"]
+    near_evals, near_ms = r.pop("near")
+    runs["fp64"].pop("near")
+    result = dict(
+        metric="particle velocity evals/s in forced RK4 time stepping at N=163842 (polar-vortex collapse, "
+               "4 evaluations per step, one HIP graph per step)",
+        value=4 * n / (r["ms_per_rk4_step"] / 1e3), unit="velocity evals/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=r["ms_per_rk4_step"], higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="ssw_l7 (polar vortex, wavenumber-1 forcing, icosahedral level 7, node-patch areas)",
+                    N=n, theta=wl["theta"], degree=wl["degree"], n_crit=64, dt_days=dt, omega_per_day=Om,
+                    forcing=fc, error_check_day=t_check, runs=runs),
+        roofline=near_roofline(near_evals, near_ms, "fp32"),
+    )
+    if not args.no_cpu:
+        log("cpu baseline (oracle direct sum of the forced field, bounded target sample)")
+        cb, _, _ = cpu_baseline(x, zf.cpu().numpy(), a, sub, budget_s=8.0, den="dist2", what="4096 seeded targets")
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,7 +478,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4"])
+    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4", "ssw"])
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -424,6 +494,9 @@ def main():
         return
     if args.workload == "rk4":
         bench_rk4(args)
+        return
+    if args.workload == "ssw":
+        bench_ssw(args)
         return
 
     import torch

@@ -242,6 +242,45 @@ stc_status stc_rk4_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offse
                            double* d_zeta, const double* d_area, double dt, double omega,
                            int32_t n_steps);
 
+/* --- vorticity forcing (Sec. 5, polar vortex collapse) ----------------------
+ *
+ * With a forcing set, every evaluation of the context (stc_upward, hence
+ * stc_velocity, the batched calls and every RK4 stage) uses the source charges
+ *   q_j = (zeta_j - F_R(x_j, t)) A_j,
+ *   F_R = (3/5) omega k^2 A(t) B(lat) cos(k lon),
+ *   A(t) = (1 - cos(pi t / T_p)) / 2 on [0, T_p), 1 on [T_p, T_f - T_p),
+ *          (1 + cos(pi (t - T_f + T_p) / T_p)) / 2 on [T_f - T_p, T_f), 0 for
+ *          t >= T_f and (reading) for t < 0,
+ *   B(lat) = s e^(1 - s), s = tan^2(lat1) / tan^2(lat), for lat > 0; 0 for lat <= 0,
+ * with lat, lon the latitude and longitude of the direction of x_j (stage
+ * points of RK4 are off the sphere).  The particles' own zeta still evolves by
+ * dzeta/dt = -2 omega u_z.  Units are the caller's (the paper: days, omega =
+ * 2 pi per day, T_p = 4, T_f = 15, lat1 = pi / 3, k = 1 or 2).
+ * `time` is t of the next single evaluation and the start time of the next
+ * stc_rk4 / stc_rk4_batched call, whose stages see t, t + dt/2, t + dt/2,
+ * t + dt of each step; after the call the context's time has advanced by
+ * n_steps dt (stc_get_forcing reads it).
+ * Errors: STC_ERR_INVALID_ARG (enqueues nothing) unless 0 <= k <= 16, omega
+ * finite, 0 < lat1 < pi/2, T_p > 0, T_f >= 2 T_p and time finite.  A NULL f
+ * switches the forcing off.  Setting or clearing drops a captured RK4 step. */
+typedef struct stc_forcing {
+    int32_t k;        /* zonal wavenumber */
+    double omega;     /* rotation rate in the amplitude (3/5) omega k^2 */
+    double lat1;      /* latitude of maximum forcing, radians */
+    double t_ramp;    /* T_p: ramp-up (and ramp-down) time */
+    double t_total;   /* T_f: the forcing is zero from T_f on */
+    double time;      /* forcing time t (see above) */
+} stc_forcing;
+stc_status stc_set_forcing(stc_ctx* ctx, const stc_forcing* f);
+/* Copies the forcing (with the current time) into *f and 1 / 0 into *on. */
+stc_status stc_get_forcing(const stc_ctx* ctx, stc_forcing* f, int32_t* on);
+/* F_R(x_i, f->time) of the forcing above at n positions d_x ((n, 3) row-major
+ * FP64, any length) into d_out (n FP64), input order; asynchronous on
+ * hip_stream (NULL: the null stream).  STC_ERR_INVALID_ARG for an invalid
+ * forcing, n < 0, or NULL / unaligned pointers with n > 0. */
+stc_status stc_forcing_field(void* hip_stream, const stc_forcing* f, int64_t n, const double* d_x,
+                             double* d_out);
+
 /* --- the learned form: gating network ---------------------------------------
  *
  * Network: 12 inputs -> 64 -> 64 -> 4 outputs, ReLU, BF16 weights and

@@ -182,13 +182,70 @@ __global__ __launch_bounds__(256) void k_node_ranges(const u32* __restrict__ lea
     }
 }
 
+// Ramp A(t) of the forcing (Sec. 5, polar vortex collapse): a half cosine up
+// over [0, T_p), 1 until T_f - T_p, a half cosine down until T_f, 0 outside
+// [0, T_f).  On the last piece (1 - cos(pi + a)) / 2 = (1 + cos a) / 2.
+__device__ double forcing_ramp(double t, double tp, double tf) {
+    constexpr double kPi = 3.141592653589793;
+    if (!(t >= 0.0) || t >= tf) return 0.0;
+    if (t < tp) return 0.5 * (1.0 - cos(t / tp * kPi));
+    if (t < tf - tp) return 1.0;
+    return 0.5 * (1.0 + cos((t - tf + tp) / tp * kPi));
+}
+
+// F_R / (amp A) at a point in any direction x (stage points of RK4 lie off the
+// sphere): B(lat) cos(k lon) without trigonometric functions.  With rho the
+// distance from the axis, tan^2(lat) = z^2 / rho^2, so the ratio
+// r = tan^2(lat1) / tan^2(lat) = tan^2(lat1) rho^2 / z^2 and B = r e^(1 - r)
+// for z > 0 (B = 0 for lat <= 0; B -> 0 at the pole, where r = 0).
+// cos(k lon) = Re((x + i y)^k) / rho^k, from the unit vector (x, y) / rho.
+__device__ double forcing_shape(int k, double tan2_1, double x, double y, double z) {
+    if (!(z > 0.0)) return 0.0;
+    const double rho2 = x * x + y * y;
+    const double r = tan2_1 * rho2 / (z * z);
+    if (!(r > 0.0) || r > 1000.0) return 0.0;  // pole, or e^(1 - r) below the smallest double
+    const double b = r * exp(1.0 - r);
+    const double rho = sqrt(rho2);
+    const double cx = x / rho, cy = y / rho;
+    double re = 1.0, im = 0.0;
+    for (int m = 0; m < k; ++m) {
+        const double t = re * cx - im * cy;
+        im = re * cy + im * cx;
+        re = t;
+    }
+    return b * re;
+}
+
+// Source charges in tree order: q = zeta A, or (zeta - F_R(x, t)) A with the
+// forcing on; x is the particle's (sorted) position.
 __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i64 n,
                                                   const double* __restrict__ zeta,
-                                                  const double* __restrict__ area, double* __restrict__ q) {
+                                                  const double* __restrict__ area, const double* __restrict__ sx,
+                                                  const double* __restrict__ sy, const double* __restrict__ sz,
+                                                  ForcingDev f, double* __restrict__ q) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const i32 j = perm[i];
-    q[i] = zeta[j] * area[j];
+    double z = zeta[j];
+    if (f.on) {
+        const double t = f.t_dev ? *f.t_dev + f.t_base : f.t_base;
+        const double a = forcing_ramp(t, f.t_ramp, f.t_total);
+        if (a != 0.0) z -= f.amp * a * forcing_shape(f.k, f.tan2_1, sx[i], sy[i], sz[i]);
+    }
+    q[i] = z * area[j];
+}
+
+// F_R(x_i, t) at caller positions (row-major (n, 3)), input order.
+__global__ __launch_bounds__(256) void k_forcing_field(i64 n, const double* __restrict__ x, ForcingDev f,
+                                                        double* __restrict__ out) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = forcing_ramp(f.t_base, f.t_ramp, f.t_total);
+    out[i] = a == 0.0 ? 0.0 : f.amp * a * forcing_shape(f.k, f.tan2_1, x[3 * i], x[3 * i + 1], x[3 * i + 2]);
+}
+
+__global__ void k_forcing_clock(double* t, double value, int set) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) t[0] = set ? value : t[0] + value;
 }
 
 // ---------------------------------------------------------------------------
@@ -832,9 +889,19 @@ void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i3
     hipLaunchKernelGGL(k_node_ranges, dim3(blocks_for(n, 256)), dim3(256), 0, s, leaf, n, L, NB, nbeg, nend);
 }
 
-void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area, double* q) {
+void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area,
+                    const double* sx, const double* sy, const double* sz, ForcingDev f, double* q) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, q);
+    hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, sx, sy, sz, f, q);
+}
+
+void launch_forcing_field(hipStream_t s, i64 n, const double* x, ForcingDev f, double* out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_forcing_field, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, f, out);
+}
+
+void launch_forcing_clock(hipStream_t s, double* t, double value, int set) {
+    hipLaunchKernelGGL(k_forcing_clock, dim3(1), dim3(64), 0, s, t, value, set);
 }
 
 void launch_upward(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,

@@ -26,7 +26,21 @@ void launch_bin(hipStream_t s, const double* x, i64 n, const NodeGeo* geo, int L
 void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* perm, u32* leaf,
                    double* sx, double* sy, double* sz);
 void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i32* nbeg, i32* nend);
-void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area, double* q);
+// Vorticity forcing of the polar-vortex collapse experiment (Sec. 5): the
+// charges become q = (zeta - F_R(x, t)) A with
+// F_R = amp A(t) B(lat) cos(k lon), amp = (3/5) Omega k^2.  The time is
+// t_base, or *t_dev + t_base when t_dev is set (RK4 stages under a graph).
+struct ForcingDev {
+    int on, k;
+    double amp, tan2_1, t_ramp, t_total, t_base;
+    const double* t_dev;
+};
+void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area,
+                    const double* sx, const double* sy, const double* sz, ForcingDev f, double* q);
+// F_R(x_i, f.t_base) at n positions in input order
+void launch_forcing_field(hipStream_t s, i64 n, const double* x, ForcingDev f, double* out);
+// single-thread update of the forcing clock: *t = set ? value : *t + value
+void launch_forcing_clock(hipStream_t s, double* t, double value, int set);
 void launch_upward(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
                    const i32* nbeg, const i32* nend, const i32* item_node, const i32* item_chunk,
                    const i32* item_base, u32 items_cap, const NodeGeo* geo, const double* sx, const double* sy,

@@ -88,6 +88,10 @@ struct stc_ctx {
     std::vector<i64> rk_offsets;
     const void *rk_px = nullptr, *rk_pz = nullptr, *rk_pa = nullptr;
     double rk_dt = 0.0, rk_om = 0.0;
+    // vorticity forcing (stc_set_forcing); forcing_t: the device clock RK4 steps read
+    bool forcing_on = false;
+    stc_forcing forcing{};
+    double* forcing_t = nullptr;
     // phase timing: 7 events per recorded evaluation
     std::vector<hipEvent_t> tev;
     int t_max = 0, t_used = 0, t_phase = -1;
@@ -306,10 +310,39 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     return check_launch(c, "tree_build");
 }
 
-stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area) {
+// Charges at the forcing's host time, or (stage_clock) at the device clock
+// plus t_off: the RK4 stages, whose start time lives on the device so that a
+// captured step can be replayed.
+bool forcing_valid(const stc_forcing* f) {
+    const double half_pi = 1.5707963267948966;
+    return f->k >= 0 && f->k <= 16 && std::isfinite(f->omega) && f->lat1 > 0.0 && f->lat1 < half_pi &&
+           f->t_ramp > 0.0 && std::isfinite(f->t_ramp) && f->t_total >= 2.0 * f->t_ramp &&
+           std::isfinite(f->t_total) && std::isfinite(f->time);
+}
+
+// Device form of a forcing at time t_base (amplitude (3/5) omega k^2).
+ForcingDev forcing_dev(const stc_forcing& h, double t_base, const double* t_dev) {
+    ForcingDev f{};
+    const double tl = tan(h.lat1);
+    f.on = 1;
+    f.k = h.k;
+    f.amp = 0.6 * h.omega * (double)h.k * (double)h.k;
+    f.tan2_1 = tl * tl;
+    f.t_ramp = h.t_ramp;
+    f.t_total = h.t_total;
+    f.t_base = t_base;
+    f.t_dev = t_dev;
+    return f;
+}
+
+stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area, bool stage_clock = false,
+                     double t_off = 0.0) {
     hipStream_t s = c->stream;
     mark(c, 1);
-    launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sq);
+    ForcingDev f{};
+    if (c->forcing_on)
+        f = stage_clock ? forcing_dev(c->forcing, t_off, c->forcing_t) : forcing_dev(c->forcing, c->forcing.time, nullptr);
+    launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sx, c->sy, c->sz, f, c->sq);
     if (c->n > 0) {
         // the highest class from the particles; the others (learned form) by
         // re-interpolating each node's own record of the highest class
@@ -628,7 +661,7 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
               dalloc(c, &c->sort_zero, kSortZeroWords) &&
               dalloc(c, &c->sort_status, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->sort_epoch, 2) &&
               dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
-              dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm) &&
+              dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm) && dalloc(c, &c->forcing_t, 1) &&
               dalloc(c, &c->item_node, c->items_cap) && dalloc(c, &c->item_chunk, c->items_cap) &&
               dalloc(c, &c->item_base, ns) && dalloc(c, &c->upart, (size_t)c->items_cap * c->cls.np[c->ndeg - 1]);
     if (ok && learned)
@@ -854,11 +887,12 @@ static stc_status rk4_enqueue_step(stc_ctx* c, int members, const i64* off, doub
     // stage nodes 0, 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6
     const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
     const double wacc[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    const double stage_t[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};  // forcing time of each stage after the step's start
     const double* xs = d_x;
     const double* zs = d_zeta;
     for (int stg = 0; stg < 4; ++stg) {
         stc_status st = do_build(c, members, off, xs);
-        if (st == STC_OK) st = do_upward(c, zs, d_area);
+        if (st == STC_OK) st = do_upward(c, zs, d_area, true, stage_t[stg]);
         if (st == STC_OK) st = do_traverse(c);
         if (st == STC_OK) st = do_eval(c, true, true, c->rk_u, false);
         if (st != STC_OK) return st;
@@ -868,6 +902,7 @@ static stc_status rk4_enqueue_step(stc_ctx* c, int members, const i64* off, doub
         zs = c->rk_z;
     }
     hipLaunchKernelGGL(k_rk4_finish, g, b, 0, s, (i64)n, c->rk_xacc, c->rk_zacc, d_x, d_zeta);
+    if (c->forcing_on) launch_forcing_clock(s, c->forcing_t, dt, 0);
     return check_launch(c, "rk4");
 }
 
@@ -921,7 +956,10 @@ static stc_status rk4_run(stc_ctx* c, int members, const i64* off, double* d_x, 
     const i64 n = off[members];
     if (n_steps < 0 || !std::isfinite(dt) || !std::isfinite(omega))
         return fail(c, STC_ERR_INVALID_ARG, "bad n_steps, dt or omega");
-    if (n == 0 || n_steps == 0) return STC_OK;
+    if (n == 0 || n_steps == 0) {
+        if (c->forcing_on) c->forcing.time += (double)n_steps * dt;
+        return STC_OK;
+    }
     if (!d_x || !d_zeta || !d_area || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area))
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
     // RK4 stage points leave the sphere (|x_s| - 1 ~ (dt |u|)^2 / 8); 1 - x.y can
@@ -929,6 +967,9 @@ static stc_status rk4_run(stc_ctx* c, int members, const i64* off, double* d_x, 
     if (c->p.denominator != STC_DEN_DIST2)
         return fail(c, STC_ERR_INVALID_ARG, "stc_rk4 needs the |x-y|^2/2 denominator (stage points are off the sphere)");
     const bool use_graph = (c->p.flags & STC_FLAG_EAGER_RK4) == 0;
+    // the steps read their start time from the device clock (a kernel, not a
+    // memset: the clock is also written inside captured steps)
+    if (c->forcing_on) launch_forcing_clock(c->stream, c->forcing_t, c->forcing.time, 1);
     if (!use_graph) {
         for (int step = 0; step < n_steps; ++step) {
             stc_status st = rk4_enqueue_step(c, members, off, d_x, d_zeta, d_area, dt, omega);
@@ -948,6 +989,34 @@ static stc_status rk4_run(stc_ctx* c, int members, const i64* off, double* d_x, 
                 return fail(c, STC_ERR_DEVICE, "hipGraphLaunch failed");
     }
     c->have_tree = c->have_upward = c->have_lists = false;  // stage data, not the final state
+    if (c->forcing_on) c->forcing.time += (double)n_steps * dt;
+    return STC_OK;
+}
+
+stc_status stc_set_forcing(stc_ctx* c, const stc_forcing* f) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (f) {
+        if (!forcing_valid(f))
+            return fail(c, STC_ERR_INVALID_ARG, "forcing needs 0 <= k <= 16, 0 < lat1 < pi/2, T_p > 0, T_f >= 2 T_p");
+        c->forcing = *f;
+    }
+    c->forcing_on = f != nullptr;
+    rk4_drop_graph(c);
+    return STC_OK;
+}
+
+stc_status stc_forcing_field(void* hip_stream, const stc_forcing* f, int64_t n, const double* d_x, double* d_out) {
+    if (!f || !forcing_valid(f) || n < 0 || (n > 0 && (!d_x || !d_out || !aligned8(d_x) || !aligned8(d_out))))
+        return STC_ERR_INVALID_ARG;
+    if (n == 0) return STC_OK;
+    launch_forcing_field(static_cast<hipStream_t>(hip_stream), n, d_x, forcing_dev(*f, f->time, nullptr), d_out);
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
+stc_status stc_get_forcing(const stc_ctx* c, stc_forcing* f, int32_t* on) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (f) *f = c->forcing;
+    if (on) *on = c->forcing_on ? 1 : 0;
     return STC_OK;
 }
 

@@ -50,6 +50,12 @@ class LaunchConfig(ctypes.Structure):
         return (self.near_threads, self.near_blocks_per_cu, self.far_threads, self.far_blocks_per_cu)
 
 
+class Forcing(ctypes.Structure):
+    """stc_forcing: the vorticity forcing of the polar-vortex collapse (Sec. 5)."""
+    _fields_ = [("k", ctypes.c_int32), ("omega", ctypes.c_double), ("lat1", ctypes.c_double),
+                ("t_ramp", ctypes.c_double), ("t_total", ctypes.c_double), ("time", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libstc.so is not built: run `python -m paper_2401_07361_amd.build` "
@@ -95,6 +101,9 @@ def _load():
         "stc_velocity": (I32, [P, I64, VP, VP, VP, VP]),
         "stc_direct": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
         "stc_rk4": (I32, [P, I64, VP, VP, VP, D, D, I32]),
+        "stc_set_forcing": (I32, [P, ctypes.POINTER(Forcing)]),
+        "stc_get_forcing": (I32, [P, ctypes.POINTER(Forcing), PI32]),
+        "stc_forcing_field": (I32, [VP, ctypes.POINTER(Forcing), I64, VP, VP]),
         "stc_sync": (I32, [P]),
         "stc_list_counts": (I32, [P, PI64, PI64]),
         "stc_copy_list": (I32, [P, I32, I64, PI64, PI64]),
@@ -216,6 +225,18 @@ def direct(x, zeta, area, targets=None, precision="fp64", denominator="dot", out
                          _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
                          _dptr(out, "out", torch.float64, 3 * m))
     _check(st)
+    return out
+
+
+def forcing_field(x, k, omega, lat1, t_ramp, t_total, time, out=None, stream=None):
+    """F_R(x_i, time) of the polar-vortex forcing (Sec. 5) at every row of x."""
+    import torch
+    n = x.shape[0]
+    if out is None:
+        out = torch.empty((n,), dtype=torch.float64, device=x.device)
+    f = Forcing(int(k), float(omega), float(lat1), float(t_ramp), float(t_total), float(time))
+    _check(_lib.stc_forcing_field(_stream(stream), ctypes.byref(f), n, _dptr(x, "x", torch.float64, 3 * n),
+                                  _dptr(out, "out", torch.float64, n)))
     return out
 
 
@@ -497,6 +518,22 @@ class Context:
         st = _lib.stc_rk4(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n), _dptr(zeta, "zeta", torch.float64, n),
                           _dptr(area, "area", torch.float64, n), float(dt), float(omega), int(n_steps))
         _check(st, self._ctx)
+
+    # vorticity forcing (Sec. 5, polar vortex collapse) ---------------------------------
+    def set_forcing(self, k, omega, lat1, t_ramp, t_total, time=0.0):
+        """Charges (zeta - F_R(x, t)) A from now on; `time` is t of the next
+        evaluation and the start time of the next rk4 call."""
+        f = Forcing(int(k), float(omega), float(lat1), float(t_ramp), float(t_total), float(time))
+        _check(_lib.stc_set_forcing(self._ctx, ctypes.byref(f)), self._ctx)
+
+    def clear_forcing(self):
+        _check(_lib.stc_set_forcing(self._ctx, None), self._ctx)
+
+    def forcing(self):
+        """(on, dict of the stc_forcing fields, time included)."""
+        f, on = Forcing(), ctypes.c_int32()
+        _check(_lib.stc_get_forcing(self._ctx, ctypes.byref(f), ctypes.byref(on)), self._ctx)
+        return bool(on.value), {name: getattr(f, name) for name, _ in Forcing._fields_}
 
     # timing -------------------------------------------------------------------------
     PHASES = ("build", "upward", "traverse", "near", "far_targets", "l2p")

@@ -92,4 +92,16 @@ def test_invalid_arguments_are_rejected_without_device_work(stc):
     assert lib.stc_direct(None, 10, None, None, None, 10, None, 0, 0, None) == 1
     assert lib.stc_direct(None, 10, None, None, None, 5, None, 0, 0, None) == 1   # m != n without targets
     assert lib.stc_direct(None, 0, None, None, None, 0, None, 0, 0, None) == 0    # empty: no-op
+    # vorticity forcing: invalid parameters and NULL pointers are refused on the host
+    import math
+    good = (1, 2 * math.pi, math.pi / 3, 4.0, 15.0, 0.0)
+    assert lib.stc_set_forcing(None, None) == 1
+    assert lib.stc_forcing_field(None, None, 10, None, None) == 1
+    assert lib.stc_forcing_field(None, ctypes.byref(stc.Forcing(*good)), 10, None, None) == 1
+    assert lib.stc_forcing_field(None, ctypes.byref(stc.Forcing(*good)), 0, None, None) == 0   # empty: no-op
+    for i, v in [(0, 17), (0, -1), (2, 0.0), (2, 1.6), (3, 0.0), (4, 7.9), (1, float("nan")), (5, float("inf"))]:
+        f = list(good)
+        f[i] = v
+        assert lib.stc_forcing_field(None, ctypes.byref(stc.Forcing(*f)), 0, None, None) == 1, (i, v)
+    assert lib.stc_get_forcing(None, None, None) == 1
     assert stc.status_string(2).startswith("interaction list")
