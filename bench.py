@@ -23,7 +23,8 @@ times graph-captured RK4 steps of the whole ensemble.
 
 ``--workload rk4`` times graph-captured RK4 steps of the Rossby-Haurwitz wave
 at N = 163842; ``--workload ssw`` those of the forced polar-vortex collapse
-(Sec. 5) at N = 163842, d = 6, theta = 0.7.
+(Sec. 5) at N = 163842, d = 6, theta = 0.7; ``--workload stream`` the stream
+function (logarithmic kernel) on the headline workload and setting.
 """
 
 import argparse
@@ -467,6 +468,51 @@ def bench_ssw(args):
     print(json.dumps(result), flush=True)
 
 
+LOG_FLOPS = 12  # per stream-function evaluation: 3 sub, |d|^2 5, x1/2 1, log 1 (counted as one), q*log + add 2
+
+
+def bench_stream(args):
+    """The stream function (Sec. 2; the logarithmic kernel through the same
+    tree) on the headline workload and setting (N = 655362 Gaussian vortex,
+    FP32 form, theta 0.8, d 10), checked against the FP64 direct stream
+    function on the 4096 seeded targets."""
+    import torch
+    import synthetic as S
+    from paper_2401_07361_amd import stc
+    from oracle import metrics
+
+    wl = S.make_workload("gv_l8", level=args.level)
+    x, z, a, sub = wl["x"], wl["zeta"], wl["area"], wl["subset"]
+    n = len(x)
+    log(f"workload gv_l8 stream function N={n} theta={args.theta} d={args.degree} {args.precision}")
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    ref = stc.direct_stream(xd, zd, ad, targets=torch.from_numpy(sub).cuda(), denominator="dist2").cpu().numpy()
+    ctx = stc.Context(n, theta=args.theta, degree=args.degree, n_crit=args.n_crit, precision=args.precision,
+                      denominator="dist2")
+    psi = ctx.stream_function(xd, zd, ad)
+    err = metrics.rel_l2_scalar(psi.cpu().numpy()[sub], ref, a[sub])
+    ms, near_ms, ph = _timed(ctx, lambda: ctx.stream_function(xd, zd, ad, out=psi), args.steps, args.warmup)
+    cnt, ev = ctx.list_counts()
+    log(f"{ms:.3f} ms per stream-function evaluation, E = {err:.3e} vs the FP64 direct sum (4096 targets)")
+    ctx.close()
+    near = dict(near_roofline(ev["PP"] + ev["PC"], near_ms, args.precision))
+    flops = LOG_FLOPS
+    near["achieved"] = round((ev["PP"] + ev["PC"]) * flops / (near_ms / 1e3) / 1e12, 3)
+    near["frac"] = round(near["achieved"] / PEAK_VALU_TFLOPS, 4)
+    near["flops_per_eval"] = flops
+    result = dict(
+        metric="particle stream-function evals/s at N=655362 (logarithmic kernel through the tree)",
+        value=n / (ms / 1e3), unit="stream-function evals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32" if args.precision == "fp32" else "f64", data="synthetic",
+        config=dict(workload="gv_l8 (Gaussian vortex, icosahedral level 8), stream function", N=n, theta=args.theta,
+                    degree=args.degree, n_crit=args.n_crit, precision=args.precision, denominator="dist2",
+                    rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), lists=cnt, phase_ms=ph),
+        roofline=near,
+    )
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,7 +524,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4", "ssw"])
+    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4", "ssw", "stream"])
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -497,6 +543,9 @@ def main():
         return
     if args.workload == "ssw":
         bench_ssw(args)
+        return
+    if args.workload == "stream":
+        bench_stream(args)
         return
 
     import torch

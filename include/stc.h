@@ -220,6 +220,26 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
                       const double* d_area, int64_t m, const int64_t* d_targets,
                       int32_t precision, int32_t denominator, double* d_u);
 
+/* Stream function (Sec. 2, stream function and Green's function):
+ *   psi_i = (1/4pi) sum_{j != i} zeta_j A_j log(den(x_i, x_j)),
+ * den = 1 - x.y or |x - y|^2 / 2 per the context's denominator, through the
+ * same tree, proxy charges and lists as the velocity (the method is kernel
+ * independent, Sec. 3) with the logarithmic kernel in the PP / PC / CP / CC
+ * interactions.  The sign is the one for which Delta psi = zeta (for
+ * zero-mean zeta) and u = x x grad psi is the velocity of stc_velocity.
+ * d_psi: n FP64 values, input order.  The forcing, if set, applies to the
+ * charges as for the velocity.  STC_ERR_INVALID_ARG for a learned context
+ * (its gating network judges velocity interactions) and for bad sizes or
+ * pointers, as stc_velocity. */
+stc_status stc_stream_function(stc_ctx* ctx, int64_t n, const double* d_x, const double* d_zeta,
+                               const double* d_area, double* d_psi);
+
+/* Direct O(N m) stream function at m targets, arguments as stc_direct; d_psi
+ * holds m FP64 values. */
+stc_status stc_direct_stream(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
+                             const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
+                             int32_t denominator, double* d_psi);
+
 /* Classical RK4 (Sec. 4) for n_steps steps of dt on (x, zeta):
  *   dx/dt = u(x; zeta A),  dzeta/dt = -2 omega u_z  (Sec. 2, discrete system)
  * Every stage is a full stc_velocity (tree rebuilt).  Stage positions are

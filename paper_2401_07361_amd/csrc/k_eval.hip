@@ -73,17 +73,43 @@ __device__ __forceinline__ float fma_t<float>(float a, float b, float c) {
     return __builtin_fmaf(a, b, c);
 }
 
-// one kernel evaluation: q (y - x) / den added to (px, py, pz)
+// Stream-function kernels (Sec. 2, stream function and Green's function):
+// kernel codes beside the two velocity denominators.  Their interaction adds
+// q log(den) to the first component only (den = 1 - x.y, or |x - y|^2 / 2
+// with the factor 1/2 applied here: the charges are not scaled), and the
+// result is psi = W_0 / 4 pi.
+constexpr int DEN_LOG_DOT = 2, DEN_LOG_DIST2 = 3;
+
+template <typename T>
+__device__ __forceinline__ T log_t(T v);
+template <>
+__device__ __forceinline__ float log_t<float>(float v) {
+    return logf(v);
+}
+template <>
+__device__ __forceinline__ double log_t<double>(double v) {
+    return log(v);
+}
+
+// one kernel evaluation: q (y - x) / den added to (px, py, pz), or, for the
+// stream function, q log(den) added to px
 template <typename T, int DEN>
 __device__ __forceinline__ void interact(const Src<T>& s, T tx, T ty, T tz, T& px, T& py, T& pz) {
     const T dx = s.x - tx, dy = s.y - ty, dz = s.z - tz;
-    T den;
-    if (DEN == STC_DEN_DIST2) den = dx * dx + dy * dy + dz * dz;  // charges carry the factor 2
-    else den = fma_t<T>(-tx, s.x, fma_t<T>(-ty, s.y, fma_t<T>(-tz, s.z, T(1))));  // 1 - x.y in three FMAs
-    const T w = s.q * rcp_t<T>(den);
-    px += w * dx;
-    py += w * dy;
-    pz += w * dz;
+    if constexpr (DEN >= DEN_LOG_DOT) {
+        T den;
+        if constexpr (DEN == DEN_LOG_DIST2) den = T(0.5) * (dx * dx + dy * dy + dz * dz);
+        else den = fma_t<T>(-tx, s.x, fma_t<T>(-ty, s.y, fma_t<T>(-tz, s.z, T(1))));
+        px += s.q * log_t<T>(den);
+    } else {
+        T den;
+        if (DEN == STC_DEN_DIST2) den = dx * dx + dy * dy + dz * dz;  // charges carry the factor 2
+        else den = fma_t<T>(-tx, s.x, fma_t<T>(-ty, s.y, fma_t<T>(-tz, s.z, T(1))));  // 1 - x.y in three FMAs
+        const T w = s.q * rcp_t<T>(den);
+        px += w * dx;
+        py += w * dy;
+        pz += w * dz;
+    }
 }
 
 // Four FP64 kernel evaluations with one reciprocal: v_rcp_f64 issues at a
@@ -98,6 +124,11 @@ __device__ __forceinline__ void interact(const Src<T>& s, T tx, T ty, T tz, T& p
 template <int DEN>
 __device__ __forceinline__ void interact4(const Src<double>* __restrict__ s, double tx, double ty, double tz,
                                           double& px, double& py, double& pz) {
+    if constexpr (DEN >= DEN_LOG_DOT) {  // no reciprocal to share
+#pragma unroll
+        for (int k = 0; k < 4; ++k) interact<double, DEN>(s[k], tx, ty, tz, px, py, pz);
+        return;
+    }
     double dx[4], dy[4], dz[4], den[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -620,6 +651,13 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
         }
     }
     if (!valid) return;
+    if (a.stream) {  // psi = W_0 / 4 pi, one value per particle
+        const double p = kInv4Pi * W0;
+        const i64 o = (i64)a.perm[i];
+        if (accumulate) u[o] += p;
+        else u[o] = p;
+        return;
+    }
     // u = -(1/4pi) x x W
     const double u0 = -kInv4Pi * (x1 * W2 - x2 * W1);
     const double u1 = -kInv4Pi * (x2 * W0 - x0 * W2);
@@ -726,6 +764,8 @@ __global__ __launch_bounds__(256) void k_direct(i64 n, const double* __restrict_
                 p[0] = W0;
                 p[1] = W1;
                 p[2] = W2;
+            } else if constexpr (DEN >= DEN_LOG_DOT) {
+                u[ti[k]] = kInv4Pi * W0;
             } else {
                 const double xg0 = x[3 * gi[k]], xg1 = x[3 * gi[k] + 1], xg2 = x[3 * gi[k] + 2];
                 u[3 * ti[k] + 0] = -kInv4Pi * (xg1 * W2 - xg2 * W1);
@@ -739,7 +779,8 @@ __global__ __launch_bounds__(256) void k_direct(i64 n, const double* __restrict_
 // sum of the chunks' W in chunk order (deterministic), then the cross product
 __global__ __launch_bounds__(256) void k_direct_reduce(const double* __restrict__ x, i64 m,
                                                        const i64* __restrict__ targets, u32 chunks,
-                                                       const double* __restrict__ part, double* __restrict__ u) {
+                                                       const double* __restrict__ part, int stream,
+                                                       double* __restrict__ u) {
     const i64 ti = (i64)blockIdx.x * 256 + threadIdx.x;
     if (ti >= m) return;
     const i64 gi = targets ? targets[ti] : ti;
@@ -749,6 +790,10 @@ __global__ __launch_bounds__(256) void k_direct_reduce(const double* __restrict_
         W0 += p[0];
         W1 += p[1];
         W2 += p[2];
+    }
+    if (stream) {
+        u[ti] = kInv4Pi * W0;
+        return;
     }
     const double xg0 = x[3 * gi], xg1 = x[3 * gi + 1], xg2 = x[3 * gi + 2];
     u[3 * ti + 0] = -kInv4Pi * (xg1 * W2 - xg2 * W1);
@@ -762,6 +807,13 @@ namespace {
 template <int NTT>
 void near_shape(hipStream_t s, const EvalArgs& a, u32 type_mask) {
     const dim3 g(a.near_grid), b(NTT);
+    if (a.stream) {
+        if (a.precision == STC_FP32) hipLaunchKernelGGL((k_near<float, DEN_LOG_DIST2, NTT>), g, b, 0, s, a, type_mask);
+        else if (a.denominator == STC_DEN_DIST2)
+            hipLaunchKernelGGL((k_near<double, DEN_LOG_DIST2, NTT>), g, b, 0, s, a, type_mask);
+        else hipLaunchKernelGGL((k_near<double, DEN_LOG_DOT, NTT>), g, b, 0, s, a, type_mask);
+        return;
+    }
     if (a.precision == STC_FP32) hipLaunchKernelGGL((k_near<float, STC_DEN_DIST2, NTT>), g, b, 0, s, a, type_mask);
     else if (a.denominator == STC_DEN_DIST2)
         hipLaunchKernelGGL((k_near<double, STC_DEN_DIST2, NTT>), g, b, 0, s, a, type_mask);
@@ -771,6 +823,13 @@ void near_shape(hipStream_t s, const EvalArgs& a, u32 type_mask) {
 template <int NTT>
 void far_shape(hipStream_t s, const EvalArgs& a) {
     const dim3 g(a.far_grid), b(NTT);
+    if (a.stream) {
+        if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, DEN_LOG_DIST2, NTT>), g, b, 0, s, a);
+        else if (a.denominator == STC_DEN_DIST2)
+            hipLaunchKernelGGL((k_far_targets<double, DEN_LOG_DIST2, NTT>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_far_targets<double, DEN_LOG_DOT, NTT>), g, b, 0, s, a);
+        return;
+    }
     if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NTT>), g, b, 0, s, a);
     else if (a.denominator == STC_DEN_DIST2)
         hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2, NTT>), g, b, 0, s, a);
@@ -858,14 +917,23 @@ void direct_split(i64 n, i64 m, int cus, int blocks_per_cu, int targets_per_bloc
 
 void launch_direct(hipStream_t s, i64 n, const double* x, const double* zeta, const double* area, i64 m,
                    const i64* targets, int precision, int denominator, u32 chunks, i64 chunk_len, double* part,
-                   double* u) {
+                   double* u, int stream) {
     if (m <= 0) return;
     const int tpb = direct_targets_per_block(precision);
     const u32 tblocks = (u32)((m + tpb - 1) / tpb);
     if (!part) chunks = 1, chunk_len = n;
     double* pp = chunks > 1 ? part : nullptr;
     const dim3 g(tblocks * chunks), b(256);
-    if (precision == STC_FP32)
+    if (stream && precision == STC_FP32)
+        hipLaunchKernelGGL((k_direct<float, DEN_LOG_DIST2, DIRECT_TP32>), g, b, 0, s, n, x, zeta, area, m, targets,
+                           chunk_len, tblocks, u, pp);
+    else if (stream && denominator == STC_DEN_DIST2)
+        hipLaunchKernelGGL((k_direct<double, DEN_LOG_DIST2, DIRECT_TP64>), g, b, 0, s, n, x, zeta, area, m, targets,
+                           chunk_len, tblocks, u, pp);
+    else if (stream)
+        hipLaunchKernelGGL((k_direct<double, DEN_LOG_DOT, DIRECT_TP64>), g, b, 0, s, n, x, zeta, area, m, targets,
+                           chunk_len, tblocks, u, pp);
+    else if (precision == STC_FP32)
         hipLaunchKernelGGL((k_direct<float, STC_DEN_DIST2, DIRECT_TP32>), g, b, 0, s, n, x, zeta, area, m, targets, chunk_len,
                            tblocks, u, pp);
     else if (denominator == STC_DEN_DIST2)
@@ -876,7 +944,7 @@ void launch_direct(hipStream_t s, i64 n, const double* x, const double* zeta, co
                            tblocks, u, pp);
     if (pp)
         hipLaunchKernelGGL(k_direct_reduce, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, x, m, targets, chunks,
-                           pp, u);
+                           pp, stream, u);
 }
 
 }  // namespace stc

@@ -138,6 +138,7 @@ struct EvalArgs {
     int NB, LB;          // node id bits per member, leaf key bits per member
     // launch shapes of the persistent segment kernels
     int near_threads, near_grid, far_threads, far_grid;
+    int stream;          // 1: the stream function's logarithmic kernel, output psi (n values)
 };
 
 void launch_near(hipStream_t s, const EvalArgs& a, u32 type_mask);
@@ -148,7 +149,7 @@ int direct_targets_per_block(int precision);
 void direct_split(i64 n, i64 m, int cus, int blocks_per_cu, int targets_per_block, u32* chunks, i64* chunk_len);
 void launch_direct(hipStream_t s, i64 n, const double* x, const double* zeta, const double* area, i64 m,
                    const i64* targets, int precision, int denominator, u32 chunks, i64 chunk_len, double* part,
-                   double* u);
+                   double* u, int stream);
 
 // k_mlp.hip -- the learned form's network (12 -> 64 -> 64 -> 4, BF16 on the matrix cores)
 int mlp_param_count();

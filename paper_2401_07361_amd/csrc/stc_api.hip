@@ -469,10 +469,11 @@ stc_status do_traverse(stc_ctx* c) {
     return check_launch(c, "traverse");
 }
 
-stc_status do_eval(stc_ctx* c, bool near, bool far, double* d_u, bool accumulate) {
+stc_status do_eval(stc_ctx* c, bool near, bool far, double* d_u, bool accumulate, bool stream = false) {
     if (c->n == 0) return STC_OK;
     hipStream_t s = c->stream;
     EvalArgs a = eval_args(c);
+    a.stream = stream ? 1 : 0;
     launch_fill_f64(s, c->Wacc, 3 * c->n, 0.0);
     u32 mask = (near ? 1u : 0u) | (far ? 2u : 0u);
     mark(c, 3);
@@ -841,8 +842,9 @@ stc_status stc_velocity_batched(stc_ctx* c, int32_t members, const int64_t* h_of
     return st;
 }
 
-stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
-                      int64_t m, const int64_t* d_targets, int32_t precision, int32_t denominator, double* d_u) {
+static stc_status direct_sum(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
+                             const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
+                             int32_t denominator, double* d_u, bool stream) {
     if (n < 0 || m < 0 || n >= 0x7fffffffLL) return STC_ERR_INVALID_ARG;
     if (precision != STC_FP64 && precision != STC_FP32) return STC_ERR_INVALID_ARG;
     if (denominator != STC_DEN_DOT && denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
@@ -871,10 +873,38 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
         (void)hipGetLastError();
         part = nullptr;
     }
-    launch_direct(s, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, chunks, chunk_len, part, d_u);
+    launch_direct(s, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, chunks, chunk_len, part, d_u,
+                  stream ? 1 : 0);
     const hipError_t le = hipGetLastError();
     if (part && hipFreeAsync(part, s) != hipSuccess) return STC_ERR_DEVICE;
     return le == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
+stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
+                      int64_t m, const int64_t* d_targets, int32_t precision, int32_t denominator, double* d_u) {
+    return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_u, false);
+}
+
+stc_status stc_direct_stream(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
+                             const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
+                             int32_t denominator, double* d_psi) {
+    return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_psi, true);
+}
+
+stc_status stc_stream_function(stc_ctx* c, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
+                               double* d_psi) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (c->learned) return fail(c, STC_ERR_INVALID_ARG, "the learned form gates velocity interactions only");
+    if (n < 0 || n > c->n_max) return fail(c, STC_ERR_INVALID_ARG, "n out of range [0, n_max]");
+    if (n > 0 && (!d_x || !d_zeta || !d_area || !d_psi || !aligned8(d_x) || !aligned8(d_zeta) ||
+                  !aligned8(d_area) || !aligned8(d_psi)))
+        return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
+    const i64 off[2] = {0, n};
+    stc_status st = do_build(c, 1, off, d_x);
+    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
+    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_eval(c, true, true, d_psi, false, true);
+    return st;
 }
 
 // Enqueues one RK4 step of every member on c->stream (no host

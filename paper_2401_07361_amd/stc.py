@@ -101,6 +101,8 @@ def _load():
         "stc_velocity": (I32, [P, I64, VP, VP, VP, VP]),
         "stc_direct": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
         "stc_rk4": (I32, [P, I64, VP, VP, VP, D, D, I32]),
+        "stc_stream_function": (I32, [P, I64, VP, VP, VP, VP]),
+        "stc_direct_stream": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
         "stc_set_forcing": (I32, [P, ctypes.POINTER(Forcing)]),
         "stc_get_forcing": (I32, [P, ctypes.POINTER(Forcing), PI32]),
         "stc_forcing_field": (I32, [VP, ctypes.POINTER(Forcing), I64, VP, VP]),
@@ -224,6 +226,21 @@ def direct(x, zeta, area, targets=None, precision="fp64", denominator="dot", out
                          _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n), m,
                          _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
                          _dptr(out, "out", torch.float64, 3 * m))
+    _check(st)
+    return out
+
+
+def direct_stream(x, zeta, area, targets=None, precision="fp64", denominator="dot", out=None, stream=None):
+    """Direct O(N^2) stream function at `targets` (int64 CUDA tensor, or None = all)."""
+    import torch
+    n = x.shape[0]
+    m = n if targets is None else targets.numel()
+    if out is None:
+        out = torch.empty((m,), dtype=torch.float64, device=x.device)
+    st = _lib.stc_direct_stream(_stream(stream), n, _dptr(x, "x", torch.float64, 3 * n),
+                                _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n), m,
+                                _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
+                                _dptr(out, "out", torch.float64, m))
     _check(st)
     return out
 
@@ -409,6 +426,20 @@ class Context:
             out = torch.empty((n, 3), dtype=torch.float64, device=x.device)
         st = _lib.stc_velocity(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n), _dptr(zeta, "zeta", torch.float64, n),
                                _dptr(area, "area", torch.float64, n), _dptr(out, "out", torch.float64, 3 * n))
+        _check(st, self._ctx)
+        self._keep = x
+        self.n = n
+        return out
+
+    def stream_function(self, x, zeta, area, out=None):
+        """psi_i = (1/4pi) sum_{j != i} q_j log(den(x_i, x_j)) through the tree (n values)."""
+        import torch
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((n,), dtype=torch.float64, device=x.device)
+        st = _lib.stc_stream_function(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n),
+                                      _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n),
+                                      _dptr(out, "out", torch.float64, n))
         _check(st, self._ctx)
         self._keep = x
         self.n = n
