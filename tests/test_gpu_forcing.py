@@ -120,3 +120,30 @@ def test_forcing_field_matches_oracle(stc_lib, k):
         scale = 0.6 * OM * max(k, 1) ** 2
         assert np.abs(got - want).max() <= 1e-13 * scale, t
         assert got[-4] == 0.0 and got[-3] == 0.0 and got[-2] == 0.0
+
+
+def test_forced_rk4_batched_bitwise_equal_single(stc_lib):
+    """The forcing acts on every member of an ensemble: forced batched steps
+    equal forced steps of each member alone, bitwise, and the clock advances
+    once per step."""
+    ens = S.make_ensemble(members=3, seed0=4, levels=(4, 5))
+    off = ens["offsets"]
+    kw = dict(theta=0.7, degree=6, n_crit=32, precision="fp32", denominator="dist2")
+    t0, dt, steps = 3.95, 0.02, 3
+    say(f"forced rk4 batch N={off[-1]}")
+    cb = stc_lib.Context(int(off[-1]), members=len(off) - 1, n_max_member=int(np.diff(off).max()), **kw)
+    cb.set_forcing(1, OM, LAT1, TP, TF, time=t0)
+    xb, zb, ab = dev(ens["x"]), dev(ens["zeta"]), dev(ens["area"])
+    cb.rk4_batched(xb, zb, ab, off, dt, OM, steps)
+    cb.sync()
+    assert cb.forcing()[1]["time"] == pytest.approx(t0 + steps * dt, abs=1e-12)
+    for m in range(len(off) - 1):
+        sl = slice(off[m], off[m + 1])
+        cs = stc_lib.Context(int(off[m + 1] - off[m]), max_level=cb.max_level, **kw)
+        cs.set_forcing(1, OM, LAT1, TP, TF, time=t0)
+        xs, zs = dev(ens["x"][sl]), dev(ens["zeta"][sl])
+        cs.rk4(xs, zs, dev(ens["area"][sl]), dt, OM, steps)
+        cs.sync()
+        assert torch.equal(xb[sl], xs) and torch.equal(zb[sl], zs), m
+        cs.close()
+    cb.close()

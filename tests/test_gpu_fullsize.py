@@ -85,3 +85,55 @@ def test_fp32_and_fp64_trees_differ_by_rounding_only(stc_lib):
     # and the FP64 tree against the GPU FP64 direct sum on the 4096 targets
     ud = stc_lib.direct(xd, zd, ad, targets=torch.from_numpy(sub).cuda()).cpu().numpy()
     assert metrics.rel_l2_velocity(u64[sub], ud, a[sub]) < 1e-6
+
+
+def test_stream_function_at_full_size(stc_lib):
+    """The stream function in the benchmark's setting at N = 655362: sampled
+    targets against the oracle's direct stream function, and the GPU's FP64
+    direct stream function on 48 targets against the same oracle values."""
+    import bench
+    wl = S.make_workload("gv_l8")
+    x, z, a = wl["x"], wl["zeta"], wl["area"]
+    n = len(x)
+    say(f"full size stream function N={n}")
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    ctx = stc_lib.Context(n, theta=bench.BENCH_THETA, degree=bench.BENCH_DEGREE, n_crit=bench.BENCH_N_CRIT,
+                          precision="fp32", denominator="dist2")
+    psi = ctx.stream_function(xd, zd, ad).cpu().numpy()
+    ctx.sync()
+    ctx.close()
+    idx = S.subset_indices(n, 48, 18)
+    ref = odirect.stream_function(x, z, a, targets=idx, den="dist2")
+    err = metrics.rel_l2_scalar(psi[idx], ref, a[idx])
+    say(f"  E on 48 sampled targets vs oracle direct = {err:.3e}")
+    assert err <= 1e-6
+    dd = stc_lib.direct_stream(xd, zd, ad, targets=torch.from_numpy(idx.astype(np.int64)).cuda(),
+                               denominator="dist2").cpu().numpy()
+    assert np.abs(dd - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_forced_velocity_at_full_size(stc_lib):
+    """The forced polar vortex at the paper's setting (N = 163842, d = 6,
+    theta = 0.7) at full forcing, FP64 and FP32, on sampled targets against
+    the oracle's direct sum of zeta - F_R (the oracle's own forcing)."""
+    from oracle import forcing as oforce
+    wl = S.make_workload("ssw_l7")
+    x, z, a = wl["x"], wl["zeta"], wl["area"]
+    n, fc, t = len(x), wl["forcing"], 8.0
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    idx = S.subset_indices(n, 48, 19)
+    zf = oforce.forced_zeta(x, z, t, fc["k"], wl["omega"], fc["lat1"], fc["t_ramp"], fc["t_total"])
+    ref = odirect.velocity(x, zf, a, targets=idx, den="dist2")
+    for prec in ("fp64", "fp32"):
+        say(f"full size forced velocity N={n} {prec}")
+        ctx = stc_lib.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision=prec,
+                              denominator="dist2")
+        ctx.set_forcing(fc["k"], wl["omega"], fc["lat1"], fc["t_ramp"], fc["t_total"], time=t)
+        u = ctx.velocity(xd, zd, ad).cpu().numpy()
+        ctx.sync()
+        ctx.close()
+        err = metrics.rel_l2_velocity(u[idx], ref, a[idx])
+        say(f"  E on 48 sampled targets vs oracle direct = {err:.3e}")
+        # d = 6 at theta = 0.7 is the paper's setting, not one tuned to 1e-6:
+        # the benchmark measures E = 5.3e-5 on 4096 targets
+        assert err <= 2e-4
