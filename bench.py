@@ -24,7 +24,8 @@ times graph-captured RK4 steps of the whole ensemble.
 ``--workload rk4`` times graph-captured RK4 steps of the Rossby-Haurwitz wave
 at N = 163842; ``--workload ssw`` those of the forced polar-vortex collapse
 (Sec. 5) at N = 163842, d = 6, theta = 0.7; ``--workload stream`` the stream
-function (logarithmic kernel) on the headline workload and setting.
+function (logarithmic kernel) on the headline workload and setting;
+``--workload plain`` the plain FP64 method (theta 0.7, d 8) at N = 10242.
 """
 
 import argparse
@@ -468,6 +469,46 @@ def bench_ssw(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_plain(args):
+    """The plain method as the paper runs it: FP64 with the 1 - x.y
+    denominator, theta 0.7, d 8, on the level-5 grid (N = 10242) with the
+    Rossby-Haurwitz wave n = 4; accuracy against the FP64 direct sum at every
+    particle."""
+    import torch
+    import synthetic as S
+    from paper_2401_07361_amd import stc
+    from oracle import metrics
+
+    wl = S.make_workload("rh4_l5")
+    x, z, a = wl["x"], wl["zeta"], wl["area"]
+    n = len(x)
+    log(f"workload rh4_l5 N={n} theta={wl['theta']} d={wl['degree']} fp64 1 - x.y")
+    xd, zd, ad = (torch.from_numpy(v).cuda() for v in (x, z, a))
+    ud = stc.direct(xd, zd, ad).cpu().numpy()
+    ctx = stc.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision="fp64", denominator="dot")
+    u = ctx.velocity(xd, zd, ad)
+    err = metrics.rel_l2_velocity(u.cpu().numpy(), ud, a)
+    ms, near_ms, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
+    cnt, ev = ctx.list_counts()
+    ctx.close()
+    log(f"{ms:.3f} ms per evaluation, E = {err:.3e} vs the FP64 direct sum (all {n} particles)")
+    result = dict(
+        metric="particle velocity evals/s at N=10242 (plain FP64 method, theta 0.7, d 8)",
+        value=n / (ms / 1e3), unit="velocity evals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+        data="synthetic",
+        config=dict(workload="rh4_l5 (Rossby-Haurwitz n=4, icosahedral level 5, A = 4 pi / N)", N=n,
+                    theta=wl["theta"], degree=wl["degree"], n_crit=64, precision="fp64", denominator="dot",
+                    rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), lists=cnt, phase_ms=ph),
+        roofline=near_roofline(ev["PP"] + ev["PC"], near_ms, "fp64"),
+    )
+    if not args.no_cpu:
+        log("cpu baseline (oracle direct sum, bounded target sample)")
+        cb, _, _ = cpu_baseline(x, z, a, np.arange(n), budget_s=8.0, den="dot", what="all particles")
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
 LOG_FLOPS = 12  # per stream-function evaluation: 3 sub, |d|^2 5, x1/2 1, log 1 (counted as one), q*log + add 2
 
 
@@ -524,7 +565,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4", "ssw", "stream"])
+    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4", "ssw", "stream", "plain"])
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -546,6 +587,9 @@ def main():
         return
     if args.workload == "stream":
         bench_stream(args)
+        return
+    if args.workload == "plain":
+        bench_plain(args)
         return
 
     import torch
