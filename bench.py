@@ -90,17 +90,19 @@ _G = {}
 
 def _oracle_worker(idx):
     from oracle import direct
-    return direct.velocity(_G["x"], _G["z"], _G["a"], targets=idx, den=_G["den"])
+    fn = direct.stream_function if _G["stream"] else direct.velocity
+    return fn(_G["x"], _G["z"], _G["a"], targets=idx, den=_G["den"])
 
 
-def cpu_baseline(x, z, a, subset, budget_s=15.0, den="dot", what="the 4096 seeded targets"):
+def cpu_baseline(x, z, a, subset, budget_s=15.0, den="dot", what="the 4096 seeded targets", stream=False):
     """The oracle's direct sum (O(N) per target) timed on the host cores over a
-    bounded sample of the target subset."""
+    bounded sample of the target subset (the stream function's with stream)."""
     from oracle import direct
     cores = min(len(os.sched_getaffinity(0)), 16)
-    _G.update(x=x, z=z, a=a, den=den)
+    _G.update(x=x, z=z, a=a, den=den, stream=stream)
+    fn = direct.stream_function if stream else direct.velocity
     t0 = time.perf_counter()
-    probe = direct.velocity(x, z, a, targets=subset[:8], den=den)
+    probe = fn(x, z, a, targets=subset[:8], den=den)
     per_target = (time.perf_counter() - t0) / 8
     m = int(min(len(subset), max(cores * 8, budget_s * cores / per_target)))
     m = max(8, (m // cores) * cores) if m >= cores else m
@@ -113,7 +115,8 @@ def cpu_baseline(x, z, a, subset, budget_s=15.0, den="dot", what="the 4096 seede
     dt = time.perf_counter() - t0
     u = np.concatenate(parts)
     return dict(value=m / dt, unit="velocity evals/s", cores=cores, kind="oracle",
-                sample=f"{m} of {what}, all {len(x)} sources, FP64 direct sum, "
+                sample=f"{m} of {what}, all {len(x)} sources, FP64 direct "
+                       f"{'stream function' if stream else 'sum'}, "
                        f"{dt:.1f} s wall"), sample, u
 
 
@@ -366,6 +369,8 @@ def bench_rk4(args):
     for prec in ("fp32", "fp64"):
         ctx = stc.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision=prec, denominator="dist2")
         u = ctx.velocity(xd, zd, ad)
+        shape = ctx.autotune(repeats=5)  # launch shape for this size, used by the evaluations below
+        log(f"{prec}: autotuned launch shape {shape}")
         err = metrics.rel_l2_velocity(u.cpu().numpy()[sub], ud, a[sub])
         ms_eval, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
@@ -379,7 +384,7 @@ def bench_rk4(args):
         torch.cuda.synchronize()
         ctx.sync()
         ms_step = t0.elapsed_time(t1) / args.steps
-        runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4),
+        runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4), launch_shape=shape,
                           rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), phase_ms=ph,
                           near=(ev["PP"] + ev["PC"], near_ms_t))
         log(f"{prec}: {ms_step:.3f} ms per RK4 step (graph), {ms_eval:.3f} ms per evaluation, E = {err:.3e}")
@@ -428,6 +433,8 @@ def bench_ssw(args):
         ctx = stc.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision=prec, denominator="dist2")
         ctx.set_forcing(*fargs, time=t_check)
         u = ctx.velocity(xd, zd, ad)
+        shape = ctx.autotune(repeats=5)  # launch shape for this size, used by the evaluations below
+        log(f"{prec}: autotuned launch shape {shape}")
         err = metrics.rel_l2_velocity(u.cpu().numpy()[sub], ud, a[sub])
         ms_eval, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
@@ -443,7 +450,7 @@ def bench_ssw(args):
         ctx.sync()
         ms_step = t0.elapsed_time(t1) / args.steps
         t_end = ctx.forcing()[1]["time"]
-        runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4),
+        runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4), launch_shape=shape,
                           rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), phase_ms=ph, forcing_time_after=t_end,
                           near=(ev["PP"] + ev["PC"], near_ms_t))
         log(f"{prec}: {ms_step:.3f} ms per forced RK4 step (graph), {ms_eval:.3f} ms per evaluation, E = {err:.3e}")
@@ -551,6 +558,11 @@ def bench_stream(args):
                     rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), lists=cnt, phase_ms=ph),
         roofline=near,
     )
+    if not args.no_cpu:
+        log("cpu baseline (oracle direct stream function, bounded target sample)")
+        cb, _, _ = cpu_baseline(x, z, a, sub, budget_s=10.0, den="dist2", stream=True)
+        cb["unit"] = "stream-function evals/s"
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
 
@@ -566,6 +578,8 @@ def main():
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4", "ssw", "stream", "plain"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="gv_l8: pick the interaction kernels' launch shape with the library's autotuner first")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -617,6 +631,8 @@ def main():
     for _ in range(args.warmup):
         ctx.velocity(xd, zd, ad, out=out)
     ctx.sync()
+    if args.autotune:
+        log(f"autotuned launch shape {ctx.autotune(repeats=5)}")
     log("warmup done")
 
     ms, near_ms, phase_ms = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, 0)
