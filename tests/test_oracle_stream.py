@@ -1,6 +1,5 @@
 """Pins for the oracle's stream function (Sec. 2, stream function and Green's
-function; the scope table's second "next" row): 50-digit brute force on tiny
-sets, the closed-form Rossby-Haurwitz stream function, u = x x grad(psi)
+function): 50-digit brute force on tiny sets, the closed-form Rossby-Haurwitz stream function, u = x x grad(psi)
 against the (separately pinned) Biot-Savart velocity, and the tree code's
 reduction to the direct sum."""
 
