@@ -497,6 +497,8 @@ def bench_plain(args):
     err = metrics.rel_l2_velocity(u.cpu().numpy(), ud, a)
     ms, near_ms, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
     cnt, ev = ctx.list_counts()
+    ug = u.cpu().numpy()
+    ctx_level = ctx.max_level
     ctx.close()
     log(f"{ms:.3f} ms per evaluation, E = {err:.3e} vs the FP64 direct sum (all {n} particles)")
     result = dict(
@@ -512,6 +514,13 @@ def bench_plain(args):
     if not args.no_cpu:
         log("cpu baseline (oracle direct sum, bounded target sample)")
         cb, _, _ = cpu_baseline(x, z, a, np.arange(n), budget_s=8.0, den="dot", what="all particles")
+        # the oracle's tree code (one process) on the same input and setting
+        from oracle import tree as otree
+        t0 = time.perf_counter()
+        ut = otree.velocity(x, z, a, theta=wl["theta"], degree=wl["degree"], n_crit=64, max_level=int(ctx_level))
+        dt_tree = time.perf_counter() - t0
+        cb["oracle_tree"] = dict(value=n / dt_tree, unit="velocity evals/s", cores=1, seconds=round(dt_tree, 2),
+                                 max_rel_diff_gpu_vs_oracle_tree=float(f"{np.abs(ug - ut).max() / np.abs(ut).max():.3e}"))
         result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
