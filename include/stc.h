@@ -234,6 +234,13 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
 stc_status stc_stream_function(stc_ctx* ctx, int64_t n, const double* d_x, const double* d_zeta,
                                const double* d_area, double* d_psi);
 
+/* The stream function of every member of an ensemble in the same launches,
+ * members as for stc_velocity_batched; d_psi: n_total values.  Each member's
+ * values are bitwise those of a single-member context. */
+stc_status stc_stream_function_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offsets,
+                                       const double* d_x, const double* d_zeta, const double* d_area,
+                                       double* d_psi);
+
 /* Direct O(N m) stream function at m targets, arguments as stc_direct; d_psi
  * holds m FP64 values. */
 stc_status stc_direct_stream(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,

@@ -907,6 +907,22 @@ stc_status stc_stream_function(stc_ctx* c, int64_t n, const double* d_x, const d
     return st;
 }
 
+stc_status stc_stream_function_batched(stc_ctx* c, int32_t members, const int64_t* h_offsets, const double* d_x,
+                                       const double* d_zeta, const double* d_area, double* d_psi) {
+    if (!c) return STC_ERR_INVALID_ARG;
+    if (c->learned) return fail(c, STC_ERR_INVALID_ARG, "the learned form gates velocity interactions only");
+    const i64 n = check_offsets(c, members, h_offsets);
+    if (n < 0) return fail(c, STC_ERR_INVALID_ARG, "bad member count or offsets");
+    if (n > 0 && (!d_x || !d_zeta || !d_area || !d_psi || !aligned8(d_x) || !aligned8(d_zeta) ||
+                  !aligned8(d_area) || !aligned8(d_psi)))
+        return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
+    stc_status st = do_build(c, members, h_offsets, d_x);
+    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
+    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_eval(c, true, true, d_psi, false, true);
+    return st;
+}
+
 // Enqueues one RK4 step of every member on c->stream (no host
 // synchronisation, no memsets).
 static stc_status rk4_enqueue_step(stc_ctx* c, int members, const i64* off, double* d_x, double* d_zeta,

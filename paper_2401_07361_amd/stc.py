@@ -102,6 +102,7 @@ def _load():
         "stc_direct": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
         "stc_rk4": (I32, [P, I64, VP, VP, VP, D, D, I32]),
         "stc_stream_function": (I32, [P, I64, VP, VP, VP, VP]),
+        "stc_stream_function_batched": (I32, [P, I32, PI64, VP, VP, VP, VP]),
         "stc_direct_stream": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
         "stc_set_forcing": (I32, [P, ctypes.POINTER(Forcing)]),
         "stc_get_forcing": (I32, [P, ctypes.POINTER(Forcing), PI32]),
@@ -440,6 +441,21 @@ class Context:
         st = _lib.stc_stream_function(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n),
                                       _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n),
                                       _dptr(out, "out", torch.float64, n))
+        _check(st, self._ctx)
+        self._keep = x
+        self.n = n
+        return out
+
+    def stream_function_batched(self, x, zeta, area, offsets, out=None):
+        """The stream function of every member (offsets as for velocity_batched)."""
+        import torch
+        n = x.shape[0]
+        off, m, poff = _offsets(offsets, n)
+        if out is None:
+            out = torch.empty((n,), dtype=torch.float64, device=x.device)
+        st = _lib.stc_stream_function_batched(self._ctx, m, poff, _dptr(x, "x", torch.float64, 3 * n),
+                                              _dptr(zeta, "zeta", torch.float64, n),
+                                              _dptr(area, "area", torch.float64, n), _dptr(out, "out", torch.float64, n))
         _check(st, self._ctx)
         self._keep = x
         self.n = n

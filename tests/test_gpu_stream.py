@@ -98,3 +98,23 @@ def test_tree_stream_fp32_and_accuracy_against_direct(stc_lib):
     assert np.abs(p32 - p64).max() <= 1e-5 * scale
     c64.close()
     c32.close()
+
+
+@pytest.mark.parametrize("precision,den", [("fp64", "dot"), ("fp32", "dist2")])
+def test_stream_function_batched_bitwise_equal_single(stc_lib, precision, den):
+    """Ensembles: every member's stream function equals a single-member
+    context's, bitwise; members of a few sizes and rotations."""
+    ens = S.make_ensemble(members=4, seed0=4, levels=(3, 4, 5))
+    off = ens["offsets"]
+    kw = dict(theta=0.7, degree=6, n_crit=32, precision=precision, denominator=den)
+    say(f"batched stream function {len(off) - 1} members N={off[-1]} {precision} {den}")
+    cb = stc_lib.Context(int(off[-1]), members=len(off) - 1, n_max_member=int(np.diff(off).max()), **kw)
+    psi = cb.stream_function_batched(dev(ens["x"]), dev(ens["zeta"]), dev(ens["area"]), off)
+    cb.sync()
+    for m in range(len(off) - 1):
+        sl = slice(off[m], off[m + 1])
+        cs = stc_lib.Context(int(off[m + 1] - off[m]), max_level=cb.max_level, **kw)
+        ps = cs.stream_function(dev(ens["x"][sl]), dev(ens["zeta"][sl]), dev(ens["area"][sl]))
+        assert torch.equal(psi[sl], ps), m
+        cs.close()
+    cb.close()
