@@ -310,9 +310,7 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     return check_launch(c, "tree_build");
 }
 
-// Charges at the forcing's host time, or (stage_clock) at the device clock
-// plus t_off: the RK4 stages, whose start time lives on the device so that a
-// captured step can be replayed.
+// Parameter ranges stc_set_forcing and stc_forcing_field accept.
 bool forcing_valid(const stc_forcing* f) {
     const double half_pi = 1.5707963267948966;
     return f->k >= 0 && f->k <= 16 && std::isfinite(f->omega) && f->lat1 > 0.0 && f->lat1 < half_pi &&
@@ -335,6 +333,9 @@ ForcingDev forcing_dev(const stc_forcing& h, double t_base, const double* t_dev)
     return f;
 }
 
+// Charges (forced at the forcing's host time, or with stage_clock at the
+// device clock plus t_off: the RK4 stages, whose start time lives on the
+// device so that a captured step can be replayed), then the proxy charges.
 stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area, bool stage_clock = false,
                      double t_off = 0.0) {
     hipStream_t s = c->stream;
