@@ -82,18 +82,29 @@ constexpr int DEN_LOG_DOT = 2, DEN_LOG_DIST2 = 3;
 
 template <typename T>
 __device__ __forceinline__ T log_t(T v);
-// FP32: the hardware base-2 logarithm (v_log_f32) times ln 2.  The
-// denominators here are normal numbers (|x - y|^2 / 2 between ~1e-6 and 2 in
-// target-relative coordinates), where the instruction is accurate to about
-// one ulp; the library logf adds range reduction and special-case handling
-// that cost about ten more instructions per evaluation.
+// FP32: the hardware base-2 logarithm (v_log_f32); the factor ln 2 that
+// turns it into the natural logarithm travels with the staged charges
+// (charge_scale).  The denominators here are normal numbers (|x - y|^2 / 2
+// between ~1e-6 and 2 in target-relative coordinates), where the instruction
+// is accurate to about one ulp; the library logf adds range reduction and
+// special-case handling that cost about ten more instructions per evaluation.
 template <>
 __device__ __forceinline__ float log_t<float>(float v) {
-    return __builtin_amdgcn_logf(v) * 0.693147180559945309f;
+    return __builtin_amdgcn_logf(v);
 }
 template <>
 __device__ __forceinline__ double log_t<double>(double v) {
     return log(v);
+}
+
+// Factor applied to every charge as it is staged: 2 for the velocity with
+// |x - y|^2 (the kernel drops the 1/2 of |x - y|^2 / 2), ln 2 for the FP32
+// logarithmic kernel (its logarithm is base 2), else 1.
+template <typename T, int DEN>
+__device__ __forceinline__ double charge_scale() {
+    if constexpr (DEN == STC_DEN_DIST2) return 2.0;
+    else if constexpr (DEN >= DEN_LOG_DOT && sizeof(T) == 4) return 0.693147180559945309;
+    else return 1.0;
 }
 
 // one kernel evaluation: q (y - x) / den added to (px, py, pz), or, for the
@@ -292,7 +303,7 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
     const int tid = threadIdx.x;
     const u64 mask = ((u64)1 << a.W) - 1;
     const u32 cmask = (1u << a.DB) - 1u;
-    const double qscale = (DEN == STC_DEN_DIST2) ? 2.0 : 1.0;
+    const double qscale = charge_scale<T, DEN>();
     for (u32 eb = e0; eb < e1; eb += NTT) {
         const u32 ne = (e1 - eb) < (u32)NTT ? (e1 - eb) : (u32)NTT;
         if (tid == 0) sh.self_flag = 0;
@@ -712,7 +723,7 @@ __global__ __launch_bounds__(256) void k_direct(i64 n, const double* __restrict_
         tz[k] = target_reg<T>(x[3 * gi[k] + 2]);
         ax[k] = ay[k] = az[k] = 0.0;
     }
-    const double qscale = (DEN == STC_DEN_DIST2) ? 2.0 : 1.0;
+    const double qscale = charge_scale<T, DEN>();
     // the next tile's source is loaded into registers before the current
     // tile is summed, so its memory latency overlaps the arithmetic
     // (the pointers stay live across the tile loop, so no register of an
