@@ -309,3 +309,24 @@ def test_learned_arguments_are_checked(stc_lib):
     with pytest.raises(stc_lib.StcError):        # misaligned parameters
         cl.set_model(p[1:1 + stc_lib.mlp_param_count()])
     cl.close()
+
+
+def test_forcing_applies_to_the_learned_form(stc_lib):
+    """The vorticity forcing acts on the charges, upstream of the gating: a
+    learned context without a network equals the fixed-degree context under
+    the same forcing, bitwise, and the forcing changes the result."""
+    x, z, a = _case()
+    om, lat1, tp, tf = 2.0 * np.pi, np.pi / 3.0, 4.0, 15.0
+    say(f"learned form with forcing N={len(x)}")
+    cl = stc_lib.Context(len(x), degree=10, precision="fp32", denominator="dist2", learned=True, theta_max=0.85,
+                         **KW)
+    cp = stc_lib.Context(len(x), degree=10, precision="fp32", denominator="dist2", max_level=cl.max_level, **KW)
+    u0 = cp.velocity(dev(x), dev(z), dev(a)).cpu().numpy()
+    for c in (cl, cp):
+        c.set_forcing(2, om, lat1, tp, tf, time=7.0)
+    ul = cl.velocity(dev(x), dev(z), dev(a)).cpu().numpy()
+    up = cp.velocity(dev(x), dev(z), dev(a)).cpu().numpy()
+    assert np.array_equal(ul, up)
+    assert np.abs(up - u0).max() > 1e-3 * np.abs(u0).max()
+    cl.close()
+    cp.close()
