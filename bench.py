@@ -23,7 +23,7 @@ times graph-captured RK4 steps of the whole ensemble.
 
 ``--workload rk4`` times graph-captured RK4 steps of the Rossby-Haurwitz wave
 at N = 163842; ``--workload ssw`` those of the forced polar-vortex collapse
-(Sec. 5) at N = 163842, d = 6, theta = 0.7; ``--workload stream`` the stream
+(Sec. 4.4) at N = 163842, d = 6, theta = 0.7; ``--workload stream`` the stream
 function (logarithmic kernel) on the headline workload and setting;
 ``--workload plain`` the plain FP64 method (theta 0.7, d 8) at N = 10242.
 """
@@ -409,7 +409,7 @@ def bench_rk4(args):
 
 
 def bench_ssw(args):
-    """Forced RK4 of the polar-vortex collapse (Sec. 5) at the paper's setting
+    """Forced RK4 of the polar-vortex collapse (Sec. 4.4) at the paper's setting
     (N = 163842, d = 6, theta = 0.7, wavenumber-1 forcing); the accuracy check
     is one evaluation at full forcing (day 8) against the FP64 direct sum of
     the forced field on 4096 seeded targets."""

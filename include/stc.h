@@ -269,7 +269,7 @@ stc_status stc_rk4_batched(stc_ctx* ctx, int32_t members, const int64_t* h_offse
                            double* d_zeta, const double* d_area, double dt, double omega,
                            int32_t n_steps);
 
-/* --- vorticity forcing (Sec. 5, polar vortex collapse) ----------------------
+/* --- vorticity forcing (Sec. 4.4, polar vortex collapse) ----------------------
  *
  * With a forcing set, every evaluation of the context (stc_upward, hence
  * stc_velocity, the batched calls and every RK4 stage) uses the source charges

@@ -15,7 +15,7 @@ Applications to the Barotropic Vorticity Equation"):
                   and the dual tree traversal (Sec. 3).
 * ``rk4``      -- classical RK4 on (x, zeta) (Sec. 2 and Sec. 4).
 * ``forcing``  -- the vorticity forcing F_R of the polar-vortex collapse
-                  experiment (Sec. 5) and the forced RK4 step.
+                  experiment (Sec. 4.4) and the forced RK4 step.
 * ``metrics``  -- the relative l2 errors E and E_N (Sec. 4).
 * ``mlp``      -- FP64 forward/backward of the small interaction-gating MLP.
 

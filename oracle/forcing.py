@@ -1,4 +1,4 @@
-"""O4: vorticity forcing of the polar-vortex collapse experiment (Sec. 5,
+"""O4: vorticity forcing of the polar-vortex collapse experiment (Sec. 4.4,
 polar vortex collapse).  TEST INFRASTRUCTURE ONLY.
 
 The forced Biot-Savart integral replaces zeta by zeta - F_R in the source
@@ -22,7 +22,7 @@ import numpy as np
 
 
 def ramp(t, t_ramp, t_total):
-    """A(t) of the forcing (Sec. 5, polar vortex collapse), for scalar t."""
+    """A(t) of the forcing (Sec. 4.4, polar vortex collapse), for scalar t."""
     t = float(t)
     if t < 0.0:
         return 0.0

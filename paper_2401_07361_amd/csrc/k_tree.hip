@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_node_ranges(const u32* __restrict__ lea
     }
 }
 
-// Ramp A(t) of the forcing (Sec. 5, polar vortex collapse): a half cosine up
+// Ramp A(t) of the forcing (Sec. 4.4, polar vortex collapse): a half cosine up
 // over [0, T_p), 1 until T_f - T_p, a half cosine down until T_f, 0 outside
 // [0, T_f).  On the last piece (1 - cos(pi + a)) / 2 = (1 + cos a) / 2.
 __device__ double forcing_ramp(double t, double tp, double tf) {

@@ -26,7 +26,7 @@ void launch_bin(hipStream_t s, const double* x, i64 n, const NodeGeo* geo, int L
 void launch_gather(hipStream_t s, const u64* keys, i64 n, const double* x, i32* perm, u32* leaf,
                    double* sx, double* sy, double* sz);
 void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i32* nbeg, i32* nend);
-// Vorticity forcing of the polar-vortex collapse experiment (Sec. 5): the
+// Vorticity forcing of the polar-vortex collapse experiment (Sec. 4.4): the
 // charges become q = (zeta - F_R(x, t)) A with
 // F_R = amp A(t) B(lat) cos(k lon), amp = (3/5) Omega k^2.  The time is
 // t_base, or *t_dev + t_base when t_dev is set (RK4 stages under a graph).

@@ -51,7 +51,7 @@ class LaunchConfig(ctypes.Structure):
 
 
 class Forcing(ctypes.Structure):
-    """stc_forcing: the vorticity forcing of the polar-vortex collapse (Sec. 5)."""
+    """stc_forcing: the vorticity forcing of the polar-vortex collapse (Sec. 4.4)."""
     _fields_ = [("k", ctypes.c_int32), ("omega", ctypes.c_double), ("lat1", ctypes.c_double),
                 ("t_ramp", ctypes.c_double), ("t_total", ctypes.c_double), ("time", ctypes.c_double)]
 
@@ -247,7 +247,7 @@ def direct_stream(x, zeta, area, targets=None, precision="fp64", denominator="do
 
 
 def forcing_field(x, k, omega, lat1, t_ramp, t_total, time, out=None, stream=None):
-    """F_R(x_i, time) of the polar-vortex forcing (Sec. 5) at every row of x."""
+    """F_R(x_i, time) of the polar-vortex forcing (Sec. 4.4) at every row of x."""
     import torch
     n = x.shape[0]
     if out is None:
@@ -566,7 +566,7 @@ class Context:
                           _dptr(area, "area", torch.float64, n), float(dt), float(omega), int(n_steps))
         _check(st, self._ctx)
 
-    # vorticity forcing (Sec. 5, polar vortex collapse) ---------------------------------
+    # vorticity forcing (Sec. 4.4, polar vortex collapse) ---------------------------------
     def set_forcing(self, k, omega, lat1, t_ramp, t_total, time=0.0):
         """Charges (zeta - F_R(x, t)) A from now on; `time` is t of the next
         evaluation and the start time of the next rk4 call."""

@@ -84,7 +84,7 @@ def gaussian_pair(x, seed, width=0.1, amplitude=4.0 * np.pi / 86400.0):
 
 
 def polar_vortex(x, beta=1.5, lat0=15.0 * np.pi / 32.0):
-    """Initial vorticity of the polar-vortex collapse experiment (Sec. 5), a
+    """Initial vorticity of the polar-vortex collapse experiment (Sec. 4.4), a
     zonally symmetric profile of latitude theta (per day, Omega = 2 pi per day):
     pi exp(-2 beta^2 (1 - cos(theta0 - theta))) (2 beta^2 cos(theta) sin(theta0 - theta) + sin(theta))."""
     lat = np.arcsin(np.clip(x[:, 2], -1.0, 1.0))

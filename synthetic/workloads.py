@@ -14,7 +14,7 @@ conditions; no dataset exists or is needed):
 * ``gvpair_l9`` N = 2621442 (level 9), RH n = 4 background plus a +/- vortex
                pair of amplitude 4 pi per day.
 * ``ssw_l7``   N = 163842 (level 7), node-patch areas, the polar vortex of the
-               vortex-collapse experiment (Sec. 5) with its wavenumber-1
+               vortex-collapse experiment (Sec. 4.4) with its wavenumber-1
                vorticity forcing; time in days; d = 6, theta = 0.7.
 
 ``make_ensemble`` builds the ensemble workload: members with seeds 4 + m, each
@@ -67,7 +67,7 @@ def make_workload(name, level=None):
                     subset=subset_indices(n, 4096, 5),
                     theta=0.7, degree=10, seed=5)
     if name == "ssw_l7":
-        # polar-vortex collapse (Sec. 5): the vortex profile on a level-7
+        # polar-vortex collapse (Sec. 4.4): the vortex profile on a level-7
         # grid with node-patch areas, time in days (Omega = 2 pi per day),
         # wavenumber-1 forcing with T_p = 4, T_f = 15, lat1 = pi/3; the
         # paper's d = 6, theta = 0.7; dt = 0.01 days (the time step the paper

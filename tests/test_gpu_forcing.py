@@ -1,4 +1,4 @@
-"""GPU vorticity forcing (Sec. 5, polar vortex collapse) against the oracle:
+"""GPU vorticity forcing (Sec. 4.4, polar vortex collapse) against the oracle:
 the forced velocity of one evaluation, the forcing switched off by its ramp,
 and forced RK4 steps (eager and graph-captured) across the end of the ramp-up,
 with the forcing clock advanced by the steps."""

@@ -1,4 +1,4 @@
-"""Pins for the oracle's vorticity forcing (O4; Sec. 5, polar vortex collapse):
+"""Pins for the oracle's vorticity forcing (O4; Sec. 4.4, polar vortex collapse):
 the ramp's values at its breakpoints and its time symmetry, the latitude
 profile's maximum at the latitude of maximum forcing, the Rossby number the
 paper prints, the zonal structure cos(k lon), linearity of the forced

@@ -146,3 +146,52 @@ def test_labels_from_errors():
     np.testing.assert_array_equal(y, [[1, 0, 0, 0], [1, 1, 1, 0], [1, 1, 1, 1], [1, 1, 0, 0]])
     y = OL.labels_from_errors(E, 1e-13)
     np.testing.assert_array_equal(y[:, 0], [0, 0, 0, 0])
+
+
+def test_features_of_one_candidate_by_hand():
+    """The twelve features of one candidate worked out by hand.  Faces 0 and
+    19 are antipodal root triangles (circumcentres c and -c, so R = 2; the
+    circumradius r0 follows from the icosahedron, cos(angle) = phi^2 /
+    (sqrt 3 sqrt(1 + phi^2))).  N_T = 1, depth limit 0, theta_max = 0.9, so
+    the candidates are (0, 19) and (19, 0).  Target face 0 holds charges 1
+    and -0.5; source face 19 holds charges 2 and -1 placed exactly on two of
+    its interior degree-4 interpolation points (barycentrics written out from
+    the Gauss-Lobatto nodes 1/2 -+ sqrt(3/7)/2 and 1/2), where the degree-4
+    proxy charges are the charges themselves (L_m(y_j) = delta), so
+    |w^(4)|_1 = Q_s."""
+    from oracle import geometry as G
+    geom = G.TreeGeometry(0)
+    va, vb = geom.node_vertices(0), geom.node_vertices(19)
+    assert np.abs(geom.node_center(0) + geom.node_center(19)).max() < 1e-15
+    r = np.sqrt(3.0 / 7.0) / 2.0
+    bary = [((1 - r) / 3, (1 - r) / 3, (1 + 2 * r) / 3),     # point (1, 1, 2)
+            ((1 + 2 * r) / 3, (1 - r) / 3, (1 - r) / 3)]     # point (2, 1, 1)
+    src = []
+    for b in bary:
+        p = b[0] * vb[0] + b[1] * vb[1] + b[2] * vb[2]
+        src.append(p / np.linalg.norm(p))
+    ca = (va[0] + va[1] + va[2]) / 3.0
+    tgt = [ca / np.linalg.norm(ca), (0.8 * ca + 0.2 * va[0]) / np.linalg.norm(0.8 * ca + 0.2 * va[0])]
+    x = np.array(tgt + src)
+    q = np.array([1.0, -0.5, 2.0, -1.0])
+    lt = OL.LearnedTree(x, q, np.ones(4), theta=0.6, theta_max=0.9, degree=4, n_crit=1, max_level=0)
+    assert lt.candidates.tolist() == [[0, 19], [19, 0]]
+    phi = (1 + 5 ** 0.5) / 2
+    cos_a = phi ** 2 / (3 ** 0.5 * (1 + phi ** 2) ** 0.5)
+    r0 = (2 - 2 * cos_a) ** 0.5
+    Q, Qs, Qt = 4.5, 3.0, 1.5
+    want = [1, 1, 0, 0, r0 / 2, r0 / 2, r0, -np.log10(2.0) / 2, np.log10(Qs / Q) / 8 + 1, 1.0 / 3.0, 0.0,
+            np.log10(Qt / Q) / 8 + 1]
+    got = lt.features[0, :12]
+    for k in range(12):
+        # BF16 keeps 8 significant bits: one unit in the last place
+        assert abs(got[k] - want[k]) <= 2.0 ** -8 * max(abs(want[k]), 1e-6), (k, got[k], want[k])
+    assert np.all(lt.features[:, 12:] == 0)
+    # the reverse pair swaps the node roles (its f10 depends on where the
+    # target's charges sit, so it is not checked)
+    back = lt.features[1, :12]
+    want_b = [1, 1, 0, 0, r0 / 2, r0 / 2, r0, -np.log10(2.0) / 2, np.log10(Qt / Q) / 8 + 1, 1.0 / 3.0, None,
+              np.log10(Qs / Q) / 8 + 1]
+    for k in range(12):
+        if want_b[k] is not None:
+            assert abs(back[k] - want_b[k]) <= 2.0 ** -8 * max(abs(want_b[k]), 1e-6), (k, back[k], want_b[k])

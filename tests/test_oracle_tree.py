@@ -149,9 +149,15 @@ def test_tangency_and_lists_independent_of_vorticity():
 
 
 def test_error_decreases_with_degree():
-    """Sec. 4: at theta = 0.7 the error falls as the degree rises; d = 6 gives
-    three to four digits (our interpolation points and N differ, so the band
-    is loose)."""
+    """Sec. 4 (runtime results): at theta = 0.7 the error falls as the degree
+    rises, and d = 6 gives three to four digits, i.e. E in [1e-4, 1e-3] at
+    N = 655362 with the paper's point set.  Our interpolation points differ
+    and the interpolated form (y - x) / den is about 1/R smaller than y / den,
+    so the band is taken one decade wider on the accurate side: [1e-5, 1e-3].
+    The oracle gives 3.6e-5 here, the same at N = 10242 and for N_T = 16 to
+    64 (the error of a far interaction does not depend on N); a wrong basis,
+    point set or list puts d = 6 above 1e-3, a tree that approximates nothing
+    puts it below 1e-5."""
     x = S.icosahedral_grid(4)
     n = len(x)
     z = S.rossby_haurwitz(x, 4)
@@ -161,7 +167,7 @@ def test_error_decreases_with_degree():
     for d in (2, 4, 6, 8):
         errs[d] = metrics.rel_l2_velocity(T.velocity(x, z, a, theta=0.7, degree=d, n_crit=16), ud, a)
     assert errs[2] > errs[4] > errs[6] > errs[8]
-    assert 1e-7 < errs[6] < 1e-3
+    assert 1e-5 < errs[6] < 1e-3
 
 
 def test_node_counts_match_brute_force_containment():
@@ -179,3 +185,40 @@ def test_node_counts_match_brute_force_containment():
                     and np.dot(x[i], np.cross(c, a)) >= 0):
                 inside.append(k)
         assert inside == [key[i]]
+
+
+def _fixture_points(geom, particles):
+    """Points strictly inside level-1 children: the child's vertex centroid,
+    normalised, then pulled 10% towards the child's first / second vertex."""
+    out = []
+    for face, child, count in particles:
+        v = geom.node_vertices(20 + 4 * face + child)
+        cen = (v[0] + v[1] + v[2]) / 3.0
+        for k in range(count):
+            p = cen if k == 0 else 0.9 * cen + 0.1 * v[k - 1]
+            out.append(p / np.linalg.norm(p))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("case", ["larger_side", "tie_refines_target", "hand_over_to_other_side"])
+def test_refinement_rule_hand_worked(case):
+    """Sec. 3, dual tree traversal: lists written out by hand from the
+    refinement rule (the larger side is refined, ties refine the target, a
+    side at its limit hands over to the other) on three small cases; each
+    would change if one part of the rule were different."""
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "traversal_refinement.json")))
+    c = fx["cases"][case]
+    geom = G.TreeGeometry(fx["max_level"])
+    for t, s_, ratio, sep in c["premises"]:
+        ct, cs = geom.node_center(t), geom.node_center(s_)
+        got = (geom.node_radius(t) + geom.node_radius(s_)) / np.linalg.norm(ct - cs)
+        assert abs(got - ratio) < 1e-3, (t, s_, got)
+        assert T.well_separated(geom, t, s_, fx["theta"]) == sep, (t, s_)
+    x = _fixture_points(geom, c["particles"])
+    pt = G.ParticleTree(x, geom, fx["n_crit"])
+    lists = T.traverse(pt, fx["theta"])
+    for k in ("PP", "PC", "CP", "CC"):
+        want = sorted(tuple(p) for p in c[k])
+        assert sorted(map(tuple, lists[k].tolist())) == want, k
