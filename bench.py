@@ -22,7 +22,9 @@ against the same members evaluated one context after the other; it also
 times graph-captured RK4 steps of the whole ensemble.
 
 ``--workload rk4`` times graph-captured RK4 steps of the Rossby-Haurwitz wave
-at N = 163842; ``--workload ssw`` those of the forced polar-vortex collapse
+at N = 163842; ``--workload rh10d`` runs that wave for its configured ten days
+(480 steps) in FP64 and FP32 and reports the phase against the closed form,
+the circulation drift and E_N, with tree and resolution controls; ``--workload ssw`` those of the forced polar-vortex collapse
 (Sec. 4.4) at N = 163842, d = 6, theta = 0.7; ``--workload stream`` the stream
 function (logarithmic kernel) on the headline workload and setting;
 ``--workload plain`` the plain FP64 method (theta 0.7, d 8) at N = 10242.
@@ -49,9 +51,19 @@ BENCH_N_CRIT = 64
 
 FP32_FLOPS = 16   # per |x-y|^2/2 kernel evaluation: 3 sub, |d|^2 5, div 1, *q 1, 3 fma 6
 FP64_FLOPS = 17   # per 1 - x.y evaluation with the (y - x) form: dot 5, 1- 1, div 1, *q 1, 3 sub, 3 fma 6
-PEAK_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, without packed FP32
+# Published MI355X peaks (vector): FP32 157.3 TFLOP/s (packed FP32 instructions), FP64 78.6 TFLOP/s.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+# What the library's FP32 code can issue: it is built without packed FP32 instructions, so FP32 and FP64
+# FMAs both issue 64 lanes per CU per clock: 256 CU x 64 lanes x 2 flop x 2.4 GHz.
+PEAK_VALU_TFLOPS = 78.6
 COPY_BYTES = 256 << 20    # calibration copy: bytes read = bytes written
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_near_gv_l8_hbm_traffic.md")
+# evaluation kernels: phase name -> (kernel, lists it evaluates, recorded HBM traffic summary)
+EVAL_KERNELS = {
+    "near": ("k_near (PP + PC)", ("PP", "PC"), os.path.join(ROOT, "profiles", "k_near_gv_l8_hbm_traffic.md")),
+    "far_targets": ("k_far_targets (CP + CC)", ("CP", "CC"),
+                    os.path.join(ROOT, "profiles", "k_far_targets_gv_l8_hbm_traffic.md")),
+}
 
 
 def kernel_source_hash():
@@ -63,13 +75,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(config_tag):
-    """HBM bytes per k_near launch from the committed counter summary, if it
-    was taken on the current kernel source and the same configuration."""
-    if not os.path.exists(TRAFFIC_FILE):
+def recorded_traffic(config_tag, path):
+    """HBM bytes per launch of one evaluation kernel from the committed counter
+    summary at `path`, if it was taken on the current kernel source and the
+    same configuration."""
+    if not os.path.exists(path):
         return None
     rec = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].strip().split(": ", 1)
             rec[k] = v.strip("` ")
@@ -98,7 +111,10 @@ def cpu_baseline(x, z, a, subset, budget_s=15.0, den="dot", what="the 4096 seede
     """The oracle's direct sum (O(N) per target) timed on the host cores over a
     bounded sample of the target subset (the stream function's with stream)."""
     from oracle import direct
-    cores = min(len(os.sched_getaffinity(0)), 16)
+    # the GPU box allots 16 CPUs to a one-GPU job (more visible CPUs are shared
+    # with other jobs), so the pool takes at most 16 processes
+    visible = len(os.sched_getaffinity(0))
+    cores = min(visible, 16)
     _G.update(x=x, z=z, a=a, den=den, stream=stream)
     fn = direct.stream_function if stream else direct.velocity
     t0 = time.perf_counter()
@@ -114,19 +130,42 @@ def cpu_baseline(x, z, a, subset, budget_s=15.0, den="dot", what="the 4096 seede
         parts = pool.map(_oracle_worker, chunks)
     dt = time.perf_counter() - t0
     u = np.concatenate(parts)
-    return dict(value=m / dt, unit="velocity evals/s", cores=cores, kind="oracle",
+    return dict(value=m / dt, unit="velocity evals/s", cores=cores, cpus_visible=visible, kind="oracle",
                 sample=f"{m} of {what}, all {len(x)} sources, FP64 direct "
                        f"{'stream function' if stream else 'sum'}, "
                        f"{dt:.1f} s wall"), sample, u
 
 
-def near_roofline(evals, ms, precision):
-    """The near-field kernel's ALU roofline entry (traffic not measured here)."""
-    flops = FP32_FLOPS if precision == "fp32" else FP64_FLOPS
-    achieved = evals * flops / (ms / 1e3) / 1e12
-    return dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=None, kernel="k_near (PP + PC)",
-                kernel_ms=round(ms, 4), kernel_evals_per_launch=int(evals))
+def roofline(evals, kern_ms, precision, flops=None, config_tag=None):
+    """ALU roofline of the evaluation kernels: an entry per kernel (k_near:
+    PP + PC, k_far_targets: CP + CC) from exact list evaluation counts and the
+    kernel's average duration measured with HIP events on the library stream
+    inside the timed region; the dominant kernel (longest per launch) is the
+    returned object, the other under "kernels".  `peak` is the published
+    vector peak of the precision; FP32 also reports the fraction of the
+    78.6 TFLOP/s the library's non-packed FP32 code can issue."""
+    fl = flops if flops is not None else (FP32_FLOPS if precision == "fp32" else FP64_FLOPS)
+    peak = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_FP64_TFLOPS
+    entries = []
+    for ph, (name, lists, tfile) in EVAL_KERNELS.items():
+        if ph not in kern_ms:
+            continue
+        ev = int(sum(evals[k] for k in lists))
+        ms = kern_ms[ph]
+        achieved = ev * fl / (ms / 1e3) / 1e12
+        e = dict(bound="alu", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s", frac=round(achieved / peak, 4),
+                 traffic=None, kernel=name, kernel_ms=round(ms, 4), kernel_evals_per_launch=ev, flops_per_eval=fl)
+        if precision == "fp32":
+            e["valu_issue_ceiling"] = PEAK_VALU_TFLOPS
+            e["frac_of_valu_issue_ceiling"] = round(achieved / PEAK_VALU_TFLOPS, 4)
+        if config_tag is not None:
+            e["traffic"] = recorded_traffic(config_tag, tfile)
+            e["traffic_source"] = ("recorded: " + os.path.relpath(tfile, ROOT)) if e["traffic"] is not None else None
+        entries.append(e)
+    entries.sort(key=lambda e: -e["kernel_ms"])
+    top = dict(entries[0])
+    top["kernels"] = entries
+    return top
 
 
 ENS_THETA, ENS_DEGREE, ENS_N_CRIT = 0.7, 8, 64
@@ -148,7 +187,7 @@ def bench_ensemble(args):
     ctx.velocity_batched(x, z, a, off, out=out)
     shape = ctx.autotune(repeats=3)
     log(f"autotuned launch shape {shape}")
-    ms, near_ms, phase_ms = _timed(ctx, lambda: ctx.velocity_batched(x, z, a, off, out=out), args.steps,
+    ms, kern_ms, phase_ms = _timed(ctx, lambda: ctx.velocity_batched(x, z, a, off, out=out), args.steps,
                                    args.warmup)
     counts, evals = ctx.list_counts()
     log(f"batched: {ms:.3f} ms per ensemble evaluation; phases {phase_ms}")
@@ -194,7 +233,7 @@ def bench_ensemble(args):
     ctx.sync()
     log(f"rk4 step (4 evaluations, one graph): {ms_rk:.3f} ms")
     ctx.close()
-    roof = near_roofline(evals["PP"] + evals["PC"], near_ms, "fp32")
+    roof = roofline(evals, kern_ms, "fp32")
     m0 = ens["members"][0]
     cb = None
     if not args.no_cpu:
@@ -237,12 +276,13 @@ def _phase_breakdown(ctx, fn, reps=3):
 
 
 def _timed(ctx, fn, steps, warmup):
-    """(ms per call over the timed region, k_near ms per launch measured with
-    events around that kernel only inside the timed region, phase breakdown)."""
+    """(ms per call over the timed region, {phase: ms per launch} of k_near and
+    k_far_targets measured with events around those kernels only inside the
+    timed region, phase breakdown)."""
     import torch
     for _ in range(warmup):
         fn()
-    ctx.set_timing(steps, phases=["near"])
+    ctx.set_timing(steps, phases=["near", "far_targets"])
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
@@ -252,8 +292,8 @@ def _timed(ctx, fn, steps, warmup):
     torch.cuda.synchronize()
     ctx.sync()
     ph, k = ctx.phase_times()
-    near_ms = ph["near"] / max(k, 1)
-    return t0.elapsed_time(t1) / steps, near_ms, _phase_breakdown(ctx, fn)
+    kern_ms = {p: ph[p] / max(k, 1) for p in ("near", "far_targets")}
+    return t0.elapsed_time(t1) / steps, kern_ms, _phase_breakdown(ctx, fn)
 
 
 def bench_learned(args):
@@ -293,11 +333,11 @@ def bench_learned(args):
         ctx = stc.Context(n, denominator="dist2", n_crit=P["n_crit"], **kw)
         if model is not None:
             ctx.set_model(model)
-        ms, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, args.warmup)
+        ms, kern_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
         if model is not None and kw.get("precision") == "fp32":
             pairs, _, _ = ctx.copy_candidates()
-            rows["_near"] = (ev["PP"] + ev["PC"], near_ms_t, len(pairs))
+            rows["_near"] = (ev, kern_ms_t, len(pairs))
         u = out.cpu().numpy()
         rows[name] = dict(ms=round(ms, 4), rel_l2_err_vs_fp64_direct=float(f"{metrics.rel_l2_velocity(u[sub], ud, a[sub]):.3e}"),
                           kernel_evals=int(sum(ev.values())), phase_ms=ph)
@@ -312,7 +352,7 @@ def bench_learned(args):
     ul = run("learned_fp32", model=params, theta=P["theta"], theta_max=P["theta_max"], degree=P["degree"],
              precision="fp32", learned=True)
     e_judge = metrics.rel_l2_velocity(ul, uj, a)
-    near_evals, near_ms, n_cand = rows.pop("_near")
+    roof_evals, roof_ms, n_cand = rows.pop("_near")
     # the network's forward pass over the candidates, timed on its own (MFMA, BF16)
     feats = F[: min(len(F), n_cand)] if n_cand <= len(F) else F
     fwd = torch.empty((feats.shape[0], 4), dtype=torch.float32, device="cuda")
@@ -344,7 +384,7 @@ def bench_learned(args):
                                   loss_first=float(f"{ln[0]:.4f}"), loss_last=float(f"{ln[-50:].mean():.4f}"),
                                   calibration=dict(accept_shift=da, class_shift=dc)),
                     runs=rows, network_forward=mlp_roof),
-        roofline=near_roofline(near_evals, near_ms, "fp32"),
+        roofline=roofline(roof_evals, roof_ms, "fp32"),
     )
     if not args.no_cpu:
         log("cpu baseline (oracle direct sum, bounded target sample)")
@@ -372,7 +412,7 @@ def bench_rk4(args):
         shape = ctx.autotune(repeats=5)  # launch shape for this size, used by the evaluations below
         log(f"{prec}: autotuned launch shape {shape}")
         err = metrics.rel_l2_velocity(u.cpu().numpy()[sub], ud, a[sub])
-        ms_eval, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
+        ms_eval, kern_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
         xs, zs = xd.clone(), zd.clone()
         ctx.rk4(xs, zs, ad, dt, Om, 1)   # captures the step graph
@@ -386,11 +426,11 @@ def bench_rk4(args):
         ms_step = t0.elapsed_time(t1) / args.steps
         runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4), launch_shape=shape,
                           rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), phase_ms=ph,
-                          near=(ev["PP"] + ev["PC"], near_ms_t))
+                          near=(ev, kern_ms_t))
         log(f"{prec}: {ms_step:.3f} ms per RK4 step (graph), {ms_eval:.3f} ms per evaluation, E = {err:.3e}")
         ctx.close()
     r = runs["fp32"]
-    near_evals, near_ms = r.pop("near")
+    roof_evals, roof_ms = r.pop("near")
     runs["fp64"].pop("near")
     result = dict(
         metric="particle velocity evals/s in RK4 time stepping at N=163842 (4 evaluations per step, one HIP graph per step)",
@@ -399,12 +439,112 @@ def bench_rk4(args):
         vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="rh4_l7 (Rossby-Haurwitz n=4, icosahedral level 7, node-patch areas)", N=n,
                     theta=wl["theta"], degree=wl["degree"], n_crit=64, dt_seconds=dt, omega=Om, runs=runs),
-        roofline=near_roofline(near_evals, near_ms, "fp32"),
+        roofline=roofline(roof_evals, roof_ms, "fp32"),
     )
     if not args.no_cpu:
         log("cpu baseline (oracle direct sum, bounded target sample)")
         cb, _, _ = cpu_baseline(x, z, a, sub, budget_s=8.0, den="dist2", what="4096 seeded targets")
         result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+
+
+def rh_ten_day_run(stc, x0, z0, a, dt, Om, steps, precision, theta, degree, day_steps=48, log=None):
+    """RK4 of the Rossby-Haurwitz wave (graph-captured steps, one sync per
+    simulated day): final (x, zeta), the k = 4 phase after every day
+    (unwrapped), and ms per step over the run."""
+    import torch
+    ctx = stc.Context(len(x0), theta=theta, degree=degree, n_crit=64, precision=precision, denominator="dist2")
+    xd, zd, ad = (torch.from_numpy(v.copy()).cuda() for v in (x0, z0, a))
+    phases = [rh_phase(x0, z0, a)]
+    ms = 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for day0 in range(0, steps, day_steps):
+        k = min(day_steps, steps - day0)
+        e0.record()
+        ctx.rk4(xd, zd, ad, dt, Om, k)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        ms += e0.elapsed_time(e1)
+        x, z = xd.cpu().numpy(), zd.cpu().numpy()
+        phases.append(rh_phase(x, z, a))
+        if log:
+            log(f"  {precision} theta={theta} d={degree} N={len(x0)}: step {day0 + k} of {steps}")
+    ctx.close()
+    ph = np.unwrap(np.array(phases))
+    return x, z, ph, ms / steps
+
+
+def rh_phase(x, z, a, k=4):
+    """Phase of the k-wave: arg sum A zeta z (x + i y)^k (the vorticity's
+    projection on the wave's pattern); it advances by k nu t."""
+    return float(np.angle(((x[:, 0] + 1j * x[:, 1]) ** k * x[:, 2] * z * a).sum()))
+
+
+def bench_rh10d(args):
+    """The Rossby-Haurwitz wave n = 4 at N = 163842 (icosahedral level 7,
+    node-patch areas), RK4 with dt = 1800 s for 480 steps (10 days), plain
+    FP64 and FP32 forms at theta 0.7, d 8.  Reported: phase after 10 days
+    against the closed-form propagation (Sec. 4, Rossby-Haurwitz phase speed),
+    relative circulation drift, E_N against the exact moved field, FP32 vs FP64
+    differences, and two controls: a tighter tree (theta 0.4, d 12, FP64) to
+    show the tree's approximation does not set the phase error, and the same
+    run at level 6 (N = 40962) to show that the particle discretisation does."""
+    import synthetic as S
+    from paper_2401_07361_amd import stc
+    from oracle import metrics
+
+    wl = S.make_workload("rh4_l7")
+    x0, z0, a = wl["x"], wl["zeta"], wl["area"]
+    n, dt, steps = len(x0), wl["dt"], wl["steps"]
+    Om = S.OMEGA_EARTH_S
+    omega = K = 7.848e-6
+    nu = (4 * (4 + 3) * omega - 2 * Om) / ((4 + 1) * (4 + 2))
+    expected = np.degrees(nu * dt * steps)
+
+    def report(tag, x, z, ph, ms, xs0, zs0, aa):
+        shift = np.degrees(ph[-1] - ph[0]) / 4
+        c, s_ = np.cos(-np.radians(shift)), np.sin(-np.radians(shift))
+        R = np.array([[c, -s_, 0], [s_, c, 0], [0, 0, 1]])
+        c2, s2 = np.cos(-nu * dt * steps), np.sin(-nu * dt * steps)
+        R2 = np.array([[c2, -s2, 0], [s2, c2, 0], [0, 0, 1]])
+        en_exact = metrics.rel_l2_scalar(z, S.rossby_haurwitz(x @ R2.T, 4, omega=omega, K=K), aa)
+        en_moved = metrics.rel_l2_scalar(z, S.rossby_haurwitz(x @ R.T, 4, omega=omega, K=K), aa)
+        drift = abs((z * aa).sum() - (zs0 * aa).sum()) / (np.abs(zs0) * aa).sum()
+        r = dict(phase_deg=round(shift, 4), phase_rel_err=round((shift - expected) / expected, 5),
+                 E_N_vs_exact=float(f"{en_exact:.4e}"), E_N_vs_field_at_measured_phase=float(f"{en_moved:.4e}"),
+                 circulation_drift=float(f"{drift:.3e}"), ms_per_rk4_step=round(ms, 4),
+                 daily_phase_deg=[round(v, 3) for v in np.degrees(ph - ph[0]) / 4])
+        log(f"{tag}: phase {shift:.3f} deg (closed form {expected:.3f}), E_N {en_exact:.3e}, "
+            f"drift {drift:.2e}, {ms:.3f} ms/step")
+        return r
+
+    runs = {}
+    finals = {}
+    for tag, prec, th, d in (("fp64", "fp64", 0.7, 8), ("fp32", "fp32", 0.7, 8),
+                             ("fp64_theta0.4_d12", "fp64", 0.4, 12)):
+        x, z, ph, ms = rh_ten_day_run(stc, x0, z0, a, dt, Om, steps, prec, th, d, log=log)
+        runs[tag] = report(tag, x, z, ph, ms, x0, z0, a)
+        finals[tag] = (x, z)
+    x6, f6 = S.icosahedral_grid(6, return_faces=True)
+    a6 = S.node_patch_areas(x6, f6)
+    z6 = S.rossby_haurwitz(x6, 4)
+    x, z, ph, ms = rh_ten_day_run(stc, x6, z6, a6, dt, Om, steps, "fp64", 0.7, 8, log=log)
+    runs["fp64_level6_N40962"] = report("fp64 level 6", x, z, ph, ms, x6, z6, a6)
+    (x64, z64), (x32, z32) = finals["fp64"], finals["fp32"]
+    fp32_vs_fp64 = dict(max_position_diff=float(f"{np.abs(x32 - x64).max():.3e}"),
+                        vorticity_rel_l2_diff=float(f"{metrics.rel_l2_scalar(z32, z64, a):.3e}"),
+                        phase_diff_deg=round(runs["fp32"]["phase_deg"] - runs["fp64"]["phase_deg"], 5))
+    r = runs["fp32"]
+    result = dict(
+        metric="RK4 steps of the ten-day Rossby-Haurwitz run at N=163842 (4 velocity evaluations per step)",
+        value=round(1e3 / r["ms_per_rk4_step"], 2), unit="RK4 steps/s", n_gpus=1, steps=steps, warmup=0,
+        ms_per_step=r["ms_per_rk4_step"], higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload="rh4_l7 ten days (Rossby-Haurwitz n=4, icosahedral level 7, node-patch areas)", N=n,
+                    theta=0.7, degree=8, n_crit=64, dt_seconds=dt, steps=steps, omega=Om,
+                    closed_form_phase_deg=round(expected, 4), runs=runs, fp32_vs_fp64=fp32_vs_fp64),
+    )
     print(json.dumps(result), flush=True)
 
 
@@ -436,7 +576,7 @@ def bench_ssw(args):
         shape = ctx.autotune(repeats=5)  # launch shape for this size, used by the evaluations below
         log(f"{prec}: autotuned launch shape {shape}")
         err = metrics.rel_l2_velocity(u.cpu().numpy()[sub], ud, a[sub])
-        ms_eval, near_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
+        ms_eval, kern_ms_t, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
         cnt, ev = ctx.list_counts()
         xs, zs = xd.clone(), zd.clone()
         ctx.set_forcing(*fargs, time=0.0)
@@ -452,11 +592,11 @@ def bench_ssw(args):
         t_end = ctx.forcing()[1]["time"]
         runs[prec] = dict(ms_per_rk4_step=round(ms_step, 4), ms_per_evaluation=round(ms_eval, 4), launch_shape=shape,
                           rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), phase_ms=ph, forcing_time_after=t_end,
-                          near=(ev["PP"] + ev["PC"], near_ms_t))
+                          near=(ev, kern_ms_t))
         log(f"{prec}: {ms_step:.3f} ms per forced RK4 step (graph), {ms_eval:.3f} ms per evaluation, E = {err:.3e}")
         ctx.close()
     r = runs["fp32"]
-    near_evals, near_ms = r.pop("near")
+    roof_evals, roof_ms = r.pop("near")
     runs["fp64"].pop("near")
     result = dict(
         metric="particle velocity evals/s in forced RK4 time stepping at N=163842 (polar-vortex collapse, "
@@ -467,7 +607,7 @@ def bench_ssw(args):
         config=dict(workload="ssw_l7 (polar vortex, wavenumber-1 forcing, icosahedral level 7, node-patch areas)",
                     N=n, theta=wl["theta"], degree=wl["degree"], n_crit=64, dt_days=dt, omega_per_day=Om,
                     forcing=fc, error_check_day=t_check, runs=runs),
-        roofline=near_roofline(near_evals, near_ms, "fp32"),
+        roofline=roofline(roof_evals, roof_ms, "fp32"),
     )
     if not args.no_cpu:
         log("cpu baseline (oracle direct sum of the forced field, bounded target sample)")
@@ -495,7 +635,7 @@ def bench_plain(args):
     ctx = stc.Context(n, theta=wl["theta"], degree=wl["degree"], n_crit=64, precision="fp64", denominator="dot")
     u = ctx.velocity(xd, zd, ad)
     err = metrics.rel_l2_velocity(u.cpu().numpy(), ud, a)
-    ms, near_ms, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
+    ms, kern_ms, ph = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=u), args.steps, args.warmup)
     cnt, ev = ctx.list_counts()
     ug = u.cpu().numpy()
     ctx_level = ctx.max_level
@@ -509,7 +649,7 @@ def bench_plain(args):
         config=dict(workload="rh4_l5 (Rossby-Haurwitz n=4, icosahedral level 5, A = 4 pi / N)", N=n,
                     theta=wl["theta"], degree=wl["degree"], n_crit=64, precision="fp64", denominator="dot",
                     rel_l2_err_vs_fp64_direct=float(f"{err:.3e}"), lists=cnt, phase_ms=ph),
-        roofline=near_roofline(ev["PP"] + ev["PC"], near_ms, "fp64"),
+        roofline=roofline(ev, kern_ms, "fp64"),
     )
     if not args.no_cpu:
         log("cpu baseline (oracle direct sum, bounded target sample)")
@@ -548,15 +688,11 @@ def bench_stream(args):
                       denominator="dist2")
     psi = ctx.stream_function(xd, zd, ad)
     err = metrics.rel_l2_scalar(psi.cpu().numpy()[sub], ref, a[sub])
-    ms, near_ms, ph = _timed(ctx, lambda: ctx.stream_function(xd, zd, ad, out=psi), args.steps, args.warmup)
+    ms, kern_ms, ph = _timed(ctx, lambda: ctx.stream_function(xd, zd, ad, out=psi), args.steps, args.warmup)
     cnt, ev = ctx.list_counts()
     log(f"{ms:.3f} ms per stream-function evaluation, E = {err:.3e} vs the FP64 direct sum (4096 targets)")
     ctx.close()
-    near = dict(near_roofline(ev["PP"] + ev["PC"], near_ms, args.precision))
-    flops = LOG_FLOPS
-    near["achieved"] = round((ev["PP"] + ev["PC"]) * flops / (near_ms / 1e3) / 1e12, 3)
-    near["frac"] = round(near["achieved"] / PEAK_VALU_TFLOPS, 4)
-    near["flops_per_eval"] = flops
+    near = roofline(ev, kern_ms, args.precision, flops=LOG_FLOPS)
     result = dict(
         metric="particle stream-function evals/s at N=655362 (logarithmic kernel through the tree)",
         value=n / (ms / 1e3), unit="stream-function evals/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -586,7 +722,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="gv_l8", choices=["gv_l8", "ensemble", "learned", "rk4", "ssw", "stream", "plain"])
+    ap.add_argument("--workload", default="gv_l8",
+                    choices=["gv_l8", "ensemble", "learned", "rk4", "rh10d", "ssw", "stream", "plain"])
     ap.add_argument("--autotune", action="store_true",
                     help="gv_l8: pick the interaction kernels' launch shape with the library's autotuner first")
     ap.add_argument("--copy-check", action="store_true",
@@ -607,6 +744,9 @@ def main():
         return
     if args.workload == "ssw":
         bench_ssw(args)
+        return
+    if args.workload == "rh10d":
+        bench_rh10d(args)
         return
     if args.workload == "stream":
         bench_stream(args)
@@ -644,16 +784,18 @@ def main():
         log(f"autotuned launch shape {ctx.autotune(repeats=5)}")
     log("warmup done")
 
-    ms, near_ms, phase_ms = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, 0)
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step; k_near {near_ms:.4f} ms; phases {json.dumps(phase_ms)}")
+    ms, kern_ms, phase_ms = _timed(ctx, lambda: ctx.velocity(xd, zd, ad, out=out), args.steps, 0)
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step; k_near {kern_ms['near']:.4f} ms, k_far_targets "
+        f"{kern_ms['far_targets']:.4f} ms; phases {json.dumps(phase_ms)}")
 
     counts, evals = ctx.list_counts()
     # accuracy: FP64 direct sum on the GPU (parity-tested against the oracle) at the 4096 targets
-    ud_t = stc.direct(xd, zd, ad, targets=sd)
+    scratch = stc.workspace_tensor(stc.direct_scratch_bytes(n, len(subset)))
+    ud_t = stc.direct(xd, zd, ad, targets=sd, scratch=scratch)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    stc.direct(xd, zd, ad, targets=sd, out=ud_t)
+    stc.direct(xd, zd, ad, targets=sd, out=ud_t, scratch=scratch)
     e1.record()
     torch.cuda.synchronize()
     direct_ms = e0.elapsed_time(e1)
@@ -665,15 +807,8 @@ def main():
     err = metrics.rel_l2_velocity(ut, ud, a[subset])
     log(f"E vs FP64 direct (4096 targets) = {err:.3e}; lists {counts}")
 
-    flops_per = FP32_FLOPS if args.precision == "fp32" else FP64_FLOPS
-    near_flops = (evals["PP"] + evals["PC"]) * flops_per
-    near_s = near_ms / 1e3
-    achieved = near_flops / near_s / 1e12
     config_tag = f"gv_l8 L{args.level} theta={args.theta} d={args.degree} n_crit={args.n_crit} {args.precision}"
-    roof = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_VALU_TFLOPS, unit="TFLOP/s",
-                frac=round(achieved / PEAK_VALU_TFLOPS, 4), traffic=recorded_traffic(config_tag),
-                kernel="k_near (PP + PC)", kernel_ms=round(near_ms, 4),
-                kernel_evals_per_launch=int(evals["PP"] + evals["PC"]))
+    roof = roofline(evals, kern_ms, args.precision, config_tag=config_tag)
 
     result = dict(
         metric="particle velocity evals/s at N=655362, rel-L2 err <=1e-6 vs FP64 direct sum",
@@ -688,7 +823,7 @@ def main():
                     kernel_source_hash=kernel_source_hash(),
                     direct_sum=dict(kernel="k_direct FP64 (1 - x.y), 4096 targets x all sources", ms=round(direct_ms, 4),
                                     evals_per_s=direct_evals / (direct_ms / 1e3), tflops=round(direct_tf, 3),
-                                    frac_of_fp64_peak=round(direct_tf / PEAK_VALU_TFLOPS, 4))),
+                                    frac_of_fp64_peak=round(direct_tf / PEAK_FP64_TFLOPS, 4))),
         roofline=roof,
     )
     ctx.close()

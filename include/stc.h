@@ -20,12 +20,19 @@
  *    stc_upward reads the last d_x given to stc_tree_build (see there).
  *  - Particle positions are (n, 3) FP64, row-major (x0 y0 z0 x1 y1 z1 ...).
  *    zeta, area: (n,) FP64.  Velocities are (n, 3) FP64 in INPUT order.
- *  - All pipeline calls are asynchronous on the context's HIP stream and
- *    allocate nothing: every device buffer is allocated by stc_create.
+ *  - Ownership: the library never allocates or frees device memory.  A
+ *    context's device buffers (geometry and interpolation tables, sorted
+ *    particles, lists, proxy records, RK4 stage state) are carved from one
+ *    caller-owned workspace (stc_workspace_size, then stc_create), which
+ *    must outlive the context; the direct sums take caller scratch.  The
+ *    library owns only the host-side stc_ctx, freed by stc_destroy.
+ *  - All pipeline calls are asynchronous on the context's HIP stream.
  *    Host-side argument errors return at once and enqueue nothing.
- *    Device-side conditions (list capacity exceeded) raise a flag in device
- *    memory that the next synchronising call (stc_sync, stc_list_counts,
- *    stc_copy_*) reports as STC_ERR_CAPACITY; outputs are then undefined.
+ *    Device-side conditions raise a flag in device memory that the next
+ *    synchronising call (stc_sync, stc_list_counts, stc_copy_*) reports:
+ *    STC_ERR_CAPACITY (list capacity exceeded), STC_ERR_NONFINITE (a
+ *    particle position, vorticity or area is NaN or infinite); outputs are
+ *    then undefined.
  *  - A context is not thread safe.  No call aborts the process or lets a C++
  *    exception escape; stc_last_error() gives a message for the last error.
  */
@@ -45,7 +52,10 @@ typedef enum stc_status {
     STC_ERR_CAPACITY = 2,    /* an interaction list outgrew its capacity      */
     STC_ERR_DEVICE = 3,      /* a HIP runtime call failed                     */
     STC_ERR_STATE = 4,       /* call out of order (e.g. upward before build)  */
-    STC_ERR_ALLOC = 5        /* device allocation failed in stc_create        */
+    STC_ERR_ALLOC = 5,       /* host allocation failed in stc_create          */
+    STC_ERR_WORKSPACE = 6,   /* workspace or scratch buffer too small or
+                                misaligned                                    */
+    STC_ERR_NONFINITE = 7    /* non-finite position, vorticity or area        */
 } stc_status;
 
 enum { STC_FP64 = 0, STC_FP32 = 1 };           /* arithmetic of the PP/PC/CP/CC sums   */
@@ -127,11 +137,22 @@ int64_t stc_total_nodes(int32_t max_level);
 /* The depth limit stc_create uses for max_level = -1. */
 int32_t stc_default_max_level(int64_t n_max, int32_t n_crit);
 
+/* Bytes of device workspace a context for these parameters and up to n_max
+ * particles needs (host-only; no device work).  Errors as stc_create. */
+stc_status stc_workspace_size(const stc_params* p, int64_t n_max, size_t* bytes);
+
 /* Creates a context for up to n_max particles: builds the triangle geometry
- * of every node down to max_level on the host (FP64, fixed operation order),
- * the interpolation tables, and allocates all device buffers.  hip_stream is
- * a hipStream_t (NULL = default stream).  On success *out owns the context. */
-stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_ctx** out);
+ * of every node down to max_level on the host (FP64, fixed operation order)
+ * and the interpolation tables, and uploads them into the caller's
+ * workspace d_ws (device memory, 256-byte aligned, at least
+ * stc_workspace_size bytes; STC_ERR_WORKSPACE otherwise), from which every
+ * device buffer of the context is carved.  The workspace stays the caller's:
+ * it must outlive the context and is not touched by anything else while the
+ * context lives.  hip_stream is a hipStream_t (NULL = default stream); the
+ * call synchronises it once after the uploads.  On success *out owns the
+ * host-side context. */
+stc_status stc_create(const stc_params* p, int64_t n_max, void* d_ws, size_t ws_bytes, void* hip_stream,
+                      stc_ctx** out);
 
 /* Ensembles (batching): a context for up to max_members independent particle
  * sets ("members") evaluated together, one kernel launch per phase for all of
@@ -144,9 +165,14 @@ stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_
  * max_level = -1 resolves with n_max_member (the largest member expected).
  * Node ids of member m are (m << node_bits) + local id (stc_node_layout).
  * 1 <= max_members <= STC_MAX_MEMBERS; 2 max_level + 5 + bits(max_members)
- * <= 32.  stc_create(p, n, s, out) is stc_create_batched(p, 1, n, n, s, out). */
+ * <= 32.  stc_create(p, n, ws, b, s, out) is
+ * stc_create_batched(p, 1, n, n, ws, b, s, out); the workspace rules are
+ * stc_create's, with its size from stc_workspace_size_batched. */
+stc_status stc_workspace_size_batched(const stc_params* p, int32_t max_members, int64_t n_max_member,
+                                      int64_t n_max_total, size_t* bytes);
 stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t n_max_member,
-                              int64_t n_max_total, void* hip_stream, stc_ctx** out);
+                              int64_t n_max_total, void* d_ws, size_t ws_bytes, void* hip_stream,
+                              stc_ctx** out);
 
 /* Node id layout: node id = (member << *node_bits) + local id, local ids
  * 0 .. *nodes_per_member - 1 as stc_total_nodes describes; per-node arrays
@@ -154,7 +180,8 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
 stc_status stc_node_layout(const stc_ctx* ctx, int32_t* node_bits, int64_t* nodes_per_member,
                            int64_t* node_array_len);
 
-/* Frees the context and its device buffers (synchronises its stream). */
+/* Frees the host-side context (synchronises its stream first); the caller's
+ * workspace is free for other use afterwards. */
 stc_status stc_destroy(stc_ctx* ctx);
 
 /* Changes the stream later calls are enqueued on. */
@@ -207,18 +234,28 @@ stc_status stc_velocity_batched(stc_ctx* ctx, int32_t members, const int64_t* h_
                                 const double* d_x, const double* d_zeta, const double* d_area,
                                 double* d_u);
 
+/* Bytes of device scratch stc_direct / stc_direct_stream need for m targets
+ * over n sources on the current device (0 when the sum is not split; the
+ * split depends on the device's compute units and the kernel's occupancy).
+ * Host-only.  STC_ERR_INVALID_ARG for bad sizes, precision or denominator. */
+stc_status stc_direct_scratch_size(int64_t n, int64_t m, int32_t precision, int32_t denominator,
+                                   size_t* bytes);
+
 /* Direct O(N^2) sum (Sec. 2, discrete system) for m targets: d_targets (m,)
  * int64 indices into [0, n), or NULL for all (then m must equal n).  Sources
  * are all n particles, the self term excluded by index.  precision STC_FP64
  * or STC_FP32 (FP32 kernel, FP64 accumulation per tile of 256 sources).
  * d_u is (m, 3).  Asynchronous on hip_stream; needs no context.  When m is
  * too small to fill the GPU the sources are split into chunks whose partial
- * sums (chunks x m x 3 doubles, a few MB at most) come from a stream-ordered
- * allocation (hipMallocAsync / hipFreeAsync on hip_stream); the chunks are
- * added in a fixed order, so the result does not vary between calls. */
+ * sums (chunks x m x 3 doubles) go to the caller's scratch d_scratch
+ * (device memory, 8-byte aligned, scratch_bytes >= stc_direct_scratch_size;
+ * STC_ERR_WORKSPACE otherwise; may be NULL when that size is 0); the chunks
+ * are added in a fixed order, so the result does not vary between calls.
+ * The scratch must not be reused before the call's work has completed. */
 stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
                       const double* d_area, int64_t m, const int64_t* d_targets,
-                      int32_t precision, int32_t denominator, double* d_u);
+                      int32_t precision, int32_t denominator, double* d_u,
+                      void* d_scratch, size_t scratch_bytes);
 
 /* Stream function (Sec. 2, stream function and Green's function):
  *   psi_i = (1/4pi) sum_{j != i} zeta_j A_j log(den(x_i, x_j)),
@@ -241,11 +278,11 @@ stc_status stc_stream_function_batched(stc_ctx* ctx, int32_t members, const int6
                                        const double* d_x, const double* d_zeta, const double* d_area,
                                        double* d_psi);
 
-/* Direct O(N m) stream function at m targets, arguments as stc_direct; d_psi
- * holds m FP64 values. */
+/* Direct O(N m) stream function at m targets, arguments (scratch included)
+ * as stc_direct; d_psi holds m FP64 values. */
 stc_status stc_direct_stream(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
                              const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
-                             int32_t denominator, double* d_psi);
+                             int32_t denominator, double* d_psi, void* d_scratch, size_t scratch_bytes);
 
 /* Classical RK4 (Sec. 4) for n_steps steps of dt on (x, zeta):
  *   dx/dt = u(x; zeta A),  dzeta/dt = -2 omega u_z  (Sec. 2, discrete system)
@@ -372,6 +409,32 @@ stc_status stc_mlp_forward(void* hip_stream, int64_t n, const uint16_t* d_x, con
 stc_status stc_mlp_grad(void* hip_stream, int64_t n, const int32_t* d_index, const uint16_t* d_x,
                         const float* d_y, const uint16_t* d_params, float* d_ws, int64_t ws_bytes,
                         float* d_grad, float* d_loss);
+
+/* Label unit of the learned form's training data: 4 pi sqrt(mean_i |u_i|^2)
+ * over n velocities d_u (n, 3) FP64 -- the size of W, the sum that the cross
+ * product with x turns into u -- written to *d_scale (one FP64, device).
+ * Fixed summation order (repeatable).  Asynchronous on hip_stream. */
+stc_status stc_label_scale(void* hip_stream, int64_t n, const double* d_u, double* d_scale);
+
+/* Device workspace bytes stc_mlp_calibrate needs for n samples. */
+int64_t stc_mlp_calibrate_workspace_bytes(int64_t n);
+
+/* Calibration of a trained network's decisions on n labelled samples (d_x
+ * (n, 16) BF16 features, d_y (n, 4) labels as stc_learned_samples writes
+ * them): with o the network's outputs (stc_mlp_forward), da is the smallest
+ * value of the grid {0} + 200 values geometric in [1e-3, 64] at which at
+ * most max_false_accept of all samples are labelled "reject" yet accepted
+ * (o0 - da > 0), and dc the smallest at which at most max_under_class of the
+ * samples labelled "accept" and accepted get fewer ordinal steps than
+ * labelled (#{k: o_k + dc > 0} < y1 + y2 + y3); the grid's largest value if
+ * none meets a bar.  d_params_out receives d_params with b3[0] - da and
+ * b3[1..3] + dc (FP64 shift, rounded to FP32 then BF16, nearest even), and
+ * d_shifts (2 FP64, device) {da, dc}.  d_ws: stc_mlp_calibrate_workspace_bytes
+ * of device scratch (STC_ERR_WORKSPACE if smaller); d_x, d_y, d_ws 16-byte
+ * aligned.  Asynchronous on hip_stream. */
+stc_status stc_mlp_calibrate(void* hip_stream, int64_t n, const uint16_t* d_x, const float* d_y,
+                             const uint16_t* d_params, double max_false_accept, double max_under_class,
+                             void* d_ws, int64_t ws_bytes, uint16_t* d_params_out, double* d_shifts);
 
 /* Adam training on the GPU: `epochs` passes over the n_samples rows in
  * minibatches of `batch` (a seeded bijection of the rows per epoch), each

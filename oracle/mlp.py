@@ -115,6 +115,60 @@ def decide(outputs):
     return o[:, 0] > 0, (o[:, 1:] > 0).sum(1)
 
 
+def calibration_grid():
+    """The bias shifts a calibration tries, in increasing order: 0, then 200
+    values in geometric progression from 1e-3 to 64."""
+    g = np.zeros(201)
+    g[1:] = 1e-3 * (64.0 / 1e-3) ** (np.arange(200) / 199.0)
+    g[-1] = 64.0
+    return g
+
+
+def calibration_shifts(outputs, labels, max_false_accept, max_under_class):
+    """(da, dc): the smallest grid values at which (a) at most
+    max_false_accept of all samples are labelled reject (y0 = 0) but accepted
+    with the acceptance logit lowered by da (o0 - da > 0), and (b) at most
+    max_under_class of the samples labelled accept and still accepted get
+    fewer positive ordinal logits, raised by dc, than their label asks for
+    (y1 + y2 + y3).  The largest grid value when no value meets a bar; 0 when
+    there is nothing to count.  Plain loops over the grid."""
+    o = np.asarray(outputs, dtype=np.float64)
+    y = np.asarray(labels, dtype=np.float64)
+    grid = calibration_grid()
+    n = len(o)
+    if n == 0:
+        return 0.0, 0.0
+    acc = y[:, 0] > 0
+    da = grid[-1]
+    for d in grid:
+        if np.count_nonzero((o[:, 0] - d > 0) & ~acc) / n <= max_false_accept:
+            da = d
+            break
+    keep = acc & (o[:, 0] - da > 0)
+    if not keep.any():
+        return float(da), 0.0
+    need = np.rint(y[keep, 1:].sum(1))
+    dc = grid[-1]
+    for d in grid:
+        under = (o[keep, 1:] + d > 0).sum(1) < need
+        if np.count_nonzero(under) / keep.sum() <= max_under_class:
+            dc = d
+            break
+    return float(da), float(dc)
+
+
+def apply_shifts(param_bits, da, dc):
+    """BF16 parameter bits with b3[0] lowered by da and b3[1..3] raised by dc
+    (the shift in FP64, rounded to FP32 and then to BF16)."""
+    p = from_bf16_bits(param_bits)
+    o = SLICES["b3"][0]
+    p[o] -= da
+    p[o + 1:o + 4] += dc
+    out = np.asarray(param_bits, dtype=np.uint16).copy()
+    out[o:o + 4] = bf16_bits(p[o:o + 4])
+    return out
+
+
 def init_params(seed):
     """He-style random initialisation (used as a starting point in tests)."""
     rng = np.random.Generator(np.random.PCG64(seed))

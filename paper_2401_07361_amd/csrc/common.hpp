@@ -43,6 +43,7 @@ enum Flag : int {
     F_BIN_EXACT = 3,  // points queued for exact point location
     F_ITEMS = 4,      // upward-pass items (pieces of big nodes' particle ranges)
     F_SORT_SPIN = 5,  // a sort's look-back exceeded its spin bound
+    F_NONFINITE_CHARGE = 6,  // a charge zeta A is NaN or infinite
     F_LEVEL = 8,      // F_LEVEL + l: nodes of level l with more than N_T particles (list length)
     F_COUNT = 24
 };

@@ -354,4 +354,27 @@ void launch_resolve(hipStream_t s, const LearnedArgs& a, bool use_model) {
     hipLaunchKernelGGL(k_resolve, dim3(1024), dim3(256), 0, s, a, use_model ? 1 : 0);
 }
 
+// 4 pi sqrt(mean |u_i|^2): the size of W (the sum the cross product with x
+// turns into u), the unit in which label tolerances are given.  One
+// workgroup: strided FP64 sums per thread, then a fixed-order tree.
+__global__ __launch_bounds__(256) void k_label_scale(const double* __restrict__ u, i64 n, double* __restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (i64 i = threadIdx.x; i < n; i += 256) {
+        const double a = u[3 * i], b = u[3 * i + 1], c = u[3 * i + 2];
+        acc += (a * a + b * b) + c * c;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = n > 0 ? 4.0 * 3.141592653589793 * sqrt(red[0] / (double)n) : 0.0;
+}
+
+void launch_label_scale(hipStream_t s, const double* u, i64 n, double* out) {
+    hipLaunchKernelGGL(k_label_scale, dim3(1), dim3(256), 0, s, u, n, out);
+}
+
 }  // namespace stc

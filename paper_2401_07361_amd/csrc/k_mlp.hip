@@ -397,6 +397,91 @@ __global__ __launch_bounds__(256) void k_mlp_round(const float* __restrict__ mas
     if (p < P_N) P[p] = f2bf(master[p]);
 }
 
+// --- calibration of the output biases ---------------------------------------
+// The network's own decisions are shifted so that on the labelled samples at
+// most a given fraction is accepted against its label (b3[0] -= da) and at
+// most a given fraction of the correctly accepted ones gets a lower degree
+// class than labelled (b3[1..3] += dc), da and dc the smallest values of the
+// grid 0, geomspace(1e-3, 64, 200) that meet the bars (the largest if none).
+// Each sample maps to the number of grid values below its threshold, so one
+// histogram per bar gives the violation count of every grid value.
+
+// # of grid values g[k] (ascending) with g[k] < v (strict) or <= v
+__device__ __forceinline__ int grid_rank(const CalibGrid& g, double v, bool inclusive) {
+    int lo = 0, hi = CalibGrid::K;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (inclusive ? (g.d[mid] <= v) : (g.d[mid] < v)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// false accepts: a sample labelled "reject" is accepted at shift d iff o0 - d > 0
+__global__ __launch_bounds__(256) void k_calib_accept(const float* __restrict__ out, const float* __restrict__ y,
+                                                      i64 n, CalibGrid g, u32* __restrict__ hist) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || y[4 * i] > 0.f) return;
+    atomicAdd(&hist[grid_rank(g, (double)out[4 * i], false)], 1u);
+}
+
+// smallest grid index k whose violation count (samples of rank > k) is at
+// most max_rate of the denominator (n, or the count in hist[K + 1]); writes
+// the shift to sel[slot] (one thread: K + 1 bins)
+__global__ void k_calib_select(const u32* __restrict__ hist, i64 n, double max_rate, CalibGrid g, int slot,
+                               double* __restrict__ sel) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double den = n >= 0 ? (double)n : (double)hist[CalibGrid::K + 1];
+    if (!(den > 0.0)) {
+        sel[slot] = 0.0;
+        return;
+    }
+    u64 above = 0;  // samples of rank > k
+    for (int r = 1; r <= CalibGrid::K; ++r) above += hist[r];
+    for (int k = 0; k < CalibGrid::K; ++k) {
+        if ((double)above / den <= max_rate) {
+            sel[slot] = g.d[k];
+            return;
+        }
+        above -= hist[k + 1];
+    }
+    sel[slot] = g.d[CalibGrid::K - 1];
+}
+
+// under-classed: among samples labelled "accept" that the shifted network
+// accepts (o0 > da), one needing `need` ordinal steps gets fewer at shift d
+// iff fewer than `need` of o1..o3 exceed -d, i.e. iff d <= the need-th
+// smallest of -o1..-o3; hist[K + 1] counts the kept samples
+__global__ __launch_bounds__(256) void k_calib_class(const float* __restrict__ out, const float* __restrict__ y,
+                                                     i64 n, CalibGrid g, const double* __restrict__ sel,
+                                                     u32* __restrict__ hist) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !(y[4 * i] > 0.f) || !((double)out[4 * i] > sel[0])) return;
+    atomicAdd(&hist[CalibGrid::K + 1], 1u);
+    const int need = (int)(y[4 * i + 1] + y[4 * i + 2] + y[4 * i + 3] + 0.5f);
+    if (need < 1) return;
+    double v0 = -(double)out[4 * i + 1], v1 = -(double)out[4 * i + 2], v2 = -(double)out[4 * i + 3];
+    if (v0 > v1) { const double t = v0; v0 = v1; v1 = t; }
+    if (v1 > v2) { const double t = v1; v1 = v2; v2 = t; }
+    if (v0 > v1) { const double t = v0; v0 = v1; v1 = t; }
+    const double th = need == 1 ? v0 : (need == 2 ? v1 : v2);
+    atomicAdd(&hist[grid_rank(g, th, true)], 1u);
+}
+
+// shifted parameters: the FP64 shift applied to the BF16 bias, rounded to
+// FP32 and then to BF16 (nearest even both times)
+__global__ __launch_bounds__(256) void k_calib_apply(const u16* __restrict__ P, const double* __restrict__ sel,
+                                                     u16* __restrict__ Q) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P_N) return;
+    u16 v = P[p];
+    if (p >= P_B3) {
+        const double b = (double)bf2f(v) + (p == P_B3 ? -sel[0] : sel[1]);
+        v = f2bf((float)b);
+    }
+    Q[p] = v;
+}
+
 }  // namespace
 
 int mlp_param_count() { return P_N; }
@@ -430,6 +515,28 @@ void launch_mlp_reduce_adam(hipStream_t s, const float* ws, int nwaves, float* g
     const float bc1 = 1.f - powf(beta1, (float)step), bc2 = 1.f - powf(beta2, (float)step);
     hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((P_N + 1 + 255) / 256), dim3(256), 0, s, ws, nwaves, grad, loss,
                        master, m1, m2, P, lr, beta1, beta2, eps, bc1, bc2);
+}
+
+// workspace: network outputs (n x 4 floats), then two histograms of 256 bins
+i64 calib_workspace_bytes(i64 n) { return 16 * n + 2 * 256 * 4; }
+
+void launch_mlp_calibrate(hipStream_t s, const u16* X, const float* Y, i64 n, const u16* P, double max_false_accept,
+                          double max_under_class, void* ws, u16* Q, double* shifts) {
+    CalibGrid g;
+    g.d[0] = 0.0;
+    for (int k = 1; k < CalibGrid::K; ++k)  // geomspace(1e-3, 64, K - 1)
+        g.d[k] = k == CalibGrid::K - 1 ? 64.0 : 1e-3 * pow(64.0 / 1e-3, (double)(k - 1) / (double)(CalibGrid::K - 2));
+    float* out = static_cast<float*>(ws);
+    u32* hist_a = reinterpret_cast<u32*>(static_cast<char*>(ws) + 16 * n);
+    u32* hist_c = hist_a + 256;
+    launch_fill_u32(s, hist_a, 512, 0u);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (n > 0) launch_mlp_forward(s, X, n, nullptr, 0, P, out);
+    if (n > 0) hipLaunchKernelGGL(k_calib_accept, dim3(blocks), dim3(256), 0, s, out, Y, n, g, hist_a);
+    hipLaunchKernelGGL(k_calib_select, dim3(1), dim3(64), 0, s, hist_a, n, max_false_accept, g, 0, shifts);
+    if (n > 0) hipLaunchKernelGGL(k_calib_class, dim3(blocks), dim3(256), 0, s, out, Y, n, g, shifts, hist_c);
+    hipLaunchKernelGGL(k_calib_select, dim3(1), dim3(64), 0, s, hist_c, (i64)-1, max_under_class, g, 1, shifts);
+    hipLaunchKernelGGL(k_calib_apply, dim3((P_N + 255) / 256), dim3(256), 0, s, P, shifts, Q);
 }
 
 void launch_mlp_batch_index(hipStream_t s, i64 n, i64 base, i64 nb, u64 a, u64 c, i32* idx) {

@@ -222,7 +222,8 @@ __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i
                                                   const double* __restrict__ zeta,
                                                   const double* __restrict__ area, const double* __restrict__ sx,
                                                   const double* __restrict__ sy, const double* __restrict__ sz,
-                                                  ForcingDev f, double* __restrict__ q) {
+                                                  ForcingDev f, double* __restrict__ q,
+                                                  u32* __restrict__ flags) {
     const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const i32 j = perm[i];
@@ -232,7 +233,9 @@ __global__ __launch_bounds__(256) void k_charges(const i32* __restrict__ perm, i
         const double a = forcing_ramp(t, f.t_ramp, f.t_total);
         if (a != 0.0) z -= f.amp * a * forcing_shape(f.k, f.tan2_1, sx[i], sy[i], sz[i]);
     }
-    q[i] = z * area[j];
+    const double qi = z * area[j];
+    if (!isfinite(qi)) atomicOr(&flags[F_NONFINITE_CHARGE], 1u);  // reported at synchronisation
+    q[i] = qi;
 }
 
 // F_R(x_i, t) at caller positions (row-major (n, 3)), input order.
@@ -890,9 +893,10 @@ void launch_node_ranges(hipStream_t s, const u32* leaf, i64 n, int L, int NB, i3
 }
 
 void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area,
-                    const double* sx, const double* sy, const double* sz, ForcingDev f, double* q) {
+                    const double* sx, const double* sy, const double* sz, ForcingDev f, double* q, u32* flags) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, sx, sy, sz, f, q);
+    hipLaunchKernelGGL(k_charges, dim3(blocks_for(n, 256)), dim3(256), 0, s, perm, n, zeta, area, sx, sy, sz, f, q,
+                       flags);
 }
 
 void launch_forcing_field(hipStream_t s, i64 n, const double* x, ForcingDev f, double* out) {

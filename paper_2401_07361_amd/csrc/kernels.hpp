@@ -35,8 +35,10 @@ struct ForcingDev {
     double amp, tan2_1, t_ramp, t_total, t_base;
     const double* t_dev;
 };
+// q = zeta A in tree order (forced: (zeta - F_R) A); a non-finite charge
+// raises flags[F_NONFINITE_CHARGE]
 void launch_charges(hipStream_t s, const i32* perm, i64 n, const double* zeta, const double* area,
-                    const double* sx, const double* sy, const double* sz, ForcingDev f, double* q);
+                    const double* sx, const double* sy, const double* sz, ForcingDev f, double* q, u32* flags);
 // F_R(x_i, f.t_base) at n positions in input order
 void launch_forcing_field(hipStream_t s, i64 n, const double* x, ForcingDev f, double* out);
 // single-thread update of the forcing clock: *t = set ? value : *t + value
@@ -160,6 +162,20 @@ void launch_mlp_reduce_adam(hipStream_t s, const float* ws, int nwaves, float* g
                             float* m1, float* m2, u16* P, float lr, float beta1, float beta2, float eps, int step);
 void launch_mlp_batch_index(hipStream_t s, i64 n, i64 base, i64 nb, u64 a, u64 c, i32* idx);
 void launch_mlp_round(hipStream_t s, const float* master, u16* P);
+// the bias-shift grid of the calibration: 0, then 200 values geometric in [1e-3, 64]
+struct CalibGrid {
+    static constexpr int K = 201;
+    double d[K];
+};
+// device workspace bytes of launch_mlp_calibrate for n samples
+i64 calib_workspace_bytes(i64 n);
+// output-bias calibration (all on the device): Q = P with b3[0] -= da and
+// b3[1..3] += dc, shifts = {da, dc}
+void launch_mlp_calibrate(hipStream_t s, const u16* X, const float* Y, i64 n, const u16* P, double max_false_accept,
+                          double max_under_class, void* ws, u16* Q, double* shifts);
+// 4 pi sqrt(mean |u_i|^2) over n velocities (n, 3), to *out (one workgroup,
+// fixed summation order)
+void launch_label_scale(hipStream_t s, const double* u, i64 n, double* out);
 
 // k_learned.hip -- gated traversal of the learned form (single member)
 struct LearnedArgs {

@@ -14,6 +14,9 @@
 
 using namespace stc;
 
+// alignment of the caller's workspace and of every buffer carved from it
+constexpr size_t kWorkspaceAlign = 256;
+
 struct stc_ctx {
     stc_params p{};
     int L = 0, np = 0, W = 0;
@@ -52,7 +55,7 @@ struct stc_ctx {
     double* ref_T = nullptr;      // degree-10 -> lower-degree re-interpolation matrices
     const uint16_t* model = nullptr;  // BF16 network parameters (caller's), or null: reject every candidate
     std::vector<i64> level_off_host;
-    // device buffers (all allocated in stc_create)
+    // device buffers (all carved from the caller's workspace in stc_create)
     NodeGeo* geo = nullptr;
     NodeMac* mac = nullptr;
     i32* ncnt = nullptr;
@@ -100,7 +103,8 @@ struct stc_ctx {
     i64 n = -1;
     const double* x = nullptr;
     bool have_tree = false, have_upward = false, have_lists = false;
-    std::vector<void*> allocs;
+    void* ws = nullptr;     // the caller's workspace (all device buffers)
+    size_t ws_bytes = 0;
     std::string err;
 };
 
@@ -109,7 +113,9 @@ static void rk4_drop_graph(stc_ctx* c);
 namespace {
 
 const char* kStatusText[] = {"ok", "invalid argument", "interaction list capacity exceeded", "HIP device error",
-                             "call out of order", "device allocation failed"};
+                             "call out of order", "host allocation failed",
+                             "workspace or scratch buffer too small or misaligned",
+                             "non-finite particle position, vorticity or area"};
 
 // Records the event that opens `phase` (and closes the previous one) of the
 // evaluation being recorded.  Phase 6 closes the evaluation.
@@ -134,15 +140,20 @@ stc_status check_launch(stc_ctx* c, const char* where) {
     return STC_OK;
 }
 
-template <typename T>
-bool dalloc(stc_ctx* c, T** p, size_t count) {
-    if (count == 0) count = 1;
-    void* ptr = nullptr;
-    if (hipMalloc(&ptr, count * sizeof(T)) != hipSuccess) return false;
-    c->allocs.push_back(ptr);
-    *p = static_cast<T*>(ptr);
-    return true;
-}
+// Device buffers of a context, carved from the caller's workspace one after
+// the other, each at a 256-byte boundary.  With base null only the total
+// size is computed (stc_workspace_size).
+struct Carver {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    void take(T** p, size_t count) {
+        if (count == 0) count = 1;
+        off = (off + kWorkspaceAlign - 1) & ~(kWorkspaceAlign - 1);
+        if (base) *p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+    }
+};
 
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
@@ -343,7 +354,7 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area, boo
     ForcingDev f{};
     if (c->forcing_on)
         f = stage_clock ? forcing_dev(c->forcing, t_off, c->forcing_t) : forcing_dev(c->forcing, c->forcing.time, nullptr);
-    launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sx, c->sy, c->sz, f, c->sq);
+    launch_charges(s, c->perm, c->n, d_zeta, d_area, c->sx, c->sy, c->sz, f, c->sq, c->flags);
     if (c->n > 0) {
         // the highest class from the particles; the others (learned form) by
         // re-interpolating each node's own record of the highest class
@@ -525,53 +536,9 @@ __global__ void k_rk4_finish(i64 n, const double* __restrict__ xacc, const doubl
     z[i] = zacc[i];
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* stc_status_string(int32_t status) {
-    if (status < 0 || status > 5) return "unknown status";
-    return kStatusText[status];
-}
-
-stc_status stc_default_params(stc_params* p) {
-    if (!p) return STC_ERR_INVALID_ARG;
-    std::memset(p, 0, sizeof(*p));
-    p->theta = 0.7;
-    p->degree = 8;
-    p->n_crit = 64;
-    p->max_level = -1;
-    p->precision = STC_FP64;
-    p->denominator = STC_DEN_DOT;
-    p->list_capacity = 0;
-    return STC_OK;
-}
-
-int32_t stc_n_basis(int32_t degree) {
-    if (degree < 1 || degree > kMaxDegree) return 0;
-    return (degree + 1) * (degree + 2) / 2;
-}
-
-int64_t stc_total_nodes(int32_t max_level) {
-    if (max_level < 0 || max_level > 12) return 0;
-    return stc::total_nodes(max_level);
-}
-
-int32_t stc_default_max_level(int64_t n_max, int32_t n_crit) {
-    if (n_crit < 1) n_crit = 1;
-    int lvl = 0;
-    while ((i64)20 * ((i64)1 << (2 * lvl)) * n_crit < n_max && lvl < 30) ++lvl;
-    return std::min(12, lvl + 2);
-}
-
-stc_status stc_create(const stc_params* p, int64_t n_max, void* hip_stream, stc_ctx** out) {
-    return stc_create_batched(p, 1, n_max, n_max, hip_stream, out);
-}
-
-stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t n_max_member, int64_t n_max_total,
-                              void* hip_stream, stc_ctx** out) {
-    if (!out) return STC_ERR_INVALID_ARG;
-    *out = nullptr;
+// Sizes of a context's tables and buffers from its parameters (no device
+// work, no host tables).
+stc_status plan(stc_ctx* c, const stc_params* p, int32_t max_members, int64_t n_max_member, int64_t n_max_total) {
     stc_status st = validate_params(p, n_max_total);
     if (st != STC_OK) return st;
     if (max_members < 1 || max_members > STC_MAX_MEMBERS || n_max_member < 0 || n_max_member > n_max_total)
@@ -583,13 +550,10 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     const int NB = std::max(1, bits_for(stc::total_nodes(L)));
     // leaf keys (member, face, 2L digits) are 32-bit; list keys hold two node ids and a type bit
     if (2 * L + 5 + mbits > 32 || NB + mbits > 31) return STC_ERR_INVALID_ARG;
-    stc_ctx* c = new (std::nothrow) stc_ctx();
-    if (!c) return STC_ERR_ALLOC;
     c->p = *p;
     c->n_max = n_max_total;
     c->n_max_member = n_max_member;
     c->max_members = max_members;
-    c->stream = static_cast<hipStream_t>(hip_stream);
     c->L = L;
     c->p.max_level = c->L;
     c->np = stc_n_basis(p->degree);
@@ -627,6 +591,181 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     c->cap = (u32)std::min<i64>(cap, 0x7fffffffLL);
     // items: one per big node plus one per UP_CHUNK particles on each level
     c->items_cap = (u32)std::min<i64>((i64)c->slot_cap + (i64)(c->L + 1) * (nm / UP_CHUNK + 1), 0x7fffffffLL);
+    c->hist_blocks = (int)((std::max<i64>(c->cap, nm) + 4095) / 4096);
+    return STC_OK;
+}
+
+// Every device buffer of a context, in workspace order.
+void carve(stc_ctx* c, Carver& cv) {
+    const size_t nm = (size_t)std::max<i64>(c->n_max, 1), NPT = (size_t)c->NPT, ns = c->slot_cap;
+    const size_t ngeo = (size_t)stc::total_nodes(c->L), nnodes = (size_t)c->n_nodes;
+    size_t nq = 0;
+    for (int k = 0; k < c->ndeg; ++k) nq += (size_t)c->cls.np[k] * c->cls.np[k];
+    const size_t nseg = nnodes << c->DB;
+    cv.take(&c->geo, ngeo);
+    cv.take(&c->mac, ngeo);
+    cv.take(&c->ncnt, nnodes);
+    cv.take(&c->slot, nnodes);
+    cv.take(&c->big_list, (size_t)(c->L + 1) * c->per_level);
+    cv.take(&c->level_off, (size_t)c->L + 2);
+    cv.take(&c->ref_points, 3 * NPT);
+    cv.take(&c->ref_vinv, nq);
+    cv.take(&c->ref_vinvT, nq);
+    cv.take(&c->ref_coef, NPT);
+    cv.take(&c->ref_expo, 3 * NPT);
+    cv.take(&c->keys_a, nm);
+    cv.take(&c->keys_b, nm);
+    cv.take(&c->perm, nm);
+    cv.take(&c->leaf, nm);
+    cv.take(&c->sx, nm);
+    cv.take(&c->sy, nm);
+    cv.take(&c->sz, nm);
+    cv.take(&c->sq, nm);
+    cv.take(&c->nbeg, nnodes);
+    cv.take(&c->nend, nnodes);
+    cv.take(&c->prox, ns * NPT);
+    cv.take(&c->alpha, ns * NPT * 3);
+    cv.take(&c->Wacc, 3 * nm);
+    cv.take(&c->front0, c->cap);
+    cv.take(&c->front1, c->cap);
+    cv.take(&c->tlist_a, c->cap);
+    cv.take(&c->tlist_b, c->cap);
+    cv.take(&c->nlist_a, c->cap);
+    cv.take(&c->nlist_b, c->cap);
+    cv.take(&c->tseg_beg, nnodes);
+    cv.take(&c->tseg_end, nnodes);
+    cv.take(&c->nseg_beg, nseg);
+    cv.take(&c->nseg_end, nseg);
+    cv.take(&c->counters, C_COUNT);
+    cv.take(&c->flags, F_COUNT);
+    cv.take(&c->evals, 8);
+    cv.take(&c->sort_zero, kSortZeroWords);
+    cv.take(&c->sort_status, (size_t)2 * 256 * c->hist_blocks);
+    cv.take(&c->sort_epoch, 2);
+    cv.take(&c->rk_x, 3 * nm);
+    cv.take(&c->rk_z, nm);
+    cv.take(&c->rk_u, 3 * nm);
+    cv.take(&c->rk_xacc, 3 * nm);
+    cv.take(&c->rk_zacc, nm);
+    cv.take(&c->forcing_t, 1);
+    cv.take(&c->item_node, c->items_cap);
+    cv.take(&c->item_chunk, c->items_cap);
+    cv.take(&c->item_base, ns);
+    cv.take(&c->upart, (size_t)c->items_cap * c->cls.np[c->ndeg - 1]);
+    if (c->learned) {
+        cv.take(&c->ref_T, (size_t)c->cls.poff[3] * c->cls.np[3]);
+        cv.take(&c->cand, c->cap);
+        cv.take(&c->feat, (size_t)c->cap * 16);
+        cv.take(&c->mlp_out, (size_t)c->cap * 4);
+        cv.take(&c->qabs, nnodes);
+        cv.take(&c->qsum, nnodes);
+    }
+}
+
+}  // namespace
+
+namespace {
+// Source chunks of a direct sum of m targets over n sources on the current
+// device and the bytes of their partial sums (0 when unsplit).
+stc_status direct_plan(i64 n, i64 m, int32_t precision, int32_t denominator, u32* chunks, i64* chunk_len,
+                       size_t* bytes) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+        return STC_ERR_DEVICE;
+    direct_split(n, m, cus, direct_blocks_per_cu(precision, denominator), direct_targets_per_block(precision), chunks,
+                 chunk_len);
+    *bytes = *chunks > 1 ? (size_t)*chunks * (size_t)m * 3 * sizeof(double) : 0;
+    return STC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* stc_status_string(int32_t status) {
+    if (status < 0 || status > 7) return "unknown status";
+    return kStatusText[status];
+}
+
+stc_status stc_default_params(stc_params* p) {
+    if (!p) return STC_ERR_INVALID_ARG;
+    std::memset(p, 0, sizeof(*p));
+    p->theta = 0.7;
+    p->degree = 8;
+    p->n_crit = 64;
+    p->max_level = -1;
+    p->precision = STC_FP64;
+    p->denominator = STC_DEN_DOT;
+    p->list_capacity = 0;
+    return STC_OK;
+}
+
+int32_t stc_n_basis(int32_t degree) {
+    if (degree < 1 || degree > kMaxDegree) return 0;
+    return (degree + 1) * (degree + 2) / 2;
+}
+
+int64_t stc_total_nodes(int32_t max_level) {
+    if (max_level < 0 || max_level > 12) return 0;
+    return stc::total_nodes(max_level);
+}
+
+int32_t stc_default_max_level(int64_t n_max, int32_t n_crit) {
+    if (n_crit < 1) n_crit = 1;
+    int lvl = 0;
+    while ((i64)20 * ((i64)1 << (2 * lvl)) * n_crit < n_max && lvl < 30) ++lvl;
+    return std::min(12, lvl + 2);
+}
+
+stc_status stc_create(const stc_params* p, int64_t n_max, void* d_ws, size_t ws_bytes, void* hip_stream,
+                      stc_ctx** out) {
+    return stc_create_batched(p, 1, n_max, n_max, d_ws, ws_bytes, hip_stream, out);
+}
+
+stc_status stc_workspace_size(const stc_params* p, int64_t n_max, size_t* bytes) {
+    return stc_workspace_size_batched(p, 1, n_max, n_max, bytes);
+}
+
+stc_status stc_workspace_size_batched(const stc_params* p, int32_t max_members, int64_t n_max_member,
+                                      int64_t n_max_total, size_t* bytes) {
+    if (!bytes) return STC_ERR_INVALID_ARG;
+    *bytes = 0;
+    stc_ctx* c = new (std::nothrow) stc_ctx();
+    if (!c) return STC_ERR_ALLOC;
+    stc_status st = plan(c, p, max_members, n_max_member, n_max_total);
+    if (st == STC_OK) {
+        Carver cv;
+        carve(c, cv);
+        *bytes = cv.off;
+    }
+    delete c;
+    return st;
+}
+
+stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t n_max_member, int64_t n_max_total,
+                              void* d_ws, size_t ws_bytes, void* hip_stream, stc_ctx** out) {
+    if (!out) return STC_ERR_INVALID_ARG;
+    *out = nullptr;
+    stc_ctx* c = new (std::nothrow) stc_ctx();
+    if (!c) return STC_ERR_ALLOC;
+    stc_status st = plan(c, p, max_members, n_max_member, n_max_total);
+    if (st != STC_OK) {
+        delete c;
+        return st;
+    }
+    {
+        Carver cv;
+        carve(c, cv);
+        if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & (kWorkspaceAlign - 1)) || ws_bytes < cv.off) {
+            delete c;
+            return STC_ERR_WORKSPACE;
+        }
+        cv = Carver{static_cast<char*>(d_ws), 0};
+        carve(c, cv);
+        c->ws = d_ws;
+        c->ws_bytes = ws_bytes;
+    }
+    c->stream = static_cast<hipStream_t>(hip_stream);
     try {
         build_tree_geometry(c->L, c->geo_host);
         for (int k = 0; k < c->ndeg; ++k)
@@ -640,40 +779,6 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     }
     c->level_off_host.resize(c->L + 2);
     for (int l = 0; l <= c->L + 1; ++l) c->level_off_host[l] = level_offset(l);
-    c->hist_blocks = (int)((std::max<i64>(c->cap, nm) + 4095) / 4096);
-    const size_t NPT = (size_t)c->NPT, ns = c->slot_cap;
-    size_t nq = 0;
-    for (int k = 0; k < c->ndeg; ++k) nq += (size_t)c->cls.np[k] * c->cls.np[k];
-    const i64 nseg = c->n_nodes << c->DB;
-    bool ok = dalloc(c, &c->geo, c->geo_host.size()) && dalloc(c, &c->mac, c->geo_host.size()) &&
-              dalloc(c, &c->ncnt, c->n_nodes) && dalloc(c, &c->slot, c->n_nodes) &&
-              dalloc(c, &c->big_list, (size_t)(c->L + 1) * c->per_level) &&
-              dalloc(c, &c->level_off, c->level_off_host.size()) && dalloc(c, &c->ref_points, 3 * NPT) &&
-              dalloc(c, &c->ref_vinv, nq) && dalloc(c, &c->ref_vinvT, nq) && dalloc(c, &c->ref_coef, NPT) &&
-              dalloc(c, &c->ref_expo, 3 * NPT) && dalloc(c, &c->keys_a, nm) && dalloc(c, &c->keys_b, nm) &&
-              dalloc(c, &c->perm, nm) && dalloc(c, &c->leaf, nm) && dalloc(c, &c->sx, nm) && dalloc(c, &c->sy, nm) &&
-              dalloc(c, &c->sz, nm) && dalloc(c, &c->sq, nm) && dalloc(c, &c->nbeg, c->n_nodes) &&
-              dalloc(c, &c->nend, c->n_nodes) && dalloc(c, &c->prox, ns * NPT) && dalloc(c, &c->alpha, ns * NPT * 3) &&
-              dalloc(c, &c->Wacc, 3 * nm) && dalloc(c, &c->front0, c->cap) && dalloc(c, &c->front1, c->cap) &&
-              dalloc(c, &c->tlist_a, c->cap) && dalloc(c, &c->tlist_b, c->cap) && dalloc(c, &c->nlist_a, c->cap) &&
-              dalloc(c, &c->nlist_b, c->cap) && dalloc(c, &c->tseg_beg, c->n_nodes) &&
-              dalloc(c, &c->tseg_end, c->n_nodes) && dalloc(c, &c->nseg_beg, nseg) &&
-              dalloc(c, &c->nseg_end, nseg) && dalloc(c, &c->counters, C_COUNT) &&
-              dalloc(c, &c->flags, F_COUNT) && dalloc(c, &c->evals, 8) &&
-              dalloc(c, &c->sort_zero, kSortZeroWords) &&
-              dalloc(c, &c->sort_status, (size_t)2 * 256 * c->hist_blocks) && dalloc(c, &c->sort_epoch, 2) &&
-              dalloc(c, &c->rk_x, 3 * nm) && dalloc(c, &c->rk_z, nm) && dalloc(c, &c->rk_u, 3 * nm) &&
-              dalloc(c, &c->rk_xacc, 3 * nm) && dalloc(c, &c->rk_zacc, nm) && dalloc(c, &c->forcing_t, 1) &&
-              dalloc(c, &c->item_node, c->items_cap) && dalloc(c, &c->item_chunk, c->items_cap) &&
-              dalloc(c, &c->item_base, ns) && dalloc(c, &c->upart, (size_t)c->items_cap * c->cls.np[c->ndeg - 1]);
-    if (ok && learned)
-        ok = dalloc(c, &c->ref_T, (size_t)c->cls.poff[3] * c->cls.np[3]) && dalloc(c, &c->cand, c->cap) && dalloc(c, &c->feat, (size_t)c->cap * 16) &&
-             dalloc(c, &c->mlp_out, (size_t)c->cap * 4) && dalloc(c, &c->qabs, c->n_nodes) &&
-             dalloc(c, &c->qsum, c->n_nodes);
-    if (!ok) {
-        stc_destroy(c);
-        return STC_ERR_ALLOC;
-    }
     c->tlist = c->tlist_a;
     c->nlist = c->nlist_a;
     hipStream_t s = c->stream;
@@ -711,7 +816,7 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     // learned form: T[(poff_c + m) * 66 + n] = sum_k (V_ref,d^{-1})_km B_k(b_10,n),
     // degree-10 point charges -> degree-d (classes 0..2), in long double
     std::vector<double> T_h;
-    if (learned) {
+    if (c->learned) {
         const RefTables& t10 = c->ref_host[3];
         for (int k = 0; k < 3; ++k) {
             const RefTables& td = c->ref_host[k];
@@ -752,7 +857,6 @@ stc_status stc_destroy(stc_ctx* c) {
     rk4_drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
-    for (void* p : c->allocs) (void)hipFree(p);
     delete c;
     return STC_OK;
 }
@@ -843,53 +947,64 @@ stc_status stc_velocity_batched(stc_ctx* c, int32_t members, const int64_t* h_of
     return st;
 }
 
-static stc_status direct_sum(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
-                             const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
-                             int32_t denominator, double* d_u, bool stream) {
+static stc_status direct_check(int64_t n, int64_t m, int32_t precision, int32_t denominator) {
     if (n < 0 || m < 0 || n >= 0x7fffffffLL) return STC_ERR_INVALID_ARG;
     if (precision != STC_FP64 && precision != STC_FP32) return STC_ERR_INVALID_ARG;
     if (denominator != STC_DEN_DOT && denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
     if (precision == STC_FP32 && denominator != STC_DEN_DIST2) return STC_ERR_INVALID_ARG;
+    return STC_OK;
+}
+
+static stc_status direct_sum(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
+                             const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
+                             int32_t denominator, double* d_u, bool stream, void* d_scratch, size_t scratch_bytes) {
+    stc_status st = direct_check(n, m, precision, denominator);
+    if (st != STC_OK) return st;
     if (!d_targets && m != n) return STC_ERR_INVALID_ARG;
     if (m == 0) return STC_OK;
     if (n == 0 || !d_x || !d_zeta || !d_area || !d_u || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area) ||
         !aligned8(d_u) || (d_targets && !aligned8(d_targets)))
         return STC_ERR_INVALID_ARG;
-    // Few targets cannot fill the chip: split the sources into chunks whose
-    // partial sums live in a stream-ordered allocation, released on the same
-    // stream after the fixed-order reduction.  If that allocation fails the
-    // sum runs unsplit.
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // Few targets cannot fill the chip: the sources are split into chunks
+    // whose partial sums go to the caller's scratch and are added in chunk
+    // order by a second kernel.
     u32 chunks = 1;
     i64 chunk_len = n;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                 hipSuccess)
-        return STC_ERR_DEVICE;
-    direct_split(n, m, cus, direct_blocks_per_cu(precision, denominator), direct_targets_per_block(precision), &chunks,
-                 &chunk_len);
+    size_t bytes = 0;
+    st = direct_plan(n, m, precision, denominator, &chunks, &chunk_len, &bytes);
+    if (st != STC_OK) return st;
     double* part = nullptr;
-    if (chunks > 1 && hipMallocAsync(reinterpret_cast<void**>(&part), (size_t)chunks * (size_t)m * 3 * sizeof(double),
-                                     s) != hipSuccess) {
-        (void)hipGetLastError();
-        part = nullptr;
+    if (bytes > 0) {
+        if (!d_scratch || !aligned8(d_scratch) || scratch_bytes < bytes) return STC_ERR_WORKSPACE;
+        part = static_cast<double*>(d_scratch);
     }
-    launch_direct(s, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, chunks, chunk_len, part, d_u,
-                  stream ? 1 : 0);
-    const hipError_t le = hipGetLastError();
-    if (part && hipFreeAsync(part, s) != hipSuccess) return STC_ERR_DEVICE;
-    return le == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+    launch_direct(static_cast<hipStream_t>(hip_stream), n, d_x, d_zeta, d_area, m, d_targets, precision, denominator,
+                  chunks, chunk_len, part, d_u, stream ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
+stc_status stc_direct_scratch_size(int64_t n, int64_t m, int32_t precision, int32_t denominator, size_t* bytes) {
+    if (!bytes) return STC_ERR_INVALID_ARG;
+    *bytes = 0;
+    stc_status st = direct_check(n, m, precision, denominator);
+    if (st != STC_OK || n == 0 || m == 0) return st;
+    u32 chunks = 1;
+    i64 chunk_len = n;
+    return direct_plan(n, m, precision, denominator, &chunks, &chunk_len, bytes);
 }
 
 stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
-                      int64_t m, const int64_t* d_targets, int32_t precision, int32_t denominator, double* d_u) {
-    return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_u, false);
+                      int64_t m, const int64_t* d_targets, int32_t precision, int32_t denominator, double* d_u,
+                      void* d_scratch, size_t scratch_bytes) {
+    return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_u, false,
+                      d_scratch, scratch_bytes);
 }
 
 stc_status stc_direct_stream(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
                              const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
-                             int32_t denominator, double* d_psi) {
-    return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_psi, true);
+                             int32_t denominator, double* d_psi, void* d_scratch, size_t scratch_bytes) {
+    return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_psi, true,
+                      d_scratch, scratch_bytes);
 }
 
 stc_status stc_stream_function(stc_ctx* c, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
@@ -1264,6 +1379,30 @@ int64_t stc_mlp_workspace_bytes(int64_t n_batch) {
     return (int64_t)mlp_workspace_floats(n_batch) * (int64_t)sizeof(float);
 }
 
+int64_t stc_mlp_calibrate_workspace_bytes(int64_t n) { return n < 0 ? 0 : (int64_t)calib_workspace_bytes(n); }
+
+stc_status stc_mlp_calibrate(void* hip_stream, int64_t n, const uint16_t* d_x, const float* d_y,
+                             const uint16_t* d_params, double max_false_accept, double max_under_class, void* d_ws,
+                             int64_t ws_bytes, uint16_t* d_params_out, double* d_shifts) {
+    if (n < 0 || n > 0x7fffffffLL || !d_params || !d_params_out || !d_shifts || !d_ws) return STC_ERR_INVALID_ARG;
+    if (n > 0 && (!d_x || !d_y)) return STC_ERR_INVALID_ARG;
+    if (!(max_false_accept >= 0.0 && max_false_accept <= 1.0) || !(max_under_class >= 0.0 && max_under_class <= 1.0))
+        return STC_ERR_INVALID_ARG;
+    if ((reinterpret_cast<uintptr_t>(d_x) & 15u) || (reinterpret_cast<uintptr_t>(d_y) & 15u) ||
+        (reinterpret_cast<uintptr_t>(d_ws) & 15u) || !aligned8(d_shifts))
+        return STC_ERR_INVALID_ARG;
+    if (ws_bytes < stc_mlp_calibrate_workspace_bytes(n)) return STC_ERR_WORKSPACE;
+    launch_mlp_calibrate(static_cast<hipStream_t>(hip_stream), d_x, d_y, n, d_params, max_false_accept,
+                         max_under_class, d_ws, d_params_out, d_shifts);
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
+stc_status stc_label_scale(void* hip_stream, int64_t n, const double* d_u, double* d_scale) {
+    if (n < 0 || !d_scale || !aligned8(d_scale) || (n > 0 && (!d_u || !aligned8(d_u)))) return STC_ERR_INVALID_ARG;
+    launch_label_scale(static_cast<hipStream_t>(hip_stream), d_u, n, d_scale);
+    return hipGetLastError() == hipSuccess ? STC_OK : STC_ERR_DEVICE;
+}
+
 stc_status stc_mlp_forward(void* hip_stream, int64_t n, const uint16_t* d_x, const uint16_t* d_params, float* d_out) {
     if (n < 0 || (n > 0 && (!d_x || !d_params || !d_out))) return STC_ERR_INVALID_ARG;
     if ((reinterpret_cast<uintptr_t>(d_x) & 15u) || (reinterpret_cast<uintptr_t>(d_out) & 15u)) return STC_ERR_INVALID_ARG;
@@ -1341,7 +1480,8 @@ stc_status stc_sync(stc_ctx* c) {
     if (h[C_OVERFLOW] || h[C_TLIST] > c->cap || h[C_NLIST] > c->cap)
         return fail(c, STC_ERR_CAPACITY, "interaction list or frontier exceeded list_capacity");
     if (f[F_SLOTS]) return fail(c, STC_ERR_CAPACITY, "proxy storage slots exceeded");
-    if (f[F_NONFINITE]) return fail(c, STC_ERR_INVALID_ARG, "non-finite particle position");
+    if (f[F_NONFINITE]) return fail(c, STC_ERR_NONFINITE, "non-finite particle position");
+    if (f[F_NONFINITE_CHARGE]) return fail(c, STC_ERR_NONFINITE, "non-finite vorticity or area (charge zeta A)");
     if (f[F_SORT_SPIN]) return fail(c, STC_ERR_DEVICE, "a sort's look-back exceeded its spin bound");
     return STC_OK;
 }

@@ -3,9 +3,11 @@
 The training data are measured by the tree code itself: for each input,
 stc_learned_samples takes the candidates of the wider criterion theta_max,
 measures every candidate's error at the four degrees against its exact pair
-sum and labels it against a tolerance; stc_mlp_train then runs Adam with the
-library's BF16 forward and backward kernels.  This module only sequences
-those calls over a set of inputs (device tensors the caller provides).
+sum and labels it against a tolerance (relative to stc_label_scale of the
+fixed-degree velocity); stc_mlp_train then runs Adam with the library's BF16
+forward and backward kernels, and stc_mlp_calibrate shifts the output biases.
+This module only sequences those calls over a set of inputs (device tensors
+the caller provides).
 """
 
 import numpy as np
@@ -14,10 +16,10 @@ from . import stc
 
 
 def velocity_scale(u):
-    """4 pi times the root mean square speed: the size of W (the sum before
-    the cross product), the unit the label tolerance is given in."""
-    un = u.double().cpu().numpy()
-    return 4.0 * np.pi * float(np.sqrt((un * un).sum(1).mean()))
+    """4 pi times the root mean square speed (stc_label_scale): the size of W
+    (the sum before the cross product), the unit the label tolerance is given
+    in."""
+    return float(stc.label_scale(u).item())
 
 
 def collect(inputs, tol_rel, theta, theta_max, degree=10, n_crit=64, cap_per_input=None, log=None):
@@ -61,27 +63,11 @@ def train(features, labels, epochs=8, batch=4096, lr=2e-3, seed=0, init_seed=1):
 
 
 def calibrate(features, labels, params, max_false_accept=1e-3, max_under_class=1e-3):
-    """Shifts the output biases so that, on the given samples, at most
-    max_false_accept of them are accepted against their label and at most
-    max_under_class of the correctly accepted ones get a lower degree class
-    than labelled: b3[0] -= delta_a, b3[1..3] += delta_c with the smallest
-    such deltas.  Returns new BF16 parameters and the two shifts."""
-    import torch
-    out = stc.mlp_forward(features, params).cpu().numpy().astype(np.float64)
-    y = labels.cpu().numpy()
-    acc = y[:, 0] > 0
-    need = y[:, 1:].sum(1)
-    deltas = np.concatenate([[0.0], np.geomspace(1e-3, 64.0, 200)])
-    da = next((d for d in deltas if ((out[:, 0] - d > 0) & ~acc).mean() <= max_false_accept), deltas[-1])
-    keep = acc & (out[:, 0] - da > 0)
-    dc = 0.0
-    if keep.any():
-        dc = next((d for d in deltas
-                   if ((out[keep, 1:] + d > 0).sum(1) < need[keep]).mean() <= max_under_class), deltas[-1])
-    p = params.float().cpu().numpy().astype(np.float64)
-    p[5248] -= da
-    p[5249:5252] += dc
-    bits = np.asarray(p, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    bits = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype(np.int16)
-    newp = torch.from_numpy(bits).to(params.device).view(torch.bfloat16)
+    """Shifts the output biases (stc_mlp_calibrate) so that, on the given
+    samples, at most max_false_accept of them are accepted against their
+    label and at most max_under_class of the correctly accepted ones get a
+    lower degree class than labelled.  Returns new BF16 parameters and the two
+    shifts."""
+    newp, shifts = stc.mlp_calibrate(features, labels, params, max_false_accept, max_under_class)
+    da, dc = shifts.cpu().tolist()
     return newp, float(da), float(dc)

@@ -62,6 +62,7 @@ def _load():
                           "(or __graft_entry__.build())")
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, D, VP = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    SZ = ctypes.c_size_t
     PI64 = ctypes.POINTER(ctypes.c_int64)
     PD = ctypes.POINTER(ctypes.c_double)
     PI32 = ctypes.POINTER(ctypes.c_int32)
@@ -71,8 +72,11 @@ def _load():
         "stc_n_basis": (I32, [I32]),
         "stc_total_nodes": (I64, [I32]),
         "stc_default_max_level": (I32, [I64, I32]),
-        "stc_create": (I32, [ctypes.POINTER(Params), I64, VP, ctypes.POINTER(P)]),
-        "stc_create_batched": (I32, [ctypes.POINTER(Params), I32, I64, I64, VP, ctypes.POINTER(P)]),
+        "stc_workspace_size": (I32, [ctypes.POINTER(Params), I64, ctypes.POINTER(SZ)]),
+        "stc_workspace_size_batched": (I32, [ctypes.POINTER(Params), I32, I64, I64, ctypes.POINTER(SZ)]),
+        "stc_create": (I32, [ctypes.POINTER(Params), I64, VP, SZ, VP, ctypes.POINTER(P)]),
+        "stc_create_batched": (I32, [ctypes.POINTER(Params), I32, I64, I64, VP, SZ, VP, ctypes.POINTER(P)]),
+        "stc_direct_scratch_size": (I32, [I64, I64, I32, I32, ctypes.POINTER(SZ)]),
         "stc_node_layout": (I32, [P, PI32, PI64, PI64]),
         "stc_tree_build_batched": (I32, [P, I32, PI64, VP]),
         "stc_velocity_batched": (I32, [P, I32, PI64, VP, VP, VP, VP]),
@@ -87,6 +91,9 @@ def _load():
         "stc_mlp_param_count": (I32, []),
         "stc_mlp_workspace_bytes": (I64, [I64]),
         "stc_mlp_forward": (I32, [VP, I64, VP, VP, VP]),
+        "stc_mlp_calibrate_workspace_bytes": (I64, [I64]),
+        "stc_mlp_calibrate": (I32, [VP, I64, VP, VP, VP, D, D, VP, I64, VP, VP]),
+        "stc_label_scale": (I32, [VP, I64, VP, VP]),
         "stc_mlp_grad": (I32, [VP, I64, VP, VP, VP, VP, VP, I64, VP, VP]),
         "stc_mlp_train": (I32, [VP, I64, VP, VP, I32, I32, ctypes.c_float, ctypes.c_uint64, VP, VP, VP, VP, VP, VP,
                                 I64, VP]),
@@ -99,11 +106,11 @@ def _load():
         "stc_eval_near": (I32, [P, VP, I32]),
         "stc_eval_far": (I32, [P, VP, I32]),
         "stc_velocity": (I32, [P, I64, VP, VP, VP, VP]),
-        "stc_direct": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
+        "stc_direct": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP, VP, SZ]),
         "stc_rk4": (I32, [P, I64, VP, VP, VP, D, D, I32]),
         "stc_stream_function": (I32, [P, I64, VP, VP, VP, VP]),
         "stc_stream_function_batched": (I32, [P, I32, PI64, VP, VP, VP, VP]),
-        "stc_direct_stream": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
+        "stc_direct_stream": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP, VP, SZ]),
         "stc_set_forcing": (I32, [P, ctypes.POINTER(Forcing)]),
         "stc_get_forcing": (I32, [P, ctypes.POINTER(Forcing), PI32]),
         "stc_forcing_field": (I32, [VP, ctypes.POINTER(Forcing), I64, VP, VP]),
@@ -216,32 +223,56 @@ def _den(d):
     return {"dot": DEN_DOT, "dist2": DEN_DIST2, DEN_DOT: DEN_DOT, DEN_DIST2: DEN_DIST2}[d]
 
 
-def direct(x, zeta, area, targets=None, precision="fp64", denominator="dot", out=None, stream=None):
-    """Direct O(N^2) velocity at `targets` (int64 CUDA tensor, or None = all)."""
+def workspace_tensor(nbytes, device=None):
+    """A device byte tensor of nbytes (256-byte aligned, as the library needs)."""
+    import torch
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
+    if t.data_ptr() % 256:
+        raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
+    return t
+
+
+def direct_scratch_bytes(n, m, precision="fp64", denominator="dot"):
+    """Bytes of caller scratch stc_direct needs for m targets over n sources."""
+    b = ctypes.c_size_t(0)
+    _check(_lib.stc_direct_scratch_size(n, m, _prec(precision), _den(denominator), ctypes.byref(b)))
+    return b.value
+
+
+def direct(x, zeta, area, targets=None, precision="fp64", denominator="dot", out=None, stream=None, scratch=None):
+    """Direct O(N^2) velocity at `targets` (int64 CUDA tensor, or None = all);
+    `scratch` a device byte tensor of direct_scratch_bytes (allocated here if None)."""
     import torch
     n = x.shape[0]
     m = n if targets is None else targets.numel()
     if out is None:
         out = torch.empty((m, 3), dtype=torch.float64, device=x.device)
+    if scratch is None:
+        scratch = workspace_tensor(direct_scratch_bytes(n, m, precision, denominator), x.device)
     st = _lib.stc_direct(_stream(stream), n, _dptr(x, "x", torch.float64, 3 * n),
                          _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n), m,
                          _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
-                         _dptr(out, "out", torch.float64, 3 * m))
+                         _dptr(out, "out", torch.float64, 3 * m), _dptr(scratch, "scratch", torch.uint8),
+                         scratch.numel())
     _check(st)
     return out
 
 
-def direct_stream(x, zeta, area, targets=None, precision="fp64", denominator="dot", out=None, stream=None):
+def direct_stream(x, zeta, area, targets=None, precision="fp64", denominator="dot", out=None, stream=None,
+                  scratch=None):
     """Direct O(N^2) stream function at `targets` (int64 CUDA tensor, or None = all)."""
     import torch
     n = x.shape[0]
     m = n if targets is None else targets.numel()
     if out is None:
         out = torch.empty((m,), dtype=torch.float64, device=x.device)
+    if scratch is None:
+        scratch = workspace_tensor(direct_scratch_bytes(n, m, precision, denominator), x.device)
     st = _lib.stc_direct_stream(_stream(stream), n, _dptr(x, "x", torch.float64, 3 * n),
                                 _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n), m,
                                 _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
-                                _dptr(out, "out", torch.float64, m))
+                                _dptr(out, "out", torch.float64, m), _dptr(scratch, "scratch", torch.uint8),
+                                scratch.numel())
     _check(st)
     return out
 
@@ -290,6 +321,32 @@ def mlp_forward(x, params, out=None, stream=None):
         out = torch.empty((n, 4), dtype=torch.float32, device=x.device)
     _check(_lib.stc_mlp_forward(_stream(stream), n, _bf16(x, "x", 16 * n), _bf16(params, "params", mlp_param_count()),
                                 _dptr(out, "out", torch.float32, 4 * n)))
+    return out
+
+
+def mlp_calibrate(x, y, params, max_false_accept=1e-3, max_under_class=1e-3, stream=None):
+    """(calibrated BF16 parameters, shifts (2,) float64 device tensor {da, dc})
+    from labelled samples: stc_mlp_calibrate."""
+    import torch
+    n = x.shape[0]
+    ws = workspace_tensor(_lib.stc_mlp_calibrate_workspace_bytes(n), x.device)
+    newp = torch.empty_like(params)
+    shifts = torch.empty(2, dtype=torch.float64, device=x.device)
+    _check(_lib.stc_mlp_calibrate(_stream(stream), n, _bf16(x, "x", 16 * n), _dptr(y, "y", torch.float32, 4 * n),
+                                  _bf16(params, "params", mlp_param_count()), float(max_false_accept),
+                                  float(max_under_class), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                  _bf16(newp, "params_out", mlp_param_count()), _dptr(shifts, "shifts", torch.float64, 2)))
+    return newp, shifts
+
+
+def label_scale(u, stream=None):
+    """4 pi sqrt(mean |u_i|^2) of velocities u (n, 3), as a (1,) float64 device
+    tensor: stc_label_scale."""
+    import torch
+    n = u.shape[0]
+    out = torch.empty(1, dtype=torch.float64, device=u.device)
+    _check(_lib.stc_label_scale(_stream(stream), n, _dptr(u, "u", torch.float64, 3 * n),
+                                _dptr(out, "scale", torch.float64, 1)))
     return out
 
 
@@ -349,7 +406,13 @@ class Context:
         self._ctx = ctypes.c_void_p()
         self._stream_obj = stream
         nmm = n_max if n_max_member is None else n_max_member
-        _check(_lib.stc_create_batched(ctypes.byref(p), members, nmm, n_max, _stream(stream), ctypes.byref(self._ctx)))
+        # every device buffer of the context lives in this caller-owned tensor
+        nbytes = ctypes.c_size_t(0)
+        _check(_lib.stc_workspace_size_batched(ctypes.byref(p), members, nmm, n_max, ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._ws = workspace_tensor(nbytes.value)
+        _check(_lib.stc_create_batched(ctypes.byref(p), members, nmm, n_max, ctypes.c_void_p(self._ws.data_ptr()),
+                                       nbytes, _stream(stream), ctypes.byref(self._ctx)))
         q = Params()
         _lib.stc_get_params(self._ctx, ctypes.byref(q))
         self.theta, self.degree, self.n_crit, self.max_level = q.theta, q.degree, q.n_crit, q.max_level
@@ -368,8 +431,9 @@ class Context:
 
     def close(self):
         if self._ctx:
-            _lib.stc_destroy(self._ctx)
+            _lib.stc_destroy(self._ctx)   # synchronises the context's stream first
             self._ctx = ctypes.c_void_p()
+        self._ws = None
 
     def __del__(self):
         try:

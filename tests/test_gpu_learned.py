@@ -52,6 +52,21 @@ def _params(seed):
     return OM.bf16_round(th)
 
 
+def _passthrough_params():
+    """Parameters whose network outputs equal input features 0..3 exactly, in
+    BF16 on the GPU and in FP64 in the oracle, for features on the grid k/16
+    in [-4, 4]: unit weights route feature k through hidden unit k (shifted
+    by +8 so the ReLUs pass it, every value a BF16 number), b3 = -8."""
+    p = {k: np.zeros(s) for k, (_, s) in OM.SLICES.items()}
+    for k in range(4):
+        p["W1"][k, k] = 1.0
+        p["b1"][k] = 8.0
+        p["W2"][k, k] = 1.0
+        p["W3"][k, k] = 1.0
+    p["b3"][:] = -8.0
+    return OM.pack(p)
+
+
 def _cos(a, b):
     return float((a * b).sum() / np.sqrt((a * a).sum() * (b * b).sum()))
 
@@ -330,3 +345,41 @@ def test_forcing_applies_to_the_learned_form(stc_lib):
     assert np.abs(up - u0).max() > 1e-3 * np.abs(u0).max()
     cl.close()
     cp.close()
+
+
+@pytest.mark.parametrize("n,fa,uc", [(20000, 0.05, 0.02), (5000, 0.001, 0.001), (3000, 1.0, 1.0)])
+def test_calibration_matches_oracle(stc_lib, n, fa, uc):
+    """stc_mlp_calibrate against the oracle's calibration on outputs both
+    sides compute exactly (pass-through network, features on a 1/16 grid, so
+    no output ties a grid value): the same shifts and bitwise the same
+    calibrated BF16 parameters."""
+    say(f"calibration n={n} fa={fa} uc={uc}")
+    rng = np.random.default_rng(n)
+    x = np.zeros((n, 16))
+    x[:, :4] = rng.integers(-64, 65, (n, 4)) / 16.0
+    y = np.zeros((n, 4), dtype=np.float32)
+    y[:, 0] = rng.uniform(size=n) < 0.6
+    steps = rng.integers(0, 4, n)
+    for k in range(3):
+        y[:, k + 1] = (y[:, 0] > 0) & (steps > k)
+    th = _passthrough_params()
+    out_o, _ = OM.forward(th, x)
+    assert np.array_equal(out_o, x[:, :4])
+    out_g = stc_lib.mlp_forward(bf16_tensor(x), bf16_tensor(th)).cpu().numpy()
+    assert np.array_equal(out_g.astype(np.float64), x[:, :4])
+    da, dc = OM.calibration_shifts(out_o, y, fa, uc)
+    newp, shifts = stc_lib.mlp_calibrate(bf16_tensor(x), dev(y), bf16_tensor(th), fa, uc)
+    got = shifts.cpu().numpy()
+    assert got[0] == pytest.approx(da, rel=1e-15, abs=0) and got[1] == pytest.approx(dc, rel=1e-15, abs=0)
+    ref_bits = OM.apply_shifts(OM.bf16_bits(th), da, dc)
+    got_bits = newp.view(torch.int16).cpu().numpy().astype(np.uint16)
+    assert np.array_equal(got_bits, ref_bits)
+
+
+def test_label_scale_matches_numpy(stc_lib):
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((100003, 3)) * 1e-5
+    say("label scale")
+    got = float(stc_lib.label_scale(dev(u)).item())
+    ref = 4.0 * np.pi * np.sqrt((u * u).sum(1).mean())
+    assert got == pytest.approx(ref, rel=1e-13)

@@ -305,12 +305,51 @@ def test_nonfinite_position_is_reported(stc_lib):
     ctx.velocity(dev(x), dev(np.ones(2000)), dev(np.ones(2000)))
     with pytest.raises(stc_lib.StcError) as e:
         ctx.sync()
-    assert e.value.status == 1 and "non-finite" in str(e.value)
+    assert e.value.status == 7 and "non-finite particle position" in str(e.value)   # STC_ERR_NONFINITE
     # the same context then takes finite input again
     x[777] = S.random_sphere_points(1, 5)[0]
     u = ctx.velocity(dev(x), dev(np.ones(2000)), dev(np.ones(2000)))
     ctx.sync()
     assert np.isfinite(u.cpu().numpy()).all()
+    # a non-finite vorticity or area is reported the same way (charge q = zeta A)
+    for bad_z, bad_a in ((np.nan, 1.0), (1.0, np.inf)):
+        z, a = np.ones(2000), np.ones(2000)
+        z[123], a[123] = bad_z, bad_a
+        say(f"non-finite charge zeta={bad_z} area={bad_a}")
+        ctx.velocity(dev(x), dev(z), dev(a), out=u)
+        with pytest.raises(stc_lib.StcError) as e:
+            ctx.sync()
+        assert e.value.status == 7 and "vorticity or area" in str(e.value)
+    ctx.velocity(dev(x), dev(np.ones(2000)), dev(np.ones(2000)), out=u)
+    ctx.sync()
+    ctx.close()
+
+
+def test_workspace_holds_every_device_buffer(stc_lib):
+    """A context's device memory is the caller's workspace tensor (sized by
+    stc_workspace_size): after a warm-up evaluation (the HIP runtime sets up
+    its own structures on first launches), three further evaluations leave
+    the device's free memory unchanged and repeat the first result bitwise."""
+    x = S.random_sphere_points(20000, 11)
+    z = S.random_sphere_points(20000, 12)[:, 0].copy()
+    a = np.full(20000, 4 * np.pi / 20000)
+    xd, zd, ad = dev(x), dev(z), dev(a)
+    say("workspace: warm-up")
+    ctx = stc_lib.Context(20000, theta=0.7, degree=6, n_crit=32, precision="fp32", denominator="dist2")
+    assert ctx._ws.numel() == ctx.workspace_bytes
+    u = ctx.velocity(xd, zd, ad)
+    u2 = torch.empty_like(u)
+    ctx.sync()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    say("workspace: measured evaluations")
+    for _ in range(3):
+        ctx.velocity(xd, zd, ad, out=u2)
+    ctx.sync()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free1 == free0, f"free device memory changed by {free0 - free1} bytes over three evaluations"
+    assert torch.equal(u, u2)
     ctx.close()
 
 

@@ -79,19 +79,21 @@ def test_invalid_arguments_are_rejected_without_device_work(stc):
         q = stc.Params()
         ctypes.memmove(ctypes.byref(q), ctypes.byref(p), ctypes.sizeof(p))
         setattr(q, field, val)
-        assert lib.stc_create(ctypes.byref(q), 1000, None, ctypes.byref(ctx)) == 1, field
+        nb = ctypes.c_size_t(0)
+        assert lib.stc_workspace_size(ctypes.byref(q), 1000, ctypes.byref(nb)) == 1, field
+        assert lib.stc_create(ctypes.byref(q), 1000, None, 0, None, ctypes.byref(ctx)) == 1, field
     # FP32 is only offered with the |x-y|^2/2 denominator
     q = stc.Params()
     ctypes.memmove(ctypes.byref(q), ctypes.byref(p), ctypes.sizeof(p))
     q.precision = 1
-    assert lib.stc_create(ctypes.byref(q), 1000, None, ctypes.byref(ctx)) == 1
-    assert lib.stc_create(ctypes.byref(p), -1, None, ctypes.byref(ctx)) == 1
+    assert lib.stc_create(ctypes.byref(q), 1000, None, 0, None, ctypes.byref(ctx)) == 1
+    assert lib.stc_create(ctypes.byref(p), -1, None, 0, None, ctypes.byref(ctx)) == 1
     # NULL context and NULL pointers
     assert lib.stc_tree_build(None, 10, None) == 1
     assert lib.stc_sync(None) == 1
-    assert lib.stc_direct(None, 10, None, None, None, 10, None, 0, 0, None) == 1
-    assert lib.stc_direct(None, 10, None, None, None, 5, None, 0, 0, None) == 1   # m != n without targets
-    assert lib.stc_direct(None, 0, None, None, None, 0, None, 0, 0, None) == 0    # empty: no-op
+    assert lib.stc_direct(None, 10, None, None, None, 10, None, 0, 0, None, None, 0) == 1
+    assert lib.stc_direct(None, 10, None, None, None, 5, None, 0, 0, None, None, 0) == 1   # m != n without targets
+    assert lib.stc_direct(None, 0, None, None, None, 0, None, 0, 0, None, None, 0) == 0    # empty: no-op
     # vorticity forcing: invalid parameters and NULL pointers are refused on the host
     import math
     good = (1, 2 * math.pi, math.pi / 3, 4.0, 15.0, 0.0)
@@ -105,3 +107,40 @@ def test_invalid_arguments_are_rejected_without_device_work(stc):
         assert lib.stc_forcing_field(None, ctypes.byref(stc.Forcing(*f)), 0, None, None) == 1, (i, v)
     assert lib.stc_get_forcing(None, None, None) == 1
     assert stc.status_string(2).startswith("interaction list")
+    assert stc.status_string(6).startswith("workspace")
+    assert stc.status_string(7).startswith("non-finite")
+
+
+def test_workspace_is_sized_and_checked_on_the_host(stc):
+    """The context's device buffers all come from the caller's workspace:
+    its size grows with n_max and the degree, and a missing, misaligned or
+    short workspace is refused (STC_ERR_WORKSPACE) before any device work."""
+    lib = stc.library()
+    p = stc.Params()
+    lib.stc_default_params(ctypes.byref(p))
+    sizes = {}
+    for n in (1000, 10242, 163842):
+        for d in (4, 10):
+            p.degree = d
+            nb = ctypes.c_size_t(0)
+            assert lib.stc_workspace_size(ctypes.byref(p), n, ctypes.byref(nb)) == 0
+            sizes[n, d] = nb.value
+    assert sizes[1000, 4] < sizes[10242, 4] < sizes[163842, 4]
+    assert all(sizes[n, 4] < sizes[n, 10] for n in (1000, 10242, 163842))
+    # 8 B keys x 6 list buffers per entry at 16 entries per particle dominate
+    assert sizes[163842, 10] > 6 * 8 * 16 * 163842
+    nb = ctypes.c_size_t(0)
+    assert lib.stc_workspace_size_batched(ctypes.byref(p), 3, 10242, 30000, ctypes.byref(nb)) == 0
+    assert nb.value > sizes[10242, 10]
+    p.degree = 8
+    assert lib.stc_workspace_size(ctypes.byref(p), 10242, ctypes.byref(nb)) == 0
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: the size check comes first
+    assert lib.stc_create(ctypes.byref(p), 10242, None, nb.value, None, ctypes.byref(ctx)) == 6
+    assert lib.stc_create(ctypes.byref(p), 10242, fake, nb.value - 1, None, ctypes.byref(ctx)) == 6
+    assert lib.stc_create(ctypes.byref(p), 10242, ctypes.c_void_p((1 << 20) + 8), nb.value, None,
+                          ctypes.byref(ctx)) == 6   # not 256-byte aligned
+    assert not ctx.value
+    sb = ctypes.c_size_t(123)
+    assert lib.stc_direct_scratch_size(0, 0, 0, 0, ctypes.byref(sb)) == 0 and sb.value == 0
+    assert lib.stc_direct_scratch_size(10, 10, 1, 0, ctypes.byref(sb)) == 1   # FP32 needs |x-y|^2/2

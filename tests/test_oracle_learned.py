@@ -195,3 +195,39 @@ def test_features_of_one_candidate_by_hand():
     for k in range(12):
         if want_b[k] is not None:
             assert abs(back[k] - want_b[k]) <= 2.0 ** -8 * max(abs(want_b[k]), 1e-6), (k, back[k], want_b[k])
+
+
+def test_calibration_shifts_hand_case():
+    """Bias calibration on ten hand-made samples.  Rejected labels with
+    acceptance logits 0.5, 2.0, -1.0 and max_false_accept 0.1: at most one of
+    ten may stay accepted, so the shift must reach 0.5 (o0 - d > 0 is strict)
+    -- the first grid value at or above 0.5 is 1e-3 * 64000^(112/199).  Of
+    the seven accepted samples (o0 = 3) one needs two ordinal steps with
+    logits (1.0, -0.3, -2.0): it is under-classed until -0.3 + d > 0, and 1/7
+    exceeds max_under_class 0.1, so dc is the first grid value above 0.3,
+    1e-3 * 64000^(103/199)."""
+    from oracle import mlp
+    out = np.zeros((10, 4))
+    y = np.zeros((10, 4))
+    out[:3, 0] = [0.5, 2.0, -1.0]
+    out[3:, 0] = 3.0
+    out[3:, 1:] = -5.0
+    y[3:, 0] = 1.0
+    out[4, 1:] = [1.0, -0.3, -2.0]
+    y[4, 1:] = [1.0, 1.0, 0.0]
+    grid = mlp.calibration_grid()
+    assert grid[112] < 0.5 < grid[113] and grid[103] < 0.3 < grid[104]
+    da, dc = mlp.calibration_shifts(out, y, 0.1, 0.1)
+    assert da == pytest.approx(1e-3 * 64000.0 ** (112 / 199), rel=1e-14)
+    assert dc == pytest.approx(1e-3 * 64000.0 ** (103 / 199), rel=1e-14)
+    # looser bars: every false accept allowed -> no shift; one in seven allowed -> no class shift
+    assert mlp.calibration_shifts(out, y, 0.3, 0.15) == (0.0, 0.0)
+    # a bar no grid value meets takes the largest grid value
+    out2 = out.copy()
+    out2[0, 0] = 100.0
+    assert mlp.calibration_shifts(out2, y, 0.0, 1.0)[0] == 64.0
+    # BF16 application: b3[0] - da and b3[1..3] + dc, rounded to FP32 then BF16
+    bits = mlp.bf16_bits(np.zeros(mlp.N_PARAMS))
+    new = mlp.apply_shifts(bits, 0.5, 0.25)
+    vals = mlp.from_bf16_bits(new)
+    assert (vals[5248:5252] == [-0.5, 0.25, 0.25, 0.25]).all() and (vals[:5248] == 0).all()
