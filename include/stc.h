@@ -257,6 +257,23 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
                       int32_t precision, int32_t denominator, double* d_u,
                       void* d_scratch, size_t scratch_bytes);
 
+/* stc_direct for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Arguments, layout, result and errors as stc_direct, and the result is
+ * bitwise that of stc_direct on the same device.  The chunks' partial sums
+ * go to a library-owned static device array of 16 MiB per GPU (allocated by
+ * the HIP runtime with the library's code object on the first call on a
+ * device and held until the process ends) instead of a stream-ordered
+ * allocation; this call allocates nothing.  A split that needs more than
+ * 16 MiB (chunks x m x 24 bytes; at most 4 x CUs x workgroups per CU x 64
+ * x 24 bytes, 12.6 MB on 256 CUs) returns STC_ERR_WORKSPACE and enqueues
+ * nothing.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race.  Every partial
+ * sum is written before it is read, so nothing is cleared between calls. */
+stc_status stc_direct_noalloc(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
+                              const double* d_area, int64_t m, const int64_t* d_targets,
+                              int32_t precision, int32_t denominator, double* d_u);
+
 /* Stream function (Sec. 2, stream function and Green's function):
  *   psi_i = (1/4pi) sum_{j != i} zeta_j A_j log(den(x_i, x_j)),
  * den = 1 - x.y or |x - y|^2 / 2 per the context's denominator, through the

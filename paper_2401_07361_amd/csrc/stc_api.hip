@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -664,7 +665,41 @@ void carve(stc_ctx* c, Carver& cv) {
 
 }  // namespace
 
+// Scratch of stc_direct_noalloc: the source chunks' partial sums
+// (chunks x m x 3 doubles) live in this file-scope array instead of a
+// stream-ordered allocation.  Each GPU holds its own copy from the first
+// call on it until the process ends.  In host code `scratch` only names the
+// symbol: its device address comes from hipGetSymbolAddress, taken once per
+// device and kept in g_scratch_addr.
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
 namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch array (set up on the first
+// call on that device, with that device current).
+stc_status noalloc_scratch(double** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return STC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return STC_ERR_DEVICE;
+        }
+        g_scratch_addr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return STC_OK;
+}
+
+// Where the chunk partial sums of a split direct sum go.
+enum class DirectScratch { Caller, Static };
+
 // Source chunks of a direct sum of m targets over n sources on the current
 // device and the bytes of their partial sums (0 when unsplit).
 stc_status direct_plan(i64 n, i64 m, int32_t precision, int32_t denominator, u32* chunks, i64* chunk_len,
@@ -957,7 +992,8 @@ static stc_status direct_check(int64_t n, int64_t m, int32_t precision, int32_t 
 
 static stc_status direct_sum(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
                              const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
-                             int32_t denominator, double* d_u, bool stream, void* d_scratch, size_t scratch_bytes) {
+                             int32_t denominator, double* d_u, bool stream, DirectScratch where, void* d_scratch,
+                             size_t scratch_bytes) {
     stc_status st = direct_check(n, m, precision, denominator);
     if (st != STC_OK) return st;
     if (!d_targets && m != n) return STC_ERR_INVALID_ARG;
@@ -966,7 +1002,8 @@ static stc_status direct_sum(void* hip_stream, int64_t n, const double* d_x, con
         !aligned8(d_u) || (d_targets && !aligned8(d_targets)))
         return STC_ERR_INVALID_ARG;
     // Few targets cannot fill the chip: the sources are split into chunks
-    // whose partial sums go to the caller's scratch and are added in chunk
+    // whose partial sums go to the caller's scratch (or, for the
+    // no-allocation form, the static scratch array) and are added in chunk
     // order by a second kernel.
     u32 chunks = 1;
     i64 chunk_len = n;
@@ -974,7 +1011,11 @@ static stc_status direct_sum(void* hip_stream, int64_t n, const double* d_x, con
     st = direct_plan(n, m, precision, denominator, &chunks, &chunk_len, &bytes);
     if (st != STC_OK) return st;
     double* part = nullptr;
-    if (bytes > 0) {
+    if (bytes > 0 && where == DirectScratch::Static) {
+        if (bytes > kNoAllocScratchBytes) return STC_ERR_WORKSPACE;
+        st = noalloc_scratch(&part);
+        if (st != STC_OK) return st;
+    } else if (bytes > 0) {
         if (!d_scratch || !aligned8(d_scratch) || scratch_bytes < bytes) return STC_ERR_WORKSPACE;
         part = static_cast<double*>(d_scratch);
     }
@@ -997,14 +1038,21 @@ stc_status stc_direct(void* hip_stream, int64_t n, const double* d_x, const doub
                       int64_t m, const int64_t* d_targets, int32_t precision, int32_t denominator, double* d_u,
                       void* d_scratch, size_t scratch_bytes) {
     return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_u, false,
-                      d_scratch, scratch_bytes);
+                      DirectScratch::Caller, d_scratch, scratch_bytes);
+}
+
+stc_status stc_direct_noalloc(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
+                              const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
+                              int32_t denominator, double* d_u) {
+    return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_u, false,
+                      DirectScratch::Static, nullptr, 0);
 }
 
 stc_status stc_direct_stream(void* hip_stream, int64_t n, const double* d_x, const double* d_zeta,
                              const double* d_area, int64_t m, const int64_t* d_targets, int32_t precision,
                              int32_t denominator, double* d_psi, void* d_scratch, size_t scratch_bytes) {
     return direct_sum(hip_stream, n, d_x, d_zeta, d_area, m, d_targets, precision, denominator, d_psi, true,
-                      d_scratch, scratch_bytes);
+                      DirectScratch::Caller, d_scratch, scratch_bytes);
 }
 
 stc_status stc_stream_function(stc_ctx* c, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,

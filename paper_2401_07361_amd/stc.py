@@ -107,6 +107,7 @@ def _load():
         "stc_eval_far": (I32, [P, VP, I32]),
         "stc_velocity": (I32, [P, I64, VP, VP, VP, VP]),
         "stc_direct": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP, VP, SZ]),
+        "stc_direct_noalloc": (I32, [VP, I64, VP, VP, VP, I64, VP, I32, I32, VP]),
         "stc_rk4": (I32, [P, I64, VP, VP, VP, D, D, I32]),
         "stc_stream_function": (I32, [P, I64, VP, VP, VP, VP]),
         "stc_stream_function_batched": (I32, [P, I32, PI64, VP, VP, VP, VP]),
@@ -254,6 +255,22 @@ def direct(x, zeta, area, targets=None, precision="fp64", denominator="dot", out
                          _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
                          _dptr(out, "out", torch.float64, 3 * m), _dptr(scratch, "scratch", torch.uint8),
                          scratch.numel())
+    _check(st)
+    return out
+
+
+def direct_noalloc(x, zeta, area, targets=None, precision="fp64", denominator="dot", out=None, stream=None):
+    """stc_direct_noalloc: the direct velocity with the library's static
+    scratch array (the caller allocates `out` beforehand to allocate nothing)."""
+    import torch
+    n = x.shape[0]
+    m = n if targets is None else targets.numel()
+    if out is None:
+        out = torch.empty((m, 3), dtype=torch.float64, device=x.device)
+    st = _lib.stc_direct_noalloc(_stream(stream), n, _dptr(x, "x", torch.float64, 3 * n),
+                                 _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n), m,
+                                 _dptr(targets, "targets", torch.int64), _prec(precision), _den(denominator),
+                                 _dptr(out, "out", torch.float64, 3 * m))
     _check(st)
     return out
 
