@@ -17,7 +17,10 @@ Applications to the Barotropic Vorticity Equation"):
 * ``forcing``  -- the vorticity forcing F_R of the polar-vortex collapse
                   experiment (Sec. 4.4) and the forced RK4 step.
 * ``metrics``  -- the relative l2 errors E and E_N (Sec. 4).
-* ``mlp``      -- FP64 forward/backward of the small interaction-gating MLP.
+* ``mlp``      -- FP64 forward/backward of the small interaction-gating MLP and
+                  the calibration of its output biases.
+* ``amr``      -- adaptive refinement and coarsening of the particle
+                  triangulation (Appendix A; Gaussian vortex, Sec. 4.3).
 
 Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this package.  The GPU library never calls it, and it imports
@@ -25,4 +28,4 @@ nothing from the GPU library: the two share only the seeded input generators
 in ``synthetic``.
 """
 
-from . import direct, geometry, interp, tree, rk4, metrics, forcing  # noqa: F401
+from . import direct, geometry, interp, tree, rk4, metrics, forcing, amr  # noqa: F401
