@@ -168,7 +168,25 @@ def roofline(evals, kern_ms, precision, flops=None, config_tag=None):
     return top
 
 
-ENS_THETA, ENS_DEGREE, ENS_N_CRIT = 0.7, 8, 64
+# the fastest setting whose worst member stays below 1e-6 (5.1e-7 on 256 targets per member;
+# theta 0.7, d 8 reaches only 3.7e-6)
+ENS_THETA, ENS_DEGREE, ENS_N_CRIT = 0.8, 10, 64
+
+
+def ensemble_member_errors(stc, x, z, a, off, u, area_h, targets=256):
+    """Area-weighted relative L2 error of each member's velocity u against its
+    FP64 direct sum (|x - y|^2 / 2) at `targets` seeded particles."""
+    import torch
+    un = u.cpu().numpy()
+    errs = []
+    for m in range(len(off) - 1):
+        lo, hi = int(off[m]), int(off[m + 1])
+        tg = np.random.default_rng(100 + m).choice(hi - lo, min(targets, hi - lo), replace=False)
+        ref = stc.direct(x[lo:hi], z[lo:hi], a[lo:hi], targets=torch.from_numpy(tg.astype(np.int64)).cuda(),
+                         denominator="dist2").cpu().numpy()
+        w = area_h[lo:hi][tg][:, None]
+        errs.append(float(np.sqrt((w * (un[lo:hi][tg] - ref) ** 2).sum() / (w * ref ** 2).sum())))
+    return errs
 
 
 def bench_ensemble(args):
@@ -191,16 +209,9 @@ def bench_ensemble(args):
                                    args.warmup)
     counts, evals = ctx.list_counts()
     log(f"batched: {ms:.3f} ms per ensemble evaluation; phases {phase_ms}")
-    # accuracy: 64 seeded targets per member against that member's FP64 direct sum
-    worst = 0.0
-    un = out.cpu().numpy()
-    for m in range(M):
-        lo, hi = int(off[m]), int(off[m + 1])
-        tg = np.random.default_rng(100 + m).choice(hi - lo, 64, replace=False)
-        ref = stc.direct(x[lo:hi], z[lo:hi], a[lo:hi], targets=torch.from_numpy(tg.astype(np.int64)).cuda(),
-                         denominator="dist2").cpu().numpy()
-        got = un[lo:hi][tg]
-        worst = max(worst, float(np.sqrt(((got - ref) ** 2).sum() / (ref ** 2).sum())))
+    # accuracy: 256 seeded targets per member against that member's FP64 direct sum
+    errs0 = ensemble_member_errors(stc, x, z, a, off, out, ens["area"])
+    worst = max(errs0)
     # the same members one context at a time (one launch sequence per member)
     singles = [stc.Context(int(off[m + 1] - off[m]), max_level=ctx.max_level, **kw) for m in range(M)]
     views = [(x[int(off[m]):int(off[m + 1])], z[int(off[m]):int(off[m + 1])], a[int(off[m]):int(off[m + 1])],
@@ -220,18 +231,25 @@ def bench_ensemble(args):
     for c in singles:
         c.close()
     log(f"one member at a time: {ms_seq:.3f} ms per ensemble evaluation")
-    # graph-captured RK4 steps of the whole ensemble (dt = 1800 s)
+    # the configured run: 24 graph-captured RK4 steps of the whole ensemble
+    # (dt = 1800 s) from the initial state, then every member's error at its
+    # final state
     xr, zr = x.clone(), z.clone()
-    ctx.rk4_batched(xr, zr, a, off, ens["dt"], S.OMEGA_EARTH_S, 1)
+    ctx.rk4_batched(xr, zr, a, off, ens["dt"], S.OMEGA_EARTH_S, 1)   # captures the step graph
     torch.cuda.synchronize()
-    rk_steps = max(1, args.steps // 4)
+    xr.copy_(x)
+    zr.copy_(z)
+    rk_steps = ens["steps"]
     t0.record()
     ctx.rk4_batched(xr, zr, a, off, ens["dt"], S.OMEGA_EARTH_S, rk_steps)
     t1.record()
     torch.cuda.synchronize()
     ms_rk = t0.elapsed_time(t1) / rk_steps
     ctx.sync()
-    log(f"rk4 step (4 evaluations, one graph): {ms_rk:.3f} ms")
+    log(f"rk4 step (4 evaluations, one graph): {ms_rk:.3f} ms over {rk_steps} steps")
+    ctx.velocity_batched(xr, zr, a, off, out=out)
+    errs = ensemble_member_errors(stc, xr, zr, a, off, out, ens["area"])
+    log(f"after {rk_steps} steps: worst member E {max(errs):.3e}, median {np.median(errs):.3e}")
     ctx.close()
     roof = roofline(evals, kern_ms, "fp32")
     m0 = ens["members"][0]
@@ -250,6 +268,10 @@ def bench_ensemble(args):
                     members=M, N=N, theta=ENS_THETA, degree=ENS_DEGREE, n_crit=ENS_N_CRIT,
                     max_level=int(ctx.max_level), precision="fp32", denominator="dist2",
                     launch_shape=list(shape), worst_member_rel_l2_err_vs_fp64_direct=float(f"{worst:.3e}"),
+                    rk4_steps=int(ens["steps"]),
+                    after_rk4=dict(worst_member_rel_l2_err=float(f"{max(errs):.3e}"),
+                                   median_member_rel_l2_err=float(f"{np.median(errs):.3e}"),
+                                   members_within_1e_6=int(sum(e <= 1e-6 for e in errs))),
                     lists=counts, kernel_evals=int(sum(evals.values())), phase_ms=phase_ms,
                     ms_one_member_at_a_time=round(ms_seq, 4), batching_speedup=round(ms_seq / ms, 3),
                     ms_per_rk4_step=round(ms_rk, 4)),
@@ -260,8 +282,10 @@ def bench_ensemble(args):
     print(json.dumps(result), flush=True)
 
 
-LEARNED = dict(theta=0.7, theta_max=0.9, degree=10, n_crit=64, tol_rel=3e-8, train_inputs=6, epochs=8,
-               batch=4096, lr=2e-3)
+# training: the configured 2e6 samples, from as many seeded N = 163842 inputs as it takes (about 64k
+# candidate pairs each)
+LEARNED = dict(theta=0.7, theta_max=0.9, degree=10, n_crit=64, tol_rel=3e-8, train_samples=2_000_000,
+               max_inputs=64, epochs=8, batch=4096, lr=2e-3)
 
 
 def _phase_breakdown(ctx, fn, reps=3):
@@ -304,15 +328,15 @@ def bench_learned(args):
 
     P = LEARNED
     t0 = time.perf_counter()
-    inputs = []
-    for k in range(P["train_inputs"]):
-        x, z, a = S.make_gate_training_input(k)
-        inputs.append(tuple(torch.from_numpy(v).cuda() for v in (x, z, a)))
-    F, Y = G.collect(inputs, P["tol_rel"], P["theta"], P["theta_max"], degree=P["degree"], n_crit=P["n_crit"],
-                     log=log)
+
+    def inputs():
+        for k in range(P["max_inputs"]):
+            yield tuple(torch.from_numpy(v).cuda() for v in S.make_gate_training_input(k))
+
+    F, Y = G.collect(inputs(), P["tol_rel"], P["theta"], P["theta_max"], degree=P["degree"], n_crit=P["n_crit"],
+                     log=log, max_samples=P["train_samples"])
     torch.cuda.synchronize()
     t_samples = time.perf_counter() - t0
-    del inputs
     t1 = time.perf_counter()
     params, losses = G.train(F, Y, epochs=P["epochs"], batch=P["batch"], lr=P["lr"])
     torch.cuda.synchronize()
@@ -548,6 +572,90 @@ def bench_rh10d(args):
     print(json.dumps(result), flush=True)
 
 
+AMR = dict(level0=5, eps1=0.0025, eps2=0.2, dt=0.01, days=3.0, max_levels=3, theta=0.7, degree=6, n_crit=64)
+
+
+def amr_run(stc, theta, degree, log=None):
+    """The Gaussian vortex of Sec. 4.3 with adaptive refinement: initial mesh
+    of 10242 particles, the initial field resolved by passes that re-evaluate
+    it at the live particles, then RK4 steps of dt = 0.01 day, each followed
+    by one adaptation pass, for 3 days.  Returns timings, particle counts and
+    the vortex track (position of the largest vorticity, daily)."""
+    import torch
+    import synthetic as S
+    P = AMR
+    x0, f0 = S.icosahedral_grid(P["level0"], return_faces=True)
+    a0 = S.node_patch_areas(x0, f0)
+    om = S.OMEGA_EARTH_DAY
+    mesh = stc.AdaptiveMesh(x0, f0, eps1=P["eps1"], eps2=P["eps2"], omega=om, max_levels=P["max_levels"])
+    mesh.set_state(torch.from_numpy(x0).cuda(), torch.from_numpy(S.gaussian_vortex_paper(x0, a0)).cuda())
+    for _ in range(P["max_levels"] + 1):
+        mesh.adapt()
+        x, z, a = mesh.particles()
+        xh, ah = x.cpu().numpy(), a.cpu().numpy()
+        mesh.set_state(x.clone(), torch.from_numpy(S.gaussian_vortex_paper(xh, ah)).cuda())
+    n_initial = mesh.stats()["particles"]
+    ctx = stc.Context(mesh.capacity, theta=theta, degree=degree, n_crit=P["n_crit"], precision="fp64",
+                      denominator="dist2")
+    steps = int(round(P["days"] / P["dt"]))
+    per_day = int(round(1.0 / P["dt"]))
+    track, counts = [], [n_initial]
+
+    def vortex_centre():
+        x, z, _ = mesh.particles()
+        k = int(torch.argmax(z).item())
+        c = x[k].cpu().numpy()
+        return [round(float(np.degrees(np.arcsin(c[2]))), 3), round(float(np.degrees(np.arctan2(c[1], c[0]))), 3)]
+
+    track.append(vortex_centre())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for day in range(0, steps, per_day):
+        mesh.rk4(ctx, P["dt"], om, min(per_day, steps - day))
+        counts.append(mesh.stats()["particles"])
+        track.append(vortex_centre())
+        if log:
+            log(f"  theta={theta} d={degree}: day {len(counts) - 1}, {counts[-1]} particles")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    x, z, a = mesh.particles()
+    circ = float((z * a).sum().item())
+    circ_abs = float((z.abs() * a).sum().item())
+    ctx.close()
+    mesh.close()
+    return dict(seconds=round(wall, 3), ms_per_step=round(wall * 1e3 / steps, 4), steps=steps,
+                particles_initial=n_initial, particles_daily=counts, vortex_track_lat_lon_deg=track,
+                circulation_rel=float(f"{abs(circ) / circ_abs:.3e}"))
+
+
+def bench_amr(args):
+    """Adaptive refinement with time stepping: the Gaussian-vortex run of
+    Sec. 4.3 (10242 initial particles, eps1 = 0.0025, eps2 = 0.2, 3 days of
+    RK4 with dt = 0.01 day and one adaptation pass per step, theta 0.7, d 6,
+    FP64), beside a reference run with a tighter tree (theta 0.4, d 10) whose
+    vortex track it should follow."""
+    from paper_2401_07361_amd import stc
+    log("amr: Gaussian vortex, theta 0.7, d 6")
+    r = amr_run(stc, AMR["theta"], AMR["degree"], log=log)
+    log("amr: reference tree theta 0.4, d 10")
+    ref = amr_run(stc, 0.4, 10, log=log)
+    tr, tf = np.radians(np.array(r["vortex_track_lat_lon_deg"])), np.radians(np.array(ref["vortex_track_lat_lon_deg"]))
+
+    def unit(ll):
+        return np.stack([np.cos(ll[:, 0]) * np.cos(ll[:, 1]), np.cos(ll[:, 0]) * np.sin(ll[:, 1]), np.sin(ll[:, 0])], 1)
+
+    sep = np.degrees(np.arccos(np.clip((unit(tr) * unit(tf)).sum(1), -1.0, 1.0)))
+    result = dict(
+        metric="RK4 steps with adaptive refinement per second, Gaussian vortex (10242 initial particles, 3 days)",
+        value=round(r["steps"] / r["seconds"], 2), unit="RK4+AMR steps/s", n_gpus=1, steps=r["steps"], warmup=0,
+        ms_per_step=r["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+        data="synthetic",
+        config=dict(workload="Gaussian vortex with AMR (Sec. 4.3)", **AMR, run=r, reference_tight_tree=dict(theta=0.4, degree=10, **ref),
+                    track_separation_deg=[round(float(v), 4) for v in sep]),
+    )
+    print(json.dumps(result), flush=True)
+
+
 def bench_ssw(args):
     """Forced RK4 of the polar-vortex collapse (Sec. 4.4) at the paper's setting
     (N = 163842, d = 6, theta = 0.7, wavenumber-1 forcing); the accuracy check
@@ -723,7 +831,7 @@ def main():
     ap.add_argument("--level", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="gv_l8",
-                    choices=["gv_l8", "ensemble", "learned", "rk4", "rh10d", "ssw", "stream", "plain"])
+                    choices=["gv_l8", "ensemble", "learned", "rk4", "rh10d", "amr", "ssw", "stream", "plain"])
     ap.add_argument("--autotune", action="store_true",
                     help="gv_l8: pick the interaction kernels' launch shape with the library's autotuner first")
     ap.add_argument("--copy-check", action="store_true",
@@ -747,6 +855,9 @@ def main():
         return
     if args.workload == "rh10d":
         bench_rh10d(args)
+        return
+    if args.workload == "amr":
+        bench_amr(args)
         return
     if args.workload == "stream":
         bench_stream(args)

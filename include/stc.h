@@ -316,6 +316,84 @@ stc_status stc_direct_stream(void* hip_stream, int64_t n, const double* d_x, con
 stc_status stc_rk4(stc_ctx* ctx, int64_t n, double* d_x, double* d_zeta, const double* d_area,
                    double dt, double omega, int32_t n_steps);
 
+/* --- adaptive mesh refinement (Appendix A; Gaussian vortex, Sec. 4.3) ------ */
+
+/* The particles are the vertices of a triangulation; every triangle of the
+ * initial mesh (n_faces triangles over the n0 initial particles, h_faces
+ * host int32 (n_faces, 3), counter-clockwise seen from outside) is the root of
+ * a refinement tree.  An adaptation pass tests every leaf triangle T (and
+ * every refined one whose children are leaves) with its vertices' current
+ * positions and vorticities:
+ *   C(T) = |A_T (zeta_1 + zeta_2 + zeta_3) / 3| >= eps1  or
+ *          max zeta - min zeta >= eps2
+ * (A_T the spherical triangle area), merges refined triangles with leaf
+ * children where C no longer holds (never below the initial mesh), then
+ * splits leaves where C holds into four (edge midpoints (a + b) / |a + b|),
+ * at most max_levels below the initial mesh.  Readings where the appendix is
+ * silent: the circulation test uses its magnitude; all decisions of a pass
+ * use the state at its start, merging before splitting (one level per pass);
+ * a midpoint particle is shared by the two triangles of its edge and removed
+ * when no leaf has it as a vertex; a new particle takes the mean absolute
+ * vorticity zeta + omega_abs z of its edge's ends (omega_abs = 2 Omega, the
+ * quantity the particle system carries unchanged) minus omega_abs z at its
+ * position; quadrature weights A_i = sum of A_T / 3 over the leaves having
+ * i as a vertex.  The live particles (the tree code's input) are kept in
+ * slot order: the initial particles first, in input order. */
+typedef struct stc_amr stc_amr;
+typedef struct stc_amr_params {
+    double eps1, eps2;   /* thresholds of the circulation and variation tests  */
+    double omega;        /* Omega of the particle system (the 2 Omega z term)  */
+    int32_t max_levels;  /* refinement levels below the initial mesh, 0..6    */
+} stc_amr_params;
+
+/* Device workspace bytes of an adaptive mesh and the largest particle count
+ * it can reach (*max_particles: every midpoint of max_levels refinements);
+ * host-only.  STC_ERR_INVALID_ARG for bad parameters or face indices. */
+stc_status stc_amr_workspace_size(const stc_amr_params* p, int64_t n0, int64_t n_faces,
+                                  const int32_t* h_faces, size_t* bytes, int64_t* max_particles);
+
+/* Creates the adaptive mesh in the caller's workspace (256-byte aligned,
+ * stc_amr_workspace_size bytes; STC_ERR_WORKSPACE otherwise): the slot tables
+ * of every triangle and particle refinement can create are built on the host
+ * and uploaded; the initial particles are live and every root a leaf.  The
+ * particle state is set with stc_amr_set_state.  Synchronises hip_stream. */
+stc_status stc_amr_create(const stc_amr_params* p, int64_t n0, int64_t n_faces, const int32_t* h_faces,
+                          void* d_ws, size_t ws_bytes, void* hip_stream, stc_amr** out);
+stc_status stc_amr_destroy(stc_amr* amr);
+
+/* Writes positions d_x (n, 3) and vorticities d_zeta (n) of the live
+ * particles (in the order stc_amr_particles gives; n must be the current
+ * count) into the mesh.  Asynchronous. */
+stc_status stc_amr_set_state(stc_amr* amr, int64_t n, const double* d_x, const double* d_zeta);
+
+/* One adaptation pass, then the live particles compacted into the arrays
+ * stc_amr_particles returns; synchronises (the new particle count). */
+stc_status stc_amr_adapt(stc_amr* amr);
+
+/* The live particles: count and device arrays x (n, 3), zeta (n), area (n)
+ * inside the mesh's workspace (valid until the next pass; the tree code may
+ * read and, through stc_amr_rk4, update them).  No synchronisation. */
+stc_status stc_amr_particles(stc_amr* amr, int64_t* n, double** d_x, double** d_zeta, double** d_area);
+
+/* After the last pass: live particles, leaf triangles, triangles merged and
+ * split by that pass, and the particle capacity.  Synchronises. */
+stc_status stc_amr_stats(stc_amr* amr, int64_t* n_particles, int64_t* n_leaves, int64_t* merged,
+                         int64_t* split, int64_t* max_particles);
+
+/* Slot of every live particle (h_slots, up to cap) and the edge ends of the
+ * first cap particle slots (h_ends (cap, 2); -1 for initial particles);
+ * either may be NULL.  Synchronises. */
+stc_status stc_amr_copy_slots(stc_amr* amr, int64_t cap, int32_t* h_slots, int32_t* h_ends);
+
+const char* stc_amr_last_error(const stc_amr* amr);
+
+/* n_steps RK4 steps of the live particles with the tree code of ctx (its
+ * parameters; the |x - y|^2 / 2 denominator; capacity >= the mesh's
+ * particle capacity), each followed by one adaptation pass.  The steps run
+ * eagerly (the particle count changes between steps).  ctx and amr must
+ * enqueue on the same stream.  Synchronises once per step. */
+stc_status stc_amr_rk4(stc_amr* amr, stc_ctx* ctx, double dt, double omega, int32_t n_steps);
+
 /* RK4 of every member of an ensemble (same dt and omega), each stage one
  * stc_velocity_batched; graph-captured like stc_rk4 (re-captured when the
  * offsets change). */

@@ -5,9 +5,10 @@
 Every source is recompiled on each call.  Flags:
 * --offload-arch=gfx950, -O3, C++17;
 * packed FP32 instructions are disabled for all device code;
-* the tree kernels and the host geometry are compiled without floating-point
-  contraction, so point location and the acceptance criterion use exactly the
-  IEEE operations written in the source.
+* the tree kernels, the adaptive-mesh kernels and the host geometry are
+  compiled without floating-point contraction, so point location, the
+  acceptance criterion and the refinement tests use exactly the IEEE
+  operations written in the source.
 """
 
 import os
@@ -38,6 +39,7 @@ SOURCES = [
     ("k_eval.hip", [], True),
     ("k_mlp.hip", [], True),
     ("k_learned.hip", [], True),
+    ("amr.hip", ["-ffp-contract=off"], True),
     ("stc_api.hip", [], True),
 ]
 
@@ -50,8 +52,13 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose=False, jobs=None):
+def build(verbose=False, jobs=None, out=None):
+    """Compiles every source and links libstc.so (or `out`).  Environment
+    STC_FAR_MFMA=1 builds the matrix-core accumulation of the target-proxy
+    kernel instead of the VALU one (kept for measurement; slower)."""
+    lib = out or OUT
     os.makedirs(BUILD, exist_ok=True)
+    far_mfma = os.environ.get("STC_FAR_MFMA", "0") == "1"
     objs = []
     procs = []
     for name, extra, dev in SOURCES:
@@ -59,6 +66,8 @@ def build(verbose=False, jobs=None):
         obj = os.path.join(BUILD, name + ".o")
         if dev:
             cmd = [HIPCC] + COMMON + DEVICE + extra + ["-c", "-o", obj, src]
+            if far_mfma and name == "k_eval.hip":
+                cmd.insert(-4, "-DSTC_FAR_MFMA=1")
         else:
             cmd = [CLANG] + COMMON + extra + ["-x", "c++", "-c", "-o", obj, src]
         if verbose:
@@ -76,11 +85,14 @@ def build(verbose=False, jobs=None):
         for cmd, out in failed:
             sys.stderr.write(" ".join(cmd) + "\n" + out + "\n")
         raise RuntimeError("compilation failed")
-    tmp = OUT + ".tmp"
+    tmp = lib + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
-    shutil.move(tmp, OUT)
-    return OUT
+    shutil.move(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    dst = None
+    if "-o" in sys.argv:
+        dst = os.path.abspath(sys.argv[sys.argv.index("-o") + 1])
+    print(build(verbose="-v" in sys.argv, out=dst))

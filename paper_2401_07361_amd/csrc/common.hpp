@@ -9,6 +9,7 @@
 
 namespace stc {
 
+using u8 = uint8_t;
 using u16 = uint16_t;
 using u32 = uint32_t;
 using u64 = uint64_t;

@@ -38,6 +38,8 @@ struct Src {
     T x, y, z, q;
 };
 
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 __device__ __forceinline__ T rcp_t(T v);
 template <>
@@ -226,22 +228,149 @@ __device__ __forceinline__ void tile_sum(const Src<T>* __restrict__ tile, int cn
     }
 }
 
+// Matrix-core form of tile_sum for the FP32 |x - y|^2 velocity kernel (see
+// UseMfma).  Every lane of the wave runs it with the same trip count (the
+// MFMA takes all 64 lanes): a lane outside the active slices (act false)
+// reads slice 0 and its blocks' results are never used; sources past cnt
+// and the excluded self pair enter with r = 0.  acc[k][i]: this lane's
+// column (lane & 3) of block row i for target k, added in FP64 per tile.
+template <bool SELF, int TP>
+__device__ __forceinline__ void tile_sum_mf(const Src<float>* __restrict__ tile, const float (*__restrict__ row)[4],
+                                            int cnt, int sl, int S, bool act, const float* tx, const float* ty,
+                                            const float* tz, const int* self_j, double (*acc)[4]) {
+    const int col = threadIdx.x & 3;
+    const int slr = act ? sl : 0;
+    mf32x4 d[TP];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) d[k] = mf32x4{0.f, 0.f, 0.f, 0.f};
+    if (!SELF) {
+        int mr;
+        const int m = div_small(cnt, S, mr);
+        const Src<float>* __restrict__ blk = tile + slr * m;
+        const float (*__restrict__ rblk)[4] = row + slr * m;
+        // four sources per step, all their LDS reads issued before the
+        // arithmetic (one wait per four sources); the MFMAs of one source
+        // go to TP different accumulators
+        int it = 0;
+        for (; it + 4 <= m; it += 4) {
+            Src<float> src[4];
+            float b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                src[u] = blk[it + u];
+                b[u] = rblk[it + u][col];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < TP; ++k) {
+                    const float dx = src[u].x - tx[k], dy = src[u].y - ty[k], dz = src[u].z - tz[k];
+                    const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
+                    d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(r, b[u], d[k], 0, 0, 0);
+                }
+        }
+        for (; it < m; ++it) {
+            const Src<float> src = blk[it];
+            const float b = rblk[it][col];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) {
+                const float dx = src.x - tx[k], dy = src.y - ty[k], dz = src.z - tz[k];
+                const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
+                d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(r, b, d[k], 0, 0, 0);
+            }
+        }
+        // at most one of the cnt - S m remaining sources per slice
+        const int j = S * m + slr;
+        const bool ok = j < cnt;
+        const int jj = ok ? j : 0;
+        const Src<float> src = tile[jj];
+        const float b = row[jj][col];
+#pragma unroll
+        for (int k = 0; k < TP; ++k) {
+            const float dx = src.x - tx[k], dy = src.y - ty[k], dz = src.z - tz[k];
+            const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
+            d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(ok ? r : 0.f, b, d[k], 0, 0, 0);
+        }
+    } else {
+        int mr;
+        const int iters = div_small(cnt + S - 1, S, mr);
+        for (int it = 0; it < iters; ++it) {
+            const int j = slr + it * S;
+            const bool ok = j < cnt;
+            const int jj = ok ? j : 0;
+            const Src<float> src = tile[jj];
+            const float b = row[jj][col];
+#pragma unroll
+            for (int k = 0; k < TP; ++k) {
+                const float dx = src.x - tx[k], dy = src.y - ty[k], dz = src.z - tz[k];
+                const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
+                d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32((ok && j != self_j[k]) ? r : 0.f, b, d[k], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TP; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[k][i] += (double)d[k][i];
+}
+
 __device__ __forceinline__ u32 logical_block() {
     const u32 G = gridDim.x, b = blockIdx.x;
     return (b % 8u) * (G / 8u) + (b / 8u);
 }
 
+// The FP32 velocity kernel of the target proxies (k_far_targets, |x - y|^2
+// denominator) accumulates on the matrix cores: per source j and target x_i
+// the VALU forms only r = 1 / |y_j - x_i|^2 (7 instructions), and
+// v_mfma_f32_4x4x1f32 adds r times the row B_j = q_j (y_j, 1) into a 4 x 4
+// block, so that W_i = sum_j r q_j y_j - x_i sum_j r q_j is recovered from
+// the block's four columns after the sums (an FMA saved per component and
+// the multiply by q per evaluation).  The split of y - x costs accuracy where
+// |y_j| (target-relative) is much larger than |y_j - x_i|: FP32 rounding of
+// the two sums grows by about |y_j| / |y_j - x_i|.  For CP and CC pairs the
+// acceptance criterion bounds that ratio by (1 + theta) / (1 - theta); for
+// near-field pairs (k_near) it is unbounded (nearly coincident particles),
+// so k_near keeps the VALU form.
+// Lane l = 4 b + i of a wave supplies A[b][i] (its own target) and
+// B[b][i] (column i of its block's source row); D[b][i][c] comes back in
+// lane 4 b + c, register i.  The 16 blocks of a wave are independent, so
+// every block must read one source stream: groups of four consecutive
+// threads share a source slice (slice widths are multiples of 4).
+// Measured on gv_l8 (N = 655362, theta 0.8, d 10): the matrix-core form of
+// k_far_targets takes 0.48-0.51 ms against 0.39 ms for the VALU form, so
+// the library is built with the VALU form; building with -DSTC_FAR_MFMA=1
+// (environment STC_FAR_MFMA=1 for the build script) selects this one.
+#ifndef STC_FAR_MFMA
+#define STC_FAR_MFMA 0
+#endif
+template <typename T, int DEN, bool FAR>
+struct UseMfma {
+    static constexpr bool value = STC_FAR_MFMA && FAR && sizeof(T) == 4 && DEN == STC_DEN_DIST2;
+};
+
 // LDS of a segment kernel with NTT threads: one tile of 2 NTT sources (two
-// consecutive ones staged per thread), one batch of NTT list entries
-template <typename T, int NTT, int TP>
+// consecutive ones staged per thread; with the matrix-core path also their
+// rows q (y, 1)), one batch of NTT list entries, and the per-slice partial
+// sums, which share the tiles' space (they are written after the last tile
+// is used).  NC partial components: 3, or 4 with the matrix-core path;
+// MAXT: targets per pass.
+template <typename T, int NTT, int TP, bool MF, int MAXT = TP * NTT>
 struct SegShared {
-    Src<T> tile[2 * NTT];
+    static constexpr int NC = MF ? 4 : 3;
+    struct Tiles {
+        Src<T> tile[2 * NTT];
+        float row[MF ? 2 * NTT : 1][4];
+    };
+    union {
+        Tiles t;
+        double red[TP][NC][NTT];  // per-slice partial sums of each thread's TP targets
+    } u;
     u32 ent_s[NTT];        // source node of a particle entry, storage slot of a proxy entry
     i32 ent_first[NTT];    // first particle of a particle source, -1 for proxy points
     u32 ent_pre[NTT + 1];  // exclusive prefix of the entries' source counts
     u32 wave_tot[NTT / 64];
     int self_flag;
-    double red[TP][3][NTT];  // per-slice partial sums of each thread's TP targets
+    float tgt[MF ? MAXT : 1][3];  // matrix-core path: the pass's target coordinates
 };
 
 // exclusive prefix over the NTT threads; returns the prefix, *total the sum
@@ -288,6 +417,31 @@ __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 firs
     return v;
 }
 
+// Writes source v to tile slot l (and, with the matrix-core path, its row
+// q (y, 1)).
+template <typename T, int NTT, int TP, bool MF, int MAXT>
+__device__ __forceinline__ void stage(SegShared<T, NTT, TP, MF, MAXT>& sh, int l, const Src<T>& v) {
+    sh.u.t.tile[l] = v;
+    if constexpr (MF) {
+        sh.u.t.row[l][0] = v.q * v.x;
+        sh.u.t.row[l][1] = v.q * v.y;
+        sh.u.t.row[l][2] = v.q * v.z;
+        sh.u.t.row[l][3] = v.q;
+    }
+}
+
+// tile_sum on a thread's accumulators acc[k][0..2] (FP64)
+template <typename T, int DEN, bool SELF, int TP>
+__device__ __forceinline__ void tile_sum_acc(const Src<T>* __restrict__ tile, int cnt, int sl, int S, const T* tx,
+                                             const T* ty, const T* tz, const int* self_j, double (*acc)[4]) {
+    double ax[TP], ay[TP], az[TP];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) ax[k] = acc[k][0], ay[k] = acc[k][1], az[k] = acc[k][2];
+    tile_sum<T, DEN, SELF, TP>(tile, cnt, sl, S, tx, ty, tz, self_j, ax, ay, az);
+#pragma unroll
+    for (int k = 0; k < TP; ++k) acc[k][0] = ax[k], acc[k][1] = ay[k], acc[k][2] = az[k];
+}
+
 // Accumulates, for this thread's TP targets, every entry of [e0, e1) in
 // `list` whose type bit is in type_mask.  Entries are taken in batches of
 // NTT: their source counts are scanned into an LDS prefix, so that for each
@@ -295,11 +449,13 @@ __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 firs
 // binary search) and all global loads of a tile are in flight together.  A
 // PP entry whose source is the target leaf itself (self_t) is evaluated on
 // its own with the j != i exclusion (me: the targets' indices there).
-template <typename T, int DEN, int NTT, int TP>
+// acc[k]: the target's sums (x, y, z), or with the matrix-core path the
+// lane's block column (see tile_sum_mf).
+template <typename T, int DEN, int NTT, int TP, bool MF, int MAXT>
 __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ list, u32 e0, u32 e1, u32 type_mask,
                                    u32 self_t, const int* me, bool act, int sl, int S, const T* tx, const T* ty,
-                                   const T* tz, double cx, double cy, double cz, SegShared<T, NTT, TP>& sh, double* ax,
-                                   double* ay, double* az) {
+                                   const T* tz, double cx, double cy, double cz, SegShared<T, NTT, TP, MF, MAXT>& sh,
+                                   double (*acc)[4]) {
     const int tid = threadIdx.x;
     const u64 mask = ((u64)1 << a.W) - 1;
     const u32 cmask = (1u << a.DB) - 1u;
@@ -340,12 +496,13 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
             const int nsrc = a.nend[self_t] - tb;
             for (int j0 = 0; j0 < nsrc; j0 += 2 * NTT) {
                 const int cnt = (nsrc - j0) < 2 * NTT ? (nsrc - j0) : 2 * NTT;
-                for (int l = tid; l < cnt; l += NTT) sh.tile[l] = load_source<T>(a, self_t, tb, j0 + l, cx, cy, cz, qscale);
+                for (int l = tid; l < cnt; l += NTT) stage(sh, l, load_source<T>(a, self_t, tb, j0 + l, cx, cy, cz, qscale));
                 __syncthreads();
                 int sj[TP];
 #pragma unroll
                 for (int k = 0; k < TP; ++k) sj[k] = me[k] - j0;
-                if (act) tile_sum<T, DEN, true, TP>(sh.tile, cnt, sl, S, tx, ty, tz, sj, ax, ay, az);
+                if constexpr (MF) tile_sum_mf<true, TP>(sh.u.t.tile, sh.u.t.row, cnt, sl, S, act, tx, ty, tz, sj, acc);
+                else if (act) tile_sum_acc<T, DEN, true, TP>(sh.u.t.tile, cnt, sl, S, tx, ty, tz, sj, acc);
                 __syncthreads();
             }
         }
@@ -362,30 +519,34 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                     if (sh.ent_pre[mid] <= g) lo = mid;
                     else hi = mid;
                 }
-                sh.tile[l0] = load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g - sh.ent_pre[lo]), cx, cy,
-                                             cz, qscale);
+                stage(sh, l0, load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g - sh.ent_pre[lo]), cx, cy, cz,
+                                             qscale));
                 if (l0 + 1 < cnt) {
                     while (sh.ent_pre[lo + 1] <= g + 1) ++lo;  // ent_pre[ne] = total > g + 1
-                    sh.tile[l0 + 1] = load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g + 1 - sh.ent_pre[lo]),
-                                                     cx, cy, cz, qscale);
+                    stage(sh, l0 + 1, load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g + 1 - sh.ent_pre[lo]),
+                                                     cx, cy, cz, qscale));
                 }
             }
             __syncthreads();
-            if (act) tile_sum<T, DEN, false, TP>(sh.tile, cnt, sl, S, tx, ty, tz, nullptr, ax, ay, az);
+            if constexpr (MF) tile_sum_mf<false, TP>(sh.u.t.tile, sh.u.t.row, cnt, sl, S, act, tx, ty, tz, nullptr, acc);
+            else if (act) tile_sum_acc<T, DEN, false, TP>(sh.u.t.tile, cnt, sl, S, tx, ty, tz, nullptr, acc);
             __syncthreads();
         }
     }
 }
 
 // A pass over up to TP x NTT targets: thread (ti, sl) takes targets ti,
-// ti + h, ... (h = ceil(ntc / TP)) and source slice sl of S = NTT / h.
-// Targets past ntc duplicate the first one and are not written back.
-template <int TP>
+// ti + h, ... (h = ceil(ntc / TP), rounded up to a multiple of 4 with the
+// matrix-core path so that its 4-lane blocks never straddle two slices) and
+// source slice sl of S = NTT / h.  Targets past ntc duplicate a valid one
+// and are not written back.
+template <int TP, bool MF = false>
 struct TargetGroup {
     int h, S, ti, sl, me[TP];
     bool act, valid[TP];
     __device__ TargetGroup(int ntc, int nthreads, int base) {
         h = (ntc + TP - 1) / TP;
+        if (MF) h = (h + 3) & ~3;
         int r;
         S = div_small(nthreads, h, r);
         sl = div_small((int)threadIdx.x, h, ti);
@@ -393,7 +554,8 @@ struct TargetGroup {
 #pragma unroll
         for (int k = 0; k < TP; ++k) {
             valid[k] = ti + k * h < ntc;
-            me[k] = base + (valid[k] ? ti + k * h : ti);
+            // a padding thread (ti >= ntc, only with rounded widths) takes the first target
+            me[k] = base + (valid[k] ? ti + k * h : (ti < ntc ? ti : 0));
         }
     }
 };
@@ -419,6 +581,29 @@ __device__ __forceinline__ void slice_sums(const double (*red)[3][NTT], int h, i
     }
 }
 
+// slice_sums of the matrix-core path: per (target, component) the sums
+// over the slices of the block columns c (sum_j r q y_c) and 3 (sum_j r q),
+// combined as W_c = sum_c - x_c sum_3 with the target's FP32 coordinate.
+template <int NTT, int TP, typename F>
+__device__ __forceinline__ void slice_sums_mf(const double (*red)[4][NTT], const float (*tgt)[3], int h, int S,
+                                              int ntc, F&& f) {
+    for (int o = threadIdx.x; o < 3 * TP * h; o += NTT) {
+        int k = 0;
+#pragma unroll
+        for (int j = 1; j < TP; ++j) k += o >= j * 3 * h;
+        const int rem = o - k * 3 * h;
+        const int c = (rem >= h) + (rem >= 2 * h), ti = rem - c * h;
+        if (ti + k * h < ntc) {
+            double sc = 0.0, s3 = 0.0;
+            for (int q = 0; q < S; ++q) {
+                sc += red[k][c][q * h + ti];
+                s3 += red[k][3][q * h + ti];
+            }
+            f(ti + k * h, c, sc - (double)tgt[ti + k * h][c] * s3);
+        }
+    }
+}
+
 // range of list entries of this workgroup (segments: key >> sh); returns
 // false if empty
 __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int sh, u32& e, u32& e_hi) {
@@ -435,11 +620,30 @@ __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_
 constexpr int NEAR_TP = 1;  // targets per thread: leaves are small, occupancy matters more
 constexpr int FAR_TP = 3;   // the proxy points of a node: each staged source feeds three targets (66 = 22 x 3: 242 of 256 threads busy, against 231 at two)
 
+// The per-slice partial sums of a pass into LDS: three components per
+// thread, or with the matrix-core path this lane's block column for the four
+// targets of its block (lane 4 b + c holds column c of rows 4 b .. 4 b + 3).
+template <typename T, int NTT, int TP, bool MF, int MAXT>
+__device__ __forceinline__ void store_partials(SegShared<T, NTT, TP, MF, MAXT>& sh, bool act,
+                                               const double (*acc)[4]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < TP; ++k) {
+        if constexpr (MF) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sh.u.red[k][tid & 3][(tid & ~3) + i] = acc[k][i];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sh.u.red[k][c][tid] = act ? acc[k][c] : 0.0;
+        }
+    }
+}
+
 template <typename T, int DEN, int NT>
 __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
     constexpr int TP = NEAR_TP;
-    __shared__ SegShared<T, NT, TP> sh;
-    const int tid = threadIdx.x;
+    constexpr bool MF = UseMfma<T, DEN, false>::value;
+    __shared__ SegShared<T, NT, TP, MF> sh;
     u32 n = a.counters[C_TLIST];
     if (n > a.cap) n = a.cap;
     u32 e, e_hi;
@@ -455,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
         for (int cb = 0; cb < nt; cb += TP * NT) {
             const int ntc = (nt - cb) < TP * NT ? (nt - cb) : TP * NT;
-            const TargetGroup<TP> tg(ntc, NT, cb);
+            const TargetGroup<TP, MF> tg(ntc, NT, cb);
             T tx[TP], ty[TP], tz[TP];
             int me[TP];
 #pragma unroll
@@ -465,22 +669,24 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
                 ty[k] = target_reg<T>(a.sy[gi] - cy);
                 tz[k] = target_reg<T>(a.sz[gi] - cz);
                 me[k] = tg.valid[k] ? tg.me[k] : -1;  // a duplicate target's exclusion never matches
+                if constexpr (MF) {
+                    if (tg.act && tg.sl == 0 && tg.valid[k]) {
+                        sh.tgt[tg.ti + k * tg.h][0] = tx[k];
+                        sh.tgt[tg.ti + k * tg.h][1] = ty[k];
+                        sh.tgt[tg.ti + k * tg.h][2] = tz[k];
+                    }
+                }
             }
-            double ax[TP], ay[TP], az[TP];
+            double acc[TP][4];
 #pragma unroll
-            for (int k = 0; k < TP; ++k) ax[k] = ay[k] = az[k] = 0.0;
-            accumulate_entries<T, DEN, NT, TP>(a, a.tlist, e, se, type_mask, t, me, tg.act, tg.sl, tg.S, tx, ty, tz,
-                                               cx, cy, cz, sh, ax, ay, az);
-#pragma unroll
-            for (int k = 0; k < TP; ++k) {
-                sh.red[k][0][tid] = tg.act ? ax[k] : 0.0;
-                sh.red[k][1][tid] = tg.act ? ay[k] : 0.0;
-                sh.red[k][2][tid] = tg.act ? az[k] : 0.0;
-            }
+            for (int k = 0; k < TP; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0;
+            accumulate_entries<T, DEN>(a, a.tlist, e, se, type_mask, t, me, tg.act, tg.sl, tg.S, tx, ty, tz, cx, cy,
+                                       cz, sh, acc);
+            store_partials(sh, tg.act, acc);
             __syncthreads();
-            slice_sums<NT, TP>(sh.red, tg.h, tg.S, ntc, [&](int j, int c, double v) {
-                a.Wacc[3 * (size_t)(tb + cb + j) + c] += v;
-            });
+            auto add = [&](int j, int c, double v) { a.Wacc[3 * (size_t)(tb + cb + j) + c] += v; };
+            if constexpr (MF) slice_sums_mf<NT, TP>(sh.u.red, sh.tgt, tg.h, tg.S, ntc, add);
+            else slice_sums<NT, TP>(sh.u.red, tg.h, tg.S, ntc, add);
             __syncthreads();
         }
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
@@ -490,7 +696,8 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
 template <typename T, int DEN, int NTT>
 __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
     constexpr int TP = FAR_TP;
-    __shared__ SegShared<T, NTT, TP> sh;
+    constexpr bool MF = UseMfma<T, DEN, true>::value;
+    __shared__ SegShared<T, NTT, TP, MF, TP * NTT / 4> sh;
     __shared__ double wt[kMaxNp][3];
     __shared__ double co[kMaxNp][3];
     __shared__ double nd[kMaxNp];
@@ -514,7 +721,7 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
         // threads: all 66 points in one pass, 33 target pairs x 7 slices)
         for (int cb = 0; cb < np; cb += TP * NTT / 4) {
             const int ntc = (np - cb) < TP * NTT / 4 ? (np - cb) : TP * NTT / 4;
-            const TargetGroup<TP> tg(ntc, NTT, cb);
+            const TargetGroup<TP, MF> tg(ntc, NTT, cb);
             T tx[TP], ty[TP], tz[TP];
             int nome[TP];
 #pragma unroll
@@ -526,24 +733,28 @@ __global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
                 ty[k] = target_reg<T>(y[1] - cy);
                 tz[k] = target_reg<T>(y[2] - cz);
                 nome[k] = -1;
+                if constexpr (MF) {
+                    if (tg.act && tg.sl == 0 && tg.valid[k]) {
+                        sh.tgt[tg.ti + k * tg.h][0] = tx[k];
+                        sh.tgt[tg.ti + k * tg.h][1] = ty[k];
+                        sh.tgt[tg.ti + k * tg.h][2] = tz[k];
+                    }
+                }
             }
-            double ax[TP], ay[TP], az[TP];
+            double acc[TP][4];
 #pragma unroll
-            for (int k = 0; k < TP; ++k) ax[k] = ay[k] = az[k] = 0.0;
-            accumulate_entries<T, DEN, NTT, TP>(a, a.nlist, e, se, 3u, 0xffffffffu, nome, tg.act, tg.sl, tg.S, tx, ty,
-                                                tz, cx, cy, cz, sh, ax, ay, az);
-#pragma unroll
-            for (int k = 0; k < TP; ++k) {
-                sh.red[k][0][tid] = tg.act ? ax[k] : 0.0;
-                sh.red[k][1][tid] = tg.act ? ay[k] : 0.0;
-                sh.red[k][2][tid] = tg.act ? az[k] : 0.0;
-            }
+            for (int k = 0; k < TP; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0;
+            accumulate_entries<T, DEN>(a, a.nlist, e, se, 3u, 0xffffffffu, nome, tg.act, tg.sl, tg.S, tx, ty, tz, cx,
+                                       cy, cz, sh, acc);
+            store_partials(sh, tg.act, acc);
             __syncthreads();
-            slice_sums<NTT, TP>(sh.red, tg.h, tg.S, ntc, [&](int j, int c, double v) { wt[cb + j][c] = v; });
+            auto put = [&](int j, int c, double v) { wt[cb + j][c] = v; };
+            if constexpr (MF) slice_sums_mf<NTT, TP>(sh.u.red, sh.tgt, tg.h, tg.S, ntc, put);
+            else slice_sums<NTT, TP>(sh.u.red, tg.h, tg.S, ntc, put);
             __syncthreads();
         }
         // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
-        block_matvec<NTT, 3>(a.ref.vinvT + qoff, np, nd, wt, &sh.red[0][0][0], co);
+        block_matvec<NTT, 3>(a.ref.vinvT + qoff, np, nd, wt, &sh.u.red[0][0][0], co);
         const size_t ts = (size_t)a.slot[t] * a.NPT + poff;
         // stored as c_k alpha_k: the basis coefficient of the interpolation
         // folded in once per node rather than once per particle

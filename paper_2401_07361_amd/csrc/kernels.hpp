@@ -3,6 +3,8 @@
 
 #include "common.hpp"
 
+struct stc_amr;
+
 namespace stc {
 
 // Degree classes: a context evaluates far-field interactions at one degree
@@ -209,4 +211,6 @@ void launch_resolve(hipStream_t s, const LearnedArgs& a, bool use_model);
 void launch_pair_errors(hipStream_t s, const LearnedArgs& la, const EvalArgs& a, int dist2, u32 lim, double* err);
 void launch_labels(hipStream_t s, const LearnedArgs& la, u32 lim, const double* err, double tol, float* y);
 
+// the stream an adaptive-mesh object enqueues on (amr.hip)
+hipStream_t amr_stream(const stc_amr* m);
 }  // namespace stc

@@ -1162,7 +1162,7 @@ static stc_status rk4_capture(stc_ctx* c, int members, const i64* off, double* d
 }
 
 static stc_status rk4_run(stc_ctx* c, int members, const i64* off, double* d_x, double* d_zeta,
-                          const double* d_area, double dt, double omega, int32_t n_steps) {
+                          const double* d_area, double dt, double omega, int32_t n_steps, bool eager = false) {
     const i64 n = off[members];
     if (n_steps < 0 || !std::isfinite(dt) || !std::isfinite(omega))
         return fail(c, STC_ERR_INVALID_ARG, "bad n_steps, dt or omega");
@@ -1176,7 +1176,7 @@ static stc_status rk4_run(stc_ctx* c, int members, const i64* off, double* d_x, 
     // then vanish or turn negative for close pairs, |x - y|^2 / 2 cannot
     if (c->p.denominator != STC_DEN_DIST2)
         return fail(c, STC_ERR_INVALID_ARG, "stc_rk4 needs the |x-y|^2/2 denominator (stage points are off the sphere)");
-    const bool use_graph = (c->p.flags & STC_FLAG_EAGER_RK4) == 0;
+    const bool use_graph = !eager && (c->p.flags & STC_FLAG_EAGER_RK4) == 0;
     // the steps read their start time from the device clock (a kernel, not a
     // memset: the clock is also written inside captured steps)
     if (c->forcing_on) launch_forcing_clock(c->stream, c->forcing_t, c->forcing.time, 1);
@@ -1243,6 +1243,26 @@ stc_status stc_rk4_batched(stc_ctx* c, int32_t members, const int64_t* h_offsets
     if (!c) return STC_ERR_INVALID_ARG;
     if (check_offsets(c, members, h_offsets) < 0) return fail(c, STC_ERR_INVALID_ARG, "bad member count or offsets");
     return rk4_run(c, members, h_offsets, d_x, d_zeta, d_area, dt, omega, n_steps);
+}
+
+stc_status stc_amr_rk4(stc_amr* m, stc_ctx* c, double dt, double omega, int32_t n_steps) {
+    if (!m || !c) return STC_ERR_INVALID_ARG;
+    if (n_steps < 0) return fail(c, STC_ERR_INVALID_ARG, "n_steps < 0");
+    if (amr_stream(m) != c->stream) return fail(c, STC_ERR_INVALID_ARG, "the mesh and the context use different streams");
+    if (c->learned || c->members != 1) return fail(c, STC_ERR_INVALID_ARG, "a single-member context without gating");
+    for (int step = 0; step < n_steps; ++step) {
+        int64_t n = 0;
+        double *x = nullptr, *z = nullptr, *a = nullptr;
+        stc_status st = stc_amr_particles(m, &n, &x, &z, &a);
+        if (st != STC_OK) return st;
+        if (n > c->n_max) return fail(c, STC_ERR_CAPACITY, "the mesh has more particles than the context holds");
+        const i64 off[2] = {0, n};
+        st = rk4_run(c, 1, off, x, z, a, dt, omega, 1, true);
+        if (st == STC_OK) st = stc_amr_set_state(m, n, x, z);
+        if (st == STC_OK) st = stc_amr_adapt(m);
+        if (st != STC_OK) return st;
+    }
+    return STC_OK;
 }
 
 stc_status stc_node_layout(const stc_ctx* c, int32_t* node_bits, int64_t* nodes_per_member, int64_t* node_array_len) {

@@ -22,12 +22,17 @@ def velocity_scale(u):
     return float(stc.label_scale(u).item())
 
 
-def collect(inputs, tol_rel, theta, theta_max, degree=10, n_crit=64, cap_per_input=None, log=None):
-    """Features (m, 16) BF16 and labels (m, 4) float32 from every input
-    (x, zeta, area); the label tolerance of an input is tol_rel times its
-    velocity scale (from a fixed-degree evaluation of the same context)."""
+def collect(inputs, tol_rel, theta, theta_max, degree=10, n_crit=64, cap_per_input=None, log=None,
+            max_samples=None):
+    """Features (m, 16) BF16 and labels (m, 4) float32 from the inputs
+    (an iterable of (x, zeta, area) device tensors, consumed lazily); the
+    label tolerance of an input is tol_rel times its velocity scale (from a
+    fixed-degree evaluation of the same context).  With max_samples, inputs
+    are taken until that many samples are collected and the result is cut to
+    exactly max_samples rows."""
     import torch
     feats, labs = [], []
+    total = 0
     for i, (x, z, a) in enumerate(inputs):
         n = x.shape[0]
         cap = cap_per_input or 4 * n
@@ -41,11 +46,17 @@ def collect(inputs, tol_rel, theta, theta_max, degree=10, n_crit=64, cap_per_inp
         ctx.close()
         feats.append(f.clone())
         labs.append(y.clone())
+        total += f.shape[0]
         if log:
             yn = y.cpu().numpy()
             log(f"input {i}: N={n} candidates {m} accepted {yn[:, 0].mean():.3f} "
-                f"class mean {(yn[:, 1:].sum(1)[yn[:, 0] > 0]).mean():.2f}")
-    return torch.cat(feats), torch.cat(labs)
+                f"class mean {(yn[:, 1:].sum(1)[yn[:, 0] > 0]).mean():.2f} (total {total})")
+        if max_samples is not None and total >= max_samples:
+            break
+    F, Y = torch.cat(feats), torch.cat(labs)
+    if max_samples is not None:
+        F, Y = F[:max_samples].contiguous(), Y[:max_samples].contiguous()
+    return F, Y
 
 
 def train(features, labels, epochs=8, batch=4096, lr=2e-3, seed=0, init_seed=1):

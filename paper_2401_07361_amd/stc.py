@@ -50,6 +50,12 @@ class LaunchConfig(ctypes.Structure):
         return (self.near_threads, self.near_blocks_per_cu, self.far_threads, self.far_blocks_per_cu)
 
 
+class AmrParams(ctypes.Structure):
+    """stc_amr_params: adaptive refinement of the particle triangulation (Appendix A)."""
+    _fields_ = [("eps1", ctypes.c_double), ("eps2", ctypes.c_double), ("omega", ctypes.c_double),
+                ("max_levels", ctypes.c_int32)]
+
+
 class Forcing(ctypes.Structure):
     """stc_forcing: the vorticity forcing of the polar-vortex collapse (Sec. 4.4)."""
     _fields_ = [("k", ctypes.c_int32), ("omega", ctypes.c_double), ("lat1", ctypes.c_double),
@@ -115,6 +121,16 @@ def _load():
         "stc_set_forcing": (I32, [P, ctypes.POINTER(Forcing)]),
         "stc_get_forcing": (I32, [P, ctypes.POINTER(Forcing), PI32]),
         "stc_forcing_field": (I32, [VP, ctypes.POINTER(Forcing), I64, VP, VP]),
+        "stc_amr_workspace_size": (I32, [ctypes.POINTER(AmrParams), I64, I64, PI32, ctypes.POINTER(SZ), PI64]),
+        "stc_amr_create": (I32, [ctypes.POINTER(AmrParams), I64, I64, PI32, VP, SZ, VP, ctypes.POINTER(P)]),
+        "stc_amr_destroy": (I32, [P]),
+        "stc_amr_set_state": (I32, [P, I64, VP, VP]),
+        "stc_amr_adapt": (I32, [P]),
+        "stc_amr_particles": (I32, [P, PI64, ctypes.POINTER(VP), ctypes.POINTER(VP), ctypes.POINTER(VP)]),
+        "stc_amr_stats": (I32, [P, PI64, PI64, PI64, PI64, PI64]),
+        "stc_amr_copy_slots": (I32, [P, I64, PI32, PI32]),
+        "stc_amr_last_error": (ctypes.c_char_p, [P]),
+        "stc_amr_rk4": (I32, [P, P, D, D, I32]),
         "stc_sync": (I32, [P]),
         "stc_list_counts": (I32, [P, PI64, PI64]),
         "stc_copy_list": (I32, [P, I32, I64, PI64, PI64]),
@@ -725,3 +741,91 @@ class Context:
         _check(_lib.stc_node_geometry(self._ctx, node_id, v.ctypes.data_as(PD), c.ctypes.data_as(PD),
                                       ctypes.byref(r)))
         return v.reshape(3, 3), c, r.value
+
+
+class AdaptiveMesh:
+    """Adaptive refinement of the particle triangulation (stc_amr_*): x0 (n0, 3)
+    and faces (F, 3) of the initial mesh (host arrays); the live particles'
+    device arrays live in this object's workspace tensor and are returned as
+    views of it."""
+
+    def __init__(self, x0, faces, eps1, eps2, omega, max_levels=3, stream=None):
+        import torch
+        self.p = AmrParams(float(eps1), float(eps2), float(omega), int(max_levels))
+        f = np.ascontiguousarray(faces, dtype=np.int32)
+        self.n0 = int(len(x0))
+        pf = f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        nb, cap = ctypes.c_size_t(0), ctypes.c_int64(0)
+        _check(_lib.stc_amr_workspace_size(ctypes.byref(self.p), self.n0, len(f), pf, ctypes.byref(nb),
+                                           ctypes.byref(cap)))
+        self.capacity = cap.value
+        self._ws = workspace_tensor(nb.value)
+        self._amr = ctypes.c_void_p()
+        _check(_lib.stc_amr_create(ctypes.byref(self.p), self.n0, len(f), pf, ctypes.c_void_p(self._ws.data_ptr()),
+                                   nb, _stream(stream), ctypes.byref(self._amr)))
+        self._stream = stream
+        x0d = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float64)).cuda()
+        self._x0 = x0d
+
+    def _check(self, st):
+        if st != 0:
+            raise StcError(st, status_string(st) + ": " + _lib.stc_amr_last_error(self._amr).decode())
+
+    def close(self):
+        if self._amr:
+            _lib.stc_amr_destroy(self._amr)
+            self._amr = ctypes.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def particles(self):
+        """(x (n, 3), zeta (n,), area (n,)): views of the live particles."""
+        import torch
+        n = ctypes.c_int64(0)
+        px, pz, pa = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        self._check(_lib.stc_amr_particles(self._amr, ctypes.byref(n), ctypes.byref(px), ctypes.byref(pz),
+                                           ctypes.byref(pa)))
+        base = self._ws.data_ptr()
+        m = n.value
+
+        def view(ptr, count):
+            off = ptr.value - base
+            return self._ws[off:off + 8 * count].view(torch.float64)
+
+        return view(px, 3 * m).view(m, 3), view(pz, m), view(pa, m)
+
+    def set_state(self, x, zeta):
+        import torch
+        n = x.shape[0]
+        self._check(_lib.stc_amr_set_state(self._amr, n, _dptr(x, "x", torch.float64, 3 * n),
+                                           _dptr(zeta, "zeta", torch.float64, n)))
+
+    def adapt(self):
+        self._check(_lib.stc_amr_adapt(self._amr))
+
+    def stats(self):
+        v = [ctypes.c_int64(0) for _ in range(5)]
+        self._check(_lib.stc_amr_stats(self._amr, *[ctypes.byref(t) for t in v]))
+        return dict(zip(("particles", "leaves", "merged", "split", "capacity"), [t.value for t in v]))
+
+    def slots(self):
+        """Slot of every live particle and the edge ends of every particle slot."""
+        n = self.particles()[1].numel()
+        sl = np.zeros(max(n, 1), dtype=np.int32)
+        ends = np.zeros((self.capacity, 2), dtype=np.int32)
+        PI32 = ctypes.POINTER(ctypes.c_int32)
+        self._check(_lib.stc_amr_copy_slots(self._amr, self.capacity, sl.ctypes.data_as(PI32),
+                                            ends.ctypes.data_as(PI32)))
+        return sl[:n], ends
+
+    def rk4(self, ctx, dt, omega, n_steps):
+        """n_steps RK4 steps of the live particles with the tree code of ctx,
+        each followed by an adaptation pass (stc_amr_rk4)."""
+        st = _lib.stc_amr_rk4(self._amr, ctx._ctx, float(dt), float(omega), int(n_steps))
+        if st != 0:
+            _check(st, ctx._ctx)
