@@ -10,7 +10,7 @@ vertices a, b, c (current positions and vorticities):
     C(T):  |A_T (zeta_a + zeta_b + zeta_c) / 3| >= eps1   (circulation)
         or max(zeta) - min(zeta)               >= eps2   (variation)
 
-A_T the spherical area of T (Van Oosterom-Strackee).  A leaf with C(T) at
+A_T the area of T (see the quadrature reading below).  A leaf with C(T) at
 depth below max_levels is split into four, (a, m_ab, m_ca), (m_ab, b, m_bc),
 (m_ca, m_bc, c), (m_ab, m_bc, m_ca); a refined triangle whose four children
 are leaves and for which C(T) no longer holds is merged back (never below the
@@ -32,9 +32,18 @@ Readings where the appendix is silent (the same in the GPU library):
   unchanged by every particle (dzeta/dt = -2 Omega dz/dt), so the new
   particle takes the mean absolute vorticity of the edge ends minus
   2 Omega z at its own position.
-* Quadrature weights after a pass: A_i = sum over the leaf triangles having
-  i as a vertex of A_T / 3 (the barycentric-dual areas the initial grid uses,
-  extended to the adapted mesh), from the current positions.
+* Areas are Lagrangian (the flow is incompressible, and without refinement
+  the paper keeps every A_i constant in time): each triangle carries the
+  area it was given when created -- an initial triangle its spherical area
+  (Van Oosterom-Strackee) at the start, the four children of a split the
+  parent's carried area in proportion to their spherical areas at the
+  moment of the split -- and a merged triangle gets back its own carried
+  area (the sum of its children's).  The straight-edged triangle of a
+  distorted mesh no longer bounds the material patch, so areas recomputed
+  from current positions grow without bound where the flow folds the mesh.
+  Quadrature weights: A_i = sum over the leaf triangles having i as a
+  vertex of A_T / 3 (the barycentric-dual areas of the initial grid); they
+  sum to 4 pi at every pass.
 * Each call of ``adapt`` is one pass; an initial condition given as a
   function is resolved by alternating passes with re-evaluating the
   function at the particles (``resolve_initial``).
@@ -62,8 +71,8 @@ def tri_area(a, b, c):
     return 2.0 * float(np.arctan2(trip, ((1.0 + ab) + bc) + ca))
 
 
-def criterion(xa, xb, xc, za, zb, zc, eps1, eps2):
-    area = tri_area(xa, xb, xc)
+def criterion(area, za, zb, zc, eps1, eps2):
+    """C(T) for a triangle of area `area` with vertex vorticities za, zb, zc."""
     circ = area * (((za + zb) + zc) / 3.0)
     spread = max(za, zb, zc) - min(za, zb, zc)
     return abs(circ) >= eps1 or spread >= eps2
@@ -85,17 +94,21 @@ class Mesh:
         self.zeta = [float(v) for v in np.asarray(zeta0, dtype=np.float64)]
         self.alive = [True] * len(self.x)
         self.edge_mid = {}          # (min, max) particle pair -> midpoint particle
-        # triangles: vertices, depth, state, children (list of 4 ids or None)
-        self.tv, self.depth, self.state, self.children = [], [], [], []
+        # triangles: vertices, depth, state, children (list of 4 ids or None), carried area
+        self.tv, self.depth, self.state, self.children, self.tarea = [], [], [], [], []
         self.roots = []
         for f in np.asarray(faces, dtype=np.int64):
-            self.roots.append(self._new_tri(tuple(int(v) for v in f), 0))
+            i, j, k = (int(v) for v in f)
+            t = self._new_tri((i, j, k), 0)
+            self.tarea[t] = tri_area(self.x[i], self.x[j], self.x[k])
+            self.roots.append(t)
 
     def _new_tri(self, v, depth):
         self.tv.append(v)
         self.depth.append(depth)
         self.state.append(LEAF)
         self.children.append(None)
+        self.tarea.append(0.0)
         return len(self.tv) - 1
 
     # -- the particle state -------------------------------------------------------
@@ -119,7 +132,7 @@ class Mesh:
         a = [0.0] * len(self.x)
         for t in self.leaves():
             i, j, k = self.tv[t]
-            w = tri_area(self.x[i], self.x[j], self.x[k]) / 3.0
+            w = self.tarea[t] / 3.0
             a[i] += w
             a[j] += w
             a[k] += w
@@ -128,8 +141,7 @@ class Mesh:
     # -- one adaptation pass -----------------------------------------------------------
     def _crit(self, t):
         i, j, k = self.tv[t]
-        return criterion(self.x[i], self.x[j], self.x[k], self.zeta[i], self.zeta[j], self.zeta[k],
-                         self.eps1, self.eps2)
+        return criterion(self.tarea[t], self.zeta[i], self.zeta[j], self.zeta[k], self.eps1, self.eps2)
 
     def _mid(self, a, b):
         key = (min(a, b), max(a, b))
@@ -178,6 +190,11 @@ class Mesh:
             else:
                 for ch in self.children[t]:
                     self.state[ch] = LEAF
+            # the parent's carried area, shared in proportion to the children's spherical areas
+            g = [tri_area(*(self.x[v] for v in self.tv[ch])) for ch in self.children[t]]
+            gs = ((g[0] + g[1]) + g[2]) + g[3]
+            for ch, gc in zip(self.children[t], g):
+                self.tarea[ch] = self.tarea[t] * (gc / gs)
             self.state[t] = REFINED
         used = set()
         for t in self.leaves():

@@ -15,17 +15,18 @@ from oracle import amr
 def test_criterion_hand_values():
     """The octant triangle (e_x, e_y, e_z) has area pi / 2 exactly."""
     ex, ey, ez = np.eye(3)
-    assert amr.tri_area(ex, ey, ez) == pytest.approx(np.pi / 2, rel=1e-15)
+    A = amr.tri_area(ex, ey, ez)
+    assert A == pytest.approx(np.pi / 2, rel=1e-15)
     # circulation (pi/2) * mean(zeta): mean 1 -> 1.5708; either sign counts
-    assert amr.criterion(ex, ey, ez, 1.0, 1.0, 1.0, 1.570, 10.0)
-    assert not amr.criterion(ex, ey, ez, 1.0, 1.0, 1.0, 1.571, 10.0)
-    assert amr.criterion(ex, ey, ez, -1.0, -1.0, -1.0, 1.570, 10.0)
+    assert amr.criterion(A, 1.0, 1.0, 1.0, 1.570, 10.0)
+    assert not amr.criterion(A, 1.0, 1.0, 1.0, 1.571, 10.0)
+    assert amr.criterion(A, -1.0, -1.0, -1.0, 1.570, 10.0)
     # the mean, not the sum: (0.5, 1, 1.5) has mean 1 as well
-    assert amr.criterion(ex, ey, ez, 0.5, 1.0, 1.5, 1.570, 10.0)
-    assert not amr.criterion(ex, ey, ez, 0.5, 1.0, 1.5, 1.571, 10.0)
+    assert amr.criterion(A, 0.5, 1.0, 1.5, 1.570, 10.0)
+    assert not amr.criterion(A, 0.5, 1.0, 1.5, 1.571, 10.0)
     # variation max - min: 0.3
-    assert amr.criterion(ex, ey, ez, 0.0, 0.3, 0.1, 10.0, 0.3)
-    assert not amr.criterion(ex, ey, ez, 0.0, 0.3, 0.1, 10.0, 0.3000001)
+    assert amr.criterion(A, 0.0, 0.3, 0.1, 10.0, 0.3)
+    assert not amr.criterion(A, 0.0, 0.3, 0.1, 10.0, 0.3000001)
 
 
 def test_new_particle_carries_mean_absolute_vorticity():
@@ -133,3 +134,39 @@ def test_gaussian_vortex_initial_resolution():
     xc = np.array([np.cos(np.pi / 20), 0.0, np.sin(np.pi / 20)])
     new = x[len(x0):]
     assert np.linalg.norm(new - xc, axis=1).max() < 1.0     # added particles sit near the vortex
+
+
+def test_areas_are_carried_not_recomputed():
+    """Moving the particles changes no weight: the triangles carry their
+    areas (the flow is incompressible); a split shares the parent's carried
+    area among its children in proportion to their spherical areas, so the
+    weights still sum to 4 pi even when the particles have moved; a merge
+    gives the parent its own carried area back."""
+    x0, f0 = S.icosahedral_grid(1, return_faces=True)
+    z0 = np.zeros(len(x0))
+    m = amr.Mesh(x0, z0, f0, eps1=1e9, eps2=0.5, omega=0.0)
+    a0 = m.particles()[3].copy()
+    # move every particle (a rotation plus a perturbation): no pass, no change of weights
+    rng = np.random.default_rng(3)
+    R = S.random_rotation(9)
+    xm = x0 @ R.T + 0.02 * rng.standard_normal(x0.shape)
+    xm /= np.linalg.norm(xm, axis=1, keepdims=True)
+    m.set_state(np.arange(len(x0)), xm, z0)
+    assert np.array_equal(m.particles()[3], a0)
+    # a spread of 1 at one particle splits its triangles there
+    z1 = z0.copy()
+    z1[7] = 1.0
+    m.set_state(np.arange(len(x0)), xm, z1)
+    m.adapt()
+    ids, x, z, a = m.particles()
+    assert len(ids) > len(x0)
+    assert a.sum() == pytest.approx(4 * np.pi, rel=1e-13)
+    # every split triangle's children carry exactly its area between them
+    for t in range(len(m.tv)):
+        if m.state[t] == amr.REFINED:
+            ch = m.children[t]
+            assert sum(m.tarea[c] for c in ch) == pytest.approx(m.tarea[t], rel=1e-14)
+    # merge back: the initial weights return bitwise
+    m.set_state(ids, x, np.zeros(len(ids)))
+    m.adapt()
+    assert np.array_equal(m.particles()[3], a0)
