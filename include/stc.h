@@ -234,6 +234,25 @@ stc_status stc_velocity_batched(stc_ctx* ctx, int32_t members, const int64_t* h_
                                 const double* d_x, const double* d_zeta, const double* d_area,
                                 double* d_u);
 
+/* One stc_velocity(ctx, n, d_x, d_zeta, d_area, d_u) captured in a HIP graph
+ * (on the context's own capture stream), replayed by stc_graph_launch on the
+ * context's current stream: the same kernels with the same arguments, and
+ * the same result as stc_velocity, without per-kernel launch costs on the
+ * host.  Host values are fixed at capture: n, the pointers, the launch
+ * shapes, the forcing and its time, the network of a learned context; a
+ * change of any of them needs a new graph.  The inputs may change in place
+ * between replays.  Every replay is bracketed by two events recorded on the
+ * launch stream (outside the graph): stc_graph_last_ms gives the last
+ * replay's duration (synchronises).  A graph must be destroyed before its
+ * context.  Errors as stc_velocity; STC_ERR_DEVICE if capture or
+ * instantiation fails; stc_graph_last_ms before any replay: STC_ERR_STATE. */
+typedef struct stc_graph stc_graph;
+stc_status stc_velocity_graph(stc_ctx* ctx, int64_t n, const double* d_x, const double* d_zeta,
+                              const double* d_area, double* d_u, stc_graph** out);
+stc_status stc_graph_launch(stc_graph* graph);
+stc_status stc_graph_last_ms(stc_graph* graph, double* ms);
+stc_status stc_graph_destroy(stc_graph* graph);
+
 /* Bytes of device scratch stc_direct / stc_direct_stream need for m targets
  * over n sources on the current device (0 when the sum is not split; the
  * split depends on the device's compute units and the kernel's occupancy).
@@ -336,9 +355,14 @@ stc_status stc_rk4(stc_ctx* ctx, int64_t n, double* d_x, double* d_zeta, const d
  * when no leaf has it as a vertex; a new particle takes the mean absolute
  * vorticity zeta + omega_abs z of its edge's ends (omega_abs = 2 Omega, the
  * quantity the particle system carries unchanged) minus omega_abs z at its
- * position; quadrature weights A_i = sum of A_T / 3 over the leaves having
- * i as a vertex.  The live particles (the tree code's input) are kept in
- * slot order: the initial particles first, in input order. */
+ * position; triangles carry their areas (the flow is incompressible): an
+ * initial triangle its spherical area at the first pass, the children of a
+ * split the parent's carried area in proportion to their spherical areas
+ * then, a merged triangle its own again; A_T in the circulation test is the
+ * carried area, and the quadrature weights are A_i = sum of carried A_T / 3
+ * over the leaves having i as a vertex (valid after the first pass).  The
+ * live particles (the tree code's input) are kept in slot order: the
+ * initial particles first, in input order. */
 typedef struct stc_amr stc_amr;
 typedef struct stc_amr_params {
     double eps1, eps2;   /* thresholds of the circulation and variation tests  */

@@ -18,8 +18,12 @@
 //   mark     live particles = vertices of the new leaves
 //   birth    a particle live now but not before: midpoint of its edge's ends,
 //            mean absolute vorticity zeta + 2 Omega z of the ends
-//   areas    A_i = sum of A_T / 3 over the leaves having i as a vertex, in
-//            slot order of the triangles (fixed, repeatable)
+//   children the four children of a split take the parent's carried area in
+//            proportion to their spherical areas (triangles carry their
+//            areas: the flow is incompressible; an initial triangle takes
+//            its spherical area at the first pass)
+//   areas    A_i = sum of carried A_T / 3 over the leaves having i as a
+//            vertex, in slot order of the triangles (fixed, repeatable)
 //   compact  live particles in slot order into the arrays the tree code
 //            reads (x, zeta, A) and the slot of each
 //
@@ -68,6 +72,7 @@ struct AmrDev {
     const i32* adj_beg; // [npart + 1] CSR of triangle slots having the particle as a vertex
     const i32* adj;
     u8 *state, *state_new, *crit, *dec;
+    double* tarea;      // [ntri] carried area (negative: not yet set)
     u8 *alive, *alive_new;
     double *x, *z;      // slot state: positions (npart x 3), vorticity
     double* area_slot;
@@ -106,7 +111,11 @@ __global__ __launch_bounds__(256) void k_amr_crit(AmrDev a, double eps1, double 
     u8 c = 0;
     if (st == T_LEAF || (st == T_REFINED && d < a.D && children_all_leaves(a.state, s, local, d, a.TS))) {
         const i32 i = a.tv[3 * s], j = a.tv[3 * s + 1], k = a.tv[3 * s + 2];
-        const double area = tri_area_dev(a.x + 3 * (i64)i, a.x + 3 * (i64)j, a.x + 3 * (i64)k);
+        double area = a.tarea[s];
+        if (area < 0.0) {  // an initial triangle at the first pass
+            area = tri_area_dev(a.x + 3 * (i64)i, a.x + 3 * (i64)j, a.x + 3 * (i64)k);
+            a.tarea[s] = area;
+        }
         const double zi = a.z[i], zj = a.z[j], zk = a.z[k];
         const double circ = area * (((zi + zj) + zk) / 3.0);
         const double zmax = fmax(fmax(zi, zj), zk), zmin = fmin(fmin(zi, zj), zk);
@@ -188,8 +197,27 @@ __global__ __launch_bounds__(256) void k_amr_birth(AmrDev a, double omega) {
     a.z[v] = absv - two_om * m2;
 }
 
-// per particle: area from its leaves (after the births, so that every leaf's
-// vertices have positions), then the new live flags become current
+// carried areas of the children of every split (after the births: the
+// children's vertices have positions)
+__global__ __launch_bounds__(256) void k_amr_child_areas(AmrDev a) {
+    const i64 s = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.ntri || a.dec[s] != D_SPLIT) return;
+    const int local = (int)(s % a.TS);
+    const int d = depth_of(local);
+    const i64 c0 = s - local + depth_start(d + 1) + 4 * (local - depth_start(d));
+    double g[4];
+    for (int c = 0; c < 4; ++c) {
+        const i64 t = c0 + c;
+        const i32 i = a.tv[3 * t], j = a.tv[3 * t + 1], k = a.tv[3 * t + 2];
+        g[c] = tri_area_dev(a.x + 3 * (i64)i, a.x + 3 * (i64)j, a.x + 3 * (i64)k);
+    }
+    const double gs = ((g[0] + g[1]) + g[2]) + g[3];
+    const double A = a.tarea[s];
+    for (int c = 0; c < 4; ++c) a.tarea[c0 + c] = A * (g[c] / gs);
+}
+
+// per particle: its weight from the carried areas of its leaves, then the
+// new live flags become current
 __global__ __launch_bounds__(256) void k_amr_areas(AmrDev a) {
     const i64 v = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= a.npart) return;
@@ -198,8 +226,7 @@ __global__ __launch_bounds__(256) void k_amr_areas(AmrDev a) {
         for (i32 e = a.adj_beg[v]; e < a.adj_beg[v + 1]; ++e) {
             const i32 t = a.adj[e];
             if (a.state_new[t] != T_LEAF) continue;
-            const i32 i = a.tv[3 * (i64)t], j = a.tv[3 * (i64)t + 1], k = a.tv[3 * (i64)t + 2];
-            acc += tri_area_dev(a.x + 3 * (i64)i, a.x + 3 * (i64)j, a.x + 3 * (i64)k) / 3.0;
+            acc += a.tarea[t] / 3.0;
         }
     }
     a.area_slot[v] = acc;
@@ -379,6 +406,7 @@ struct stc_amr {
     i32 *tv = nullptr, *ends = nullptr, *adj_beg = nullptr, *adj = nullptr;
     u8 *state = nullptr, *state_new = nullptr, *crit = nullptr, *dec = nullptr, *alive = nullptr,
        *alive_new = nullptr;
+    double* tarea = nullptr;
     double *x = nullptr, *z = nullptr, *area_slot = nullptr, *cx = nullptr, *cz = nullptr, *ca = nullptr;
     i32* slot_of = nullptr;
     u32 *counters = nullptr, *block_sums = nullptr;
@@ -398,6 +426,7 @@ struct stc_amr {
         a.state_new = state_new;
         a.crit = crit;
         a.dec = dec;
+        a.tarea = tarea;
         a.alive = alive;
         a.alive_new = alive_new;
         a.x = x;
@@ -425,6 +454,7 @@ void carve_amr(stc_amr* m, Carve& cv) {
     cv.take(&m->state_new, nt);
     cv.take(&m->crit, nt);
     cv.take(&m->dec, nt);
+    cv.take(&m->tarea, nt);
     cv.take(&m->alive, np);
     cv.take(&m->alive_new, np);
     cv.take(&m->x, 3 * np);
@@ -464,6 +494,7 @@ void enqueue_pass(stc_amr* m) {
     hipLaunchKernelGGL(k_amr_clear_alive, dim3(blocks(a.npart)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_amr_mark, dim3(blocks(a.ntri)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_amr_birth, dim3(blocks(a.npart)), dim3(256), 0, s, a, m->p.omega);
+    hipLaunchKernelGGL(k_amr_child_areas, dim3(blocks(a.ntri)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_amr_areas, dim3(blocks(a.npart)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_amr_commit, dim3(blocks(std::max(a.ntri, a.npart))), dim3(256), 0, s, a);
 }
@@ -533,6 +564,7 @@ stc_status stc_amr_create(const stc_amr_params* p, int64_t n0, int64_t n_faces, 
     // initial state: every root a leaf, the other slots off, the initial particles live
     std::vector<u8> st0((size_t)t.ntri, T_OFF);
     for (i64 r = 0; r < m->nf; ++r) st0[(size_t)(r * t.TS)] = T_LEAF;
+    const std::vector<double> ta0((size_t)t.ntri, -1.0);
     std::vector<u8> al0((size_t)t.npart, 0);
     std::fill(al0.begin(), al0.begin() + m->n0, (u8)1);
     std::vector<i32> slot0((size_t)m->n0);
@@ -543,6 +575,7 @@ stc_status stc_amr_create(const stc_amr_params* p, int64_t n0, int64_t n_faces, 
     bool ok = up(m->tv, t.tv.data(), t.tv.size() * sizeof(i32)) && up(m->ends, t.ends.data(), t.ends.size() * sizeof(i32)) &&
               up(m->adj_beg, t.adj_beg.data(), t.adj_beg.size() * sizeof(i32)) &&
               up(m->adj, t.adj.data(), t.adj.size() * sizeof(i32)) && up(m->state, st0.data(), st0.size()) &&
+              up(m->tarea, ta0.data(), ta0.size() * sizeof(double)) &&
               up(m->alive, al0.data(), al0.size()) && up(m->slot_of, slot0.data(), slot0.size() * sizeof(i32));
     launch_fill_u32(s, m->counters, 8, 0u);
     if (!ok || hipStreamSynchronize(s) != hipSuccess) {

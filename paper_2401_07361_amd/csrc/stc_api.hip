@@ -1753,6 +1753,102 @@ stc_status stc_phase_times(stc_ctx* c, double ms[6], int64_t* n_evals) {
     return STC_OK;
 }
 
+// --- one evaluation captured in a HIP graph ------------------------------------
+
+struct stc_graph {
+    stc_ctx* ctx = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};  // around the last replay, on the launch stream
+    bool launched = false;
+};
+
+stc_status stc_velocity_graph(stc_ctx* c, int64_t n, const double* d_x, const double* d_zeta, const double* d_area,
+                              double* d_u, stc_graph** out) {
+    if (!c || !out) return STC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n < 1 || n > c->n_max) return fail(c, STC_ERR_INVALID_ARG, "n out of range [1, n_max]");
+    if (!d_x || !d_zeta || !d_area || !d_u || !aligned8(d_x) || !aligned8(d_zeta) || !aligned8(d_area) ||
+        !aligned8(d_u))
+        return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
+    stc_graph* g = new (std::nothrow) stc_graph();
+    if (!g) return STC_ERR_ALLOC;
+    g->ctx = c;
+    for (hipEvent_t& e : g->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            stc_graph_destroy(g);
+            return fail(c, STC_ERR_DEVICE, "hipEventCreate failed");
+        }
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        stc_graph_destroy(g);
+        return fail(c, STC_ERR_DEVICE, "creating the capture stream failed");
+    }
+    // capture on the context's capture stream, with the context's phase
+    // timing off (its events belong to eager evaluations)
+    const int tmax = c->t_max;
+    c->t_max = 0;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    hipGraph_t graph = nullptr;
+    stc_status st = STC_OK;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = fail(c, STC_ERR_DEVICE, "hipStreamBeginCapture failed");
+    } else {
+        const i64 off[2] = {0, n};
+        st = do_build(c, 1, off, d_x);
+        if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
+        if (st == STC_OK) st = do_traverse(c);
+        if (st == STC_OK) st = do_eval(c, true, true, d_u, false);
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        if (st == STC_OK && e != hipSuccess) st = fail(c, STC_ERR_DEVICE, "hipStreamEndCapture failed");
+    }
+    c->stream = user;
+    c->t_max = tmax;
+    if (st == STC_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        g->exec = nullptr;
+        st = fail(c, STC_ERR_DEVICE, "hipGraphInstantiate failed");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != STC_OK) {
+        stc_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return STC_OK;
+}
+
+stc_status stc_graph_launch(stc_graph* g) {
+    if (!g || !g->exec) return STC_ERR_INVALID_ARG;
+    hipStream_t s = g->ctx->stream;
+    if (hipEventRecord(g->ev[0], s) != hipSuccess || hipGraphLaunch(g->exec, s) != hipSuccess ||
+        hipEventRecord(g->ev[1], s) != hipSuccess)
+        return fail(g->ctx, STC_ERR_DEVICE, "hipGraphLaunch failed");
+    g->launched = true;
+    return STC_OK;
+}
+
+stc_status stc_graph_last_ms(stc_graph* g, double* ms) {
+    if (!g || !ms) return STC_ERR_INVALID_ARG;
+    *ms = 0.0;
+    if (!g->launched) return fail(g->ctx, STC_ERR_STATE, "the graph has not been launched");
+    if (hipEventSynchronize(g->ev[1]) != hipSuccess) return fail(g->ctx, STC_ERR_DEVICE, "synchronisation failed");
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g->ev[0], g->ev[1]) != hipSuccess)
+        return fail(g->ctx, STC_ERR_DEVICE, "event timing failed");
+    *ms = t;
+    return STC_OK;
+}
+
+stc_status stc_graph_destroy(stc_graph* g) {
+    if (!g) return STC_ERR_INVALID_ARG;
+    if (g->ctx) (void)hipStreamSynchronize(g->ctx->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    for (hipEvent_t e : g->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete g;
+    return STC_OK;
+}
+
 const char* stc_last_error(const stc_ctx* c) { return c ? c->err.c_str() : ""; }
 
 }  // extern "C"

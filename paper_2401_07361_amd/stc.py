@@ -131,6 +131,10 @@ def _load():
         "stc_amr_copy_slots": (I32, [P, I64, PI32, PI32]),
         "stc_amr_last_error": (ctypes.c_char_p, [P]),
         "stc_amr_rk4": (I32, [P, P, D, D, I32]),
+        "stc_velocity_graph": (I32, [P, I64, VP, VP, VP, VP, ctypes.POINTER(P)]),
+        "stc_graph_launch": (I32, [P]),
+        "stc_graph_last_ms": (I32, [P, PD]),
+        "stc_graph_destroy": (I32, [P]),
         "stc_sync": (I32, [P]),
         "stc_list_counts": (I32, [P, PI64, PI64]),
         "stc_copy_list": (I32, [P, I32, I64, PI64, PI64]),
@@ -679,6 +683,19 @@ class Context:
         _check(_lib.stc_get_forcing(self._ctx, ctypes.byref(f), ctypes.byref(on)), self._ctx)
         return bool(on.value), {name: getattr(f, name) for name, _ in Forcing._fields_}
 
+    # graph-captured evaluation ------------------------------------------------------
+    def velocity_graph(self, x, zeta, area, out):
+        """A VelocityGraph replaying velocity(x, zeta, area, out=out) (stc_velocity_graph)."""
+        import torch
+        n = x.shape[0]
+        g = ctypes.c_void_p()
+        _check(_lib.stc_velocity_graph(self._ctx, n, _dptr(x, "x", torch.float64, 3 * n),
+                                       _dptr(zeta, "zeta", torch.float64, n), _dptr(area, "area", torch.float64, n),
+                                       _dptr(out, "out", torch.float64, 3 * n), ctypes.byref(g)), self._ctx)
+        self._keep = x
+        self.n = n
+        return VelocityGraph(self, g, (x, zeta, area, out))
+
     # timing -------------------------------------------------------------------------
     PHASES = ("build", "upward", "traverse", "near", "far_targets", "l2p")
 
@@ -741,6 +758,34 @@ class Context:
         _check(_lib.stc_node_geometry(self._ctx, node_id, v.ctypes.data_as(PD), c.ctypes.data_as(PD),
                                       ctypes.byref(r)))
         return v.reshape(3, 3), c, r.value
+
+
+class VelocityGraph:
+    """One captured velocity evaluation (stc_velocity_graph); destroy it
+    before its context."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self._g, self._keep = ctx, handle, keep
+
+    def launch(self):
+        _check(_lib.stc_graph_launch(self._g), self.ctx._ctx)
+
+    def last_ms(self):
+        """Duration of the last replay in ms (synchronises)."""
+        ms = ctypes.c_double()
+        _check(_lib.stc_graph_last_ms(self._g, ctypes.byref(ms)), self.ctx._ctx)
+        return ms.value
+
+    def close(self):
+        if self._g:
+            _lib.stc_graph_destroy(self._g)
+            self._g = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class AdaptiveMesh:

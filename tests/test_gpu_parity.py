@@ -408,3 +408,30 @@ def test_rk4_matches_oracle(stc_lib):
     assert np.abs(xg - xr).max() < bar_x
     assert np.abs(zg - zr).max() < bar_z
     ctx.close()
+
+
+@pytest.mark.parametrize("precision,den", [("fp64", "dot"), ("fp32", "dist2")])
+def test_velocity_graph_replays_equal_eager(stc_lib, precision, den):
+    """stc_velocity_graph: every replay (with eager evaluations of the same
+    context and synchronisations between replays, and the vorticity changed
+    in place) is bitwise the eager evaluation of the same inputs; the
+    replay's duration is positive."""
+    x = S.random_sphere_points(7001, 21)
+    a = np.full(7001, 4 * np.pi / 7001)
+    kw = dict(theta=0.7, degree=6, n_crit=32, precision=precision, denominator=den)
+    ctx = stc_lib.Context(7001, **kw)
+    xd, ad = dev(x), dev(a)
+    zd = dev(S.rossby_haurwitz(x, 4))
+    ug = torch.empty((7001, 3), dtype=torch.float64, device="cuda")
+    g = ctx.velocity_graph(xd, zd, ad, ug)
+    for k in range(3):
+        say(f"graph replay {k} {precision}")
+        zd.copy_(dev(S.rossby_haurwitz(x, 3 + k) + 1e-3 * k))
+        g.launch()
+        torch.cuda.synchronize()
+        assert g.last_ms() > 0
+        ue = ctx.velocity(xd, zd, ad)          # eager work of the program between replays
+        ctx.sync()
+        assert torch.equal(ug, ue), k
+    g.close()
+    ctx.close()
