@@ -36,7 +36,9 @@ SOURCES = [
     ("geometry.cpp", ["-ffp-contract=off"], False),
     ("k_sort.hip", [], True),
     ("k_tree.hip", ["-ffp-contract=off"], True),
-    ("k_eval.hip", [], True),
+    # matrix-core operands and results in ordinary VGPRs (no copies through
+    # the accumulation registers in the target-proxy kernel's inner loop)
+    ("k_eval.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form"], True),
     ("k_mlp.hip", [], True),
     ("k_learned.hip", [], True),
     ("amr.hip", ["-ffp-contract=off"], True),
@@ -54,7 +56,7 @@ def _run(cmd):
 
 def build(verbose=False, jobs=None, out=None):
     """Compiles every source and links libstc.so (or `out`).  Environment
-    STC_FAR_MFMA=1 builds the matrix-core accumulation of the target-proxy
+    STC_FAR_MFMA=1 builds the matrix-core form of the FP32 target-proxy
     kernel instead of the VALU one (kept for measurement; slower)."""
     lib = out or OUT
     os.makedirs(BUILD, exist_ok=True)

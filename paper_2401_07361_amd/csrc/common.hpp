@@ -292,28 +292,29 @@ __device__ __forceinline__ int div_small(int a, int b, int& r) {
     return q;
 }
 
-// Block-wide product out[k][c] = sum_m Mt[m * np + k] * sc[m] * in[m][c] for
-// k < np, c < NC, with all NT threads: thread t handles row k = t % np and
-// the m-range of group t / np (NT / np groups); partial sums meet in red
-// (LDS, >= NT * NC doubles).  Mt is read row by row, consecutive threads
-// reading consecutive k (coalesced).  sc may be null (all ones).  Must be
-// called by every thread of the block; ends with a barrier.
+// Block-wide product out[k][c] = sum_m Mt[m * nout + k] * sc[m] * in[m][c]
+// for k < nout, m < nin, c < NC, with all NT threads: thread t handles row
+// k = t % nout and the m-range of group t / nout (NT / nout groups);
+// partial sums meet in red (LDS, >= NT * NC doubles).  Mt is read row by
+// row, consecutive threads reading consecutive k (coalesced).  sc may be
+// null (all ones).  Must be called by every thread of the block; ends with a
+// barrier.
 template <int NT, int NC>
-__device__ __forceinline__ void block_matvec(const double* __restrict__ Mt, int np, const double* sc,
+__device__ __forceinline__ void block_matvec(const double* __restrict__ Mt, int nin, int nout, const double* sc,
                                              const double (*in)[NC], double* red, double (*out)[NC]) {
     const int tid = threadIdx.x;
     int rem, k;
-    const int G = div_small(NT, np, rem);
-    const int g = div_small(tid, np, k);
+    const int G = div_small(NT, nout, rem);
+    const int g = div_small(tid, nout, k);
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (g < G) {
-        const int per = div_small(np + G - 1, G, rem);
-        const int m0 = g * per, m1 = (m0 + per) < np ? (m0 + per) : np;
+        const int per = div_small(nin + G - 1, G, rem);
+        const int m0 = g * per, m1 = (m0 + per) < nin ? (m0 + per) : nin;
 #pragma unroll 4
         for (int m = m0; m < m1; ++m) {
-            const double f = Mt[(size_t)m * np + k] * (sc ? sc[m] : 1.0);
+            const double f = Mt[(size_t)m * nout + k] * (sc ? sc[m] : 1.0);
 #pragma unroll
             for (int c = 0; c < NC; ++c) acc[c] += f * in[m][c];
         }
@@ -321,11 +322,11 @@ __device__ __forceinline__ void block_matvec(const double* __restrict__ Mt, int 
 #pragma unroll
     for (int c = 0; c < NC; ++c) red[c * NT + tid] = (g < G) ? acc[c] : 0.0;
     __syncthreads();
-    if (tid < np) {
+    if (tid < nout) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             double s = 0.0;
-            for (int gg = 0; gg < G; ++gg) s += red[c * NT + gg * np + tid];
+            for (int gg = 0; gg < G; ++gg) s += red[c * NT + gg * nout + tid];
             out[tid][c] = s;
         }
     }

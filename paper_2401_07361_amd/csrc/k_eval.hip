@@ -25,6 +25,8 @@
 // threads split as (target, source slice) with NTT / n_targets slices.
 // FP32 mode: coordinates relative to the target triangle's circumcentre,
 // rounded from FP64; partial sums per tile in FP32, added into FP64.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "stc.h"
@@ -228,149 +230,99 @@ __device__ __forceinline__ void tile_sum(const Src<T>* __restrict__ tile, int cn
     }
 }
 
-// Matrix-core form of tile_sum for the FP32 |x - y|^2 velocity kernel (see
-// UseMfma).  Every lane of the wave runs it with the same trip count (the
-// MFMA takes all 64 lanes): a lane outside the active slices (act false)
-// reads slice 0 and its blocks' results are never used; sources past cnt
-// and the excluded self pair enter with r = 0.  acc[k][i]: this lane's
-// column (lane & 3) of block row i for target k, added in FP64 per tile.
-template <bool SELF, int TP>
-__device__ __forceinline__ void tile_sum_mf(const Src<float>* __restrict__ tile, const float (*__restrict__ row)[4],
-                                            int cnt, int sl, int S, bool act, const float* tx, const float* ty,
-                                            const float* tz, const int* self_j, double (*acc)[4]) {
-    const int col = threadIdx.x & 3;
-    const int slr = act ? sl : 0;
-    mf32x4 d[TP];
-#pragma unroll
-    for (int k = 0; k < TP; ++k) d[k] = mf32x4{0.f, 0.f, 0.f, 0.f};
-    if (!SELF) {
-        int mr;
-        const int m = div_small(cnt, S, mr);
-        const Src<float>* __restrict__ blk = tile + slr * m;
-        const float (*__restrict__ rblk)[4] = row + slr * m;
-        // four sources per step, all their LDS reads issued before the
-        // arithmetic (one wait per four sources); the MFMAs of one source
-        // go to TP different accumulators
-        int it = 0;
-        for (; it + 4 <= m; it += 4) {
-            Src<float> src[4];
-            float b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                src[u] = blk[it + u];
-                b[u] = rblk[it + u][col];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int k = 0; k < TP; ++k) {
-                    const float dx = src[u].x - tx[k], dy = src[u].y - ty[k], dz = src[u].z - tz[k];
-                    const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
-                    d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(r, b[u], d[k], 0, 0, 0);
-                }
-        }
-        for (; it < m; ++it) {
-            const Src<float> src = blk[it];
-            const float b = rblk[it][col];
-#pragma unroll
-            for (int k = 0; k < TP; ++k) {
-                const float dx = src.x - tx[k], dy = src.y - ty[k], dz = src.z - tz[k];
-                const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
-                d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(r, b, d[k], 0, 0, 0);
-            }
-        }
-        // at most one of the cnt - S m remaining sources per slice
-        const int j = S * m + slr;
-        const bool ok = j < cnt;
-        const int jj = ok ? j : 0;
-        const Src<float> src = tile[jj];
-        const float b = row[jj][col];
-#pragma unroll
-        for (int k = 0; k < TP; ++k) {
-            const float dx = src.x - tx[k], dy = src.y - ty[k], dz = src.z - tz[k];
-            const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
-            d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(ok ? r : 0.f, b, d[k], 0, 0, 0);
-        }
-    } else {
-        int mr;
-        const int iters = div_small(cnt + S - 1, S, mr);
-        for (int it = 0; it < iters; ++it) {
-            const int j = slr + it * S;
-            const bool ok = j < cnt;
-            const int jj = ok ? j : 0;
-            const Src<float> src = tile[jj];
-            const float b = row[jj][col];
-#pragma unroll
-            for (int k = 0; k < TP; ++k) {
-                const float dx = src.x - tx[k], dy = src.y - ty[k], dz = src.z - tz[k];
-                const float r = __builtin_amdgcn_rcpf(dx * dx + dy * dy + dz * dz);
-                d[k] = __builtin_amdgcn_mfma_f32_4x4x1f32((ok && j != self_j[k]) ? r : 0.f, b, d[k], 0, 0, 0);
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < TP; ++k)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[k][i] += (double)d[k][i];
-}
-
 __device__ __forceinline__ u32 logical_block() {
     const u32 G = gridDim.x, b = blockIdx.x;
     return (b % 8u) * (G / 8u) + (b / 8u);
 }
 
-// The FP32 velocity kernel of the target proxies (k_far_targets, |x - y|^2
-// denominator) accumulates on the matrix cores: per source j and target x_i
-// the VALU forms only r = 1 / |y_j - x_i|^2 (7 instructions), and
-// v_mfma_f32_4x4x1f32 adds r times the row B_j = q_j (y_j, 1) into a 4 x 4
-// block, so that W_i = sum_j r q_j y_j - x_i sum_j r q_j is recovered from
-// the block's four columns after the sums (an FMA saved per component and
-// the multiply by q per evaluation).  The split of y - x costs accuracy where
-// |y_j| (target-relative) is much larger than |y_j - x_i|: FP32 rounding of
-// the two sums grows by about |y_j| / |y_j - x_i|.  For CP and CC pairs the
-// acceptance criterion bounds that ratio by (1 + theta) / (1 - theta); for
-// near-field pairs (k_near) it is unbounded (nearly coincident particles),
-// so k_near keeps the VALU form.
-// Lane l = 4 b + i of a wave supplies A[b][i] (its own target) and
-// B[b][i] (column i of its block's source row); D[b][i][c] comes back in
-// lane 4 b + c, register i.  The 16 blocks of a wave are independent, so
-// every block must read one source stream: groups of four consecutive
-// threads share a source slice (slice widths are multiples of 4).
-// Measured on gv_l8 (N = 655362, theta 0.8, d 10): the matrix-core form of
-// k_far_targets takes 0.48-0.51 ms against 0.39 ms for the VALU form, so
-// the library is built with the VALU form; building with -DSTC_FAR_MFMA=1
-// (environment STC_FAR_MFMA=1 for the build script) selects this one.
+// Matrix-core form of the FP32 velocity kernel of the target proxies
+// (k_far_targets, |x - y|^2 denominator).  For a group of 16 target points x
+// and a chunk of 16 sources y (both relative to the target node's centre)
+// the denominators form a rank-4 product plus a rank-1 term,
+//   |x - y|^2 = |x|^2 + (y, |y|^2) . (-2 x, 1),
+// one v_mfma_f32_16x16x4f32 with the sources as A (16 x 4), the targets as
+// B (4 x 16) and |x|^2 as C; the VALU takes the reciprocals of the 256
+// results; four v_mfma_f32_4x4x1f32 then add r times the rows q (y, 1) into
+// 4 x 4 blocks (block b: targets 4 (b % 4) .. + 3, sources 4 (b / 4) + i of
+// the chunk in step i), so that
+//   W(x) = sum_j r q_j y_j - x sum_j r q_j
+// is recovered from the blocks' four columns.  The VALU issues one reciprocal
+// per pair instead of eleven instructions.  Both rewrites cost accuracy where
+// |y| (target-relative) is much larger than |y - x|: FP32 rounding grows by
+// about (|x| + |y|)^2 / |x - y|^2 in the denominator and |y| / |y - x| in the
+// sum; for CP and CC pairs the acceptance criterion bounds both ratios
+// ((1 + theta) / (1 - theta) for the second, its square for the first); for
+// near-field pairs they are unbounded, so k_near keeps the VALU form.
+// Operand layouts (measured): 16x16x4 A[i][k] in lane 16 k + i, B[k][j] in
+// lane 16 k + j, D[i][j] in lane 16 (i / 4) + j register i % 4; 4x4x1 block b
+// row i from lane 4 b + i (A), column j from lane 4 b + j (B), D[b][i][j] in
+// lane 4 b + j register i.  Up to 80 target points per pass (5 groups,
+// degree <= 11).
+// Measured issue costs on gfx950 (cycles per wave instruction per SIMD):
+// FP32 FMA 4, v_rcp_f32 8, 16x16x4 MFMA 32, 4x4x1 MFMA 8.  Per 256 pairs
+// this form needs 64 matrix-core and 32 VALU cycles against 192 VALU cycles,
+// but within one wave each chunk is a dependent chain (MFMA -> reciprocal ->
+// MFMA) and the kernel reaches about a third of that bound: on gv_l8
+// (theta 0.8, d 10) 0.400 ms against 0.375 ms for the VALU form (both with
+// k_far_finish), E 5.01e-7 against 4.95e-7.  The library is built with the
+// VALU form; -DSTC_FAR_MFMA=1 (environment STC_FAR_MFMA=1 for the build
+// script) selects this one.
 #ifndef STC_FAR_MFMA
 #define STC_FAR_MFMA 0
 #endif
-template <typename T, int DEN, bool FAR>
-struct UseMfma {
-    static constexpr bool value = STC_FAR_MFMA && FAR && sizeof(T) == 4 && DEN == STC_DEN_DIST2;
-};
+constexpr int kMfTargets = 80;
+constexpr int kMfGroups = kMfTargets / 16;
 
 // LDS of a segment kernel with NTT threads: one tile of 2 NTT sources (two
-// consecutive ones staged per thread; with the matrix-core path also their
-// rows q (y, 1)), one batch of NTT list entries, and the per-slice partial
-// sums, which share the tiles' space (they are written after the last tile
-// is used).  NC partial components: 3, or 4 with the matrix-core path;
-// MAXT: targets per pass.
-template <typename T, int NTT, int TP, bool MF, int MAXT = TP * NTT>
+// consecutive ones staged per thread), one batch of NTT list entries, and
+// the per-slice partial sums, which share the tiles' space (they are
+// written after the last tile is used).  The matrix-core form (MF) stages
+// each source as y = (x, y, z, |y|^2) and its row q (y, 1), the rows of four
+// consecutive sources interleaved by component ([(l / 4) 4 + c][l % 4]) so
+// that a lane reads its four B operands with one 16-byte load; its partial
+// sums are per wave, and the pass's target points (x, |x|^2) sit in tgt.
+// (The matrix-core members are empty placeholders in the VALU form, so that
+// its layout, and with it the kernels' register allocation, is unchanged.)
+template <int NTT, bool MF>
+struct MfShared {
+    struct Tiles {
+        mf32x4 y[2 * NTT];    // (x, y, z, 1)
+        mf32x4 row[2 * NTT];  // q (x, y, z, 1), four sources interleaved by component
+        float b[2 * NTT];     // |y|^2
+    };
+    struct Sums {
+        double v[NTT / 64][kMfTargets][4];  // per-wave sums (columns q y, q) of the pass's targets
+    };
+    struct Targets {
+        mf32x4 v[kMfTargets];  // the pass's target points (x, |x|^2)
+    };
+};
+template <int NTT>
+struct MfShared<NTT, false> {
+    struct Tiles {
+        float unused;
+    };
+    using Sums = Tiles;
+    using Targets = Tiles;
+};
+
+template <typename T, int NTT, int TP, bool MF>
 struct SegShared {
-    static constexpr int NC = MF ? 4 : 3;
     struct Tiles {
         Src<T> tile[2 * NTT];
-        float row[MF ? 2 * NTT : 1][4];
     };
     union {
         Tiles t;
-        double red[TP][NC][NTT];  // per-slice partial sums of each thread's TP targets
+        typename MfShared<NTT, MF>::Tiles m;
+        double red[TP][3][NTT];  // per-slice partial sums of each thread's TP targets
+        typename MfShared<NTT, MF>::Sums wred;
     } u;
     u32 ent_s[NTT];        // source node of a particle entry, storage slot of a proxy entry
     i32 ent_first[NTT];    // first particle of a particle source, -1 for proxy points
     u32 ent_pre[NTT + 1];  // exclusive prefix of the entries' source counts
     u32 wave_tot[NTT / 64];
     int self_flag;
-    float tgt[MF ? MAXT : 1][3];  // matrix-core path: the pass's target coordinates
+    typename MfShared<NTT, MF>::Targets tgt;
 };
 
 // exclusive prefix over the NTT threads; returns the prefix, *total the sum
@@ -417,20 +369,32 @@ __device__ __forceinline__ Src<T> load_source(const EvalArgs& a, u32 s, i32 firs
     return v;
 }
 
-// Writes source v to tile slot l (and, with the matrix-core path, its row
-// q (y, 1)).
-template <typename T, int NTT, int TP, bool MF, int MAXT>
-__device__ __forceinline__ void stage(SegShared<T, NTT, TP, MF, MAXT>& sh, int l, const Src<T>& v) {
+// Writes source v to tile slot l.
+template <typename T, int NTT, int TP>
+__device__ __forceinline__ void stage(SegShared<T, NTT, TP, false>& sh, int l, const Src<T>& v) {
     sh.u.t.tile[l] = v;
-    if constexpr (MF) {
-        sh.u.t.row[l][0] = v.q * v.x;
-        sh.u.t.row[l][1] = v.q * v.y;
-        sh.u.t.row[l][2] = v.q * v.z;
-        sh.u.t.row[l][3] = v.q;
-    }
 }
 
-// tile_sum on a thread's accumulators acc[k][0..2] (FP64)
+// Matrix-core form: source v (or, with dummy, a source of charge zero at the
+// origin with |y|^2 = 1, which pads a chunk to 16) to slot l.
+template <int NTT, int TP>
+__device__ __forceinline__ void stage_mf(SegShared<float, NTT, TP, true>& sh, int l, const Src<float>& v, bool dummy) {
+    float* row = reinterpret_cast<float*>(sh.u.m.row) + (((l >> 2) * 4) << 2) + (l & 3);
+    if (dummy) {
+        sh.u.m.y[l] = mf32x4{0.f, 0.f, 0.f, 1.f};
+        sh.u.m.b[l] = 1.f;
+        row[0] = row[4] = row[8] = row[12] = 0.f;
+        return;
+    }
+    const double b = ((double)v.x * v.x + (double)v.y * v.y) + (double)v.z * v.z;
+    sh.u.m.y[l] = mf32x4{v.x, v.y, v.z, 1.f};
+    sh.u.m.b[l] = (float)b;
+    row[0] = v.q * v.x;
+    row[4] = v.q * v.y;
+    row[8] = v.q * v.z;
+    row[12] = v.q;
+}
+
 template <typename T, int DEN, bool SELF, int TP>
 __device__ __forceinline__ void tile_sum_acc(const Src<T>* __restrict__ tile, int cnt, int sl, int S, const T* tx,
                                              const T* ty, const T* tz, const int* self_j, double (*acc)[4]) {
@@ -449,12 +413,11 @@ __device__ __forceinline__ void tile_sum_acc(const Src<T>* __restrict__ tile, in
 // binary search) and all global loads of a tile are in flight together.  A
 // PP entry whose source is the target leaf itself (self_t) is evaluated on
 // its own with the j != i exclusion (me: the targets' indices there).
-// acc[k]: the target's sums (x, y, z), or with the matrix-core path the
-// lane's block column (see tile_sum_mf).
-template <typename T, int DEN, int NTT, int TP, bool MF, int MAXT>
+// acc[k]: the target's sums (x, y, z).
+template <typename T, int DEN, int NTT, int TP>
 __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ list, u32 e0, u32 e1, u32 type_mask,
                                    u32 self_t, const int* me, bool act, int sl, int S, const T* tx, const T* ty,
-                                   const T* tz, double cx, double cy, double cz, SegShared<T, NTT, TP, MF, MAXT>& sh,
+                                   const T* tz, double cx, double cy, double cz, SegShared<T, NTT, TP, false>& sh,
                                    double (*acc)[4]) {
     const int tid = threadIdx.x;
     const u64 mask = ((u64)1 << a.W) - 1;
@@ -501,8 +464,7 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                 int sj[TP];
 #pragma unroll
                 for (int k = 0; k < TP; ++k) sj[k] = me[k] - j0;
-                if constexpr (MF) tile_sum_mf<true, TP>(sh.u.t.tile, sh.u.t.row, cnt, sl, S, act, tx, ty, tz, sj, acc);
-                else if (act) tile_sum_acc<T, DEN, true, TP>(sh.u.t.tile, cnt, sl, S, tx, ty, tz, sj, acc);
+                if (act) tile_sum_acc<T, DEN, true, TP>(sh.u.t.tile, cnt, sl, S, tx, ty, tz, sj, acc);
                 __syncthreads();
             }
         }
@@ -528,25 +490,121 @@ __device__ void accumulate_entries(const EvalArgs& a, const u64* __restrict__ li
                 }
             }
             __syncthreads();
-            if constexpr (MF) tile_sum_mf<false, TP>(sh.u.t.tile, sh.u.t.row, cnt, sl, S, act, tx, ty, tz, nullptr, acc);
-            else if (act) tile_sum_acc<T, DEN, false, TP>(sh.u.t.tile, cnt, sl, S, tx, ty, tz, nullptr, acc);
+            if (act) tile_sum_acc<T, DEN, false, TP>(sh.u.t.tile, cnt, sl, S, tx, ty, tz, nullptr, acc);
+            __syncthreads();
+        }
+    }
+}
+
+// Matrix-core form of one tile: wave w takes the 16-source chunks w, w + NW,
+// ... of the cntp (a multiple of 16) staged sources; for each of the NG
+// target groups, one 16x16x4 product (A: the sources (y, 1), B: the group's
+// (-2 x, |x|^2), C: the sources' |y|^2) gives the 256 denominators, the VALU
+// their reciprocals, and four 4x4x1 products add r q (y, 1) into the
+// group's blocks (acc[g]); the groups' products are independent, so their
+// latencies overlap.  bop[g]: this lane's B operand of group g.
+template <int NG, int NTT, int TP>
+__device__ __forceinline__ void tile_sum_mfma(const SegShared<float, NTT, TP, true>& sh, int cntp, const float* bop,
+                                              mf32x4* acc) {
+    constexpr int NW = NTT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const float* __restrict__ yf = reinterpret_cast<const float*>(sh.u.m.y);
+    const mf32x4* __restrict__ bq = reinterpret_cast<const mf32x4*>(sh.u.m.b);
+    for (int ch = w; ch * 16 < cntp; ch += NW) {
+        const float ya = yf[(ch * 16 + (lane & 15)) * 4 + (lane >> 4)];
+        const mf32x4 b = sh.u.m.row[(ch * 4 + (lane >> 4)) * 4 + (lane & 3)];
+        const mf32x4 c = bq[ch * 4 + (lane >> 4)];  // |y|^2 of rows 4 (lane / 16) + i
+        mf32x4 den[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) den[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya, bop[g], c, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                acc[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(__builtin_amdgcn_rcpf(den[g][i]), b[i], acc[g], 0, 0, 0);
+    }
+}
+
+// accumulate_entries for the matrix-core form (target proxies; no self
+// pair): the same entry batches and tiles, sources staged as y, |y|^2 and
+// rows, each tile padded to a multiple of 16 by sources of charge zero.  The
+// block sums stay in FP32 over the pass (acc, per lane: about a quarter of
+// the pass's sources per accumulator).
+template <int NG, int NTT, int TP>
+__device__ void accumulate_entries_mf(const EvalArgs& a, const u64* __restrict__ list, u32 e0, u32 e1, double cx,
+                                      double cy, double cz, SegShared<float, NTT, TP, true>& sh, const float* bop,
+                                      mf32x4* acc) {
+    const int tid = threadIdx.x;
+    const u64 mask = ((u64)1 << a.W) - 1;
+    const u32 cmask = (1u << a.DB) - 1u;
+    const double qscale = charge_scale<float, STC_DEN_DIST2>();
+    for (u32 eb = e0; eb < e1; eb += NTT) {
+        const u32 ne = (e1 - eb) < (u32)NTT ? (e1 - eb) : (u32)NTT;
+        u32 size = 0;
+        if ((u32)tid < ne) {
+            const u64 key = list[eb + tid];
+            const int type = (int)((key >> a.W) & 1u);
+            const u32 s = (u32)(key & mask);
+            if (type == 0) {
+                const i32 b = a.nbeg[s];
+                sh.ent_s[tid] = s;
+                sh.ent_first[tid] = b;
+                size = (u32)(a.nend[s] - b);
+            } else {
+                const int c = (int)((key >> (a.W + 1)) & cmask);
+                sh.ent_s[tid] = (u32)a.slot[s] * (u32)a.NPT + (u32)STC_PICK4(a.cls.poff, c);
+                sh.ent_first[tid] = -1;
+                size = (u32)STC_PICK4(a.cls.np, c);
+            }
+        }
+        u32 total = 0;
+        const u32 pre = block_exclusive_scan<NTT>(size, sh.wave_tot, &total);
+        if ((u32)tid < ne) sh.ent_pre[tid] = pre;
+        if (tid == 0) sh.ent_pre[ne] = total;
+        __syncthreads();
+        for (u32 g0 = 0; g0 < total; g0 += 2 * NTT) {
+            const int cnt = (total - g0) < (u32)(2 * NTT) ? (int)(total - g0) : 2 * NTT;
+            const int cntp = (cnt + 15) & ~15;
+            const int l0 = 2 * tid;
+            if (l0 < cnt) {
+                // the entry holding source g: binary search over the prefix;
+                // source g + 1 lies in the same entry or a later one
+                const u32 g = g0 + l0;
+                u32 lo = 0, hi = ne;
+                while (hi - lo > 1) {
+                    const u32 mid = (lo + hi) >> 1;
+                    if (sh.ent_pre[mid] <= g) lo = mid;
+                    else hi = mid;
+                }
+                stage_mf(sh, l0, load_source<float>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g - sh.ent_pre[lo]), cx,
+                                                    cy, cz, qscale), false);
+                if (l0 + 1 < cnt) {
+                    while (sh.ent_pre[lo + 1] <= g + 1) ++lo;  // ent_pre[ne] = total > g + 1
+                    stage_mf(sh, l0 + 1, load_source<float>(a, sh.ent_s[lo], sh.ent_first[lo],
+                                                            (int)(g + 1 - sh.ent_pre[lo]), cx, cy, cz, qscale), false);
+                } else if (l0 + 1 < cntp) {
+                    stage_mf(sh, l0 + 1, Src<float>{}, true);
+                }
+            } else if (l0 < cntp) {
+                stage_mf(sh, l0, Src<float>{}, true);
+                if (l0 + 1 < cntp) stage_mf(sh, l0 + 1, Src<float>{}, true);
+            }
+            __syncthreads();
+            tile_sum_mfma<NG>(sh, cntp, bop, acc);
             __syncthreads();
         }
     }
 }
 
 // A pass over up to TP x NTT targets: thread (ti, sl) takes targets ti,
-// ti + h, ... (h = ceil(ntc / TP), rounded up to a multiple of 4 with the
-// matrix-core path so that its 4-lane blocks never straddle two slices) and
-// source slice sl of S = NTT / h.  Targets past ntc duplicate a valid one
-// and are not written back.
-template <int TP, bool MF = false>
+// ti + h, ... (h = ceil(ntc / TP)) and source slice sl of S = NTT / h.
+// Targets past ntc duplicate a valid one and are not written back.
+template <int TP>
 struct TargetGroup {
     int h, S, ti, sl, me[TP];
     bool act, valid[TP];
     __device__ TargetGroup(int ntc, int nthreads, int base) {
         h = (ntc + TP - 1) / TP;
-        if (MF) h = (h + 3) & ~3;
         int r;
         S = div_small(nthreads, h, r);
         sl = div_small((int)threadIdx.x, h, ti);
@@ -554,8 +612,7 @@ struct TargetGroup {
 #pragma unroll
         for (int k = 0; k < TP; ++k) {
             valid[k] = ti + k * h < ntc;
-            // a padding thread (ti >= ntc, only with rounded widths) takes the first target
-            me[k] = base + (valid[k] ? ti + k * h : (ti < ntc ? ti : 0));
+            me[k] = base + (valid[k] ? ti + k * h : ti);
         }
     }
 };
@@ -581,29 +638,6 @@ __device__ __forceinline__ void slice_sums(const double (*red)[3][NTT], int h, i
     }
 }
 
-// slice_sums of the matrix-core path: per (target, component) the sums
-// over the slices of the block columns c (sum_j r q y_c) and 3 (sum_j r q),
-// combined as W_c = sum_c - x_c sum_3 with the target's FP32 coordinate.
-template <int NTT, int TP, typename F>
-__device__ __forceinline__ void slice_sums_mf(const double (*red)[4][NTT], const float (*tgt)[3], int h, int S,
-                                              int ntc, F&& f) {
-    for (int o = threadIdx.x; o < 3 * TP * h; o += NTT) {
-        int k = 0;
-#pragma unroll
-        for (int j = 1; j < TP; ++j) k += o >= j * 3 * h;
-        const int rem = o - k * 3 * h;
-        const int c = (rem >= h) + (rem >= 2 * h), ti = rem - c * h;
-        if (ti + k * h < ntc) {
-            double sc = 0.0, s3 = 0.0;
-            for (int q = 0; q < S; ++q) {
-                sc += red[k][c][q * h + ti];
-                s3 += red[k][3][q * h + ti];
-            }
-            f(ti + k * h, c, sc - (double)tgt[ti + k * h][c] * s3);
-        }
-    }
-}
-
 // range of list entries of this workgroup (segments: key >> sh); returns
 // false if empty
 __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int sh, u32& e, u32& e_hi) {
@@ -620,30 +654,21 @@ __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_
 constexpr int NEAR_TP = 1;  // targets per thread: leaves are small, occupancy matters more
 constexpr int FAR_TP = 3;   // the proxy points of a node: each staged source feeds three targets (66 = 22 x 3: 242 of 256 threads busy, against 231 at two)
 
-// The per-slice partial sums of a pass into LDS: three components per
-// thread, or with the matrix-core path this lane's block column for the four
-// targets of its block (lane 4 b + c holds column c of rows 4 b .. 4 b + 3).
-template <typename T, int NTT, int TP, bool MF, int MAXT>
-__device__ __forceinline__ void store_partials(SegShared<T, NTT, TP, MF, MAXT>& sh, bool act,
-                                               const double (*acc)[4]) {
+// The per-slice partial sums of a pass into LDS, three components per
+// thread.
+template <typename T, int NTT, int TP>
+__device__ __forceinline__ void store_partials(SegShared<T, NTT, TP, false>& sh, bool act, const double (*acc)[4]) {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < TP; ++k) {
-        if constexpr (MF) {
+    for (int k = 0; k < TP; ++k)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sh.u.red[k][tid & 3][(tid & ~3) + i] = acc[k][i];
-        } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sh.u.red[k][c][tid] = act ? acc[k][c] : 0.0;
-        }
-    }
+        for (int c = 0; c < 3; ++c) sh.u.red[k][c][tid] = act ? acc[k][c] : 0.0;
 }
 
 template <typename T, int DEN, int NT>
 __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
     constexpr int TP = NEAR_TP;
-    constexpr bool MF = UseMfma<T, DEN, false>::value;
-    __shared__ SegShared<T, NT, TP, MF> sh;
+    __shared__ SegShared<T, NT, TP, false> sh;
     u32 n = a.counters[C_TLIST];
     if (n > a.cap) n = a.cap;
     u32 e, e_hi;
@@ -659,7 +684,7 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
         for (int cb = 0; cb < nt; cb += TP * NT) {
             const int ntc = (nt - cb) < TP * NT ? (nt - cb) : TP * NT;
-            const TargetGroup<TP, MF> tg(ntc, NT, cb);
+            const TargetGroup<TP> tg(ntc, NT, cb);
             T tx[TP], ty[TP], tz[TP];
             int me[TP];
 #pragma unroll
@@ -669,13 +694,6 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
                 ty[k] = target_reg<T>(a.sy[gi] - cy);
                 tz[k] = target_reg<T>(a.sz[gi] - cz);
                 me[k] = tg.valid[k] ? tg.me[k] : -1;  // a duplicate target's exclusion never matches
-                if constexpr (MF) {
-                    if (tg.act && tg.sl == 0 && tg.valid[k]) {
-                        sh.tgt[tg.ti + k * tg.h][0] = tx[k];
-                        sh.tgt[tg.ti + k * tg.h][1] = ty[k];
-                        sh.tgt[tg.ti + k * tg.h][2] = tz[k];
-                    }
-                }
             }
             double acc[TP][4];
 #pragma unroll
@@ -685,82 +703,330 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
             store_partials(sh, tg.act, acc);
             __syncthreads();
             auto add = [&](int j, int c, double v) { a.Wacc[3 * (size_t)(tb + cb + j) + c] += v; };
-            if constexpr (MF) slice_sums_mf<NT, TP>(sh.u.red, sh.tgt, tg.h, tg.S, ntc, add);
-            else slice_sums<NT, TP>(sh.u.red, tg.h, tg.S, ntc, add);
+            slice_sums<NT, TP>(sh.u.red, tg.h, tg.S, ntc, add);
             __syncthreads();
         }
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
     }
 }
 
-template <typename T, int DEN, int NTT>
-__global__ __launch_bounds__(NTT) void k_far_targets(EvalArgs a) {
+// One class pass of the matrix-core form over NG groups of 16 target
+// points (sh.tgt): the per-lane block sums of entries [ec, ce), then (in
+// FP64) the four source subgroups of a block row meet in lanes 0..15 (lane
+// 4 b + j, register i: target 16 g + 4 b + i, column j) and go to the wave's
+// row of sh.u.wred.  Ends with a barrier.
+template <int NG, int NTT, int TP>
+__device__ __forceinline__ void far_pass_mf(const EvalArgs& a, u32 ec, u32 ce, double cx, double cy, double cz,
+                                            SegShared<float, NTT, TP, true>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4;
+    float bop[NG];
+    mf32x4 acc[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const mf32x4 tv = sh.tgt.v[16 * g + (lane & 15)];
+        bop[g] = kq < 3 ? -2.f * tv[kq] : tv[3];
+        acc[g] = mf32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    accumulate_entries_mf<NG>(a, a.nlist, ec, ce, cx, cy, cz, sh, bop, acc);
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double v = (double)acc[g][i];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (lane < 16) sh.u.wred.v[w][16 * g + 4 * (lane >> 2) + i][lane & 3] = v;
+        }
+    __syncthreads();
+}
+
+// Target-side far field (CP and CC), one list segment per target node t:
+// the node's interpolation points x~_m (its proxy points, as the upward pass
+// stored them) of each degree class present receive
+//   W(x~_m) = sum over the class's entries of q (y - x~_m) / den,
+// written to the node's coefficient record in place of the coefficients,
+// which k_far_finish forms from them.  With the learned form the classes
+// present go to cls_mask[slot].
+// MF: the matrix-core form (FP32 velocity, at most kMfTargets points per
+// class); LEARNED: the degree classes of the learned form.
+// (The matrix-core form of the plain method fits 128 VGPRs, four waves per
+// SIMD; unconstrained it takes a few more and only three.)
+template <typename T, int DEN, int NTT, bool MF, bool LEARNED>
+__global__ __launch_bounds__(NTT) __attribute__((amdgpu_waves_per_eu((MF && !LEARNED) ? 4 : 1))) void k_far_targets(
+    EvalArgs a) {
     constexpr int TP = FAR_TP;
-    constexpr bool MF = UseMfma<T, DEN, true>::value;
-    __shared__ SegShared<T, NTT, TP, MF, TP * NTT / 4> sh;
+    __shared__ SegShared<T, NTT, TP, MF> sh;
     __shared__ double wt[kMaxNp][3];
-    __shared__ double co[kMaxNp][3];
-    __shared__ double nd[kMaxNp];
     const int tid = threadIdx.x;
     u32 n = a.counters[C_NLIST];
     if (n > a.cap) n = a.cap;
     u32 e, e_hi;
-    const int shf = a.W + 1;  // segments by (target, degree class)
+    const int shf = a.W + 1 + a.DB;  // segments by target node (all classes)
     if (!wg_range(n, a.nlist, a.nseg_end, shf, e, e_hi)) return;
     const bool rel = sizeof(T) == 4;
     while (e < e_hi) {
-        const u32 vt = (u32)(a.nlist[e] >> shf);
-        const u32 t = vt >> a.DB;
-        const int c = (int)(vt & ((1u << a.DB) - 1u));
-        const int np = STC_PICK4(a.cls.np, c), d = STC_PICK4(a.cls.deg, c);
-        const int poff = STC_PICK4(a.cls.poff, c), qoff = STC_PICK4(a.cls.qoff, c);
-        const u32 se = (u32)a.nseg_end[vt];
+        const u32 t = (u32)(a.nlist[e] >> shf);
+        const u32 se = (u32)a.nseg_end[t];
         const NodeGeo& gt = a.geo[t & a.node_mask];
         const double cx = rel ? gt.c[0] : 0.0, cy = rel ? gt.c[1] : 0.0, cz = rel ? gt.c[2] : 0.0;
-        // target points in passes of up to TP NTT / 4 (degree 10 with 256
-        // threads: all 66 points in one pass, 33 target pairs x 7 slices)
-        for (int cb = 0; cb < np; cb += TP * NTT / 4) {
-            const int ntc = (np - cb) < TP * NTT / 4 ? (np - cb) : TP * NTT / 4;
-            const TargetGroup<TP, MF> tg(ntc, NTT, cb);
-            T tx[TP], ty[TP], tz[TP];
-            int nome[TP];
-#pragma unroll
-            for (int k = 0; k < TP; ++k) {
-                double y[3];
-                const double nrm = proxy_point(gt, a.ref.points + 3 * (poff + tg.me[k]), y);
-                if (tg.act && tg.sl == 0 && tg.valid[k]) nd[tg.me[k]] = ipow(nrm, d);
-                tx[k] = target_reg<T>(y[0] - cx);
-                ty[k] = target_reg<T>(y[1] - cy);
-                tz[k] = target_reg<T>(y[2] - cz);
-                nome[k] = -1;
-                if constexpr (MF) {
-                    if (tg.act && tg.sl == 0 && tg.valid[k]) {
-                        sh.tgt[tg.ti + k * tg.h][0] = tx[k];
-                        sh.tgt[tg.ti + k * tg.h][1] = ty[k];
-                        sh.tgt[tg.ti + k * tg.h][2] = tz[k];
+        const size_t rec = (size_t)a.slot[t] * a.NPT;
+        // W(x~_m) of class c's points from entries [ec, ce), written to the
+        // class's record
+        auto class_values = [&](int c, u32 ec, u32 ce) {
+            const int np = STC_PICK4(a.cls.np, c), poff = STC_PICK4(a.cls.poff, c);
+            const Prox* __restrict__ tp = a.prox + rec + poff;
+            if constexpr (MF) {
+                // all points in one pass, groups of 16 (padding points at the
+                // origin with |x|^2 = 1 keep every denominator positive)
+                const int ng = (np + 15) >> 4;
+                for (int m = tid; m < 16 * ng; m += NTT) {
+                    if (m < np) {
+                        const Prox pm = tp[m];
+                        const float x0 = (float)(pm.x - cx), x1 = (float)(pm.y - cy), x2 = (float)(pm.z - cz);
+                        const double a2 = ((double)x0 * x0 + (double)x1 * x1) + (double)x2 * x2;
+                        sh.tgt.v[m] = mf32x4{x0, x1, x2, (float)a2};
+                    } else {
+                        sh.tgt.v[m] = mf32x4{0.f, 0.f, 0.f, 1.f};
                     }
                 }
-            }
-            double acc[TP][4];
+                __syncthreads();
+                switch (ng) {
+                    case 1: far_pass_mf<1>(a, ec, ce, cx, cy, cz, sh); break;
+                    case 2: far_pass_mf<2>(a, ec, ce, cx, cy, cz, sh); break;
+                    case 3: far_pass_mf<3>(a, ec, ce, cx, cy, cz, sh); break;
+                    case 4: far_pass_mf<4>(a, ec, ce, cx, cy, cz, sh); break;
+                    default: far_pass_mf<5>(a, ec, ce, cx, cy, cz, sh); break;
+                }
+                for (int o = tid; o < 3 * np; o += NTT) {
+                    const int m = o / 3, cc = o - 3 * m;
+                    double sc = 0.0, s3 = 0.0;
+                    for (int ww = 0; ww < NTT / 64; ++ww) {
+                        sc += sh.u.wred.v[ww][m][cc];
+                        s3 += sh.u.wred.v[ww][m][3];
+                    }
+                    a.alpha[(rec + poff) * 3 + o] = sc - (double)sh.tgt.v[m][cc] * s3;
+                }
+                __syncthreads();
+            } else {
+                // target points in passes of up to TP NTT / 4 (degree 10 with
+                // 256 threads: all 66 points in one pass, 33 target pairs x 7
+                // slices)
+                for (int cb = 0; cb < np; cb += TP * NTT / 4) {
+                    const int ntc = (np - cb) < TP * NTT / 4 ? (np - cb) : TP * NTT / 4;
+                    const TargetGroup<TP> tg(ntc, NTT, cb);
+                    T tx[TP], ty[TP], tz[TP];
+                    int nome[TP];
 #pragma unroll
-            for (int k = 0; k < TP; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0;
-            accumulate_entries<T, DEN>(a, a.nlist, e, se, 3u, 0xffffffffu, nome, tg.act, tg.sl, tg.S, tx, ty, tz, cx,
-                                       cy, cz, sh, acc);
-            store_partials(sh, tg.act, acc);
-            __syncthreads();
-            auto put = [&](int j, int c, double v) { wt[cb + j][c] = v; };
-            if constexpr (MF) slice_sums_mf<NTT, TP>(sh.u.red, sh.tgt, tg.h, tg.S, ntc, put);
-            else slice_sums<NTT, TP>(sh.u.red, tg.h, tg.S, ntc, put);
-            __syncthreads();
+                    for (int k = 0; k < TP; ++k) {
+                        const Prox pm = tp[tg.me[k]];
+                        tx[k] = target_reg<T>(pm.x - cx);
+                        ty[k] = target_reg<T>(pm.y - cy);
+                        tz[k] = target_reg<T>(pm.z - cz);
+                        nome[k] = -1;
+                    }
+                    double acc[TP][4];
+#pragma unroll
+                    for (int k = 0; k < TP; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0;
+                    accumulate_entries<T, DEN>(a, a.nlist, ec, ce, 3u, 0xffffffffu, nome, tg.act, tg.sl, tg.S, tx, ty,
+                                               tz, cx, cy, cz, sh, acc);
+                    store_partials(sh, tg.act, acc);
+                    __syncthreads();
+                    auto put = [&](int j, int cc, double v) { wt[cb + j][cc] = v; };
+                    slice_sums<NTT, TP>(sh.u.red, tg.h, tg.S, ntc, put);
+                    __syncthreads();
+                }
+                for (int o = tid; o < 3 * np; o += NTT) a.alpha[(rec + poff) * 3 + o] = wt[o / 3][o % 3];
+            }
+        };
+        if constexpr (!LEARNED) {
+            class_values(0, e, se);
+        } else {
+            const u32 cmask = (1u << a.DB) - 1u;
+            u32 present = 0;
+            u32 ec = e;
+            while (ec < se) {  // the classes present, in increasing order
+                const int c = (int)((a.nlist[ec] >> (a.W + 1)) & cmask);
+                u32 lo = ec, hi = se;  // class(lo) == c; class(hi) > c or hi == se
+                while (hi - lo > 1) {
+                    const u32 mid = (lo + hi) >> 1;
+                    if ((int)((a.nlist[mid] >> (a.W + 1)) & cmask) == c) lo = mid;
+                    else hi = mid;
+                }
+                class_values(c, ec, hi);
+                present |= 1u << c;
+                ec = hi;
+            }
+            if (tid == 0) a.cls_mask[a.slot[t]] = present;
         }
-        // alpha_k = sum_n (V_ref^{-1})_{kn} |b_n1 v1 + b_n2 v2 + b_n3 v3|^d W(x~_n)
-        block_matvec<NTT, 3>(a.ref.vinvT + qoff, np, nd, wt, &sh.u.red[0][0][0], co);
-        const size_t ts = (size_t)a.slot[t] * a.NPT + poff;
-        // stored as c_k alpha_k: the basis coefficient of the interpolation
-        // folded in once per node rather than once per particle
-        for (int k = tid; k < 3 * np; k += NTT) a.alpha[ts * 3 + k] = a.ref.coef[poff + k / 3] * co[k / 3][k % 3];
         __syncthreads();
         e = se > e ? se : e + 1;  // a segment always ends after its first entry
+    }
+}
+
+// The coefficients of every target node of the far lists from the values
+// k_far_targets left in its record (Sec. 3, interpolation in triangles):
+//   alpha_k = sum_m (V_ref^{-1})_km |P_m|^d W(x~_m),
+// P_m = b_m1 v1 + b_m2 v2 + b_m3 v3 the unnormalised point, stored as
+// c_k alpha_k (the basis multinomial folded in once per node rather than
+// once per particle).  The learned form folds its classes into one
+// degree-10 record: on the sphere a degree-d polynomial in the barycentrics
+// equals a degree-10 one (times |V b|^(10 - d) = 1, d even), so the
+// degree-10 interpolant through its values at the degree-10 points
+// reproduces it exactly (up to rounding); its scaled values there are
+//   v_n = |P10_n|^(10 - d) sum_m T_nm |P_m|^d W(x~_m),
+// T_nm = sum_k (V_ref,d^{-1})_km B_k(b_10,n) (the class's Lagrange basis at
+// the degree-10 reference points; identity for degree 10), and the record is
+// c_k sum_n (V_ref,10^{-1})_kn (sum over classes of v_n); a node with
+// degree-10 work only takes the one-class formula (bitwise the method
+// without gating).  One workgroup per node with more than N_T particles (all
+// levels in one index space); nodes without far-field work are skipped.
+// One node's coefficients of class c by one wave: lane k forms
+// sum_m Vt[m np + k] |P_m|^d W_m in order of m (Vt: the class's transposed
+// inverse Vandermonde matrix, in LDS or global memory), the values staged
+// in the wave's own LDS rows (wv, nd).
+__device__ __forceinline__ void finish_class_wave(const EvalArgs& a, const NodeGeo& g, size_t rec, int c,
+                                                  const double* __restrict__ Vt, double (*wv)[3], double* nd) {
+    const int lane = threadIdx.x & 63;
+    const int np = STC_PICK4(a.cls.np, c), poff = STC_PICK4(a.cls.poff, c), d = STC_PICK4(a.cls.deg, c);
+    for (int m = lane; m < np; m += 64) {
+        double y[3];
+        const double sc = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
+        nd[m] = sc;
+        wv[m][0] = a.alpha[(rec + poff + m) * 3];
+        wv[m][1] = a.alpha[(rec + poff + m) * 3 + 1];
+        wv[m][2] = a.alpha[(rec + poff + m) * 3 + 2];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int k = lane; k < np; k += 64) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int m = 0; m < np; ++m) {
+            const double f = Vt[m * np + k] * nd[m];
+            s0 += f * wv[m][0];
+            s1 += f * wv[m][1];
+            s2 += f * wv[m][2];
+        }
+        const double ck = a.ref.coef[poff + k];
+        a.alpha[(rec + poff + k) * 3] = ck * s0;
+        a.alpha[(rec + poff + k) * 3 + 1] = ck * s1;
+        a.alpha[(rec + poff + k) * 3 + 2] = ck * s2;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// index gi of the flattened list of nodes with more than N_T particles
+__device__ __forceinline__ i64 big_node(const EvalArgs& a, u32 gi) {
+    int lvl = 0;
+    for (; lvl <= a.L; ++lvl) {
+        const u32 nl = a.level_big[lvl] < a.per_level ? a.level_big[lvl] : a.per_level;
+        if (gi < nl) break;
+        gi -= nl;
+    }
+    return a.big_list[(size_t)lvl * a.per_level + gi];
+}
+
+__device__ __forceinline__ u32 big_node_count(const EvalArgs& a) {
+    u32 total = 0;
+    for (int lvl = 0; lvl <= a.L; ++lvl) total += a.level_big[lvl] < a.per_level ? a.level_big[lvl] : a.per_level;
+    return total;
+}
+
+// The coefficients of every target node of the far lists from the values
+// k_far_targets left in its record (Sec. 3, interpolation in triangles):
+//   alpha_k = sum_m (V_ref^{-1})_km |P_m|^d W(x~_m),
+// P_m = b_m1 v1 + b_m2 v2 + b_m3 v3 the unnormalised point, stored as
+// c_k alpha_k (the basis multinomial folded in once per node rather than
+// once per particle).  One wave per node with more than N_T particles (all
+// levels in one index space; nodes without far-field work are skipped),
+// V^{-1} staged in LDS once per workgroup when it fits (vt_lds).
+__global__ __launch_bounds__(256) void k_far_finish_one(EvalArgs a, int vt_lds) {
+    extern __shared__ double dyn[];
+    __shared__ double wv[4][kMaxNp][3];
+    __shared__ double nd[4][kMaxNp];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const int np = a.cls.np[0];
+    const double* Vt = a.ref.vinvT + a.cls.qoff[0];
+    if (vt_lds) {
+        for (int i = tid; i < np * np; i += 256) dyn[i] = Vt[i];
+        __syncthreads();
+        Vt = dyn;
+    }
+    const u32 total = big_node_count(a);
+    for (u32 gi = blockIdx.x * 4 + w; gi < total; gi += gridDim.x * 4) {
+        const i64 node = big_node(a, gi);
+        if (a.nseg_end[node] == 0) continue;  // no far-field work at this node
+        finish_class_wave(a, a.geo[node & a.node_mask], (size_t)a.slot[node] * a.NPT, 0, Vt, wv[w], nd[w]);
+    }
+}
+
+// The learned form folds its classes into one degree-10 record: on the
+// sphere a degree-d polynomial in the barycentrics equals a degree-10 one
+// (times |V b|^(10 - d) = 1, d even), so the degree-10 interpolant through
+// its values at the degree-10 points reproduces it exactly (up to
+// rounding); its scaled values there are
+//   v_n = |P10_n|^(10 - d) sum_m T_nm |P_m|^d W(x~_m),
+// T_nm = sum_k (V_ref,d^{-1})_km B_k(b_10,n) (the class's Lagrange basis at
+// the degree-10 reference points; identity for degree 10), and the record is
+// c_k sum_n (V_ref,10^{-1})_kn (sum over classes of v_n).  A node with
+// degree-10 work only takes the one-class formula of k_far_finish_one (the
+// same arithmetic, so without a network the learned context is bitwise the
+// method without gating).  One workgroup per node.
+__global__ __launch_bounds__(256) void k_far_finish_learned(EvalArgs a) {
+    __shared__ double w[kMaxNp][3];
+    __shared__ double nd[kMaxNp];
+    __shared__ double co[kMaxNp][3];
+    __shared__ double red[3 * 256];
+    __shared__ double v10[kMaxNp][3];
+    const int tid = threadIdx.x;
+    const u32 total = big_node_count(a);
+    for (u32 gi = blockIdx.x; gi < total; gi += gridDim.x) {
+        const i64 node = big_node(a, gi);
+        if (a.nseg_end[node] == 0) continue;  // no far-field work at this node
+        const NodeGeo& g = a.geo[node & a.node_mask];
+        const size_t rec = (size_t)a.slot[node] * a.NPT;
+        const u32 present = a.cls_mask[a.slot[node]];
+        if (present == 8u) {
+            if (tid < 64) finish_class_wave(a, g, rec, 3, a.ref.vinvT + a.cls.qoff[3], w, nd);
+            __syncthreads();
+            continue;
+        }
+        const int np10 = a.cls.np[3], poff10 = a.cls.poff[3], d10 = a.cls.deg[3];
+        for (int m = tid; m < np10; m += 256) v10[m][0] = v10[m][1] = v10[m][2] = 0.0;
+        for (int c = 0; c < 4; ++c) {
+            if (!((present >> c) & 1u)) continue;
+            const int np = STC_PICK4(a.cls.np, c), poff = STC_PICK4(a.cls.poff, c), d = STC_PICK4(a.cls.deg, c);
+            for (int m = tid; m < np; m += 256) {
+                double y[3];
+                nd[m] = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
+                w[m][0] = a.alpha[(rec + poff + m) * 3];
+                w[m][1] = a.alpha[(rec + poff + m) * 3 + 1];
+                w[m][2] = a.alpha[(rec + poff + m) * 3 + 2];
+            }
+            __syncthreads();
+            if (c < 3) {
+                block_matvec<256, 3>(a.up_T + (size_t)poff * np10, np, np10, nd, w, red, co);
+                for (int m = tid; m < np10; m += 256) {
+                    double y[3];
+                    const double sc = ipow(proxy_point(g, a.ref.points + 3 * (poff10 + m), y), d10 - d);
+                    v10[m][0] += sc * co[m][0];
+                    v10[m][1] += sc * co[m][1];
+                    v10[m][2] += sc * co[m][2];
+                }
+            } else {
+                for (int m = tid; m < np10; m += 256) {
+                    v10[m][0] += nd[m] * w[m][0];
+                    v10[m][1] += nd[m] * w[m][1];
+                    v10[m][2] += nd[m] * w[m][2];
+                }
+            }
+            __syncthreads();
+        }
+        block_matvec<256, 3>(a.up_H, np10, np10, nullptr, v10, red, co);
+        for (int k = tid; k < 3 * np10; k += 256) a.alpha[(rec + poff10) * 3 + k] = co[k / 3][k % 3];
+        __syncthreads();
     }
 }
 
@@ -835,8 +1101,9 @@ __device__ __forceinline__ void l2p_level(const EvalArgs& a, int poff, bool has,
     }
 }
 
-// D0..D3: degrees of the classes in use (0 = class unused)
-template <int D0, int D1, int D2, int D3>
+// D: the degree of the stored far-field record (the context's degree, or 10
+// for the learned form, whose classes are folded into one record)
+template <int D>
 __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, double* __restrict__ u, int accumulate) {
     const int tid = threadIdx.x;
     const i64 i0 = (i64)blockIdx.x * blockDim.x + tid;
@@ -849,9 +1116,10 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
         const int L = a.L;
         const i64 mbase = (i64)(leaf >> a.LB) << a.NB;
         const u32 kl = leaf & ((1u << a.LB) - 1u);
-        // which of the particle's nodes hold far-field coefficients, per
-        // class (bit = level): independent loads, issued together
-        u32 hb[4] = {0u, 0u, 0u, 0u};
+        const int poff = a.cls.poff[a.ndeg - 1];
+        // which of the particle's nodes hold far-field coefficients (bit =
+        // level): independent loads, issued together
+        u32 hb = 0u;
 #pragma unroll
         for (int lvl = 0; lvl <= kMaxLevels; ++lvl) {
             const int lc = lvl < L ? lvl : L;
@@ -859,22 +1127,12 @@ __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, do
             // a level without nodes of more than N_T particles has no target
             // node of the proxy lists
             const bool lv = valid && lvl <= L && a.level_big[lc] != 0u;
-            const i64 sg = nd << a.DB;
-            if (lv && a.nseg_end[sg] != 0) hb[0] |= 1u << lvl;
-            if (D1 > 0 && lv && a.nseg_end[sg | 1] != 0) hb[1] |= 1u << lvl;
-            if (D2 > 0 && lv && a.nseg_end[sg | 2] != 0) hb[2] |= 1u << lvl;
-            if (D3 > 0 && lv && a.nseg_end[sg | 3] != 0) hb[3] |= 1u << lvl;
+            if (lv && a.nseg_end[nd] != 0) hb |= 1u << lvl;
         }
         for (int lvl = 0; lvl <= L; ++lvl) {
             if (a.level_big[lvl] == 0u) continue;  // uniform: no work at all
             const i64 nd = mbase + a.level_off_tab[lvl] + (i64)(kl >> (2 * (L - lvl)));
-            l2p_level<D0>(a, STC_PICK4(a.cls.poff, 0), (hb[0] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
-            if (D1 > 0)
-                l2p_level<D1 ? D1 : 1>(a, STC_PICK4(a.cls.poff, 1), (hb[1] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
-            if (D2 > 0)
-                l2p_level<D2 ? D2 : 1>(a, STC_PICK4(a.cls.poff, 2), (hb[2] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
-            if (D3 > 0)
-                l2p_level<D3 ? D3 : 1>(a, STC_PICK4(a.cls.poff, 3), (hb[3] >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
+            l2p_level<D>(a, poff, (hb >> lvl) & 1u, nd, x0, x1, x2, W0, W1, W2);
         }
     }
     if (!valid) return;
@@ -1050,17 +1308,32 @@ void near_shape(hipStream_t s, const EvalArgs& a, u32 type_mask) {
 template <int NTT>
 void far_shape(hipStream_t s, const EvalArgs& a) {
     const dim3 g(a.far_grid), b(NTT);
-    if (a.stream) {
-        if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, DEN_LOG_DIST2, NTT>), g, b, 0, s, a);
+    if (a.stream) {  // (never with the learned form)
+        if (a.precision == STC_FP32)
+            hipLaunchKernelGGL((k_far_targets<float, DEN_LOG_DIST2, NTT, false, false>), g, b, 0, s, a);
         else if (a.denominator == STC_DEN_DIST2)
-            hipLaunchKernelGGL((k_far_targets<double, DEN_LOG_DIST2, NTT>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_far_targets<double, DEN_LOG_DOT, NTT>), g, b, 0, s, a);
+            hipLaunchKernelGGL((k_far_targets<double, DEN_LOG_DIST2, NTT, false, false>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_far_targets<double, DEN_LOG_DOT, NTT, false, false>), g, b, 0, s, a);
         return;
     }
-    if (a.precision == STC_FP32) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NTT>), g, b, 0, s, a);
-    else if (a.denominator == STC_DEN_DIST2)
-        hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2, NTT>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DOT, NTT>), g, b, 0, s, a);
+    const bool learned = a.DB != 0;
+    if (a.precision == STC_FP32) {
+        // the matrix-core form covers classes of up to kMfTargets points
+        constexpr bool MF = STC_FAR_MFMA != 0;
+        if (MF && a.cls.np[a.ndeg - 1] <= kMfTargets) {
+            if (learned) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NTT, MF, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NTT, MF, false>), g, b, 0, s, a);
+        } else {
+            if (learned) hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NTT, false, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_far_targets<float, STC_DEN_DIST2, NTT, false, false>), g, b, 0, s, a);
+        }
+    } else if (a.denominator == STC_DEN_DIST2) {
+        if (learned) hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2, NTT, false, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DIST2, NTT, false, false>), g, b, 0, s, a);
+    } else {
+        if (learned) hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DOT, NTT, false, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_far_targets<double, STC_DEN_DOT, NTT, false, false>), g, b, 0, s, a);
+    }
 }
 }  // namespace
 
@@ -1077,17 +1350,28 @@ void launch_far_targets(hipStream_t s, const EvalArgs& a) {
     else far_shape<256>(s, a);
 }
 
+void launch_far_finish(hipStream_t s, const EvalArgs& a) {
+    if (a.DB != 0) {
+        const unsigned grid = (unsigned)std::min<u32>(std::max<u32>(a.per_level, 1u), 2048u);
+        hipLaunchKernelGGL(k_far_finish_learned, dim3(grid), dim3(256), 0, s, a);
+        return;
+    }
+    // V^{-1} in LDS up to 66 points (degree 10: 34.8 KB, with the waves'
+    // rows 50 KB of the 64 KB a workgroup may take)
+    const int np = a.cls.np[0];
+    const int lds = np <= 66 ? 1 : 0;
+    const size_t bytes = lds ? (size_t)np * np * sizeof(double) : 0;
+    const unsigned grid = (unsigned)std::min<u32>(std::max<u32>((a.per_level + 3) / 4, 1u), 1024u);
+    hipLaunchKernelGGL(k_far_finish_one, dim3(grid), dim3(256), bytes, s, a, lds);
+}
+
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate) {
     if (a.n <= 0) return;
     const dim3 g((unsigned)((a.n + 255) / 256)), b(256);
     const int f = do_far ? 1 : 0, acc = accumulate ? 1 : 0;
-    if (a.ndeg == 4) {  // the learned form's classes: degrees 4, 6, 8, 10
-        hipLaunchKernelGGL((k_l2p_finalize<4, 6, 8, 10>), g, b, 0, s, a, f, d_u, acc);
-        return;
-    }
-    switch (a.cls.deg[0]) {
+    switch (a.cls.deg[a.ndeg - 1]) {
 #define STC_L2P_CASE(D) \
-    case D: hipLaunchKernelGGL((k_l2p_finalize<D, 0, 0, 0>), g, b, 0, s, a, f, d_u, acc); break;
+    case D: hipLaunchKernelGGL((k_l2p_finalize<D>), g, b, 0, s, a, f, d_u, acc); break;
         STC_L2P_CASE(1) STC_L2P_CASE(2) STC_L2P_CASE(3) STC_L2P_CASE(4) STC_L2P_CASE(5) STC_L2P_CASE(6)
         STC_L2P_CASE(7) STC_L2P_CASE(8) STC_L2P_CASE(9) STC_L2P_CASE(10) STC_L2P_CASE(11) STC_L2P_CASE(12)
         STC_L2P_CASE(13) STC_L2P_CASE(14)

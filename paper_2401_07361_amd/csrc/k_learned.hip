@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_pair_errors(LearnedArgs la, EvalArgs a,
                     }
                 }
                 __syncthreads();
-                block_matvec<256, 3>(a.ref.vinvT + qoff, np, nd, wt, red, &al[poff]);
+                block_matvec<256, 3>(a.ref.vinvT + qoff, np, np, nd, wt, red, &al[poff]);
             }
         }
         double e[4] = {0.0, 0.0, 0.0, 0.0};

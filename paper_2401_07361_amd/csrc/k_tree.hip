@@ -488,11 +488,13 @@ __global__ __launch_bounds__(256) void k_upward_finish(int L, const u32* __restr
 // Lower-degree proxy charges from the degree-10 ones (learned form).  The
 // degree-d interpolant's space lies inside the degree-10 one, so the degree-d
 // charges are the degree-10 point charges re-interpolated:
-//   w_d,m = |P_d,m|^d sum_n T_mn w_10,n / |P_10,n|^d,
+//   w_d,m = |P_d,m|^d sum_n T_nm w_10,n / |P_10,n|^d,
 // P = b_1 v_1 + b_2 v_2 + b_3 v_3 the unnormalised point of reference
-// barycentrics b, and T_mn = sum_k (V_ref,d^{-1})_km B_k(b_10,n) a fixed
+// barycentrics b, and T_nm = sum_k (V_ref,d^{-1})_km B_k(b_10,n) a fixed
 // reference matrix (the multinomial-scaled basis is homogeneous of degree d,
-// so the node's geometry enters only through |P|).  One wave per node.
+// so the node's geometry enters only through |P|), stored [n][m] so that the
+// lanes (one output m each) read consecutive entries.  One wave per node,
+// all levels' nodes in one index space.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_downsample(int L, int NB, const u32* __restrict__ flags,
                                                      const i32* __restrict__ big_list, u32 per_level,
@@ -504,37 +506,42 @@ __global__ __launch_bounds__(256) void k_downsample(int L, int NB, const u32* __
     const u32 lm = (1u << NB) - 1u;
     const int np10 = cls.np[3], poff10 = cls.poff[3];
     const int nout = cls.poff[3];  // points of classes 0..2
-    for (int lvl = 0; lvl <= L; ++lvl) {
-        u32 nbl = flags[F_LEVEL + lvl];
-        if (nbl > per_level) nbl = per_level;
-        for (u32 b0 = blockIdx.x * 4; b0 < nbl; b0 += gridDim.x * 4) {
-            const u32 bi = b0 + w;
-            const bool ok = bi < nbl;
-            const i64 node = ok ? big_list[(size_t)lvl * per_level + bi] : 0;
-            const NodeGeo& g = geo[node & lm];
-            const size_t rec = ok ? (size_t)slot[node] * NPT : 0;
-            for (int n = lane; n < np10 && ok; n += 64) {
-                double y[3];
-                const double nrm = proxy_point(g, ref_points + 3 * (poff10 + n), y);
-                const double w10 = prox[rec + poff10 + n].w;
-                for (int c = 0; c < 3; ++c) src[w][c][n] = w10 / ipow(nrm, cls.deg[c]);
+    u32 total = 0;
+    for (int lvl = 0; lvl <= L; ++lvl) total += flags[F_LEVEL + lvl] < per_level ? flags[F_LEVEL + lvl] : per_level;
+    for (u32 b0 = blockIdx.x * 4; b0 < total; b0 += gridDim.x * 4) {  // the same trip count in all waves
+        u32 bi = b0 + w;
+        const bool ok = bi < total;
+        int lvl = 0;
+        if (ok)
+            for (; lvl <= L; ++lvl) {
+                const u32 nl = flags[F_LEVEL + lvl] < per_level ? flags[F_LEVEL + lvl] : per_level;
+                if (bi < nl) break;
+                bi -= nl;
             }
-            __syncthreads();
-            for (int o = lane; o < nout && ok; o += 64) {
-                const int c = o < cls.poff[1] ? 0 : (o < cls.poff[2] ? 1 : 2);
-                double acc = 0.0;
-                for (int n = 0; n < np10; ++n) acc += T[(size_t)o * np10 + n] * src[w][c][n];
-                double y[3];
-                const double nrm = proxy_point(g, ref_points + 3 * o, y);
-                Prox pr;
-                pr.x = y[0];
-                pr.y = y[1];
-                pr.z = y[2];
-                pr.w = ipow(nrm, cls.deg[c]) * acc;
-                prox[rec + o] = pr;
-            }
-            __syncthreads();
+        const i64 node = ok ? big_list[(size_t)lvl * per_level + bi] : 0;
+        const NodeGeo& g = geo[node & lm];
+        const size_t rec = ok ? (size_t)slot[node] * NPT : 0;
+        for (int n = lane; n < np10 && ok; n += 64) {
+            double y[3];
+            const double nrm = proxy_point(g, ref_points + 3 * (poff10 + n), y);
+            const double w10 = prox[rec + poff10 + n].w;
+            for (int c = 0; c < 3; ++c) src[w][c][n] = w10 / ipow(nrm, cls.deg[c]);
         }
+        __syncthreads();
+        for (int o = lane; o < nout && ok; o += 64) {
+            const int c = o < cls.poff[1] ? 0 : (o < cls.poff[2] ? 1 : 2);
+            double acc = 0.0;
+            for (int n = 0; n < np10; ++n) acc += T[(size_t)n * nout + o] * src[w][c][n];
+            double y[3];
+            const double nrm = proxy_point(g, ref_points + 3 * o, y);
+            Prox pr;
+            pr.x = y[0];
+            pr.y = y[1];
+            pr.z = y[2];
+            pr.w = ipow(nrm, cls.deg[c]) * acc;
+            prox[rec + o] = pr;
+        }
+        __syncthreads();
     }
 }
 
@@ -799,8 +806,8 @@ __global__ __launch_bounds__(256) void k_node_counts(const i32* __restrict__ nbe
     }
 }
 
-// Segments of sorted lists: entries with the same key >> shift (the target,
-// or the target and degree class) occupy [seg_beg[.], seg_end[.]).  Arrays
+// Segments of sorted lists: entries with the same key >> shift (the target
+// node) occupy [seg_beg[.], seg_end[.]).  Arrays
 // must be zeroed before.  grid.y = list.
 __global__ __launch_bounds__(256) void k_segments(SegLists sg, u32 cap) {
     const int y = blockIdx.y;

@@ -143,10 +143,20 @@ struct EvalArgs {
     // launch shapes of the persistent segment kernels
     int near_threads, near_grid, far_threads, far_grid;
     int stream;          // 1: the stream function's logarithmic kernel, output psi (n values)
+    // learned form: class c's Lagrange basis at the degree-10 reference
+    // points, [(poff_c + m) * np10 + n], and c_k (V_ref,10^{-1})_kn, [n * np10 + k]
+    const double* up_T;
+    const double* up_H;
+    // nodes with more than N_T particles, per level (k_far_finish), and the
+    // learned form's degree classes present at each target node (by slot)
+    const i32* big_list;
+    u32 per_level;
+    u32* cls_mask;
 };
 
 void launch_near(hipStream_t s, const EvalArgs& a, u32 type_mask);
 void launch_far_targets(hipStream_t s, const EvalArgs& a);
+void launch_far_finish(hipStream_t s, const EvalArgs& a);
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate);
 int direct_blocks_per_cu(int precision, int denominator);
 int direct_targets_per_block(int precision);

@@ -53,7 +53,10 @@ struct stc_ctx {
     u16* feat = nullptr;          // their features (BF16, 16 per candidate)
     float* mlp_out = nullptr;     // network outputs per candidate
     double *qabs = nullptr, *qsum = nullptr;  // per-node charge sums
-    double* ref_T = nullptr;      // degree-10 -> lower-degree re-interpolation matrices
+    double* ref_T = nullptr;      // degree-10 -> lower-degree re-interpolation, [n][o] (n: degree-10 point)
+    double* up_T = nullptr;       // T transposed, [poff_c + m][n]: class c's Lagrange basis at the degree-10 points
+    double* up_H = nullptr;       // degree-10 coefficients from values, [n][k] = c_k (V_ref,10^{-1})_kn
+    u32* cls_mask = nullptr;      // degree classes with far-field work at each target node (by slot)
     const uint16_t* model = nullptr;  // BF16 network parameters (caller's), or null: reject every candidate
     std::vector<i64> level_off_host;
     // device buffers (all carved from the caller's workspace in stc_create)
@@ -247,6 +250,11 @@ EvalArgs eval_args(stc_ctx* c) {
     a.near_grid = grid_for(c, sh.near_blocks_per_cu);
     a.far_threads = sh.far_threads;
     a.far_grid = grid_for(c, sh.far_blocks_per_cu);
+    a.up_T = c->up_T;
+    a.up_H = c->up_H;
+    a.big_list = c->big_list;
+    a.per_level = c->per_level;
+    a.cls_mask = c->cls_mask;
     return a;
 }
 
@@ -473,7 +481,7 @@ stc_status do_traverse(stc_ctx* c) {
     }
     SegLists sg{{c->tlist, c->nlist},
                 {c->counters + C_TLIST, c->counters + C_NLIST},
-                {c->W + 1 + c->DB, c->W + 1},
+                {c->W + 1 + c->DB, c->W + 1 + c->DB},
                 {c->tseg_beg, c->nseg_beg},
                 {c->tseg_end, c->nseg_end},
                 2};
@@ -492,7 +500,10 @@ stc_status do_eval(stc_ctx* c, bool near, bool far, double* d_u, bool accumulate
     mark(c, 3);
     launch_near(s, a, mask);
     mark(c, 4);
-    if (far) launch_far_targets(s, a);
+    if (far) {
+        launch_far_targets(s, a);
+        launch_far_finish(s, a);
+    }
     mark(c, 5);
     launch_l2p_finalize(s, a, far, d_u, accumulate);
     mark(c, 6);
@@ -655,6 +666,9 @@ void carve(stc_ctx* c, Carver& cv) {
     cv.take(&c->upart, (size_t)c->items_cap * c->cls.np[c->ndeg - 1]);
     if (c->learned) {
         cv.take(&c->ref_T, (size_t)c->cls.poff[3] * c->cls.np[3]);
+        cv.take(&c->up_T, (size_t)c->cls.poff[3] * c->cls.np[3]);
+        cv.take(&c->up_H, (size_t)c->cls.np[3] * c->cls.np[3]);
+        cv.take(&c->cls_mask, c->slot_cap);
         cv.take(&c->cand, c->cap);
         cv.take(&c->feat, (size_t)c->cap * 16);
         cv.take(&c->mlp_out, (size_t)c->cap * 4);
@@ -848,11 +862,19 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
     // the epoch of the pass that wrote it; epochs start at 1)
     cp = cp && hipMemsetAsync(c->sort_status, 0, (size_t)2 * 256 * c->hist_blocks * sizeof(u64), s) == hipSuccess &&
          hipMemsetAsync(c->sort_epoch, 0, 2 * sizeof(u32), s) == hipSuccess;
-    // learned form: T[(poff_c + m) * 66 + n] = sum_k (V_ref,d^{-1})_km B_k(b_10,n),
-    // degree-10 point charges -> degree-d (classes 0..2), in long double
-    std::vector<double> T_h;
+    // learned form, in long double:
+    //   T[n * 88 + poff_c + m] = sum_k (V_ref,d^{-1})_km B_k(b_10,n): class c's
+    //     Lagrange basis at the degree-10 reference points (degree-10 point
+    //     charges -> degree d in the upward pass; kept transposed as well,
+    //     [(poff_c + m) * 66 + n], for the far field's values -> degree 10);
+    //   H[n * 66 + k] = c_k (V_ref,10^{-1})_kn: degree-10 coefficients (times
+    //     their multinomials, as stored) from values at the degree-10 points
+    std::vector<double> T_h, Tu_h, H_h;
     if (c->learned) {
         const RefTables& t10 = c->ref_host[3];
+        const int nout = c->cls.poff[3];
+        T_h.assign((size_t)t10.np * nout, 0.0);
+        Tu_h.assign((size_t)nout * t10.np, 0.0);
         for (int k = 0; k < 3; ++k) {
             const RefTables& td = c->ref_host[k];
             for (int m = 0; m < td.np; ++m)
@@ -864,10 +886,18 @@ stc_status stc_create_batched(const stc_params* p, int32_t max_members, int64_t 
                             for (int e = 0; e < td.expo[3 * kk + a]; ++e) B *= (long double)t10.points[3 * n + a];
                         acc += (long double)td.vinv[(size_t)kk * td.np + m] * B;
                     }
-                    T_h.push_back((double)acc);
+                    T_h[(size_t)n * nout + c->cls.poff[k] + m] = (double)acc;
+                    Tu_h[(size_t)(c->cls.poff[k] + m) * t10.np + n] = (double)acc;
                 }
         }
-        cp = cp && up(c->ref_T, T_h.data(), T_h.size() * sizeof(double));
+        H_h.assign((size_t)t10.np * t10.np, 0.0);
+        for (int n = 0; n < t10.np; ++n)
+            for (int kk = 0; kk < t10.np; ++kk)
+                H_h[(size_t)n * t10.np + kk] =
+                    (double)((long double)t10.coef[kk] * (long double)t10.vinv[(size_t)kk * t10.np + n]);
+        cp = cp && up(c->ref_T, T_h.data(), T_h.size() * sizeof(double)) &&
+             up(c->up_T, Tu_h.data(), Tu_h.size() * sizeof(double)) &&
+             up(c->up_H, H_h.data(), H_h.size() * sizeof(double));
     }
     launch_fill_u32(s, c->counters, C_COUNT, 0u);
     launch_fill_u32(s, c->flags, F_COUNT, 0u);
