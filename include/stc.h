@@ -636,10 +636,15 @@ stc_status stc_reference_tables(int32_t degree, double* h_points, double* h_vinv
 
 /* Phase timing.  stc_set_timing(ctx, k) with k > 0 creates HIP events for k
  * evaluations; each following evaluation (stc_velocity, or the pipeline calls
- * that make one up) records events on the context stream around its phases:
- * 0 tree build, 1 upward pass, 2 traversal (incl. list sort), 3 near-side
- * interactions (one kernel: PP and PC), 4 target-proxy interactions (one
- * kernel: CP and CC), 5 interpolation to particles and output.  k = 0 turns
+ * that make one up) records a begin and an end event around each of its
+ * phases, on the stream the phase runs on: 0 tree build, 1 upward pass, 2
+ * traversal (incl. list sort), 3 near-side interactions (one kernel: PP and
+ * PC), 4 target-proxy interactions (one kernel: CP and CC, the values at the
+ * target proxy points), 5 interpolation (the coefficients formed from those
+ * values, the interpolation to particles) and output.
+ * Outside the learned form phase 1 runs on the context's side stream while
+ * phase 2 runs, so the phases of an evaluation need not add up to its
+ * duration.  k = 0 turns
  * timing off and frees the events.  stc_phase_times synchronises and returns
  * the summed milliseconds per phase over the recorded evaluations (ms[6]) and
  * their number; recording restarts afterwards.  Evaluations beyond k are not

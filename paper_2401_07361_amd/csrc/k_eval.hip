@@ -277,16 +277,18 @@ constexpr int kMfGroups = kMfTargets / 16;
 // consecutive ones staged per thread), one batch of NTT list entries, and
 // the per-slice partial sums, which share the tiles' space (they are
 // written after the last tile is used).  The matrix-core form (MF) stages
-// each source as y = (x, y, z, |y|^2) and its row q (y, 1), the rows of four
-// consecutive sources interleaved by component ([(l / 4) 4 + c][l % 4]) so
-// that a lane reads its four B operands with one 16-byte load; its partial
-// sums are per wave, and the pass's target points (x, |x|^2) sit in tgt.
+// each source's (x, y, z, 1) transposed per chunk of 16 ([chunk][c][l % 16],
+// so that the A operand's lanes read consecutive words), its |y|^2, and its
+// row q (y, 1), the rows of four consecutive sources interleaved by
+// component ([(l / 4) 4 + c][l % 4]) so that a lane reads its four B
+// operands with one 16-byte load; its partial sums are per wave, and the
+// pass's target points (x, |x|^2) sit in tgt.
 // (The matrix-core members are empty placeholders in the VALU form, so that
 // its layout, and with it the kernels' register allocation, is unchanged.)
 template <int NTT, bool MF>
 struct MfShared {
     struct Tiles {
-        mf32x4 y[2 * NTT];    // (x, y, z, 1)
+        float y[2 * NTT / 16][4][16];  // per chunk of 16 sources: x, y, z, 1 (the A operand's rows)
         mf32x4 row[2 * NTT];  // q (x, y, z, 1), four sources interleaved by component
         float b[2 * NTT];     // |y|^2
     };
@@ -381,13 +383,19 @@ template <int NTT, int TP>
 __device__ __forceinline__ void stage_mf(SegShared<float, NTT, TP, true>& sh, int l, const Src<float>& v, bool dummy) {
     float* row = reinterpret_cast<float*>(sh.u.m.row) + (((l >> 2) * 4) << 2) + (l & 3);
     if (dummy) {
-        sh.u.m.y[l] = mf32x4{0.f, 0.f, 0.f, 1.f};
+        sh.u.m.y[l >> 4][0][l & 15] = 0.f;
+        sh.u.m.y[l >> 4][1][l & 15] = 0.f;
+        sh.u.m.y[l >> 4][2][l & 15] = 0.f;
+        sh.u.m.y[l >> 4][3][l & 15] = 1.f;
         sh.u.m.b[l] = 1.f;
         row[0] = row[4] = row[8] = row[12] = 0.f;
         return;
     }
     const double b = ((double)v.x * v.x + (double)v.y * v.y) + (double)v.z * v.z;
-    sh.u.m.y[l] = mf32x4{v.x, v.y, v.z, 1.f};
+    sh.u.m.y[l >> 4][0][l & 15] = v.x;
+    sh.u.m.y[l >> 4][1][l & 15] = v.y;
+    sh.u.m.y[l >> 4][2][l & 15] = v.z;
+    sh.u.m.y[l >> 4][3][l & 15] = 1.f;
     sh.u.m.b[l] = (float)b;
     row[0] = v.q * v.x;
     row[4] = v.q * v.y;
@@ -508,10 +516,10 @@ __device__ __forceinline__ void tile_sum_mfma(const SegShared<float, NTT, TP, tr
                                               mf32x4* acc) {
     constexpr int NW = NTT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const float* __restrict__ yf = reinterpret_cast<const float*>(sh.u.m.y);
+    const float* __restrict__ yf = &sh.u.m.y[0][0][0];
     const mf32x4* __restrict__ bq = reinterpret_cast<const mf32x4*>(sh.u.m.b);
     for (int ch = w; ch * 16 < cntp; ch += NW) {
-        const float ya = yf[(ch * 16 + (lane & 15)) * 4 + (lane >> 4)];
+        const float ya = yf[ch * 64 + lane];  // A[lane % 16][lane / 16]: consecutive lanes, no bank conflicts
         const mf32x4 b = sh.u.m.row[(ch * 4 + (lane >> 4)) * 4 + (lane & 3)];
         const mf32x4 c = bq[ch * 4 + (lane >> 4)];  // |y|^2 of rows 4 (lane / 16) + i
         mf32x4 den[NG];
@@ -702,7 +710,10 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
                                        cz, sh, acc);
             store_partials(sh, tg.act, acc);
             __syncthreads();
-            auto add = [&](int j, int c, double v) { a.Wacc[3 * (size_t)(tb + cb + j) + c] += v; };
+            // every particle's leaf has a segment (its PP entry with itself),
+            // processed by one workgroup in one pass per target: this is the
+            // particle's first and only write of the near-side sums
+            auto add = [&](int j, int c, double v) { a.Wacc[3 * (size_t)(tb + cb + j) + c] = v; };
             slice_sums<NT, TP>(sh.u.red, tg.h, tg.S, ntc, add);
             __syncthreads();
         }
@@ -863,75 +874,32 @@ __global__ __launch_bounds__(NTT) __attribute__((amdgpu_waves_per_eu((MF && !LEA
     }
 }
 
-// The coefficients of every target node of the far lists from the values
-// k_far_targets left in its record (Sec. 3, interpolation in triangles):
-//   alpha_k = sum_m (V_ref^{-1})_km |P_m|^d W(x~_m),
-// P_m = b_m1 v1 + b_m2 v2 + b_m3 v3 the unnormalised point, stored as
-// c_k alpha_k (the basis multinomial folded in once per node rather than
-// once per particle).  The learned form folds its classes into one
-// degree-10 record: on the sphere a degree-d polynomial in the barycentrics
-// equals a degree-10 one (times |V b|^(10 - d) = 1, d even), so the
-// degree-10 interpolant through its values at the degree-10 points
-// reproduces it exactly (up to rounding); its scaled values there are
-//   v_n = |P10_n|^(10 - d) sum_m T_nm |P_m|^d W(x~_m),
-// T_nm = sum_k (V_ref,d^{-1})_km B_k(b_10,n) (the class's Lagrange basis at
-// the degree-10 reference points; identity for degree 10), and the record is
-// c_k sum_n (V_ref,10^{-1})_kn (sum over classes of v_n); a node with
-// degree-10 work only takes the one-class formula (bitwise the method
-// without gating).  One workgroup per node with more than N_T particles (all
-// levels in one index space); nodes without far-field work are skipped.
-// One node's coefficients of class c by one wave: lane k forms
-// sum_m Vt[m np + k] |P_m|^d W_m in order of m (Vt: the class's transposed
-// inverse Vandermonde matrix, in LDS or global memory), the values staged
-// in the wave's own LDS rows (wv, nd).
-__device__ __forceinline__ void finish_class_wave(const EvalArgs& a, const NodeGeo& g, size_t rec, int c,
-                                                  const double* __restrict__ Vt, double (*wv)[3], double* nd) {
-    const int lane = threadIdx.x & 63;
-    const int np = STC_PICK4(a.cls.np, c), poff = STC_PICK4(a.cls.poff, c), d = STC_PICK4(a.cls.deg, c);
-    for (int m = lane; m < np; m += 64) {
-        double y[3];
-        const double sc = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
-        nd[m] = sc;
-        wv[m][0] = a.alpha[(rec + poff + m) * 3];
-        wv[m][1] = a.alpha[(rec + poff + m) * 3 + 1];
-        wv[m][2] = a.alpha[(rec + poff + m) * 3 + 2];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int k = lane; k < np; k += 64) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int m = 0; m < np; ++m) {
-            const double f = Vt[m * np + k] * nd[m];
-            s0 += f * wv[m][0];
-            s1 += f * wv[m][1];
-            s2 += f * wv[m][2];
-        }
-        const double ck = a.ref.coef[poff + k];
-        a.alpha[(rec + poff + k) * 3] = ck * s0;
-        a.alpha[(rec + poff + k) * 3 + 1] = ck * s1;
-        a.alpha[(rec + poff + k) * 3 + 2] = ck * s2;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// i64 value of lane `src` (wave-uniform result)
+__device__ __forceinline__ i64 readlane64(i64 v, int src) {
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, src);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)((u64)v >> 32), src);
+    return (i64)(((u64)hi << 32) | lo);
 }
 
-// index gi of the flattened list of nodes with more than N_T particles
-__device__ __forceinline__ i64 big_node(const EvalArgs& a, u32 gi) {
+// The nodes with more than N_T particles of all levels in one index space:
+// lvl_end[l] = the number of such nodes at levels <= l (each level's count
+// capped at its list's capacity), filled once per workgroup (ends with a
+// barrier), so that finding a node's level costs no global loads.
+__device__ __forceinline__ u32 big_node_table(const EvalArgs& a, u32* lvl_end) {
+    const int tid = threadIdx.x;
+    if (tid <= a.L) lvl_end[tid] = a.level_big[tid] < a.per_level ? a.level_big[tid] : a.per_level;  // loads in parallel
+    __syncthreads();
+    if (tid == 0)
+        for (int lvl = 1; lvl <= a.L; ++lvl) lvl_end[lvl] += lvl_end[lvl - 1];
+    __syncthreads();
+    return lvl_end[a.L];
+}
+
+// node gi of that index space
+__device__ __forceinline__ i64 big_node(const EvalArgs& a, const u32* lvl_end, u32 gi) {
     int lvl = 0;
-    for (; lvl <= a.L; ++lvl) {
-        const u32 nl = a.level_big[lvl] < a.per_level ? a.level_big[lvl] : a.per_level;
-        if (gi < nl) break;
-        gi -= nl;
-    }
-    return a.big_list[(size_t)lvl * a.per_level + gi];
-}
-
-__device__ __forceinline__ u32 big_node_count(const EvalArgs& a) {
-    u32 total = 0;
-    for (int lvl = 0; lvl <= a.L; ++lvl) total += a.level_big[lvl] < a.per_level ? a.level_big[lvl] : a.per_level;
-    return total;
+    while (gi >= lvl_end[lvl]) ++lvl;
+    return a.big_list[(size_t)lvl * a.per_level + (gi - (lvl > 0 ? lvl_end[lvl - 1] : 0u))];
 }
 
 // The coefficients of every target node of the far lists from the values
@@ -939,26 +907,79 @@ __device__ __forceinline__ u32 big_node_count(const EvalArgs& a) {
 //   alpha_k = sum_m (V_ref^{-1})_km |P_m|^d W(x~_m),
 // P_m = b_m1 v1 + b_m2 v2 + b_m3 v3 the unnormalised point, stored as
 // c_k alpha_k (the basis multinomial folded in once per node rather than
-// once per particle).  One wave per node with more than N_T particles (all
-// levels in one index space; nodes without far-field work are skipped),
-// V^{-1} staged in LDS once per workgroup when it fits (vt_lds).
-__global__ __launch_bounds__(256) void k_far_finish_one(EvalArgs a, int vt_lds) {
-    extern __shared__ double dyn[];
-    __shared__ double wv[4][kMaxNp][3];
-    __shared__ double nd[4][kMaxNp];
-    const int tid = threadIdx.x, w = tid >> 6;
-    const int np = a.cls.np[0];
-    const double* Vt = a.ref.vinvT + a.cls.qoff[0];
-    if (vt_lds) {
-        for (int i = tid; i < np * np; i += 256) dyn[i] = Vt[i];
-        __syncthreads();
-        Vt = dyn;
-    }
-    const u32 total = big_node_count(a);
-    for (u32 gi = blockIdx.x * 4 + w; gi < total; gi += gridDim.x * 4) {
-        const i64 node = big_node(a, gi);
+// once per particle).  One workgroup per node with more than N_T particles
+// (all levels in one index space; nodes without far-field work are
+// skipped).  The product is block_matvec's (the same sums in the same
+// order), with each thread's matrix entries loaded all at once before its
+// FMAs when its share of the rows is at most kFinPer (degree <= 10), so that
+// a node waits on one round of loads instead of a chain.
+constexpr int kFinPer = 22;
+__global__ __launch_bounds__(256) void k_far_finish_one(EvalArgs a) {
+    __shared__ double w[kMaxNp][3];
+    __shared__ double nd[kMaxNp];
+    __shared__ double co[kMaxNp][3];
+    __shared__ double red[3 * 256];
+    __shared__ u32 lvl_end[kMaxLevels + 1];
+    const int tid = threadIdx.x;
+    const int np = a.cls.np[0], poff = a.cls.poff[0], d = a.cls.deg[0];
+    const double* __restrict__ Vt = a.ref.vinvT + a.cls.qoff[0];
+    int rem, k;
+    const int G = div_small(256, np, rem);
+    const int grp = div_small(tid, np, k);
+    const int per = div_small(np + G - 1, G, rem);
+    const int m0 = grp * per, m1 = (m0 + per) < np ? (m0 + per) : np;
+    const bool pref = per <= kFinPer;
+    const u32 total = big_node_table(a, lvl_end);
+    for (u32 gi = blockIdx.x; gi < total; gi += gridDim.x) {
+        const i64 node = big_node(a, lvl_end, gi);
         if (a.nseg_end[node] == 0) continue;  // no far-field work at this node
-        finish_class_wave(a, a.geo[node & a.node_mask], (size_t)a.slot[node] * a.NPT, 0, Vt, wv[w], nd[w]);
+        const NodeGeo& g = a.geo[node & a.node_mask];
+        const size_t rec = (size_t)a.slot[node] * a.NPT + poff;
+        // this thread's matrix entries, in flight while the values arrive
+        double mv[kFinPer];
+        if (pref && grp < G) {
+#pragma unroll
+            for (int j = 0; j < kFinPer; ++j) mv[j] = (m0 + j < m1) ? Vt[(size_t)(m0 + j) * np + k] : 0.0;
+        }
+        for (int m = tid; m < np; m += 256) {
+            double y[3];
+            nd[m] = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
+            w[m][0] = a.alpha[(rec + m) * 3];
+            w[m][1] = a.alpha[(rec + m) * 3 + 1];
+            w[m][2] = a.alpha[(rec + m) * 3 + 2];
+        }
+        __syncthreads();
+        if (pref) {
+            double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+            if (grp < G) {
+#pragma unroll
+                for (int j = 0; j < kFinPer; ++j) {
+                    if (m0 + j < m1) {
+                        const double f = mv[j] * nd[m0 + j];
+                        acc0 += f * w[m0 + j][0];
+                        acc1 += f * w[m0 + j][1];
+                        acc2 += f * w[m0 + j][2];
+                    }
+                }
+            }
+            red[tid] = (grp < G) ? acc0 : 0.0;
+            red[256 + tid] = (grp < G) ? acc1 : 0.0;
+            red[512 + tid] = (grp < G) ? acc2 : 0.0;
+            __syncthreads();
+            if (tid < np) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double sum = 0.0;
+                    for (int gg = 0; gg < G; ++gg) sum += red[c * 256 + gg * np + tid];
+                    co[tid][c] = sum;
+                }
+            }
+            __syncthreads();
+        } else {
+            block_matvec<256, 3>(Vt, np, np, nd, w, red, co);
+        }
+        for (int q = tid; q < 3 * np; q += 256) a.alpha[rec * 3 + q] = a.ref.coef[poff + q / 3] * co[q / 3][q % 3];
+        __syncthreads();
     }
 }
 
@@ -980,19 +1001,32 @@ __global__ __launch_bounds__(256) void k_far_finish_learned(EvalArgs a) {
     __shared__ double co[kMaxNp][3];
     __shared__ double red[3 * 256];
     __shared__ double v10[kMaxNp][3];
+    __shared__ u32 lvl_end[kMaxLevels + 1];
     const int tid = threadIdx.x;
-    const u32 total = big_node_count(a);
+    const u32 total = big_node_table(a, lvl_end);
     for (u32 gi = blockIdx.x; gi < total; gi += gridDim.x) {
-        const i64 node = big_node(a, gi);
+        const i64 node = big_node(a, lvl_end, gi);
         if (a.nseg_end[node] == 0) continue;  // no far-field work at this node
         const NodeGeo& g = a.geo[node & a.node_mask];
         const size_t rec = (size_t)a.slot[node] * a.NPT;
         const u32 present = a.cls_mask[a.slot[node]];
-        if (present == 8u) {
-            if (tid < 64) finish_class_wave(a, g, rec, 3, a.ref.vinvT + a.cls.qoff[3], w, nd);
+        if (present == 8u) {  // the one-class formula of k_far_finish_one
+            const int np = a.cls.np[3], poff = a.cls.poff[3], d = a.cls.deg[3];
+            for (int m = tid; m < np; m += 256) {
+                double y[3];
+                nd[m] = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
+                w[m][0] = a.alpha[(rec + poff + m) * 3];
+                w[m][1] = a.alpha[(rec + poff + m) * 3 + 1];
+                w[m][2] = a.alpha[(rec + poff + m) * 3 + 2];
+            }
+            __syncthreads();
+            block_matvec<256, 3>(a.ref.vinvT + a.cls.qoff[3], np, np, nd, w, red, co);
+            for (int k = tid; k < 3 * np; k += 256)
+                a.alpha[(rec + poff) * 3 + k] = a.ref.coef[poff + k / 3] * co[k / 3][k % 3];
             __syncthreads();
             continue;
         }
+
         const int np10 = a.cls.np[3], poff10 = a.cls.poff[3], d10 = a.cls.deg[3];
         for (int m = tid; m < np10; m += 256) v10[m][0] = v10[m][1] = v10[m][2] = 0.0;
         for (int c = 0; c < 4; ++c) {
@@ -1042,13 +1076,6 @@ __global__ __launch_bounds__(256) void k_far_finish_learned(EvalArgs a) {
 // and enter the FMAs as scalar operands, with only the node's lanes active.
 // Per-lane copies (from LDS) would cost 64 x 8 bytes of LDS return per
 // coefficient and wave, twice the FP64 work they feed.
-
-// i64 value of lane `src` (wave-uniform result)
-__device__ __forceinline__ i64 readlane64(i64 v, int src) {
-    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)v, src);
-    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)((u64)v >> 32), src);
-    return (i64)(((u64)hi << 32) | lo);
-}
 
 // class of degree D (point offset poff) at one level: `has` marks a
 // particle whose node nd at this level holds far-field coefficients
@@ -1356,13 +1383,8 @@ void launch_far_finish(hipStream_t s, const EvalArgs& a) {
         hipLaunchKernelGGL(k_far_finish_learned, dim3(grid), dim3(256), 0, s, a);
         return;
     }
-    // V^{-1} in LDS up to 66 points (degree 10: 34.8 KB, with the waves'
-    // rows 50 KB of the 64 KB a workgroup may take)
-    const int np = a.cls.np[0];
-    const int lds = np <= 66 ? 1 : 0;
-    const size_t bytes = lds ? (size_t)np * np * sizeof(double) : 0;
-    const unsigned grid = (unsigned)std::min<u32>(std::max<u32>((a.per_level + 3) / 4, 1u), 1024u);
-    hipLaunchKernelGGL(k_far_finish_one, dim3(grid), dim3(256), bytes, s, a, lds);
+    const unsigned grid = (unsigned)std::min<u32>(std::max<u32>(a.per_level, 1u), 2048u);
+    hipLaunchKernelGGL(k_far_finish_one, dim3(grid), dim3(256), 0, s, a);
 }
 
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate) {

@@ -417,14 +417,15 @@ __global__ __launch_bounds__(256) void k_upward_finish(int L, const u32* __restr
         for (int t = tid; t < NP * NP; t += 256) vl[t] = ref.vinv[t];
     }
     const double* __restrict__ V = LDS_V ? vl : ref.vinv;
-    u32 lvl_end[kMaxLevels + 1];
-    u32 total = 0;
-    for (int l = 0; l <= L; ++l) {
-        u32 nbl = flags[F_LEVEL + l];
-        if (nbl > per_level) nbl = per_level;
-        total += nbl;
-        lvl_end[l] = total;
-    }
+    // big nodes at levels <= l: the level counts loaded in parallel, then
+    // the prefix (LDS, so that no thread indexes a register array)
+    __shared__ u32 lvl_end[kMaxLevels + 1];
+    if (tid <= L) lvl_end[tid] = flags[F_LEVEL + tid] < per_level ? flags[F_LEVEL + tid] : per_level;
+    __syncthreads();
+    if (tid == 0)
+        for (int l = 1; l <= L; ++l) lvl_end[l] += lvl_end[l - 1];
+    __syncthreads();
+    const u32 total = lvl_end[L];
     const u32 n_batch = (total + R - 1) / R;
     for (u32 bj = blockIdx.x; bj < n_batch; bj += gridDim.x) {
         const u32 g0 = bj * R;
@@ -502,23 +503,27 @@ __global__ __launch_bounds__(256) void k_downsample(int L, int NB, const u32* __
                                                      const double* __restrict__ ref_points, const double* __restrict__ T,
                                                      ClassTab cls, int NPT, Prox* __restrict__ prox) {
     __shared__ double src[4][3][kMaxNp];
+    __shared__ u32 lvl_end[kMaxLevels + 1];  // big nodes at levels <= l
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const u32 lm = (1u << NB) - 1u;
     const int np10 = cls.np[3], poff10 = cls.poff[3];
     const int nout = cls.poff[3];  // points of classes 0..2
-    u32 total = 0;
-    for (int lvl = 0; lvl <= L; ++lvl) total += flags[F_LEVEL + lvl] < per_level ? flags[F_LEVEL + lvl] : per_level;
+    if (threadIdx.x == 0) {
+        u32 total = 0;
+        for (int lvl = 0; lvl <= L; ++lvl) {
+            total += flags[F_LEVEL + lvl] < per_level ? flags[F_LEVEL + lvl] : per_level;
+            lvl_end[lvl] = total;
+        }
+    }
+    __syncthreads();
+    const u32 total = lvl_end[L];
     for (u32 b0 = blockIdx.x * 4; b0 < total; b0 += gridDim.x * 4) {  // the same trip count in all waves
-        u32 bi = b0 + w;
+        const u32 bi = b0 + w;
         const bool ok = bi < total;
         int lvl = 0;
         if (ok)
-            for (; lvl <= L; ++lvl) {
-                const u32 nl = flags[F_LEVEL + lvl] < per_level ? flags[F_LEVEL + lvl] : per_level;
-                if (bi < nl) break;
-                bi -= nl;
-            }
-        const i64 node = ok ? big_list[(size_t)lvl * per_level + bi] : 0;
+            while (bi >= lvl_end[lvl]) ++lvl;
+        const i64 node = ok ? big_list[(size_t)lvl * per_level + (bi - (lvl > 0 ? lvl_end[lvl - 1] : 0u))] : 0;
         const NodeGeo& g = geo[node & lm];
         const size_t rec = ok ? (size_t)slot[node] * NPT : 0;
         for (int n = lane; n < np10 && ok; n += 64) {

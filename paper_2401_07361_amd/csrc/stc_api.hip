@@ -90,6 +90,10 @@ struct stc_ctx {
     double *rk_x = nullptr, *rk_z = nullptr, *rk_u = nullptr, *rk_xacc = nullptr, *rk_zacc = nullptr;
     // one captured RK4 step, replayed per step (key: the arguments it was captured for)
     hipStream_t cap_stream = nullptr;
+    // the upward pass runs here, concurrently with the traversal (they
+    // depend only on the tree build); ev_fork / ev_join order it
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t rk_exec = nullptr;
     i64 rk_n = -1;
     std::vector<i64> rk_offsets;
@@ -121,16 +125,20 @@ const char* kStatusText[] = {"ok", "invalid argument", "interaction list capacit
                              "workspace or scratch buffer too small or misaligned",
                              "non-finite particle position, vorticity or area"};
 
-// Records the event that opens `phase` (and closes the previous one) of the
-// evaluation being recorded.  Phase 6 closes the evaluation.
-// boundary b (0..6) starts phase b and ends phase b - 1; an event is
-// recorded only where a timed phase starts or ends (each event on the stream
-// costs a few microseconds between kernels)
-void mark(stc_ctx* c, int b) {
+// Phase timing of the evaluation being recorded: an event pair (begin, end)
+// per timed phase, recorded on the stream the phase runs on (phases may run
+// on two streams at once; each event on a stream costs a few microseconds
+// between kernels, so only the timed phases record).  The end of phase 5
+// closes the evaluation.
+void phase_begin(stc_ctx* c, int p) {
     if (c->t_max == 0 || c->t_used >= c->t_max) return;
-    const bool need = ((c->t_mask >> b) & 1u) || (b > 0 && ((c->t_mask >> (b - 1)) & 1u));
-    if (need) (void)hipEventRecord(c->tev[(size_t)c->t_used * 7 + b], c->stream);
-    if (b == 6) ++c->t_used;
+    if ((c->t_mask >> p) & 1u) (void)hipEventRecord(c->tev[(size_t)c->t_used * 12 + 2 * p], c->stream);
+}
+
+void phase_end(stc_ctx* c, int p) {
+    if (c->t_max == 0 || c->t_used >= c->t_max) return;
+    if ((c->t_mask >> p) & 1u) (void)hipEventRecord(c->tev[(size_t)c->t_used * 12 + 2 * p + 1], c->stream);
+    if (p == 5) ++c->t_used;
 }
 
 stc_status fail(stc_ctx* c, stc_status st, const std::string& msg) {
@@ -301,7 +309,7 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     c->have_tree = true;
     c->have_upward = false;
     c->have_lists = false;
-    mark(c, 0);
+    phase_begin(c, 0);
     {
         FillSet f{};
         f.add(c->flags, F_COUNT);
@@ -312,6 +320,7 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     }
     if (n == 0) {
         launch_fill_u32(s, reinterpret_cast<u32*>(c->ncnt), c->used_nodes, 0u);
+        phase_end(c, 0);
         return check_launch(c, "tree_build");
     }
     MemberOffsets mo{};
@@ -327,6 +336,7 @@ stc_status do_build(stc_ctx* c, int members, const i64* off, const double* d_x) 
     launch_node_counts(s, c->nbeg, c->nend, c->used_nodes, c->p.n_crit, c->NB, c->L, c->level_off, c->ncnt, c->slot,
                        c->slot_cap, c->big_list, c->per_level, c->item_node, c->item_chunk, c->item_base,
                        c->items_cap, c->flags);
+    phase_end(c, 0);
     return check_launch(c, "tree_build");
 }
 
@@ -359,7 +369,7 @@ ForcingDev forcing_dev(const stc_forcing& h, double t_base, const double* t_dev)
 stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area, bool stage_clock = false,
                      double t_off = 0.0) {
     hipStream_t s = c->stream;
-    mark(c, 1);
+    phase_begin(c, 1);
     ForcingDev f{};
     if (c->forcing_on)
         f = stage_clock ? forcing_dev(c->forcing, t_off, c->forcing_t) : forcing_dev(c->forcing, c->forcing.time, nullptr);
@@ -377,6 +387,7 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area, boo
     }
     if (c->learned && c->n > 0)
         launch_node_charge_sums(s, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->sq, c->qabs, c->qsum);
+    phase_end(c, 1);
     c->have_upward = true;
     return check_launch(c, "upward");
 }
@@ -434,7 +445,7 @@ TravArgs trav_args(stc_ctx* c, double theta, int dcf) {
 
 stc_status do_traverse(stc_ctx* c) {
     hipStream_t s = c->stream;
-    mark(c, 2);
+    phase_begin(c, 2);
     {
         // traversal counters and the segment tables of the sorted lists
         FillSet f{};
@@ -486,8 +497,56 @@ stc_status do_traverse(stc_ctx* c) {
                 {c->tseg_end, c->nseg_end},
                 2};
     launch_segments(s, sg, c->cap);
+    phase_end(c, 2);
     c->have_lists = true;
     return check_launch(c, "traverse");
+}
+
+// The context's side stream and its fork / join events, created on first use.
+stc_status side_ready(stc_ctx* c) {
+    if (!c->side_stream && hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->side_stream = nullptr;
+        return fail(c, STC_ERR_DEVICE, "creating the side stream failed");
+    }
+    if (!c->ev_fork && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        c->ev_fork = nullptr;
+        return fail(c, STC_ERR_DEVICE, "hipEventCreate failed");
+    }
+    if (!c->ev_join && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        c->ev_join = nullptr;
+        return fail(c, STC_ERR_DEVICE, "hipEventCreate failed");
+    }
+    return STC_OK;
+}
+
+// The upward pass and the traversal.  Both read only what the tree build
+// wrote (the traversal of the learned form also reads the node charge sums
+// of the upward pass), so outside the learned form the upward pass runs on
+// the context's side stream while the traversal runs on its stream, joined
+// before the evaluation (also under graph capture, where the fork and the
+// join become edges of the graph).
+stc_status do_upward_traverse(stc_ctx* c, const double* d_zeta, const double* d_area, bool stage_clock = false,
+                              double t_off = 0.0) {
+    if (c->learned || c->n == 0) {
+        stc_status st = do_upward(c, d_zeta, d_area, stage_clock, t_off);
+        if (st == STC_OK) st = do_traverse(c);
+        return st;
+    }
+    const stc_status sf = side_ready(c);
+    if (sf != STC_OK) return sf;
+    hipStream_t main = c->stream;
+    if (hipEventRecord(c->ev_fork, main) != hipSuccess || hipStreamWaitEvent(c->side_stream, c->ev_fork, 0) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "stream fork failed");
+    c->stream = c->side_stream;
+    stc_status st = do_upward(c, d_zeta, d_area, stage_clock, t_off);
+    c->stream = main;
+    // the join is recorded and waited on whatever happened, so that a
+    // capture stays well formed
+    const bool joined = hipEventRecord(c->ev_join, c->side_stream) == hipSuccess;
+    const stc_status st2 = do_traverse(c);
+    if (!joined || hipStreamWaitEvent(main, c->ev_join, 0) != hipSuccess)
+        return fail(c, STC_ERR_DEVICE, "stream join failed");
+    return st != STC_OK ? st : st2;
 }
 
 stc_status do_eval(stc_ctx* c, bool near, bool far, double* d_u, bool accumulate, bool stream = false) {
@@ -495,18 +554,22 @@ stc_status do_eval(stc_ctx* c, bool near, bool far, double* d_u, bool accumulate
     hipStream_t s = c->stream;
     EvalArgs a = eval_args(c);
     a.stream = stream ? 1 : 0;
-    launch_fill_f64(s, c->Wacc, 3 * c->n, 0.0);
     u32 mask = (near ? 1u : 0u) | (far ? 2u : 0u);
-    mark(c, 3);
+    // near side, then the target-proxy values and their coefficients.  Running the
+    // coefficients on the side stream beside k_near measured no faster: the two
+    // kernels share the chip and each stretches by the other's time.
+    phase_begin(c, 3);
     launch_near(s, a, mask);
-    mark(c, 4);
+    phase_end(c, 3);
     if (far) {
+        phase_begin(c, 4);
         launch_far_targets(s, a);
-        launch_far_finish(s, a);
+        phase_end(c, 4);
     }
-    mark(c, 5);
+    phase_begin(c, 5);
+    if (far) launch_far_finish(s, a);
     launch_l2p_finalize(s, a, far, d_u, accumulate);
-    mark(c, 6);
+    phase_end(c, 5);
     return check_launch(c, "eval");
 }
 
@@ -921,6 +984,12 @@ stc_status stc_destroy(stc_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     rk4_drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) {
+        (void)hipStreamSynchronize(c->side_stream);
+        (void)hipStreamDestroy(c->side_stream);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     delete c;
     return STC_OK;
@@ -991,8 +1060,7 @@ stc_status stc_velocity(stc_ctx* c, int64_t n, const double* d_x, const double* 
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
     const i64 off[2] = {0, n};
     stc_status st = do_build(c, 1, off, d_x);
-    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
-    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_upward_traverse(c, d_zeta, d_area);
     if (st == STC_OK) st = do_eval(c, true, true, d_u, false);
     return st;
 }
@@ -1006,8 +1074,7 @@ stc_status stc_velocity_batched(stc_ctx* c, int32_t members, const int64_t* h_of
                   !aligned8(d_u)))
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
     stc_status st = do_build(c, members, h_offsets, d_x);
-    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
-    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_upward_traverse(c, d_zeta, d_area);
     if (st == STC_OK) st = do_eval(c, true, true, d_u, false);
     return st;
 }
@@ -1095,8 +1162,7 @@ stc_status stc_stream_function(stc_ctx* c, int64_t n, const double* d_x, const d
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
     const i64 off[2] = {0, n};
     stc_status st = do_build(c, 1, off, d_x);
-    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
-    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_upward_traverse(c, d_zeta, d_area);
     if (st == STC_OK) st = do_eval(c, true, true, d_psi, false, true);
     return st;
 }
@@ -1111,8 +1177,7 @@ stc_status stc_stream_function_batched(stc_ctx* c, int32_t members, const int64_
                   !aligned8(d_area) || !aligned8(d_psi)))
         return fail(c, STC_ERR_INVALID_ARG, "NULL or misaligned pointer");
     stc_status st = do_build(c, members, h_offsets, d_x);
-    if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
-    if (st == STC_OK) st = do_traverse(c);
+    if (st == STC_OK) st = do_upward_traverse(c, d_zeta, d_area);
     if (st == STC_OK) st = do_eval(c, true, true, d_psi, false, true);
     return st;
 }
@@ -1132,8 +1197,7 @@ static stc_status rk4_enqueue_step(stc_ctx* c, int members, const i64* off, doub
     const double* zs = d_zeta;
     for (int stg = 0; stg < 4; ++stg) {
         stc_status st = do_build(c, members, off, xs);
-        if (st == STC_OK) st = do_upward(c, zs, d_area, true, stage_t[stg]);
-        if (st == STC_OK) st = do_traverse(c);
+        if (st == STC_OK) st = do_upward_traverse(c, zs, d_area, true, stage_t[stg]);
         if (st == STC_OK) st = do_eval(c, true, true, c->rk_u, false);
         if (st != STC_OK) return st;
         hipLaunchKernelGGL(k_rk4_combine, g, b, 0, s, (i64)n, d_x, d_zeta, c->rk_u, omega, cnext[stg], wacc[stg],
@@ -1754,7 +1818,7 @@ stc_status stc_set_timing_phases(stc_ctx* c, int32_t max_evals, uint32_t phase_m
     c->tev.clear();
     c->t_max = c->t_used = 0;
     if (max_evals == 0) return STC_OK;
-    c->tev.resize((size_t)max_evals * 7);
+    c->tev.resize((size_t)max_evals * 12);
     for (auto& e : c->tev)
         if (hipEventCreate(&e) != hipSuccess) {
             e = nullptr;
@@ -1773,7 +1837,7 @@ stc_status stc_phase_times(stc_ctx* c, double ms[6], int64_t* n_evals) {
         for (int p = 0; p < 6; ++p) {
             if (!((c->t_mask >> p) & 1u)) continue;
             float t = 0.f;
-            if (hipEventElapsedTime(&t, c->tev[(size_t)k * 7 + p], c->tev[(size_t)k * 7 + p + 1]) != hipSuccess)
+            if (hipEventElapsedTime(&t, c->tev[(size_t)k * 12 + 2 * p], c->tev[(size_t)k * 12 + 2 * p + 1]) != hipSuccess)
                 return fail(c, STC_ERR_DEVICE, "event timing failed (was every phase of the evaluation run?)");
             ms[p] += t;
         }
@@ -1826,8 +1890,7 @@ stc_status stc_velocity_graph(stc_ctx* c, int64_t n, const double* d_x, const do
     } else {
         const i64 off[2] = {0, n};
         st = do_build(c, 1, off, d_x);
-        if (st == STC_OK) st = do_upward(c, d_zeta, d_area);
-        if (st == STC_OK) st = do_traverse(c);
+        if (st == STC_OK) st = do_upward_traverse(c, d_zeta, d_area);
         if (st == STC_OK) st = do_eval(c, true, true, d_u, false);
         const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
         if (st == STC_OK && e != hipSuccess) st = fail(c, STC_ERR_DEVICE, "hipStreamEndCapture failed");
