@@ -235,6 +235,25 @@ __device__ __forceinline__ u32 logical_block() {
     return (b % 8u) * (G / 8u) + (b / 8u);
 }
 
+// Position in the list of workgroup b of a segment kernel.  The dispatcher
+// deals workgroups to the eight XCDs in turn (b runs on XCD b % 8); each XCD
+// takes runs of kXcdRun consecutive list chunks, the runs dealt to the XCDs
+// in turn, so that neighbouring chunks (which share sources) meet in one L2
+// while every XCD gets its share of each part of the list.  (Contiguous
+// eighths of the list per XCD, as logical_block gives, put the coarse levels'
+// target nodes, which come first and can carry several times the work of the
+// fine ones, on one XCD: 2.2 times the mean work there on the learned form's
+// far list at N = 2621442.)  A bijection of [0, G) for G a multiple of 8.
+constexpr u32 kXcdRun = 16;
+__device__ __forceinline__ u32 segment_block() {
+    const u32 G = gridDim.x, b = blockIdx.x;
+    if (G % 8u) return b;
+    const u32 q = b / 8u, x = b % 8u, Q = q / kXcdRun, j = q % kXcdRun;
+    const u32 full = (G / 8u) / kXcdRun;  // complete runs per XCD
+    const u32 run = Q < full ? kXcdRun : (G / 8u) - full * kXcdRun;
+    return Q * 8u * kXcdRun + x * run + j;
+}
+
 // Matrix-core form of the FP32 velocity kernel of the target proxies
 // (k_far_targets, |x - y|^2 denominator).  For a group of 16 target points x
 // and a chunk of 16 sources y (both relative to the target node's centre)
@@ -651,7 +670,7 @@ __device__ __forceinline__ void slice_sums(const double (*red)[3][NTT], int h, i
 __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int sh, u32& e, u32& e_hi) {
     const u32 G = gridDim.x;
     const u32 chunk = (n + G - 1) / G;
-    const u64 lo = (u64)logical_block() * chunk;
+    const u64 lo = (u64)segment_block() * chunk;
     if (lo >= n) return false;
     e = (u32)lo;
     e_hi = (u64)e + chunk < n ? e + chunk : n;
@@ -671,6 +690,202 @@ __device__ __forceinline__ void store_partials(SegShared<T, NTT, TP, false>& sh,
     for (int k = 0; k < TP; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) sh.u.red[k][c][tid] = act ? acc[k][c] : 0.0;
+}
+
+// The learned form's far segment of one target node in a single pass over
+// its entries, every degree class present at once (a pass per class would
+// repeat the segment's chain of dependent loads, its barriers and its slice
+// reduction for each class).  Class c with n_c sources in the segment takes
+// h_c = ceil(np_c / TP) target groups times S_c slices of the workgroup's
+// threads, S_c = 1 + floor((NTT - sum h) n_c / sum h n), and a region of K_c =
+// floor(2 NTT S_c / sum S) slots of every tile, filled with the class's next
+// K_c sources, so that every active thread sums about the same number of
+// sources in every tile.  With one class this is the fixed-degree pass:
+// S = floor(NTT / h), K = 2 NTT, the same staging, slices and sums.
+// (Every class fits at once: np <= 120 for d <= 14, so sum h <= 108 <= NTT.)
+struct LearnedSplit {
+    u32 src[4];   // sources of each class in the current entry batch
+    u32 tot[4];   // ... in the whole segment
+    u32 bp[4];    // first source of each class in the batch's prefix
+    int base[4], h[4], S[4], K[4], R[4];
+    int nout[5];  // exclusive prefix of the classes' 3 TP h reduction slots
+};
+
+// Entry batch [eb, eb + ne) of a learned far segment: sources per entry and
+// their prefix into sh, the batch's sources per class into sp.src / sp.bp
+// (entries are sorted by class).  Starts and ends with a barrier.
+template <typename T, int NTT, int TP>
+__device__ void learned_batch(const EvalArgs& a, u32 eb, u32 ne, SegShared<T, NTT, TP, false>& sh, LearnedSplit& sp) {
+    const int tid = threadIdx.x;
+    const u64 mask = ((u64)1 << a.W) - 1;
+    const u32 cmask = (1u << a.DB) - 1u;
+    if (tid < 4) sp.src[tid] = 0u;
+    __syncthreads();
+    u32 size = 0;
+    if ((u32)tid < ne) {
+        const u64 key = a.nlist[eb + tid];
+        const u32 s = (u32)(key & mask);
+        const int c = (int)((key >> (a.W + 1)) & cmask);
+        if (((key >> a.W) & 1u) == 0u) {  // CP: the particles of source node s
+            const i32 b = a.nbeg[s];
+            sh.ent_s[tid] = s;
+            sh.ent_first[tid] = b;
+            size = (u32)(a.nend[s] - b);
+        } else {  // CC: the proxy points of s's class-c record
+            sh.ent_s[tid] = (u32)a.slot[s] * (u32)a.NPT + (u32)STC_PICK4(a.cls.poff, c);
+            sh.ent_first[tid] = -1;
+            size = (u32)STC_PICK4(a.cls.np, c);
+        }
+        atomicAdd(&sp.src[c], size);
+    }
+    u32 total = 0;
+    const u32 pre = block_exclusive_scan<NTT>(size, sh.wave_tot, &total);
+    if ((u32)tid < ne) sh.ent_pre[tid] = pre;
+    if (tid == 0) {
+        sh.ent_pre[ne] = total;
+        u32 p = 0;
+        for (int c = 0; c < 4; ++c) {
+            sp.bp[c] = p;
+            p += sp.src[c];
+        }
+    }
+    __syncthreads();
+}
+
+// W(x~_m) of every class present in target node t's learned far segment
+// [e, se), written to the classes' records at rec; the classes present
+// (those with sources) go to cls_mask[slot].  Ends with a barrier.
+template <typename T, int DEN, int NTT, int TP>
+__device__ void learned_far_values(const EvalArgs& a, u32 e, u32 se, u32 t, size_t rec, double cx, double cy,
+                                   double cz, SegShared<T, NTT, TP, false>& sh) {
+    __shared__ LearnedSplit sp;
+    const int tid = threadIdx.x;
+    const double qscale = charge_scale<T, DEN>();
+    const u32 nseg = se - e;
+    learned_batch(a, e, nseg < (u32)NTT ? nseg : (u32)NTT, sh, sp);
+    if (tid < 4) sp.tot[tid] = sp.src[tid];
+    for (u32 eb = e + NTT; eb < se; eb += NTT) {  // a segment longer than one batch: its totals first
+        learned_batch(a, eb, (se - eb) < (u32)NTT ? (se - eb) : (u32)NTT, sh, sp);
+        if (tid < 4) sp.tot[tid] += sp.src[tid];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int H = 0;
+        u64 hw = 0;
+        for (int c = 0; c < 4; ++c) {
+            sp.h[c] = sp.tot[c] ? (STC_PICK4(a.cls.np, c) + TP - 1) / TP : 0;
+            H += sp.h[c];
+            hw += (u64)sp.h[c] * sp.tot[c];
+        }
+        int base = 0, sum_s = 0, no = 0;
+        for (int c = 0; c < 4; ++c) {
+            sp.S[c] = sp.h[c] ? 1 + (int)((u64)(NTT - H) * sp.tot[c] / hw) : 0;
+            sp.base[c] = base;
+            base += sp.h[c] * sp.S[c];
+            sum_s += sp.S[c];
+            sp.nout[c] = no;
+            no += 3 * TP * sp.h[c];
+        }
+        sp.nout[4] = no;
+        int R = 0;
+        for (int c = 0; c < 4; ++c) {
+            sp.K[c] = sp.S[c] ? (2 * NTT * sp.S[c]) / sum_s : 0;
+            sp.R[c] = R;
+            R += sp.K[c];
+        }
+    }
+    __syncthreads();
+    // this thread's class, target group ti and slice sl
+    int c = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (tid >= sp.base[k] && tid < sp.base[k] + sp.h[k] * sp.S[k]) c = k;
+    const bool act = c >= 0;
+    const int cc = act ? c : 0;
+    const int h = act ? sp.h[cc] : 1;
+    int ti;
+    const int sl = div_small(act ? tid - sp.base[cc] : 0, h, ti);
+    const int np = STC_PICK4(a.cls.np, cc);
+    const Prox* __restrict__ tp = a.prox + rec + STC_PICK4(a.cls.poff, cc);
+    T tx[TP], ty[TP], tz[TP];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) {
+        const int m = ti + k * h < np ? ti + k * h : ti;
+        const Prox pm = tp[act ? m : 0];
+        tx[k] = target_reg<T>(pm.x - cx);
+        ty[k] = target_reg<T>(pm.y - cy);
+        tz[k] = target_reg<T>(pm.z - cz);
+    }
+    double acc[TP][4];
+#pragma unroll
+    for (int k = 0; k < TP; ++k) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = 0.0;
+    for (u32 eb = e; eb < se; eb += NTT) {
+        const u32 ne = (se - eb) < (u32)NTT ? (se - eb) : (u32)NTT;
+        if (nseg > (u32)NTT) learned_batch(a, eb, ne, sh, sp);
+        int ntile = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (sp.K[k]) {
+                const int nt = (int)((sp.src[k] + (u32)sp.K[k] - 1u) / (u32)sp.K[k]);
+                ntile = nt > ntile ? nt : ntile;
+            }
+        for (int it = 0; it < ntile; ++it) {
+#pragma unroll
+            for (int l = 2 * tid; l < 2 * tid + 2; ++l) {
+                int rc = -1;  // the class region holding tile slot l
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (l >= sp.R[k] && l < sp.R[k] + sp.K[k]) rc = k;
+                if (rc < 0) continue;
+                const u32 off = (u32)it * (u32)sp.K[rc] + (u32)(l - sp.R[rc]);
+                if (off >= sp.src[rc]) continue;
+                const u32 g = sp.bp[rc] + off;  // the entry holding batch source g
+                u32 lo = 0, hi = ne;
+                while (hi - lo > 1) {
+                    const u32 mid = (lo + hi) >> 1;
+                    if (sh.ent_pre[mid] <= g) lo = mid;
+                    else hi = mid;
+                }
+                stage(sh, l,
+                      load_source<T>(a, sh.ent_s[lo], sh.ent_first[lo], (int)(g - sh.ent_pre[lo]), cx, cy, cz, qscale));
+            }
+            __syncthreads();
+            if (act) {
+                const u32 off = (u32)it * (u32)sp.K[c];
+                const int cnt = off < sp.src[c] ? ((sp.src[c] - off) < (u32)sp.K[c] ? (int)(sp.src[c] - off) : sp.K[c]) : 0;
+                if (cnt > 0)
+                    tile_sum_acc<T, DEN, false, TP>(sh.u.t.tile + sp.R[c], cnt, sl, sp.S[c], tx, ty, tz, nullptr, acc);
+            }
+            __syncthreads();
+        }
+    }
+    store_partials(sh, act, acc);
+    __syncthreads();
+    // slot o of class k4: (target group tj, component, target k of the
+    // group) as in slice_sums, slices added in order from zero
+    for (int o = tid; o < sp.nout[4]; o += NTT) {
+        int k4 = 0;
+        while (o >= sp.nout[k4 + 1]) ++k4;
+        const int hc = sp.h[k4], r0 = o - sp.nout[k4];
+        int k = 0;
+#pragma unroll
+        for (int j = 1; j < TP; ++j) k += r0 >= j * 3 * hc;
+        const int rem = r0 - k * 3 * hc;
+        const int comp = (rem >= hc) + (rem >= 2 * hc), tj = rem - comp * hc;
+        const int j = tj + k * hc;
+        if (j < STC_PICK4(a.cls.np, k4)) {
+            double sum = 0.0;
+            for (int q = 0; q < sp.S[k4]; ++q) sum += sh.u.red[k][comp][sp.base[k4] + q * hc + tj];
+            a.alpha[(rec + (size_t)STC_PICK4(a.cls.poff, k4) + j) * 3 + comp] = sum;
+        }
+    }
+    if (tid == 0) {
+        u32 present = 0;
+        for (int k = 0; k < 4; ++k)
+            if (sp.tot[k]) present |= 1u << k;
+        a.cls_mask[a.slot[t]] = present;
+    }
+    __syncthreads();
 }
 
 template <typename T, int DEN, int NT>
@@ -851,6 +1066,8 @@ __global__ __launch_bounds__(NTT) __attribute__((amdgpu_waves_per_eu((MF && !LEA
         };
         if constexpr (!LEARNED) {
             class_values(0, e, se);
+        } else if constexpr (!MF) {
+            learned_far_values<T, DEN, NTT, TP>(a, e, se, t, rec, cx, cy, cz, sh);
         } else {
             const u32 cmask = (1u << a.DB) - 1u;
             u32 present = 0;
