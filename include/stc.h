@@ -642,10 +642,10 @@ stc_status stc_reference_tables(int32_t degree, double* h_points, double* h_vinv
  * PC), 4 target-proxy interactions (one kernel: CP and CC, the values at the
  * target proxy points), 5 interpolation (the coefficients formed from those
  * values, the interpolation to particles) and output.
- * Outside the learned form phase 1 runs on the context's side stream while
- * phase 2 runs, so the phases of an evaluation need not add up to its
- * duration.  k = 0 turns
- * timing off and frees the events.  stc_phase_times synchronises and returns
+ * Phase 1 runs on the context's side stream while phase 2 runs (in the
+ * learned form until the gating, which waits for it), so the phases of an
+ * evaluation need not add up to its duration.  k = 0 turns timing off and
+ * frees the events.  stc_phase_times synchronises and returns
  * the summed milliseconds per phase over the recorded evaluations (ms[6]) and
  * their number; recording restarts afterwards.  Evaluations beyond k are not
  * recorded. */

@@ -666,11 +666,15 @@ __device__ __forceinline__ void slice_sums(const double (*red)[3][NTT], int h, i
 }
 
 // range of list entries of this workgroup (segments: key >> sh); returns
-// false if empty
+// false if empty.  spread: list chunks by segment_block (the far lists,
+// whose coarse target nodes carry more work), else by logical_block (the
+// near lists: target leaves of similar work, and neighbouring leaves, which
+// share sources, in one XCD's L2).
+template <bool SPREAD>
 __device__ __forceinline__ bool wg_range(u32 n, const u64* list, const i32* seg_end, int sh, u32& e, u32& e_hi) {
     const u32 G = gridDim.x;
     const u32 chunk = (n + G - 1) / G;
-    const u64 lo = (u64)segment_block() * chunk;
+    const u64 lo = (u64)(SPREAD ? segment_block() : logical_block()) * chunk;
     if (lo >= n) return false;
     e = (u32)lo;
     e_hi = (u64)e + chunk < n ? e + chunk : n;
@@ -896,7 +900,7 @@ __global__ __launch_bounds__(NT) void k_near(EvalArgs a, u32 type_mask) {
     if (n > a.cap) n = a.cap;
     u32 e, e_hi;
     const int shf = a.W + 1 + a.DB;
-    if (!wg_range(n, a.tlist, a.tseg_end, shf, e, e_hi)) return;
+    if (!wg_range<false>(n, a.tlist, a.tseg_end, shf, e, e_hi)) return;
     const bool rel = sizeof(T) == 4;  // FP32: coordinates relative to the target circumcentre
     while (e < e_hi) {
         const u32 t = (u32)(a.tlist[e] >> shf);
@@ -988,7 +992,7 @@ __global__ __launch_bounds__(NTT) __attribute__((amdgpu_waves_per_eu((MF && !LEA
     if (n > a.cap) n = a.cap;
     u32 e, e_hi;
     const int shf = a.W + 1 + a.DB;  // segments by target node (all classes)
-    if (!wg_range(n, a.nlist, a.nseg_end, shf, e, e_hi)) return;
+    if (!wg_range<true>(n, a.nlist, a.nseg_end, shf, e, e_hi)) return;
     const bool rel = sizeof(T) == 4;
     while (e < e_hi) {
         const u32 t = (u32)(a.nlist[e] >> shf);
@@ -1200,6 +1204,9 @@ __global__ __launch_bounds__(256) void k_far_finish_one(EvalArgs a) {
     }
 }
 
+// the learned form's classes: degrees 4, 6, 8 and 10, 15 + 28 + 45 + 66 points
+constexpr int kLearnedNpt = 154;
+
 // The learned form folds its classes into one degree-10 record: on the
 // sphere a degree-d polynomial in the barycentrics equals a degree-10 one
 // (times |V b|^(10 - d) = 1, d even), so the degree-10 interpolant through
@@ -1211,13 +1218,19 @@ __global__ __launch_bounds__(256) void k_far_finish_one(EvalArgs a) {
 // c_k sum_n (V_ref,10^{-1})_kn (sum over classes of v_n).  A node with
 // degree-10 work only takes the one-class formula of k_far_finish_one (the
 // same arithmetic, so without a network the learned context is bitwise the
-// method without gating).  One workgroup per node.
+// method without gating).  Other nodes take three steps with a barrier
+// each: the present classes' scaled values and the degree-10 points'
+// factors, then a thread per (lower class, degree-10 point) for the class's
+// part of v, then the product with the degree-10 table.  One workgroup per
+// node.
 __global__ __launch_bounds__(256) void k_far_finish_learned(EvalArgs a) {
     __shared__ double w[kMaxNp][3];
     __shared__ double nd[kMaxNp];
     __shared__ double co[kMaxNp][3];
     __shared__ double red[3 * 256];
     __shared__ double v10[kMaxNp][3];
+    __shared__ double xs[kLearnedNpt][3];
+    __shared__ double sc10[3][kMaxNp];
     __shared__ u32 lvl_end[kMaxLevels + 1];
     const int tid = threadIdx.x;
     const u32 total = big_node_table(a, lvl_end);
@@ -1244,37 +1257,59 @@ __global__ __launch_bounds__(256) void k_far_finish_learned(EvalArgs a) {
             continue;
         }
 
+        // every present class's scaled values |P_m|^d W(x~_m) at its record
+        // offsets, and the degree-10 points' factors |P10_n|^(10 - d) of the
+        // lower classes, in one pass over the node's points
         const int np10 = a.cls.np[3], poff10 = a.cls.poff[3], d10 = a.cls.deg[3];
-        for (int m = tid; m < np10; m += 256) v10[m][0] = v10[m][1] = v10[m][2] = 0.0;
-        for (int c = 0; c < 4; ++c) {
-            if (!((present >> c) & 1u)) continue;
-            const int np = STC_PICK4(a.cls.np, c), poff = STC_PICK4(a.cls.poff, c), d = STC_PICK4(a.cls.deg, c);
-            for (int m = tid; m < np; m += 256) {
-                double y[3];
-                nd[m] = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
-                w[m][0] = a.alpha[(rec + poff + m) * 3];
-                w[m][1] = a.alpha[(rec + poff + m) * 3 + 1];
-                w[m][2] = a.alpha[(rec + poff + m) * 3 + 2];
+        for (int i = tid; i < poff10 + np10; i += 256) {
+            const int c = (i >= a.cls.poff[1]) + (i >= a.cls.poff[2]) + (i >= poff10);
+            const bool here = (present >> c) & 1u;
+            if (!here && c < 3) continue;
+            double y[3];
+            const double r = proxy_point(g, a.ref.points + 3 * i, y);
+            if (here) {
+                const double f = ipow(r, STC_PICK4(a.cls.deg, c));
+#pragma unroll
+                for (int j = 0; j < 3; ++j) xs[i][j] = f * a.alpha[(rec + i) * 3 + j];
             }
-            __syncthreads();
-            if (c < 3) {
-                block_matvec<256, 3>(a.up_T + (size_t)poff * np10, np, np10, nd, w, red, co);
-                for (int m = tid; m < np10; m += 256) {
-                    double y[3];
-                    const double sc = ipow(proxy_point(g, a.ref.points + 3 * (poff10 + m), y), d10 - d);
-                    v10[m][0] += sc * co[m][0];
-                    v10[m][1] += sc * co[m][1];
-                    v10[m][2] += sc * co[m][2];
-                }
-            } else {
-                for (int m = tid; m < np10; m += 256) {
-                    v10[m][0] += nd[m] * w[m][0];
-                    v10[m][1] += nd[m] * w[m][1];
-                    v10[m][2] += nd[m] * w[m][2];
-                }
-            }
-            __syncthreads();
+            if (c == 3)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) sc10[k][i - poff10] = ipow(r, d10 - a.cls.deg[k]);
         }
+        __syncthreads();
+        // threads 66 k + n: class k's part of v10[n] (k < 3), the class's
+        // Lagrange basis at degree-10 point n times its scaled values
+        {
+            int n;
+            const int k = div_small(tid, np10, n);
+            double acc[3] = {0.0, 0.0, 0.0};
+            if (k < 3 && ((present >> k) & 1u)) {
+                const int np = STC_PICK4(a.cls.np, k), poff = STC_PICK4(a.cls.poff, k);
+                const double* __restrict__ T = a.up_T + (size_t)poff * np10 + n;
+#pragma unroll 4
+                for (int m = 0; m < np; ++m) {
+                    const double f = T[(size_t)m * np10];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) acc[j] += f * xs[poff + m][j];
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j) acc[j] *= sc10[k][n];
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) red[j * 256 + tid] = acc[j];
+        }
+        __syncthreads();
+        // v10 = the classes in order (absent ones add zero), degree 10 last
+        if (tid < np10) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                double v = 0.0;
+                for (int k = 0; k < 3; ++k) v += red[j * 256 + k * np10 + tid];
+                if (present & 8u) v += xs[poff10 + tid][j];
+                v10[tid][j] = v;
+            }
+        }
+        __syncthreads();
         block_matvec<256, 3>(a.up_H, np10, np10, nullptr, v10, red, co);
         for (int k = tid; k < 3 * np10; k += 256) a.alpha[(rec + poff10) * 3 + k] = co[k / 3][k % 3];
         __syncthreads();

@@ -94,6 +94,9 @@ struct stc_ctx {
     // depend only on the tree build); ev_fork / ev_join order it
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // set while the learned form's upward pass runs on side_stream: the
+    // gating waits on ev_join before it reads the node charges
+    bool gate_waits_upward = false;
     hipGraphExec_t rk_exec = nullptr;
     i64 rk_n = -1;
     std::vector<i64> rk_offsets;
@@ -471,6 +474,8 @@ stc_status do_traverse(stc_ctx* c) {
         launch_traverse_levels(s, tc, C_FRONT, true, c->cand);
         LearnedArgs la = learned_args(c);
         c->cand_view = c->cand;
+        if (c->gate_waits_upward && hipStreamWaitEvent(s, c->ev_join, 0) != hipSuccess)
+            return fail(c, STC_ERR_DEVICE, "stream join failed");
         if (c->model) {
             launch_features(s, la);
             launch_mlp_forward_list(s, la);
@@ -520,14 +525,14 @@ stc_status side_ready(stc_ctx* c) {
 }
 
 // The upward pass and the traversal.  Both read only what the tree build
-// wrote (the traversal of the learned form also reads the node charge sums
-// of the upward pass), so outside the learned form the upward pass runs on
-// the context's side stream while the traversal runs on its stream, joined
-// before the evaluation (also under graph capture, where the fork and the
-// join become edges of the graph).
+// wrote (in the learned form the gating after the candidate traversal also
+// reads the upward pass's charges), so the upward pass runs on the context's
+// side stream while the traversal runs on its stream, joined before the
+// learned gating and before the evaluation (also under graph capture, where
+// the fork and the join become edges of the graph).
 stc_status do_upward_traverse(stc_ctx* c, const double* d_zeta, const double* d_area, bool stage_clock = false,
                               double t_off = 0.0) {
-    if (c->learned || c->n == 0) {
+    if (c->n == 0) {
         stc_status st = do_upward(c, d_zeta, d_area, stage_clock, t_off);
         if (st == STC_OK) st = do_traverse(c);
         return st;
@@ -543,7 +548,11 @@ stc_status do_upward_traverse(stc_ctx* c, const double* d_zeta, const double* d_
     // the join is recorded and waited on whatever happened, so that a
     // capture stays well formed
     const bool joined = hipEventRecord(c->ev_join, c->side_stream) == hipSuccess;
+    // the learned form's candidate traversal needs only the tree build; its
+    // gating (features, network, resolve) waits for the upward pass
+    c->gate_waits_upward = c->learned && joined;
     const stc_status st2 = do_traverse(c);
+    c->gate_waits_upward = false;
     if (!joined || hipStreamWaitEvent(main, c->ev_join, 0) != hipSuccess)
         return fail(c, STC_ERR_DEVICE, "stream join failed");
     return st != STC_OK ? st : st2;
