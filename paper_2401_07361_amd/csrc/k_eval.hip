@@ -1135,7 +1135,7 @@ __device__ __forceinline__ i64 big_node(const EvalArgs& a, const u32* lvl_end, u
 // FMAs when its share of the rows is at most kFinPer (degree <= 10), so that
 // a node waits on one round of loads instead of a chain.
 constexpr int kFinPer = 22;
-__global__ __launch_bounds__(256) void k_far_finish_one(EvalArgs a) {
+__global__ __launch_bounds__(256) void k_far_finish_one_block(EvalArgs a) {
     __shared__ double w[kMaxNp][3];
     __shared__ double nd[kMaxNp];
     __shared__ double co[kMaxNp][3];
@@ -1204,6 +1204,173 @@ __global__ __launch_bounds__(256) void k_far_finish_one(EvalArgs a) {
     }
 }
 
+// LDS writes of a wave visible to its other lanes: a wave's LDS operations
+// execute in order, and the fences keep the compiler from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Output k of the one-class coefficient product (three components): the
+// rows summed in the groups of 256 / np rows that a 256-thread workgroup's
+// block_matvec forms, the groups added in order, so that the result is
+// bitwise that of k_far_finish_one_block.  Vt: V^-1 transposed (np x np,
+// [m][k]); nd, w: the node's scaled values.
+__device__ __forceinline__ void one_class_sums(const double* Vt, int np, const double* nd, const double (*w)[3],
+                                               int k, double* s) {
+    int rem;
+    const int G = div_small(256, np, rem);
+    const int per = div_small(np + G - 1, G, rem);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 1
+    for (int gg = 0; gg < G; ++gg) {
+        const int m0 = gg * per, m1 = (m0 + per) < np ? (m0 + per) : np;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+        for (int m = m0; m < m1; ++m) {
+            const double f = Vt[m * np + k] * nd[m];
+            a0 += f * w[m][0];
+            a1 += f * w[m][1];
+            a2 += f * w[m][2];
+        }
+        s0 += a0;
+        s1 += a1;
+        s2 += a2;
+    }
+    s[0] = s0;
+    s[1] = s1;
+    s[2] = s2;
+}
+
+// A node's scaled values at one point: |P_m|^d and W(x~_m) (32 bytes, read
+// by a wave's lanes together as two 16-byte broadcasts).
+struct alignas(16) NdW {
+    double nd, w[3];
+};
+
+// Every output of a node by one wave: lane l < h = ceil(np / 2) takes
+// outputs l and l + h, so that each row's broadcast inputs serve two outputs
+// (LDS issue, not arithmetic, bounds this product); the sums are
+// one_class_sums', times c_k.
+__device__ __forceinline__ void wave_one_class(const double* Vt, int np, const NdW* x, const double* coef,
+                                               double* alpha_rec) {
+    const int lane = threadIdx.x & 63;
+    const int h = (np + 1) >> 1;
+    if (lane >= h) return;
+    const int k0 = lane, k1 = lane + h;
+    const bool two = k1 < np;
+    int rem;
+    const int G = div_small(256, np, rem);
+    const int per = div_small(np + G - 1, G, rem);
+    double s[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll 1
+    for (int gg = 0; gg < G; ++gg) {
+        const int m0 = gg * per, m1 = (m0 + per) < np ? (m0 + per) : np;
+        double a[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+#pragma unroll 2
+        for (int m = m0; m < m1; ++m) {
+            const NdW xm = x[m];
+            const double f0 = Vt[m * np + k0] * xm.nd;
+            const double f1 = (two ? Vt[m * np + k1] : 0.0) * xm.nd;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[0][c] += f0 * xm.w[c];
+                a[1][c] += f1 * xm.w[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            s[0][c] += a[0][c];
+            s[1][c] += a[1][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) alpha_rec[3 * k0 + c] = coef[k0] * s[0][c];
+    if (two)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) alpha_rec[3 * k1 + c] = coef[k1] * s[1][c];
+}
+
+// The nodes with far-field work of workgroup range [c0, c0 + cnt) of the
+// big-node index space, fetched by one thread each (the chain node -> its
+// segment -> its slot -> its class mask is then paid once per chunk, not once
+// per node): node (-1: no far work), coefficient record and classes present.
+// Ends with a barrier.
+constexpr int kFinChunk = 512;
+struct FinNodes {
+    i64 node[kFinChunk];
+    u64 rec[kFinChunk];
+    u32 present[kFinChunk];
+};
+__device__ __forceinline__ void fin_fetch_nodes(const EvalArgs& a, const u32* lvl_end, u32 c0, u32 cnt, bool learned,
+                                                FinNodes& fn) {
+    const int tid = threadIdx.x;
+    for (u32 i = tid; i < cnt; i += blockDim.x) {
+        i64 node = big_node(a, lvl_end, c0 + i);
+        u64 rec = 0;
+        u32 present = 0;
+        if (a.nseg_end[node] == 0) {
+            node = -1;  // no far-field work at this node
+        } else {
+            const i32 sl = a.slot[node];
+            rec = (u64)sl * (u64)a.NPT;
+            present = learned ? a.cls_mask[sl] : 1u;
+        }
+        fn.node[i] = node;
+        fn.rec[i] = rec;
+        fn.present[i] = present;
+    }
+    __syncthreads();
+}
+
+// The coefficients of every target node of the far lists (the one-class
+// formula above) with V^-1 in LDS, read once per workgroup: a wave per node,
+// kFinWaves nodes of a workgroup at a time, the workgroup's nodes fetched a
+// chunk at a time (a workgroup per node read the 35 KB table from L2 for
+// every node and waited on the node's chain of loads).  Degree <= 10 (np <= 66); larger
+// degrees take k_far_finish_one_block.
+constexpr int kFinWaves = 8;
+constexpr int kFinNp = 66;
+__global__ __launch_bounds__(64 * kFinWaves) void k_far_finish_one(EvalArgs a) {
+    __shared__ double Vs[kFinNp * kFinNp];
+    __shared__ NdW xv[kFinWaves][kFinNp];
+    __shared__ FinNodes fn;
+    __shared__ u32 lvl_end[kMaxLevels + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wi = tid >> 6;
+    const int np = a.cls.np[0], poff = a.cls.poff[0], d = a.cls.deg[0];
+    const double* __restrict__ Vt = a.ref.vinvT + a.cls.qoff[0];
+#pragma unroll 9
+    for (int i = tid; i < np * np; i += 64 * kFinWaves) Vs[i] = Vt[i];
+    const u32 total = big_node_table(a, lvl_end);  // ends with a barrier
+    // this workgroup's contiguous range of the big nodes, in chunks
+    const u32 per = (total + gridDim.x - 1) / gridDim.x;
+    const u32 lo = blockIdx.x * per, hi = (lo + per) < total ? (lo + per) : total;
+    for (u32 c0 = lo; c0 < hi; c0 += kFinChunk) {
+        const u32 cnt = (hi - c0) < (u32)kFinChunk ? (hi - c0) : (u32)kFinChunk;
+        fin_fetch_nodes(a, lvl_end, c0, cnt, false, fn);
+        for (u32 j = wi; j < cnt; j += kFinWaves) {
+            const i64 node = fn.node[j];
+            if (node < 0) continue;
+            const NodeGeo& g = a.geo[node & a.node_mask];
+            const size_t rec = (size_t)fn.rec[j] + poff;
+            for (int m = lane; m < np; m += 64) {
+                double y[3];
+                NdW v;
+                v.nd = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
+                v.w[0] = a.alpha[(rec + m) * 3];
+                v.w[1] = a.alpha[(rec + m) * 3 + 1];
+                v.w[2] = a.alpha[(rec + m) * 3 + 2];
+                xv[wi][m] = v;
+            }
+            wave_lds_sync();
+            wave_one_class(Vs, np, xv[wi], a.ref.coef + poff, a.alpha + rec * 3);
+            wave_lds_sync();  // the next node's values replace these
+        }
+        __syncthreads();  // the next chunk replaces the node list
+    }
+}
+
 // the learned form's classes: degrees 4, 6, 8 and 10, 15 + 28 + 45 + 66 points
 constexpr int kLearnedNpt = 154;
 
@@ -1218,101 +1385,161 @@ constexpr int kLearnedNpt = 154;
 // c_k sum_n (V_ref,10^{-1})_kn (sum over classes of v_n).  A node with
 // degree-10 work only takes the one-class formula of k_far_finish_one (the
 // same arithmetic, so without a network the learned context is bitwise the
-// method without gating).  Other nodes take three steps with a barrier
-// each: the present classes' scaled values and the degree-10 points'
-// factors, then a thread per (lower class, degree-10 point) for the class's
-// part of v, then the product with the degree-10 table.  One workgroup per
-// node.
-__global__ __launch_bounds__(256) void k_far_finish_learned(EvalArgs a) {
-    __shared__ double w[kMaxNp][3];
-    __shared__ double nd[kMaxNp];
-    __shared__ double co[kMaxNp][3];
-    __shared__ double red[3 * 256];
-    __shared__ double v10[kMaxNp][3];
-    __shared__ double xs[kLearnedNpt][3];
-    __shared__ double sc10[3][kMaxNp];
+// method without gating).  The tables (up_T of the lower classes, up_H)
+// sit in LDS, read once per workgroup; the workgroup takes kFinBatch nodes
+// at a time: a thread per (node, point) for the present classes' scaled
+// values and the degree-10 points' factors, then a thread per (node,
+// degree-10 point) for v (classes in order), then a thread per (node, output)
+// for the product with up_H in the row groups of a 256-thread block_matvec.
+constexpr int kLearnedNlow = kLearnedNpt - kFinNp;  // points of the classes below degree 10 (88)
+constexpr int kFinBatch = 7;                         // nodes per round: 7 x 66 items fit 512 threads
+struct LearnedFinishLds {
+    double T[kLearnedNlow * kFinNp];  // up_T of classes 0..2: [poff_c + m][n]
+    double H[kFinNp * kFinNp];        // up_H: [n][k]
+    double xs[kFinBatch][kLearnedNpt][3];
+    double sc[kFinBatch][3][kFinNp];
+    double v10[kFinBatch][kFinNp][3];
+};
+
+__global__ __launch_bounds__(64 * kFinWaves) void k_far_finish_learned(EvalArgs a) {
+    __shared__ LearnedFinishLds sh;
+    __shared__ FinNodes fn;
     __shared__ u32 lvl_end[kMaxLevels + 1];
     const int tid = threadIdx.x;
-    const u32 total = big_node_table(a, lvl_end);
-    for (u32 gi = blockIdx.x; gi < total; gi += gridDim.x) {
-        const i64 node = big_node(a, lvl_end, gi);
-        if (a.nseg_end[node] == 0) continue;  // no far-field work at this node
-        const NodeGeo& g = a.geo[node & a.node_mask];
-        const size_t rec = (size_t)a.slot[node] * a.NPT;
-        const u32 present = a.cls_mask[a.slot[node]];
-        if (present == 8u) {  // the one-class formula of k_far_finish_one
-            const int np = a.cls.np[3], poff = a.cls.poff[3], d = a.cls.deg[3];
-            for (int m = tid; m < np; m += 256) {
-                double y[3];
-                nd[m] = ipow(proxy_point(g, a.ref.points + 3 * (poff + m), y), d);
-                w[m][0] = a.alpha[(rec + poff + m) * 3];
-                w[m][1] = a.alpha[(rec + poff + m) * 3 + 1];
-                w[m][2] = a.alpha[(rec + poff + m) * 3 + 2];
-            }
-            __syncthreads();
-            block_matvec<256, 3>(a.ref.vinvT + a.cls.qoff[3], np, np, nd, w, red, co);
-            for (int k = tid; k < 3 * np; k += 256)
-                a.alpha[(rec + poff) * 3 + k] = a.ref.coef[poff + k / 3] * co[k / 3][k % 3];
-            __syncthreads();
-            continue;
-        }
-
-        // every present class's scaled values |P_m|^d W(x~_m) at its record
-        // offsets, and the degree-10 points' factors |P10_n|^(10 - d) of the
-        // lower classes, in one pass over the node's points
-        const int np10 = a.cls.np[3], poff10 = a.cls.poff[3], d10 = a.cls.deg[3];
-        for (int i = tid; i < poff10 + np10; i += 256) {
-            const int c = (i >= a.cls.poff[1]) + (i >= a.cls.poff[2]) + (i >= poff10);
-            const bool here = (present >> c) & 1u;
-            if (!here && c < 3) continue;
-            double y[3];
-            const double r = proxy_point(g, a.ref.points + 3 * i, y);
-            if (here) {
-                const double f = ipow(r, STC_PICK4(a.cls.deg, c));
-#pragma unroll
-                for (int j = 0; j < 3; ++j) xs[i][j] = f * a.alpha[(rec + i) * 3 + j];
-            }
-            if (c == 3)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) sc10[k][i - poff10] = ipow(r, d10 - a.cls.deg[k]);
-        }
-        __syncthreads();
-        // threads 66 k + n: class k's part of v10[n] (k < 3), the class's
-        // Lagrange basis at degree-10 point n times its scaled values
-        {
-            int n;
-            const int k = div_small(tid, np10, n);
-            double acc[3] = {0.0, 0.0, 0.0};
-            if (k < 3 && ((present >> k) & 1u)) {
-                const int np = STC_PICK4(a.cls.np, k), poff = STC_PICK4(a.cls.poff, k);
-                const double* __restrict__ T = a.up_T + (size_t)poff * np10 + n;
-#pragma unroll 4
-                for (int m = 0; m < np; ++m) {
-                    const double f = T[(size_t)m * np10];
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) acc[j] += f * xs[poff + m][j];
+#pragma unroll 12
+    for (int i = tid; i < kLearnedNlow * kFinNp; i += 64 * kFinWaves) sh.T[i] = a.up_T[i];
+#pragma unroll 9
+    for (int i = tid; i < kFinNp * kFinNp; i += 64 * kFinWaves) sh.H[i] = a.up_H[i];
+    const u32 total = big_node_table(a, lvl_end);  // ends with a barrier
+    const int np10 = kFinNp, poff10 = kLearnedNlow, d10 = a.cls.deg[3];
+    // this thread's item of the two product steps: batch node ib, point or
+    // output n (ib >= kFinBatch: none).  (Two items per thread, as in
+    // wave_one_class, measured slower here: 231 of the 512 threads active.)
+    int n_it;
+    const int ib = div_small(tid, np10, n_it);
+    const u32 per = (total + gridDim.x - 1) / gridDim.x;  // this workgroup's range, in chunks
+    const u32 lo = blockIdx.x * per, hi = (lo + per) < total ? (lo + per) : total;
+    for (u32 c0 = lo; c0 < hi; c0 += kFinChunk) {
+        const u32 cnt = (hi - c0) < (u32)kFinChunk ? (hi - c0) : (u32)kFinChunk;
+        fin_fetch_nodes(a, lvl_end, c0, cnt, true, fn);
+        for (u32 g0 = 0; g0 < cnt; g0 += kFinBatch) {
+            // every (node, point) item of the batch's scaled values over the
+            // whole workgroup
+#pragma unroll 1
+            for (int it = tid; it < kFinBatch * kLearnedNpt; it += 64 * kFinWaves) {
+                int i;
+                const int b = div_small(it, kLearnedNpt, i);
+                if (g0 + b >= cnt) continue;
+                const i64 node = fn.node[g0 + b];
+                if (node < 0) continue;
+                const u32 present = fn.present[g0 + b];
+                const size_t rec = fn.rec[g0 + b];
+                const NodeGeo& g = a.geo[node & a.node_mask];
+                const int c = (i >= a.cls.poff[1]) + (i >= a.cls.poff[2]) + (i >= poff10);
+                double (*xs)[3] = sh.xs[b];
+                if (present == 8u) {  // the one-class formula: nd in sc[0], values in xs
+                    if (c < 3) continue;
+                    const int m = i - poff10;
+                    double y[3];
+                    sh.sc[b][0][m] = ipow(proxy_point(g, a.ref.points + 3 * i, y), d10);
+                    xs[m][0] = a.alpha[(rec + i) * 3];
+                    xs[m][1] = a.alpha[(rec + i) * 3 + 1];
+                    xs[m][2] = a.alpha[(rec + i) * 3 + 2];
+                    continue;
                 }
+                // every present class's |P_m|^d W(x~_m) at its record offsets,
+                // and the degree-10 points' |P10_n|^(10 - d) of the lower classes
+                const bool here = (present >> c) & 1u;
+                if (!here && c < 3) continue;
+                double y[3];
+                const double r = proxy_point(g, a.ref.points + 3 * i, y);
+                if (here) {
+                    const double f = ipow(r, STC_PICK4(a.cls.deg, c));
 #pragma unroll
-                for (int j = 0; j < 3; ++j) acc[j] *= sc10[k][n];
+                    for (int j = 0; j < 3; ++j) xs[i][j] = f * a.alpha[(rec + i) * 3 + j];
+                }
+                if (c == 3)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) sh.sc[b][k][i - poff10] = ipow(r, d10 - a.cls.deg[k]);
             }
-#pragma unroll
-            for (int j = 0; j < 3; ++j) red[j * 256 + tid] = acc[j];
-        }
-        __syncthreads();
-        // v10 = the classes in order (absent ones add zero), degree 10 last
-        if (tid < np10) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                double v = 0.0;
-                for (int k = 0; k < 3; ++k) v += red[j * 256 + k * np10 + tid];
-                if (present & 8u) v += xs[poff10 + tid][j];
-                v10[tid][j] = v;
+            __syncthreads();
+            // v10[ib][n] = the lower classes' parts in class order (the class's
+            // Lagrange basis at degree-10 point n times its scaled values, times
+            // the point's factor), then the degree-10 values
+            if (ib < kFinBatch && g0 + ib < cnt && fn.node[g0 + ib] >= 0 && fn.present[g0 + ib] != 8u) {
+                const u32 present = fn.present[g0 + ib];
+                const double (*xs)[3] = sh.xs[ib];
+                const int n = n_it;
+                double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll 1
+                for (int k = 0; k < 3; ++k) {
+                    if (!((present >> k) & 1u)) continue;
+                    const int np = STC_PICK4(a.cls.np, k), poff = STC_PICK4(a.cls.poff, k);
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+                    for (int m = 0; m < np; ++m) {
+                        const double f = sh.T[(poff + m) * np10 + n];
+                        a0 += f * xs[poff + m][0];
+                        a1 += f * xs[poff + m][1];
+                        a2 += f * xs[poff + m][2];
+                    }
+                    const double sk = sh.sc[ib][k][n];
+                    {
+#pragma clang fp contract(off)
+                        v0 += a0 * sk;
+                        v1 += a1 * sk;
+                        v2 += a2 * sk;
+                    }
+                }
+                if (present & 8u) {
+                    v0 += xs[poff10 + n][0];
+                    v1 += xs[poff10 + n][1];
+                    v2 += xs[poff10 + n][2];
+                }
+                sh.v10[ib][n][0] = v0;
+                sh.v10[ib][n][1] = v1;
+                sh.v10[ib][n][2] = v2;
             }
+            __syncthreads();
+            // output k = n_it of node ib: c_k (V_ref,10^{-1} v)_k with up_H in
+            // block_matvec's row groups, or the one-class formula
+            if (ib < kFinBatch && g0 + ib < cnt && fn.node[g0 + ib] >= 0) {
+                const int k = n_it;
+                const size_t out = (fn.rec[g0 + ib] + poff10 + k) * 3;
+                double sum[3];
+                if (fn.present[g0 + ib] == 8u) {
+                    one_class_sums(a.ref.vinvT + a.cls.qoff[3], np10, sh.sc[ib][0], sh.xs[ib], k, sum);
+                    const double ck = a.ref.coef[poff10 + k];
+                    a.alpha[out] = ck * sum[0];
+                    a.alpha[out + 1] = ck * sum[1];
+                    a.alpha[out + 2] = ck * sum[2];
+                } else {
+                    int rem;
+                    const int G = div_small(256, np10, rem);
+                    const int per = div_small(np10 + G - 1, G, rem);
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 1
+                    for (int gg = 0; gg < G; ++gg) {
+                        const int m0 = gg * per, m1 = (m0 + per) < np10 ? (m0 + per) : np10;
+                        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+                        for (int m = m0; m < m1; ++m) {
+                            const double f = sh.H[m * np10 + k];
+                            a0 += f * sh.v10[ib][m][0];
+                            a1 += f * sh.v10[ib][m][1];
+                            a2 += f * sh.v10[ib][m][2];
+                        }
+                        s0 += a0;
+                        s1 += a1;
+                        s2 += a2;
+                    }
+                    a.alpha[out] = s0;
+                    a.alpha[out + 1] = s1;
+                    a.alpha[out + 2] = s2;
+                }
+            }
+            __syncthreads();  // the next batch replaces these
         }
-        __syncthreads();
-        block_matvec<256, 3>(a.up_H, np10, np10, nullptr, v10, red, co);
-        for (int k = tid; k < 3 * np10; k += 256) a.alpha[(rec + poff10) * 3 + k] = co[k / 3][k % 3];
-        __syncthreads();
     }
 }
 
@@ -1630,13 +1857,17 @@ void launch_far_targets(hipStream_t s, const EvalArgs& a) {
 }
 
 void launch_far_finish(hipStream_t s, const EvalArgs& a) {
-    if (a.DB != 0) {
-        const unsigned grid = (unsigned)std::min<u32>(std::max<u32>(a.per_level, 1u), 2048u);
-        hipLaunchKernelGGL(k_far_finish_learned, dim3(grid), dim3(256), 0, s, a);
+    const u32 cus = (u32)std::max(a.cus, 1);
+    if (a.DB != 0) {  // 140 KB of LDS: one workgroup per CU
+        hipLaunchKernelGGL(k_far_finish_learned, dim3(cus), dim3(64 * kFinWaves), 0, s, a);
+        return;
+    }
+    if (a.cls.np[0] <= kFinNp) {  // 62 KB of LDS: two workgroups per CU
+        hipLaunchKernelGGL(k_far_finish_one, dim3(2 * cus), dim3(64 * kFinWaves), 0, s, a);
         return;
     }
     const unsigned grid = (unsigned)std::min<u32>(std::max<u32>(a.per_level, 1u), 2048u);
-    hipLaunchKernelGGL(k_far_finish_one, dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_far_finish_one_block, dim3(grid), dim3(256), 0, s, a);
 }
 
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate) {

@@ -494,20 +494,28 @@ __global__ __launch_bounds__(256) void k_upward_finish(int L, const u32* __restr
 // barycentrics b, and T_nm = sum_k (V_ref,d^{-1})_km B_k(b_10,n) a fixed
 // reference matrix (the multinomial-scaled basis is homogeneous of degree d,
 // so the node's geometry enters only through |P|), stored [n][m] so that the
-// lanes (one output m each) read consecutive entries.  One wave per node,
-// all levels' nodes in one index space.
+// lanes (one output m each) read consecutive entries.  The table sits in
+// LDS, read once per workgroup (every node reading its 46 KB from L2 cost
+// more than the arithmetic); one wave per node, each wave walking its own
+// nodes, all levels' nodes in one index space.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_downsample(int L, int NB, const u32* __restrict__ flags,
-                                                     const i32* __restrict__ big_list, u32 per_level,
-                                                     const NodeGeo* __restrict__ geo, const i32* __restrict__ slot,
-                                                     const double* __restrict__ ref_points, const double* __restrict__ T,
-                                                     ClassTab cls, int NPT, Prox* __restrict__ prox) {
-    __shared__ double src[4][3][kMaxNp];
+constexpr int kDsWaves = 8;
+constexpr int kDsTable = 66 * 88;  // degree 10 -> degrees 4, 6, 8: 66 inputs x 88 outputs
+__global__ __launch_bounds__(64 * kDsWaves) void k_downsample(int L, int NB, const u32* __restrict__ flags,
+                                                              const i32* __restrict__ big_list, u32 per_level,
+                                                              const NodeGeo* __restrict__ geo,
+                                                              const i32* __restrict__ slot,
+                                                              const double* __restrict__ ref_points,
+                                                              const double* __restrict__ T, ClassTab cls, int NPT,
+                                                              Prox* __restrict__ prox) {
+    __shared__ double Ts[kDsTable];
+    __shared__ double src[kDsWaves][3][kMaxNp];
     __shared__ u32 lvl_end[kMaxLevels + 1];  // big nodes at levels <= l
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const u32 lm = (1u << NB) - 1u;
     const int np10 = cls.np[3], poff10 = cls.poff[3];
     const int nout = cls.poff[3];  // points of classes 0..2
+    for (int i = threadIdx.x; i < np10 * nout; i += 64 * kDsWaves) Ts[i] = T[i];
     if (threadIdx.x == 0) {
         u32 total = 0;
         for (int lvl = 0; lvl <= L; ++lvl) {
@@ -517,26 +525,27 @@ __global__ __launch_bounds__(256) void k_downsample(int L, int NB, const u32* __
     }
     __syncthreads();
     const u32 total = lvl_end[L];
-    for (u32 b0 = blockIdx.x * 4; b0 < total; b0 += gridDim.x * 4) {  // the same trip count in all waves
-        const u32 bi = b0 + w;
-        const bool ok = bi < total;
+    // each wave its own nodes; a wave's LDS rows are its own, so it waits
+    // only on itself
+    for (u32 bi = blockIdx.x * kDsWaves + w; bi < total; bi += gridDim.x * kDsWaves) {
         int lvl = 0;
-        if (ok)
-            while (bi >= lvl_end[lvl]) ++lvl;
-        const i64 node = ok ? big_list[(size_t)lvl * per_level + (bi - (lvl > 0 ? lvl_end[lvl - 1] : 0u))] : 0;
+        while (bi >= lvl_end[lvl]) ++lvl;
+        const i64 node = big_list[(size_t)lvl * per_level + (bi - (lvl > 0 ? lvl_end[lvl - 1] : 0u))];
         const NodeGeo& g = geo[node & lm];
-        const size_t rec = ok ? (size_t)slot[node] * NPT : 0;
-        for (int n = lane; n < np10 && ok; n += 64) {
+        const size_t rec = (size_t)slot[node] * NPT;
+        for (int n = lane; n < np10; n += 64) {
             double y[3];
             const double nrm = proxy_point(g, ref_points + 3 * (poff10 + n), y);
             const double w10 = prox[rec + poff10 + n].w;
             for (int c = 0; c < 3; ++c) src[w][c][n] = w10 / ipow(nrm, cls.deg[c]);
         }
-        __syncthreads();
-        for (int o = lane; o < nout && ok; o += 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int o = lane; o < nout; o += 64) {
             const int c = o < cls.poff[1] ? 0 : (o < cls.poff[2] ? 1 : 2);
             double acc = 0.0;
-            for (int n = 0; n < np10; ++n) acc += T[(size_t)n * nout + o] * src[w][c][n];
+            for (int n = 0; n < np10; ++n) acc += Ts[n * nout + o] * src[w][c][n];
             double y[3];
             const double nrm = proxy_point(g, ref_points + 3 * o, y);
             Prox pr;
@@ -546,7 +555,9 @@ __global__ __launch_bounds__(256) void k_downsample(int L, int NB, const u32* __
             pr.w = ipow(nrm, cls.deg[c]) * acc;
             prox[rec + o] = pr;
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -948,10 +959,13 @@ void launch_upward(hipStream_t s, int L, int NB, const u32* flags, const i32* bi
 
 void launch_downsample(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
                        const NodeGeo* geo, const i32* slot, const double* ref_points, const double* T, ClassTab cls,
-                       int NPT, Prox* prox) {
-    const unsigned grid = (unsigned)std::min<u32>(std::max<u32>((per_level + 3) / 4, 1u), 2048u);
-    hipLaunchKernelGGL(k_downsample, dim3(grid), dim3(256), 0, s, L, NB, flags, big_list, per_level, geo, slot,
-                       ref_points, T, cls, NPT, prox);
+                       int NPT, Prox* prox, int cus) {
+    // the learned form's classes are degrees 4, 6, 8 and 10 (stc_create), so
+    // the table is 66 x 88; 69 KB of LDS: two workgroups per CU
+    const u32 want = std::max<u32>((per_level + kDsWaves - 1) / kDsWaves, 1u);
+    const unsigned grid = (unsigned)std::min<u32>(want, (u32)(2 * std::max(cus, 1)));
+    hipLaunchKernelGGL(k_downsample, dim3(grid), dim3(64 * kDsWaves), 0, s, L, NB, flags, big_list, per_level, geo,
+                       slot, ref_points, T, cls, NPT, prox);
 }
 
 void launch_fill_u32(hipStream_t s, u32* p, i64 n, u32 v) {

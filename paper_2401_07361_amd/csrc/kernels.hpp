@@ -52,7 +52,7 @@ void launch_upward(hipStream_t s, int L, int NB, const u32* flags, const i32* bi
                    Prox* prox);
 void launch_downsample(hipStream_t s, int L, int NB, const u32* flags, const i32* big_list, u32 per_level,
                        const NodeGeo* geo, const i32* slot, const double* ref_points, const double* T, ClassTab cls,
-                       int NPT, Prox* prox);
+                       int NPT, Prox* prox, int cus);
 void launch_node_counts(hipStream_t s, const i32* nbeg, const i32* nend, i64 n_nodes, int n_crit, int NB, int L,
                         const i64* level_off_dev, i32* ncnt, i32* slot, u32 slot_cap, i32* big_list, u32 per_level,
                         i32* item_node, i32* item_chunk, i32* item_base, u32 items_cap, u32* flags);
@@ -151,6 +151,7 @@ struct EvalArgs {
     // learned form's degree classes present at each target node (by slot)
     const i32* big_list;
     u32 per_level;
+    int cus;  // compute units of the device (workgroups of the one-per-CU finish kernels)
     u32* cls_mask;
 };
 

@@ -265,6 +265,7 @@ EvalArgs eval_args(stc_ctx* c) {
     a.up_H = c->up_H;
     a.big_list = c->big_list;
     a.per_level = c->per_level;
+    a.cus = c->cus;
     a.cls_mask = c->cls_mask;
     return a;
 }
@@ -386,7 +387,7 @@ stc_status do_upward(stc_ctx* c, const double* d_zeta, const double* d_area, boo
                       ref_dev(c, top), c->NPT, c->cls.poff[top], c->slot, c->prox);
         if (top > 0)
             launch_downsample(s, c->L, c->NB, c->flags, c->big_list, c->per_level, c->geo, c->slot, c->ref_points,
-                              c->ref_T, c->cls, c->NPT, c->prox);
+                              c->ref_T, c->cls, c->NPT, c->prox, c->cus);
     }
     if (c->learned && c->n > 0)
         launch_node_charge_sums(s, c->nbeg, c->nend, c->level_off_host.data(), c->L, c->sq, c->qabs, c->qsum);
