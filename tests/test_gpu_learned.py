@@ -277,25 +277,26 @@ def _ms_per_eval(ctx, xd, zd, ad, reps=5):
 
 
 def test_trained_gate_gains_over_fixed_degree(stc_lib):
-    """The learned form end to end: samples labelled by the tree code's own
-    measured pair errors at N = 163842 (six seeded inputs), GPU training and
-    calibration, then the evaluation at N = 2621442 (Gaussian vortex pair on
-    a Rossby-Haurwitz background): rel-L2 error <= 1e-6 against the FP64
+    """The learned form end to end, trained as configured: 2e6 samples
+    labelled by the tree code's own measured pair errors at N = 163842
+    (seeded inputs taken until that many), GPU training and calibration,
+    then the evaluation at N = 2621442 (Gaussian vortex pair on a
+    Rossby-Haurwitz background): rel-L2 error <= 1e-6 against the FP64
     direct sum on 4096 seeded targets, within 1e-6 of the fixed-degree-10
     FP64 tree (the judge), and fewer kernel evaluations than both that tree
     and the fastest fixed-degree FP32 setting that meets 1e-6 on this input
     (theta 0.8, d = 10).  Wall-clock time of the learned form and of that
-    FP32 setting is measured and reported; the learned form is not required
-    to be faster (its gating, lower-degree upward pass and second traversal
-    cost about as much as the evaluations it saves)."""
+    FP32 setting is measured (best of three rounds of five evaluations,
+    alternating) and reported; the learned form must not be slower."""
     from paper_2401_07361_amd import gate_training as G
     from oracle import metrics
-    inputs = []
-    for k in range(6):
-        x, z, a = S.make_gate_training_input(k)
-        inputs.append((dev(x), dev(z), dev(a)))
-    F, Y = G.collect(inputs, 3e-8, theta=0.7, theta_max=0.9, log=say)
-    del inputs
+
+    def inputs():
+        for k in range(64):
+            x, z, a = S.make_gate_training_input(k)
+            yield dev(x), dev(z), dev(a)
+
+    F, Y = G.collect(inputs(), 3e-8, theta=0.7, theta_max=0.9, log=say, max_samples=2_000_000)
     params, losses = G.train(F, Y, epochs=8, batch=4096, lr=2e-3)
     ln = losses.cpu().numpy()
     say(f"  {F.shape[0]} samples, loss {ln[0]:.3f} -> {ln[-50:].mean():.3f}")
@@ -316,12 +317,14 @@ def test_trained_gate_gains_over_fixed_degree(stc_lib):
     ul = ctx.velocity(xd, zd, ad).cpu().numpy()
     _, el = ctx.list_counts()
     cls = {k: np.bincount(ctx.copy_list_classes(k), minlength=4).tolist() for k in ("PC", "CP", "CC")}
-    ms_learned = _ms_per_eval(ctx, xd, zd, ad)
-    ctx.close()
     fixed = stc_lib.Context(n, theta=0.8, degree=10, n_crit=64, precision="fp32", denominator="dist2")
     uf = fixed.velocity(xd, zd, ad).cpu().numpy()
     _, ef = fixed.list_counts()
-    ms_fixed = _ms_per_eval(fixed, xd, zd, ad)
+    ms_learned, ms_fixed = float("inf"), float("inf")
+    for _ in range(3):
+        ms_learned = min(ms_learned, _ms_per_eval(ctx, xd, zd, ad))
+        ms_fixed = min(ms_fixed, _ms_per_eval(fixed, xd, zd, ad))
+    ctx.close()
     fixed.close()
     e_fixed = metrics.rel_l2_velocity(uf[sub], ud, a[sub])
     e_direct = metrics.rel_l2_velocity(ul[sub], ud, a[sub])
@@ -337,6 +340,7 @@ def test_trained_gate_gains_over_fixed_degree(stc_lib):
     assert sum(el.values()) < 0.6 * sum(ej.values())
     assert sum(el.values()) < 0.7 * sum(ef.values())
     assert sum(1 for c in cls["CC"] if c > 0) >= 3   # the network uses several degrees
+    assert ms_learned < ms_fixed
 
 
 def test_learned_arguments_are_checked(stc_lib):
