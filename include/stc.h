@@ -478,8 +478,10 @@ stc_status stc_forcing_field(void* hip_stream, const stc_forcing* f, int64_t n, 
  * particles:  [n_t > n_crit], [n_s > n_crit] (1 or 0), level_t / 8, level_s / 8, r_t/R,
  * r_s/R, (r_t + r_s)/R, -log10 R / 2, log10(Q_s/Q)/8 + 1, |sum_s q|/Q_s,
  * log10(|w_s^(4)|_1 / Q_s)/2 (degree-4 proxy charges; 0 for a small source),
- * log10(Q_t/Q)/8 + 1.  Training loss per row: BCE(o0, y0) + y0 sum_k BCE(o_k,
- * y_k) (labels y: accept, then the three ordinal targets).  */
+ * log10(Q_t/Q)/8 + 1.  Training loss per row: a(y0) BCE(o0, y0) + y0 sum_k
+ * h(y_k) BCE(o_k, y_k) (labels y: accept, then the three ordinal targets;
+ * a(0) = 8, a(1) = 1, h(1) = 8, h(0) = 1: accepting a reject-labelled pair
+ * and choosing a degree below the labelled one weigh eight times).  */
 
 /* The BF16 parameters the traversal of a learned context uses (device
  * pointer, 16-byte aligned, kept until replaced; NULL rejects every candidate,

@@ -5,9 +5,15 @@ Parameters are one flat vector of 5252 values: W1 [12][64] (input f to hidden
 h), b1 [64], W2 [64][64], b2 [64], W3 [64][4], b3 [4].  Outputs: o0 the
 acceptance logit, o1..o3 ordinal logits (degree above 4, 6, 8).  Loss per
 row, averaged over the batch:
-    BCE(o0, y0) + y0 * sum_{k=1..3} BCE(o_k, y_k),
+    a(y0) BCE(o0, y0) + y0 * sum_{k=1..3} h(y_k) BCE(o_k, y_k),
 BCE(o, y) = max(o, 0) - o y + log(1 + exp(-|o|)) (logits), so the ordinal
-targets count only where the pair is acceptable.
+targets count only where the pair is acceptable.  The two costly mistakes,
+accepting a pair labelled reject and choosing a degree below the labelled
+one, weigh W_REJECT and W_HIGHER times the others: a(0) = W_REJECT,
+a(1) = 1, h(1) = W_HIGHER, h(0) = 1.  A constant network's best logits then
+sit ln W lower (acceptance) and higher (ordinals) than the labels' log-odds,
+so the trained network's own decisions lean to the safe side and the bias
+shifts of the calibration after training stay small.
 
 Everything is FP64.  `act_round`, when given, is applied to the hidden
 activations and to the back-propagated pre-activation gradients, the places
@@ -69,14 +75,24 @@ def forward(theta, x, act_round=None):
     return o, dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2)
 
 
+W_REJECT = 8.0
+W_HIGHER = 8.0
+
+
 def bce(o, y):
     return np.maximum(o, 0.0) - o * y + np.log1p(np.exp(-np.abs(o)))
+
+
+def _weights(y):
+    """Per-row weight of the acceptance term and per-row, per-ordinal weights."""
+    return 1.0 + (W_REJECT - 1.0) * (1.0 - y[:, 0]), 1.0 + (W_HIGHER - 1.0) * y[:, 1:]
 
 
 def loss(theta, x, y, act_round=None):
     o, _ = forward(theta, x, act_round)
     y = np.asarray(y, dtype=np.float64)
-    per = bce(o[:, 0], y[:, 0]) + y[:, 0] * bce(o[:, 1:], y[:, 1:]).sum(1)
+    wa, wo = _weights(y)
+    per = wa * bce(o[:, 0], y[:, 0]) + y[:, 0] * (wo * bce(o[:, 1:], y[:, 1:])).sum(1)
     return float(per.mean())
 
 
@@ -92,9 +108,10 @@ def grad(theta, x, y, act_round=None):
     y = np.asarray(y, dtype=np.float64)
     n = len(o)
     r = act_round if act_round is not None else (lambda v: v)
+    wa, wo = _weights(y)
     d3 = np.empty_like(o)
-    d3[:, 0] = (_sigmoid(o[:, 0]) - y[:, 0]) / n
-    d3[:, 1:] = y[:, :1] * (_sigmoid(o[:, 1:]) - y[:, 1:]) / n
+    d3[:, 0] = wa * (_sigmoid(o[:, 0]) - y[:, 0]) / n
+    d3[:, 1:] = y[:, :1] * wo * (_sigmoid(o[:, 1:]) - y[:, 1:]) / n
     d3r = r(d3)
     g = {"W3": c["h2"].T @ d3r, "b3": d3.sum(0)}
     d2 = (d3r @ p["W3"].T) * (c["z2"] > 0)

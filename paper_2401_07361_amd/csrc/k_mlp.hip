@@ -16,8 +16,12 @@
 // registers in the forward pass.  Weight gradients contract over samples;
 // their operands are staged through LDS in [unit][sample] order.
 //
-// Loss (per sample, mean over the batch): BCE(o0, y0) + y0 * sum_k BCE(o_k,
-// y_k), k = 1..3 -- the ordinal targets count only for accepted samples.
+// Loss (per sample, mean over the batch): a(y0) BCE(o0, y0) + y0 * sum_k
+// h(y_k) BCE(o_k, y_k), k = 1..3 -- the ordinal targets count only for
+// accepted samples; the costly mistakes weigh more: a sample labelled reject
+// kWReject times in the acceptance term, a "degree above" target kWHigher
+// times in its ordinal term (the network's own decisions then lean to the
+// safe side, and the calibration after training moves the biases less).
 #include <algorithm>
 #include <cmath>
 
@@ -180,6 +184,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const u16* __restrict__ X, 
 
 __device__ __forceinline__ float sigmoid(float o) { return 1.f / (1.f + __expf(-o)); }
 
+constexpr float kWReject = 8.f;  // weight of a reject-labelled sample's acceptance term
+constexpr float kWHigher = 8.f;  // weight of a "degree above" ordinal target
+
 // BCE with logits: max(o, 0) - o y + log(1 + exp(-|o|))
 __device__ __forceinline__ float bce(float o, float y) { return fmaxf(o, 0.f) - o * y + log1pf(__expf(-fabsf(o))); }
 
@@ -264,12 +271,14 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const u16* __restrict__ X, con
         if (ok && g == 0) {
             const float4 y = *reinterpret_cast<const float4*>(Y + row * 4);
             const float yv[4] = {y.x, y.y, y.z, y.w};
-            loss += bce(z3[0], yv[0]);
-            d3[0] = (sigmoid(z3[0]) - yv[0]) * inv_b;
+            const float wa = 1.f + (kWReject - 1.f) * (1.f - yv[0]);
+            loss += wa * bce(z3[0], yv[0]);
+            d3[0] = wa * (sigmoid(z3[0]) - yv[0]) * inv_b;
 #pragma unroll
             for (int k = 1; k < 4; ++k) {
-                loss += yv[0] * bce(z3[k], yv[k]);
-                d3[k] = yv[0] * (sigmoid(z3[k]) - yv[k]) * inv_b;
+                const float wo = 1.f + (kWHigher - 1.f) * yv[k];
+                loss += yv[0] * wo * bce(z3[k], yv[k]);
+                d3[k] = yv[0] * wo * (sigmoid(z3[k]) - yv[k]) * inv_b;
             }
         }
         gb3 += d3;

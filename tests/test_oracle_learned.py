@@ -44,12 +44,43 @@ def test_loss_and_output_bias_gradient_closed_form():
     x, y = _data(10, 2)
     sig = 1 / (1 + np.exp(-b3))
     soft = np.log1p(np.exp(b3))            # BCE(o, y) = log(1 + e^o) - o y
-    want = np.mean([soft[0] - b3[0] * r[0] + r[0] * sum(soft[k] - b3[k] * r[k] for k in (1, 2, 3)) for r in y])
+    wr, wh = mlp.W_REJECT, mlp.W_HIGHER
+
+    def row(r):                            # reject rows weigh wr, "higher degree" targets wh
+        a = wr if r[0] == 0 else 1.0
+        return a * (soft[0] - b3[0] * r[0]) + r[0] * sum((wh if r[k] == 1 else 1.0) * (soft[k] - b3[k] * r[k])
+                                                          for k in (1, 2, 3))
+    want = np.mean([row(r) for r in y])
     assert abs(mlp.loss(th, x, y) - want) < 1e-14
     g = mlp.unpack(mlp.grad(th, x, y))["b3"]
-    assert abs(g[0] - np.mean(sig[0] - y[:, 0])) < 1e-14
+    assert abs(g[0] - np.mean(np.where(y[:, 0] == 0, wr, 1.0) * (sig[0] - y[:, 0]))) < 1e-14
     for k in (1, 2, 3):
-        assert abs(g[k] - np.mean(y[:, 0] * (sig[k] - y[:, k]))) < 1e-14
+        assert abs(g[k] - np.mean(y[:, 0] * np.where(y[:, k] == 1, wh, 1.0) * (sig[k] - y[:, k]))) < 1e-14
+
+
+def test_weighted_optimum_of_a_constant_network():
+    # all weights zero: the loss is minimised over b3 where its gradient
+    # vanishes, at the labels' log-odds with the reject rows (acceptance) and
+    # the "higher degree" targets among accepted rows (ordinals) counted
+    # W_REJECT and W_HIGHER times: o0 = ln(n1 / (W_REJECT n0)),
+    # ok = ln(W_HIGHER m1 / m0)
+    x, y = _data(60, 7)
+    n1, n0 = y[:, 0].sum(), (1 - y[:, 0]).sum()
+    acc = y[:, 0] == 1
+    b3 = np.empty(4)
+    b3[0] = np.log(n1 / (mlp.W_REJECT * n0))
+    for k in (1, 2, 3):
+        m1, m0 = y[acc, k].sum(), (1 - y[acc, k]).sum()
+        b3[k] = np.log(mlp.W_HIGHER * m1 / m0)
+    th = mlp.pack({"W1": np.zeros((12, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+                   "W3": np.zeros((64, 4)), "b3": b3})
+    g = mlp.unpack(mlp.grad(th, x, y))["b3"]
+    assert np.abs(g).max() < 1e-14
+    # the unweighted log-odds are not the optimum: the weights move it by ln W
+    b3[0] += np.log(mlp.W_REJECT)
+    th2 = mlp.pack({"W1": np.zeros((12, 64)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+                    "W3": np.zeros((64, 4)), "b3": b3})
+    assert mlp.unpack(mlp.grad(th2, x, y))["b3"][0] > 1e-3
 
 
 def test_bf16_rounding_ties_to_even():
