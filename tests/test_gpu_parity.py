@@ -42,7 +42,7 @@ def _case(name):
     if name == "grid_l5":           # every particle on tree edges (exact ties)
         x = S.icosahedral_grid(5)
         z = S.rossby_haurwitz(x, 4)
-    elif name == "rotated_l4":
+    elif name in ("rotated_l4", "rotated_l4_d12"):
         x = S.icosahedral_grid(4) @ S.random_rotation(11).T
         z = S.rossby_haurwitz(x, 3)
     elif name == "random_7001":     # ragged leaves
@@ -73,6 +73,7 @@ CASES = {
     "clustered_6000": (0.8, 4, 24, 4),
     "tiny_50": (0.7, 3, 4, None),
     "planes_3000": (0.7, 5, 16, None),
+    "rotated_l4_d12": (0.7, 12, 96, None),  # 91 proxy points: the coefficient kernel for more than 66
 }
 
 # Denominator for the FP64 parity of each case.  The literal 1 - x.y loses
@@ -82,7 +83,7 @@ CASES = {
 # |x - y|^2 / 2 form (the paper's remedy, Sec. 2), whose rounding error
 # does not grow as pairs approach.
 CASE_DEN = {"grid_l5": "dot", "rotated_l4": "dot", "random_7001": "dist2", "clustered_6000": "dist2",
-            "tiny_50": "dot", "planes_3000": "dist2"}
+            "tiny_50": "dot", "planes_3000": "dist2", "rotated_l4_d12": "dot"}
 
 
 @functools.lru_cache(maxsize=None)
