@@ -1612,7 +1612,11 @@ __device__ __forceinline__ void l2p_level(const EvalArgs& a, int poff, bool has,
 template <int D>
 __global__ __launch_bounds__(256) void k_l2p_finalize(EvalArgs a, int do_far, double* __restrict__ u, int accumulate) {
     const int tid = threadIdx.x;
-    const i64 i0 = (i64)blockIdx.x * blockDim.x + tid;
+    // contiguous eighths of the particles per XCD (the grid is a multiple of
+    // 8): an XCD's waves then read the coefficients of its own nodes, which
+    // stay in its L2 (dealt in turn, every XCD read every node's)
+    const u32 blk = (gridDim.x % 8u == 0u) ? logical_block() : blockIdx.x;
+    const i64 i0 = (i64)blk * blockDim.x + tid;
     const bool valid = i0 < a.n;
     const i64 i = valid ? i0 : a.n - 1;
     const double x0 = a.sx[i], x1 = a.sy[i], x2 = a.sz[i];
@@ -1872,7 +1876,7 @@ void launch_far_finish(hipStream_t s, const EvalArgs& a) {
 
 void launch_l2p_finalize(hipStream_t s, const EvalArgs& a, bool do_far, double* d_u, bool accumulate) {
     if (a.n <= 0) return;
-    const dim3 g((unsigned)((a.n + 255) / 256)), b(256);
+    const dim3 g((unsigned)(((a.n + 255) / 256 + 7) / 8 * 8)), b(256);
     const int f = do_far ? 1 : 0, acc = accumulate ? 1 : 0;
     switch (a.cls.deg[a.ndeg - 1]) {
 #define STC_L2P_CASE(D) \
