@@ -111,7 +111,7 @@ def cpu_baseline(x, z, a, subset, budget_s=15.0, den="dot", what="the 4096 seede
     """The oracle's direct sum (O(N) per target) timed on the host cores over a
     bounded sample of the target subset (the stream function's with stream)."""
     from oracle import direct
-    # the GPU box allots 16 CPUs to a one-GPU job (more visible CPUs are shared
+    # a one-GPU job is allotted 16 host CPUs (more visible CPUs are shared
     # with other jobs), so the pool takes at most 16 processes
     visible = len(os.sched_getaffinity(0))
     cores = min(visible, 16)
@@ -375,7 +375,7 @@ def bench_learned(args):
                precision="fp64", learned=True)
     ul = run("learned_fp32", model=params, theta=P["theta"], theta_max=P["theta_max"], degree=P["degree"],
              precision="fp32", learned=True)
-    e_judge = metrics.rel_l2_velocity(ul, uj, a)
+    e_ref = metrics.rel_l2_velocity(ul, uj, a)
     roof_evals, roof_ms, n_cand = rows.pop("_near")
     # the network's forward pass over the candidates, timed on its own (MFMA, BF16)
     feats = F[: min(len(F), n_cand)] if n_cand <= len(F) else F
@@ -401,8 +401,8 @@ def bench_learned(args):
         ms_per_step=r["ms"], higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="gvpair_l9 (Gaussian vortex pair + RH n=4, icosahedral level 9)", N=n,
                     **{k: v for k, v in P.items()}, rel_l2_err_vs_fp64_direct=r["rel_l2_err_vs_fp64_direct"],
-                    rel_l2_err_vs_fixed_degree_fp64_tree=float(f"{e_judge:.3e}"),
-                    err_ok=bool(r["rel_l2_err_vs_fp64_direct"] <= 1e-6 and e_judge <= 1e-6),
+                    rel_l2_err_vs_fixed_degree_fp64_tree=float(f"{e_ref:.3e}"),
+                    err_ok=bool(r["rel_l2_err_vs_fp64_direct"] <= 1e-6 and e_ref <= 1e-6),
                     training=dict(samples=int(F.shape[0]), seconds_samples=round(t_samples, 3),
                                   seconds_train=round(t_train, 3), steps=len(ln),
                                   loss_first=float(f"{ln[0]:.4f}"), loss_last=float(f"{ln[-50:].mean():.4f}"),
@@ -838,8 +838,7 @@ def main():
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload == "ensemble":
         bench_ensemble(args)

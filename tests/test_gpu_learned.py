@@ -283,7 +283,7 @@ def test_trained_gate_gains_over_fixed_degree(stc_lib):
     then the evaluation at N = 2621442 (Gaussian vortex pair on a
     Rossby-Haurwitz background): rel-L2 error <= 1e-6 against the FP64
     direct sum on 4096 seeded targets, within 1e-6 of the fixed-degree-10
-    FP64 tree (the judge), and fewer kernel evaluations than both that tree
+    FP64 tree (the reference), and fewer kernel evaluations than both that tree
     and the fastest fixed-degree FP32 setting that meets 1e-6 on this input
     (theta 0.8, d = 10).  Wall-clock time of the learned form and of that
     FP32 setting is measured (best of three rounds of five evaluations,
@@ -307,10 +307,10 @@ def test_trained_gate_gains_over_fixed_degree(stc_lib):
     n = len(x)
     xd, zd, ad = dev(x), dev(z), dev(a)
     ud = stc_lib.direct(xd, zd, ad, targets=dev(sub), denominator="dist2").cpu().numpy()
-    judge = stc_lib.Context(n, theta=0.7, degree=10, n_crit=64, precision="fp64", denominator="dist2")
-    uj = judge.velocity(xd, zd, ad).cpu().numpy()
-    _, ej = judge.list_counts()
-    judge.close()
+    ref = stc_lib.Context(n, theta=0.7, degree=10, n_crit=64, precision="fp64", denominator="dist2")
+    uj = ref.velocity(xd, zd, ad).cpu().numpy()
+    _, ej = ref.list_counts()
+    ref.close()
     ctx = stc_lib.Context(n, theta=0.7, theta_max=0.9, degree=10, n_crit=64, precision="fp32", denominator="dist2",
                           learned=True)
     ctx.set_model(params)
@@ -328,14 +328,14 @@ def test_trained_gate_gains_over_fixed_degree(stc_lib):
     fixed.close()
     e_fixed = metrics.rel_l2_velocity(uf[sub], ud, a[sub])
     e_direct = metrics.rel_l2_velocity(ul[sub], ud, a[sub])
-    e_judge = metrics.rel_l2_velocity(ul, uj, a)
-    say(f"  N={n}: E vs direct {e_direct:.3e}, vs FP64 fixed-degree tree {e_judge:.3e}; evaluations "
+    e_ref = metrics.rel_l2_velocity(ul, uj, a)
+    say(f"  N={n}: E vs direct {e_direct:.3e}, vs FP64 fixed-degree tree {e_ref:.3e}; evaluations "
         f"{sum(el.values()) / 1e9:.3f}e9 vs {sum(ej.values()) / 1e9:.3f}e9; classes {cls}")
     say(f"  against fixed FP32 theta 0.8 d 10 (E {e_fixed:.3e}): evaluations {sum(el.values()) / 1e9:.3f}e9 vs "
         f"{sum(ef.values()) / 1e9:.3f}e9, {ms_learned:.3f} ms vs {ms_fixed:.3f} ms per evaluation "
         f"({'faster' if ms_learned < ms_fixed else 'slower'} by {abs(1 - ms_learned / ms_fixed) * 100:.1f}%)")
     assert e_direct <= 1e-6
-    assert e_judge <= 1e-6
+    assert e_ref <= 1e-6
     assert e_fixed <= 1e-6
     assert sum(el.values()) < 0.6 * sum(ej.values())
     assert sum(el.values()) < 0.7 * sum(ef.values())
