@@ -246,7 +246,7 @@ def test_velocity_fp64_dist2(stc_lib):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["grid_l5", "random_7001"])
+@pytest.mark.parametrize("name", ["grid_l5", "random_7001", "rotated_l4_d12"])
 def test_velocity_fp32_precision_form(stc_lib, name):
     """FP32 sums with target-relative coordinates: the difference from the
     FP64 tree is rounding only (the lists are identical)."""
